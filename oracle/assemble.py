@@ -1,0 +1,189 @@
+"""Whole-problem evaluation and assembly (float64, CPU).
+
+``Oracle(problem)`` builds the static (elastic + every free diagonal) and
+dynamic (contact) patterns with ``pattern.build`` and then, for positions x:
+
+* ``eval(x)``: per-stencil energies, gradients and local Hessians
+  (``local.py``) plus the inertia term 1/2 sum_v m_v |x_v - x_tilde_v|^2
+  (or, for a static problem, the gravity potential -sum_v m_v g . x_v);
+* ``assemble(ev)``: scatter-adds every local 3x3 block into its slot (as is
+  when v_a <= v_b, transposed otherwise), adds m_v I to the static diagonal
+  blocks, and sums the gradient per vertex.
+
+The global Hessian is H = H_static + H_dynamic, both upper-triangular BSR with
+row-major 3x3 blocks (appendix "Global Hessian Compression").
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import torch
+
+from . import energy as en
+from . import local, pattern
+
+F_SPACE, X_SPACE = local.F_SPACE, local.X_SPACE
+PROJECTED, EXACT = local.PROJECTED, local.EXACT
+
+
+class Oracle:
+    def __init__(self, prob, proj=F_SPACE, classic=False):
+        self.p = prob
+        self.n = int(prob["n_free"])
+        self.proj = proj
+        self.classic = classic
+        n = self.n
+        self.tet_idx = np.asarray(prob["tet_idx"], np.int64)
+        self.cidx = np.asarray(prob["cidx"], np.int64)
+        self.ctype = np.asarray(prob["ctype"], np.int64)
+        self.rp_s, self.ci_s, (self.slot_t,) = pattern.build(n, [self.tet_idx], True)
+        self.rp_d, self.ci_d, (self.slot_c,) = pattern.build(n, [self.cidx], False)
+        self.pairs_t = pattern.stencil_pairs(self.tet_idx)
+        self.pairs_c = pattern.stencil_pairs(self.cidx)
+        t = local.T
+        self.x_fixed = t(prob["x_fixed"]).reshape(-1, 3)
+        self.dm_inv = t(prob["dm_inv"])
+        self.vol = t(prob["vol"])
+        nt = self.tet_idx.shape[0]
+        if "mu_t" in prob:
+            self.mu = t(prob["mu_t"])
+            self.lam = t(prob["lam_t"])
+        else:
+            self.mu = torch.full((nt,), float(prob["mu"]))
+            self.lam = torch.full((nt,), float(prob["lam"]))
+        self.mass = np.asarray(prob["mass"], np.float64)
+        self.x_tilde = np.asarray(prob["x_tilde"], np.float64)
+        self.static = bool(prob.get("static", False))
+        self.gravity = np.asarray(prob.get("gravity", [0.0, 0.0, -9.81]), np.float64)
+
+    # ------------------------------------------------------------ pieces
+    def inertia(self, x):
+        """Inertia (dynamic) or gravity potential (static): energy, gradient."""
+        if self.static:
+            e = -np.sum(self.mass[:, None] * self.gravity[None, :] * x)
+            g = -self.mass[:, None] * self.gravity[None, :] * np.ones_like(x)
+            return e, g
+        dx = x - self.x_tilde
+        return 0.5 * np.sum(self.mass[:, None] * dx * dx), self.mass[:, None] * dx
+
+    def tets(self, x, hess=PROJECTED, mu=None, lam=None):
+        xt, free = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
+        return local.snh_local(xt, self.dm_inv, self.mu if mu is None else mu,
+                               self.lam if lam is None else lam, self.vol,
+                               float(self.p["h"]), free, self.proj, hess)
+
+    def contacts(self, x, hess=PROJECTED):
+        xc, free = local.gather_positions(local.T(x), self.x_fixed, self.cidx, self.n)
+        return local.contact_local(xc, torch.as_tensor(self.ctype), free,
+                                   float(self.p["kappa"]), float(self.p["dhat"]), hess,
+                                   self.classic)
+
+    # ------------------------------------------------------------ whole problem
+    def eval(self, x, hess=PROJECTED):
+        x = np.asarray(x, np.float64).reshape(self.n, 3)
+        e_i, g_i = self.inertia(x)
+        Et, gt, Ht = self.tets(x, hess)
+        Ec, gc, Hc, d = self.contacts(x, hess)
+        return dict(x=x, E_inertia=e_i, g_inertia=g_i, E_t=Et.numpy(), g_t=gt.numpy(),
+                    H_t=Ht.numpy(), E_c=Ec.numpy(), g_c=gc.numpy(), H_c=Hc.numpy(),
+                    d=d.numpy(), E_elastic=float(Et.sum()), E_contact=float(Ec.sum()),
+                    E=e_i + float(Et.sum()) + float(Ec.sum()))
+
+    def _scatter_blocks(self, nnzb, idx, pairs, slots, H):
+        vals = np.zeros((nnzb, 3, 3))
+        ok = slots >= 0
+        s_i, q_i = np.nonzero(ok)
+        a = pairs[s_i, q_i, 0]
+        b = pairs[s_i, q_i, 1]
+        rr = 3 * a[:, None, None] + np.arange(3)[None, :, None]
+        cc = 3 * b[:, None, None] + np.arange(3)[None, None, :]
+        blk = H[s_i[:, None, None], rr, cc]  # (m, 3, 3): rows of v_a, cols of v_b
+        flip = idx[s_i, a] > idx[s_i, b]
+        blk[flip] = blk[flip].transpose(0, 2, 1)
+        np.add.at(vals, slots[s_i, q_i], blk)
+        return vals
+
+    def _scatter_grad(self, idx, g):
+        out = np.zeros((self.n, 3))
+        free = (idx >= 0) & (idx < self.n)
+        s_i, a = np.nonzero(free)
+        np.add.at(out, idx[s_i, a], g[s_i, a])
+        return out
+
+    def assemble(self, ev):
+        n = self.n
+        vals_s = self._scatter_blocks(len(self.ci_s), self.tet_idx, self.pairs_t, self.slot_t, ev["H_t"])
+        vals_d = self._scatter_blocks(len(self.ci_d), self.cidx, self.pairs_c, self.slot_c, ev["H_c"])
+        if not self.static:
+            vals_s[self.rp_s[:-1]] += self.mass[:, None, None] * np.eye(3)[None]
+        g = ev["g_inertia"] + self._scatter_grad(self.tet_idx, ev["g_t"]) + \
+            self._scatter_grad(self.cidx, ev["g_c"])
+        return dict(values_s=vals_s, values_d=vals_d, grad=g.reshape(n, 3))
+
+    def energy(self, x):
+        """Total energy only (line search)."""
+        x = np.asarray(x, np.float64).reshape(self.n, 3)
+        e_i, _ = self.inertia(x)
+        xt, _ = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
+        h2 = float(self.p["h"]) ** 2
+        Et = h2 * torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol)
+        xc, _ = local.gather_positions(local.T(x), self.x_fixed, self.cidx, self.n)
+        d = self.distances(x)
+        dhat, kappa = float(self.p["dhat"]), float(self.p["kappa"])
+        dt = torch.as_tensor(d)
+        bfun = en.barrier_ipc_classic if self.classic else en.barrier
+        act = dt < dhat
+        Ec = torch.where(act, bfun(torch.where(act, dt, torch.full_like(dt, dhat)), dhat, kappa),
+                         torch.zeros_like(dt))
+        return e_i + float(Et.sum()) + float(Ec.sum())
+
+    def distances(self, x):
+        xc, _ = local.gather_positions(local.T(np.asarray(x).reshape(self.n, 3)), self.x_fixed,
+                                       self.cidx, self.n)
+        d = torch.zeros(xc.shape[0])
+        ct = torch.as_tensor(self.ctype)
+        for t in range(4):
+            sel = torch.nonzero(ct == t).flatten()
+            if sel.numel():
+                d[sel] = torch.vmap(en.DIST[t])(xc[sel])
+        return d.numpy()
+
+    def sides(self, x):
+        xc, _ = local.gather_positions(local.T(np.asarray(x).reshape(self.n, 3)), self.x_fixed,
+                                       self.cidx, self.n)
+        return en.signed_side(xc, torch.as_tensor(self.ctype)).numpy()
+
+    # ------------------------------------------------------------ matrices
+    def diag_blocks(self, asm):
+        """Sum of the static and dynamic diagonal blocks of every free vertex."""
+        D = asm["values_s"][self.rp_s[:-1]].copy()
+        rows_d = np.repeat(np.arange(self.n), np.diff(self.rp_d))
+        is_diag = rows_d == self.ci_d
+        D[rows_d[is_diag]] += asm["values_d"][is_diag]
+        return D
+
+    def csr(self, asm):
+        """Full symmetric scalar CSR of H = H_s + H_d (both triangles)."""
+        n = self.n
+        mats = []
+        for rp, ci, vals in ((self.rp_s, self.ci_s, asm["values_s"]),
+                             (self.rp_d, self.ci_d, asm["values_d"])):
+            rows = np.repeat(np.arange(n), np.diff(rp))
+            bsr = sp.bsr_matrix((vals, ci, rp), shape=(3 * n, 3 * n))
+            upper = bsr.tocsr()
+            off = rows != ci
+            bsr_off = sp.bsr_matrix((vals[off], ci[off], np.concatenate(
+                [[0], np.cumsum(np.bincount(rows[off], minlength=n))])), shape=(3 * n, 3 * n))
+            mats.append(upper + bsr_off.tocsr().T)
+        return (mats[0] + mats[1]).tocsr()
+
+
+def to_dense(rp, ci, vals, n):
+    """Expand an upper BSR part to a dense symmetric 3n x 3n matrix."""
+    D = np.zeros((3 * n, 3 * n))
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    for k, (r, c) in enumerate(zip(rows, ci)):
+        D[3 * r:3 * r + 3, 3 * c:3 * c + 3] += vals[k]
+        if r != c:
+            D[3 * c:3 * c + 3, 3 * r:3 * r + 3] += vals[k].T
+    return D
