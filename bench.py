@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark: one IPC Newton iteration on one MI355X.
+
+A step is one full pass of the hot path on the 40x40x40-cell workload
+(384,000 stable Neo-Hookean tets, 68,921 free vertices, 200k point-triangle +
+200k edge-edge barrier stencils against a fixed collider, float64): per-stencil
+energy / gradient / projected Hessian, atomic-free BSR assembly, block-Jacobi
+PCG to 1e-8, and the feasibility line search.  Every step starts from the same
+positions (copied on the device), so every step does the same work.
+
+Prints ONE JSON line.  `value` is stencils processed per second of Newton
+iteration (Mstencils/s); `ms_per_step` is the Newton-iteration time.  After the
+timed steps a profiled pass times every kernel class with HIP events on the
+library's stream (the `roofline` object), and the CPU oracle runs one Newton
+step of the same workload (`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "Newton-iter ms (eval+BSR assembly+PCG) at 384k tets; Mstencils/s; HBM % peak"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+
+# Algorithmic work per unit ("Measurement"):
+SNH_FLOPS_PER_TET = 3.5e4        # 9x9 Jacobi eigen-projection dominated
+CONTACT_FLOPS = {0: 3.0e4, 1: 1.0e4, 2: 3.0e4, 3: 1.0e4}  # PT 9x9, EE 6x6 eigenproblems
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic(prob, g, view):
+    """Per-launch algorithmic bytes / flops of each kernel class."""
+    n = g.n
+    nt = g.nt
+    ct = prob["ctype"]
+    nnzb = view.nnzb_static + view.nnzb_dynamic
+    c_flops = sum(CONTACT_FLOPS[int(t)] * int((ct == t).sum()) for t in range(4))
+    return {
+        # FP64 ALU bound
+        "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
+        "contact_eval": ("alu", c_flops, "TFLOP/s"),
+        # HBM bound: what the method must move
+        "assemble": ("hbm", 72.0 * nnzb + 24.0 * n, "GB/s"),
+        "block_inverse": ("hbm", 2 * 72.0 * n, "GB/s"),
+        # values + column index once per stored block, row pointers, u read, w written
+        "pcg_spmv": ("hbm", 76.0 * nnzb + 8.0 * (n + 1) + 48.0 * n, "GB/s"),
+        # p, s, w, u, x, r and M^-1 read; p, s, x, r, u written
+        "pcg_update": ("hbm", n * (6 * 24.0 + 72.0 + 5 * 24.0), "GB/s"),
+        "inertia": ("hbm", n * (24.0 * 2 + 8.0 + 72.0 + 24.0), "GB/s"),
+    }
+
+
+def cpu_baseline(prob):
+    """The oracle's Newton step on the same workload (host cores)."""
+    import torch
+    from oracle import assemble as oasm
+    from oracle import newton as onewton
+    t0 = time.perf_counter()
+    o = oasm.Oracle(prob)
+    t1 = time.perf_counter()
+    _, info = onewton.newton_step(o, prob["x0"], rtol=1e-8)
+    t2 = time.perf_counter()
+    stencils = prob["tet_idx"].shape[0] + prob["ctype"].shape[0]
+    return {"value": stencils / (t2 - t1) / 1e6, "unit": "Mstencils/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "the full workload: one Newton step (eval + assembly + PCG to 1e-8 + line search); "
+                      f"{t2 - t1:.2f} s, pattern set-up {t1 - t0:.2f} s excluded, {info['cg_iters']} PCG iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profiled-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cells", type=int, default=40, help="block size (default: the 40^3 workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU sharding "
+              "of this path is a design in DESIGN.md, not a built mode)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2605_23088_amd import synth
+    from paper_2605_23088_amd.yasps import KERNEL_CLASSES, Yasps
+
+    log("[bench] generating workload")
+    if args.cells == 40:
+        prob = synth.c2_block()
+    else:
+        c = args.cells
+        prob = synth.block_problem(c, c, c, 1.0 / c, 200_000 * c ** 3 // 64000, 200_000 * c ** 3 // 64000,
+                                   synth.SEEDS["C2"], name=f"C2-{c}")
+    nt, nc = prob["tet_idx"].shape[0], prob["ctype"].shape[0]
+    log(f"[bench] {nt} tets, {prob['n_free']} free vertices, {nc} contacts; creating context")
+    g = Yasps(prob)
+    x0 = torch.as_tensor(prob["x0"], dtype=torch.float64, device="cuda").contiguous()
+    x = x0.clone()
+    for i in range(args.warmup):
+        x.copy_(x0)
+        info = g.newton_step(x)
+        log(f"[bench] warmup {i}: cg {info['cg_iters']} alpha {info['alpha']:.4g}")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.copy_(x0)
+        infos.append(g.newton_step(x))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step")
+    phases = {k: float(np.mean([i[f"ms_{k}"] for i in infos])) for k in ("eval", "assemble", "pcg", "linesearch")}
+
+    # profiled pass: per-kernel-class device time with HIP events on the library stream
+    g.profile(True)
+    for _ in range(args.profiled_steps):
+        x.copy_(x0)
+        g.newton_step(x)
+    stats = g.profile_stats()
+    g.profile(False)
+    view = g.view()
+    model = algorithmic(prob, g, view)
+    kernels = {}
+    for name, st in stats.items():
+        if not st["launches"]:
+            continue
+        avg_ms = st["total_ms"] / st["launches"]
+        k = {"launches_per_step": st["launches"] / args.profiled_steps, "avg_ms": avg_ms,
+             "ms_per_step": st["total_ms"] / args.profiled_steps}
+        if name in model:
+            bound, work, unit = model[name]
+            rate = work / (avg_ms * 1e-3)
+            if bound == "hbm":
+                k.update(bound="hbm", achieved=rate / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=rate / 1e9 / HBM_PEAK_GBS, algorithmic_bytes=work)
+            else:
+                k.update(bound="alu", achieved=rate / 1e12, peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s",
+                         frac=rate / 1e12 / FP64_VECTOR_TFLOPS, algorithmic_flops=work)
+        kernels[name] = k
+    dom = max((n for n in kernels if "bound" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
+    d = kernels[dom]
+    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+                "frac": d["frac"], "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(prob)
+
+    stencils = nt + nc
+    line = {
+        "metric": METRIC,
+        "value": stencils / (ms / 1000.0) / 1e6,
+        "unit": "Mstencils/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.cells}x{args.cells}x{args.cells}-cell Kuhn block: {nt} tets, "
+                               f"{prob['n_free']} free vertices, {int((prob['ctype'] == 0).sum())} PT + "
+                               f"{int((prob['ctype'] == 1).sum())} EE collider stencils; FP64 Newton step, "
+                               "PCG rtol 1e-8",
+                   "tets": nt, "contacts": nc, "free_vertices": int(prob["n_free"]),
+                   "nnzb_static": view.nnzb_static, "nnzb_dynamic": view.nnzb_dynamic},
+        "newton_iter_ms": ms,
+        "phases_ms": phases,
+        "pcg_iters": int(np.mean([i["cg_iters"] for i in infos])),
+        "line_search_trials": int(np.mean([i["ls_trials"] for i in infos])),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,259 @@
+/*
+ * yasps.h -- C ABI of the MI355X (gfx950) library for one Newton iteration of
+ * Incremental Potential Contact,
+ *
+ *     E(x) = 1/2 |x - x_tilde|_M^2 + h^2 sum_t Psi_t(x) + sum_s kappa b(d_s(x)),
+ *
+ * after "YASPS: A Symbolic Framework for Extensible, High-Performance IPC
+ * Simulation" (ACM TOG 45(4), 2026).  The library evaluates per-stencil
+ * energy, gradient and PSD-projected local Hessians (stable Neo-Hookean tets,
+ * Eq. snh; log-barrier contact stencils, section "Eigendecomposition:
+ * Automatic Optimization"), assembles them without atomics into a 3x3
+ * block-sparse upper-triangular Hessian (appendix "Global Hessian
+ * Compression"), and solves H p = b with block-Jacobi preconditioned CG
+ * (section "Solver", appendices "SpMV" and "Preconditioner").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array pointers in yasps_problem / yasps_contacts and every x / b / p
+ *   argument are DEVICE pointers on the device that is current when
+ *   yasps_create is called.  They stay owned by the caller and must outlive
+ *   the context (problem arrays) or the call (x, b, p).
+ * - Vertex ids: 0 <= i < n_free is a free vertex (3 DoF); n_free <= i <
+ *   n_free + n_fixed is fixed vertex i - n_free (no DoF; the paper's
+ *   "special primitive whose degrees of freedom are excluded from
+ *   differentiation", Table 1 caption); -1 marks an unused stencil entry.
+ * - Positions and vectors over free vertices are (n_free, 3) row-major f64.
+ * - Per-stencil arrays are structure-of-arrays: tet_idx is [4][n_tets]
+ *   (entry k of tet t at tet_idx[k * n_tets + t]), dm_inv is [9][n_tets]
+ *   (row-major 3x3 components), contact idx is [4][n_contacts].
+ * - Work is enqueued on the stream given to yasps_create; calls return after
+ *   their host-visible scalars (energies, solver info) are final.
+ * - Every call returns a yasps_status; no C++ exception crosses the ABI.
+ *   yasps_last_error() describes the last failure of a context.
+ * - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef YASPS_H
+#define YASPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t yasps_status;
+#define YASPS_OK 0
+#define YASPS_E_ARG (-1)        /* invalid argument, index out of range, repeated vertex in a stencil */
+#define YASPS_E_HIP (-2)        /* a HIP runtime call failed */
+#define YASPS_E_DOMAIN (-3)     /* a contact stencil has squared distance d <= 0 */
+#define YASPS_E_NONFINITE (-4)  /* NaN/Inf in positions or in an evaluated quantity */
+#define YASPS_E_NOCONV (-5)     /* PCG hit max_iter; the last iterate is still returned */
+#define YASPS_E_BREAKDOWN (-6)  /* PCG met p^T H p <= 0 (matrix not positive definite) */
+#define YASPS_E_UNIMPL (-7)     /* option not implemented */
+#define YASPS_E_LINESEARCH (-8) /* no admissible step after the maximum number of halvings */
+
+/* contact stencil types and their vertex order */
+#define YASPS_PT 0 /* (p, t0, t1, t2): squared distance from p to the plane of the triangle */
+#define YASPS_EE 1 /* (a0, a1, b0, b1): squared distance between the two edge lines */
+#define YASPS_PE 2 /* (p, e0, e1, -1): squared distance from p to the edge line */
+#define YASPS_PP 3 /* (p, q, -1, -1): squared distance between the points */
+
+/* yasps_params.precision */
+#define YASPS_FP64 0  /* everything in float64 */
+#define YASPS_MIXED 1 /* float32 element Hessians, BSR values and PCG inner vectors; contact
+                         geometry, barrier, contact projection, energies, gradient and the
+                         Newton residual stay float64 */
+/* yasps_params.proj: where the Neo-Hookean Hessian is projected */
+#define YASPS_F_SPACE 0 /* h^2 J_F^T Proj(d2Psi/dF2) J_F (9x9 eigenproblem), section
+                           "Eigendecomposition: Manual Optimization" */
+#define YASPS_X_SPACE 1 /* Proj(h^2 d2Psi/dx2) over the tet's free vertices */
+/* yasps_params.hessian and the `flags` argument of yasps_eval_stencils */
+#define YASPS_PROJECTED 0 /* local Hessians projected to the PSD cone (negative eigenvalues -> 0) */
+#define YASPS_EXACT 1     /* unprojected local Hessians (adjoint solves) */
+/* yasps_params.barrier */
+#define YASPS_SQLOG 0       /* kappa (d - dhat)^2 log(d/dhat)^2, as printed in the paper */
+#define YASPS_IPC_CLASSIC 1 /* -kappa (d - dhat)^2 log(d/dhat) */
+
+typedef struct yasps_ctx yasps_ctx;
+
+typedef struct {
+  int32_t n_free;          /* free vertices */
+  int32_t n_fixed;         /* fixed vertices */
+  const double* x_fixed;   /* (n_fixed, 3) positions of fixed vertices; may be NULL if n_fixed == 0 */
+  const double* mass;      /* (n_free) lumped masses */
+  const double* x_tilde;   /* (n_free, 3) inertial target x0 + h v0 + h^2 g; ignored if is_static */
+  int32_t n_tets;
+  const int32_t* tet_idx;  /* [4][n_tets] vertex ids, positively oriented at rest */
+  const double* dm_inv;    /* [9][n_tets] inverse rest edge matrices Dm^-1, row-major components */
+  const double* vol;       /* [n_tets] rest volumes */
+  const double* mu_lambda; /* [2][n_tets] per-tet Lame parameters, or NULL to use mu / lambda */
+  double mu, lambda;       /* global Lame parameters when mu_lambda is NULL */
+  double h;                /* time step; the elastic term is scaled by h^2 */
+  double kappa;            /* barrier stiffness */
+  double dhat;             /* barrier activation, a SQUARED distance; d >= dhat contributes 0 */
+  double gravity[3];       /* used only when is_static: adds -sum_v m_v gravity . x_v */
+  int32_t is_static;       /* 1: static equilibrium (no inertia term), 0: implicit Euler step */
+} yasps_problem;
+
+typedef struct {
+  int32_t n_contacts;
+  const int32_t* type; /* [n_contacts] YASPS_PT / EE / PE / PP */
+  const int32_t* idx;  /* [4][n_contacts] vertex ids in the order given for the type */
+} yasps_contacts;
+
+typedef struct {
+  int32_t precision; /* YASPS_FP64 or YASPS_MIXED */
+  int32_t proj;      /* YASPS_F_SPACE or YASPS_X_SPACE */
+  int32_t hessian;   /* default Hessian mode of yasps_newton_step: YASPS_PROJECTED */
+  int32_t barrier;   /* YASPS_SQLOG or YASPS_IPC_CLASSIC */
+} yasps_params;
+
+typedef struct {
+  double energy;    /* total E(x), summed in float64 in a fixed order */
+  double e_inertia; /* 1/2 |x - x_tilde|_M^2, or -sum m g.x when static */
+  double e_elastic; /* h^2 sum Psi_t */
+  double e_contact; /* sum kappa b(d_s) */
+  double min_d;     /* smallest contact squared distance (+inf without contacts) */
+  int32_t n_active; /* contact stencils with d < dhat */
+} yasps_eval_info;
+
+/* Device views of context-owned storage, valid until the next yasps_set_contacts
+ * or yasps_destroy.  Upper-triangular BSR with row-major 3x3 blocks; the diagonal
+ * block is the first block of every static row.  H = H_static + H_dynamic. */
+typedef struct {
+  int32_t n_rows;       /* = n_free */
+  int32_t nnzb_static;  /* elastic pairs + every free diagonal */
+  int32_t nnzb_dynamic; /* contact pairs */
+  const int32_t* row_ptr_s; const int32_t* col_idx_s; const void* values_s;
+  const int32_t* row_ptr_d; const int32_t* col_idx_d; const void* values_d;
+  int32_t values_are_f32; /* 1 in the MIXED precision form, else float64 */
+  const double* grad;     /* (n_free, 3) float64 gradient */
+  const double* block_inv;/* (n_free, 9) float64 inverses of the diagonal blocks of H */
+} yasps_bsr_view;
+
+typedef struct {
+  int32_t iters;       /* matrix-vector products performed */
+  double rel_residual; /* |b - H x| / |b| of the recurrence residual at exit */
+  int32_t status;      /* YASPS_OK, YASPS_E_NOCONV or YASPS_E_BREAKDOWN */
+} yasps_pcg_info;
+
+typedef struct {
+  double rtol;          /* PCG relative tolerance (default 1e-8) */
+  int32_t max_iter;     /* PCG iteration cap (default 20000) */
+  int32_t max_halvings; /* line-search halvings (default 40) */
+  double armijo;        /* sufficient-decrease constant (default 1e-4) */
+} yasps_newton_params;
+
+typedef struct {
+  double e0, e1;       /* energy before / after the step */
+  double alpha;        /* accepted step length (0 if none) */
+  double alpha0;       /* initial step bound min(1, 0.4 min sqrt(d) / max |p_v|) */
+  double grad_dot_p;   /* g . p (< 0 for a descent direction) */
+  int32_t cg_iters;
+  double cg_rel_residual;
+  int32_t cg_status;
+  int32_t ls_trials;
+  /* phase times measured with HIP events on the context stream (ms) */
+  float ms_eval, ms_assemble, ms_pcg, ms_linesearch;
+} yasps_newton_info;
+
+/* Creates a context bound to the current device and `hip_stream` (a hipStream_t,
+ * NULL = default stream).  Validates the tets (ids in range, 4 distinct vertices),
+ * builds the static pattern and slot map (appendix "Global Hessian Compression"),
+ * and allocates the workspace.  `opt` may be NULL for defaults.
+ * Errors: YASPS_E_ARG, YASPS_E_UNIMPL, YASPS_E_HIP.  *out is NULL on failure. */
+yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem* P,
+                          const yasps_params* opt);
+
+/* Replaces the contact stencil list (the paper's dynamic primitives, section
+ * "Index Generator" and the static/dynamic split of the index-computation
+ * evaluation) and rebuilds the dynamic pattern and slot map.  The arrays are
+ * copied; the caller may free them after the call.  Errors: YASPS_E_ARG
+ * (bad type, id out of range, repeated vertex), YASPS_E_HIP. */
+yasps_status yasps_set_contacts(yasps_ctx* ctx, const yasps_contacts* C);
+
+/* Evaluates every stencil at positions x (n_free, 3): energies, gradients and
+ * local Hessians (flags: YASPS_PROJECTED or YASPS_EXACT), staged for assembly.
+ * Fills *info (may be NULL).  Errors: YASPS_E_DOMAIN (some contact d <= 0),
+ * YASPS_E_NONFINITE, YASPS_E_HIP. */
+yasps_status yasps_eval_stencils(yasps_ctx* ctx, const double* x, int32_t flags,
+                                 yasps_eval_info* info);
+
+/* Sums the staged contributions of the last yasps_eval_stencils into the BSR
+ * values, the gradient and the inverted diagonal blocks (block-Jacobi M^-1),
+ * without atomics and in a fixed order (bitwise reproducible).  *view (may be
+ * NULL) receives device pointers to the result.  Errors: YASPS_E_HIP,
+ * YASPS_E_ARG if called before any evaluation. */
+yasps_status yasps_assemble_bsr(yasps_ctx* ctx, yasps_bsr_view* view);
+
+/* Solves H x = b with block-Jacobi preconditioned CG on the assembled H
+ * (x0 = 0, stop when |r| <= rtol |b| or after max_iter products).  b and x
+ * are (n_free, 3) device arrays; x is overwritten.  The system is solved as
+ * given (the paper's convention, section "Solution Extraction").
+ * Errors: YASPS_E_NOCONV (x holds the last iterate), YASPS_E_BREAKDOWN,
+ * YASPS_E_ARG, YASPS_E_HIP. */
+yasps_status yasps_pcg(yasps_ctx* ctx, const double* b, double* x, double rtol, int32_t max_iter,
+                       yasps_pcg_info* info);
+
+/* One projected-Newton step on the current stencil set: evaluate, assemble,
+ * solve H p = -g, then backtrack from alpha0 = min(1, 0.4 min_s sqrt(d_s) /
+ * max_v |p_v|) by halving until every contact d > 0, every PT/EE stencil keeps
+ * its side of the plane/line, and E(x + alpha p) <= E(x) + armijo alpha g.p.
+ * x (n_free, 3) is updated in place.  `prm` may be NULL for defaults.
+ * Errors: as eval / pcg, plus YASPS_E_LINESEARCH (x unchanged). */
+yasps_status yasps_newton_step(yasps_ctx* ctx, double* x, const yasps_newton_params* prm,
+                               yasps_newton_info* info);
+
+/* Copies one part of the pattern to HOST arrays for inspection (bit-exact tests):
+ * part 0 = static, 1 = dynamic.  row_ptr has n_free + 1 entries, col_idx nnzb,
+ * slot [n_stencils][10] (tets for part 0, contacts for part 1; local pair (a, b),
+ * a <= b, enumerated row by row over the stencil's used vertices; -1 = no block).
+ * Any output pointer may be NULL.  Errors: YASPS_E_ARG. */
+yasps_status yasps_get_pattern(yasps_ctx* ctx, int32_t part, int32_t* row_ptr, int32_t* col_idx,
+                               int32_t* slot);
+
+/* Adjoint of the static-equilibrium solve with per-tet Young's modulus theta_t
+ * (mu_t, lambda_t proportional to theta_t): for every tet writes
+ * grad_theta[t] = -lambda_t^T d/dx (Psi_t(x) / theta_t), the mixed partial
+ * d2E/dx dtheta_t contracted with the adjoint vector lambda (n_free, 3).
+ * theta (n_tets) and grad_theta (n_tets) are device arrays.
+ * Errors: YASPS_E_ARG, YASPS_E_HIP. */
+yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* lambda,
+                                 const double* theta, double* grad_theta);
+
+/* Kernel classes timed by the opt-in profiler (yasps_profile_*). */
+#define YASPS_K_INERTIA 0       /* inertia / gravity term per vertex */
+#define YASPS_K_SNH 1           /* Neo-Hookean tet evaluation (energy, gradient, projected Hessian) */
+#define YASPS_K_CONTACT 2       /* contact stencil evaluation (all groups) */
+#define YASPS_K_ASSEMBLE 3      /* segmented sums of the staged blocks and gradient */
+#define YASPS_K_BLOCKINV 4      /* block-Jacobi inverse */
+#define YASPS_K_SPMV 5          /* PCG: w = H u with the u.w partials */
+#define YASPS_K_PCG_UPDATE 6    /* PCG: recurrences, vector updates, preconditioning */
+#define YASPS_K_LINESEARCH 7    /* line-search energy and feasibility kernels */
+#define YASPS_K_COUNT 8
+
+/* Opt-in per-kernel timing with HIP events recorded on the context stream
+ * around every launch of each class (adds a little launch overhead; off by
+ * default).  enable = 1 turns it on and clears the totals, 0 turns it off.
+ * yasps_profile_query returns the launches and the summed device time (ms)
+ * of one class since it was enabled.  Errors: YASPS_E_ARG, YASPS_E_HIP. */
+yasps_status yasps_profile_enable(yasps_ctx* ctx, int32_t enable);
+yasps_status yasps_profile_query(yasps_ctx* ctx, int32_t kernel_class, int32_t* launches, double* total_ms);
+
+/* y = H x with the assembled H (both parts), through the same SpMV kernel the
+ * solver uses (appendix "SpMV"); x, y (n_free, 3) device arrays.
+ * Errors: YASPS_E_ARG (before assembly), YASPS_E_HIP. */
+yasps_status yasps_spmv(yasps_ctx* ctx, const double* x, double* y);
+
+/* Frees the context and everything it owns.  NULL is accepted. */
+void yasps_destroy(yasps_ctx* ctx);
+
+/* Message describing the last error of ctx (or of the last failed create when
+ * ctx is NULL).  The string is owned by the library. */
+const char* yasps_last_error(const yasps_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YASPS_H */

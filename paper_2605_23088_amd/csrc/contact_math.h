@@ -1,0 +1,401 @@
+// Log-barrier contact stencils: energy, gradient and projected local Hessian
+// of one stencil (host/device arithmetic shared by the kernels and the host
+// checks of the device math).
+//
+// Barrier (section "Eigendecomposition: Automatic Optimization" and the
+// point-point code listing of section "Energies"), d a SQUARED distance:
+//   b(d) = (d - dhat)^2 log(d/dhat)^2,  E = kappa b(d) for 0 < d < dhat, else 0.
+// With u = d - dhat, L = log(d/dhat):
+//   b' = 2uL^2 + 2u^2 L/d,   b'' = 2L^2 + 8uL/d + 2u^2 (1 - L)/d^2.
+// (classic IPC form -u^2 L: b' = -2uL - u^2/d, b'' = -2L - 4u/d + u^2/d^2.)
+//
+// Distances are type-fixed (the stencil's type names the closest-feature pair):
+//   PT, EE: d = s^2/N,  s = w . (e1 x e2),  N = |e1 x e2|^2 with
+//           PT: w = p - t0, e1 = t1 - t0, e2 = t2 - t0
+//           EE: w = a0 - b0, e1 = a1 - a0, e2 = b1 - b0
+//   PE:     d = S/N,  S = |a x b|^2,  N = |b - a|^2,  a = e0 - p, b = e1 - p
+//   PP:     d = |q - p|^2
+// Derivatives are taken in these difference variables u (hand-derived closed
+// forms below) and mapped to the stencil's vertices by the constant incidence
+// matrix M (u_U = sum_a M[U][a] x_a):  H_x = (M (x) I3)^T H_u (M (x) I3).
+//
+// Projection (section "Eigendecomposition (EVD) and PSD Projection") acts on
+// the Hessian restricted to the stencil's free vertices (fixed vertices are
+// excluded from differentiation).  When every vertex is free the energy is
+// translation invariant, H_x annihilates the 3 translations, and
+// Proj(H_x) = Q Proj(Q^T H_x Q) Q^T with Q = Hm (x) I3 (Hm the Helmert basis
+// of the vectors orthogonal to (1,...,1)): an exact reduction from 12 to 9
+// (PT, EE), 9 to 6 (PE) and 6 to 3 (PP) dimensions.
+#pragma once
+
+#include "eigen.h"
+
+namespace yasps {
+namespace cmath {
+
+template <int TYPE>
+struct Topo;
+// PT: x = (p, t0, t1, t2); u = (w, e1, e2)
+template <>
+struct Topo<0> {
+  static constexpr int NV = 4, NU = 3;
+  static YHD constexpr int M(int U, int a) {
+    return U == 0 ? (a == 0 ? 1 : a == 1 ? -1 : 0) : U == 1 ? (a == 2 ? 1 : a == 1 ? -1 : 0)
+                                                            : (a == 3 ? 1 : a == 1 ? -1 : 0);
+  }
+};
+// EE: x = (a0, a1, b0, b1); u = (w = a0 - b0, e1 = a1 - a0, e2 = b1 - b0)
+template <>
+struct Topo<1> {
+  static constexpr int NV = 4, NU = 3;
+  static YHD constexpr int M(int U, int a) {
+    return U == 0 ? (a == 0 ? 1 : a == 2 ? -1 : 0) : U == 1 ? (a == 1 ? 1 : a == 0 ? -1 : 0)
+                                                            : (a == 3 ? 1 : a == 2 ? -1 : 0);
+  }
+};
+// PE: x = (p, e0, e1); u = (a = e0 - p, b = e1 - p)
+template <>
+struct Topo<2> {
+  static constexpr int NV = 3, NU = 2;
+  static YHD constexpr int M(int U, int a) {
+    return U == 0 ? (a == 1 ? 1 : a == 0 ? -1 : 0) : (a == 2 ? 1 : a == 0 ? -1 : 0);
+  }
+};
+// PP: x = (p, q); u = q - p
+template <>
+struct Topo<3> {
+  static constexpr int NV = 2, NU = 1;
+  static YHD constexpr int M(int, int a) { return a == 1 ? 1 : -1; }
+};
+
+// Helmert basis: column j (j = 0..k-2) of the k x (k-1) orthonormal basis of
+// vectors orthogonal to (1, ..., 1).
+YHD double helmert(int a, int j) {
+  const double s = 1.0 / sqrt(double((j + 1) * (j + 2)));
+  return a <= j ? s : (a == j + 1 ? -double(j + 1) * s : 0.0);
+}
+
+YHD void cross(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+YHD double dot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+// [a]x (i, l)
+YHD double cm(const double a[3], int i, int l) {
+  if (i == l) return 0.0;
+  if (i == 0) return l == 1 ? -a[2] : a[1];
+  if (i == 1) return l == 0 ? a[2] : -a[0];
+  return l == 0 ? -a[1] : a[0];
+}
+
+// Squared distance, its gradient and Hessian in the difference variables.
+template <int TYPE>
+struct Dist {
+  static constexpr int NU = Topo<TYPE>::NU;
+  double d;
+  double g[3 * NU];
+  Sym<3 * NU, double> H;
+};
+
+// Q(x) = |x1 x x2|^2 type quantity: gradient and Hessian blocks for
+// n = e1 x e2:  dN/de1 = 2 e2 x n, dN/de2 = 2 n x e1,
+//   (e1,e1) = 2(|e2|^2 I - e2 e2^T), (e2,e2) = 2(|e1|^2 I - e1 e1^T),
+//   (e1,e2) = 2(e1 e2^T - (e1.e2) I - [n]x).
+YHD double crossnorm_hess(const double e1[3], const double e2[3], const double n[3], int B1, int B2,
+                           int i, int l) {
+  if (B1 == 0 && B2 == 0) return 2.0 * ((i == l ? dot(e2, e2) : 0.0) - e2[i] * e2[l]);
+  if (B1 == 1 && B2 == 1) return 2.0 * ((i == l ? dot(e1, e1) : 0.0) - e1[i] * e1[l]);
+  if (B1 == 0 && B2 == 1) return 2.0 * (e1[i] * e2[l] - (i == l ? dot(e1, e2) : 0.0) - cm(n, i, l));
+  // (e2, e1) = transpose of (e1, e2)
+  return 2.0 * (e1[l] * e2[i] - (i == l ? dot(e1, e2) : 0.0) - cm(n, l, i));
+}
+
+// PT / EE: u = (w, e1, e2), d = s^2 / N.
+//   ds = (n, e2 x w, w x e1);  d2s: (w,e1) = -[e2]x, (w,e2) = [e1]x, (e1,e2) = -[w]x
+//   dN = (0, 2 e2 x n, 2 n x e1);  d2N as crossnorm_hess on (e1, e2)
+//   grad d = (2s/N) ds - (s^2/N^2) dN
+//   hess d = (2/N) ds ds^T + (2s/N) d2s - (2s/N^2)(ds dN^T + dN ds^T)
+//            - (s^2/N^2) d2N + (2 s^2/N^3) dN dN^T
+YHD double d2s_block(const double w[3], const double e1[3], const double e2[3], int B1, int B2, int i,
+                      int l) {
+  if (B1 == B2) return 0.0;
+  if (B1 == 0 && B2 == 1) return -cm(e2, i, l);
+  if (B1 == 0 && B2 == 2) return cm(e1, i, l);
+  if (B1 == 1 && B2 == 2) return -cm(w, i, l);
+  if (B1 == 1 && B2 == 0) return -cm(e2, l, i);
+  if (B1 == 2 && B2 == 0) return cm(e1, l, i);
+  return -cm(w, l, i);  // (2, 1)
+}
+
+template <int TYPE>
+YHD void distance(const double (&u)[Topo<TYPE>::NU][3], Dist<TYPE>& D, double& side) {
+  if constexpr (TYPE == 0 || TYPE == 1) {
+    const double *w = u[0], *e1 = u[1], *e2 = u[2];
+    double n[3], e2w[3], we1[3], e2n[3], ne1[3];
+    cross(e1, e2, n);
+    cross(e2, w, e2w);
+    cross(w, e1, we1);
+    cross(e2, n, e2n);
+    cross(n, e1, ne1);
+    const double s = dot(w, n), N = dot(n, n);
+    side = s;
+    const double iN = 1.0 / N;
+    const double d = s * s * iN;
+    D.d = d;
+    double ds[9], dN[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ds[i] = n[i];
+      ds[3 + i] = e2w[i];
+      ds[6 + i] = we1[i];
+      dN[i] = 0.0;
+      dN[3 + i] = 2.0 * e2n[i];
+      dN[6 + i] = 2.0 * ne1[i];
+    }
+    const double c1 = 2.0 * s * iN, c2 = s * s * iN * iN;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) D.g[r] = c1 * ds[r] - c2 * dN[r];
+    const double k_ss = 2.0 * iN, k_s = 2.0 * s * iN, k_sN = 2.0 * s * iN * iN, k_N = c2,
+                 k_NN = 2.0 * s * s * iN * iN * iN;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int c = r; c < 9; ++c) {
+        const int B1 = r / 3, B2 = c / 3, i = r % 3, l = c % 3;
+        const double hN = (B1 == 0 || B2 == 0) ? 0.0 : crossnorm_hess(e1, e2, n, B1 - 1, B2 - 1, i, l);
+        D.H(r, c) = k_ss * ds[r] * ds[c] + k_s * d2s_block(w, e1, e2, B1, B2, i, l) -
+                    k_sN * (ds[r] * dN[c] + dN[r] * ds[c]) - k_N * hN + k_NN * dN[r] * dN[c];
+      }
+  } else if constexpr (TYPE == 2) {
+    // PE: u = (a, b), d = S/N, S = |a x b|^2, N = |b - a|^2
+    const double *a = u[0], *b = u[1];
+    double c[3], bc[3], ca[3], ba[3];
+    cross(a, b, c);
+    cross(b, c, bc);
+    cross(c, a, ca);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ba[i] = b[i] - a[i];
+    const double S = dot(c, c), N = dot(ba, ba);
+    side = 1.0;
+    const double iN = 1.0 / N;
+    D.d = S * iN;
+    double dS[6], dN[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dS[i] = 2.0 * bc[i];
+      dS[3 + i] = 2.0 * ca[i];
+      dN[i] = -2.0 * ba[i];
+      dN[3 + i] = 2.0 * ba[i];
+    }
+    const double k_S = iN, k_N = S * iN * iN;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) D.g[r] = k_S * dS[r] - k_N * dN[r];
+    const double k_SN = iN * iN, k_NN = 2.0 * S * iN * iN * iN;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int cc = r; cc < 6; ++cc) {
+        const int B1 = r / 3, B2 = cc / 3, i = r % 3, l = cc % 3;
+        const double hS = crossnorm_hess(a, b, c, B1, B2, i, l);
+        const double hN = (i == l) ? (B1 == B2 ? 2.0 : -2.0) : 0.0;
+        D.H(r, cc) = k_S * hS - k_SN * (dS[r] * dN[cc] + dN[r] * dS[cc]) - k_N * hN + k_NN * dN[r] * dN[cc];
+      }
+  } else {
+    const double* v = u[0];
+    side = 1.0;
+    D.d = dot(v, v);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) D.g[i] = 2.0 * v[i];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = r; cc < 3; ++cc) D.H(r, cc) = (r == cc) ? 2.0 : 0.0;
+  }
+}
+
+// b, b', b'' of the barrier.
+YHD void barrier(double d, double dhat, int classic, double& b0, double& b1, double& b2) {
+  const double u = d - dhat, L = log(d / dhat), id = 1.0 / d;
+  if (classic) {
+    b0 = -u * u * L;
+    b1 = -2.0 * u * L - u * u * id;
+    b2 = -2.0 * L - 4.0 * u * id + u * u * id * id;
+  } else {
+    b0 = u * u * L * L;
+    b1 = 2.0 * u * L * L + 2.0 * u * u * L * id;
+    b2 = 2.0 * L * L + 8.0 * u * L * id + 2.0 * u * u * (1.0 - L) * id * id;
+  }
+}
+
+YHD int pair_index(int a, int b, int k) { return a * k - (a * (a - 1)) / 2 + (b - a); }
+
+// Difference variables u_U = sum_a M[U][a] x_a of a stencil; false on non-finite input.
+template <int TYPE>
+YHD bool diff_vars(const double (&xv)[4][3], double (&u)[Topo<TYPE>::NU][3]) {
+  constexpr int NV = Topo<TYPE>::NV, NU = Topo<TYPE>::NU;
+  bool ok = true;
+#pragma unroll
+  for (int U = 0; U < NU; ++U)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int m = Topo<TYPE>::M(U, k);
+        if (m == 1) acc += xv[k][i];
+        if (m == -1) acc -= xv[k][i];
+      }
+      u[U][i] = acc;
+      ok = ok && finite(acc);
+    }
+  return ok;
+}
+
+// Energy, free-vertex gradient rows and free-vertex upper Hessian blocks of one
+// stencil with K free vertices, fl[k] = local index of the k-th free vertex
+// (increasing).  grad_sink(k, g[3]) receives the gradient row of free vertex k;
+// block_sink(I, J, B[3][3]) the block of free vertices (I <= J) with rows of
+// vertex fl[I].  Returns false when an input is not finite.  d receives the
+// squared distance; e = kappa b(d) (0 when d >= dhat or d <= 0).
+template <int TYPE, int K, bool EXACT, class GS, class BS>
+YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
+                         double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink) {
+  constexpr int NV = Topo<TYPE>::NV, NU = Topo<TYPE>::NU;
+  double u[NU][3];
+  const bool ok = diff_vars<TYPE>(xv, u);
+  Dist<TYPE> D;
+  distance<TYPE>(u, D, side);
+  d = D.d;
+  const bool active = D.d > 0.0 && D.d < dhat;
+  double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+  if (active) barrier(D.d, dhat, classic, b0, b1, b2);
+  e = kappa * b0;
+  const double kb1 = kappa * b1, kb2 = kappa * b2;
+  // u-space barrier gradient and Hessian (zero when inactive)
+  double gu[3 * NU];
+#pragma unroll
+  for (int r = 0; r < 3 * NU; ++r) gu[r] = kb1 * D.g[r];
+#pragma unroll
+  for (int r = 0; r < 3 * NU; ++r)
+#pragma unroll
+    for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
+  // coefficients M[U][fl[k]] selected at run time from the compile-time table
+  double Mf[NU][K];
+#pragma unroll
+  for (int U = 0; U < NU; ++U)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double m = 0.0;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) m = (fl[k] == q) ? double(Topo<TYPE>::M(U, q)) : m;
+      Mf[U][k] = m;
+    }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double g[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int U = 0; U < NU; ++U) acc = fma(Mf[U][k], gu[3 * U + i], acc);
+      g[i] = acc;
+    }
+    grad_sink(k, g);
+  }
+  if constexpr (K == NV && !EXACT) {
+    // all vertices free: project in the Helmert basis (translation-free subspace)
+    constexpr int NR = NV - 1;
+    double R[NU][NR];
+#pragma unroll
+    for (int U = 0; U < NU; ++U)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc += double(Topo<TYPE>::M(U, q)) * helmert(q, j);
+        R[U][j] = acc;
+      }
+    Sym<3 * NR, double> A;
+#pragma unroll
+    for (int I = 0; I < NR; ++I)
+#pragma unroll
+      for (int J = I; J < NR; ++J)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            if (I == J && l < i) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int U = 0; U < NU; ++U)
+#pragma unroll
+              for (int W = 0; W < NU; ++W) acc = fma(R[U][I] * R[W][J], D.H(3 * U + i, 3 * W + l), acc);
+            A(3 * I + i, 3 * J + l) = acc;
+          }
+    psd_project<3 * NR, double>(A);
+#pragma unroll
+    for (int p = 0; p < NV; ++p)
+#pragma unroll
+      for (int q = p; q < NV; ++q) {
+        double B[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            double acc = 0.0;
+#pragma unroll
+            for (int I = 0; I < NR; ++I)
+#pragma unroll
+              for (int J = 0; J < NR; ++J) acc = fma(helmert(p, I) * helmert(q, J), A(3 * I + i, 3 * J + l), acc);
+            B[i][l] = acc;
+          }
+        if (p == q) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int l = i + 1; l < 3; ++l) {
+              const double m = 0.5 * (B[i][l] + B[l][i]);
+              B[i][l] = m;
+              B[l][i] = m;
+            }
+        }
+        block_sink(p, q, B);
+      }
+  } else {
+    // free principal submatrix: block (I, J) = sum_UW M[U][fl_I] M[W][fl_J] H_u(U, W)
+    Sym<3 * K, double> A;
+#pragma unroll
+    for (int I = 0; I < K; ++I)
+#pragma unroll
+      for (int J = I; J < K; ++J)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            if (I == J && l < i) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int U = 0; U < NU; ++U)
+#pragma unroll
+              for (int W = 0; W < NU; ++W) acc = fma(Mf[U][I] * Mf[W][J], D.H(3 * U + i, 3 * W + l), acc);
+            A(3 * I + i, 3 * J + l) = acc;
+          }
+    if (!EXACT) psd_project<3 * K, double>(A);
+#pragma unroll
+    for (int I = 0; I < K; ++I)
+#pragma unroll
+      for (int J = I; J < K; ++J) {
+        double B[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) B[i][l] = A(3 * I + i, 3 * J + l);
+        block_sink(I, J, B);
+      }
+  }
+  return ok;
+}
+
+}  // namespace cmath
+}  // namespace yasps

@@ -1,0 +1,137 @@
+// Internal launch interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace yasps {
+
+constexpr int EVAL_BLOCK = 128;   // threads per workgroup of the stencil kernels
+constexpr int RED_BLOCK = 256;    // threads per workgroup of reductions / vector kernels
+
+// Elastic (stable Neo-Hookean) tets.
+struct SnhArgs {
+  int n_free;
+  const double* x;        // (n_free, 3)
+  const double* x_fixed;  // (n_fixed, 3)
+  int nt;
+  const int32_t* idx;     // [4][nt]
+  const double* dm_inv;   // [9][nt]
+  const double* vol;      // [nt]
+  const double* mu_lam;   // [2][nt] or null
+  double mu, lam;
+  double h2;
+  const int32_t* spos;    // [10][nt] staged block position of each local pair, -1 = none
+  const int32_t* gpos;    // [4][nt] staged gradient position of each vertex, -1 = fixed
+  double* blk;            // staged 3x3 blocks (9 doubles each)
+  float* blk32;           // staged blocks in float32 (precision form) or null
+  double* grd;            // staged gradient 3-vectors
+  double* e_part;         // one energy partial per workgroup
+  uint32_t* flags;
+};
+void launch_snh_eval(const SnhArgs& a, bool exact, bool mixed, hipStream_t s);
+// Energy only at x (line search); writes one partial per workgroup.
+void launch_snh_energy(const SnhArgs& a, hipStream_t s);
+// grad_theta[t] = -lambda_t . d/dx (Psi_t / theta_t)
+void launch_snh_theta_adjoint(const SnhArgs& a, const double* lambda, const double* theta,
+                              double* out, hipStream_t s);
+
+// Inertia (dynamic) or gravity potential (static) per free vertex.
+struct InertiaArgs {
+  int n;
+  const double* x;
+  const double* x_tilde;
+  const double* mass;
+  int is_static;
+  double g[3];
+  const int32_t* spos;  // [n] staged position of m I in the static part (-1 when static)
+  const int32_t* gpos;  // [n]
+  double* blk;
+  float* blk32;
+  double* grd;
+  double* e_part;
+  uint32_t* flags;
+};
+void launch_inertia(const InertiaArgs& a, hipStream_t s);
+void launch_inertia_energy(const InertiaArgs& a, hipStream_t s);
+
+// Contact stencils, processed in groups of equal (type, number of free vertices)
+// stored contiguously.
+struct ContactArgs {
+  int n_free;
+  const double* x;
+  const double* x_fixed;
+  int begin, end;        // stencil range of this group in the sorted arrays
+  int nc;                // all stencils (stride of the SoA arrays)
+  const int32_t* idx;    // [4][nc]
+  const int32_t* spos;   // [10][nc] canonical local-pair order
+  const int32_t* gpos;   // [4][nc]
+  double kappa, dhat;
+  int barrier;           // 0 squared-log, 1 classic
+  double* blk;
+  double* grd;
+  double* e_part;        // per workgroup of this group (offset by the caller)
+  double* d_out;         // [nc] squared distance
+  double* dmin_part;     // per workgroup minimum of d
+  double* nact_part;     // per workgroup count of active stencils
+  uint32_t* flags;
+};
+void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, hipStream_t s);
+// Line-search trial at y = x + alpha p: energy partials, feasibility (d > 0 and
+// PT/EE side kept) per workgroup.
+void launch_contact_energy(int type, const ContactArgs& a, const double* x0, double* bad_part,
+                           hipStream_t s);
+
+// Segmented sums of staged contributions (atomic-free assembly).
+void launch_segsum_blocks(int nslots, const int32_t* cptr, const double* staged, double* out,
+                          hipStream_t s);
+void launch_segsum_blocks_f32(int nslots, const int32_t* cptr, const float* staged, float* out,
+                              hipStream_t s);
+void launch_segsum_grad(int n, const int32_t* gptr_s, const double* stg_s, const int32_t* gptr_d,
+                        const double* stg_d, double* grad, hipStream_t s);
+// Block-Jacobi inverse of static + dynamic diagonal blocks.
+void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
+                          const int32_t* ddiag, const double* vals_d, double* inv,
+                          uint32_t* flags, hipStream_t s);
+void launch_block_inverse_f32(int n, const int32_t* row_ptr_s, const float* vals_s,
+                              const int32_t* ddiag, const float* vals_d, double* inv,
+                              uint32_t* flags, hipStream_t s);
+
+// Deterministic final sums of per-workgroup partials: out[k] = sum (or min) of
+// parts[off[k] .. off[k+1]).
+void launch_finalize(int nseg, const int* off_host, const double* parts, const int* kind_host,
+                     double* out, hipStream_t s);
+
+// Vector helpers.
+void launch_axpy_to(int n3, const double* x, double alpha, const double* p, double* y,
+                    hipStream_t s);                            // y = x + alpha p
+void launch_scale(int n3, const double* x, double a, double* y, hipStream_t s);  // y = a x
+void launch_max_norm3(int n, const double* p, double* part, int nblk, hipStream_t s);
+// per-workgroup partial sums of a . b (grid-stride, fixed order)
+void launch_dot(int n3, const double* a, const double* b, double* part, int nblk, hipStream_t s);
+
+// PCG.
+struct PcgMatrix {
+  int n;
+  // static part
+  const int32_t* rp_s; const int32_t* ci_s; const double* v_s; const float* v_s32;
+  const int32_t* tp_s; const int32_t* tslot_s; const int32_t* trow_s;
+  // dynamic part
+  const int32_t* rp_d; const int32_t* ci_d; const double* v_d; const float* v_d32;
+  const int32_t* tp_d; const int32_t* tslot_d; const int32_t* trow_d;
+  const double* minv;  // (n, 9)
+};
+struct PcgState;  // device-side scalars, defined in pcg.hip
+// Optional per-launch timing hook (kernel class ids as in yasps.h).
+struct LaunchTimer {
+  virtual void begin(int cls) = 0;
+  virtual void end() = 0;
+};
+int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter,
+              bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
+              LaunchTimer* tm);
+size_t pcg_workspace_bytes(int n);
+// y = H x (both parts, symmetric upper storage) through the solver's SpMV kernel.
+void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s);
+
+}  // namespace yasps

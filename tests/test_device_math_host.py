@@ -1,0 +1,75 @@
+"""The GPU kernels' per-stencil contact arithmetic (contact_math.h, compiled
+for the host by hipcc) against the oracle, on the CPU: every type, every number
+of free vertices, projected and exact Hessians."""
+import ctypes as C
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import native_build
+from oracle import energy as en
+from oracle import local
+
+torch.set_default_dtype(torch.float64)
+KAPPA, DHAT = 1e4, 1e-3
+NV = (4, 4, 3, 2)
+
+
+@pytest.fixture(scope="module")
+def harness():
+    L = native_build.load("contact_host")
+    L.contact_host.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                               C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.contact_host.restype = C.c_int
+    return L
+
+
+def stencils(t, n, seed):
+    rng = np.random.default_rng(seed)
+    if t == 0:
+        base = np.array([[0.3, 0.3, 0.4], [0, 0, 0], [1, 0, 0], [0, 1, 0]]) * 0.05
+    elif t == 1:
+        base = np.array([[0.0, 0.5, 0.0], [1.0, 0.5, 0.0], [0.5, 0.0, 0.4], [0.5, 1.0, 0.4]]) * 0.05
+    elif t == 2:
+        base = np.array([[0.5, 0.3, 0.0], [0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0, 0, 0]]) * 0.05
+    else:
+        base = np.array([[0.0, 0.0, 0.0], [0.015, 0.01, 0.0], [0, 0, 0], [0, 0, 0]])
+    x = base[None] + 0.002 * rng.standard_normal((n, 4, 3))
+    x[:, NV[t]:] = 0.0
+    return x
+
+
+def run_host(L, t, K, exact, x, fl):
+    e, d = C.c_double(), C.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    xs = np.ascontiguousarray(x, np.float64)
+    f = np.ascontiguousarray(fl, np.int32)
+    rc = L.contact_host(t, K, int(exact), xs.ctypes.data, f.ctypes.data, KAPPA, DHAT, 0, C.byref(e), C.byref(d),
+                        g.ctypes.data, H.ctypes.data)
+    assert rc == 0
+    return e.value, d.value, g.reshape(4, 3), H.reshape(12, 12)
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3])
+@pytest.mark.parametrize("exact", [False, True])
+def test_contact_math_matches_oracle(harness, t, exact):
+    n = 6
+    x = stencils(t, n, 100 + t)
+    for K in range(1, NV[t] + 1):
+        for freeset in itertools.combinations(range(NV[t]), K):
+            fl = list(freeset) + [0] * (4 - K)
+            free = torch.zeros(n, 4, dtype=torch.bool)
+            free[:, list(freeset)] = True
+            Eo, go, Ho, do = local.contact_local(torch.tensor(x), torch.full((n,), t), free, KAPPA, DHAT,
+                                                 local.EXACT if exact else local.PROJECTED)
+            for s in range(n):
+                e, d, g, H = run_host(harness, t, K, exact, x[s], fl)
+                sc = np.abs(Ho[s].numpy()).max() + 1e-300
+                assert abs(d - float(do[s])) <= 1e-12 * float(do[s])
+                assert abs(e - float(Eo[s])) <= 1e-10 * abs(float(Eo[s])) + 1e-300
+                assert np.abs(g - go[s].numpy()).max() <= 1e-10 * np.abs(go[s].numpy()).max()
+                err = np.abs(H - Ho[s].numpy()).max()
+                assert err <= 1e-10 * sc, (t, K, freeset, exact, s, err, sc)

@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: bit-exact pattern and slot map; float64 values within 1e-10 of the sum of
+absolute contributions per entry (energies: of the per-stencil magnitudes);
+PCG iteration counts within +-2 of the oracle's; line-search step lengths equal.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import assemble as oasm
+from oracle import newton as onewton
+from oracle import pcg as opcg
+from paper_2605_23088_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def case(name):
+    if name == "C1":
+        return synth.c1_two_cubes()
+    if name == "block":
+        return synth.small_block(seed=11, nx=5, ny=4, nz=3, n_pt=150, n_ee=150)
+    if name == "block_mid":
+        return synth.small_block(seed=12, nx=10, ny=9, nz=8, n_pt=600, n_ee=500)
+    if name == "static":
+        return synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200)
+    raise KeyError(name)
+
+
+CASES = ["C1", "block", "block_mid", "static"]
+_cache = {}
+
+
+def setup(name):
+    if name not in _cache:
+        from paper_2605_23088_amd.yasps import Yasps
+        p = case(name)
+        o = oasm.Oracle(p)
+        g = Yasps(p)
+        _cache[name] = (p, o, g)
+    return _cache[name]
+
+
+def xdev(p, x=None):
+    return torch.as_tensor(p["x0"] if x is None else x, dtype=torch.float64, device="cuda").contiguous()
+
+
+def abs_sums(o, ev):
+    """Per-entry error scales: the sum, over the contributions to an entry, of the
+    contributing stencil's local-Hessian Frobenius norm (the rounding of an
+    eigen-projection is proportional to the norm of the whole local matrix, not
+    to the entry), and likewise the contributing stencils' gradient norms."""
+    def fro(H):
+        return np.broadcast_to(np.sqrt((H * H).sum(axis=(1, 2)))[:, None, None], H.shape)
+
+    def gnorm(g):
+        return np.broadcast_to(np.sqrt((g * g).sum(axis=(1, 2)))[:, None, None], g.shape)
+
+    vs = o._scatter_blocks(len(o.ci_s), o.tet_idx, o.pairs_t, o.slot_t, fro(ev["H_t"]))
+    vd = o._scatter_blocks(len(o.ci_d), o.cidx, o.pairs_c, o.slot_c, fro(ev["H_c"]))
+    if not o.static:
+        vs[o.rp_s[:-1]] += np.abs(o.mass)[:, None, None] * np.eye(3)[None]
+    # a tet's gradient is a difference of stress terms of size ~ h^2 V (mu + lam) |F| |Dm^-1|,
+    # which cancel exactly at rest: its rounding scales with those terms
+    st = tet_stress_scale(o)
+    gt = np.maximum(gnorm(ev["g_t"]), np.broadcast_to(st[:, None, None], ev["g_t"].shape))
+    g = np.abs(ev["g_inertia"]) + o._scatter_grad(o.tet_idx, gt) + o._scatter_grad(o.cidx, gnorm(ev["g_c"]))
+    return vs, vd, g
+
+
+def tet_stress_scale(o):
+    h2 = float(o.p["h"]) ** 2
+    dm = o.dm_inv.numpy()
+    return h2 * o.vol.numpy() * (o.mu.numpy() + o.lam.numpy()) * np.sqrt((dm * dm).sum(axis=(1, 2))) * 4.0
+
+
+def within(gpu, ref, scale, tol=TOL):
+    err = np.abs(np.asarray(gpu) - np.asarray(ref))
+    bad = err > tol * np.asarray(scale) + 1e-300
+    assert not bad.any(), f"{bad.sum()} entries off; worst {err.max():.3e} (scale {np.max(scale):.3e})"
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_pattern_bit_exact(name):
+    p, o, g = setup(name)
+    rp, ci, sl = g.pattern(0)
+    assert np.array_equal(rp, o.rp_s) and np.array_equal(ci, o.ci_s) and np.array_equal(sl, o.slot_t)
+    rp, ci, sl = g.pattern(1)
+    assert np.array_equal(rp, o.rp_d) and np.array_equal(ci, o.ci_d) and np.array_equal(sl, o.slot_c)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("exact", [False, True])
+def test_eval_and_assembly_parity(name, exact):
+    p, o, g = setup(name)
+    hess = oasm.EXACT if exact else oasm.PROJECTED
+    ev = o.eval(p["x0"], hess)
+    asm = o.assemble(ev)
+    info = g.eval(xdev(p), exact=exact)
+    e_scale = np.maximum(np.abs(ev["E_t"]), tet_stress_scale(o) / np.sqrt((o.dm_inv.numpy() ** 2).sum(axis=(1, 2))))
+    mag_e = e_scale.sum() + np.abs(ev["E_c"]).sum() + abs(ev["E_inertia"])
+    assert abs(info["e_elastic"] - ev["E_elastic"]) <= TOL * e_scale.sum() + 1e-300
+    assert abs(info["e_contact"] - ev["E_contact"]) <= TOL * np.abs(ev["E_c"]).sum() + 1e-300
+    assert abs(info["energy"] - ev["E"]) <= TOL * mag_e
+    if len(ev["d"]):
+        assert info["min_d"] == pytest.approx(ev["d"].min(), rel=1e-12)
+        assert info["n_active"] == int((ev["d"] < p["dhat"]).sum())
+    out = g.assemble()
+    vs, vd, gs = abs_sums(o, ev)
+    within(out["values_s"].cpu().numpy(), asm["values_s"], vs)
+    if len(o.ci_d):
+        within(out["values_d"].cpu().numpy(), asm["values_d"], vd)
+    within(out["grad"].cpu().numpy(), asm["grad"], gs)
+    D = o.diag_blocks(asm)
+    Minv = opcg.block_inverse(D)
+    bi = out["block_inv"].cpu().numpy()
+    cond = np.linalg.cond(D)
+    assert np.all(np.abs(bi - Minv) <= 1e-12 * cond[:, None, None] * np.abs(Minv).max(axis=(1, 2))[:, None, None])
+    # stored diagonal blocks are exactly symmetric
+    d = out["values_s"].cpu().numpy()[o.rp_s[:-1]]
+    assert np.array_equal(d, d.transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_pcg_parity(name):
+    p, o, g = setup(name)
+    ev = o.eval(p["x0"])
+    asm = o.assemble(ev)
+    H = o.csr(asm)
+    Minv = opcg.block_inverse(o.diag_blocks(asm))
+    b = -asm["grad"].ravel()
+    x_o, it_o, rel_o, st_o = opcg.pcg(lambda v: H @ v, b, Minv, 1e-8, 20000)
+    g.eval(xdev(p))
+    g.assemble(copy=False)
+    bd = torch.as_tensor(b, device="cuda").view(-1, 3).contiguous()
+    x, info = g.pcg(bd, rtol=1e-8)
+    assert info["status"] == 0 and st_o == "ok"
+    assert abs(info["iters"] - it_o) <= 2, (info["iters"], it_o)
+    xg = x.cpu().numpy().ravel()
+    r = np.linalg.norm(H @ xg - b) / np.linalg.norm(b)
+    assert r <= 1e-8 * 1.05, r
+    # tight solves agree with each other
+    x2, info2 = g.pcg(bd, rtol=1e-13)
+    x_t, _, _, _ = opcg.pcg(lambda v: H @ v, b, Minv, 1e-13, 20000)
+    assert np.linalg.norm(x2.cpu().numpy().ravel() - x_t) <= 1e-9 * np.linalg.norm(x_t)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_newton_step_parity(name):
+    p, o, g = setup(name)
+    x1_o, info_o = onewton.newton_step(o, p["x0"], rtol=1e-10)
+    x = xdev(p)
+    info = g.newton_step(x, rtol=1e-10)
+    assert info["status"] == 0
+    # same initial bound (it depends on max |p_v|, solved to 1e-10) and the same halvings
+    assert info["alpha0"] == pytest.approx(onewton.initial_step(o, p["x0"], info_o["p"]), rel=1e-8)
+    assert round(np.log2(info["alpha0"] / info["alpha"])) == round(np.log2(
+        onewton.initial_step(o, p["x0"], info_o["p"]) / info_o["alpha"]))
+    mag = abs(info_o["E0"]) + 1e-300
+    assert abs(info["e0"] - info_o["E0"]) <= 1e-10 * mag
+    assert abs(info["e1"] - info_o["E1"]) <= 1e-8 * mag
+    assert np.abs(x.cpu().numpy() - x1_o).max() <= 1e-7 * np.abs(info_o["p"]).max() + 1e-15
+
+
+def test_bitwise_reproducible():
+    p, o, g = setup("block_mid")
+    outs = []
+    for _ in range(3):
+        g.eval(xdev(p))
+        a = g.assemble()
+        outs.append({k: v.cpu().numpy().tobytes() for k, v in a.items()})
+    assert outs[0] == outs[1] == outs[2]
+    b = -a["grad"].contiguous()
+    x1, i1 = g.pcg(b)
+    x2, i2 = g.pcg(b)
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+
+
+def test_error_paths():
+    from paper_2605_23088_amd.yasps import E_ARG, E_BREAKDOWN, E_DOMAIN, E_NOCONV, E_NONFINITE, Yasps, YaspsError
+    p, o, g = setup("block")
+    x = xdev(p)
+    # NaN in x -> E_NONFINITE
+    xb = x.clone()
+    xb[3, 1] = float("nan")
+    assert g.eval(xb, allow=(E_NONFINITE,))["status"] == E_NONFINITE
+    # max_iter = 1 -> E_NOCONV with an iterate and a residual
+    g.eval(x)
+    a = g.assemble()
+    xs, info = g.pcg(-a["grad"].contiguous(), rtol=1e-12, max_iter=1)
+    assert info["rc"] == E_NOCONV and info["iters"] == 1 and info["rel_residual"] > 0
+    assert torch.isfinite(xs).all()
+    # out-of-range and repeated ids -> E_ARG
+    bad = p["cidx"].copy()
+    bad[0, 1] = bad[0, 2]
+    with pytest.raises(YaspsError) as e:
+        g.set_contacts(p["ctype"], bad)
+    assert e.value.status == E_ARG
+    bad = p["cidx"].copy()
+    bad[1, 0] = p["n_free"] + p["x_fixed"].shape[0] + 5
+    with pytest.raises(YaspsError):
+        g.set_contacts(p["ctype"], bad)
+    # a point exactly on its triangle's plane -> E_DOMAIN
+    q = dict(p)
+    xf = p["x_fixed"].copy()
+    s = int(np.flatnonzero(p["ctype"] == 0)[0])
+    fid = p["cidx"][s, 0] - p["n_free"]
+    tri = p["cidx"][s, 1:]
+    xf[fid] = p["x0"][tri].mean(axis=0)
+    q["x_fixed"] = xf
+    gq = Yasps(q)
+    assert gq.eval(xdev(q), allow=(E_DOMAIN,))["status"] == E_DOMAIN
+    gq.close()
+    # negative masses, no tets or contacts: an indefinite H -> E_BREAKDOWN
+    r = dict(p)
+    r["mass"] = -np.abs(p["mass"])
+    r["tet_idx"] = np.zeros((0, 4), np.int32)
+    r["dm_inv"] = np.zeros((0, 3, 3))
+    r["vol"] = np.zeros(0)
+    gr = Yasps(r, contacts=False)
+    gr.eval(xdev(r))
+    ar = gr.assemble()
+    _, info = gr.pcg(ar["grad"].contiguous() + 1.0, allow=(E_BREAKDOWN,))
+    assert info["rc"] == E_BREAKDOWN
+    gr.close()
+    g.set_contacts(p["ctype"], p["cidx"])  # restore
+
+
+def test_empty_contacts_and_no_tets():
+    from paper_2605_23088_amd.yasps import Yasps
+    p = synth.small_block(seed=3, nx=3, ny=2, nz=2, n_pt=0, n_ee=0)
+    o = oasm.Oracle(p)
+    g = Yasps(p)
+    ev = o.eval(p["x0"])
+    info = g.eval(xdev(p))
+    assert abs(info["energy"] - ev["E"]) <= TOL * (np.abs(ev["E_t"]).sum() + abs(ev["E_inertia"]))
+    a = g.assemble()
+    asm = o.assemble(ev)
+    vs, _, gs = abs_sums(o, ev)
+    within(a["values_s"].cpu().numpy(), asm["values_s"], vs)
+    within(a["grad"].cpu().numpy(), asm["grad"], gs)
+    x = xdev(p)
+    ni = g.newton_step(x)
+    assert ni["status"] == 0 and ni["alpha0"] == 1.0
