@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 
 # Algorithmic work per unit ("Measurement"):
-SNH_FLOPS_PER_TET = 3.5e4        # 9x9 Jacobi eigen-projection dominated
+SNH_FLOPS_PER_TET = 4.0e3        # closed-form F-space eigensystem: 3x3 SVD, 9 rank-one modes, J_F map
 CONTACT_FLOPS = {0: 3.0e4, 1: 1.0e4, 2: 3.0e4, 3: 1.0e4}  # PT 9x9, EE 6x6 eigenproblems
 
 

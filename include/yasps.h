@@ -143,6 +143,8 @@ typedef struct {
   int32_t max_iter;     /* PCG iteration cap (default 20000) */
   int32_t max_halvings; /* line-search halvings (default 40) */
   double armijo;        /* sufficient-decrease constant (default 1e-4) */
+  double tie_rtol;      /* a trial with |E - E(x)| <= tie_rtol |E(x)| also counts as a decrease
+                           (for solves driven to the rounding floor of E); 0 = plain Armijo */
 } yasps_newton_params;
 
 typedef struct {
@@ -150,6 +152,8 @@ typedef struct {
   double alpha;        /* accepted step length (0 if none) */
   double alpha0;       /* initial step bound min(1, 0.4 min sqrt(d) / max |p_v|) */
   double grad_dot_p;   /* g . p (< 0 for a descent direction) */
+  double grad_max;     /* max_v |g_v| at the start of the step (stop rules) */
+  double step_max;     /* max_v |alpha p_v| of the accepted step */
   int32_t cg_iters;
   double cg_rel_residual;
   int32_t cg_status;

@@ -36,7 +36,10 @@ def initial_step(orc, x, p):
     return min(1.0, 0.4 * np.sqrt(dmin) / pmax)
 
 
-def line_search(orc, x, p, E0, g, max_halvings=40):
+def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
+    """tie_rtol > 0: a trial whose energy differs from E0 by at most
+    tie_rtol |E0| also counts as sufficient decrease (solves driven to the
+    rounding floor of E, where Armijo can no longer decide)."""
     alpha = initial_step(orc, x, p)
     gp = float(g.ravel() @ p.ravel())
     s0 = np.sign(orc.sides(x))
@@ -51,15 +54,15 @@ def line_search(orc, x, p, E0, g, max_halvings=40):
             ok = bool((d > 0).all()) and bool((st == s0).all())
         if ok:
             E1 = orc.energy(xt)
-            if E1 <= E0 + 1e-4 * alpha * gp:
+            if E1 <= E0 + 1e-4 * alpha * gp or abs(E1 - E0) <= tie_rtol * abs(E0):
                 return alpha, xt, E1, trials
         alpha *= 0.5
     return 0.0, x, E0, trials
 
 
-def newton_step(orc, x, rtol=1e-8, max_iter=20000):
+def newton_step(orc, x, rtol=1e-8, max_iter=20000, tie_rtol=0.0):
     x = np.asarray(x, np.float64).reshape(orc.n, 3)
     ev, asm, H, p, it, rel, status = solve_direction(orc, x, rtol, max_iter)
-    alpha, x1, E1, trials = line_search(orc, x, p, ev["E"], asm["grad"])
+    alpha, x1, E1, trials = line_search(orc, x, p, ev["E"], asm["grad"], tie_rtol=tie_rtol)
     return x1, dict(E0=ev["E"], E1=E1, alpha=alpha, cg_iters=it, cg_rel=rel,
                     cg_status=status, ls_trials=trials, p=p, grad=asm["grad"])

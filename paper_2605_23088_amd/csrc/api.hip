@@ -121,7 +121,7 @@ struct yasps_ctx {
           *ddiag = nullptr;
   int nblk_d = 0, ngrd_d = 0;
   double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
-  float* vals_d32 = nullptr;
+  float *stg_d32 = nullptr, *vals_d32 = nullptr;
 
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
@@ -208,7 +208,7 @@ PartsLayout parts_layout(const yasps_ctx* c) {
 
 yasps_status ensure_parts(yasps_ctx* c) {
   const PartsLayout L = parts_layout(c);
-  const int need = std::max(L.off[5], 2 * grid_of(std::max(c->n, 1), RED_BLOCK)) + 8;
+  const int need = std::max(L.off[5], 3 * grid_of(std::max(c->n, 1), RED_BLOCK)) + 8;
   if (need <= c->nparts_alloc) return YASPS_OK;
   HIPCHK(c, dalloc(c->allocs, &c->parts, (size_t)need));
   c->nparts_alloc = need;
@@ -271,6 +271,7 @@ ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, in
   a.dhat = c->P.dhat;
   a.barrier = c->prm.barrier;
   a.blk = c->stg_d;
+  a.blk32 = c->stg_d32;
   a.grd = c->gstg_d;
   const PartsLayout L = parts_layout(c);
   a.e_part = c->parts + L.off[2] + part_off;
@@ -359,7 +360,6 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (prm.proj != YASPS_F_SPACE) return fail(nullptr, YASPS_E_UNIMPL, "only F-space Neo-Hookean projection is built");
   if (prm.hessian != YASPS_PROJECTED && prm.hessian != YASPS_EXACT) return fail(nullptr, YASPS_E_ARG, "unknown hessian mode");
   if (prm.barrier != YASPS_SQLOG && prm.barrier != YASPS_IPC_CLASSIC) return fail(nullptr, YASPS_E_ARG, "unknown barrier");
-  if (prm.precision == YASPS_MIXED) return fail(nullptr, YASPS_E_UNIMPL, "mixed precision form not built yet");
 
   yasps_ctx* c = new (std::nothrow) yasps_ctx();
   if (!c) return fail(nullptr, YASPS_E_ARG, "out of host memory");
@@ -406,9 +406,14 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   UP(c->lead_gpos, st.lead_gpos);
   UP(c->cptr_s, st.cptr);
   UP(c->gptr_s, st.gptr);
-  AL(c->stg_s, 9 * (size_t)st.nblocks);
+  if (prm.precision == YASPS_MIXED) {
+    AL(c->stg_s32, 9 * (size_t)st.nblocks);
+    AL(c->vals_s32, 9 * (size_t)c->hpat_s.nnzb);
+  } else {
+    AL(c->stg_s, 9 * (size_t)st.nblocks);
+    AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
+  }
   AL(c->gstg_s, 3 * (size_t)st.ngrads);
-  AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
   AL(c->grad, 3 * (size_t)c->n);
   AL(c->minv, 9 * (size_t)c->n);
   AL(c->scal, 64);
@@ -500,9 +505,14 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   HIPCHK(c, upload(c->dyn_allocs, &c->cptr_d, st.cptr, c->stream));
   HIPCHK(c, upload(c->dyn_allocs, &c->gptr_d, st.gptr, c->stream));
   HIPCHK(c, upload(c->dyn_allocs, &c->ddiag, ddiag, c->stream));
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
+  if (c->prm.precision == YASPS_MIXED) {
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)st.nblocks));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)c->hpat_d.nnzb));
+  } else {
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)c->hpat_d.nnzb));
+  }
   HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)st.ngrads));
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)c->hpat_d.nnzb));
   HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
   s = ensure_parts(c);
   if (s) return s;
@@ -521,7 +531,7 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
   launch_inertia(inertia_args(c, x), c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_SNH);
-  launch_snh_eval(snh_args(c, x), exact, false, c->stream);
+  launch_snh_eval(snh_args(c, x), exact, c->prm.precision == YASPS_MIXED, c->stream);
   c->prof.end();
   int off = 0;
   c->prof.begin(YASPS_K_CONTACT);
@@ -556,15 +566,25 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
 yasps_status run_assemble(yasps_ctx* c) {
   HIPCHK(c, hipMemsetAsync(c->flags, 0, 4, c->stream));
   c->prof.begin(YASPS_K_ASSEMBLE);
-  launch_segsum_blocks(c->ps.nnzb, c->cptr_s, c->stg_s, c->vals_s, c->stream);
+  const bool mixed = c->prm.precision == YASPS_MIXED;
   const bool dyn = c->nc > 0;
-  if (dyn) launch_segsum_blocks(c->pd.nnzb, c->cptr_d, c->stg_d, c->vals_d, c->stream);
-  launch_segsum_grad(c->n, c->gptr_s, c->gstg_s, dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad,
-                     c->stream);
+  if (mixed) {
+    launch_segsum_blocks_f32(c->ps.nnzb, c->nblk_s, c->cptr_s, c->stg_s32, c->vals_s32, c->stream);
+    if (dyn) launch_segsum_blocks_f32(c->pd.nnzb, c->nblk_d, c->cptr_d, c->stg_d32, c->vals_d32, c->stream);
+  } else {
+    launch_segsum_blocks(c->ps.nnzb, c->nblk_s, c->cptr_s, c->stg_s, c->vals_s, c->stream);
+    if (dyn) launch_segsum_blocks(c->pd.nnzb, c->nblk_d, c->cptr_d, c->stg_d, c->vals_d, c->stream);
+  }
+  launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
+                     dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
-  launch_block_inverse(c->n, c->ps.rp, c->vals_s, dyn ? c->ddiag : nullptr, dyn ? c->vals_d : nullptr, c->minv,
-                       c->flags, c->stream);
+  if (mixed)
+    launch_block_inverse_f32(c->n, c->ps.rp, c->vals_s32, dyn ? c->ddiag : nullptr, dyn ? c->vals_d32 : nullptr,
+                             c->minv, c->flags, c->stream);
+  else
+    launch_block_inverse(c->n, c->ps.rp, c->vals_s, dyn ? c->ddiag : nullptr, dyn ? c->vals_d : nullptr, c->minv,
+                         c->flags, c->stream);
   c->prof.end();
   HIPCHK(c, hipGetLastError());
   return YASPS_OK;
@@ -620,13 +640,14 @@ yasps_status yasps_assemble_bsr(yasps_ctx* c, yasps_bsr_view* view) {
     view->n_rows = c->n;
     view->nnzb_static = c->ps.nnzb;
     view->nnzb_dynamic = c->nc ? c->pd.nnzb : 0;
+    const bool mixed = c->prm.precision == YASPS_MIXED;
     view->row_ptr_s = c->ps.rp;
     view->col_idx_s = c->ps.ci;
-    view->values_s = c->vals_s;
+    view->values_s = mixed ? (const void*)c->vals_s32 : (const void*)c->vals_s;
     view->row_ptr_d = c->nc ? c->pd.rp : nullptr;
     view->col_idx_d = c->nc ? c->pd.ci : nullptr;
-    view->values_d = c->nc ? c->vals_d : nullptr;
-    view->values_are_f32 = 0;
+    view->values_d = c->nc ? (mixed ? (const void*)c->vals_d32 : (const void*)c->vals_d) : nullptr;
+    view->values_are_f32 = mixed ? 1 : 0;
     view->grad = c->grad;
     view->block_inv = c->minv;
   }
@@ -642,7 +663,8 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
   double rel = 0.0;
   int status = 0;
   const int it =
-      pcg_solve(pcg_matrix(c), b, x, rtol, max_iter, false, c->pcg_work, &rel, &status, c->stream, &c->prof);
+      pcg_solve(pcg_matrix(c), b, x, rtol, max_iter, c->prm.precision == YASPS_MIXED, c->pcg_work, &rel, &status,
+                c->stream, &c->prof);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipGetLastError());
@@ -658,7 +680,7 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
 
 yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_params* prm, yasps_newton_info* info) {
   if (!c || !x) return fail(c, YASPS_E_ARG, "NULL argument");
-  yasps_newton_params p{1e-8, 20000, 40, 1e-4};
+  yasps_newton_params p{1e-8, 20000, 40, 1e-4, 0.0};
   if (prm) p = *prm;
   HIPCHK(c, hipSetDevice(c->device));
   hipEvent_t ev[5];
@@ -681,8 +703,8 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);
   double rel = 0.0;
   int status = 0;
-  const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter, false, c->pcg_work, &rel, &status,
-                           c->stream, &c->prof);
+  const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter,
+                           c->prm.precision == YASPS_MIXED, c->pcg_work, &rel, &status, c->stream, &c->prof);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipEventRecord(ev[3], c->stream));
@@ -691,20 +713,22 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   ni.cg_rel_residual = rel;
   ni.cg_status = status;
   if (status == YASPS_E_BREAKDOWN) return fail(c, YASPS_E_BREAKDOWN, "PCG breakdown: p^T H p <= 0");
-  // max |p_v| and g . p on the device
+  // max |p_v|, g . p and max |g_v| on the device
   {
     const int nb = grid_of(c->n, RED_BLOCK);
     const int nd = std::min(nb, 1024);
     launch_max_norm3(c->n, c->p_dir, c->parts, nb, c->stream);
     launch_dot(3 * c->n, c->grad, c->p_dir, c->parts + nb, nd, c->stream);
-    int off[3] = {0, nb, nb + nd};
-    int kind[2] = {2, 0};
-    launch_finalize(2, off, c->parts, kind, c->scal, c->stream);
-    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    launch_max_norm3(c->n, c->grad, c->parts + nb + nd, nb, c->stream);
+    int off[4] = {0, nb, nb + nd, 2 * nb + nd};
+    int kind[3] = {2, 0, 2};
+    launch_finalize(3, off, c->parts, kind, c->scal, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double pmax = c->host_scal[0];
   const double gp = c->host_scal[1];
+  ni.grad_max = c->host_scal[2];
   ni.grad_dot_p = gp;
   double alpha = 1.0;
   if (c->nc > 0 && pmax > 0.0) alpha = std::min(1.0, 0.4 * std::sqrt(ei.min_d) / pmax);
@@ -719,7 +743,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     ++trials;
     s = trial_energy(c, x, c->x_trial, &E, &feas);
     if (s) return s;
-    if (feas && E <= ei.energy + p.armijo * alpha * gp) {
+    if (feas && (E <= ei.energy + p.armijo * alpha * gp || std::fabs(E - ei.energy) <= p.tie_rtol * std::fabs(ei.energy))) {
       accepted = true;
       E1 = E;
       break;
@@ -735,6 +759,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   (void)hipEventElapsedTime(&ni.ms_linesearch, ev[3], ev[4]);
   ni.e1 = E1;
   ni.alpha = accepted ? alpha : 0.0;
+  ni.step_max = accepted ? alpha * pmax : 0.0;
   ni.ls_trials = trials;
   if (info) *info = ni;
   if (!accepted) return fail(c, YASPS_E_LINESEARCH, "no admissible step after the maximum number of halvings");

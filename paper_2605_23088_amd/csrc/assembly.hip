@@ -15,33 +15,66 @@ namespace yasps {
 
 namespace {
 
-// One thread per (slot, component): out[9 k + c] = sum_j staged[9 j + c],
-// j over the slot's contiguous contribution range.
-template <class T, class ACC>
-__global__ __launch_bounds__(RED_BLOCK) void segsum_blocks_kernel(int nslots, const int32_t* __restrict__ cptr,
-                                                                  const T* __restrict__ stg, T* __restrict__ out) {
-  const size_t t = (size_t)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (t >= (size_t)nslots * 9) return;
-  const int k = (int)(t / 9), c = (int)(t % 9);
-  const int b = cptr[k], e = cptr[k + 1];
-  ACC acc = ACC(0);
-  for (int j = b; j < e; ++j) acc += ACC(stg[9 * (size_t)j + c]);
-  out[t] = T(acc);
+// A group of G lanes per segment: lane l sums contributions l, l + G, ... of
+// its segment (W values each, contiguous, so a group reads G consecutive
+// contributions per step), then the group combines its partial sums with a
+// fixed butterfly and lane 0 writes the W results.  Two ranges (static and
+// dynamic parts of the gradient) may be chained per segment.
+template <class T, int W, int G>
+__global__ __launch_bounds__(RED_BLOCK) void segsum_kernel(int nseg, const int32_t* __restrict__ p1,
+                                                           const T* __restrict__ s1, const int32_t* __restrict__ p2,
+                                                           const T* __restrict__ s2, T* __restrict__ out) {
+  const int seg = (blockIdx.x * RED_BLOCK + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  if (seg < nseg) {
+    for (int j = p1[seg] + lane, e = p1[seg + 1]; j < e; j += G) {
+      const T* src = s1 + (size_t)W * j;
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] += double(src[c]);
+    }
+    if (p2) {
+      for (int j = p2[seg] + lane, e = p2[seg + 1]; j < e; j += G) {
+        const T* src = s2 + (size_t)W * j;
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[c] += double(src[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] += __shfl_xor(acc[c], m, G);
+  }
+  if (seg < nseg && lane == 0) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) out[(size_t)W * seg + c] = T(acc[c]);
+  }
 }
 
-__global__ __launch_bounds__(RED_BLOCK) void segsum_grad_kernel(int n, const int32_t* __restrict__ gs,
-                                                                const double* __restrict__ ss,
-                                                                const int32_t* __restrict__ gd,
-                                                                const double* __restrict__ sd,
-                                                                double* __restrict__ grad) {
-  const size_t t = (size_t)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (t >= (size_t)n * 3) return;
-  const int v = (int)(t / 3), c = (int)(t % 3);
-  double acc = 0.0;
-  for (int j = gs[v], e = gs[v + 1]; j < e; ++j) acc += ss[3 * (size_t)j + c];
-  if (gd)
-    for (int j = gd[v], e = gd[v + 1]; j < e; ++j) acc += sd[3 * (size_t)j + c];
-  grad[t] = acc;
+// group size from the mean segment length (power of two in [4, 64])
+int group_for(long long items, int nseg) {
+  const double mean = nseg > 0 ? double(items) / nseg : 1.0;
+  int g = 4;
+  while (g < 64 && g < mean) g *= 2;
+  return g;
+}
+
+template <class T, int W>
+void launch_segsum(int nseg, const int32_t* p1, const T* s1, const int32_t* p2, const T* s2, T* out, int G,
+                   hipStream_t s) {
+  if (nseg == 0) return;
+  const size_t threads = (size_t)nseg * G;
+  const dim3 grid((unsigned)((threads + RED_BLOCK - 1) / RED_BLOCK));
+  switch (G) {
+    case 4: hipLaunchKernelGGL((segsum_kernel<T, W, 4>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+    case 8: hipLaunchKernelGGL((segsum_kernel<T, W, 8>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+    case 16: hipLaunchKernelGGL((segsum_kernel<T, W, 16>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+    case 32: hipLaunchKernelGGL((segsum_kernel<T, W, 32>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+    default: hipLaunchKernelGGL((segsum_kernel<T, W, 64>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+  }
 }
 
 template <class T>
@@ -155,26 +188,19 @@ void launch_dot(int n3, const double* a, const double* b, double* part, int nblk
   hipLaunchKernelGGL(dot_kernel, dim3(nblk), dim3(RED_BLOCK), 0, s, n3, a, b, part);
 }
 
-void launch_segsum_blocks(int nslots, const int32_t* cptr, const double* staged, double* out, hipStream_t s) {
-  if (nslots == 0) return;
-  const size_t nt = (size_t)nslots * 9;
-  hipLaunchKernelGGL((segsum_blocks_kernel<double, double>), dim3((nt + RED_BLOCK - 1) / RED_BLOCK),
-                     dim3(RED_BLOCK), 0, s, nslots, cptr, staged, out);
+void launch_segsum_blocks(int nslots, long long ncontrib, const int32_t* cptr, const double* staged, double* out,
+                          hipStream_t s) {
+  launch_segsum<double, 9>(nslots, cptr, staged, nullptr, nullptr, out, group_for(ncontrib, nslots), s);
 }
 
-void launch_segsum_blocks_f32(int nslots, const int32_t* cptr, const float* staged, float* out, hipStream_t s) {
-  if (nslots == 0) return;
-  const size_t nt = (size_t)nslots * 9;
-  hipLaunchKernelGGL((segsum_blocks_kernel<float, float>), dim3((nt + RED_BLOCK - 1) / RED_BLOCK),
-                     dim3(RED_BLOCK), 0, s, nslots, cptr, staged, out);
+void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cptr, const float* staged, float* out,
+                              hipStream_t s) {
+  launch_segsum<float, 9>(nslots, cptr, staged, nullptr, nullptr, out, group_for(ncontrib, nslots), s);
 }
 
-void launch_segsum_grad(int n, const int32_t* gptr_s, const double* stg_s, const int32_t* gptr_d,
-                        const double* stg_d, double* grad, hipStream_t s) {
-  if (n == 0) return;
-  const size_t nt = (size_t)n * 3;
-  hipLaunchKernelGGL(segsum_grad_kernel, dim3((nt + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s, n,
-                     gptr_s, stg_s, gptr_d, stg_d, grad);
+void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
+                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s) {
+  launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s);
 }
 
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s, const int32_t* ddiag,

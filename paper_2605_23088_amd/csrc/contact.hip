@@ -49,12 +49,20 @@ __global__ __launch_bounds__(EVAL_BLOCK) void contact_kernel(ContactArgs a) {
     };
     auto bsink = [&](int I, int J, const double (&B)[3][3]) {
       const int pos = a.spos[pair_index(fl[I], fl[J], NV) * nc + s];
-      double* dst = a.blk + 9 * (size_t)pos;
       const bool tr = v[fl[I]] > v[fl[J]];
+      if (a.blk32) {
+        float* dst = a.blk32 + 9 * (size_t)pos;
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int l = 0; l < 3; ++l) dst[3 * i + l] = tr ? B[l][i] : B[i][l];
+          for (int l = 0; l < 3; ++l) dst[3 * i + l] = float(tr ? B[l][i] : B[i][l]);
+      } else {
+        double* dst = a.blk + 9 * (size_t)pos;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) dst[3 * i + l] = tr ? B[l][i] : B[i][l];
+      }
     };
     const bool ok = contact_stencil<TYPE, K, EXACT>(xv, fl, a.kappa, a.dhat, a.barrier, e, d, side, gsink, bsink);
     a.d_out[s] = d;

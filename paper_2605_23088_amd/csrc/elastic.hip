@@ -19,6 +19,7 @@
 #include "blockreduce.h"
 #include "eigen.h"
 #include "kernels.h"
+#include "snh_math.h"
 
 namespace yasps {
 
@@ -107,58 +108,90 @@ YDEV constexpr int eps3(int j, int k, int m) {
   return ((j == 0 && k == 1 && m == 2) || (j == 1 && k == 2 && m == 0) || (j == 2 && k == 0 && m == 1)) ? 1 : -1;
 }
 
-struct SnhScalars {
-  double psi;
+template <class R>
+struct Invariants {
+  R f[3][3];    // columns of F
+  R cof[3][3];  // columns of cof F
+  R Ic, J, alpha, Jm, ic1, k1;
 };
 
-// Psi, dPsi/dF (P), and optionally d2Psi/dF2 (H).  Returns Psi (without h^2).
-template <class R, bool WANT_H>
-YDEV R snh_local(const Tet<R>& T, R P[3][3], Sym<9, R>* H) {
-  R f[3][3];  // columns
+template <class R>
+YDEV void invariants(const Tet<R>& T, Invariants<R>& I) {
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) f[j][i] = T.F[i][j];
-  R cof[3][3];
-  cross3(f[1], f[2], cof[0]);
-  cross3(f[2], f[0], cof[1]);
-  cross3(f[0], f[1], cof[2]);
+    for (int i = 0; i < 3; ++i) I.f[j][i] = T.F[i][j];
+  cross3(I.f[1], I.f[2], I.cof[0]);
+  cross3(I.f[2], I.f[0], I.cof[1]);
+  cross3(I.f[0], I.f[1], I.cof[2]);
   R Ic = R(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Ic = fmaR(T.F[i][j], T.F[i][j], Ic);
-  const R J = f[0][0] * cof[0][0] + f[0][1] * cof[0][1] + f[0][2] * cof[0][2];
+  I.Ic = Ic;
+  I.J = I.f[0][0] * I.cof[0][0] + I.f[0][1] * I.cof[0][1] + I.f[0][2] * I.cof[0][2];
+  I.alpha = R(1) + R(3) * T.mu / (R(4) * T.lam);
+  I.Jm = I.J - I.alpha;
+  I.ic1 = R(1) / (Ic + R(1));
+  I.k1 = T.mu * (R(1) - I.ic1);
+}
+
+// Psi (without h^2) and P = dPsi/dF.
+template <class R>
+YDEV R snh_energy_grad(const Tet<R>& T, R P[3][3]) {
+  Invariants<R> I;
+  invariants(T, I);
   const R mu = T.mu, lam = T.lam, V = T.vol;
-  const R alpha = R(1) + R(3) * mu / (R(4) * lam);
-  const R Jm = J - alpha;
-  const R psi_rest = -R(0.5) * mu * logR(R(4)) + R(0.5) * lam * (R(1) - alpha) * (R(1) - alpha);
-  const R psi = V * (R(0.5) * mu * (Ic - R(3)) - R(0.5) * mu * logR(Ic + R(1)) + R(0.5) * lam * Jm * Jm - psi_rest);
-  const R ic1 = R(1) / (Ic + R(1));
-  const R k1 = mu * (R(1) - ic1);
+  const R psi_rest = -R(0.5) * mu * logR(R(4)) + R(0.5) * lam * (R(1) - I.alpha) * (R(1) - I.alpha);
+  const R psi = V * (R(0.5) * mu * (I.Ic - R(3)) - R(0.5) * mu * logR(I.Ic + R(1)) + R(0.5) * lam * I.Jm * I.Jm -
+                     psi_rest);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[i][j] = V * (k1 * T.F[i][j] + lam * Jm * cof[j][i]);
-  if constexpr (WANT_H) {
-    const R k2 = R(2) * mu * ic1 * ic1;
-    const R kJ = lam * Jm;
-#pragma unroll
-    for (int r = 0; r < 9; ++r)
-#pragma unroll
-      for (int c = r; c < 9; ++c) {
-        const int i = r % 3, j = r / 3, l = c % 3, k = c / 3;
-        R h = k2 * f[j][i] * f[k][l] + lam * cof[j][i] * cof[k][l];
-        if (r == c) h += k1;
-        if (j != k) {
-          const int m = 3 - j - k;
-          // eps_jkm [f_m]x^T (i, l) = -eps_jkm [f_m]x (i, l)
-          h += kJ * R(-eps3(j, k, m)) * crossmat(f[m], i, l);
-        }
-        (*H)(r, c) = V * h;
-      }
-  }
+    for (int j = 0; j < 3; ++j) P[i][j] = V * (I.k1 * T.F[i][j] + lam * I.Jm * I.cof[j][i]);
   return psi;
+}
+
+// H = d2Psi/dF2 (9x9, vec column-major).
+template <class R>
+YDEV void snh_hessian(const Tet<R>& T, Sym<9, R>& H) {
+  Invariants<R> I;
+  invariants(T, I);
+  const R lam = T.lam, V = T.vol;
+  const R k2 = R(2) * T.mu * I.ic1 * I.ic1;
+  const R kJ = lam * I.Jm;
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int c = r; c < 9; ++c) {
+      const int i = r % 3, j = r / 3, l = c % 3, k = c / 3;
+      R h = k2 * I.f[j][i] * I.f[k][l] + lam * I.cof[j][i] * I.cof[k][l];
+      if (r == c) h += I.k1;
+      if (j != k) {
+        const int m = 3 - j - k;
+        // eps_jkm [f_m]x^T (i, l) = -eps_jkm [f_m]x (i, l)
+        h += kJ * R(-eps3(j, k, m)) * crossmat(I.f[m], i, l);
+      }
+      H(r, c) = V * h;
+    }
+}
+
+template <class R>
+YDEV void convert_tet(const Tet<double>& T, Tet<R>& O) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) O.v[k] = T.v[k];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) O.Dp[a][j] = R(T.Dp[a][j]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) O.F[i][j] = R(T.F[i][j]);
+  O.vol = R(T.vol);
+  O.mu = R(T.mu);
+  O.lam = R(T.lam);
 }
 
 template <class R, class OUT>
@@ -169,11 +202,27 @@ YDEV void store_block(OUT* dst, const R B[3][3], bool transpose) {
     for (int l = 0; l < 3; ++l) dst[3 * i + l] = OUT(transpose ? B[l][i] : B[i][l]);
 }
 
+// The 4 gradient rows h^2 J_F^T vec P (float64) to their staged slots.
+YDEV void scatter_grad(const SnhArgs& a, int t, const Tet<double>& T, const double P[3][3]) {
+  const int nt = a.nt;
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa) {
+    const int pos = a.gpos[aa * nt + t];
+    if (pos < 0) continue;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc = fma(T.Dp[aa][j], P[i][j], acc);
+      a.grd[3 * (size_t)pos + i] = a.h2 * acc;
+    }
+  }
+}
+
 // Writes the 10 upper 3x3 blocks h^2 J_F^T A J_F (A = projected or exact
-// d2Psi/dF2) and the 4 gradient rows h^2 J_F^T vec P to their staged slots.
+// d2Psi/dF2) to their staged slots.
 template <class R, class OUT>
-YDEV void scatter_tet(const SnhArgs& a, int t, const Tet<R>& T, const Sym<9, R>& A,
-                      const R P[3][3], OUT* blk) {
+YDEV void scatter_tet(const SnhArgs& a, int t, const Tet<R>& T, const Sym<9, R>& A, OUT* blk) {
   const int nt = a.nt;
   const R h2 = R(a.h2);
 #pragma unroll
@@ -219,18 +268,6 @@ YDEV void scatter_tet(const SnhArgs& a, int t, const Tet<R>& T, const Sym<9, R>&
       store_block(blk + 9 * (size_t)pos, B, T.v[aa] > T.v[b]);
     }
   }
-#pragma unroll
-  for (int aa = 0; aa < 4; ++aa) {
-    const int pos = a.gpos[aa * nt + t];
-    if (pos < 0) continue;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      R acc = R(0);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) acc = fmaR(T.Dp[aa][j], P[i][j], acc);
-      a.grd[3 * (size_t)pos + i] = double(h2 * acc);
-    }
-  }
 }
 
 template <class R, bool EXACT>
@@ -239,18 +276,31 @@ __global__ __launch_bounds__(EVAL_BLOCK) void snh_eval_kernel(SnhArgs a) {
   const int t = blockIdx.x * EVAL_BLOCK + threadIdx.x;
   double e = 0.0;
   if (t < a.nt) {
-    Tet<R> T;
-    const bool ok = load_tet<R>(a, t, T);
-    R P[3][3];
-    Sym<9, R> H;
-    const R psi = snh_local<R, true>(T, P, &H);
-    if (!EXACT) psd_project<9, R>(H);
-    e = a.h2 * double(psi);
+    // energy and gradient in float64; Hessian and its projection in R
+    Tet<double> T;
+    const bool ok = load_tet<double>(a, t, T);
+    {
+      double P[3][3];
+      e = a.h2 * snh_energy_grad<double>(T, P);
+      scatter_grad(a, t, T, P);
+    }
     if (!ok || !finite(e)) atomicOr(a.flags, FLAG_NONFINITE);
+    // projected: closed-form eigensystem of d2Psi/dF2 (snh_math.h); exact: the Hessian itself
+    Sym<9, R> H;
     if constexpr (sizeof(R) == 8) {
-      scatter_tet<R, double>(a, t, T, H, P, a.blk);
+      if (EXACT)
+        snh_hessian<double>(T, H);
+      else
+        snh::projected_hessian<double>(T.F, T.mu, T.lam, T.vol, H);
+      scatter_tet<double, double>(a, t, T, H, a.blk);
     } else {
-      scatter_tet<R, float>(a, t, T, H, P, a.blk32);
+      Tet<R> TR;
+      convert_tet<R>(T, TR);
+      if (EXACT)
+        snh_hessian<R>(TR, H);
+      else
+        snh::projected_hessian<R>(TR.F, TR.mu, TR.lam, TR.vol, H);
+      scatter_tet<R, float>(a, t, TR, H, a.blk32);
     }
   }
   const double s = block_sum<EVAL_BLOCK>(e, lds);
@@ -265,7 +315,7 @@ __global__ __launch_bounds__(EVAL_BLOCK) void snh_energy_kernel(SnhArgs a) {
     Tet<double> T;
     const bool ok = load_tet<double>(a, t, T);
     double P[3][3];
-    e = a.h2 * snh_local<double, false>(T, P, nullptr);
+    e = a.h2 * snh_energy_grad<double>(T, P);
     if (!ok || !finite(e)) e = __builtin_nan("");
   }
   const double s = block_sum<EVAL_BLOCK>(e, lds);
@@ -279,7 +329,7 @@ __global__ __launch_bounds__(EVAL_BLOCK) void snh_theta_kernel(SnhArgs a, const 
   Tet<double> T;
   load_tet<double>(a, t, T);
   double P[3][3];
-  snh_local<double, false>(T, P, nullptr);
+  snh_energy_grad<double>(T, P);
   double acc = 0.0;
 #pragma unroll
   for (int aa = 0; aa < 4; ++aa) {

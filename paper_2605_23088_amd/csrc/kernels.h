@@ -69,6 +69,7 @@ struct ContactArgs {
   double kappa, dhat;
   int barrier;           // 0 squared-log, 1 classic
   double* blk;
+  float* blk32;          // float32 staged blocks (precision form) instead of blk, or null
   double* grd;
   double* e_part;        // per workgroup of this group (offset by the caller)
   double* d_out;         // [nc] squared distance
@@ -83,12 +84,13 @@ void launch_contact_energy(int type, const ContactArgs& a, const double* x0, dou
                            hipStream_t s);
 
 // Segmented sums of staged contributions (atomic-free assembly).
-void launch_segsum_blocks(int nslots, const int32_t* cptr, const double* staged, double* out,
-                          hipStream_t s);
-void launch_segsum_blocks_f32(int nslots, const int32_t* cptr, const float* staged, float* out,
-                              hipStream_t s);
-void launch_segsum_grad(int n, const int32_t* gptr_s, const double* stg_s, const int32_t* gptr_d,
-                        const double* stg_d, double* grad, hipStream_t s);
+// (ncontrib = total staged contributions, used to size the lane groups)
+void launch_segsum_blocks(int nslots, long long ncontrib, const int32_t* cptr, const double* staged,
+                          double* out, hipStream_t s);
+void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cptr, const float* staged,
+                              float* out, hipStream_t s);
+void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
+                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s);
 // Block-Jacobi inverse of static + dynamic diagonal blocks.
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
                           const int32_t* ddiag, const double* vals_d, double* inv,

@@ -15,12 +15,13 @@
 //   u = M^-1 r, w = H u, gamma = r.u, delta = u.w
 //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
 //   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
-// Two kernels per iteration: (B) w = H u with the delta partials, and (C) the
-// scalar recurrences, vector updates, preconditioning and the next gamma and
-// |r|^2 partials.  The last workgroup of each kernel (detected with a counter)
-// sums the partials in a fixed order, so results are bitwise reproducible.
-// Convergence is tested on the device; the host only polls a flag every few
-// iterations.
+// Two kernels per iteration: (B) the convergence test and w = H u with the
+// delta partials, and (C) the scalar recurrences, vector updates,
+// preconditioning and the next gamma and |r|^2 partials.  Each kernel runs a
+// bounded grid (grid-stride loops) and every workgroup re-sums the previous
+// kernel's partials in the same fixed order, so there are no atomics and the
+// results are bitwise reproducible.  Convergence is tested on the device; the
+// host only polls a flag every few iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,62 +32,57 @@
 namespace yasps {
 
 constexpr int SPMV_G = 8;                       // lanes per block row
-constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup
+constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup and pass
+constexpr int MAX_WG_B = 1024;                  // workgroups of the SpMV kernel
+constexpr int MAX_WG_C = 512;                   // workgroups of the update kernel
 
+// Device scalars.  gamma / alpha are double-buffered by iteration parity;
+// `iter` is written only by the update kernel and `iter_b` only by the SpMV
+// kernel, so no kernel reads a scalar that it also writes.
 struct PcgState {
-  double gamma, gamma_prev, delta, rr, bb, alpha, tol2;
-  int iter, done, status, max_iter;
-  unsigned int counter_b, counter_c;
+  double gamma[2], alpha[2];
+  double bb, rr, tol2;
+  int iter, iter_b, done, status, max_iter;
+  int restart_at;  // iteration whose search direction restarts from u (beta = 0)
 };
 
 namespace {
 
-YDEV double load_relaxed(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-// Sum of the partials by the last workgroup to finish (fixed order).
-YDEV bool last_block(unsigned int* counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  return last;
-}
-
-YDEV double sum_partials(const double* part, int n, double* lds) {
+// Sum of n partials in a fixed order (strided per thread, then a fixed tree),
+// computed identically by every workgroup that needs it.
+YDEV double sum_partials(const double* __restrict__ part, int n, double* lds) {
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += RED_BLOCK) acc += load_relaxed(part + j);
+  for (int j = threadIdx.x; j < n; j += RED_BLOCK) acc += part[j];
   return block_sum<RED_BLOCK>(acc, lds);
 }
 
-template <class T>
-YDEV void block_mv(const T* B, const double* x, double acc[3]) {
+template <class T, class X>
+YDEV void block_mv(const T* B, const X* x, double acc[3]) {
   const double x0 = x[0], x1 = x[1], x2 = x[2];
   acc[0] = fma(double(B[0]), x0, fma(double(B[1]), x1, fma(double(B[2]), x2, acc[0])));
   acc[1] = fma(double(B[3]), x0, fma(double(B[4]), x1, fma(double(B[5]), x2, acc[1])));
   acc[2] = fma(double(B[6]), x0, fma(double(B[7]), x1, fma(double(B[8]), x2, acc[2])));
 }
-template <class T>
-YDEV void block_mtv(const T* B, const double* x, double acc[3]) {
+template <class T, class X>
+YDEV void block_mtv(const T* B, const X* x, double acc[3]) {
   const double x0 = x[0], x1 = x[1], x2 = x[2];
   acc[0] = fma(double(B[0]), x0, fma(double(B[3]), x1, fma(double(B[6]), x2, acc[0])));
   acc[1] = fma(double(B[1]), x0, fma(double(B[4]), x1, fma(double(B[7]), x2, acc[1])));
   acc[2] = fma(double(B[2]), x0, fma(double(B[5]), x1, fma(double(B[8]), x2, acc[2])));
 }
 
-template <class T>
+template <class T, class X>
 YDEV void row_part(const int32_t* rp, const int32_t* ci, const T* v, const int32_t* tp, const int32_t* ts,
-                   const int32_t* tr, int row, int lane, const double* x, double acc[3]) {
+                   const int32_t* tr, int row, int lane, const X* x, double acc[3]) {
   for (int k = rp[row] + lane, e = rp[row + 1]; k < e; k += SPMV_G) block_mv(v + 9 * (size_t)k, x + 3 * (size_t)ci[k], acc);
   for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
     block_mtv(v + 9 * (size_t)ts[k], x + 3 * (size_t)tr[k], acc);
 }
 
-// y_row = (H x)_row for the row owned by this lane group; valid in lane 0 of the group.
-YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const double* x, double acc[3]) {
+// (H x)_row for the row owned by this lane group; the sum is valid in every
+// lane of the group after the butterfly.
+template <class X>
+YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
   if (row < A.n) {
     if (A.v_s32)
@@ -107,38 +103,43 @@ YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const double* x, doubl
   }
 }
 
+// Krylov vectors in VT (float64, or float32 in the precision form); the
+// solution x is always float64.
+template <class VT>
 struct Vecs {
-  double *r, *u, *w, *p, *s, *part_b, *part_c;  // part_c holds 2 * nblocks_c partials
+  VT *r, *u, *w, *p, *s;
+  double *part_b, *part_c;  // part_c holds 2 * MAX_WG_C partials
 };
 
-YDEV void precondition(const double* minv, int v, const double r[3], double u[3]) {
+YDEV void precondition(const double* minv, int v, const double r[3], double u[3]) {  // u = M^-1 r
   const double* M = minv + 9 * (size_t)v;
   u[0] = M[0] * r[0] + M[1] * r[1] + M[2] * r[2];
   u[1] = M[3] * r[0] + M[4] * r[1] + M[5] * r[2];
   u[2] = M[6] * r[0] + M[7] * r[1] + M[8] * r[2];
 }
 
-// r = b, x = 0, p = s = 0, u = M^-1 r; gamma, |r|^2 partials.
+// r = b, x = 0, p = s = 0, u = M^-1 r; gamma and |r|^2 partials.
+template <class VT>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const double* __restrict__ b,
-                                                             double* __restrict__ x, Vecs V, PcgState* st) {
+                                                             double* __restrict__ x, Vecs<VT> V, PcgState* st) {
   __shared__ double lds[RED_BLOCK];
-  const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
   double g = 0.0, rr = 0.0;
-  if (v < A.n) {
+  for (int v = blockIdx.x * RED_BLOCK + threadIdx.x; v < A.n; v += gridDim.x * RED_BLOCK) {
     double r[3], u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      r[c] = b[3 * (size_t)v + c];
-      V.r[3 * (size_t)v + c] = r[c];
+      r[c] = double(VT(b[3 * (size_t)v + c]));
+      V.r[3 * (size_t)v + c] = VT(r[c]);
       x[3 * (size_t)v + c] = 0.0;
-      V.p[3 * (size_t)v + c] = 0.0;
-      V.s[3 * (size_t)v + c] = 0.0;
+      V.p[3 * (size_t)v + c] = VT(0);
+      V.s[3 * (size_t)v + c] = VT(0);
     }
     precondition(A.minv, v, r, u);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      V.u[3 * (size_t)v + c] = u[c];
-      g = fma(r[c], u[c], g);
+      const VT uc = VT(u[c]);
+      V.u[3 * (size_t)v + c] = uc;
+      g = fma(r[c], double(uc), g);
       rr = fma(r[c], r[c], rr);
     }
   }
@@ -148,84 +149,137 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
   }
-  if (last_block(&st->counter_c)) {
-    const double G = sum_partials(V.part_c, gridDim.x, lds);
-    const double R = sum_partials(V.part_c + gridDim.x, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      st->gamma = G;
-      st->gamma_prev = 1.0;
-      st->rr = R;
-      st->bb = R;
-      st->alpha = 1.0;
-      st->iter = 0;
-      st->status = 0;
-      st->done = (R <= st->tol2 * R) ? 1 : 0;
-      if (!st->done && st->max_iter <= 0) {
-        st->done = 1;
-        st->status = -5;
+}
+
+// Residual replacement (precision form): r = b - H x evaluated with float64
+// vectors and accumulation, then u = M^-1 r and the gamma / |r|^2 partials,
+// replacing what the float32 recurrence carried.
+template <class VT>
+__global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
+                                                                const double* __restrict__ x, Vecs<VT> V,
+                                                                PcgState* st) {
+  if (st->done) return;
+  __shared__ double lds[RED_BLOCK];
+  const int lane = threadIdx.x % SPMV_G;
+  double g = 0.0, rr = 0.0;
+  for (int base = blockIdx.x * SPMV_ROWS; base < A.n; base += gridDim.x * SPMV_ROWS) {
+    const int row = base + threadIdx.x / SPMV_G;
+    double acc[3];
+    spmv_row(A, row, lane, x, acc);
+    if (lane == 0 && row < A.n) {
+      double r[3], u[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)row + c] - acc[c];
+      precondition(A.minv, row, r, u);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const VT rc = VT(r[c]), uc = VT(u[c]);
+        V.r[3 * (size_t)row + c] = rc;
+        V.u[3 * (size_t)row + c] = uc;
+        g = fma(double(rc), double(uc), g);
+        rr = fma(r[c], r[c], rr);
       }
-      st->counter_c = 0;
     }
+  }
+  const double gs = block_sum<RED_BLOCK>(g, lds);
+  const double rs = block_sum<RED_BLOCK>(rr, lds);
+  if (threadIdx.x == 0) {
+    V.part_c[blockIdx.x] = gs;
+    V.part_c[gridDim.x + blockIdx.x] = rs;
   }
 }
 
-// w = H u, delta partials.
-__global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs V, PcgState* st) {
-  if (st->done) return;
+// Iteration i: convergence test on |r_i|, then w = H u with the u.w partials.
+// `nb_c` is the update kernel's grid (number of gamma / |r|^2 partials).
+// standalone: plain y = H x (no solver bookkeeping).
+template <class VT>
+__global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
+                                                             int standalone) {
   __shared__ double lds[RED_BLOCK];
-  const int row = blockIdx.x * SPMV_ROWS + threadIdx.x / SPMV_G;
+  if (!standalone) {
+    if (st->done) return;
+    const int i = st->iter;
+    const double G = sum_partials(V.part_c, nb_c, lds);
+    const double R = sum_partials(V.part_c + nb_c, nb_c, lds);
+    const double bb = i == 0 ? R : st->bb;
+    const bool conv = R <= st->tol2 * bb;
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (first) {
+      st->gamma[i & 1] = G;
+      st->rr = R;
+      st->iter_b = i;
+      if (i == 0) st->bb = bb;
+    }
+    if (conv || i >= st->max_iter) {
+      if (first) {
+        st->status = conv ? 0 : -5;
+        st->done = 1;
+      }
+      return;
+    }
+  }
   const int lane = threadIdx.x % SPMV_G;
-  double acc[3];
-  spmv_row(A, row, lane, V.u, acc);
   double d = 0.0;
-  if (lane == 0 && row < A.n) {
+  for (int base = blockIdx.x * SPMV_ROWS; base < A.n; base += gridDim.x * SPMV_ROWS) {
+    const int row = base + threadIdx.x / SPMV_G;
+    double acc[3];
+    spmv_row(A, row, lane, V.u, acc);
+    if (lane == 0 && row < A.n) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      V.w[3 * (size_t)row + c] = acc[c];
-      d = fma(V.u[3 * (size_t)row + c], acc[c], d);
+      for (int c = 0; c < 3; ++c) {
+        const VT wc = VT(acc[c]);
+        V.w[3 * (size_t)row + c] = wc;
+        d = fma(double(V.u[3 * (size_t)row + c]), double(wc), d);
+      }
     }
   }
   const double ds = block_sum<RED_BLOCK>(d, lds);
   if (threadIdx.x == 0) V.part_b[blockIdx.x] = ds;
-  if (last_block(&st->counter_b)) {
-    const double D = sum_partials(V.part_b, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      st->delta = D;
-      st->counter_b = 0;
-    }
-  }
 }
 
-__global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs V,
-                                                               PcgState* st) {
+// Iteration i: scalar recurrences, vector updates, preconditioning, and the
+// gamma / |r|^2 partials of iteration i + 1.  `nb_b` = SpMV grid.
+template <class VT>
+__global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
+                                                               PcgState* st, int nb_b) {
   if (st->done) return;
   __shared__ double lds[RED_BLOCK];
-  const double gamma = st->gamma, delta = st->delta;
-  const int iter = st->iter;
-  const double beta = iter == 0 ? 0.0 : gamma / st->gamma_prev;
-  const double pAp = iter == 0 ? delta : delta - beta * gamma / st->alpha;
-  const bool breakdown = !(pAp > 0.0);
+  const int i = st->iter_b;
+  const double gamma = st->gamma[i & 1];
+  const double delta = sum_partials(V.part_b, nb_b, lds);
+  const bool restart = i == st->restart_at;
+  const double beta = restart ? 0.0 : gamma / st->gamma[(i - 1) & 1];
+  const double pAp = restart ? delta : delta - beta * gamma / st->alpha[(i - 1) & 1];
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pAp > 0.0)) {
+    if (first) {
+      st->status = -6;
+      st->done = 1;
+    }
+    return;
+  }
   const double alpha = gamma / pAp;
-  const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
   double g = 0.0, rr = 0.0;
-  if (v < A.n && !breakdown) {
+  for (int v = blockIdx.x * RED_BLOCK + threadIdx.x; v < A.n; v += gridDim.x * RED_BLOCK) {
     double r[3], u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const size_t i = 3 * (size_t)v + c;
-      const double p = fma(beta, V.p[i], V.u[i]);
-      const double s = fma(beta, V.s[i], V.w[i]);
-      V.p[i] = p;
-      V.s[i] = s;
-      x[i] = fma(alpha, p, x[i]);
-      r[c] = fma(-alpha, s, V.r[i]);
-      V.r[i] = r[c];
+      const size_t k = 3 * (size_t)v + c;
+      const VT p = VT(fma(beta, double(V.p[k]), double(V.u[k])));
+      const VT s = VT(fma(beta, double(V.s[k]), double(V.w[k])));
+      V.p[k] = p;
+      V.s[k] = s;
+      x[k] = fma(alpha, double(p), x[k]);
+      const VT rc = VT(fma(-alpha, double(s), double(V.r[k])));
+      r[c] = double(rc);
+      V.r[k] = rc;
     }
     precondition(A.minv, v, r, u);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      V.u[3 * (size_t)v + c] = u[c];
-      g = fma(r[c], u[c], g);
+      const VT uc = VT(u[c]);
+      V.u[3 * (size_t)v + c] = uc;
+      g = fma(r[c], double(uc), g);
       rr = fma(r[c], r[c], rr);
     }
   }
@@ -235,79 +289,60 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
   }
-  if (last_block(&st->counter_c)) {
-    const double G = sum_partials(V.part_c, gridDim.x, lds);
-    const double R = sum_partials(V.part_c + gridDim.x, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      if (breakdown) {
-        st->done = 1;
-        st->status = -6;
-      } else {
-        st->gamma_prev = gamma;
-        st->gamma = G;
-        st->rr = R;
-        st->alpha = alpha;
-        st->iter = iter + 1;
-        if (R <= st->tol2 * st->bb) {
-          st->done = 1;
-        } else if (iter + 1 >= st->max_iter) {
-          st->done = 1;
-          st->status = -5;
-        }
-      }
-      st->counter_c = 0;
-    }
+  if (first) {
+    st->alpha[i & 1] = alpha;
+    st->iter = i + 1;
   }
+}
+
+int grid_b(int n) { return std::max(1, std::min((n + SPMV_ROWS - 1) / SPMV_ROWS, MAX_WG_B)); }
+int grid_c(int n) { return std::max(1, std::min((n + RED_BLOCK - 1) / RED_BLOCK, MAX_WG_C)); }
+
+template <class VT>
+void carve(void* work, int n, PcgState*& st, Vecs<VT>& V) {
+  const size_t n3 = 3 * (size_t)n;
+  char* w = static_cast<char*>(work);
+  st = reinterpret_cast<PcgState*>(w);
+  double* parts = reinterpret_cast<double*>(w + ((sizeof(PcgState) + 255) / 256) * 256);
+  V.part_b = parts;
+  V.part_c = parts + MAX_WG_B;
+  VT* base = reinterpret_cast<VT*>(parts + MAX_WG_B + 2 * MAX_WG_C);
+  V.r = base;
+  V.u = V.r + n3;
+  V.w = V.u + n3;
+  V.p = V.w + n3;
+  V.s = V.p + n3;
 }
 
 }  // namespace
 
 size_t pcg_workspace_bytes(int n) {
   const size_t n3 = 3 * (size_t)std::max(n, 1);
-  const size_t nb_b = ((size_t)n + SPMV_ROWS - 1) / SPMV_ROWS + 1;
-  const size_t nb_c = ((size_t)n + RED_BLOCK - 1) / RED_BLOCK + 1;
-  return sizeof(PcgState) + 256 + sizeof(double) * (5 * n3 + nb_b + 2 * nb_c) + 256;
-}
-
-namespace {
-
-void carve(void* work, int n, PcgState*& st, Vecs& V) {
-  const size_t n3 = 3 * (size_t)n;
-  char* w = static_cast<char*>(work);
-  st = reinterpret_cast<PcgState*>(w);
-  double* base = reinterpret_cast<double*>(w + ((sizeof(PcgState) + 255) / 256) * 256);
-  const int nb_b = (n + SPMV_ROWS - 1) / SPMV_ROWS;
-  V.r = base;
-  V.u = V.r + n3;
-  V.w = V.u + n3;
-  V.p = V.w + n3;
-  V.s = V.p + n3;
-  V.part_b = V.s + n3;
-  V.part_c = V.part_b + nb_b + 1;
-}
-
-}  // namespace
+  return 256 + ((sizeof(PcgState) + 255) / 256) * 256 + sizeof(double) * (5 * n3 + MAX_WG_B + 2 * MAX_WG_C);
+}  // float64 vectors; the float32 form uses half of the vector part
 
 void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s) {
   if (A.n == 0) return;
   PcgState* st;
-  Vecs V;
+  Vecs<double> V;
   carve(work, A.n, st, V);
   V.u = const_cast<double*>(x);
   V.w = y;
-  (void)hipMemsetAsync(st, 0, sizeof(PcgState), s);
-  hipLaunchKernelGGL(pcg_spmv_kernel, dim3((A.n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(RED_BLOCK), 0, s, A, V, st);
+  hipLaunchKernelGGL(pcg_spmv_kernel<double>, dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
 }
 
-int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, bool mixed, void* work,
-              double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm) {
-  (void)mixed;
+namespace {
+
+template <class VT>
+int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, void* work, double* rel_out,
+            int* status_out, hipStream_t s, LaunchTimer* tm) {
+  constexpr bool MIXED = sizeof(VT) == 4;
+  constexpr int REPLACE_EVERY = 50;  // float64 residual replacement period (precision form)
   const int n = A.n;
   PcgState* st;
-  Vecs V;
+  Vecs<VT> V;
   carve(work, n, st, V);
-  const int nb_b = (n + SPMV_ROWS - 1) / SPMV_ROWS;
-  const int nb_c = (n + RED_BLOCK - 1) / RED_BLOCK;
+  const int nb_b = grid_b(n), nb_c = grid_c(n);
   PcgState h{};
   h.tol2 = rtol * rtol;
   h.max_iter = max_iter;
@@ -318,27 +353,70 @@ int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int m
     return 0;
   }
   if (tm) tm->begin(6);
-  hipLaunchKernelGGL(pcg_init_kernel, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+  hipLaunchKernelGGL(pcg_init_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
   if (tm) tm->end();
   int batch = 8;
+  long long launched = 0;  // (SpMV, update) pairs issued = iteration index while not done
   PcgState hs{};
+  int verified_at = -1;
+  int restarts = 0;
+  constexpr int MAX_RESTARTS = 32;
   for (;;) {
     for (int k = 0; k < batch; ++k) {
       if (tm) tm->begin(5);
-      hipLaunchKernelGGL(pcg_spmv_kernel, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, V, st);
+      hipLaunchKernelGGL(pcg_spmv_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, V, st, nb_c, 0);
       if (tm) tm->end();
       if (tm) tm->begin(6);
-      hipLaunchKernelGGL(pcg_update_kernel, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, x, V, st);
+      hipLaunchKernelGGL(pcg_update_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, x, V, st, nb_b);
       if (tm) tm->end();
+      ++launched;
+      if (MIXED && launched % REPLACE_EVERY == 0) {
+        if (tm) tm->begin(5);
+        hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+        if (tm) tm->end();
+      }
     }
     if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
-    if (hs.done) break;
+    if (hs.done && MIXED && hs.status == -6 && restarts < MAX_RESTARTS) {
+      // float32 recurrence lost positivity of p^T H p: restart the search
+      // direction from a float64 true residual at the same iterate
+      ++restarts;
+      PcgState fix = hs;
+      fix.done = 0;
+      fix.status = 0;
+      fix.restart_at = hs.iter_b;
+      fix.iter = hs.iter_b;
+      if (hipMemcpyAsync(st, &fix, sizeof(fix), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
+      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      launched = hs.iter_b;
+      batch = 8;
+      continue;
+    }
+    if (hs.done) {
+      if (!MIXED || hs.status != 0 || verified_at == hs.iter_b) break;
+      // converged on the recurrence residual: confirm with a float64 true residual
+      verified_at = hs.iter_b;
+      const int zero = 0;
+      if (hipMemcpyAsync(&st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
+      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      launched = hs.iter_b;
+      batch = 8;
+      continue;
+    }
     batch = std::min(batch * 2, 64);
   }
   *rel_out = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
   *status_out = hs.status;
-  return hs.iter;
+  return hs.iter_b;
+}
+
+}  // namespace
+
+int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, bool mixed, void* work,
+              double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm) {
+  return mixed ? pcg_run<float>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm)
+               : pcg_run<double>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm);
 }
 
 }  // namespace yasps

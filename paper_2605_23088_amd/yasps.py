@@ -66,12 +66,13 @@ class PcgInfo(C.Structure):
 
 
 class NewtonParams(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("max_halvings", C.c_int32), ("armijo", C.c_double)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("max_halvings", C.c_int32), ("armijo", C.c_double),
+                ("tie_rtol", C.c_double)]
 
 
 class NewtonInfo(C.Structure):
     _fields_ = [("e0", C.c_double), ("e1", C.c_double), ("alpha", C.c_double), ("alpha0", C.c_double),
-                ("grad_dot_p", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_residual", C.c_double),
+                ("grad_dot_p", C.c_double), ("grad_max", C.c_double), ("step_max", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_residual", C.c_double),
                 ("cg_status", C.c_int32), ("ls_trials", C.c_int32), ("ms_eval", C.c_float),
                 ("ms_assemble", C.c_float), ("ms_pcg", C.c_float), ("ms_linesearch", C.c_float)]
 
@@ -231,17 +232,18 @@ class Yasps:
         if not copy:
             return v
         n = self.n
+        vt = torch.float32 if v.values_are_f32 else torch.float64
         out = dict(
             row_ptr_s=self._dev_copy(v.row_ptr_s, n + 1, torch.int32),
             col_idx_s=self._dev_copy(v.col_idx_s, v.nnzb_static, torch.int32),
-            values_s=self._dev_copy(v.values_s, 9 * v.nnzb_static, torch.float64).view(-1, 3, 3),
+            values_s=self._dev_copy(v.values_s, 9 * v.nnzb_static, vt).view(-1, 3, 3),
             grad=self._dev_copy(v.grad, 3 * n, torch.float64).view(n, 3),
             block_inv=self._dev_copy(v.block_inv, 9 * n, torch.float64).view(n, 3, 3),
         )
         if v.nnzb_dynamic:
             out["row_ptr_d"] = self._dev_copy(v.row_ptr_d, n + 1, torch.int32)
             out["col_idx_d"] = self._dev_copy(v.col_idx_d, v.nnzb_dynamic, torch.int32)
-            out["values_d"] = self._dev_copy(v.values_d, 9 * v.nnzb_dynamic, torch.float64).view(-1, 3, 3)
+            out["values_d"] = self._dev_copy(v.values_d, 9 * v.nnzb_dynamic, vt).view(-1, 3, 3)
         return out
 
     def _dev_copy(self, ptr, count, dtype):
@@ -260,8 +262,9 @@ class Yasps:
         rc = self._check(lib().yasps_pcg(self.ctx, _ptr(b), _ptr(x), rtol, max_iter, C.byref(info)), allow)
         return x, dict(iters=info.iters, rel_residual=info.rel_residual, status=info.status, rc=rc)
 
-    def newton_step(self, x, rtol=1e-8, max_iter=20000, max_halvings=40, armijo=1e-4, allow=(E_NOCONV,)):
-        prm = NewtonParams(rtol, max_iter, max_halvings, armijo)
+    def newton_step(self, x, rtol=1e-8, max_iter=20000, max_halvings=40, armijo=1e-4, tie_rtol=0.0,
+                    allow=(E_NOCONV,)):
+        prm = NewtonParams(rtol, max_iter, max_halvings, armijo, tie_rtol)
         info = NewtonInfo()
         rc = self._check(lib().yasps_newton_step(self.ctx, _ptr(x), C.byref(prm), C.byref(info)), allow)
         out = {k: getattr(info, k) for k, _ in NewtonInfo._fields_}

@@ -1,0 +1,67 @@
+"""Differentiation form on the GPU: the torch.autograd.Function over the
+library's static-equilibrium solve, checked against the oracle's adjoint
+gradient and against central finite differences of the GPU forward solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj
+from oracle import assemble as oasm
+from paper_2605_23088_amd import synth
+
+pytestmark = pytest.mark.gpu
+GTOL = 5e-11
+
+
+def loss_and_grad(solver, theta_np, x0, x_tgt):
+    from paper_2605_23088_amd.adjoint import YaspsEquilibrium
+    theta = torch.as_tensor(theta_np, dtype=torch.float64, device="cuda").requires_grad_(True)
+    xs = YaspsEquilibrium.apply(theta, solver, x0)
+    L = ((xs - x_tgt) ** 2).sum()
+    L.backward()
+    return float(L), theta.grad.detach().cpu().numpy(), xs.detach()
+
+
+def test_adjoint_matches_oracle():
+    from paper_2605_23088_amd.adjoint import StaticEquilibrium
+    p = synth.c5_static(seed=21, nx=4, ny=3, nz=3, a=0.05, n_pt=40)
+    o = oasm.Oracle(p)
+    oadj.set_theta(o, p["theta"])
+    xs_o, _ = oadj.solve_equilibrium(o, p["x0"], gtol=GTOL)
+    g_o, _ = oadj.theta_gradient(o, xs_o, p["x_tgt"])
+    s = StaticEquilibrium(p, gtol=GTOL)
+    x0 = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda")
+    xt = torch.as_tensor(p["x_tgt"], dtype=torch.float64, device="cuda")
+    L, g, xs = loss_and_grad(s, p["theta"], x0, xt)
+    disp = np.abs(xs_o - p["x0"]).max()
+    assert np.abs(xs.cpu().numpy() - xs_o).max() <= 1e-8 * disp
+    assert np.abs(g - g_o).max() <= 1e-4 * np.abs(g_o).max()
+    # special case: the target at the equilibrium gives a zero gradient
+    _, g0, _ = loss_and_grad(s, p["theta"], x0, xs)
+    assert np.abs(g0).max() <= 1e-12 * np.abs(g_o).max()
+
+
+def test_adjoint_matches_finite_differences():
+    from paper_2605_23088_amd.adjoint import StaticEquilibrium
+    p = synth.c5_static(seed=20265, nx=12, ny=12, nz=8, a=0.02, n_pt=2000)
+    s = StaticEquilibrium(p, gtol=GTOL)
+    x0 = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda")
+    xt = torch.as_tensor(p["x_tgt"], dtype=torch.float64, device="cuda")
+    L, g, xs = loss_and_grad(s, p["theta"], x0, xt)
+    rng = np.random.default_rng(20265)
+    gmax = np.abs(g).max()
+    theta = torch.as_tensor(p["theta"], dtype=torch.float64, device="cuda")
+    bad = []
+    for t in rng.choice(len(g), 32, replace=False):
+        eps = 1e-4 * p["theta"][t]
+        th = theta.clone()
+        th[t] += eps
+        s.set_theta(th)
+        Lp = float(((s.solve(xs) - xt) ** 2).sum())
+        th[t] -= 2 * eps
+        s.set_theta(th)
+        Lm = float(((s.solve(xs) - xt) ** 2).sum())
+        fd = (Lp - Lm) / (2 * eps)
+        if abs(g[t] - fd) > 1e-3 * abs(fd) + 1e-8 * gmax:
+            bad.append((int(t), g[t], fd))
+    assert not bad, bad
