@@ -105,7 +105,6 @@ typedef struct {
 typedef struct {
   int32_t precision; /* YASPS_FP64 or YASPS_MIXED */
   int32_t proj;      /* YASPS_F_SPACE or YASPS_X_SPACE */
-  int32_t hessian;   /* default Hessian mode of yasps_newton_step: YASPS_PROJECTED */
   int32_t barrier;   /* YASPS_SQLOG or YASPS_IPC_CLASSIC */
 } yasps_params;
 
@@ -145,6 +144,9 @@ typedef struct {
   double armijo;        /* sufficient-decrease constant (default 1e-4) */
   double tie_rtol;      /* a trial with |E - E(x)| <= tie_rtol |E(x)| also counts as a decrease
                            (for solves driven to the rounding floor of E); 0 = plain Armijo */
+  int32_t hessian;      /* YASPS_PROJECTED (default, 0): projected Newton; YASPS_EXACT: solve with the
+                           unprojected Hessian (near a minimum where it is positive definite; returns
+                           YASPS_E_BREAKDOWN when PCG meets p^T H p <= 0) */
 } yasps_newton_params;
 
 typedef struct {

@@ -36,9 +36,18 @@ class Oracle:
         self.tet_idx = np.asarray(prob["tet_idx"], np.int64)
         self.cidx = np.asarray(prob["cidx"], np.int64)
         self.ctype = np.asarray(prob["ctype"], np.int64)
-        self.rp_s, self.ci_s, (self.slot_t,) = pattern.build(n, [self.tet_idx], True)
+        nf = len(prob.get("tri_idx", []))
+        nh = len(prob.get("hinge_idx", []))
+        self.tri_idx = np.full((nf, 4), -1, np.int64)
+        if nf:
+            self.tri_idx[:, :3] = np.asarray(prob["tri_idx"], np.int64)
+        self.hinge_idx = np.asarray(prob["hinge_idx"], np.int64).reshape(-1, 4) if nh else np.zeros((0, 4), np.int64)
+        self.rp_s, self.ci_s, (self.slot_t, self.slot_f, self.slot_h) = pattern.build(
+            n, [self.tet_idx, self.tri_idx, self.hinge_idx], True)
         self.rp_d, self.ci_d, (self.slot_c,) = pattern.build(n, [self.cidx], False)
         self.pairs_t = pattern.stencil_pairs(self.tet_idx)
+        self.pairs_f = pattern.stencil_pairs(self.tri_idx)
+        self.pairs_h = pattern.stencil_pairs(self.hinge_idx)
         self.pairs_c = pattern.stencil_pairs(self.cidx)
         t = local.T
         self.x_fixed = t(prob["x_fixed"]).reshape(-1, 3)
@@ -54,6 +63,13 @@ class Oracle:
         self.mass = np.asarray(prob["mass"], np.float64)
         self.x_tilde = np.asarray(prob["x_tilde"], np.float64)
         self.static = bool(prob.get("static", False))
+        if nf:
+            self.tri_dm_inv = t(prob["tri_dm_inv"]).reshape(-1, 2, 2)
+            self.tri_area = t(prob["tri_area"])
+        if nh:
+            hr = np.asarray(prob["hinge_rest"], np.float64).reshape(-1, 2)
+            self.hinge_theta = t(hr[:, 0])
+            self.hinge_stiff = t(hr[:, 1])
         self.gravity = np.asarray(prob.get("gravity", [0.0, 0.0, -9.81]), np.float64)
 
     # ------------------------------------------------------------ pieces
@@ -72,6 +88,20 @@ class Oracle:
                                self.lam if lam is None else lam, self.vol,
                                float(self.p["h"]), free, self.proj, hess)
 
+    def tris(self, x, hess=PROJECTED):
+        if not len(self.tri_idx):
+            return torch.zeros(0), torch.zeros(0, 4, 3), torch.zeros(0, 12, 12)
+        xf, free = local.gather_positions(local.T(x), self.x_fixed, self.tri_idx, self.n)
+        p = self.p
+        return local.membrane_local(xf[:, :3], self.tri_dm_inv, self.tri_area, p["thickness"], p["mu_c"],
+                                    p["lam_c"], float(p["h"]), free, hess)
+
+    def hinges(self, x, hess=PROJECTED):
+        if not len(self.hinge_idx):
+            return torch.zeros(0), torch.zeros(0, 4, 3), torch.zeros(0, 12, 12)
+        xh, free = local.gather_positions(local.T(x), self.x_fixed, self.hinge_idx, self.n)
+        return local.hinge_local(xh, self.hinge_theta, self.hinge_stiff, float(self.p["h"]), free, hess)
+
     def contacts(self, x, hess=PROJECTED):
         xc, free = local.gather_positions(local.T(x), self.x_fixed, self.cidx, self.n)
         return local.contact_local(xc, torch.as_tensor(self.ctype), free,
@@ -83,11 +113,15 @@ class Oracle:
         x = np.asarray(x, np.float64).reshape(self.n, 3)
         e_i, g_i = self.inertia(x)
         Et, gt, Ht = self.tets(x, hess)
+        Ef, gf, Hf = self.tris(x, hess)
+        Eh, gh, Hh = self.hinges(x, hess)
         Ec, gc, Hc, d = self.contacts(x, hess)
+        e_el = float(Et.sum()) + float(Ef.sum()) + float(Eh.sum())
         return dict(x=x, E_inertia=e_i, g_inertia=g_i, E_t=Et.numpy(), g_t=gt.numpy(),
-                    H_t=Ht.numpy(), E_c=Ec.numpy(), g_c=gc.numpy(), H_c=Hc.numpy(),
-                    d=d.numpy(), E_elastic=float(Et.sum()), E_contact=float(Ec.sum()),
-                    E=e_i + float(Et.sum()) + float(Ec.sum()))
+                    H_t=Ht.numpy(), E_f=Ef.numpy(), g_f=gf.numpy(), H_f=Hf.numpy(), E_h=Eh.numpy(),
+                    g_h=gh.numpy(), H_h=Hh.numpy(), E_c=Ec.numpy(), g_c=gc.numpy(), H_c=Hc.numpy(),
+                    d=d.numpy(), E_elastic=e_el, E_contact=float(Ec.sum()),
+                    E=e_i + e_el + float(Ec.sum()))
 
     def _scatter_blocks(self, nnzb, idx, pairs, slots, H):
         vals = np.zeros((nnzb, 3, 3))
@@ -113,11 +147,19 @@ class Oracle:
     def assemble(self, ev):
         n = self.n
         vals_s = self._scatter_blocks(len(self.ci_s), self.tet_idx, self.pairs_t, self.slot_t, ev["H_t"])
+        if len(self.tri_idx):
+            vals_s += self._scatter_blocks(len(self.ci_s), self.tri_idx, self.pairs_f, self.slot_f, ev["H_f"])
+        if len(self.hinge_idx):
+            vals_s += self._scatter_blocks(len(self.ci_s), self.hinge_idx, self.pairs_h, self.slot_h, ev["H_h"])
         vals_d = self._scatter_blocks(len(self.ci_d), self.cidx, self.pairs_c, self.slot_c, ev["H_c"])
         if not self.static:
             vals_s[self.rp_s[:-1]] += self.mass[:, None, None] * np.eye(3)[None]
         g = ev["g_inertia"] + self._scatter_grad(self.tet_idx, ev["g_t"]) + \
             self._scatter_grad(self.cidx, ev["g_c"])
+        if len(self.tri_idx):
+            g = g + self._scatter_grad(self.tri_idx, ev["g_f"])
+        if len(self.hinge_idx):
+            g = g + self._scatter_grad(self.hinge_idx, ev["g_h"])
         return dict(values_s=vals_s, values_d=vals_d, grad=g.reshape(n, 3))
 
     def energy(self, x):
@@ -127,7 +169,9 @@ class Oracle:
         xt, _ = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
         h2 = float(self.p["h"]) ** 2
         Et = h2 * torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol)
-        xc, _ = local.gather_positions(local.T(x), self.x_fixed, self.cidx, self.n)
+        Ecl = 0.0
+        if len(self.tri_idx) or len(self.hinge_idx):
+            Ecl = float(self.tris(x)[0].sum()) + float(self.hinges(x)[0].sum())
         d = self.distances(x)
         dhat, kappa = float(self.p["dhat"]), float(self.p["kappa"])
         dt = torch.as_tensor(d)
@@ -135,7 +179,7 @@ class Oracle:
         act = dt < dhat
         Ec = torch.where(act, bfun(torch.where(act, dt, torch.full_like(dt, dhat)), dhat, kappa),
                          torch.zeros_like(dt))
-        return e_i + float(Et.sum()) + float(Ec.sum())
+        return e_i + float(Et.sum()) + Ecl + float(Ec.sum())
 
     def distances(self, x):
         xc, _ = local.gather_positions(local.T(np.asarray(x).reshape(self.n, 3)), self.x_fixed,

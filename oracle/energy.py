@@ -121,3 +121,37 @@ def signed_side(x, ctype):
     n_ee = torch.linalg.cross(q1 - p, q3 - q2, dim=1)
     s_ee = ((p - q2) * n_ee).sum(1)
     return torch.where(ctype == 0, s_pt, torch.where(ctype == 1, s_ee, torch.ones_like(s_pt)))
+
+
+# ---------------------------------------------------------------- cloth
+
+
+def membrane_deformation(xf, dm_inv2):
+    """3x2 deformation gradient [x1 - x0, x2 - x0] Dm^-1 of a triangle (rest shape
+    Dm in a 2-D orthonormal frame of the rest triangle)."""
+    Ds = torch.stack([xf[1] - xf[0], xf[2] - xf[0]], dim=1)
+    return Ds @ dm_inv2
+
+
+def stvk_membrane(xf, dm_inv2, area, thickness, mu, lam):
+    """StVK membrane: A t [mu tr(G^2) + lam/2 (tr G)^2] with G = (F^T F - I) / 2."""
+    F = membrane_deformation(xf, dm_inv2)
+    G = 0.5 * (F.T @ F - torch.eye(2, dtype=F.dtype))
+    return area * thickness * (mu * (G * G).sum() + 0.5 * lam * torch.trace(G) ** 2)
+
+
+def hinge_angle(x):
+    """Dihedral angle of the hinge (x0, x1 shared edge; x2, x3 the opposite
+    vertices of the two triangles): atan2((n1 x n2) . e_hat, n1 . n2) with the
+    unnormalised normals n1 = (x1 - x0) x (x2 - x0), n2 = (x3 - x0) x (x1 - x0)
+    (both triangles oriented consistently; zero for a flat hinge)."""
+    e = x[1] - x[0]
+    n1 = torch.linalg.cross(e, x[2] - x[0])
+    n2 = torch.linalg.cross(x[3] - x[0], e)
+    return torch.atan2(torch.dot(torch.linalg.cross(n1, n2), e) / torch.sqrt(torch.dot(e, e)), torch.dot(n1, n2))
+
+
+def hinge_energy(x, theta_bar, stiffness):
+    """Discrete-shells bending k_b 3|e_bar|^2/(A1 + A2) (theta - theta_bar)^2;
+    `stiffness` is the precomputed rest factor k_b 3|e_bar|^2/(A1 + A2)."""
+    return stiffness * (hinge_angle(x) - theta_bar) ** 2

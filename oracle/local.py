@@ -92,6 +92,55 @@ def snh_local(xt, dm_inv, mu, lam, vol, h, free, proj=F_SPACE, hess=PROJECTED):
     return E, g, sym(H * mm)
 
 
+def membrane_local(xf, dm_inv2, area, thickness, mu, lam, h, free, hess=PROJECTED):
+    """StVK membrane triangles.  xf (n, 3, 3), dm_inv2 (n, 2, 2), area (n,).
+    Energy h^2 Psi, gradient, and h^2 J_F^T Proj(d2Psi/dF2) J_F (6x6 F-space
+    projection) over the free vertices, padded to (n, 12, 12) / (n, 4, 3)."""
+    n = xf.shape[0]
+    h2 = h * h
+    t = torch.full((n,), float(thickness))
+    m = torch.full((n,), float(mu))
+    l = torch.full((n,), float(lam))
+
+    def psi_x(x, D, A, tt, mm, ll):
+        return en.stvk_membrane(x, D, A, tt, mm, ll)
+
+    def psi_F(F, A, tt, mm, ll):
+        G = 0.5 * (F.T @ F - torch.eye(2, dtype=F.dtype))
+        return A * tt * (mm * (G * G).sum() + 0.5 * ll * torch.trace(G) ** 2)
+
+    E = h2 * vmap(psi_x)(xf, dm_inv2, area, t, m, l)
+    g3 = h2 * vmap(grad(psi_x))(xf, dm_inv2, area, t, m, l) * free[:, :3].unsqueeze(-1)
+    m9 = free[:, :3].repeat_interleave(3, dim=1)
+    mm9 = (m9.unsqueeze(2) & m9.unsqueeze(1)).to(xf.dtype)
+    if hess == EXACT:
+        H9 = h2 * vmap(hessian(psi_x))(xf, dm_inv2, area, t, m, l).reshape(n, 9, 9) * mm9
+    else:
+        F = vmap(en.membrane_deformation)(xf, dm_inv2)
+        HF = vmap(hessian(psi_F))(F, area, t, m, l).reshape(n, 6, 6)
+        JF = vmap(jacrev(en.membrane_deformation))(xf, dm_inv2).reshape(n, 6, 9)
+        H9 = h2 * (JF.transpose(1, 2) @ psd_project(HF) @ JF) * mm9
+    g = torch.zeros(n, 4, 3)
+    g[:, :3] = g3
+    H = torch.zeros(n, 12, 12)
+    H[:, :9, :9] = sym(H9)
+    return E, g, H
+
+
+def hinge_local(xh, theta_bar, stiffness, h, free, hess=PROJECTED):
+    """Dihedral bending hinges.  xh (n, 4, 3); energy h^2 E_b, gradient, and the
+    free principal submatrix of h^2 d2E_b/dx2, projected unless hess=EXACT."""
+    n = xh.shape[0]
+    h2 = h * h
+    E = h2 * vmap(en.hinge_energy)(xh, theta_bar, stiffness)
+    g = h2 * vmap(grad(en.hinge_energy))(xh, theta_bar, stiffness) * free.unsqueeze(-1)
+    H = h2 * vmap(hessian(en.hinge_energy))(xh, theta_bar, stiffness).reshape(n, 12, 12)
+    m12 = _mask12(free)
+    if hess == EXACT:
+        return E, g, sym(H * (m12.unsqueeze(2) & m12.unsqueeze(1)).to(xh.dtype))
+    return E, g, sym(project_principal(H, m12))
+
+
 def contact_local(xc, ctype, free, kappa, dhat, hess=PROJECTED, classic=False):
     """Barrier stencils.  xc (n, 4, 3) vertex rows (unused rows arbitrary finite),
     ctype (n,), free (n, 4) bool (False for fixed and unused vertices).

@@ -60,9 +60,14 @@ def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
     return 0.0, x, E0, trials
 
 
-def newton_step(orc, x, rtol=1e-8, max_iter=20000, tie_rtol=0.0):
+def newton_step(orc, x, rtol=1e-8, max_iter=20000, tie_rtol=0.0, hess=0):
+    """hess=1 (EXACT) solves with the unprojected Hessian; the caller checks
+    ``cg_status`` ('breakdown' when that matrix is not positive definite)."""
     x = np.asarray(x, np.float64).reshape(orc.n, 3)
-    ev, asm, H, p, it, rel, status = solve_direction(orc, x, rtol, max_iter)
+    ev, asm, H, p, it, rel, status = solve_direction(orc, x, rtol, max_iter, hess)
+    if status == "breakdown":
+        return x, dict(E0=ev["E"], E1=ev["E"], alpha=0.0, cg_iters=it, cg_rel=rel, cg_status=status,
+                       ls_trials=0, p=p, grad=asm["grad"])
     alpha, x1, E1, trials = line_search(orc, x, p, ev["E"], asm["grad"], tie_rtol=tie_rtol)
     return x1, dict(E0=ev["E"], E1=E1, alpha=alpha, cg_iters=it, cg_rel=rel,
                     cg_status=status, ls_trials=trials, p=p, grad=asm["grad"])

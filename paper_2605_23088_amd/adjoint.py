@@ -1,8 +1,13 @@
 """Differentiable static equilibrium: x*(theta) for per-tet Young's moduli theta.
 
-Forward: projected Newton steps of the library on the static problem
+Forward: Newton steps of the library on the static problem
 E(x; theta) = sum_t Psi_t(x; theta_t) + sum_s kappa b(d_s) - sum_v m_v g . x_v
-until max_v |grad_v E| <= gtol * max_v m_v |g|.
+until max_v |grad_v E| <= gtol * max_v m_v |g|: projected steps first, then,
+once the gradient is below ``EXACT_SWITCH`` of that scale, steps with the exact
+Hessian (projected Newton converges only linearly where the projection still
+clamps modes of indefinite local Hessians; the exact Hessian must be positive
+definite at x* for the adjoint solve anyway).  An exact step whose PCG breaks
+down or whose line search fails is replaced by a projected step.
 
 Backward (implicit differentiation of grad_x E(x*; theta) = 0): with the
 upstream gradient dL/dx*, solve H(x*) lambda = dL/dx* by the library's PCG on
@@ -15,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .yasps import EXACT, Yasps, YaspsError
+from .yasps import E_BREAKDOWN, E_LINESEARCH, EXACT, PROJECTED, Yasps, YaspsError
 
 
 class StaticEquilibrium:
@@ -24,6 +29,7 @@ class StaticEquilibrium:
     context whose per-tet parameters are rewritten in place for each theta."""
 
     TIE_RTOL = 1e-14
+    EXACT_SWITCH = 1e-3
 
     def __init__(self, prob, device="cuda", gtol=1e-10, max_newton=60, rtol=1e-12):
         if "mu_t" not in prob:
@@ -44,13 +50,32 @@ class StaticEquilibrium:
         ml[0].copy_(theta * self.mu1)
         ml[1].copy_(theta * self.lam1)
 
+    def _step(self, x, hessian):
+        return self.lib.newton_step(x, rtol=self.rtol, max_iter=100000, tie_rtol=self.TIE_RTOL, hessian=hessian)
+
     def solve(self, x0):
         x = x0.detach().clone().contiguous()
+        gmax = np.inf
         for k in range(self.max_newton):
-            info = self.lib.newton_step(x, rtol=self.rtol, max_iter=100000, tie_rtol=self.TIE_RTOL)
+            info = None
+            if gmax <= self.EXACT_SWITCH * self.gscale:
+                xk = x.clone()
+                try:
+                    info = self._step(x, EXACT)
+                    if info["alpha"] == 0.0:
+                        info = None
+                except YaspsError as e:
+                    if e.status not in (E_BREAKDOWN, E_LINESEARCH):
+                        raise
+                if info is None:
+                    x.copy_(xk)
+            if info is None:
+                info = self._step(x, PROJECTED)
             self.newton_iters = k + 1
+            # grad_max is the gradient at the start of the step
             if info["grad_max"] <= self.gtol * self.gscale:
                 return x
+            gmax = info["grad_max"]
         raise YaspsError(-5, f"static equilibrium not reached in {self.max_newton} Newton steps "
                              f"(max |g| = {info['grad_max']:.3e})")
 

@@ -353,12 +353,11 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (P->n_tets > 0 && (!P->tet_idx || !P->dm_inv || !P->vol)) return fail(nullptr, YASPS_E_ARG, "tet arrays missing");
   if (!(P->dhat > 0.0) || !(P->kappa >= 0.0) || !(P->h > 0.0))
     return fail(nullptr, YASPS_E_ARG, "dhat, kappa and h must be positive");
-  yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_PROJECTED, YASPS_SQLOG};
+  yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_SQLOG};
   if (opt) prm = *opt;
   if (prm.precision != YASPS_FP64 && prm.precision != YASPS_MIXED)
     return fail(nullptr, YASPS_E_ARG, "unknown precision");
   if (prm.proj != YASPS_F_SPACE) return fail(nullptr, YASPS_E_UNIMPL, "only F-space Neo-Hookean projection is built");
-  if (prm.hessian != YASPS_PROJECTED && prm.hessian != YASPS_EXACT) return fail(nullptr, YASPS_E_ARG, "unknown hessian mode");
   if (prm.barrier != YASPS_SQLOG && prm.barrier != YASPS_IPC_CLASSIC) return fail(nullptr, YASPS_E_ARG, "unknown barrier");
 
   yasps_ctx* c = new (std::nothrow) yasps_ctx();
@@ -680,8 +679,9 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
 
 yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_params* prm, yasps_newton_info* info) {
   if (!c || !x) return fail(c, YASPS_E_ARG, "NULL argument");
-  yasps_newton_params p{1e-8, 20000, 40, 1e-4, 0.0};
+  yasps_newton_params p{1e-8, 20000, 40, 1e-4, 0.0, YASPS_PROJECTED};
   if (prm) p = *prm;
+  if (p.hessian != YASPS_PROJECTED && p.hessian != YASPS_EXACT) return fail(c, YASPS_E_ARG, "unknown hessian mode");
   HIPCHK(c, hipSetDevice(c->device));
   hipEvent_t ev[5];
   for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
@@ -694,7 +694,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   yasps_newton_info ni{};
   HIPCHK(c, hipEventRecord(ev[0], c->stream));
   yasps_eval_info ei{};
-  yasps_status s = run_eval(c, x, c->prm.hessian, &ei);
+  yasps_status s = run_eval(c, x, p.hessian, &ei);
   if (s) return s;
   HIPCHK(c, hipEventRecord(ev[1], c->stream));
   s = run_assemble(c);

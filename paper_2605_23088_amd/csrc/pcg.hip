@@ -153,7 +153,9 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
 
 // Residual replacement (precision form): r = b - H x evaluated with float64
 // vectors and accumulation, then u = M^-1 r and the gamma / |r|^2 partials,
-// replacing what the float32 recurrence carried.
+// replacing what the float32 recurrence carried.  Launched on the update
+// kernel's grid: its partials take the same [gamma | |r|^2] layout of gridDim.x
+// entries each that the next SpMV kernel sums.
 template <class VT>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
                                                                 const double* __restrict__ x, Vecs<VT> V,
@@ -372,7 +374,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       ++launched;
       if (MIXED && launched % REPLACE_EVERY == 0) {
         if (tm) tm->begin(5);
-        hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+        hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
         if (tm) tm->end();
       }
     }
@@ -388,7 +390,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       fix.restart_at = hs.iter_b;
       fix.iter = hs.iter_b;
       if (hipMemcpyAsync(st, &fix, sizeof(fix), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
       launched = hs.iter_b;
       batch = 8;
       continue;
@@ -399,7 +401,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       verified_at = hs.iter_b;
       const int zero = 0;
       if (hipMemcpyAsync(&st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
       launched = hs.iter_b;
       batch = 8;
       continue;

@@ -402,3 +402,309 @@ def small_block(seed=7, nx=5, ny=4, nz=3, n_pt=150, n_ee=150, **kw):
     """A few-hundred-tet version of the metric workload for fast parity runs."""
     return block_problem(nx, ny, nz, 1.0 / max(nx, ny, nz), n_pt, n_ee, seed,
                          name=f"block{nx}x{ny}x{nz}", **kw)
+
+
+# --------------------------------------------------------------------------
+# Cloth sheets and the heterogeneous workload
+# --------------------------------------------------------------------------
+
+def sheet(n, angle, center=(0.5, 0.5)):
+    """A unit square sheet of n x n cells rotated by `angle` about `center` in
+    the horizontal plane.  Returns rest coordinates (V, 2) in the sheet frame,
+    world (x, y) of every vertex, CCW triangles (2 per cell, split along the
+    (0,0)-(1,1) diagonal), and hinges (e0, e1, w1, w2) over interior edges with
+    (e0, e1, w1) and (e1, e0, w2) the two triangles (so the two unnormalised
+    normals (e1 - e0) x (w1 - e0) and (w2 - e0) x (e1 - e0) agree on a flat
+    sheet)."""
+    j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    uv = np.stack([i.ravel(), j.ravel()], 1).astype(np.float64) / n
+    c, s = np.cos(angle), np.sin(angle)
+    d = uv - 0.5
+    xy = np.stack([c * d[:, 0] - s * d[:, 1], s * d[:, 0] + c * d[:, 1]], 1) + np.asarray(center)
+    vid = lambda a, b: a + (n + 1) * b
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    v00, v10, v01, v11 = vid(ii, jj), vid(ii + 1, jj), vid(ii, jj + 1), vid(ii + 1, jj + 1)
+    tris = np.concatenate([np.stack([v00, v10, v11], 1), np.stack([v00, v11, v01], 1)])
+    # hinges from the directed edges of the CCW triangles
+    de = np.concatenate([tris[:, [0, 1, 2]], tris[:, [1, 2, 0]], tris[:, [2, 0, 1]]])  # (e0, e1, wing)
+    key = de[:, 0] * (n + 1) ** 2 + de[:, 1]
+    twin = de[:, 1] * (n + 1) ** 2 + de[:, 0]
+    order = np.argsort(key)
+    pos = np.searchsorted(key[order], twin)
+    pos = np.minimum(pos, len(key) - 1)
+    has = key[order][pos] == twin
+    a_idx = np.flatnonzero(has & (de[:, 0] < de[:, 1]))
+    b_idx = order[pos[a_idx]]
+    hinges = np.stack([de[a_idx, 0], de[a_idx, 1], de[a_idx, 2], de[b_idx, 2]], 1)
+    return uv, xy, tris.astype(np.int64), hinges.astype(np.int64)
+
+
+def _tri_wave(t):
+    return 2.0 * np.abs(t - np.floor(t + 0.5))
+
+
+def _closest_pt_triangle(p, a, b, c):
+    """Closest point of triangles (a, b, c) to points p (vectorised Voronoi-region
+    test of Ericson, Real-Time Collision Detection, sec. 5.1.5).  Returns the
+    squared distance and the region: 0 face, 1 edge ab, 2 edge bc, 3 edge ca,
+    4 vertex a, 5 vertex b, 6 vertex c."""
+    ab, ac, ap = b - a, c - a, p - a
+    d1, d2 = (ab * ap).sum(1), (ac * ap).sum(1)
+    bp = p - b
+    d3, d4 = (ab * bp).sum(1), (ac * bp).sum(1)
+    cp = p - c
+    d5, d6 = (ab * cp).sum(1), (ac * cp).sum(1)
+    va = d3 * d6 - d5 * d4
+    vb = d5 * d2 - d1 * d6
+    vc = d1 * d4 - d3 * d2
+    region = np.zeros(len(p), np.int64)
+    q = np.empty_like(p)
+    denom = va + vb + vc
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = vb / denom
+        w = vc / denom
+    q[:] = a + ab * v[:, None] + ac * w[:, None]
+    # edges
+    m_ab = (vc <= 0) & (d1 >= 0) & (d3 <= 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_ab = d1 / (d1 - d3)
+    q[m_ab] = (a + ab * t_ab[:, None])[m_ab]
+    region[m_ab] = 1
+    m_ac = (vb <= 0) & (d2 >= 0) & (d6 <= 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_ac = d2 / (d2 - d6)
+    q[m_ac] = (a + ac * t_ac[:, None])[m_ac]
+    region[m_ac] = 3
+    m_bc = (va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_bc = (d4 - d3) / ((d4 - d3) + (d5 - d6))
+    q[m_bc] = (b + (c - b) * t_bc[:, None])[m_bc]
+    region[m_bc] = 2
+    # vertices
+    m_a = (d1 <= 0) & (d2 <= 0)
+    m_b = (d3 >= 0) & (d4 <= d3)
+    m_c = (d6 >= 0) & (d5 <= d6)
+    q[m_a], region[m_a] = a[m_a], 4
+    q[m_b], region[m_b] = b[m_b], 5
+    q[m_c], region[m_c] = c[m_c], 6
+    return ((p - q) ** 2).sum(1), region
+
+
+def _closest_seg_seg(p1, q1, p2, q2):
+    """Closest points of segments p1q1 and p2q2 (Ericson sec. 5.1.9, vectorised,
+    non-degenerate segments).  Returns squared distance, s, t (parameters on
+    each segment, clamped to [0, 1])."""
+    d1, d2, r = q1 - p1, q2 - p2, p1 - p2
+    a, e, f = (d1 * d1).sum(1), (d2 * d2).sum(1), (d2 * r).sum(1)
+    c, b = (d1 * r).sum(1), (d1 * d2).sum(1)
+    denom = a * e - b * b
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.where(denom > 0, np.clip((b * f - c * e) / denom, 0.0, 1.0), 0.0)
+        t = (b * s + f) / e
+    lo, hi = t < 0, t > 1
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.where(lo, np.clip(-c / a, 0, 1), np.where(hi, np.clip((b - c) / a, 0, 1), s))
+    t = np.clip(t, 0, 1)
+    c1 = p1 + d1 * s[:, None]
+    c2 = p2 + d2 * t[:, None]
+    return ((c1 - c2) ** 2).sum(1), s, t
+
+
+def _pairs_near(pts_xy, prim_lo_xy, prim_hi_xy, cell, reach):
+    """Hashed proximity search in the horizontal plane: every (point, primitive)
+    pair whose point lies within `reach` of the primitive's xy bounding box.
+    Primitives are hashed into every cell of side `cell` their grown box
+    touches; points look up their own cell, then the exact box test filters."""
+    glo = prim_lo_xy - reach
+    ghi = prim_hi_xy + reach
+    klo = np.floor(glo / cell).astype(np.int64)
+    khi = np.floor(ghi / cell).astype(np.int64)
+    span = khi - klo + 1
+    base = np.floor(min(pts_xy[:, 0].min(), glo[:, 0].min()) / cell) - 1, \
+        np.floor(min(pts_xy[:, 1].min(), glo[:, 1].min()) / cell) - 1
+    width = 4 + int(np.ceil((max(pts_xy[:, 0].max(), ghi[:, 0].max()) / cell) - base[0]))
+    cells, owners = [], []
+    for dx in range(int(span[:, 0].max())):
+        for dy in range(int(span[:, 1].max())):
+            o = np.flatnonzero((dx < span[:, 0]) & (dy < span[:, 1]))
+            cells.append((klo[o, 0] + dx - int(base[0])) + width * (klo[o, 1] + dy - int(base[1])))
+            owners.append(o)
+    cells = np.concatenate(cells)
+    owners = np.concatenate(owners)
+    order = np.argsort(cells, kind="stable")
+    cells, owners = cells[order], owners[order]
+    kp = np.floor(pts_xy / cell).astype(np.int64)
+    ph = (kp[:, 0] - int(base[0])) + width * (kp[:, 1] - int(base[1]))
+    lo = np.searchsorted(cells, ph, "left")
+    cnt = np.searchsorted(cells, ph, "right") - lo
+    pi = np.repeat(np.arange(len(ph)), cnt)
+    first = np.repeat(lo - (np.cumsum(cnt) - cnt), cnt)
+    oi = owners[np.arange(len(pi)) + first]
+    q = pts_xy[pi]
+    inside = np.all((q >= glo[oi]) & (q <= ghi[oi]), axis=1)
+    return pi[inside], oi[inside]
+
+
+def _xy_box(X, prims):
+    P = X[prims][..., :2]
+    return P.min(axis=1), P.max(axis=1)
+
+
+def _point_side(Xp, pid, Xt, tris, dhat, reach, cell):
+    """Points `pid` of one layer against the triangles of another: Voronoi-region
+    classification of every candidate within the window, d < dhat.  Returns
+    (point, tri-local) index arrays and the region code per kept pair."""
+    lo, hi = _xy_box(Xt, tris)
+    pi, ti = _pairs_near(Xp[pid, :2], lo, hi, cell, reach)
+    P = Xp[pid[pi]]
+    d, reg = _closest_pt_triangle(P, Xt[tris[ti, 0]], Xt[tris[ti, 1]], Xt[tris[ti, 2]])
+    keep = d < dhat
+    return pid[pi[keep]], ti[keep], reg[keep], d[keep]
+
+
+def _proximity(layers, dhat, reach, cell, eps_cross=1e-3):
+    """Typed proximity stencils between every pair of distinct layers (global
+    vertex ids).  Each layer is (X, off, surface triangles, surface edges,
+    surface points) in its own local ids.  Returns {type: (m, 4) int64 pool}
+    deduplicated by canonical tuple, and the matching squared distances."""
+    pools = {PT: [], EE: [], PE: [], PP: []}
+    dists = {PT: [], EE: [], PE: [], PP: []}
+    edge_of_region = np.array([[0, 1], [1, 2], [2, 0]])
+    for l in range(len(layers)):
+        for u in range(len(layers)):
+            if l == u:
+                continue
+            XL, oL, tL, eL, vL = layers[l]
+            XU, oU, tU, eU, vU = layers[u]
+            # points of U against triangles of L (both orders are visited)
+            p, t, reg, d = _point_side(XU, vU, XL, tL, dhat, reach, cell)
+            face = reg == 0
+            pools[PT].append(np.stack([p[face] + oU, *(tL[t[face]].T + oL)], 1))
+            dists[PT].append(d[face])
+            ed = (reg >= 1) & (reg <= 3)
+            e = tL[t[ed][:, None], edge_of_region[reg[ed] - 1]] + oL
+            e.sort(axis=1)
+            pools[PE].append(np.stack([p[ed] + oU, e[:, 0], e[:, 1], np.full(ed.sum(), -1)], 1))
+            dists[PE].append(d[ed])
+            vx = reg >= 4
+            q = tL[t[vx], reg[vx] - 4] + oL
+            a_, b_ = p[vx] + oU, q
+            pools[PP].append(np.stack([np.minimum(a_, b_), np.maximum(a_, b_), np.full(vx.sum(), -1),
+                                       np.full(vx.sum(), -1)], 1))
+            dists[PP].append(d[vx])
+            if u < l:
+                continue
+            # edges of U against edges of L (each unordered layer pair once)
+            mid = 0.5 * (XU[eU[:, 0], :2] + XU[eU[:, 1], :2])
+            lo, hi = _xy_box(XL, eL)
+            ui, li = _pairs_near(mid, lo, hi, cell, reach)
+            p1, q1 = XU[eU[ui, 0]], XU[eU[ui, 1]]
+            p2, q2 = XL[eL[li, 0]], XL[eL[li, 1]]
+            dd, s, tt = _closest_seg_seg(p1, q1, p2, q2)
+            cr = np.cross(q1 - p1, q2 - p2)
+            ok = (cr * cr).sum(1) >= eps_cross * ((q1 - p1) ** 2).sum(1) * ((q2 - p2) ** 2).sum(1)
+            ok &= (dd < dhat) & (s > 0) & (s < 1) & (tt > 0) & (tt < 1)
+            A = eU[ui[ok]] + oU
+            B = eL[li[ok]] + oL
+            lo_first = A[:, 0] < B[:, 0]
+            pools[EE].append(np.where(lo_first[:, None], np.concatenate([A, B], 1), np.concatenate([B, A], 1)))
+            dists[EE].append(dd[ok])
+    out, dout = {}, {}
+    for t in pools:
+        P = np.concatenate(pools[t]).astype(np.int64)
+        D = np.concatenate(dists[t])
+        P, first = np.unique(P, axis=0, return_index=True)
+        out[t], dout[t] = P, D[first]
+    return out, dout
+
+
+def c3_cloth(seed=SEEDS["C3"], block=(50, 50, 20), a=0.02, sheet_cells=250, n_sheets=4,
+             counts=(400_000, 400_000, 150_000, 50_000), E=1e5, nu=0.4, E_c=1e5, nu_c=0.3, rho=1000.0,
+             thickness=1e-3, k_b=0.055, h=1e-2, kappa=1e4, dhat=1e-3, reach=None, name="C3"):
+    """Heterogeneous workload: a Kuhn tet block (per-tet random rest shapes as in
+    the 40^3 workload, top face flat) under `n_sheets` stacked cloth sheets
+    (StVK membrane + dihedral bending, flat at rest), sheet k rotated by
+    7.5 + 15k degrees about the vertical axis through (0.5, 0.5), heights given
+    by nested gap fields z_k = z_top + sum_{j<=k} g_j with
+    g_j = sqrt(10^(-5 + 2 w_j)), w_j = tri(4 (x cos b_j + y sin b_j)), b_j seeded.
+
+    Contacts: a near-field hashed proximity search (window `reach`, default one
+    sheet spacing) between every pair of layers, Voronoi-region classification
+    of point-triangle candidates into PT / PE / PP, interior-closest-point EE
+    candidates with IPC's near-parallel cut, d < dhat, de-duplication by
+    canonical tuple, then seeded subsampling to exactly `counts`
+    (PT, EE, PE, PP).  Fails if a type has fewer candidates than asked for."""
+    r_pos, r_con, r_beta, _ = _streams(seed)
+    nx, ny, nz = block
+    Xb = grid_vertices(nx, ny, nz, a)
+    tets = kuhn_tets(nx, ny, nz)
+    dm_inv, vol = _random_rest_shapes(r_pos, Xb, tets)
+    nb = Xb.shape[0]
+    ztop = nz * a
+    betas = r_beta.uniform(0, 2 * np.pi, n_sheets)
+    spacing = 1.0 / sheet_cells
+    reach = spacing if reach is None else reach
+    top_k = nz
+    layers = [(Xb, 0, face_triangles(nx, ny, top_k), face_edges(nx, ny, top_k),
+               np.unique(face_triangles(nx, ny, top_k)))]
+    tri_all, dm2_all, area_all, hinge_all, hstiff_all, Xs = [], [], [], [], [], []
+    off = nb
+    z = None
+    for k in range(n_sheets):
+        uv, xy, tris, hinges = sheet(sheet_cells, np.deg2rad(7.5 + 15.0 * k))
+        w = _tri_wave(4.0 * (xy[:, 0] * np.cos(betas[k]) + xy[:, 1] * np.sin(betas[k])))
+        gap = np.sqrt(10.0 ** (-5.0 + 2.0 * w))
+        z = (ztop if z is None else z) + gap
+        X = np.concatenate([xy, z[:, None]], 1)
+        Xs.append(X)
+        Dm = np.stack([uv[tris[:, 1]] - uv[tris[:, 0]], uv[tris[:, 2]] - uv[tris[:, 0]]], 2)
+        dm2_all.append(np.linalg.inv(Dm))
+        area_all.append(0.5 * np.abs(np.linalg.det(Dm)))
+        tri_all.append(tris + off)
+        e2 = ((uv[hinges[:, 1]] - uv[hinges[:, 0]]) ** 2).sum(1)
+        u1, u2 = uv[hinges[:, 1]] - uv[hinges[:, 0]], uv[hinges[:, 2]] - uv[hinges[:, 0]]
+        u3 = uv[hinges[:, 3]] - uv[hinges[:, 0]]
+        A12 = 0.5 * (np.abs(u1[:, 0] * u2[:, 1] - u1[:, 1] * u2[:, 0]) +
+                     np.abs(u1[:, 0] * u3[:, 1] - u1[:, 1] * u3[:, 0]))
+        hinge_all.append(hinges + off)
+        hstiff_all.append(k_b * 3.0 * e2 / A12)
+        edges = np.unique(np.sort(np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]]), 1), axis=0)
+        layers.append((X, off, tris, edges, np.arange(X.shape[0])))
+        off += X.shape[0]
+    pool, pdist = _proximity(layers, dhat, reach, cell=max(reach, spacing))
+    ctype, cidx, dsel = [], [], []
+    for t, want in zip((PT, EE, PE, PP), counts):
+        if len(pool[t]) < want:
+            raise RuntimeError(f"{name}: only {len(pool[t])} candidates of type {t} for {want} stencils")
+        pick = np.sort(r_con.choice(len(pool[t]), want, replace=False))
+        cidx.append(pool[t][pick])
+        dsel.append(pdist[t][pick])
+        ctype.append(np.full(want, t))
+    X0 = np.concatenate([Xb] + Xs)
+    n = X0.shape[0]
+    tri_idx = np.concatenate(tri_all)
+    tri_area = np.concatenate(area_all)
+    mass = _lumped_mass(n, tets, vol, rho)
+    np.add.at(mass, tri_idx.ravel(), np.repeat(rho * thickness * tri_area / 3.0, 3))
+    mu, lam = lame(E, nu)
+    hidx = np.concatenate(hinge_all)
+    p = _pack(n, X0, np.zeros((0, 3)), mass, X0 + h * h * GRAVITY, tets, dm_inv, vol,
+              np.concatenate(ctype), np.concatenate(cidx), mu=mu, lam=lam, h=h, kappa=kappa, dhat=dhat,
+              rho=rho, name=name)
+    p.update(tri_idx=np.ascontiguousarray(tri_idx, dtype=np.int32),
+             tri_dm_inv=np.ascontiguousarray(np.concatenate(dm2_all)),
+             tri_area=np.ascontiguousarray(tri_area),
+             mu_c=E_c / (2.0 * (1.0 + nu_c)), lam_c=E_c * nu_c / (1.0 - nu_c * nu_c), thickness=thickness,
+             hinge_idx=np.ascontiguousarray(hidx, dtype=np.int32),
+             hinge_rest=np.ascontiguousarray(np.stack([np.zeros(len(hidx)), np.concatenate(hstiff_all)], 1)),
+             contact_d=np.concatenate(dsel),
+             pool_sizes={int(t): int(len(pool[t])) for t in pool})
+    return p
+
+
+def small_cloth(seed=31, counts=(250, 250, 100, 40)):
+    """A few-thousand-stencil version of the heterogeneous workload: a 6x6x2
+    block under two 14x14 sheets."""
+    return c3_cloth(seed=seed, block=(6, 6, 2), a=1.0 / 6, sheet_cells=14, n_sheets=2, counts=counts,
+                    name="cloth_small")

@@ -46,7 +46,7 @@ class Contacts(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("proj", C.c_int32), ("hessian", C.c_int32), ("barrier", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("proj", C.c_int32), ("barrier", C.c_int32)]
 
 
 class EvalInfo(C.Structure):
@@ -67,7 +67,7 @@ class PcgInfo(C.Structure):
 
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("max_halvings", C.c_int32), ("armijo", C.c_double),
-                ("tie_rtol", C.c_double)]
+                ("tie_rtol", C.c_double), ("hessian", C.c_int32)]
 
 
 class NewtonInfo(C.Structure):
@@ -134,8 +134,7 @@ class Yasps:
     :mod:`paper_2605_23088_amd.synth`).  Problem arrays are uploaded once and
     kept alive here; positions are (n_free, 3) float64 CUDA tensors."""
 
-    def __init__(self, prob, device="cuda", precision=FP64, proj=F_SPACE, hessian=PROJECTED, barrier=SQLOG,
-                 contacts=True):
+    def __init__(self, prob, device="cuda", precision=FP64, proj=F_SPACE, barrier=SQLOG, contacts=True):
         if not torch.cuda.is_available():
             raise RuntimeError("the yasps library needs a ROCm GPU")
         self.dev = torch.device(device)
@@ -175,7 +174,7 @@ class Yasps:
         g = np.asarray(prob.get("gravity", [0, 0, -9.81]), np.float64)
         P.gravity = (C.c_double * 3)(*g)
         P.is_static = int(bool(prob.get("static", False)))
-        self.params = Params(precision, proj, hessian, barrier)
+        self.params = Params(precision, proj, barrier)
         self.stream = torch.cuda.current_stream(d)
         ctx = C.c_void_p()
         rc = L.yasps_create(C.byref(ctx), C.c_void_p(self.stream.cuda_stream), C.byref(P), C.byref(self.params))
@@ -263,8 +262,8 @@ class Yasps:
         return x, dict(iters=info.iters, rel_residual=info.rel_residual, status=info.status, rc=rc)
 
     def newton_step(self, x, rtol=1e-8, max_iter=20000, max_halvings=40, armijo=1e-4, tie_rtol=0.0,
-                    allow=(E_NOCONV,)):
-        prm = NewtonParams(rtol, max_iter, max_halvings, armijo, tie_rtol)
+                    hessian=PROJECTED, allow=(E_NOCONV,)):
+        prm = NewtonParams(rtol, max_iter, max_halvings, armijo, tie_rtol, hessian)
         info = NewtonInfo()
         rc = self._check(lib().yasps_newton_step(self.ctx, _ptr(x), C.byref(prm), C.byref(info)), allow)
         out = {k: getattr(info, k) for k, _ in NewtonInfo._fields_}
