@@ -1,12 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: one IPC Newton iteration on one MI355X.
 
-A step is one full pass of the hot path on the 40x40x40-cell workload
-(384,000 stable Neo-Hookean tets, 68,921 free vertices, 200k point-triangle +
-200k edge-edge barrier stencils against a fixed collider, float64): per-stencil
-energy / gradient / projected Hessian, atomic-free BSR assembly, block-Jacobi
-PCG to 1e-8, and the feasibility line search.  Every step starts from the same
-positions (copied on the device), so every step does the same work.
+A step is one full pass of the hot path: per-stencil energy / gradient /
+projected Hessian, atomic-free BSR assembly, block-Jacobi PCG to 1e-8, and the
+feasibility line search.  Every step starts from the same positions (copied on
+the device), so every step does the same work.  Workloads:
+
+* ``block40`` (default): 40x40x40-cell block, 384,000 stable Neo-Hookean tets,
+  68,921 free vertices, 200k point-triangle + 200k edge-edge barrier stencils
+  against a fixed collider, float64;
+* ``cloth``: the heterogeneous scene, 300,000 tets + four 250x250 cloth sheets
+  (500,000 StVK membrane triangles, 748,000 hinges) + 1M PT/EE/PE/PP contacts
+  (40/40/15/5 %), float64;
+* ``block80``: 80x80x52-cell block, 1,996,800 tets + 750k PT + 750k EE, run in
+  float64 or (``--precision mixed``) in the precision form.
 
 Prints ONE JSON line.  `value` is stencils processed per second of Newton
 iteration (Mstencils/s); `ms_per_step` is the Newton-iteration time.  After the
@@ -26,9 +33,11 @@ METRIC = "Newton-iter ms (eval+BSR assembly+PCG) at 384k tets; Mstencils/s; HBM 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 
-# Algorithmic work per unit ("Measurement"):
+# Algorithmic work per unit:
 SNH_FLOPS_PER_TET = 4.0e3        # closed-form F-space eigensystem: 3x3 SVD, 9 rank-one modes, J_F map
 CONTACT_FLOPS = {0: 3.0e4, 1: 1.0e4, 2: 3.0e4, 3: 1.0e4}  # PT 9x9, EE 6x6 eigenproblems
+MEMBRANE_FLOPS = 6.0e3           # 6x6 F-space Jacobi eigenproblem and the J_F map
+HINGE_FLOPS = 3.0e4              # 9x9 Helmert-reduced Jacobi eigenproblem
 
 
 def log(msg):
@@ -42,7 +51,9 @@ def algorithmic(prob, g, view):
     ct = prob["ctype"]
     nnzb = view.nnzb_static + view.nnzb_dynamic
     c_flops = sum(CONTACT_FLOPS[int(t)] * int((ct == t).sum()) for t in range(4))
+    cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))
     return {
+        "cloth_eval": ("alu", cl_flops, "TFLOP/s"),
         # FP64 ALU bound
         "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
         "contact_eval": ("alu", c_flops, "TFLOP/s"),
@@ -57,20 +68,48 @@ def algorithmic(prob, g, view):
     }
 
 
-def cpu_baseline(prob):
-    """The oracle's Newton step on the same workload (host cores)."""
+def n_stencils(prob):
+    return (prob["tet_idx"].shape[0] + prob["ctype"].shape[0] + len(prob.get("tri_idx", [])) +
+            len(prob.get("hinge_idx", [])))
+
+
+def subsample(prob, frac, seed=1):
+    """Every stencil class thinned to a seeded fraction (same vertices)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    q = dict(prob)
+
+    def pick(n):
+        return np.sort(rng.choice(n, max(1, int(n * frac)), replace=False))
+
+    k = pick(prob["tet_idx"].shape[0])
+    q["tet_idx"], q["dm_inv"], q["vol"] = prob["tet_idx"][k], prob["dm_inv"][k], prob["vol"][k]
+    k = pick(prob["ctype"].shape[0])
+    q["ctype"], q["cidx"] = prob["ctype"][k], prob["cidx"][k]
+    if len(prob.get("tri_idx", [])):
+        k = pick(len(prob["tri_idx"]))
+        q["tri_idx"], q["tri_dm_inv"], q["tri_area"] = prob["tri_idx"][k], prob["tri_dm_inv"][k], prob["tri_area"][k]
+        k = pick(len(prob["hinge_idx"]))
+        q["hinge_idx"], q["hinge_rest"] = prob["hinge_idx"][k], prob["hinge_rest"][k]
+    return q
+
+
+def cpu_baseline(prob, frac=1.0):
+    """The oracle's Newton step on the workload, or on a seeded fraction of its
+    stencils (host cores)."""
     import torch
     from oracle import assemble as oasm
     from oracle import newton as onewton
+    q = prob if frac >= 1.0 else subsample(prob, frac)
     t0 = time.perf_counter()
-    o = oasm.Oracle(prob)
+    o = oasm.Oracle(q)
     t1 = time.perf_counter()
-    _, info = onewton.newton_step(o, prob["x0"], rtol=1e-8)
+    _, info = onewton.newton_step(o, q["x0"], rtol=1e-8)
     t2 = time.perf_counter()
-    stencils = prob["tet_idx"].shape[0] + prob["ctype"].shape[0]
-    return {"value": stencils / (t2 - t1) / 1e6, "unit": "Mstencils/s", "cores": torch.get_num_threads(),
+    what = "the full workload" if frac >= 1.0 else f"a seeded {frac:g} fraction of every stencil class"
+    return {"value": n_stencils(q) / (t2 - t1) / 1e6, "unit": "Mstencils/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": "the full workload: one Newton step (eval + assembly + PCG to 1e-8 + line search); "
+            "sample": f"{what}: one Newton step (eval + assembly + PCG to 1e-8 + line search); "
                       f"{t2 - t1:.2f} s, pattern set-up {t1 - t0:.2f} s excluded, {info['cg_iters']} PCG iterations"}
 
 
@@ -81,7 +120,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profiled-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cells", type=int, default=40, help="block size (default: the 40^3 workload)")
+    ap.add_argument("--cells", type=int, default=40, help="block size of the block40 workload")
+    ap.add_argument("--workload", choices=["block40", "cloth", "block80"], default="block40")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU sharding "
@@ -92,18 +133,32 @@ def main():
     import torch
 
     from paper_2605_23088_amd import synth
-    from paper_2605_23088_amd.yasps import KERNEL_CLASSES, Yasps
+    from paper_2605_23088_amd.yasps import FP64, KERNEL_CLASSES, MIXED, Yasps
 
-    log("[bench] generating workload")
-    if args.cells == 40:
+    log(f"[bench] generating workload {args.workload}")
+    cpu_frac = 1.0
+    if args.workload == "cloth":
+        prob = synth.c3_cloth()
+        cpu_frac = 0.125
+        desc = ("heterogeneous scene: 50x50x20-cell tet block + four 250x250 cloth sheets (StVK membranes, "
+                "dihedral hinges), 1M PT/EE/PE/PP contacts 40/40/15/5 %")
+    elif args.workload == "block80":
+        prob = synth.c4_block()
+        cpu_frac = 0.125
+        desc = "80x80x52-cell Kuhn block + 750k PT + 750k EE collider stencils"
+    elif args.cells == 40:
         prob = synth.c2_block()
+        desc = "40x40x40-cell Kuhn block"
     else:
         c = args.cells
         prob = synth.block_problem(c, c, c, 1.0 / c, 200_000 * c ** 3 // 64000, 200_000 * c ** 3 // 64000,
                                    synth.SEEDS["C2"], name=f"C2-{c}")
+        desc = f"{c}x{c}x{c}-cell Kuhn block"
     nt, nc = prob["tet_idx"].shape[0], prob["ctype"].shape[0]
-    log(f"[bench] {nt} tets, {prob['n_free']} free vertices, {nc} contacts; creating context")
-    g = Yasps(prob)
+    nf, nh = len(prob.get("tri_idx", [])), len(prob.get("hinge_idx", []))
+    log(f"[bench] {nt} tets, {nf} triangles, {nh} hinges, {prob['n_free']} free vertices, {nc} contacts; "
+        "creating context")
+    g = Yasps(prob, precision=MIXED if args.precision == "mixed" else FP64)
     x0 = torch.as_tensor(prob["x0"], dtype=torch.float64, device="cuda").contiguous()
     x = x0.clone()
     for i in range(args.warmup):
@@ -124,10 +179,14 @@ def main():
 
     # profiled pass: per-kernel-class device time with HIP events on the library stream
     g.profile(True)
+    pinfos = []
     for _ in range(args.profiled_steps):
         x.copy_(x0)
-        g.newton_step(x)
+        pinfos.append(g.newton_step(x))
     stats = g.profile_stats()
+    # PCG launches that do work: one SpMV and one update per iteration (the
+    # last polling batch also issues launches that exit at once)
+    cg_work = float(np.mean([i["cg_iters"] for i in pinfos]))
     g.profile(False)
     view = g.view()
     model = algorithmic(prob, g, view)
@@ -136,6 +195,8 @@ def main():
         if not st["launches"]:
             continue
         avg_ms = st["total_ms"] / st["launches"]
+        if name in ("pcg_spmv", "pcg_update"):
+            avg_ms = st["total_ms"] / args.profiled_steps / cg_work
         k = {"launches_per_step": st["launches"] / args.profiled_steps, "avg_ms": avg_ms,
              "ms_per_step": st["total_ms"] / args.profiled_steps}
         if name in model:
@@ -156,9 +217,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(prob)
+        cpu = cpu_baseline(prob, cpu_frac)
 
-    stencils = nt + nc
+    stencils = n_stencils(prob)
+    types = np.bincount(prob["ctype"], minlength=4)
     line = {
         "metric": METRIC,
         "value": stencils / (ms / 1000.0) / 1e6,
@@ -170,13 +232,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.cells}x{args.cells}x{args.cells}-cell Kuhn block: {nt} tets, "
-                               f"{prob['n_free']} free vertices, {int((prob['ctype'] == 0).sum())} PT + "
-                               f"{int((prob['ctype'] == 1).sum())} EE collider stencils; FP64 Newton step, "
-                               "PCG rtol 1e-8",
-                   "tets": nt, "contacts": nc, "free_vertices": int(prob["n_free"]),
+        "config": {"workload": f"{desc}: {nt} tets, {nf} membrane triangles, {nh} hinges, "
+                               f"{prob['n_free']} free vertices, {types[0]} PT + {types[1]} EE + {types[2]} PE + "
+                               f"{types[3]} PP contact stencils; {args.precision.upper()} Newton step, PCG rtol 1e-8",
+                   "tets": nt, "triangles": nf, "hinges": nh, "contacts": nc, "free_vertices": int(prob["n_free"]),
                    "nnzb_static": view.nnzb_static, "nnzb_dynamic": view.nnzb_dynamic},
         "newton_iter_ms": ms,
         "phases_ms": phases,

@@ -4,6 +4,9 @@
  *
  *     E(x) = 1/2 |x - x_tilde|_M^2 + h^2 sum_t Psi_t(x) + sum_s kappa b(d_s(x)),
  *
+ * where the elastic sum runs over tets and, for cloth, over StVK membrane
+ * triangles and dihedral bending hinges (the paper's cloth examples,
+ * section "Examples").
  * after "YASPS: A Symbolic Framework for Extensible, High-Performance IPC
  * Simulation" (ACM TOG 45(4), 2026).  The library evaluates per-stencil
  * energy, gradient and PSD-projected local Hessians (stable Neo-Hookean tets,
@@ -68,7 +71,7 @@ typedef int32_t yasps_status;
 #define YASPS_F_SPACE 0 /* h^2 J_F^T Proj(d2Psi/dF2) J_F (9x9 eigenproblem), section
                            "Eigendecomposition: Manual Optimization" */
 #define YASPS_X_SPACE 1 /* Proj(h^2 d2Psi/dx2) over the tet's free vertices */
-/* yasps_params.hessian and the `flags` argument of yasps_eval_stencils */
+/* yasps_newton_params.hessian and the `flags` argument of yasps_eval_stencils */
 #define YASPS_PROJECTED 0 /* local Hessians projected to the PSD cone (negative eigenvalues -> 0) */
 #define YASPS_EXACT 1     /* unprojected local Hessians (adjoint solves) */
 /* yasps_params.barrier */
@@ -94,6 +97,22 @@ typedef struct {
   double dhat;             /* barrier activation, a SQUARED distance; d >= dhat contributes 0 */
   double gravity[3];       /* used only when is_static: adds -sum_v m_v gravity . x_v */
   int32_t is_static;       /* 1: static equilibrium (no inertia term), 0: implicit Euler step */
+  /* Cloth (all optional; n_tris = n_hinges = 0 for volumetric scenes).  Both
+   * terms are elastic energies and are scaled by h^2 like the tets'. */
+  int32_t n_tris;           /* StVK membrane triangles */
+  const int32_t* tri_idx;   /* [3][n_tris] vertex ids, counter-clockwise in the rest frame */
+  const double* tri_dm_inv; /* [4][n_tris] inverse 2x2 rest edge matrices [X1 - X0, X2 - X0]^-1 in a
+                               2-D frame of the rest triangle, row-major components */
+  const double* tri_area;   /* [n_tris] rest areas */
+  double mu_c, lambda_c;    /* membrane Lame parameters: Psi = A t [mu tr(G^2) + lambda/2 (tr G)^2],
+                               G = (F^T F - I) / 2 */
+  double thickness;         /* t */
+  int32_t n_hinges;         /* dihedral bending hinges */
+  const int32_t* hinge_idx; /* [4][n_hinges]: shared edge (x0, x1), then the wing x2 of the triangle
+                               (x0, x1, x2) and the wing x3 of the triangle (x1, x0, x3); at least one
+                               free vertex each */
+  const double* hinge_rest; /* [2][n_hinges]: rest angle theta_bar, stiffness k (E = k (theta -
+                               theta_bar)^2, k = k_b 3 |e_bar|^2 / (A1 + A2) for discrete shells) */
 } yasps_problem;
 
 typedef struct {
@@ -237,7 +256,8 @@ yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* 
 #define YASPS_K_SPMV 5          /* PCG: w = H u with the u.w partials */
 #define YASPS_K_PCG_UPDATE 6    /* PCG: recurrences, vector updates, preconditioning */
 #define YASPS_K_LINESEARCH 7    /* line-search energy and feasibility kernels */
-#define YASPS_K_COUNT 8
+#define YASPS_K_CLOTH 8         /* membrane and hinge evaluation */
+#define YASPS_K_COUNT 9
 
 /* Opt-in per-kernel timing with HIP events recorded on the context stream
  * around every launch of each class (adds a little launch overhead; off by

@@ -170,8 +170,17 @@ class Oracle:
         h2 = float(self.p["h"]) ** 2
         Et = h2 * torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol)
         Ecl = 0.0
-        if len(self.tri_idx) or len(self.hinge_idx):
-            Ecl = float(self.tris(x)[0].sum()) + float(self.hinges(x)[0].sum())
+        if len(self.tri_idx):
+            p = self.p
+            xf, _ = local.gather_positions(local.T(x), self.x_fixed, self.tri_idx, self.n)
+            nf = xf.shape[0]
+            Ef = torch.vmap(en.stvk_membrane)(xf[:, :3], self.tri_dm_inv, self.tri_area,
+                                              torch.full((nf,), float(p["thickness"])),
+                                              torch.full((nf,), float(p["mu_c"])), torch.full((nf,), float(p["lam_c"])))
+            Ecl += h2 * float(Ef.sum())
+        if len(self.hinge_idx):
+            xh, _ = local.gather_positions(local.T(x), self.x_fixed, self.hinge_idx, self.n)
+            Ecl += h2 * float(torch.vmap(en.hinge_energy)(xh, self.hinge_theta, self.hinge_stiff).sum())
         d = self.distances(x)
         dhat, kappa = float(self.p["dhat"]), float(self.p["kappa"])
         dt = torch.as_tensor(d)

@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libyasps.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("YASPS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "elastic.hip", "contact.hip", "assembly.hip", "pcg.hip", "pattern.cpp"]
+SOURCES = ["api.hip", "elastic.hip", "contact.hip", "cloth.hip", "assembly.hip", "pcg.hip", "pattern.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

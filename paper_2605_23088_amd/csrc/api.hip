@@ -99,7 +99,7 @@ struct yasps_ctx {
   hipStream_t stream = nullptr;
   yasps_problem P{};
   yasps_params prm{};
-  int n = 0, nt = 0, nc = 0;
+  int n = 0, nt = 0, nc = 0, nf = 0, nh = 0;
   std::string err;
   std::vector<void*> allocs;      // everything allocated for the static part / workspace
   std::vector<void*> dyn_allocs;  // everything allocated for the current contacts
@@ -112,6 +112,10 @@ struct yasps_ctx {
   int nblk_s = 0, ngrd_s = 0;
   double *stg_s = nullptr, *gstg_s = nullptr, *vals_s = nullptr;
   float *stg_s32 = nullptr, *vals_s32 = nullptr;
+  // cloth (static part): membranes in API order, hinges grouped by free-vertex count
+  int32_t *spos_f = nullptr, *gpos_f = nullptr, *spos_h = nullptr, *gpos_h = nullptr, *h_idx = nullptr;
+  double* h_rest = nullptr;
+  std::vector<Group> hgroups;
 
   // dynamic part
   PartPattern hpat_d;
@@ -188,7 +192,8 @@ yasps_status upload_part(yasps_ctx* c, std::vector<void*>& list, const PartPatte
   return YASPS_OK;
 }
 
-// Partials layout: [inertia | tets | contact energy | contact min d | contact active count]
+// Partials layout: [inertia | tets, membranes, hinge groups | contact energy |
+// contact min d | contact active count]
 struct PartsLayout {
   int off[6];
 };
@@ -197,9 +202,11 @@ PartsLayout parts_layout(const yasps_ctx* c) {
   PartsLayout L;
   int nce = 0;
   for (const Group& g : c->groups) nce += grid_of(g.end - g.begin, EVAL_BLOCK);
+  int nel = grid_of(c->nt, EVAL_BLOCK) + grid_of(c->nf, EVAL_BLOCK);
+  for (const Group& g : c->hgroups) nel += grid_of(g.end - g.begin, EVAL_BLOCK);
   L.off[0] = 0;
   L.off[1] = L.off[0] + grid_of(c->n, EVAL_BLOCK);
-  L.off[2] = L.off[1] + grid_of(c->nt, EVAL_BLOCK);
+  L.off[2] = L.off[1] + nel;
   L.off[3] = L.off[2] + nce;
   L.off[4] = L.off[3] + nce;
   L.off[5] = L.off[4] + nce;
@@ -234,6 +241,51 @@ SnhArgs snh_args(const yasps_ctx* c, const double* x) {
   a.blk32 = c->stg_s32;
   a.grd = c->gstg_s;
   a.e_part = c->parts + parts_layout(c).off[1];
+  a.flags = c->flags;
+  return a;
+}
+
+MembraneArgs membrane_args(const yasps_ctx* c, const double* x) {
+  MembraneArgs a{};
+  a.n_free = c->n;
+  a.x = x;
+  a.x_fixed = c->P.x_fixed;
+  a.nf = c->nf;
+  a.idx = c->P.tri_idx;
+  a.dm_inv = c->P.tri_dm_inv;
+  a.area = c->P.tri_area;
+  a.mu = c->P.mu_c;
+  a.lam = c->P.lambda_c;
+  a.thick = c->P.thickness;
+  a.h2 = c->P.h * c->P.h;
+  a.spos = c->spos_f;
+  a.gpos = c->gpos_f;
+  a.blk = c->stg_s;
+  a.blk32 = c->prm.precision == YASPS_MIXED ? c->stg_s32 : nullptr;
+  a.grd = c->gstg_s;
+  a.e_part = c->parts + parts_layout(c).off[1] + grid_of(c->nt, EVAL_BLOCK);
+  a.flags = c->flags;
+  return a;
+}
+
+// part_off: partials before this group within the hinge partials
+HingeArgs hinge_args(const yasps_ctx* c, const double* x, const Group& g, int part_off) {
+  HingeArgs a{};
+  a.n_free = c->n;
+  a.x = x;
+  a.x_fixed = c->P.x_fixed;
+  a.begin = g.begin;
+  a.end = g.end;
+  a.nh = c->nh;
+  a.idx = c->h_idx;
+  a.rest = c->h_rest;
+  a.h2 = c->P.h * c->P.h;
+  a.spos = c->spos_h;
+  a.gpos = c->gpos_h;
+  a.blk = c->stg_s;
+  a.blk32 = c->prm.precision == YASPS_MIXED ? c->stg_s32 : nullptr;
+  a.grd = c->gstg_s;
+  a.e_part = c->parts + parts_layout(c).off[1] + grid_of(c->nt, EVAL_BLOCK) + grid_of(c->nf, EVAL_BLOCK) + part_off;
   a.flags = c->flags;
   return a;
 }
@@ -351,6 +403,10 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
     return fail(nullptr, YASPS_E_ARG, "mass / x_tilde missing");
   if (P->n_fixed > 0 && !P->x_fixed) return fail(nullptr, YASPS_E_ARG, "x_fixed missing");
   if (P->n_tets > 0 && (!P->tet_idx || !P->dm_inv || !P->vol)) return fail(nullptr, YASPS_E_ARG, "tet arrays missing");
+  if (P->n_tris < 0 || P->n_hinges < 0) return fail(nullptr, YASPS_E_ARG, "negative cloth size");
+  if (P->n_tris > 0 && (!P->tri_idx || !P->tri_dm_inv || !P->tri_area))
+    return fail(nullptr, YASPS_E_ARG, "triangle arrays missing");
+  if (P->n_hinges > 0 && (!P->hinge_idx || !P->hinge_rest)) return fail(nullptr, YASPS_E_ARG, "hinge arrays missing");
   if (!(P->dhat > 0.0) || !(P->kappa >= 0.0) || !(P->h > 0.0))
     return fail(nullptr, YASPS_E_ARG, "dhat, kappa and h must be positive");
   yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_SQLOG};
@@ -385,22 +441,91 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
       if (!valid_ids(htet.data(), c->nt, t, 4, nall))
         return bail(fail(c, YASPS_E_ARG, "tet " + std::to_string(t) + ": vertex id out of range or repeated"));
   }
-  build_pattern(c->n, htet.data(), c->nt, true, c->hpat_s);
+  // static stencils: tets, then membrane triangles (4th entry -1), then hinges,
+  // in API order for the pattern and slot map
+  c->nf = P->n_tris;
+  c->nh = P->n_hinges;
+  const int nt = c->nt, nf = c->nf, nh = c->nh, ns = nt + nf + nh;
+  std::vector<int32_t> hst((size_t)4 * ns, -1);
+  std::vector<int32_t> htri((size_t)3 * nf), hhin((size_t)4 * nh);
+  std::vector<double> hrest((size_t)2 * nh);
+  if (nf && hipMemcpy(htri.data(), P->tri_idx, htri.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(fail(c, YASPS_E_HIP, "copying tri_idx failed"));
+  if (nh && (hipMemcpy(hhin.data(), P->hinge_idx, hhin.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(hrest.data(), P->hinge_rest, hrest.size() * 8, hipMemcpyDeviceToHost) != hipSuccess))
+    return bail(fail(c, YASPS_E_HIP, "copying hinge arrays failed"));
+  for (int a = 0; a < 4; ++a) {
+    for (int t = 0; t < nt; ++t) hst[(size_t)a * ns + t] = htet[(size_t)a * nt + t];
+    if (a < 3)
+      for (int f = 0; f < nf; ++f) hst[(size_t)a * ns + nt + f] = htri[(size_t)a * nf + f];
+    for (int h = 0; h < nh; ++h) hst[(size_t)a * ns + nt + nf + h] = hhin[(size_t)a * nh + h];
+  }
+  {
+    const int nall = P->n_free + P->n_fixed;
+    for (int f = 0; f < nf; ++f)
+      if (!valid_ids(hst.data(), ns, nt + f, 3, nall))
+        return bail(fail(c, YASPS_E_ARG, "triangle " + std::to_string(f) + ": vertex id out of range or repeated"));
+    for (int h = 0; h < nh; ++h)
+      if (!valid_ids(hst.data(), ns, nt + nf + h, 4, nall))
+        return bail(fail(c, YASPS_E_ARG, "hinge " + std::to_string(h) + ": vertex id out of range or repeated"));
+  }
+  // hinge storage order: stable by number of free vertices
+  std::vector<int> hfree(nh);
+  for (int h = 0; h < nh; ++h) {
+    int k = 0;
+    for (int a = 0; a < 4; ++a) k += hhin[(size_t)a * nh + h] < c->n ? 1 : 0;
+    if (k == 0) return bail(fail(c, YASPS_E_ARG, "hinge " + std::to_string(h) + ": no free vertex"));
+    hfree[h] = k;
+  }
+  std::vector<int32_t> horder(nh);
+  std::iota(horder.begin(), horder.end(), 0);
+  std::stable_sort(horder.begin(), horder.end(), [&](int a, int b) { return hfree[a] < hfree[b]; });
+  for (int j = 0; j < nh;) {
+    int e = j;
+    while (e < nh && hfree[horder[e]] == hfree[horder[j]]) ++e;
+    c->hgroups.push_back(Group{0, hfree[horder[j]], j, e});
+    j = e;
+  }
+  build_pattern(c->n, hst.data(), ns, true, c->hpat_s);
   Staging st;
-  std::vector<int32_t> order(c->nt);
-  std::iota(order.begin(), order.end(), 0);
+  std::vector<int32_t> order(ns);
+  std::iota(order.begin(), order.begin() + nt + nf, 0);
+  for (int j = 0; j < nh; ++j) order[nt + nf + j] = nt + nf + horder[j];
   const bool dyn = !P->is_static;
-  build_staging(c->n, htet.data(), c->nt, c->hpat_s, order, dyn, true, st);
+  build_staging(c->n, hst.data(), ns, c->hpat_s, order, dyn, true, st);
   yasps_status s = upload_part(c, c->allocs, c->hpat_s, c->ps);
   if (s) return bail(s);
+  // per-class staging positions (storage order) and the hinge arrays in storage order
+  auto rows = [&](const std::vector<int32_t>& src, int nrows, int j0, int cnt) {
+    std::vector<int32_t> out((size_t)nrows * cnt);
+    for (int q = 0; q < nrows; ++q)
+      for (int j = 0; j < cnt; ++j) out[(size_t)q * cnt + j] = src[(size_t)q * ns + j0 + j];
+    return out;
+  };
+  std::vector<int32_t> hidx_s((size_t)4 * nh);
+  std::vector<double> hrest_s((size_t)2 * nh);
+  for (int j = 0; j < nh; ++j) {
+    for (int a = 0; a < 4; ++a) hidx_s[(size_t)a * nh + j] = hhin[(size_t)a * nh + horder[j]];
+    for (int r = 0; r < 2; ++r) hrest_s[(size_t)r * nh + j] = hrest[(size_t)r * nh + horder[j]];
+  }
   c->nblk_s = st.nblocks;
   c->ngrd_s = st.ngrads;
 #define UP(dst, vec) \
   if (upload(c->allocs, &dst, vec, c->stream) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "upload " #dst));
 #define AL(dst, n) \
   if (dalloc(c->allocs, &dst, (size_t)(n)) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "hipMalloc " #dst));
-  UP(c->spos_t, st.spos);
-  UP(c->gpos_t, st.gpos);
+  // (host sources stay alive until the stream synchronisation at the end)
+  const std::vector<int32_t> spos_t = rows(st.spos, 10, 0, nt), gpos_t = rows(st.gpos, 4, 0, nt);
+  const std::vector<int32_t> spos_f = rows(st.spos, 6, nt, nf), gpos_f = rows(st.gpos, 3, nt, nf);
+  const std::vector<int32_t> spos_h = rows(st.spos, 10, nt + nf, nh), gpos_h = rows(st.gpos, 4, nt + nf, nh);
+  UP(c->spos_t, spos_t);
+  UP(c->gpos_t, gpos_t);
+  UP(c->spos_f, spos_f);
+  UP(c->gpos_f, gpos_f);
+  UP(c->spos_h, spos_h);
+  UP(c->gpos_h, gpos_h);
+  UP(c->h_idx, hidx_s);
+  UP(c->h_rest, hrest_s);
   UP(c->lead_spos, st.lead_spos);
   UP(c->lead_gpos, st.lead_gpos);
   UP(c->cptr_s, st.cptr);
@@ -532,6 +657,16 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
   c->prof.begin(YASPS_K_SNH);
   launch_snh_eval(snh_args(c, x), exact, c->prm.precision == YASPS_MIXED, c->stream);
   c->prof.end();
+  if (c->nf || c->nh) {
+    c->prof.begin(YASPS_K_CLOTH);
+    launch_membrane_eval(membrane_args(c, x), exact, c->stream);
+    int hoff = 0;
+    for (const Group& g : c->hgroups) {
+      launch_hinge_eval(g.nfree, hinge_args(c, x, g, hoff), exact, c->stream);
+      hoff += grid_of(g.end - g.begin, EVAL_BLOCK);
+    }
+    c->prof.end();
+  }
   int off = 0;
   c->prof.begin(YASPS_K_CONTACT);
   for (const Group& g : c->groups) {
@@ -597,6 +732,12 @@ yasps_status trial_energy(yasps_ctx* c, const double* x0, const double* xt, doub
   launch_inertia_energy(ia, c->stream);
   SnhArgs sa = snh_args(c, xt);
   launch_snh_energy(sa, c->stream);
+  launch_membrane_energy(membrane_args(c, xt), c->stream);
+  int hoff = 0;
+  for (const Group& g : c->hgroups) {
+    launch_hinge_energy(hinge_args(c, xt, g, hoff), c->stream);
+    hoff += grid_of(g.end - g.begin, EVAL_BLOCK);
+  }
   int off = 0;
   for (const Group& g : c->groups) {
     ContactArgs ca = contact_args(c, xt, g, off);

@@ -252,34 +252,18 @@ YHD bool diff_vars(const double (&xv)[4][3], double (&u)[Topo<TYPE>::NU][3]) {
   return ok;
 }
 
-// Energy, free-vertex gradient rows and free-vertex upper Hessian blocks of one
-// stencil with K free vertices, fl[k] = local index of the k-th free vertex
-// (increasing).  grad_sink(k, g[3]) receives the gradient row of free vertex k;
-// block_sink(I, J, B[3][3]) the block of free vertices (I <= J) with rows of
-// vertex fl[I].  Returns false when an input is not finite.  d receives the
-// squared distance; e = kappa b(d) (0 when d >= dhat or d <= 0).
-template <int TYPE, int K, bool EXACT, class GS, class BS>
-YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
-                         double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink) {
-  constexpr int NV = Topo<TYPE>::NV, NU = Topo<TYPE>::NU;
-  double u[NU][3];
-  const bool ok = diff_vars<TYPE>(xv, u);
-  Dist<TYPE> D;
-  distance<TYPE>(u, D, side);
-  d = D.d;
-  const bool active = D.d > 0.0 && D.d < dhat;
-  double b0 = 0.0, b1 = 0.0, b2 = 0.0;
-  if (active) barrier(D.d, dhat, classic, b0, b1, b2);
-  e = kappa * b0;
-  const double kb1 = kappa * b1, kb2 = kappa * b2;
-  // u-space barrier gradient and Hessian (zero when inactive)
-  double gu[3 * NU];
-#pragma unroll
-  for (int r = 0; r < 3 * NU; ++r) gu[r] = kb1 * D.g[r];
-#pragma unroll
-  for (int r = 0; r < 3 * NU; ++r)
-#pragma unroll
-    for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
+// Maps a u-space gradient gu (3 NU) and Hessian Hu (3 NU x 3 NU, upper) of an
+// energy of the difference variables u_U = sum_a TOPO::M(U, a) x_a to the
+// stencil's K free vertices (fl[k] = local index of the k-th free vertex,
+// increasing): grad_sink(k, g[3]) receives the gradient row of free vertex k,
+// block_sink(I, J, B[3][3]) the upper block of free vertices I <= J (rows of
+// vertex fl[I]).  Unless EXACT the Hessian is projected to the PSD cone: in the
+// Helmert basis when every vertex is free (exact reduction, the energy is
+// translation invariant), else on the free principal submatrix.
+template <class TOPO, int K, bool EXACT, class GS, class BS>
+YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double>& Hu, const int (&fl)[4],
+                      GS&& grad_sink, BS&& block_sink) {
+  constexpr int NV = TOPO::NV, NU = TOPO::NU;
   // coefficients M[U][fl[k]] selected at run time from the compile-time table
   double Mf[NU][K];
 #pragma unroll
@@ -288,7 +272,7 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
     for (int k = 0; k < K; ++k) {
       double m = 0.0;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) m = (fl[k] == q) ? double(Topo<TYPE>::M(U, q)) : m;
+      for (int q = 0; q < NV; ++q) m = (fl[k] == q) ? double(TOPO::M(U, q)) : m;
       Mf[U][k] = m;
     }
 #pragma unroll
@@ -313,7 +297,7 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
       for (int j = 0; j < NR; ++j) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) acc += double(Topo<TYPE>::M(U, q)) * helmert(q, j);
+        for (int q = 0; q < NV; ++q) acc += double(TOPO::M(U, q)) * helmert(q, j);
         R[U][j] = acc;
       }
     Sym<3 * NR, double> A;
@@ -330,7 +314,7 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
 #pragma unroll
             for (int U = 0; U < NU; ++U)
 #pragma unroll
-              for (int W = 0; W < NU; ++W) acc = fma(R[U][I] * R[W][J], D.H(3 * U + i, 3 * W + l), acc);
+              for (int W = 0; W < NU; ++W) acc = fma(R[U][I] * R[W][J], Hu(3 * U + i, 3 * W + l), acc);
             A(3 * I + i, 3 * J + l) = acc;
           }
     psd_project<3 * NR, double>(A);
@@ -378,7 +362,7 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
 #pragma unroll
             for (int U = 0; U < NU; ++U)
 #pragma unroll
-              for (int W = 0; W < NU; ++W) acc = fma(Mf[U][I] * Mf[W][J], D.H(3 * U + i, 3 * W + l), acc);
+              for (int W = 0; W < NU; ++W) acc = fma(Mf[U][I] * Mf[W][J], Hu(3 * U + i, 3 * W + l), acc);
             A(3 * I + i, 3 * J + l) = acc;
           }
     if (!EXACT) psd_project<3 * K, double>(A);
@@ -394,6 +378,35 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
         block_sink(I, J, B);
       }
   }
+}
+
+// Energy, free-vertex gradient rows and free-vertex upper Hessian blocks of one
+// contact stencil with K free vertices (sinks as in emit_reduced).  Returns
+// false when an input is not finite.  d receives the squared distance;
+// e = kappa b(d) (0 when d >= dhat or d <= 0).
+template <int TYPE, int K, bool EXACT, class GS, class BS>
+YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
+                         double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink) {
+  constexpr int NU = Topo<TYPE>::NU;
+  double u[NU][3];
+  const bool ok = diff_vars<TYPE>(xv, u);
+  Dist<TYPE> D;
+  distance<TYPE>(u, D, side);
+  d = D.d;
+  const bool active = D.d > 0.0 && D.d < dhat;
+  double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+  if (active) barrier(D.d, dhat, classic, b0, b1, b2);
+  e = kappa * b0;
+  const double kb1 = kappa * b1, kb2 = kappa * b2;
+  // u-space barrier gradient and Hessian (zero when inactive)
+  double gu[3 * NU];
+#pragma unroll
+  for (int r = 0; r < 3 * NU; ++r) gu[r] = kb1 * D.g[r];
+#pragma unroll
+  for (int r = 0; r < 3 * NU; ++r)
+#pragma unroll
+    for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
+  emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
   return ok;
 }
 

@@ -36,6 +36,47 @@ void launch_snh_energy(const SnhArgs& a, hipStream_t s);
 void launch_snh_theta_adjoint(const SnhArgs& a, const double* lambda, const double* theta,
                               double* out, hipStream_t s);
 
+// Cloth: StVK membrane triangles (3 vertices) and dihedral hinges (4).
+struct MembraneArgs {
+  int n_free;
+  const double* x;
+  const double* x_fixed;
+  int nf;
+  const int32_t* idx;     // [3][nf]
+  const double* dm_inv;   // [4][nf] row-major 2x2 inverse rest shapes
+  const double* area;     // [nf]
+  double mu, lam, thick, h2;
+  const int32_t* spos;    // [6][nf] staged block position per local pair (-1 = none)
+  const int32_t* gpos;    // [3][nf]
+  double* blk;
+  float* blk32;           // float32 staged blocks (precision form) instead of blk, or null
+  double* grd;
+  double* e_part;
+  uint32_t* flags;
+};
+void launch_membrane_eval(const MembraneArgs& a, bool exact, hipStream_t s);
+void launch_membrane_energy(const MembraneArgs& a, hipStream_t s);
+
+// Hinges stored grouped by number of free vertices; [begin, end) is one group.
+struct HingeArgs {
+  int n_free;
+  const double* x;
+  const double* x_fixed;
+  int begin, end, nh;
+  const int32_t* idx;     // [4][nh] storage order: shared edge x0, x1, wings x2, x3
+  const double* rest;     // [2][nh] rest angle, stiffness
+  double h2;
+  const int32_t* spos;    // [10][nh]
+  const int32_t* gpos;    // [4][nh]
+  double* blk;
+  float* blk32;
+  double* grd;
+  double* e_part;         // partials of this group
+  uint32_t* flags;
+};
+void launch_hinge_eval(int nfree, const HingeArgs& a, bool exact, hipStream_t s);
+void launch_hinge_energy(const HingeArgs& a, hipStream_t s);
+
 // Inertia (dynamic) or gravity potential (static) per free vertex.
 struct InertiaArgs {
   int n;

@@ -28,9 +28,9 @@ SQLOG, IPC_CLASSIC = 0, 1
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
            "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
            "yasps_profile_query", "yasps_spmv", "yasps_destroy", "yasps_last_error"]
-K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH = range(8)
+K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH, K_CLOTH = range(9)
 KERNEL_CLASSES = ["inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "pcg_spmv", "pcg_update",
-                  "linesearch"]
+                  "linesearch", "cloth_eval"]
 
 
 class Problem(C.Structure):
@@ -38,7 +38,10 @@ class Problem(C.Structure):
                 ("x_tilde", C.c_void_p), ("n_tets", C.c_int32), ("tet_idx", C.c_void_p), ("dm_inv", C.c_void_p),
                 ("vol", C.c_void_p), ("mu_lambda", C.c_void_p), ("mu", C.c_double), ("lambda_", C.c_double),
                 ("h", C.c_double), ("kappa", C.c_double), ("dhat", C.c_double), ("gravity", C.c_double * 3),
-                ("is_static", C.c_int32)]
+                ("is_static", C.c_int32), ("n_tris", C.c_int32), ("tri_idx", C.c_void_p),
+                ("tri_dm_inv", C.c_void_p), ("tri_area", C.c_void_p), ("mu_c", C.c_double), ("lambda_c", C.c_double),
+                ("thickness", C.c_double), ("n_hinges", C.c_int32), ("hinge_idx", C.c_void_p),
+                ("hinge_rest", C.c_void_p)]
 
 
 class Contacts(C.Structure):
@@ -174,6 +177,30 @@ class Yasps:
         g = np.asarray(prob.get("gravity", [0, 0, -9.81]), np.float64)
         P.gravity = (C.c_double * 3)(*g)
         P.is_static = int(bool(prob.get("static", False)))
+        # cloth: membrane triangles and bending hinges, structure-of-arrays
+        self.nf = int(len(prob.get("tri_idx", [])))
+        self.nh = int(len(prob.get("hinge_idx", [])))
+        i32 = dict(dtype=torch.int32, device=d)
+        if self.nf:
+            nf = self.nf
+            self._tri = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["tri_idx"], np.int32).T), **i32)
+            self._tdm = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["tri_dm_inv"]).reshape(nf, 4).T), **f64)
+            self._tarea = torch.as_tensor(np.asarray(prob["tri_area"], np.float64), **f64).contiguous()
+            P.n_tris = nf
+            P.tri_idx = _ptr(self._tri)
+            P.tri_dm_inv = _ptr(self._tdm)
+            P.tri_area = _ptr(self._tarea)
+            P.mu_c = float(prob["mu_c"])
+            P.lambda_c = float(prob["lam_c"])
+            P.thickness = float(prob["thickness"])
+        if self.nh:
+            nh = self.nh
+            self._hin = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["hinge_idx"], np.int32).T), **i32)
+            self._hrest = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["hinge_rest"]).reshape(nh, 2).T),
+                                          **f64)
+            P.n_hinges = nh
+            P.hinge_idx = _ptr(self._hin)
+            P.hinge_rest = _ptr(self._hrest)
         self.params = Params(precision, proj, barrier)
         self.stream = torch.cuda.current_stream(d)
         ctx = C.c_void_p()
@@ -272,7 +299,7 @@ class Yasps:
 
     def pattern(self, part):
         n = self.n
-        ns = self.nt if part == 0 else self.nc
+        ns = self.nt + self.nf + self.nh if part == 0 else self.nc
         rp = np.zeros(n + 1, np.int32)
         lib().yasps_get_pattern(self.ctx, part, rp.ctypes.data_as(C.c_void_p), None, None)
         ci = np.zeros(max(int(rp[-1]), 1), np.int32)
