@@ -162,25 +162,24 @@ class Oracle:
             g = g + self._scatter_grad(self.hinge_idx, ev["g_h"])
         return dict(values_s=vals_s, values_d=vals_d, grad=g.reshape(n, 3))
 
-    def energy(self, x):
-        """Total energy only (line search)."""
+    def energy_parts(self, x):
+        """Energies only (line search): inertia, tets, membranes, hinges, contacts."""
         x = np.asarray(x, np.float64).reshape(self.n, 3)
         e_i, _ = self.inertia(x)
         xt, _ = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
         h2 = float(self.p["h"]) ** 2
-        Et = h2 * torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol)
-        Ecl = 0.0
+        Et = h2 * float(torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol).sum())
+        Ef = Eh = 0.0
         if len(self.tri_idx):
             p = self.p
             xf, _ = local.gather_positions(local.T(x), self.x_fixed, self.tri_idx, self.n)
             nf = xf.shape[0]
-            Ef = torch.vmap(en.stvk_membrane)(xf[:, :3], self.tri_dm_inv, self.tri_area,
-                                              torch.full((nf,), float(p["thickness"])),
-                                              torch.full((nf,), float(p["mu_c"])), torch.full((nf,), float(p["lam_c"])))
-            Ecl += h2 * float(Ef.sum())
+            Ef = h2 * float(torch.vmap(en.stvk_membrane)(
+                xf[:, :3], self.tri_dm_inv, self.tri_area, torch.full((nf,), float(p["thickness"])),
+                torch.full((nf,), float(p["mu_c"])), torch.full((nf,), float(p["lam_c"]))).sum())
         if len(self.hinge_idx):
             xh, _ = local.gather_positions(local.T(x), self.x_fixed, self.hinge_idx, self.n)
-            Ecl += h2 * float(torch.vmap(en.hinge_energy)(xh, self.hinge_theta, self.hinge_stiff).sum())
+            Eh = h2 * float(torch.vmap(en.hinge_energy)(xh, self.hinge_theta, self.hinge_stiff).sum())
         d = self.distances(x)
         dhat, kappa = float(self.p["dhat"]), float(self.p["kappa"])
         dt = torch.as_tensor(d)
@@ -188,7 +187,13 @@ class Oracle:
         act = dt < dhat
         Ec = torch.where(act, bfun(torch.where(act, dt, torch.full_like(dt, dhat)), dhat, kappa),
                          torch.zeros_like(dt))
-        return e_i + float(Et.sum()) + Ecl + float(Ec.sum())
+        return dict(inertia=e_i, tets=Et, membranes=Ef, hinges=Eh, contacts=float(Ec.sum()),
+                    contact_terms=Ec.numpy())
+
+    def energy(self, x):
+        """Total energy only (line search)."""
+        e = self.energy_parts(x)
+        return e["inertia"] + e["tets"] + e["membranes"] + e["hinges"] + e["contacts"]
 
     def distances(self, x):
         xc, _ = local.gather_positions(local.T(np.asarray(x).reshape(self.n, 3)), self.x_fixed,

