@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--cells", type=int, default=40, help="block size of the block40 workload")
     ap.add_argument("--workload", choices=["block40", "cloth", "block80"], default="block40")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (the reference kernel that scales "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU sharding "
@@ -131,6 +134,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
+        return
 
     from paper_2605_23088_amd import synth
     from paper_2605_23088_amd.yasps import FP64, KERNEL_CLASSES, MIXED, Yasps

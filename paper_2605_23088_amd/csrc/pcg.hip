@@ -35,6 +35,8 @@ constexpr int SPMV_G = 8;                       // lanes per block row
 constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup and pass
 constexpr int MAX_WG_B = 1024;                  // workgroups of the SpMV kernel
 constexpr int MAX_WG_C = 512;                   // workgroups of the update kernel
+constexpr int UPD_VERTS = 64;                   // vertices per update-kernel workgroup pass
+constexpr int UPD_BLOCK = 3 * UPD_VERTS;        // update kernel: one thread per vertex component
 
 // Device scalars.  gamma / alpha are double-buffered by iteration parity;
 // `iter` is written only by the update kernel and `iter_b` only by the SpMV
@@ -50,10 +52,11 @@ namespace {
 
 // Sum of n partials in a fixed order (strided per thread, then a fixed tree),
 // computed identically by every workgroup that needs it.
+template <int BLOCK = RED_BLOCK>
 YDEV double sum_partials(const double* __restrict__ part, int n, double* lds) {
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += RED_BLOCK) acc += part[j];
-  return block_sum<RED_BLOCK>(acc, lds);
+  for (int j = threadIdx.x; j < n; j += BLOCK) acc += part[j];
+  return block_sum<BLOCK>(acc, lds);
 }
 
 template <class T, class X>
@@ -248,15 +251,19 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
 }
 
 // Iteration i: scalar recurrences, vector updates, preconditioning, and the
-// gamma / |r|^2 partials of iteration i + 1.  `nb_b` = SpMV grid.
+// gamma / |r|^2 partials of iteration i + 1.  `nb_b` = SpMV grid.  One thread
+// per vertex component (coalesced vector traffic, 3x the threads of a
+// per-vertex mapping); the three residual components of a vertex meet in LDS
+// for the 3x3 block-Jacobi product.
 template <class VT>
-__global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
+__global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
                                                                PcgState* st, int nb_b) {
   if (st->done) return;
-  __shared__ double lds[RED_BLOCK];
+  __shared__ double lds[UPD_BLOCK];
+  __shared__ double rsh[UPD_BLOCK];
   const int i = st->iter_b;
   const double gamma = st->gamma[i & 1];
-  const double delta = sum_partials(V.part_b, nb_b, lds);
+  const double delta = sum_partials<UPD_BLOCK>(V.part_b, nb_b, lds);
   const bool restart = i == st->restart_at;
   const double beta = restart ? 0.0 : gamma / st->gamma[(i - 1) & 1];
   const double pAp = restart ? delta : delta - beta * gamma / st->alpha[(i - 1) & 1];
@@ -269,32 +276,37 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     return;
   }
   const double alpha = gamma / pAp;
+  const int t = threadIdx.x;
+  const int vl = t / 3, c = t - 3 * (t / 3);
   double g = 0.0, rr = 0.0;
-  for (int v = blockIdx.x * RED_BLOCK + threadIdx.x; v < A.n; v += gridDim.x * RED_BLOCK) {
-    double r[3], u[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t k = 3 * (size_t)v + c;
+  for (int base = blockIdx.x * UPD_VERTS; base < A.n; base += gridDim.x * UPD_VERTS) {
+    const int v = base + vl;
+    const bool live = v < A.n;
+    const size_t k = 3 * (size_t)base + t;  // = 3 v + c
+    double r = 0.0;
+    if (live) {
       const VT p = VT(fma(beta, double(V.p[k]), double(V.u[k])));
-      const VT s = VT(fma(beta, double(V.s[k]), double(V.w[k])));
+      const VT sv = VT(fma(beta, double(V.s[k]), double(V.w[k])));
       V.p[k] = p;
-      V.s[k] = s;
+      V.s[k] = sv;
       x[k] = fma(alpha, double(p), x[k]);
-      const VT rc = VT(fma(-alpha, double(s), double(V.r[k])));
-      r[c] = double(rc);
+      const VT rc = VT(fma(-alpha, double(sv), double(V.r[k])));
       V.r[k] = rc;
+      r = double(rc);
     }
-    precondition(A.minv, v, r, u);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const VT uc = VT(u[c]);
-      V.u[3 * (size_t)v + c] = uc;
-      g = fma(r[c], double(uc), g);
-      rr = fma(r[c], r[c], rr);
+    rsh[t] = r;
+    __syncthreads();
+    if (live) {
+      const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
+      const VT uc = VT(M[0] * rsh[3 * vl] + M[1] * rsh[3 * vl + 1] + M[2] * rsh[3 * vl + 2]);
+      V.u[k] = uc;
+      g = fma(r, double(uc), g);
+      rr = fma(r, r, rr);
     }
+    __syncthreads();  // rsh is rewritten by the next pass
   }
-  const double gs = block_sum<RED_BLOCK>(g, lds);
-  const double rs = block_sum<RED_BLOCK>(rr, lds);
+  const double gs = block_sum<UPD_BLOCK>(g, lds);
+  const double rs = block_sum<UPD_BLOCK>(rr, lds);
   if (threadIdx.x == 0) {
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
@@ -306,7 +318,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
 }
 
 int grid_b(int n) { return std::max(1, std::min((n + SPMV_ROWS - 1) / SPMV_ROWS, MAX_WG_B)); }
-int grid_c(int n) { return std::max(1, std::min((n + RED_BLOCK - 1) / RED_BLOCK, MAX_WG_C)); }
+int grid_c(int n) { return std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C)); }
 
 template <class VT>
 void carve(void* work, int n, PcgState*& st, Vecs<VT>& V) {
@@ -377,7 +389,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       hipLaunchKernelGGL(pcg_spmv_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, V, st, nb_c, 0);
       if (tm) tm->end();
       if (tm) tm->begin(6);
-      hipLaunchKernelGGL(pcg_update_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, x, V, st, nb_b);
+      hipLaunchKernelGGL(pcg_update_kernel<VT>, dim3(nb_c), dim3(UPD_BLOCK), 0, s, A, x, V, st, nb_b);
       if (tm) tm->end();
       ++launched;
       if (MIXED && launched % REPLACE_EVERY == 0) {
