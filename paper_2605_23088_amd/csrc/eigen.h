@@ -22,11 +22,15 @@ YHD void jacobi_rotate(Sym<N, R>& A, R (&V)[N][N]) {
   const R apq = A(P, Q);
   const R app = A(P, P);
   const R aqq = A(Q, Q);
+  // Branch-free: the divisions always run (with a harmless denominator when
+  // apq = 0) and a select discards them, so no values stay live across
+  // divergent control flow (which multiplied the register footprint).
   const bool zero = (apq == R(0));
-  const R theta = zero ? R(0) : (aqq - app) / (R(2) * apq);
+  const R theta = (aqq - app) / (zero ? R(1) : R(2) * apq);
   const R sgn = theta >= R(0) ? R(1) : R(-1);
   // t = tan of the rotation angle, the smaller root of t^2 + 2 theta t - 1 = 0
-  const R t = zero ? R(0) : sgn / (fabsR(theta) + sqrtR(fmaR(theta, theta, R(1))));
+  const R tr = sgn / (fabsR(theta) + sqrtR(fmaR(theta, theta, R(1))));
+  const R t = zero ? R(0) : tr;
   const R c = R(1) / sqrtR(fmaR(t, t, R(1)));
   const R s = t * c;
   A(P, P) = fmaR(-t, apq, app);
