@@ -97,8 +97,12 @@ typedef struct {
   double dhat;             /* barrier activation, a SQUARED distance; d >= dhat contributes 0 */
   double gravity[3];       /* used only when is_static: adds -sum_v m_v gravity . x_v */
   int32_t is_static;       /* 1: static equilibrium (no inertia term), 0: implicit Euler step */
-  /* Cloth (all optional; n_tris = n_hinges = 0 for volumetric scenes).  Both
-   * terms are elastic energies and are scaled by h^2 like the tets'. */
+  /* Cloth (all optional; n_tris = n_hinges = 0 for volumetric scenes), the
+   * membrane and bending terms of the paper's cloth examples (section
+   * "Examples"; StVK membrane, discrete-shells dihedral bending).  Both are
+   * elastic energies and are scaled by h^2 like the tets'.  The membrane
+   * Hessian is projected in F-space (6x6); the hinge Hessian on its free
+   * vertices (section "Eigendecomposition (EVD) and PSD Projection"). */
   int32_t n_tris;           /* StVK membrane triangles */
   const int32_t* tri_idx;   /* [3][n_tris] vertex ids, counter-clockwise in the rest frame */
   const double* tri_dm_inv; /* [4][n_tris] inverse 2x2 rest edge matrices [X1 - X0, X2 - X0]^-1 in a
@@ -130,7 +134,7 @@ typedef struct {
 typedef struct {
   double energy;    /* total E(x), summed in float64 in a fixed order */
   double e_inertia; /* 1/2 |x - x_tilde|_M^2, or -sum m g.x when static */
-  double e_elastic; /* h^2 sum Psi_t */
+  double e_elastic; /* h^2 sum of the tet, membrane and hinge energies */
   double e_contact; /* sum kappa b(d_s) */
   double min_d;     /* smallest contact squared distance (+inf without contacts) */
   int32_t n_active; /* contact stencils with d < dhat */
@@ -184,9 +188,11 @@ typedef struct {
 } yasps_newton_info;
 
 /* Creates a context bound to the current device and `hip_stream` (a hipStream_t,
- * NULL = default stream).  Validates the tets (ids in range, 4 distinct vertices),
- * builds the static pattern and slot map (appendix "Global Hessian Compression"),
- * and allocates the workspace.  `opt` may be NULL for defaults.
+ * NULL = default stream).  Validates the tets, triangles and hinges (ids in
+ * range, distinct vertices, every hinge with a free vertex), builds the static
+ * pattern and slot map over tets, then triangles, then hinges (appendix
+ * "Global Hessian Compression"), and allocates the workspace.  `opt` may be
+ * NULL for defaults.
  * Errors: YASPS_E_ARG, YASPS_E_UNIMPL, YASPS_E_HIP.  *out is NULL on failure. */
 yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem* P,
                           const yasps_params* opt);
@@ -221,8 +227,9 @@ yasps_status yasps_assemble_bsr(yasps_ctx* ctx, yasps_bsr_view* view);
 yasps_status yasps_pcg(yasps_ctx* ctx, const double* b, double* x, double rtol, int32_t max_iter,
                        yasps_pcg_info* info);
 
-/* One projected-Newton step on the current stencil set: evaluate, assemble,
- * solve H p = -g, then backtrack from alpha0 = min(1, 0.4 min_s sqrt(d_s) /
+/* One Newton step on the current stencil set (projected local Hessians unless
+ * prm->hessian = YASPS_EXACT): evaluate, assemble, solve H p = -g, then
+ * backtrack from alpha0 = min(1, 0.4 min_s sqrt(d_s) /
  * max_v |p_v|) by halving until every contact d > 0, every PT/EE stencil keeps
  * its side of the plane/line, and E(x + alpha p) <= E(x) + armijo alpha g.p.
  * x (n_free, 3) is updated in place.  `prm` may be NULL for defaults.
@@ -232,7 +239,8 @@ yasps_status yasps_newton_step(yasps_ctx* ctx, double* x, const yasps_newton_par
 
 /* Copies one part of the pattern to HOST arrays for inspection (bit-exact tests):
  * part 0 = static, 1 = dynamic.  row_ptr has n_free + 1 entries, col_idx nnzb,
- * slot [n_stencils][10] (tets for part 0, contacts for part 1; local pair (a, b),
+ * slot [n_stencils][10] (part 0: tets, then triangles, then hinges, each in the
+ * order given at create; part 1: contacts in the order given; local pair (a, b),
  * a <= b, enumerated row by row over the stencil's used vertices; -1 = no block).
  * Any output pointer may be NULL.  Errors: YASPS_E_ARG. */
 yasps_status yasps_get_pattern(yasps_ctx* ctx, int32_t part, int32_t* row_ptr, int32_t* col_idx,

@@ -88,8 +88,8 @@ struct Profiler : LaunchTimer {
 };
 
 struct Part {  // device copy of one pattern part
-  int nnzb = 0, ntr = 0;
-  int32_t *rp = nullptr, *ci = nullptr, *tp = nullptr, *tslot = nullptr, *trow = nullptr;
+  int nnzb = 0;
+  int32_t *rp = nullptr, *ci = nullptr;
 };
 
 }  // namespace
@@ -110,8 +110,8 @@ struct yasps_ctx {
   int32_t *spos_t = nullptr, *gpos_t = nullptr, *lead_spos = nullptr, *lead_gpos = nullptr;
   int32_t *cptr_s = nullptr, *gptr_s = nullptr;
   int nblk_s = 0, ngrd_s = 0;
-  double *stg_s = nullptr, *gstg_s = nullptr, *vals_s = nullptr, *lvals_s = nullptr;
-  float *stg_s32 = nullptr, *vals_s32 = nullptr, *lvals_s32 = nullptr;
+  double *stg_s = nullptr, *gstg_s = nullptr, *vals_s = nullptr;
+  float *stg_s32 = nullptr, *vals_s32 = nullptr;
   // cloth (static part): membranes in API order, hinges grouped by free-vertex count
   int32_t *spos_f = nullptr, *gpos_f = nullptr, *spos_h = nullptr, *gpos_h = nullptr, *h_idx = nullptr;
   double* h_rest = nullptr;
@@ -124,8 +124,16 @@ struct yasps_ctx {
   int32_t *c_idx = nullptr, *spos_c = nullptr, *gpos_c = nullptr, *cptr_d = nullptr, *gptr_d = nullptr,
           *ddiag = nullptr;
   int nblk_d = 0, ngrd_d = 0;
-  double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *lvals_d = nullptr, *d_c = nullptr;
-  float *stg_d32 = nullptr, *vals_d32 = nullptr, *lvals_d32 = nullptr;
+  double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
+  float *stg_d32 = nullptr, *vals_d32 = nullptr;
+
+  // SpMV matrix: both triangles of both parts, structure of arrays (rebuilt
+  // with the contacts)
+  std::vector<void*> full_allocs;
+  int32_t *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
+  double* f_vals = nullptr;
+  float* f_vals32 = nullptr;
+  long long f_nnz = 0;
 
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
@@ -135,6 +143,7 @@ struct yasps_ctx {
   double* host_scal = nullptr;  // pinned
   int nparts_alloc = 0;
   bool evaluated = false;
+  bool assembled = false;  // the SpMV matrix holds the values of the last assembly
   Profiler prof;
 };
 
@@ -183,12 +192,29 @@ int grid_of(int n, int block) { return (n + block - 1) / block; }
 
 yasps_status upload_part(yasps_ctx* c, std::vector<void*>& list, const PartPattern& h, Part& d) {
   d.nnzb = h.nnzb;
-  d.ntr = (int)h.tslot.size();
   HIPCHK(c, upload(list, &d.rp, h.row_ptr, c->stream));
   HIPCHK(c, upload(list, &d.ci, h.col_idx, c->stream));
-  HIPCHK(c, upload(list, &d.tp, h.tptr, c->stream));
-  HIPCHK(c, upload(list, &d.tslot, h.tslot, c->stream));
-  HIPCHK(c, upload(list, &d.trow, h.trow, c->stream));
+  return YASPS_OK;
+}
+
+// (Re)builds the SpMV matrix layout over the current parts; synchronises the
+// stream so the host pattern can go out of scope.
+yasps_status build_full_matrix(yasps_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_list(c->full_allocs);
+  FullPattern fp;
+  build_full(c->n, c->hpat_s, c->nc ? &c->hpat_d : nullptr, fp);
+  c->f_nnz = (long long)fp.col.size();
+  HIPCHK(c, upload(c->full_allocs, &c->f_rp, fp.row_ptr, c->stream));
+  HIPCHK(c, upload(c->full_allocs, &c->f_col, fp.col, c->stream));
+  HIPCHK(c, upload(c->full_allocs, &c->f_src, fp.src, c->stream));
+  c->f_vals = nullptr;
+  c->f_vals32 = nullptr;
+  if (c->prm.precision == YASPS_MIXED)
+    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
+  else
+    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals, 9 * (size_t)c->f_nnz));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return YASPS_OK;
 }
 
@@ -337,27 +363,11 @@ ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, in
 PcgMatrix pcg_matrix(const yasps_ctx* c) {
   PcgMatrix A{};
   A.n = c->n;
-  A.rp_s = c->ps.rp;
-  A.ci_s = c->ps.ci;
-  A.tp_s = c->ps.tp;
-  A.tslot_s = c->ps.tslot;
-  A.trow_s = c->ps.trow;
-  const bool mixed = c->prm.precision == YASPS_MIXED;
-  A.v_s = mixed ? nullptr : c->vals_s;
-  A.v_s32 = mixed ? c->vals_s32 : nullptr;
-  A.lv_s = mixed ? nullptr : c->lvals_s;
-  A.lv_s32 = mixed ? c->lvals_s32 : nullptr;
-  if (c->nc > 0 && c->pd.nnzb > 0) {
-    A.rp_d = c->pd.rp;
-    A.ci_d = c->pd.ci;
-    A.tp_d = c->pd.tp;
-    A.tslot_d = c->pd.tslot;
-    A.trow_d = c->pd.trow;
-    A.v_d = mixed ? nullptr : c->vals_d;
-    A.v_d32 = mixed ? c->vals_d32 : nullptr;
-    A.lv_d = mixed ? nullptr : c->lvals_d;
-    A.lv_d32 = mixed ? c->lvals_d32 : nullptr;
-  }
+  A.rp = c->f_rp;
+  A.col = c->f_col;
+  A.v = c->f_vals;
+  A.v32 = c->f_vals32;
+  A.nnz = c->f_nnz;
   A.minv = c->minv;
   return A;
 }
@@ -392,6 +402,7 @@ void yasps_destroy(yasps_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  free_list(ctx->full_allocs);
   free_list(ctx->dyn_allocs);
   free_list(ctx->allocs);
   if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
@@ -537,11 +548,9 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (prm.precision == YASPS_MIXED) {
     AL(c->stg_s32, 9 * (size_t)st.nblocks);
     AL(c->vals_s32, 9 * (size_t)c->hpat_s.nnzb);
-    AL(c->lvals_s32, 9 * (size_t)c->ps.ntr);
   } else {
     AL(c->stg_s, 9 * (size_t)st.nblocks);
     AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
-    AL(c->lvals_s, 9 * (size_t)c->ps.ntr);
   }
   AL(c->gstg_s, 3 * (size_t)st.ngrads);
   AL(c->grad, 3 * (size_t)c->n);
@@ -561,6 +570,8 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   s = ensure_parts(c);
   if (s) return bail(s);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "stream sync"));
+  s = build_full_matrix(c);
+  if (s) return bail(s);
 #undef UP
 #undef AL
   *out = c;
@@ -574,10 +585,16 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_list(c->dyn_allocs);
+  free_list(c->full_allocs);  // rebuilt below, or at the next assembly if this call fails
+  c->f_rp = c->f_col = c->f_src = nullptr;
+  c->f_vals = nullptr;
+  c->f_vals32 = nullptr;
+  c->f_nnz = 0;
   c->groups.clear();
   c->pd = Part{};
   c->hpat_d = PartPattern{};
   c->evaluated = false;
+  c->assembled = false;
   const int nc = C->n_contacts;
   std::vector<int32_t> ty(nc), idx((size_t)4 * nc);
   if (nc) {
@@ -638,18 +655,16 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   if (c->prm.precision == YASPS_MIXED) {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)st.nblocks));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)c->hpat_d.nnzb));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->lvals_d32, 9 * (size_t)c->pd.ntr));
   } else {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)c->hpat_d.nnzb));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->lvals_d, 9 * (size_t)c->pd.ntr));
   }
   HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)st.ngrads));
   HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
   s = ensure_parts(c);
   if (s) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return YASPS_OK;
+  return build_full_matrix(c);
 }
 
 namespace {
@@ -706,6 +721,10 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
 }
 
 yasps_status run_assemble(yasps_ctx* c) {
+  if (!c->f_rp) {
+    const yasps_status s = build_full_matrix(c);
+    if (s) return s;
+  }
   HIPCHK(c, hipMemsetAsync(c->flags, 0, 4, c->stream));
   c->prof.begin(YASPS_K_ASSEMBLE);
   const bool mixed = c->prm.precision == YASPS_MIXED;
@@ -719,14 +738,12 @@ yasps_status run_assemble(yasps_ctx* c) {
   }
   launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
                      dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
-  // lower-triangle copies for contiguous SpMV reads
-  if (mixed) {
-    launch_mirror_f32(c->ps.ntr, c->ps.tslot, c->vals_s32, c->lvals_s32, c->stream);
-    if (dyn) launch_mirror_f32(c->pd.ntr, c->pd.tslot, c->vals_d32, c->lvals_d32, c->stream);
-  } else {
-    launch_mirror(c->ps.ntr, c->ps.tslot, c->vals_s, c->lvals_s, c->stream);
-    if (dyn) launch_mirror(c->pd.ntr, c->pd.tslot, c->vals_d, c->lvals_d, c->stream);
-  }
+  // both triangles, row by row, structure of arrays, for the SpMV
+  if (mixed)
+    launch_full_gather_f32(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s32, dyn ? c->vals_d32 : nullptr, c->f_vals32,
+                           c->stream);
+  else
+    launch_full_gather(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s, dyn ? c->vals_d : nullptr, c->f_vals, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)
@@ -737,6 +754,7 @@ yasps_status run_assemble(yasps_ctx* c) {
                          c->flags, c->stream);
   c->prof.end();
   HIPCHK(c, hipGetLastError());
+  c->assembled = true;
   return YASPS_OK;
 }
 
@@ -814,7 +832,7 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
                        yasps_pcg_info* info) {
   if (!c || !b || !x) return fail(c, YASPS_E_ARG, "NULL argument");
   if (!(rtol >= 0.0) || max_iter < 0) return fail(c, YASPS_E_ARG, "bad rtol / max_iter");
-  if (!c->evaluated) return fail(c, YASPS_E_ARG, "pcg called before assembly");
+  if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "pcg called before assembly");
   HIPCHK(c, hipSetDevice(c->device));
   double rel = 0.0;
   int status = 0;
@@ -959,7 +977,7 @@ yasps_status yasps_profile_query(yasps_ctx* c, int32_t cls, int32_t* launches, d
 
 yasps_status yasps_spmv(yasps_ctx* c, const double* x, double* y) {
   if (!c || !x || !y) return fail(c, YASPS_E_ARG, "NULL argument");
-  if (!c->evaluated) return fail(c, YASPS_E_ARG, "spmv called before assembly");
+  if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "spmv called before assembly");
   HIPCHK(c, hipSetDevice(c->device));
   c->prof.begin(YASPS_K_SPMV);
   launch_spmv(pcg_matrix(c), x, y, c->pcg_work, c->stream);

@@ -77,17 +77,22 @@ void launch_segsum(int nseg, const int32_t* p1, const T* s1, const int32_t* p2, 
   }
 }
 
-// lv[k] = transpose(v[tslot[k]]): one thread per value, contiguous writes,
-// reads gathered 72 bytes (36 in float32) at a time.
+// vf[q * nnz + k] = entry q of the source block of k (transposed when src < 0):
+// one thread per value, coalesced writes, reads gathered 72 (36) bytes at a time.
 template <class T>
-__global__ __launch_bounds__(RED_BLOCK) void mirror_kernel(long long nval, const int32_t* __restrict__ tslot,
-                                                           const T* __restrict__ v, T* __restrict__ lv) {
+__global__ __launch_bounds__(RED_BLOCK) void full_gather_kernel(long long nnz, const int32_t* __restrict__ src,
+                                                                int nnzb_s, const T* __restrict__ vs,
+                                                                const T* __restrict__ vd, T* __restrict__ vf) {
   const long long e = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (e >= nval) return;
-  const long long k = e / 9;
-  const int q = (int)(e - 9 * k);
-  const int i = q / 3, j = q - 3 * (q / 3);
-  lv[e] = v[9 * (size_t)tslot[k] + 3 * j + i];
+  if (e >= 9 * nnz) return;
+  const int q = (int)(e / nnz);
+  const long long k = e - (long long)q * nnz;
+  const int32_t sk = src[k];
+  const bool tr = sk < 0;
+  const int b = tr ? -sk - 1 : sk;
+  const int qq = tr ? 3 * (q % 3) + q / 3 : q;
+  const T* base = b < nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - nnzb_s);
+  vf[e] = base[qq];
 }
 
 template <class T>
@@ -216,18 +221,20 @@ void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const 
   launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s);
 }
 
-void launch_mirror(int ntr, const int32_t* tslot, const double* v, double* lv, hipStream_t s) {
-  if (ntr <= 0) return;
-  const long long nval = 9LL * ntr;
-  hipLaunchKernelGGL((mirror_kernel<double>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)), dim3(RED_BLOCK), 0,
-                     s, nval, tslot, v, lv);
+void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const double* vs, const double* vd,
+                        double* vf, hipStream_t s) {
+  if (nnz <= 0) return;
+  const long long nval = 9 * nnz;
+  hipLaunchKernelGGL((full_gather_kernel<double>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)),
+                     dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
 }
 
-void launch_mirror_f32(int ntr, const int32_t* tslot, const float* v, float* lv, hipStream_t s) {
-  if (ntr <= 0) return;
-  const long long nval = 9LL * ntr;
-  hipLaunchKernelGGL((mirror_kernel<float>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)), dim3(RED_BLOCK), 0,
-                     s, nval, tslot, v, lv);
+void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
+                            float* vf, hipStream_t s) {
+  if (nnz <= 0) return;
+  const long long nval = 9 * nnz;
+  hipLaunchKernelGGL((full_gather_kernel<float>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)),
+                     dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
 }
 
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s, const int32_t* ddiag,

@@ -132,10 +132,12 @@ void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cpt
                               float* out, hipStream_t s);
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
                         const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s);
-// Mirror of the upper off-diagonal blocks into lower-triangle row order:
-// lv[k] = transpose(v[tslot[k]]) for the ntr entries of the transpose index.
-void launch_mirror(int ntr, const int32_t* tslot, const double* v, double* lv, hipStream_t s);
-void launch_mirror_f32(int ntr, const int32_t* tslot, const float* v, float* lv, hipStream_t s);
+// Fills the SpMV matrix values vf[q * nnz + k] from the stored upper blocks
+// (src as in FullPattern: static blocks vs, then dynamic blocks vd).
+void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const double* vs, const double* vd,
+                        double* vf, hipStream_t s);
+void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
+                            float* vf, hipStream_t s);
 // Block-Jacobi inverse of static + dynamic diagonal blocks.
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
                           const int32_t* ddiag, const double* vals_d, double* inv,
@@ -160,15 +162,14 @@ void launch_dot(int n3, const double* a, const double* b, double* part, int nblk
 // PCG.
 struct PcgMatrix {
   int n;
-  // static part; lv_* = the off-diagonal blocks mirrored into lower-triangle row
-  // order (entry k of the transpose index holds the transpose of block tslot[k])
-  const int32_t* rp_s; const int32_t* ci_s; const double* v_s; const float* v_s32;
-  const int32_t* tp_s; const int32_t* tslot_s; const int32_t* trow_s;
-  const double* lv_s; const float* lv_s32;
-  // dynamic part
-  const int32_t* rp_d; const int32_t* ci_d; const double* v_d; const float* v_d32;
-  const int32_t* tp_d; const int32_t* tslot_d; const int32_t* trow_d;
-  const double* lv_d; const float* lv_d32;
+  // both triangles of H_static + H_dynamic, row by row (see FullPattern),
+  // block values as structure of arrays [9][nnz] (entry q of block k at
+  // v[q * nnz + k]), float64 or, in the precision form, float32
+  const int32_t* rp;
+  const int32_t* col;
+  const double* v;
+  const float* v32;
+  long long nnz;
   const double* minv;  // (n, 9)
 };
 struct PcgState;  // device-side scalars, defined in pcg.hip

@@ -120,4 +120,29 @@ void build_staging(int n, const int32_t* idx, int ns, const PartPattern& pat, co
   }
 }
 
+void build_full(int n, const PartPattern& stat, const PartPattern* dyn, FullPattern& out) {
+  out.row_ptr.assign(n + 1, 0);
+  out.col.clear();
+  out.src.clear();
+  const size_t total = 2 * (size_t)stat.nnzb + (dyn ? 2 * (size_t)dyn->nnzb : 0);
+  out.col.reserve(total);
+  out.src.reserve(total);
+  auto add_part = [&](const PartPattern& p, int r, int32_t base) {
+    if (p.row_ptr.empty()) return;
+    for (int k = p.row_ptr[r]; k < p.row_ptr[r + 1]; ++k) {
+      out.col.push_back(p.col_idx[k]);
+      out.src.push_back(base + k);
+    }
+    for (int j = p.tptr[r]; j < p.tptr[r + 1]; ++j) {
+      out.col.push_back(p.trow[j]);
+      out.src.push_back(-(base + p.tslot[j]) - 1);
+    }
+  };
+  for (int r = 0; r < n; ++r) {
+    add_part(stat, r, 0);
+    if (dyn) add_part(*dyn, r, stat.nnzb);
+    out.row_ptr[r + 1] = (int32_t)out.col.size();
+  }
+}
+
 }  // namespace yasps

@@ -52,4 +52,14 @@ void build_staging(int n_free, const int32_t* idx_soa, int ns, const PartPattern
 
 int used_vertices(const int32_t* idx_soa, int ns, int s);
 
+// Both triangles of H = H_static + H_dynamic, row by row, for the SpMV: row r
+// lists its static upper blocks, the static blocks whose column is r
+// (transposed), then the same for the dynamic part.  src[k] >= 0 names stored
+// block src[k] as is, src[k] < 0 names stored block -src[k] - 1 transposed;
+// stored blocks are numbered static first, then dynamic.
+struct FullPattern {
+  std::vector<int32_t> row_ptr, col, src;
+};
+void build_full(int n_free, const PartPattern& stat, const PartPattern* dyn, FullPattern& out);
+
 }  // namespace yasps

@@ -1,14 +1,15 @@
 // Block-Jacobi preconditioned conjugate gradient on the symmetric 3x3 BSR
 // Hessian (section "Solver", appendices "SpMV" and "Preconditioner").
 //
-// SpMV.  The Hessian is stored once, as its upper triangle (appendix "Global
-// Hessian Compression"); the paper's SpMV adds, for every off-diagonal block,
-// the transposed product with atomics (Algorithm "CUDA Block Level SpMV").
-// Here a group of G lanes owns one block row and gathers both its row blocks
-// (B x_col) and, through a precomputed transpose index, the blocks whose
-// column is this row (B^T x_row); the lanes' partial 3-vectors are combined by
-// a fixed butterfly.  No atomics, deterministic, and every block is read twice
-// (once per side), the same traffic as full symmetric storage without storing it.
+// SpMV.  The Hessian is assembled once, as its upper triangle (appendix
+// "Global Hessian Compression"); the paper's SpMV adds, for every off-diagonal
+// block, the transposed product with atomics (Algorithm "CUDA Block Level
+// SpMV").  Here, after each assembly, a gather pass writes both triangles of
+// H_static + H_dynamic row by row in structure-of-arrays form; a group of G
+// lanes owns one block row, the lanes read consecutive blocks (coalesced), and
+// their partial 3-vectors are combined by a fixed butterfly.  No atomics,
+// deterministic; every off-diagonal block is read twice per product (once per
+// side), as with full symmetric storage.
 //
 // Iteration.  PCG with one global reduction phase per iteration (the
 // Chronopoulos-Gear arrangement, equal to standard PCG in exact arithmetic):
@@ -59,53 +60,31 @@ YDEV double sum_partials(const double* __restrict__ part, int n, double* lds) {
   return block_sum<BLOCK>(acc, lds);
 }
 
+// (H x)_row for the row owned by this lane group: each lane takes every
+// SPMV_G-th block of the row (structure-of-arrays values, so the lanes of a
+// group read consecutive addresses); the sum is valid in every lane of the
+// group after the butterfly.
 template <class T, class X>
-YDEV void block_mv(const T* B, const X* x, double acc[3]) {
-  const double x0 = x[0], x1 = x[1], x2 = x[2];
-  acc[0] = fma(double(B[0]), x0, fma(double(B[1]), x1, fma(double(B[2]), x2, acc[0])));
-  acc[1] = fma(double(B[3]), x0, fma(double(B[4]), x1, fma(double(B[5]), x2, acc[1])));
-  acc[2] = fma(double(B[6]), x0, fma(double(B[7]), x1, fma(double(B[8]), x2, acc[2])));
-}
-template <class T, class X>
-YDEV void block_mtv(const T* B, const X* x, double acc[3]) {
-  const double x0 = x[0], x1 = x[1], x2 = x[2];
-  acc[0] = fma(double(B[0]), x0, fma(double(B[3]), x1, fma(double(B[6]), x2, acc[0])));
-  acc[1] = fma(double(B[1]), x0, fma(double(B[4]), x1, fma(double(B[7]), x2, acc[1])));
-  acc[2] = fma(double(B[2]), x0, fma(double(B[5]), x1, fma(double(B[8]), x2, acc[2])));
-}
-
-// One part's contribution to row `row`: its stored (upper) blocks, then the
-// blocks whose column is `row` -- read contiguously from the mirrored lower
-// copy `lv` when there is one, else gathered through the transpose index.
-template <class T, class X>
-YDEV void row_part(const int32_t* rp, const int32_t* ci, const T* v, const int32_t* tp, const int32_t* ts,
-                   const int32_t* tr, const T* lv, int row, int lane, const X* x, double acc[3]) {
-  for (int k = rp[row] + lane, e = rp[row + 1]; k < e; k += SPMV_G) block_mv(v + 9 * (size_t)k, x + 3 * (size_t)ci[k], acc);
-  if (lv) {
-    for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
-      block_mv(lv + 9 * (size_t)k, x + 3 * (size_t)tr[k], acc);
-  } else {
-    for (int k = tp[row] + lane, e = tp[row + 1]; k < e; k += SPMV_G)
-      block_mtv(v + 9 * (size_t)ts[k], x + 3 * (size_t)tr[k], acc);
+YDEV void row_blocks(const PcgMatrix& A, const T* __restrict__ v, int row, int lane, const X* x, double acc[3]) {
+  const size_t nnz = (size_t)A.nnz;
+  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
+    const X* xc = x + 3 * (size_t)A.col[k];
+    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
+    const T* b = v + k;
+    acc[0] = fma(double(b[0]), x0, fma(double(b[nnz]), x1, fma(double(b[2 * nnz]), x2, acc[0])));
+    acc[1] = fma(double(b[3 * nnz]), x0, fma(double(b[4 * nnz]), x1, fma(double(b[5 * nnz]), x2, acc[1])));
+    acc[2] = fma(double(b[6 * nnz]), x0, fma(double(b[7 * nnz]), x1, fma(double(b[8 * nnz]), x2, acc[2])));
   }
 }
 
-// (H x)_row for the row owned by this lane group; the sum is valid in every
-// lane of the group after the butterfly.
 template <class X>
 YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
   if (row < A.n) {
-    if (A.v_s32)
-      row_part(A.rp_s, A.ci_s, A.v_s32, A.tp_s, A.tslot_s, A.trow_s, A.lv_s32, row, lane, x, acc);
+    if (A.v32)
+      row_blocks(A, A.v32, row, lane, x, acc);
     else
-      row_part(A.rp_s, A.ci_s, A.v_s, A.tp_s, A.tslot_s, A.trow_s, A.lv_s, row, lane, x, acc);
-    if (A.rp_d) {
-      if (A.v_d32)
-        row_part(A.rp_d, A.ci_d, A.v_d32, A.tp_d, A.tslot_d, A.trow_d, A.lv_d32, row, lane, x, acc);
-      else
-        row_part(A.rp_d, A.ci_d, A.v_d, A.tp_d, A.tslot_d, A.trow_d, A.lv_d, row, lane, x, acc);
-    }
+      row_blocks(A, A.v, row, lane, x, acc);
   }
 #pragma unroll
   for (int m = SPMV_G / 2; m > 0; m >>= 1) {
