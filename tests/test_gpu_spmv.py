@@ -1,0 +1,65 @@
+"""The solver's matrix-vector product (yasps_spmv, the kernel PCG uses) against
+the oracle's assembled H on the same inputs: float64 and the precision form,
+static and dynamic parts, after the contact set is replaced, and after a
+rejected contact set (the product then covers the static part only)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import assemble as oasm
+from paper_2605_23088_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def xdev(x):
+    return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+
+
+def check_product(o, g, p, x, rtol):
+    ev = o.eval(p["x0"])
+    H = o.csr(o.assemble(ev))
+    g.eval(xdev(p["x0"]))
+    g.assemble(copy=False)
+    y = g.spmv(xdev(x)).cpu().numpy().ravel()
+    ref = H @ x.ravel()
+    # per-row scale: |H| |x| (the sum of absolute products of the row)
+    scale = abs(H) @ np.abs(x.ravel())
+    assert np.all(np.abs(y - ref) <= rtol * scale + 1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spmv_matches_oracle(precision):
+    from paper_2605_23088_amd.yasps import FP64, MIXED, Yasps
+    p = synth.small_block(seed=21, nx=7, ny=6, nz=5, n_pt=300, n_ee=250)
+    o = oasm.Oracle(p)
+    g = Yasps(p, precision=MIXED if precision == "mixed" else FP64)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((p["n_free"], 3))
+    # float64: products of float64 values; precision form: float32 values
+    check_product(o, g, p, x, 1e-13 if precision == "fp64" else 2e-7)
+    g.close()
+
+
+def test_spmv_after_contact_changes():
+    from paper_2605_23088_amd.yasps import E_ARG, Yasps, YaspsError
+    p = synth.small_block(seed=22, nx=6, ny=5, nz=4, n_pt=200, n_ee=200)
+    g = Yasps(p)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((p["n_free"], 3))
+    check_product(oasm.Oracle(p), g, p, x, 1e-13)
+    # a different contact set (every other stencil)
+    q = dict(p)
+    q["ctype"], q["cidx"] = p["ctype"][::2].copy(), p["cidx"][::2].copy()
+    g.set_contacts(q["ctype"], q["cidx"])
+    check_product(oasm.Oracle(q), g, q, x, 1e-13)
+    # a rejected contact set leaves no contacts: the product is the static part's
+    bad = p["cidx"].copy()
+    bad[0, 1] = bad[0, 2]
+    with pytest.raises(YaspsError) as e:
+        g.set_contacts(p["ctype"], bad)
+    assert e.value.status == E_ARG
+    r = dict(p)
+    r["ctype"], r["cidx"] = p["ctype"][:0], p["cidx"][:0]
+    check_product(oasm.Oracle(r), g, r, x, 1e-13)
+    g.close()
