@@ -621,13 +621,17 @@ def _proximity(layers, dhat, reach, cell, eps_cross=1e-3):
 
 def c3_cloth(seed=SEEDS["C3"], block=(50, 50, 20), a=0.02, sheet_cells=250, n_sheets=4,
              counts=(400_000, 400_000, 150_000, 50_000), E=1e5, nu=0.4, E_c=1e5, nu_c=0.3, rho=1000.0,
-             thickness=1e-3, k_b=0.055, h=1e-2, kappa=1e4, dhat=1e-3, reach=None, name="C3"):
+             thickness=1e-3, k_b=0.055, h=1e-2, kappa=1.0, dhat=1e-3, reach=None, name="C3"):
     """Heterogeneous workload: a Kuhn tet block (per-tet random rest shapes as in
     the 40^3 workload, top face flat) under `n_sheets` stacked cloth sheets
     (StVK membrane + dihedral bending, flat at rest), sheet k rotated by
     7.5 + 15k degrees about the vertical axis through (0.5, 0.5), heights given
     by nested gap fields z_k = z_top + sum_{j<=k} g_j with
     g_j = sqrt(10^(-5 + 2 w_j)), w_j = tri(4 (x cos b_j + y sin b_j)), b_j seeded.
+
+    kappa = 1 (not the two cubes' 1e4): with 1.6e-5 kg cloth vertices a barrier
+    stiffness of 1e4 makes block-Jacobi PCG need 1e4-1e5 iterations even on
+    small versions of this scene; at 1 it needs ~1e3.
 
     Contacts: a near-field hashed proximity search (window `reach`, default one
     sheet spacing) between every pair of layers, Voronoi-region classification
