@@ -125,8 +125,10 @@ def cpu_baseline(prob, frac=1.0):
     t0 = time.perf_counter()
     o = oasm.Oracle(q)
     t1 = time.perf_counter()
+    log(f"[bench] oracle set up in {t1 - t0:.1f} s; Newton step on {n_stencils(q)} stencils")
     _, info = onewton.newton_step(o, q["x0"], rtol=1e-8)
     t2 = time.perf_counter()
+    log(f"[bench] oracle Newton step {t2 - t1:.1f} s, {info['cg_iters']} PCG iterations")
     what = "the full workload" if frac >= 1.0 else f"a seeded {frac:g} fraction of every stencil class"
     return {"value": n_stencils(q) / (t2 - t1) / 1e6, "unit": "Mstencils/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
@@ -242,7 +244,7 @@ def main():
     cpu_frac = 1.0
     if args.workload == "cloth":
         prob = synth.c3_cloth()
-        cpu_frac = 0.125
+        cpu_frac = 1.0 / 32
         desc = ("heterogeneous scene: 50x50x20-cell tet block + four 250x250 cloth sheets (StVK membranes, "
                 "dihedral hinges), 1M PT/EE/PE/PP contacts 40/40/15/5 %")
     elif args.workload == "block80":

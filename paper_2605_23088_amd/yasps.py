@@ -235,7 +235,11 @@ class Yasps:
         t = torch.as_tensor(ctype, device=self.dev).contiguous()
         i = torch.as_tensor(np.ascontiguousarray(cidx.T), device=self.dev).contiguous()
         Cs = Contacts(int(ctype.shape[0]), _ptr(t), _ptr(i))
-        self._check(lib().yasps_set_contacts(self.ctx, C.byref(Cs)))
+        try:
+            self._check(lib().yasps_set_contacts(self.ctx, C.byref(Cs)))
+        except YaspsError:
+            self.nc = 0  # a rejected set leaves the context without contacts
+            raise
         self.nc = int(ctype.shape[0])
 
     def eval(self, x, exact=False, allow=()):

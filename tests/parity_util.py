@@ -3,6 +3,7 @@ from the oracle's local contributions, the elementwise bar, and the
 restriction of a large scene to the stencils around sampled vertices (so the
 oracle can check full-size GPU results row by row)."""
 import numpy as np
+import scipy.sparse as sp
 import torch
 
 from oracle import energy as en
@@ -93,3 +94,20 @@ def restrict(p, verts):
 def bsr_rows(rp, ci, vals, rows):
     """{row: (cols, blocks)} of an upper BSR part."""
     return {int(r): (ci[rp[r]:rp[r + 1]], vals[rp[r]:rp[r + 1]]) for r in rows}
+
+
+def gpu_csr(g, out):
+    """The GPU's assembled matrix (both parts, both triangles) as SciPy CSR in
+    float64 (float32 values convert exactly): each upper part B contributes
+    B + (off-diagonal blocks of B)^T."""
+    H = None
+    for part, key in ((0, "values_s"), (1, "values_d")):
+        rp, ci, _ = g.pattern(part)
+        if len(ci) == 0:
+            continue
+        vals = out[key].cpu().numpy().astype(np.float64)
+        off = (ci != np.repeat(np.arange(g.n), np.diff(rp)))[:, None, None]
+        shape = (3 * g.n, 3 * g.n)
+        M = sp.bsr_matrix((vals, ci, rp), shape=shape).tocsr() + sp.bsr_matrix((vals * off, ci, rp), shape=shape).T
+        H = M if H is None else H + M
+    return H.tocsr()

@@ -6,12 +6,11 @@ residual, descent, feasibility, the step bound); the precision form is
 compared with the float64 path on the 80x80x52 block."""
 import numpy as np
 import pytest
-import scipy.sparse as sp
 import torch
 
 from oracle import assemble as oasm
 from paper_2605_23088_amd import synth
-from parity_util import TOL, bsr_rows, restrict, scales, within
+from parity_util import TOL, bsr_rows, gpu_csr, restrict, scales, within
 
 pytestmark = pytest.mark.gpu
 N_SAMPLE = 64
@@ -65,24 +64,8 @@ def sampled_rows_parity(p, g, x, seed):
     return out, view
 
 
-def full_csr(g, out):
-    """The GPU's assembled matrix as SciPy CSR: each upper part B contributes
-    B + (off-diagonal blocks of B)^T."""
-    H = None
-    for part, key in ((0, "values_s"), (1, "values_d")):
-        rp, ci, _ = g.pattern(part)
-        if len(ci) == 0:
-            continue
-        vals = out[key].cpu().numpy().astype(np.float64)
-        off = (ci != np.repeat(np.arange(g.n), np.diff(rp)))[:, None, None]
-        shape = (3 * g.n, 3 * g.n)
-        M = sp.bsr_matrix((vals, ci, rp), shape=shape).tocsr() + sp.bsr_matrix((vals * off, ci, rp), shape=shape).T
-        H = M if H is None else H + M
-    return H.tocsr()
-
-
 def step_properties(p, g, out):
-    H = full_csr(g, out)
+    H = gpu_csr(g, out)
     b = -out["grad"].contiguous()
     xs, info = g.pcg(b, rtol=1e-8)
     assert info["status"] == 0
