@@ -16,14 +16,13 @@
 //   u = M^-1 r, w = H u, gamma = r.u, delta = u.w
 //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
 //   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
-// Two kernels per iteration: (B) w = H u and delta, and (C) the scalar
-// recurrences, vector updates, preconditioning, the next gamma and |r|^2 and
-// the convergence test.  Each kernel's workgroups publish partial sums; the
-// workgroup that arrives last (one ticket per workgroup) adds them in index
-// order and writes the scalars, so the next kernel reads a few scalars instead
-// of re-summing partials in every workgroup.  The sums have a fixed order, so
-// the results are bitwise reproducible.  The host only polls a flag every few
-// iterations.
+// Two kernels per iteration: (B) the convergence test and w = H u with the
+// delta partials, and (C) the scalar recurrences, vector updates,
+// preconditioning and the next gamma and |r|^2 partials.  Each kernel runs a
+// bounded grid (grid-stride loops) and every workgroup re-sums the previous
+// kernel's partials in the same fixed order, so there are no atomics and the
+// results are bitwise reproducible.  Convergence is tested on the device; the
+// host only polls a flag every few iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,71 +34,30 @@ namespace yasps {
 
 constexpr int SPMV_G = 8;                       // lanes per block row
 constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup and pass
-constexpr int MAX_WG_B = 2048;                  // workgroups of the SpMV kernel
-constexpr int MAX_WG_C = 2048;                  // workgroups of the update kernel
+constexpr int MAX_WG_B = 1024;                  // workgroups of the SpMV kernel
+constexpr int MAX_WG_C = 512;                   // workgroups of the update kernel
 constexpr int UPD_VERTS = 64;                   // vertices per update-kernel workgroup pass
 constexpr int UPD_BLOCK = 3 * UPD_VERTS;        // update kernel: one thread per vertex component
 
-// Device scalars.  gamma / alpha are double-buffered by iteration parity so a
-// kernel never reads a slot that its own last workgroup writes; `iter` counts
-// completed iterations (matrix-vector products).  The tickets count arrivals
-// of the SpMV (b) and update / init / replacement (c) workgroups and are reset
-// by the last arrival.
+// Device scalars.  gamma / alpha are double-buffered by iteration parity;
+// `iter` is written only by the update kernel and `iter_b` only by the SpMV
+// kernel, so no kernel reads a scalar that it also writes.
 struct PcgState {
   double gamma[2], alpha[2];
-  double delta, bb, rr, tol2;
-  int iter, done, status, max_iter;
+  double bb, rr, tol2;
+  int iter, iter_b, done, status, max_iter;
   int restart_at;  // iteration whose search direction restarts from u (beta = 0)
-  unsigned int ticket_b, ticket_c;
 };
 
 namespace {
 
-// Called by every thread after thread 0 stored this workgroup's partials:
-// true in the workgroup that arrives last, which then sees every partial.
-YDEV bool last_arrival(unsigned int* ticket, int* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();  // release: this workgroup's partials before its ticket
-    *flag = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *flag != 0;
-  if (last) __threadfence();  // acquire: the other workgroups' partials
-  return last;
-}
-
-// Sum of the n partials in a fixed order (strided per thread, then a fixed
-// tree), read through the device-coherent path.
-template <int BLOCK>
-YDEV double sum_partials(const double* part, int n, double* lds) {
+// Sum of n partials in a fixed order (strided per thread, then a fixed tree),
+// computed identically by every workgroup that needs it.
+template <int BLOCK = RED_BLOCK>
+YDEV double sum_partials(const double* __restrict__ part, int n, double* lds) {
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += BLOCK) acc += __hip_atomic_load(part + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int j = threadIdx.x; j < n; j += BLOCK) acc += part[j];
   return block_sum<BLOCK>(acc, lds);
-}
-
-// The last workgroup's bookkeeping of a gamma / |r|^2 reduction for iteration i:
-// store both, test convergence (and the iteration cap), reset the ticket.
-template <int BLOCK>
-YDEV void finish_gamma(PcgState* st, const double* part_c, int i, bool first_iteration, double* lds) {
-  const int nb = gridDim.x;
-  const double G = sum_partials<BLOCK>(part_c, nb, lds);
-  const double R = sum_partials<BLOCK>(part_c + nb, nb, lds);
-  if (threadIdx.x == 0) {
-    if (first_iteration) st->bb = R;
-    const double bb = first_iteration ? R : st->bb;
-    st->gamma[i & 1] = G;
-    st->rr = R;
-    st->iter = i;
-    if (R <= st->tol2 * bb) {
-      st->status = 0;
-      st->done = 1;
-    } else if (i >= st->max_iter) {
-      st->status = -5;
-      st->done = 1;
-    }
-    st->ticket_c = 0;
-  }
 }
 
 // (H x)_row for the row owned by this lane group: each lane takes every
@@ -177,18 +135,17 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
   }
   const double gs = block_sum<RED_BLOCK>(g, lds);
   const double rs = block_sum<RED_BLOCK>(rr, lds);
-  __shared__ int flag;
   if (threadIdx.x == 0) {
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
   }
-  if (last_arrival(&st->ticket_c, &flag)) finish_gamma<RED_BLOCK>(st, V.part_c, 0, true, lds);
 }
 
 // Residual replacement (precision form): r = b - H x evaluated with float64
-// vectors and accumulation, then u = M^-1 r, gamma and |r|^2 of the current
-// iteration (replacing what the float32 recurrence carried) and the
-// convergence test on this true residual.
+// vectors and accumulation, then u = M^-1 r and the gamma / |r|^2 partials,
+// replacing what the float32 recurrence carried.  Launched on the update
+// kernel's grid: its partials take the same [gamma | |r|^2] layout of gridDim.x
+// entries each that the next SpMV kernel sums.
 template <class VT>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
                                                                 const double* __restrict__ x, Vecs<VT> V,
@@ -218,21 +175,41 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   }
   const double gs = block_sum<RED_BLOCK>(g, lds);
   const double rs = block_sum<RED_BLOCK>(rr, lds);
-  __shared__ int flag;
   if (threadIdx.x == 0) {
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
   }
-  if (last_arrival(&st->ticket_c, &flag)) finish_gamma<RED_BLOCK>(st, V.part_c, st->iter, false, lds);
 }
 
-// Iteration i: w = H u and delta = u.w.  standalone: plain y = H x (no
-// solver bookkeeping).
+// Iteration i: convergence test on |r_i|, then w = H u with the u.w partials.
+// `nb_c` is the update kernel's grid (number of gamma / |r|^2 partials).
+// standalone: plain y = H x (no solver bookkeeping).
 template <class VT>
-__global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int standalone) {
+__global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
+                                                             int standalone) {
   __shared__ double lds[RED_BLOCK];
-  __shared__ int flag;
-  if (!standalone && st->done) return;
+  if (!standalone) {
+    if (st->done) return;
+    const int i = st->iter;
+    const double G = sum_partials(V.part_c, nb_c, lds);
+    const double R = sum_partials(V.part_c + nb_c, nb_c, lds);
+    const double bb = i == 0 ? R : st->bb;
+    const bool conv = R <= st->tol2 * bb;
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (first) {
+      st->gamma[i & 1] = G;
+      st->rr = R;
+      st->iter_b = i;
+      if (i == 0) st->bb = bb;
+    }
+    if (conv || i >= st->max_iter) {
+      if (first) {
+        st->status = conv ? 0 : -5;
+        st->done = 1;
+      }
+      return;
+    }
+  }
   const int lane = threadIdx.x % SPMV_G;
   double d = 0.0;
   for (int base = blockIdx.x * SPMV_ROWS; base < A.n; base += gridDim.x * SPMV_ROWS) {
@@ -248,68 +225,64 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
       }
     }
   }
-  if (standalone) return;
   const double ds = block_sum<RED_BLOCK>(d, lds);
   if (threadIdx.x == 0) V.part_b[blockIdx.x] = ds;
-  if (last_arrival(&st->ticket_b, &flag)) {
-    const double delta = sum_partials<RED_BLOCK>(V.part_b, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      st->delta = delta;
-      st->ticket_b = 0;
-    }
-  }
 }
 
-// Iteration i: scalar recurrences, vector updates, preconditioning, then
-// gamma / |r|^2 of iteration i + 1 and the convergence test (last workgroup).
-// One thread per vertex component (coalesced vector traffic, 3x the threads
-// of a per-vertex mapping); the three residual components of a vertex meet in
-// LDS for the 3x3 block-Jacobi product.
+// Iteration i: scalar recurrences, vector updates, preconditioning, and the
+// gamma / |r|^2 partials of iteration i + 1.  `nb_b` = SpMV grid.  One thread
+// per vertex component (coalesced vector traffic, 3x the threads of a
+// per-vertex mapping); the three residual components of a vertex meet in LDS
+// for the 3x3 block-Jacobi product.
 template <class VT>
 __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
-                                                               PcgState* st) {
+                                                               PcgState* st, int nb_b) {
   if (st->done) return;
   __shared__ double lds[UPD_BLOCK];
   __shared__ double rsh[UPD_BLOCK];
-  __shared__ int flag;
-  const int i = st->iter;
+  const int i = st->iter_b;
   const double gamma = st->gamma[i & 1];
-  const double delta = st->delta;
+  const double delta = sum_partials<UPD_BLOCK>(V.part_b, nb_b, lds);
   const bool restart = i == st->restart_at;
   const double beta = restart ? 0.0 : gamma / st->gamma[(i - 1) & 1];
   const double pAp = restart ? delta : delta - beta * gamma / st->alpha[(i - 1) & 1];
-  const bool broken = !(pAp > 0.0);  // identical in every workgroup
-  const double alpha = broken ? 0.0 : gamma / pAp;
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pAp > 0.0)) {
+    if (first) {
+      st->status = -6;
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = gamma / pAp;
   const int t = threadIdx.x;
   const int vl = t / 3, c = t - 3 * (t / 3);
   double g = 0.0, rr = 0.0;
-  if (!broken) {
-    for (int base = blockIdx.x * UPD_VERTS; base < A.n; base += gridDim.x * UPD_VERTS) {
-      const int v = base + vl;
-      const bool live = v < A.n;
-      const size_t k = 3 * (size_t)base + t;  // = 3 v + c
-      double r = 0.0;
-      if (live) {
-        const VT p = VT(fma(beta, double(V.p[k]), double(V.u[k])));
-        const VT sv = VT(fma(beta, double(V.s[k]), double(V.w[k])));
-        V.p[k] = p;
-        V.s[k] = sv;
-        x[k] = fma(alpha, double(p), x[k]);
-        const VT rc = VT(fma(-alpha, double(sv), double(V.r[k])));
-        V.r[k] = rc;
-        r = double(rc);
-      }
-      rsh[t] = r;
-      __syncthreads();
-      if (live) {
-        const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
-        const VT uc = VT(M[0] * rsh[3 * vl] + M[1] * rsh[3 * vl + 1] + M[2] * rsh[3 * vl + 2]);
-        V.u[k] = uc;
-        g = fma(r, double(uc), g);
-        rr = fma(r, r, rr);
-      }
-      __syncthreads();  // rsh is rewritten by the next pass
+  for (int base = blockIdx.x * UPD_VERTS; base < A.n; base += gridDim.x * UPD_VERTS) {
+    const int v = base + vl;
+    const bool live = v < A.n;
+    const size_t k = 3 * (size_t)base + t;  // = 3 v + c
+    double r = 0.0;
+    if (live) {
+      const VT p = VT(fma(beta, double(V.p[k]), double(V.u[k])));
+      const VT sv = VT(fma(beta, double(V.s[k]), double(V.w[k])));
+      V.p[k] = p;
+      V.s[k] = sv;
+      x[k] = fma(alpha, double(p), x[k]);
+      const VT rc = VT(fma(-alpha, double(sv), double(V.r[k])));
+      V.r[k] = rc;
+      r = double(rc);
     }
+    rsh[t] = r;
+    __syncthreads();
+    if (live) {
+      const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
+      const VT uc = VT(M[0] * rsh[3 * vl] + M[1] * rsh[3 * vl + 1] + M[2] * rsh[3 * vl + 2]);
+      V.u[k] = uc;
+      g = fma(r, double(uc), g);
+      rr = fma(r, r, rr);
+    }
+    __syncthreads();  // rsh is rewritten by the next pass
   }
   const double gs = block_sum<UPD_BLOCK>(g, lds);
   const double rs = block_sum<UPD_BLOCK>(rr, lds);
@@ -317,17 +290,9 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     V.part_c[blockIdx.x] = gs;
     V.part_c[gridDim.x + blockIdx.x] = rs;
   }
-  if (last_arrival(&st->ticket_c, &flag)) {
-    if (broken) {
-      if (threadIdx.x == 0) {
-        st->status = -6;
-        st->done = 1;
-        st->ticket_c = 0;
-      }
-    } else {
-      if (threadIdx.x == 0) st->alpha[i & 1] = alpha;
-      finish_gamma<UPD_BLOCK>(st, V.part_c, i + 1, false, lds);
-    }
+  if (first) {
+    st->alpha[i & 1] = alpha;
+    st->iter = i + 1;
   }
 }
 
@@ -364,7 +329,7 @@ void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hip
   carve(work, A.n, st, V);
   V.u = const_cast<double*>(x);
   V.w = y;
-  hipLaunchKernelGGL(pcg_spmv_kernel<double>, dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1);
+  hipLaunchKernelGGL(pcg_spmv_kernel<double>, dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
 }
 
 namespace {
@@ -392,7 +357,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   hipLaunchKernelGGL(pcg_init_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
   if (tm) tm->end();
   int batch = 8;
-  long long launched = 0;  // (SpMV, update) pairs issued (the replacement period counts these)
+  long long launched = 0;  // (SpMV, update) pairs issued = iteration index while not done
   PcgState hs{};
   int verified_at = -1;
   int restarts = 0;
@@ -400,10 +365,10 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   for (;;) {
     for (int k = 0; k < batch; ++k) {
       if (tm) tm->begin(5);
-      hipLaunchKernelGGL(pcg_spmv_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, V, st, 0);
+      hipLaunchKernelGGL(pcg_spmv_kernel<VT>, dim3(nb_b), dim3(RED_BLOCK), 0, s, A, V, st, nb_c, 0);
       if (tm) tm->end();
       if (tm) tm->begin(6);
-      hipLaunchKernelGGL(pcg_update_kernel<VT>, dim3(nb_c), dim3(UPD_BLOCK), 0, s, A, x, V, st);
+      hipLaunchKernelGGL(pcg_update_kernel<VT>, dim3(nb_c), dim3(UPD_BLOCK), 0, s, A, x, V, st, nb_b);
       if (tm) tm->end();
       ++launched;
       if (MIXED && launched % REPLACE_EVERY == 0) {
@@ -421,22 +386,22 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       PcgState fix = hs;
       fix.done = 0;
       fix.status = 0;
-      fix.restart_at = hs.iter;
-      fix.iter = hs.iter;
+      fix.restart_at = hs.iter_b;
+      fix.iter = hs.iter_b;
       if (hipMemcpyAsync(st, &fix, sizeof(fix), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
       hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
-      launched = hs.iter;
+      launched = hs.iter_b;
       batch = 8;
       continue;
     }
     if (hs.done) {
-      if (!MIXED || hs.status != 0 || verified_at == hs.iter) break;
+      if (!MIXED || hs.status != 0 || verified_at == hs.iter_b) break;
       // converged on the recurrence residual: confirm with a float64 true residual
-      verified_at = hs.iter;
+      verified_at = hs.iter_b;
       const int zero = 0;
       if (hipMemcpyAsync(&st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
       hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
-      launched = hs.iter;
+      launched = hs.iter_b;
       batch = 8;
       continue;
     }
@@ -444,7 +409,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   }
   *rel_out = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
   *status_out = hs.status;
-  return hs.iter;
+  return hs.iter_b;
 }
 
 }  // namespace
