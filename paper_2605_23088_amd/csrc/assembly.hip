@@ -78,21 +78,25 @@ void launch_segsum(int nseg, const int32_t* p1, const T* s1, const int32_t* p2, 
 }
 
 // vf[q * nnz + k] = entry q of the source block of k (transposed when src < 0):
-// one thread per value, coalesced writes, reads gathered 72 (36) bytes at a time.
+// one thread per block; each thread reads its source block's 72 (36) contiguous
+// bytes, and for every q the lanes write consecutive addresses.
 template <class T>
 __global__ __launch_bounds__(RED_BLOCK) void full_gather_kernel(long long nnz, const int32_t* __restrict__ src,
                                                                 int nnzb_s, const T* __restrict__ vs,
                                                                 const T* __restrict__ vd, T* __restrict__ vf) {
-  const long long e = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (e >= 9 * nnz) return;
-  const int q = (int)(e / nnz);
-  const long long k = e - (long long)q * nnz;
+  const long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (k >= nnz) return;
   const int32_t sk = src[k];
   const bool tr = sk < 0;
   const int b = tr ? -sk - 1 : sk;
-  const int qq = tr ? 3 * (q % 3) + q / 3 : q;
   const T* base = b < nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - nnzb_s);
-  vf[e] = base[qq];
+  T B[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) B[q] = base[q];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) vf[(size_t)(3 * i + j) * nnz + k] = tr ? B[3 * j + i] : B[3 * i + j];
 }
 
 template <class T>
@@ -224,16 +228,14 @@ void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const 
 void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const double* vs, const double* vd,
                         double* vf, hipStream_t s) {
   if (nnz <= 0) return;
-  const long long nval = 9 * nnz;
-  hipLaunchKernelGGL((full_gather_kernel<double>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)),
+  hipLaunchKernelGGL((full_gather_kernel<double>), dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)),
                      dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
 }
 
 void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
                             float* vf, hipStream_t s) {
   if (nnz <= 0) return;
-  const long long nval = 9 * nnz;
-  hipLaunchKernelGGL((full_gather_kernel<float>), dim3((unsigned)((nval + RED_BLOCK - 1) / RED_BLOCK)),
+  hipLaunchKernelGGL((full_gather_kernel<float>), dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)),
                      dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
 }
 
