@@ -32,11 +32,25 @@
 
 namespace yasps {
 
-constexpr int SPMV_G = 8;                       // lanes per block row
+// Launch shapes (compile-time; the defaults come from sweeps on the 40^3 and
+// 80x80x52 workloads).
+#ifndef YASPS_SPMV_G
+#define YASPS_SPMV_G 8
+#endif
+#ifndef YASPS_MAX_WG_B
+#define YASPS_MAX_WG_B 1024
+#endif
+#ifndef YASPS_MAX_WG_C
+#define YASPS_MAX_WG_C 512
+#endif
+#ifndef YASPS_UPD_VERTS
+#define YASPS_UPD_VERTS 64
+#endif
+constexpr int SPMV_G = YASPS_SPMV_G;            // lanes per block row
 constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup and pass
-constexpr int MAX_WG_B = 1024;                  // workgroups of the SpMV kernel
-constexpr int MAX_WG_C = 512;                   // workgroups of the update kernel
-constexpr int UPD_VERTS = 64;                   // vertices per update-kernel workgroup pass
+constexpr int MAX_WG_B = YASPS_MAX_WG_B;        // workgroups of the SpMV kernel
+constexpr int MAX_WG_C = YASPS_MAX_WG_C;        // workgroups of the update kernel
+constexpr int UPD_VERTS = YASPS_UPD_VERTS;      // vertices per update-kernel workgroup pass
 constexpr int UPD_BLOCK = 3 * UPD_VERTS;        // update kernel: one thread per vertex component
 
 // Device scalars.  gamma / alpha are double-buffered by iteration parity;
