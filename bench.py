@@ -156,7 +156,7 @@ def bench_static(args):
 
     log("[bench] generating the static workload")
     prob = synth.c5_static()
-    s = StaticEquilibrium(prob, gtol=1e-9)
+    s = StaticEquilibrium(prob, gtol=1e-9, verbose=True)
     theta = torch.as_tensor(prob["theta"], dtype=torch.float64, device="cuda")
     x0 = torch.as_tensor(prob["x0"], dtype=torch.float64, device="cuda").contiguous()
     xt = torch.as_tensor(prob["x_tgt"], dtype=torch.float64, device="cuda")

@@ -41,29 +41,23 @@ def converged(orc, x, p_dir=None, gtol=1e-9):
 
 
 TIE_RTOL = 1e-14  # energy changes this small (relative) are below what E resolves
-EXACT_SWITCH = 1e-3  # relative gradient below which steps use the exact Hessian
-
-
 def solve_equilibrium(orc, x0, max_newton=60, gtol=1e-9):
-    """Newton to the stop rule.  Projected steps first; once max_v |g_v| falls
-    below EXACT_SWITCH max_v m_v |g|, steps solve with the exact Hessian (the
-    matrix of the adjoint solve, which must be positive definite at x*),
-    because near the minimum the PSD projection still clamps modes of
-    indefinite element and contact Hessians and projected Newton then
-    converges only linearly.  An exact step whose PCG breaks down or whose line
-    search fails is replaced by a projected step.  Near the minimum the energy
-    change of a step falls below the rounding of E, so trials that change E by
-    at most TIE_RTOL |E| count as a decrease (feasibility is still enforced)."""
+    """Newton to the stop rule.  Every step first solves with the exact
+    Hessian (the matrix of the adjoint solve, positive definite at a strict
+    minimum) and falls back to the projected Hessian when that PCG breaks down
+    (the exact Hessian is indefinite there) or its direction is not one of
+    descent or finds no admissible step.  Projected Newton alone converges only
+    linearly wherever the projection clamps modes of indefinite element and
+    contact Hessians (ratio ~0.95 per step measured on the static block), the
+    exact steps converge quadratically once they apply.  Near the minimum the
+    energy change of a step falls below the rounding of E, so trials that
+    change E by at most TIE_RTOL |E| count as a decrease (feasibility is still
+    enforced)."""
     x = np.array(x0, dtype=np.float64)
-    scale = np.max(orc.mass) * np.linalg.norm(orc.gravity)
-    _, gmax = converged(orc, x, None, gtol)
+    gmax = np.inf
     for k in range(max_newton):
-        x1, info = None, None
-        if gmax <= EXACT_SWITCH * scale:
-            x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL, hess=1)
-            if info["cg_status"] != "ok" or info["alpha"] == 0.0:
-                x1 = None
-        if x1 is None:
+        x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL, hess=1)
+        if info["cg_status"] != "ok" or info["alpha"] == 0.0:
             x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL)
         ok, gmax = converged(orc, x1, info["p"], gtol)
         x = x1

@@ -42,6 +42,8 @@ def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
     rounding floor of E, where Armijo can no longer decide)."""
     alpha = initial_step(orc, x, p)
     gp = float(g.ravel() @ p.ravel())
+    if gp >= 0.0 and np.abs(p).max() > 0.0:
+        return 0.0, x, E0, 0  # not a descent direction (exact Hessian away from a minimum)
     s0 = np.sign(orc.sides(x))
     trials = 0
     for _ in range(max_halvings + 1):

@@ -2,12 +2,12 @@
 
 Forward: Newton steps of the library on the static problem
 E(x; theta) = sum_t Psi_t(x; theta_t) + sum_s kappa b(d_s) - sum_v m_v g . x_v
-until max_v |grad_v E| <= gtol * max_v m_v |g|: projected steps first, then,
-once the gradient is below ``EXACT_SWITCH`` of that scale, steps with the exact
-Hessian (projected Newton converges only linearly where the projection still
-clamps modes of indefinite local Hessians; the exact Hessian must be positive
-definite at x* for the adjoint solve anyway).  An exact step whose PCG breaks
-down or whose line search fails is replaced by a projected step.
+until max_v |grad_v E| <= gtol * max_v m_v |g|.  Every step first solves with
+the exact Hessian (positive definite at a strict minimum, and the adjoint
+solve's matrix anyway) and falls back to the projected Hessian when that PCG
+breaks down, its direction is not one of descent, or it finds no admissible
+step; projected Newton alone converges only linearly wherever the projection
+clamps modes of indefinite local Hessians.
 
 Backward (implicit differentiation of grad_x E(x*; theta) = 0): with the
 upstream gradient dL/dx*, solve H(x*) lambda = dL/dx* by the library's PCG on
@@ -29,9 +29,8 @@ class StaticEquilibrium:
     context whose per-tet parameters are rewritten in place for each theta."""
 
     TIE_RTOL = 1e-14
-    EXACT_SWITCH = 1e-3
 
-    def __init__(self, prob, device="cuda", gtol=1e-10, max_newton=60, rtol=1e-12):
+    def __init__(self, prob, device="cuda", gtol=1e-10, max_newton=60, rtol=1e-12, verbose=False):
         if "mu_t" not in prob:
             raise ValueError("the problem needs per-tet Lame parameters")
         self.prob = prob
@@ -44,6 +43,8 @@ class StaticEquilibrium:
         m = np.asarray(prob["mass"])
         self.gscale = float(m.max() * np.linalg.norm(prob["gravity"]))
         self.newton_iters = 0
+        self.exact_steps = 0
+        self.verbose = verbose
 
     def set_theta(self, theta):
         ml = self.lib._ml  # [2][n_t] device array read by every evaluation
@@ -51,31 +52,36 @@ class StaticEquilibrium:
         ml[1].copy_(theta * self.lam1)
 
     def _step(self, x, hessian):
-        return self.lib.newton_step(x, rtol=self.rtol, max_iter=100000, tie_rtol=self.TIE_RTOL, hessian=hessian)
+        # an exact-Hessian attempt away from the minimum may never converge: bound it
+        cap = 20000 if hessian == EXACT else 100000
+        return self.lib.newton_step(x, rtol=self.rtol, max_iter=cap, tie_rtol=self.TIE_RTOL, hessian=hessian)
 
     def solve(self, x0):
         x = x0.detach().clone().contiguous()
-        gmax = np.inf
+        xk = torch.empty_like(x)
+        self.exact_steps = 0
         for k in range(self.max_newton):
-            info = None
-            if gmax <= self.EXACT_SWITCH * self.gscale:
-                xk = x.clone()
-                try:
-                    info = self._step(x, EXACT)
-                    if info["alpha"] == 0.0:
-                        info = None
-                except YaspsError as e:
-                    if e.status not in (E_BREAKDOWN, E_LINESEARCH):
-                        raise
-                if info is None:
-                    x.copy_(xk)
+            info, kind = None, "exact"
+            xk.copy_(x)
+            try:
+                info = self._step(x, EXACT)
+                if info["alpha"] == 0.0:
+                    info = None
+                else:
+                    self.exact_steps += 1
+            except YaspsError as e:
+                if e.status not in (E_BREAKDOWN, E_LINESEARCH):
+                    raise
             if info is None:
-                info = self._step(x, PROJECTED)
+                x.copy_(xk)
+                info, kind = self._step(x, PROJECTED), "projected"
             self.newton_iters = k + 1
+            if self.verbose:
+                print(f"[equilibrium] step {k}: {kind}, max|g| {info['grad_max']:.3e}, alpha {info['alpha']:.3g}, "
+                      f"{info['cg_iters']} PCG iterations", flush=True)
             # grad_max is the gradient at the start of the step
             if info["grad_max"] <= self.gtol * self.gscale:
                 return x
-            gmax = info["grad_max"]
         raise YaspsError(-5, f"static equilibrium not reached in {self.max_newton} Newton steps "
                              f"(max |g| = {info['grad_max']:.3e})")
 

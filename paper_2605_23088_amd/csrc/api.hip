@@ -905,6 +905,12 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   const double gp = c->host_scal[1];
   ni.grad_max = c->host_scal[2];
   ni.grad_dot_p = gp;
+  if (!(gp < 0.0) && pmax > 0.0) {
+    // possible with the exact Hessian away from a minimum: not a descent direction
+    ni.e1 = ei.energy;
+    if (info) *info = ni;
+    return fail(c, YASPS_E_LINESEARCH, "the Newton direction is not a descent direction (g.p >= 0)");
+  }
   double alpha = 1.0;
   if (c->nc > 0 && pmax > 0.0) alpha = std::min(1.0, 0.4 * std::sqrt(ei.min_d) / pmax);
   ni.alpha0 = alpha;

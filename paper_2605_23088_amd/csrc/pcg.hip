@@ -91,6 +91,26 @@ YDEV void row_blocks(const PcgMatrix& A, const T* __restrict__ v, int row, int l
   }
 }
 
+// The block rows of the SpMV-shaped kernels are split into NXCD contiguous
+// ranges, one per XCD: workgroups are dispatched to the XCDs round robin by
+// index, so workgroup b runs on XCD b % NXCD and makes passes over that XCD's
+// range.  The column gathers of one XCD then stay near its own rows (mesh
+// locality) and in its own L2.  These kernels' grids are multiples of NXCD.
+constexpr int NXCD = 8;
+static_assert(MAX_WG_B % NXCD == 0 && MAX_WG_C % NXCD == 0, "partial-sum arrays hold the rounded grids");
+struct RowRange {
+  int end, first, stride;
+};
+YDEV RowRange xcd_rows(int n) {
+  const int xcd = blockIdx.x % NXCD, j = blockIdx.x / NXCD, per = gridDim.x / NXCD;
+  RowRange r;
+  const int begin = (int)((long long)n * xcd / NXCD);
+  r.end = (int)((long long)n * (xcd + 1) / NXCD);
+  r.first = begin + j * SPMV_ROWS;
+  r.stride = per * SPMV_ROWS;
+  return r;
+}
+
 template <class X>
 YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
@@ -168,11 +188,13 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   __shared__ double lds[RED_BLOCK];
   const int lane = threadIdx.x % SPMV_G;
   double g = 0.0, rr = 0.0;
-  for (int base = blockIdx.x * SPMV_ROWS; base < A.n; base += gridDim.x * SPMV_ROWS) {
+  const RowRange R = xcd_rows(A.n);
+  for (int base = R.first; base < R.end; base += R.stride) {
     const int row = base + threadIdx.x / SPMV_G;
+    const bool live = row < R.end;
     double acc[3];
-    spmv_row(A, row, lane, x, acc);
-    if (lane == 0 && row < A.n) {
+    spmv_row(A, live ? row : A.n, lane, x, acc);
+    if (lane == 0 && live) {
       double r[3], u[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)row + c] - acc[c];
@@ -226,11 +248,13 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
   }
   const int lane = threadIdx.x % SPMV_G;
   double d = 0.0;
-  for (int base = blockIdx.x * SPMV_ROWS; base < A.n; base += gridDim.x * SPMV_ROWS) {
+  const RowRange R = xcd_rows(A.n);
+  for (int base = R.first; base < R.end; base += R.stride) {
     const int row = base + threadIdx.x / SPMV_G;
+    const bool live = row < R.end;
     double acc[3];
-    spmv_row(A, row, lane, V.u, acc);
-    if (lane == 0 && row < A.n) {
+    spmv_row(A, live ? row : A.n, lane, V.u, acc);
+    if (lane == 0 && live) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const VT wc = VT(acc[c]);
@@ -310,8 +334,11 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
   }
 }
 
-int grid_b(int n) { return std::max(1, std::min((n + SPMV_ROWS - 1) / SPMV_ROWS, MAX_WG_B)); }
-int grid_c(int n) { return std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C)); }
+// Grids are multiples of NXCD (the SpMV-shaped kernels split rows per XCD; the
+// replacement kernel runs on the update kernel's grid).
+int round_xcd(int g) { return (g + NXCD - 1) / NXCD * NXCD; }
+int grid_b(int n) { return round_xcd(std::max(1, std::min((n + SPMV_ROWS - 1) / SPMV_ROWS, MAX_WG_B))); }
+int grid_c(int n) { return round_xcd(std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C))); }
 
 template <class VT>
 void carve(void* work, int n, PcgState*& st, Vecs<VT>& V) {
