@@ -17,6 +17,8 @@ by ``yasps_theta_adjoint``.  Every step runs in the library's kernels.
 """
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 import torch
 
@@ -78,7 +80,7 @@ class StaticEquilibrium:
             self.newton_iters = k + 1
             if self.verbose:
                 print(f"[equilibrium] step {k}: {kind}, max|g| {info['grad_max']:.3e}, alpha {info['alpha']:.3g}, "
-                      f"{info['cg_iters']} PCG iterations", flush=True)
+                      f"{info['cg_iters']} PCG iterations", file=sys.stderr, flush=True)
             # grad_max is the gradient at the start of the step
             if info["grad_max"] <= self.gtol * self.gscale:
                 return x
