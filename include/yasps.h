@@ -170,6 +170,9 @@ typedef struct {
   int32_t hessian;      /* YASPS_PROJECTED (default, 0): projected Newton; YASPS_EXACT: solve with the
                            unprojected Hessian (near a minimum where it is positive definite; returns
                            YASPS_E_BREAKDOWN when PCG meets p^T H p <= 0) */
+  double shift;         /* >= 0: the solve uses H + shift diag(m_v I) (Levenberg-Marquardt damping with
+                           the lumped masses; the assembled BSR holds the shifted matrix until the next
+                           assembly); the line search still uses E itself.  0 = plain Newton */
 } yasps_newton_params;
 
 typedef struct {

@@ -41,28 +41,43 @@ def converged(orc, x, p_dir=None, gtol=1e-9):
 
 
 TIE_RTOL = 1e-14  # energy changes this small (relative) are below what E resolves
+def shift_scale(orc, x):
+    """1 % of the median ratio of the Hessian's diagonal (trace / 3 per vertex)
+    to the vertex mass: the first Levenberg-Marquardt shift."""
+    asm = orc.assemble(orc.eval(x, oasm.EXACT))
+    tr = np.abs(np.trace(orc.diag_blocks(asm), axis1=1, axis2=2)) / 3.0
+    return 1e-2 * float(np.median(tr / np.asarray(orc.mass)))
+
+
 def solve_equilibrium(orc, x0, max_newton=60, gtol=1e-9):
-    """Newton to the stop rule.  Every step first solves with the exact
-    Hessian (the matrix of the adjoint solve, positive definite at a strict
-    minimum) and falls back to the projected Hessian when that PCG breaks down
-    (the exact Hessian is indefinite there) or its direction is not one of
-    descent or finds no admissible step.  Projected Newton alone converges only
-    linearly wherever the projection clamps modes of indefinite element and
-    contact Hessians (ratio ~0.95 per step measured on the static block), the
-    exact steps converge quadratically once they apply.  Near the minimum the
-    energy change of a step falls below the rounding of E, so trials that
-    change E by at most TIE_RTOL |E| count as a decrease (feasibility is still
-    enforced)."""
+    """Damped exact Newton to the stop rule: each step solves
+    (H_exact + mu M) p = -g (Levenberg-Marquardt with the lumped masses) and
+    line-searches E; a step whose PCG breaks down, whose direction is not one
+    of descent or whose line search fails is retried with a larger mu (x
+    unchanged), and mu shrinks by 4 after full steps (to 0 once below 1e-6 of
+    its first value), so the iteration becomes plain exact Newton near the
+    minimum, where the exact Hessian (the adjoint solve's matrix) is positive
+    definite.  Projected Newton alone converges only linearly wherever the
+    projection clamps modes of indefinite element and contact Hessians.  Near
+    the minimum the energy change of a step falls below the rounding of E, so
+    trials that change E by at most TIE_RTOL |E| count as a decrease
+    (feasibility is still enforced)."""
     x = np.array(x0, dtype=np.float64)
     gmax = np.inf
+    mu, mu0 = 0.0, None
     for k in range(max_newton):
-        x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL, hess=1)
+        x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL, hess=1, shift=mu)
         if info["cg_status"] != "ok" or info["alpha"] == 0.0:
-            x1, info = onewton.newton_step(orc, x, rtol=1e-12, max_iter=50000, tie_rtol=TIE_RTOL)
+            if mu0 is None:
+                mu0 = shift_scale(orc, x)
+            mu = mu0 if mu == 0.0 else 4.0 * mu
+            continue
         ok, gmax = converged(orc, x1, info["p"], gtol)
         x = x1
         if ok:
             return x, k + 1
+        if info["alpha"] == 1.0 and mu > 0.0:
+            mu = 0.0 if mu / 4.0 < 1e-6 * mu0 else mu / 4.0
     raise RuntimeError(f"equilibrium not reached (|g|_inf = {gmax:.3e})")
 
 

@@ -14,15 +14,23 @@ stencil set:
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 from . import pcg as pcgmod
 
 
-def solve_direction(orc, x, rtol=1e-8, max_iter=20000, hess=0):
+def solve_direction(orc, x, rtol=1e-8, max_iter=20000, hess=0, shift=0.0):
+    """p = -(H + shift M)^-1 g by block-Jacobi PCG (shift: Levenberg-Marquardt
+    damping with the lumped masses M; 0 for plain Newton)."""
     ev = orc.eval(x, hess)
     asm = orc.assemble(ev)
     H = orc.csr(asm)
-    Minv = pcgmod.block_inverse(orc.diag_blocks(asm))
+    D = orc.diag_blocks(asm)
+    if shift:
+        m3 = np.repeat(shift * np.asarray(orc.mass), 3)
+        H = (H + sp.diags(m3)).tocsr()
+        D = D + (shift * np.asarray(orc.mass))[:, None, None] * np.eye(3)[None]
+    Minv = pcgmod.block_inverse(D)
     g = asm["grad"].ravel()
     p, it, rel, status = pcgmod.pcg(lambda v: H @ v, -g, Minv, rtol, max_iter)
     return ev, asm, H, p.reshape(-1, 3), it, rel, status
@@ -62,11 +70,12 @@ def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
     return 0.0, x, E0, trials
 
 
-def newton_step(orc, x, rtol=1e-8, max_iter=20000, tie_rtol=0.0, hess=0):
+def newton_step(orc, x, rtol=1e-8, max_iter=20000, tie_rtol=0.0, hess=0, shift=0.0):
     """hess=1 (EXACT) solves with the unprojected Hessian; the caller checks
-    ``cg_status`` ('breakdown' when that matrix is not positive definite)."""
+    ``cg_status`` ('breakdown' when that matrix is not positive definite).
+    shift: Levenberg-Marquardt damping (H + shift M) of the solve only."""
     x = np.asarray(x, np.float64).reshape(orc.n, 3)
-    ev, asm, H, p, it, rel, status = solve_direction(orc, x, rtol, max_iter, hess)
+    ev, asm, H, p, it, rel, status = solve_direction(orc, x, rtol, max_iter, hess, shift)
     if status == "breakdown":
         return x, dict(E0=ev["E"], E1=ev["E"], alpha=0.0, cg_iters=it, cg_rel=rel, cg_status=status,
                        ls_trials=0, p=p, grad=asm["grad"])

@@ -1,13 +1,14 @@
 """Differentiable static equilibrium: x*(theta) for per-tet Young's moduli theta.
 
-Forward: Newton steps of the library on the static problem
+Forward: damped exact Newton steps of the library on the static problem
 E(x; theta) = sum_t Psi_t(x; theta_t) + sum_s kappa b(d_s) - sum_v m_v g . x_v
-until max_v |grad_v E| <= gtol * max_v m_v |g|.  Every step first solves with
-the exact Hessian (positive definite at a strict minimum, and the adjoint
-solve's matrix anyway) and falls back to the projected Hessian when that PCG
-breaks down, its direction is not one of descent, or it finds no admissible
-step; projected Newton alone converges only linearly wherever the projection
-clamps modes of indefinite local Hessians.
+until max_v |grad_v E| <= gtol * max_v m_v |g|: each step solves
+(H_exact + mu M) p = -g (Levenberg-Marquardt with the lumped masses) and
+line-searches E; mu grows when a step fails (indefinite H_exact away from the
+minimum) and vanishes near it, where the iteration is plain exact Newton
+(quadratic).  Projected Newton alone converges only linearly wherever the
+projection clamps modes of indefinite local Hessians, and on the 48x48x29
+static block it stalls.
 
 Backward (implicit differentiation of grad_x E(x*; theta) = 0): with the
 upstream gradient dL/dx*, solve H(x*) lambda = dL/dx* by the library's PCG on
@@ -53,37 +54,61 @@ class StaticEquilibrium:
         ml[0].copy_(theta * self.mu1)
         ml[1].copy_(theta * self.lam1)
 
-    def _step(self, x, hessian):
+    def _step(self, x, hessian, shift=0.0):
         # an exact-Hessian attempt away from the minimum may never converge: bound it
         cap = 20000 if hessian == EXACT else 100000
-        return self.lib.newton_step(x, rtol=self.rtol, max_iter=cap, tie_rtol=self.TIE_RTOL, hessian=hessian)
+        return self.lib.newton_step(x, rtol=self.rtol, max_iter=cap, tie_rtol=self.TIE_RTOL, hessian=hessian,
+                                    shift=shift)
+
+    def _shift_scale(self):
+        """A Levenberg-Marquardt shift of ~1 % of the typical diagonal of the
+        last assembled Hessian, in units of the mass (the shift multiplies m_v)."""
+        out = self.lib.assemble()
+        rp = out["row_ptr_s"].cpu().numpy()
+        diag = out["values_s"][torch.as_tensor(rp[:-1], device=out["values_s"].device)]
+        tr = torch.diagonal(diag, dim1=1, dim2=2).sum(dim=1).abs().cpu().numpy() / 3.0
+        m = np.asarray(self.prob["mass"])
+        return 1e-2 * float(np.median(tr / m))
 
     def solve(self, x0):
+        """Damped exact Newton: each step solves (H_exact + mu M) p = -g and
+        takes the line search on E.  mu starts at 0; a step whose PCG breaks
+        down, whose direction is not one of descent, or whose line search fails
+        is retried with a larger mu (x unchanged), and mu shrinks after full
+        steps, so the iteration becomes plain exact Newton near the minimum."""
         x = x0.detach().clone().contiguous()
         xk = torch.empty_like(x)
         self.exact_steps = 0
+        mu, mu0 = 0.0, None
+        info = {"grad_max": float("inf")}
         for k in range(self.max_newton):
-            info, kind = None, "exact"
             xk.copy_(x)
+            ok = True
             try:
-                info = self._step(x, EXACT)
-                if info["alpha"] == 0.0:
-                    info = None
-                else:
-                    self.exact_steps += 1
+                info = self._step(x, EXACT, mu)
+                ok = info["alpha"] > 0.0
             except YaspsError as e:
                 if e.status not in (E_BREAKDOWN, E_LINESEARCH):
                     raise
-            if info is None:
-                x.copy_(xk)
-                info, kind = self._step(x, PROJECTED), "projected"
+                ok = False
             self.newton_iters = k + 1
+            if not ok:
+                x.copy_(xk)
+                if mu0 is None:
+                    mu0 = self._shift_scale()
+                mu = mu0 if mu == 0.0 else 4.0 * mu
+                if self.verbose:
+                    print(f"[equilibrium] step {k}: rejected, shift -> {mu:.3e}", file=sys.stderr, flush=True)
+                continue
+            self.exact_steps += 1
             if self.verbose:
-                print(f"[equilibrium] step {k}: {kind}, max|g| {info['grad_max']:.3e}, alpha {info['alpha']:.3g}, "
-                      f"{info['cg_iters']} PCG iterations", file=sys.stderr, flush=True)
+                print(f"[equilibrium] step {k}: shift {mu:.3e}, max|g| {info['grad_max']:.3e}, "
+                      f"alpha {info['alpha']:.3g}, {info['cg_iters']} PCG iterations", file=sys.stderr, flush=True)
             # grad_max is the gradient at the start of the step
             if info["grad_max"] <= self.gtol * self.gscale:
                 return x
+            if info["alpha"] == 1.0 and mu > 0.0:
+                mu = 0.0 if mu0 is not None and mu / 4.0 < 1e-6 * mu0 else mu / 4.0
         raise YaspsError(-5, f"static equilibrium not reached in {self.max_newton} Newton steps "
                              f"(max |g| = {info['grad_max']:.3e})")
 

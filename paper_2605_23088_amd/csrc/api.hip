@@ -720,7 +720,8 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
   return check_flags(c, f);
 }
 
-yasps_status run_assemble(yasps_ctx* c) {
+// shift > 0 adds shift m_v I to the diagonal blocks (Newton steps with damping).
+yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   if (!c->f_rp) {
     const yasps_status s = build_full_matrix(c);
     if (s) return s;
@@ -738,6 +739,7 @@ yasps_status run_assemble(yasps_ctx* c) {
   }
   launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
                      dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
+  launch_add_mass_shift(c->n, c->ps.rp, c->P.mass, shift, c->vals_s, mixed ? c->vals_s32 : nullptr, c->stream);
   // both triangles, row by row, structure of arrays, for the SpMV
   if (mixed)
     launch_full_gather_f32(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s32, dyn ? c->vals_d32 : nullptr, c->f_vals32,
@@ -854,8 +856,9 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
 
 yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_params* prm, yasps_newton_info* info) {
   if (!c || !x) return fail(c, YASPS_E_ARG, "NULL argument");
-  yasps_newton_params p{1e-8, 20000, 40, 1e-4, 0.0, YASPS_PROJECTED};
+  yasps_newton_params p{1e-8, 20000, 40, 1e-4, 0.0, YASPS_PROJECTED, 0.0};
   if (prm) p = *prm;
+  if (!(p.shift >= 0.0)) return fail(c, YASPS_E_ARG, "shift must be >= 0");
   if (p.hessian != YASPS_PROJECTED && p.hessian != YASPS_EXACT) return fail(c, YASPS_E_ARG, "unknown hessian mode");
   HIPCHK(c, hipSetDevice(c->device));
   hipEvent_t ev[5];
@@ -872,7 +875,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   yasps_status s = run_eval(c, x, p.hessian, &ei);
   if (s) return s;
   HIPCHK(c, hipEventRecord(ev[1], c->stream));
-  s = run_assemble(c);
+  s = run_assemble(c, p.shift);
   if (s) return s;
   HIPCHK(c, hipEventRecord(ev[2], c->stream));
   launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);

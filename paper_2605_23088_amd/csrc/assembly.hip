@@ -100,6 +100,19 @@ __global__ __launch_bounds__(RED_BLOCK) void full_gather_kernel(long long nnz, c
 }
 
 template <class T>
+__global__ __launch_bounds__(RED_BLOCK) void mass_shift_kernel(int n, const int32_t* __restrict__ rp,
+                                                               const double* __restrict__ mass, double shift,
+                                                               T* __restrict__ vals) {
+  const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (v >= n) return;
+  T* B = vals + 9 * (size_t)rp[v];
+  const T d = T(shift * mass[v]);
+  B[0] += d;
+  B[4] += d;
+  B[8] += d;
+}
+
+template <class T>
 __global__ __launch_bounds__(RED_BLOCK) void block_inverse_kernel(int n, const int32_t* __restrict__ rp_s,
                                                                   const T* __restrict__ vs,
                                                                   const int32_t* __restrict__ ddiag,
@@ -237,6 +250,16 @@ void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const
   if (nnz <= 0) return;
   hipLaunchKernelGGL((full_gather_kernel<float>), dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)),
                      dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
+}
+
+void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
+                           float* vals_s32, hipStream_t s) {
+  if (n == 0 || shift == 0.0) return;
+  const dim3 grid((n + RED_BLOCK - 1) / RED_BLOCK);
+  if (vals_s32)
+    hipLaunchKernelGGL((mass_shift_kernel<float>), grid, dim3(RED_BLOCK), 0, s, n, row_ptr_s, mass, shift, vals_s32);
+  else
+    hipLaunchKernelGGL((mass_shift_kernel<double>), grid, dim3(RED_BLOCK), 0, s, n, row_ptr_s, mass, shift, vals_s);
 }
 
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s, const int32_t* ddiag,

@@ -138,6 +138,9 @@ void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const dou
                         double* vf, hipStream_t s);
 void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
                             float* vf, hipStream_t s);
+// vals_s[row_ptr_s[v]] += shift m_v I (the diagonal block is first in its static row).
+void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
+                           float* vals_s32, hipStream_t s);
 // Block-Jacobi inverse of static + dynamic diagonal blocks.
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
                           const int32_t* ddiag, const double* vals_d, double* inv,

@@ -70,7 +70,7 @@ class PcgInfo(C.Structure):
 
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("max_halvings", C.c_int32), ("armijo", C.c_double),
-                ("tie_rtol", C.c_double), ("hessian", C.c_int32)]
+                ("tie_rtol", C.c_double), ("hessian", C.c_int32), ("shift", C.c_double)]
 
 
 class NewtonInfo(C.Structure):
@@ -293,8 +293,8 @@ class Yasps:
         return x, dict(iters=info.iters, rel_residual=info.rel_residual, status=info.status, rc=rc)
 
     def newton_step(self, x, rtol=1e-8, max_iter=20000, max_halvings=40, armijo=1e-4, tie_rtol=0.0,
-                    hessian=PROJECTED, allow=(E_NOCONV,)):
-        prm = NewtonParams(rtol, max_iter, max_halvings, armijo, tie_rtol, hessian)
+                    hessian=PROJECTED, shift=0.0, allow=(E_NOCONV,)):
+        prm = NewtonParams(rtol, max_iter, max_halvings, armijo, tie_rtol, hessian, shift)
         info = NewtonInfo()
         rc = self._check(lib().yasps_newton_step(self.ctx, _ptr(x), C.byref(prm), C.byref(info)), allow)
         out = {k: getattr(info, k) for k, _ in NewtonInfo._fields_}
