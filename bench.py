@@ -142,6 +142,36 @@ def cpu_baseline(prob, frac=1.0, solve=True):
             "sample": f"{part}: {what}; {t2 - t1:.2f} s, pattern set-up {t1 - t0:.2f} s excluded"}
 
 
+def kernel_table(stats, model, steps, cg_work, workload, precision):
+    """Per-kernel-class launches, average device time and roofline position
+    from the profiler's statistics over `steps` profiled steps that ran
+    `cg_work` PCG iterations in all; the roofline entry is the class with the
+    largest time that has a work model."""
+    kernels = {}
+    for name, st in stats.items():
+        if not st["launches"]:
+            continue
+        avg_ms = st["total_ms"] / st["launches"]
+        if name in ("pcg_spmv", "pcg_update") and cg_work > 0:
+            avg_ms = st["total_ms"] / cg_work
+        k = {"launches_per_step": st["launches"] / steps, "avg_ms": avg_ms, "ms_per_step": st["total_ms"] / steps}
+        if name in model:
+            bound, work, unit = model[name]
+            rate = work / (avg_ms * 1e-3)
+            if bound == "hbm":
+                k.update(bound="hbm", achieved=rate / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=rate / 1e9 / HBM_PEAK_GBS, algorithmic_bytes=work)
+            else:
+                k.update(bound="alu", achieved=rate / 1e12, peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s",
+                         frac=rate / 1e12 / FP64_VECTOR_TFLOPS, algorithmic_flops=work)
+        kernels[name] = k
+    dom = max((n for n in kernels if "bound" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
+    d = kernels[dom]
+    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                "unit": d["unit"], "frac": d["frac"], "traffic": measured_traffic(dom, workload, precision)}
+    return kernels, roofline
+
+
 def bench_static(args):
     """Differentiation form on the 48x48x29-cell static block (400,896 tets,
     4 corners fixed, per-tet Young's moduli, 300k PT stencils): the forward
@@ -298,34 +328,12 @@ def main():
             x.copy_(x0)
             pinfos.append(g.newton_step(x))
         stats = g.profile_stats()
+        g.profile(False)
         # PCG launches that do work: one SpMV and one update per iteration (the
         # last polling batch also issues launches that exit at once)
-        cg_work = float(np.mean([i["cg_iters"] for i in pinfos]))
-        g.profile(False)
-        model = algorithmic(prob, g, view)
-        for name, st in stats.items():
-            if not st["launches"]:
-                continue
-            avg_ms = st["total_ms"] / st["launches"]
-            if name in ("pcg_spmv", "pcg_update"):
-                avg_ms = st["total_ms"] / args.profiled_steps / cg_work
-            k = {"launches_per_step": st["launches"] / args.profiled_steps, "avg_ms": avg_ms,
-                 "ms_per_step": st["total_ms"] / args.profiled_steps}
-            if name in model:
-                bound, work, unit = model[name]
-                rate = work / (avg_ms * 1e-3)
-                if bound == "hbm":
-                    k.update(bound="hbm", achieved=rate / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=rate / 1e9 / HBM_PEAK_GBS, algorithmic_bytes=work)
-                else:
-                    k.update(bound="alu", achieved=rate / 1e12, peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s",
-                             frac=rate / 1e12 / FP64_VECTOR_TFLOPS, algorithmic_flops=work)
-            kernels[name] = k
-        dom = max((n for n in kernels if "bound" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
-        d = kernels[dom]
-        roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                    "unit": d["unit"], "frac": d["frac"],
-                    "traffic": measured_traffic(dom, args.workload, args.precision)}
+        cg_work = args.profiled_steps * float(np.mean([i["cg_iters"] for i in pinfos]))
+        kernels, roofline = kernel_table(stats, algorithmic(prob, g, view), args.profiled_steps, cg_work,
+                                         args.workload, args.precision)
 
     cpu = None
     if not args.no_cpu_baseline:

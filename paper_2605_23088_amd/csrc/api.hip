@@ -58,6 +58,14 @@ struct Profiler : LaunchTimer {
     if (!on || pending.empty()) return;
     (void)hipEventRecord(pending.back().b, stream);
   }
+  bool kernel_events(int cls, hipEvent_t* start, hipEvent_t* stop) override {
+    if (!on) return false;
+    Rec r{cls, get(), get()};
+    pending.push_back(r);
+    *start = r.a;
+    *stop = r.b;
+    return true;
+  }
   // call after the stream has been synchronised
   void collect() {
     for (Rec& r : pending) {

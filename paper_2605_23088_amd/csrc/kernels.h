@@ -176,10 +176,15 @@ struct PcgMatrix {
   const double* minv;  // (n, 9)
 };
 struct PcgState;  // device-side scalars, defined in pcg.hip
-// Optional per-launch timing hook (kernel class ids as in yasps.h).
+// Optional per-launch timing hook (kernel class ids as in yasps.h).  begin /
+// end bracket a group of launches with stream events; kernel_events hands out
+// an event pair that a single launch carries itself (hipExtLaunchKernelGGL),
+// which then reads the kernel's own start and end, without the marker packets'
+// dispatch gaps.
 struct LaunchTimer {
   virtual void begin(int cls) = 0;
   virtual void end() = 0;
+  virtual bool kernel_events(int cls, hipEvent_t* start, hipEvent_t* stop) = 0;
 };
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter,
               bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
