@@ -105,6 +105,9 @@ def subsample(prob, frac, seed=1):
 
     k = pick(prob["tet_idx"].shape[0])
     q["tet_idx"], q["dm_inv"], q["vol"] = prob["tet_idx"][k], prob["dm_inv"][k], prob["vol"][k]
+    for key in ("mu_t", "lam_t", "theta"):  # per-tet parameters
+        if key in prob:
+            q[key] = prob[key][k]
     k = pick(prob["ctype"].shape[0])
     q["ctype"], q["cidx"] = prob["ctype"][k], prob["cidx"][k]
     if len(prob.get("tri_idx", [])):
@@ -133,7 +136,7 @@ def cpu_baseline(prob, frac=1.0, solve=True):
         what = f"one Newton step (eval + assembly + PCG to 1e-8 + line search, {info['cg_iters']} PCG iterations)"
     else:
         o.assemble(o.eval(q["x0"]))
-        what = "evaluation + assembly only (the PCG of this stiff scene takes thousands of iterations)"
+        what = "evaluation + assembly only (the PCG takes thousands of iterations here)"
     t2 = time.perf_counter()
     log(f"[bench] oracle {t2 - t1:.1f} s")
     part = "the full workload" if frac >= 1.0 else f"a seeded {frac:g} fraction of every stencil class"
@@ -174,10 +177,11 @@ def kernel_table(stats, model, steps, cg_work, workload, precision):
 
 def bench_static(args):
     """Differentiation form on the 48x48x29-cell static block (400,896 tets,
-    4 corners fixed, per-tet Young's moduli, 300k PT stencils): the forward
+    bottom rim fixed, per-tet Young's moduli, 300k PT stencils): the forward
     equilibrium solve from x0 (Newton to max|g| <= 1e-9 of the weight scale)
     and the backward pass (adjoint PCG on the exact Hessian + per-tet mixed
-    partials), each timed end to end after one untimed warm-up pair."""
+    partials), each timed end to end after one untimed warm-up pair; then one
+    profiled backward pass for the per-kernel table."""
     import numpy as np
     import torch
 
@@ -191,7 +195,7 @@ def bench_static(args):
     x0 = torch.as_tensor(prob["x0"], dtype=torch.float64, device="cuda").contiguous()
     xt = torch.as_tensor(prob["x_tgt"], dtype=torch.float64, device="cuda")
     s.set_theta(theta)
-    fw, bw, iters = [], [], []
+    fw, bw, iters, cg = [], [], [], []
     for k in range(1 + max(1, args.steps)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -201,14 +205,30 @@ def bench_static(args):
         g, lam = s.adjoint(xs, theta, 2.0 * (xs - xt))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        log(f"[bench] static pass {k}: forward {t1 - t0:.3f} s in {s.newton_iters} Newton steps, "
-            f"backward {t2 - t1:.3f} s")
+        log(f"[bench] static pass {k}: forward {t1 - t0:.3f} s in {s.newton_iters} Newton steps "
+            f"({s.cg_iters} PCG iterations), backward {t2 - t1:.3f} s ({s.adjoint_info['iters']} PCG iterations)")
         if k > 0:
             fw.append(t1 - t0)
             bw.append(t2 - t1)
             iters.append(s.newton_iters)
+            cg.append(s.cg_iters)
     n_it = float(np.mean(iters))
     ms_iter = 1e3 * float(np.mean(fw)) / n_it
+
+    kernels, roofline = {}, None
+    if args.profiled_steps > 0:
+        s.lib.profile(True)
+        s.adjoint(xs, theta, 2.0 * (xs - xt))
+        stats = s.lib.profile_stats()
+        s.lib.profile(False)
+        kernels, roofline = kernel_table(stats, algorithmic(prob, s.lib, s.lib.view()), 1,
+                                         float(s.adjoint_info["iters"]), "static", "fp64")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(prob, 0.5, False)
+
     stencils = n_stencils(prob)
     line = {
         "metric": METRIC,
@@ -224,16 +244,19 @@ def bench_static(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"static 48x48x29-cell block, {len(prob['tet_idx'])} tets with per-tet moduli, "
-                               f"{len(prob['ctype'])} PT stencils, 4 corners fixed; equilibrium to max|g| <= "
+                               f"{len(prob['ctype'])} PT stencils, bottom rim fixed; equilibrium to max|g| <= "
                                "1e-9 m g_max, then the adjoint of L = |x* - x_tgt|^2",
                    "tets": len(prob["tet_idx"]), "contacts": len(prob["ctype"]),
                    "free_vertices": int(prob["n_free"])},
         "forward_s": float(np.mean(fw)),
         "newton_iters": n_it,
         "newton_iter_ms": ms_iter,
+        "forward_pcg_iters": float(np.mean(cg)),
         "backward_ms": 1e3 * float(np.mean(bw)),
-        "roofline": None,
-        "cpu_baseline": None,
+        "backward_pcg_iters": int(s.adjoint_info["iters"]),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -47,6 +47,8 @@ class StaticEquilibrium:
         self.gscale = float(m.max() * np.linalg.norm(prob["gravity"]))
         self.newton_iters = 0
         self.exact_steps = 0
+        self.cg_iters = 0  # PCG iterations of the accepted steps of the last solve
+        self.adjoint_info = None  # PCG info of the last adjoint solve
         self.verbose = verbose
 
     def set_theta(self, theta):
@@ -79,6 +81,7 @@ class StaticEquilibrium:
         x = x0.detach().clone().contiguous()
         xk = torch.empty_like(x)
         self.exact_steps = 0
+        self.cg_iters = 0
         mu, mu0 = 0.0, None
         info = {"grad_max": float("inf")}
         for k in range(self.max_newton):
@@ -101,6 +104,7 @@ class StaticEquilibrium:
                     print(f"[equilibrium] step {k}: rejected, shift -> {mu:.3e}", file=sys.stderr, flush=True)
                 continue
             self.exact_steps += 1
+            self.cg_iters += info["cg_iters"]
             if self.verbose:
                 print(f"[equilibrium] step {k}: shift {mu:.3e}, max|g| {info['grad_max']:.3e}, "
                       f"alpha {info['alpha']:.3g}, {info['cg_iters']} PCG iterations", file=sys.stderr, flush=True)
@@ -117,6 +121,7 @@ class StaticEquilibrium:
         self.lib.eval(x_star, exact=True)
         self.lib.view()  # assemble the exact Hessian
         lam, info = self.lib.pcg(dl_dx.contiguous(), rtol=rtol, max_iter=100000, allow=())
+        self.adjoint_info = info
         return self.lib.theta_adjoint(x_star, lam, theta.contiguous()), lam
 
 

@@ -66,15 +66,6 @@ struct PcgState {
 
 namespace {
 
-// Sum of n partials in a fixed order (strided per thread, then a fixed tree),
-// computed identically by every workgroup that needs it.
-template <int BLOCK = RED_BLOCK>
-YDEV double sum_partials(const double* __restrict__ part, int n, double* lds) {
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += BLOCK) acc += part[j];
-  return block_sum<BLOCK>(acc, lds);
-}
-
 // (H x)_row for the row owned by this lane group: each lane takes every
 // SPMV_G-th block of the row (structure-of-arrays values, so the lanes of a
 // group read consecutive addresses); the sum is valid in every lane of the
@@ -218,34 +209,28 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   }
 }
 
-// Iteration i: convergence test on |r_i|, then w = H u with the u.w partials.
-// `nb_c` is the update kernel's grid (number of gamma / |r|^2 partials).
-// standalone: plain y = H x (no solver bookkeeping).
+// Iteration i: w = H u with the u.w partials, then (workgroup 0) the
+// convergence test on |r_i| from the update kernel's partials.  Only workgroup
+// 0 needs gamma_i and |r_i|^2, so no other workgroup reduces them; their
+// partials are loaded before the product and summed after it, so the loads
+// overlap the matrix stream.  When the test finds convergence (or max_iter),
+// this launch's w is not used: `done` stops the update kernel and every later
+// launch.  `nb_c` is the update kernel's grid (number of gamma / |r|^2
+// partials).  standalone: plain y = H x (no solver bookkeeping).
 template <class VT>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
                                                              int standalone) {
   __shared__ double lds[RED_BLOCK];
-  if (!standalone) {
-    if (st->done) return;
-    const int i = st->iter;
-    const double G = sum_partials(V.part_c, nb_c, lds);
-    const double R = sum_partials(V.part_c + nb_c, nb_c, lds);
-    const double bb = i == 0 ? R : st->bb;
-    const bool conv = R <= st->tol2 * bb;
-    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
-    if (first) {
-      st->gamma[i & 1] = G;
-      st->rr = R;
-      st->iter_b = i;
-      if (i == 0) st->bb = bb;
-    }
-    if (conv || i >= st->max_iter) {
-      if (first) {
-        st->status = conv ? 0 : -5;
-        st->done = 1;
-      }
-      return;
-    }
+  if (!standalone && st->done) return;
+  const bool book = !standalone && blockIdx.x == 0;  // uniform per workgroup
+  constexpr int PC = (MAX_WG_C + RED_BLOCK - 1) / RED_BLOCK;
+  double gp[PC], rp[PC];
+#pragma unroll
+  for (int q = 0; q < PC; ++q) {
+    const int j = threadIdx.x + q * RED_BLOCK;
+    const bool in = book && j < nb_c;
+    gp[q] = in ? V.part_c[j] : 0.0;
+    rp[q] = in ? V.part_c[nb_c + j] : 0.0;
   }
   const int lane = threadIdx.x % SPMV_G;
   double d = 0.0;
@@ -266,22 +251,90 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
   }
   const double ds = block_sum<RED_BLOCK>(d, lds);
   if (threadIdx.x == 0) V.part_b[blockIdx.x] = ds;
+  if (!book) return;
+  // the same association as a strided per-thread sum followed by block_sum
+  double ga = 0.0, ra = 0.0;
+#pragma unroll
+  for (int q = 0; q < PC; ++q) {
+    ga += gp[q];
+    ra += rp[q];
+  }
+  const double G = block_sum<RED_BLOCK>(ga, lds);
+  const double Rr = block_sum<RED_BLOCK>(ra, lds);
+  if (threadIdx.x == 0) {
+    const int i = st->iter;
+    const double bb = i == 0 ? Rr : st->bb;
+    const bool conv = Rr <= st->tol2 * bb;
+    st->gamma[i & 1] = G;
+    st->rr = Rr;
+    st->iter_b = i;
+    if (i == 0) st->bb = bb;
+    if (conv || i >= st->max_iter) {
+      st->status = conv ? 0 : -5;
+      st->done = 1;
+    }
+  }
+}
+
+// One pass of the update kernel: the values a thread reads, loaded before the
+// scalars that combine them are known.
+template <class VT>
+struct UpdLoads {
+  double p, s, u, w, x, r, m0, m1, m2;
+};
+
+template <class VT>
+YDEV UpdLoads<VT> upd_load(const PcgMatrix& A, const double* x, const Vecs<VT>& V, int base, int t, int vl, int c) {
+  UpdLoads<VT> L{};
+  const int v = base + vl;
+  if (v < A.n) {
+    const size_t k = 3 * (size_t)base + t;  // = 3 v + c
+    L.p = double(V.p[k]);
+    L.s = double(V.s[k]);
+    L.u = double(V.u[k]);
+    L.w = double(V.w[k]);
+    L.x = x[k];
+    L.r = double(V.r[k]);
+    const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
+    L.m0 = M[0];
+    L.m1 = M[1];
+    L.m2 = M[2];
+  }
+  return L;
 }
 
 // Iteration i: scalar recurrences, vector updates, preconditioning, and the
 // gamma / |r|^2 partials of iteration i + 1.  `nb_b` = SpMV grid.  One thread
 // per vertex component (coalesced vector traffic, 3x the threads of a
 // per-vertex mapping); the three residual components of a vertex meet in LDS
-// for the 3x3 block-Jacobi product.
+// for the 3x3 block-Jacobi product.  Each pass's vectors are loaded before
+// alpha and beta are known (the first pass before the reduction of the SpMV
+// partials, the next one while the current one computes).
 template <class VT>
 __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
                                                                PcgState* st, int nb_b) {
   if (st->done) return;
   __shared__ double lds[UPD_BLOCK];
   __shared__ double rsh[UPD_BLOCK];
+  const int t = threadIdx.x;
+  const int vl = t / 3, c = t - 3 * (t / 3);
+  const int stride = gridDim.x * UPD_VERTS;
+  int base = blockIdx.x * UPD_VERTS;
+  // the SpMV partials first (their sum is needed first), then the first pass
+  constexpr int PB = (MAX_WG_B + UPD_BLOCK - 1) / UPD_BLOCK;
+  double bp[PB];
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int j = t + q * UPD_BLOCK;
+    bp[q] = j < nb_b ? V.part_b[j] : 0.0;
+  }
+  UpdLoads<VT> cur = upd_load(A, x, V, base, t, vl, c);
   const int i = st->iter_b;
   const double gamma = st->gamma[i & 1];
-  const double delta = sum_partials<UPD_BLOCK>(V.part_b, nb_b, lds);
+  double dacc = 0.0;  // the association of a strided per-thread sum
+#pragma unroll
+  for (int q = 0; q < PB; ++q) dacc += bp[q];
+  const double delta = block_sum<UPD_BLOCK>(dacc, lds);
   const bool restart = i == st->restart_at;
   const double beta = restart ? 0.0 : gamma / st->gamma[(i - 1) & 1];
   const double pAp = restart ? delta : delta - beta * gamma / st->alpha[(i - 1) & 1];
@@ -294,34 +347,33 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     return;
   }
   const double alpha = gamma / pAp;
-  const int t = threadIdx.x;
-  const int vl = t / 3, c = t - 3 * (t / 3);
   double g = 0.0, rr = 0.0;
-  for (int base = blockIdx.x * UPD_VERTS; base < A.n; base += gridDim.x * UPD_VERTS) {
+  for (; base < A.n; base += stride) {
+    const UpdLoads<VT> nxt = upd_load(A, x, V, base + stride, t, vl, c);
     const int v = base + vl;
     const bool live = v < A.n;
     const size_t k = 3 * (size_t)base + t;  // = 3 v + c
     double r = 0.0;
     if (live) {
-      const VT p = VT(fma(beta, double(V.p[k]), double(V.u[k])));
-      const VT sv = VT(fma(beta, double(V.s[k]), double(V.w[k])));
+      const VT p = VT(fma(beta, cur.p, cur.u));
+      const VT sv = VT(fma(beta, cur.s, cur.w));
       V.p[k] = p;
       V.s[k] = sv;
-      x[k] = fma(alpha, double(p), x[k]);
-      const VT rc = VT(fma(-alpha, double(sv), double(V.r[k])));
+      x[k] = fma(alpha, double(p), cur.x);
+      const VT rc = VT(fma(-alpha, double(sv), cur.r));
       V.r[k] = rc;
       r = double(rc);
     }
     rsh[t] = r;
     __syncthreads();
     if (live) {
-      const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
-      const VT uc = VT(M[0] * rsh[3 * vl] + M[1] * rsh[3 * vl + 1] + M[2] * rsh[3 * vl + 2]);
+      const VT uc = VT(cur.m0 * rsh[3 * vl] + cur.m1 * rsh[3 * vl + 1] + cur.m2 * rsh[3 * vl + 2]);
       V.u[k] = uc;
       g = fma(r, double(uc), g);
       rr = fma(r, r, rr);
     }
     __syncthreads();  // rsh is rewritten by the next pass
+    cur = nxt;
   }
   const double gs = block_sum<UPD_BLOCK>(g, lds);
   const double rs = block_sum<UPD_BLOCK>(rr, lds);

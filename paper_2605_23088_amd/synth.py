@@ -180,11 +180,12 @@ def _pack(n_free, x0, x_fixed, mass, x_tilde, tets, dm_inv, vol, ctype, cidx, **
 # Contacts against a fixed collider under the bottom face
 # --------------------------------------------------------------------------
 
-def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3):
+def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, tri_ok=None):
     """PT and EE stencils between the bottom face (z = 0) of a grid block and a
     private fixed feature per stencil placed below it.
 
-    PT: a uniformly chosen bottom triangle and a fixed point at
+    PT: a uniformly chosen bottom triangle (among those where `tri_ok`, a mask
+        over the bottom triangles, is set) and a fixed point at
         centroid - sqrt(d) z, d ~ U(dlo, dhi) (d is a squared distance).
     EE: a uniformly chosen bottom edge and a fixed horizontal edge of length a,
         perpendicular to it, through midpoint - sqrt(d) z.
@@ -195,7 +196,8 @@ def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3):
     fixed = []
     ctype, cidx = [], []
     if n_pt:
-        t = tris[rng.integers(0, tris.shape[0], size=n_pt)]
+        pool = tris if tri_ok is None else tris[tri_ok]
+        t = pool[rng.integers(0, pool.shape[0], size=n_pt)]
         d = rng.uniform(dlo, dhi, size=n_pt)
         c = X[t].mean(axis=1)
         c[:, 2] -= np.sqrt(d)
@@ -360,38 +362,61 @@ def c4_block(seed=SEEDS["C4"], n_pt=750_000, n_ee=750_000):
 
 
 def c5_static(seed=SEEDS["C5"], nx=48, ny=48, nz=29, a=0.02, n_pt=300_000, nu=0.4,
-              rho=1000.0, kappa=1e4, dhat=1e-3):
+              rho=1000.0, kappa=136.0, dhat=1e-3, pin="rim"):
     """Differentiation-form workload: static equilibrium of a 48x48x29-cell block
     (400,896 tets, 72,030 vertices) under gravity, per-tet Young's modulus
-    theta log-uniform in [5e4, 2e5], the 4 bottom-corner vertices fixed, and
-    300k PT stencils against fixed points under the bottom face.  Also returns
-    a seeded target x_tgt = x0 + N(0, 1e-3)."""
+    theta log-uniform in [5e4, 2e5], 300k PT stencils against fixed points
+    under the bottom face, and fixed vertices `pin`: "rim" (default) the
+    boundary ring of the bottom face (192 vertices), "corners" its 4 corners.
+    The PT stencils avoid bottom triangles whose 3 vertices are all fixed.
+    Also returns a seeded target x_tgt = x0 + N(0, 1e-3).
+
+    The contacts act along the normals of the bottom triangles, so once the
+    bottom sags they push sideways as well; with only the 4 corners fixed,
+    nothing but the shear of the elements at those 4 vertices holds the block,
+    and it slides off as a near-rigid body (an almost singular exact Hessian).
+    The fixed rim holds it.
+
+    kappa = 136: at x0 the barriers' total upward force on the free vertices
+    of the default block (38.42 kappa N) equals their weight (5,240.0 N) to
+    within 0.3 %, so the block rests on the contact layer.  The two cubes' kappa = 1e4 would push up with
+    about 76 times the weight against the fixed vertices.  Smaller blocks pass
+    their own kappa."""
     r_pos, r_con, r_theta, r_tgt = _streams(seed)
     X = grid_vertices(nx, ny, nz, a)
     tets = kuhn_tets(nx, ny, nz)
     Ds = _edge_matrix(X, tets)
     dm_inv, vol = np.linalg.inv(Ds), np.abs(np.linalg.det(Ds)) / 6.0
     nv = X.shape[0]
-    corners = np.array([grid_vid(nx, ny, i, j, 0) for i in (0, nx) for j in (0, ny)])
+    if pin == "corners":
+        pinned = np.array([grid_vid(nx, ny, i, j, 0) for i in (0, nx) for j in (0, ny)])
+    elif pin == "rim":
+        pinned = np.array([grid_vid(nx, ny, i, j, 0) for j in range(ny + 1) for i in range(nx + 1)
+                           if i in (0, nx) or j in (0, ny)])
+    else:
+        raise ValueError(f"unknown pin set {pin!r}")
     is_fixed = np.zeros(nv, bool)
-    is_fixed[corners] = True
+    is_fixed[pinned] = True
     free = np.flatnonzero(~is_fixed)
     n_free = free.size
+    n_pin = pinned.size
     new_id = np.empty(nv, np.int64)
     new_id[free] = np.arange(n_free)
-    new_id[corners] = n_free + np.arange(4)
-    # contacts (vertex ids in the original numbering, fixed partners after the 4 corners)
-    ctype, cidx, x_part = _collider_contacts(r_con, X, nx, ny, n_pt, 0, nv)
+    new_id[pinned] = n_free + np.arange(n_pin)
+    # contacts (vertex ids in the original numbering, fixed partners after the
+    # pinned vertices) on bottom triangles with at least one free vertex
+    tri_ok = None if pin == "corners" else ~is_fixed[face_triangles(nx, ny, 0)].all(axis=1)
+    ctype, cidx, x_part = _collider_contacts(r_con, X, nx, ny, n_pt, 0, nv, tri_ok=tri_ok)
     cidx = cidx.astype(np.int64)
     part = cidx[:, 0] - nv
     tri = new_id[cidx[:, 1:]]
-    cidx = np.concatenate([(n_free + 4 + part)[:, None], tri], 1)
+    cidx = np.concatenate([(n_free + n_pin + part)[:, None], tri], 1)
     theta = np.exp(r_theta.uniform(np.log(5e4), np.log(2e5), size=tets.shape[0]))
     mu1, lam1 = lame(1.0, nu)
     mass_all = _lumped_mass(nv, tets, vol, rho)
     x0 = X[free]
     x_tgt = x0 + r_tgt.normal(0.0, 1e-3, size=x0.shape)
-    x_fixed = np.concatenate([X[corners], x_part])
+    x_fixed = np.concatenate([X[pinned], x_part])
     return _pack(n_free, x0, x_fixed, mass_all[free], np.zeros_like(x0), new_id[tets], dm_inv,
                  vol, ctype, cidx, mu_t=theta * mu1, lam_t=theta * lam1, theta=theta,
                  mu1=mu1, lam1=lam1, h=1.0, kappa=kappa, dhat=dhat, rho=rho, static=True,

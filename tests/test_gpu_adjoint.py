@@ -24,7 +24,7 @@ def loss_and_grad(solver, theta_np, x0, x_tgt):
 
 def test_adjoint_matches_oracle():
     from paper_2605_23088_amd.adjoint import StaticEquilibrium
-    p = synth.c5_static(seed=21, nx=4, ny=3, nz=3, a=0.05, n_pt=40)
+    p = synth.c5_static(seed=21, nx=4, ny=3, nz=3, a=0.05, n_pt=40, kappa=1e4, pin="corners")
     o = oasm.Oracle(p)
     oadj.set_theta(o, p["theta"])
     xs_o, _ = oadj.solve_equilibrium(o, p["x0"], gtol=GTOL)
@@ -43,7 +43,7 @@ def test_adjoint_matches_oracle():
 
 def test_adjoint_matches_finite_differences():
     from paper_2605_23088_amd.adjoint import StaticEquilibrium
-    p = synth.c5_static(seed=20265, nx=12, ny=12, nz=8, a=0.02, n_pt=2000)
+    p = synth.c5_static(seed=20265, nx=12, ny=12, nz=8, a=0.02, n_pt=2000, kappa=1e4, pin="corners")
     s = StaticEquilibrium(p, gtol=GTOL)
     x0 = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda")
     xt = torch.as_tensor(p["x_tgt"], dtype=torch.float64, device="cuda")

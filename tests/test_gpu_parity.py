@@ -26,7 +26,7 @@ def case(name):
     if name == "block_mid":
         return synth.small_block(seed=12, nx=10, ny=9, nz=8, n_pt=600, n_ee=500)
     if name == "static":
-        return synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200)
+        return synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200, kappa=1e4, pin="corners")
     raise KeyError(name)
 
 

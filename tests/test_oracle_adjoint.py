@@ -13,7 +13,7 @@ GTOL = 5e-11
 
 @pytest.fixture(scope="module")
 def static_case():
-    p = synth.c5_static(seed=21, nx=4, ny=3, nz=3, a=0.05, n_pt=40)
+    p = synth.c5_static(seed=21, nx=4, ny=3, nz=3, a=0.05, n_pt=40, kappa=1e4, pin="corners")
     o = oasm.Oracle(p)
     adjoint.set_theta(o, p["theta"])
     xs, _ = adjoint.solve_equilibrium(o, p["x0"], gtol=GTOL)
