@@ -142,6 +142,7 @@ struct yasps_ctx {
   double* f_vals = nullptr;
   float* f_vals32 = nullptr;
   long long f_nnz = 0;
+  int f_xsplit[PCG_XCDS + 1] = {};
 
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
@@ -213,6 +214,16 @@ yasps_status build_full_matrix(yasps_ctx* c) {
   FullPattern fp;
   build_full(c->n, c->hpat_s, c->nc ? &c->hpat_d : nullptr, fp);
   c->f_nnz = (long long)fp.col.size();
+  // XCD row ranges of equal work: a row costs its blocks plus about two blocks'
+  // worth of fixed work (row pointers, the lane-group reduction, the output)
+  constexpr long long ROW_COST = 2;
+  const long long work = c->f_nnz + ROW_COST * c->n;
+  int r = 0;
+  for (int x = 0; x <= PCG_XCDS; ++x) {
+    const long long target = work * x / PCG_XCDS;
+    while (r < c->n && (long long)fp.row_ptr[r] + ROW_COST * r < target) ++r;
+    c->f_xsplit[x] = x == PCG_XCDS ? c->n : r;
+  }
   HIPCHK(c, upload(c->full_allocs, &c->f_rp, fp.row_ptr, c->stream));
   HIPCHK(c, upload(c->full_allocs, &c->f_col, fp.col, c->stream));
   HIPCHK(c, upload(c->full_allocs, &c->f_src, fp.src, c->stream));
@@ -377,6 +388,7 @@ PcgMatrix pcg_matrix(const yasps_ctx* c) {
   A.v32 = c->f_vals32;
   A.nnz = c->f_nnz;
   A.minv = c->minv;
+  for (int x = 0; x <= PCG_XCDS; ++x) A.xsplit[x] = c->f_xsplit[x];
   return A;
 }
 

@@ -163,8 +163,13 @@ void launch_max_norm3(int n, const double* p, double* part, int nblk, hipStream_
 void launch_dot(int n3, const double* a, const double* b, double* part, int nblk, hipStream_t s);
 
 // PCG.
+// XCDs of the part: the SpMV-shaped kernels give each a contiguous row range.
+constexpr int PCG_XCDS = 8;
 struct PcgMatrix {
   int n;
+  // first row of each XCD's range (xsplit[PCG_XCDS] = n), chosen on the host so
+  // that the ranges hold equal work (blocks plus a per-row overhead)
+  int xsplit[PCG_XCDS + 1];
   // both triangles of H_static + H_dynamic, row by row (see FullPattern),
   // block values as structure of arrays [9][nnz] (entry q of block k at
   // v[q * nnz + k]), float64 or, in the precision form, float32

@@ -84,21 +84,21 @@ YDEV void row_blocks(const PcgMatrix& A, const T* __restrict__ v, int row, int l
 }
 
 // The block rows of the SpMV-shaped kernels are split into NXCD contiguous
-// ranges, one per XCD: workgroups are dispatched to the XCDs round robin by
-// index, so workgroup b runs on XCD b % NXCD and makes passes over that XCD's
-// range.  The column gathers of one XCD then stay near its own rows (mesh
-// locality) and in its own L2.  These kernels' grids are multiples of NXCD.
-constexpr int NXCD = 8;
+// ranges of equal work (A.xsplit), one per XCD: workgroups are dispatched to
+// the XCDs round robin by index, so workgroup b runs on XCD b % NXCD and makes
+// passes over that XCD's range.  The column gathers of one XCD then stay near
+// its own rows (mesh locality) and in its own L2.  These kernels' grids are
+// multiples of NXCD.
+constexpr int NXCD = PCG_XCDS;
 static_assert(MAX_WG_B % NXCD == 0 && MAX_WG_C % NXCD == 0, "partial-sum arrays hold the rounded grids");
 struct RowRange {
   int end, first, stride;
 };
-YDEV RowRange xcd_rows(int n) {
+YDEV RowRange xcd_rows(const PcgMatrix& A) {
   const int xcd = blockIdx.x % NXCD, j = blockIdx.x / NXCD, per = gridDim.x / NXCD;
   RowRange r;
-  const int begin = (int)((long long)n * xcd / NXCD);
-  r.end = (int)((long long)n * (xcd + 1) / NXCD);
-  r.first = begin + j * SPMV_ROWS;
+  r.end = A.xsplit[xcd + 1];
+  r.first = A.xsplit[xcd] + j * SPMV_ROWS;
   r.stride = per * SPMV_ROWS;
   return r;
 }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   __shared__ double lds[RED_BLOCK];
   const int lane = threadIdx.x % SPMV_G;
   double g = 0.0, rr = 0.0;
-  const RowRange R = xcd_rows(A.n);
+  const RowRange R = xcd_rows(A);
   for (int base = R.first; base < R.end; base += R.stride) {
     const int row = base + threadIdx.x / SPMV_G;
     const bool live = row < R.end;
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
   }
   const int lane = threadIdx.x % SPMV_G;
   double d = 0.0;
-  const RowRange R = xcd_rows(A.n);
+  const RowRange R = xcd_rows(A);
   for (int base = R.first; base < R.end; base += R.stride) {
     const int row = base + threadIdx.x / SPMV_G;
     const bool live = row < R.end;
