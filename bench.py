@@ -44,15 +44,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic(prob, g, view):
-    """Per-launch algorithmic bytes / flops of each kernel class."""
+def algorithmic(prob, g, view, projected=True):
+    """Per-launch algorithmic bytes / flops of each kernel class.  The flop
+    models count the eigen-projections; with projected=False (exact Hessians,
+    no projection) the evaluation kernels are left unmodelled."""
     n = g.n
     nt = g.nt
     ct = prob["ctype"]
     nnzb = view.nnzb_static + view.nnzb_dynamic
     c_flops = sum(CONTACT_FLOPS[int(t)] * int((ct == t).sum()) for t in range(4))
     cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))
-    return {
+    model = {
         "cloth_eval": ("alu", cl_flops, "TFLOP/s"),
         # FP64 ALU bound
         "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
@@ -66,6 +68,10 @@ def algorithmic(prob, g, view):
         "pcg_update": ("hbm", n * (6 * 24.0 + 72.0 + 5 * 24.0), "GB/s"),
         "inertia": ("hbm", n * (24.0 * 2 + 8.0 + 72.0 + 24.0), "GB/s"),
     }
+    if not projected:
+        for k in ("cloth_eval", "snh_eval", "contact_eval"):
+            del model[k]
+    return model
 
 
 KERNEL_SOURCES = {"pcg_spmv": "pcg.hip", "pcg_update": "pcg.hip", "assemble": "assembly.hip",
@@ -221,7 +227,7 @@ def bench_static(args):
         s.adjoint(xs, theta, 2.0 * (xs - xt))
         stats = s.lib.profile_stats()
         s.lib.profile(False)
-        kernels, roofline = kernel_table(stats, algorithmic(prob, s.lib, s.lib.view()), 1,
+        kernels, roofline = kernel_table(stats, algorithmic(prob, s.lib, s.lib.view(), projected=False), 1,
                                          float(s.adjoint_info["iters"]), "static", "fp64")
 
     cpu = None

@@ -36,10 +36,10 @@ namespace yasps {
 // Launch shapes (compile-time; the defaults come from sweeps on the 40^3 and
 // 80x80x52 workloads).
 #ifndef YASPS_SPMV_G
-#define YASPS_SPMV_G 8
+#define YASPS_SPMV_G 16
 #endif
 #ifndef YASPS_MAX_WG_B
-#define YASPS_MAX_WG_B 1024
+#define YASPS_MAX_WG_B 4096
 #endif
 #ifndef YASPS_MAX_WG_C
 #define YASPS_MAX_WG_C 512
