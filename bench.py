@@ -36,6 +36,7 @@ FP64_VECTOR_TFLOPS = 78.6
 # Algorithmic work per unit:
 SNH_FLOPS_PER_TET = 4.0e3        # closed-form F-space eigensystem: 3x3 SVD, 9 rank-one modes, J_F map
 CONTACT_FLOPS = {0: 3.0e4, 1: 1.0e4, 2: 3.0e4, 3: 1.0e4}  # PT 9x9, EE 6x6 eigenproblems
+PT_FIXED_POINT_FLOPS = 1.25e4    # 6x6 eigenproblem + frame / QR transforms (point fixed, triangle free)
 MEMBRANE_FLOPS = 6.0e3           # 6x6 F-space Jacobi eigenproblem and the J_F map
 HINGE_FLOPS = 3.0e4              # 9x9 Helmert-reduced Jacobi eigenproblem
 
@@ -48,19 +49,36 @@ def algorithmic(prob, g, view, projected=True):
     """Per-launch algorithmic bytes / flops of each kernel class.  The flop
     models count the eigen-projections; with projected=False (exact Hessians,
     no projection) the evaluation kernels are left unmodelled."""
+    import numpy as np
     n = g.n
     nt = g.nt
     ct = prob["ctype"]
     nnzb = view.nnzb_static + view.nnzb_dynamic
-    c_flops = sum(CONTACT_FLOPS[int(t)] * int((ct == t).sum()) for t in range(4))
+    ci = np.asarray(prob["cidx"])
+    pt_fp = (ct == 0) & (ci[:, 0] >= n) & (ci[:, 1:] < n).all(axis=1) if len(ct) else np.zeros(0, bool)
+    c_flops = (sum(CONTACT_FLOPS[int(t)] * int(((ct == t) & ~pt_fp).sum()) for t in range(4)) +
+               PT_FIXED_POINT_FLOPS * int(pt_fp.sum()))
+
+    def contributions(idx):  # (upper blocks, gradient rows) one stencil class contributes
+        if len(idx) == 0:
+            return 0, 0
+        k = ((np.asarray(idx) >= 0) & (np.asarray(idx) < n)).sum(axis=1)
+        return int((k * (k + 1) // 2).sum()), int(k.sum())
+
+    nb, ng = n if not prob.get("static") else 0, n  # inertia: diagonal block (dynamic form), gradient row
+    for key in ("tet_idx", "tri_idx", "hinge_idx", "cidx"):
+        b, r = contributions(prob.get(key, []))
+        nb, ng = nb + b, ng + r
     cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))
     model = {
         "cloth_eval": ("alu", cl_flops, "TFLOP/s"),
         # FP64 ALU bound
         "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
         "contact_eval": ("alu", c_flops, "TFLOP/s"),
-        # HBM bound: what the method must move
-        "assemble": ("hbm", 72.0 * nnzb + 24.0 * n, "GB/s"),
+        # HBM bound: what the method must move.  Assembly reads every staged
+        # contribution (72 B per block, 24 B per gradient row) and writes the
+        # upper blocks and the gradient
+        "assemble": ("hbm", 72.0 * (nb + nnzb) + 24.0 * (ng + n), "GB/s"),
         "block_inverse": ("hbm", 2 * 72.0 * n, "GB/s"),
         # values + column index once per stored block, row pointers, u read, w written
         "pcg_spmv": ("hbm", 76.0 * nnzb + 8.0 * (n + 1) + 48.0 * n, "GB/s"),

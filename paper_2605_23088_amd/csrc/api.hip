@@ -639,7 +639,10 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
       c->nc = 0;
       return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": no free vertex");
     }
-    key[s] = ty[s] * 8 + nf;
+    // point-triangle stencils against a fixed point get their own group (and
+    // kernel): their projection reduces to a 6 x 6 eigenproblem
+    const bool pt_fixed_point = ty[s] == 0 && nf == 3 && idx[s] >= c->n;
+    key[s] = ty[s] * 8 + (pt_fixed_point ? PT_TRIANGLE_FREE : nf);
   }
   c->nc = nc;
   build_pattern(c->n, idx.data(), nc, false, c->hpat_d);

@@ -252,6 +252,170 @@ YHD bool diff_vars(const double (&xv)[4][3], double (&u)[Topo<TYPE>::NU][3]) {
   return ok;
 }
 
+// PSD projection of the 9 x 9 Hessian A of a point-triangle stencil whose
+// point is fixed (free vertices t0, t1, t2).  The plane distance does not
+// change when the triangle's vertices move inside their plane, so in the
+// orthonormal frame F = [t1 t2 n] of the plane (applied to every vertex) the
+// Hessian is M = [[0, B^T], [B, C]]: a zero 6 x 6 in-plane block, the 3 x 6
+// normal-by-in-plane block B and the 3 x 3 normal block C.  With the
+// Householder factorisation B^T = Q R (Q 6 x 3 orthonormal), M = W M6 W^T,
+// W = diag(Q, I3), M6 = [[0, R], [R^T, C]], and M annihilates the in-plane
+// directions orthogonal to Q; so Proj(M) = W Proj(M6) W^T, a 6 x 6 instead of
+// a 9 x 9 eigenproblem.  The computed in-plane block is zero up to rounding
+// and is dropped.  F's columns are (t1, t2, n) as rows of Fr.
+YHD void project_pt_fixed_point(Sym<9, double>& A, const double (&Fr)[3][3]) {
+  // frame coordinates: P'(Ia, Jb) = sum_ij Fr[a][i] A(3I+i, 3J+j) Fr[b][j]
+  double Bt[6][3];  // Bt[2I+a][J] = P'(I a, J n), a in {t1, t2}
+  double Cn[3][3];  // P'(I n, J n)
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      double T[3][3];  // Fr A_IJ
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc = fma(Fr[a][i], A(3 * I + i, 3 * J + j), acc);
+          T[a][j] = acc;
+        }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc = fma(T[a][j], Fr[2][j], acc);
+        if (a < 2)
+          Bt[2 * I + a][J] = acc;
+        else
+          Cn[I][J] = acc;
+      }
+    }
+  // Householder QR of Bt (6 x 3): Bt = Q R
+  double V[3][6];  // reflector vectors (v_k has zeros above row k)
+  double R[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) nrm2 = r >= k ? fma(Bt[r][k], Bt[r][k], nrm2) : nrm2;
+    const double nrm = sqrt(nrm2);
+    const double alpha = Bt[k][k] >= 0.0 ? -nrm : nrm;  // v = x - alpha e_k, no cancellation
+    double vn2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const double v = r < k ? 0.0 : (r == k ? Bt[k][k] - alpha : Bt[r][k]);
+      V[k][r] = v;
+      vn2 = fma(v, v, vn2);
+    }
+    const double inv = vn2 > 0.0 ? 2.0 / vn2 : 0.0;  // H_k = I - inv v v^T (identity when x = 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < k) continue;
+      double dotv = 0.0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) dotv = fma(V[k][r], Bt[r][c], dotv);
+      const double f = inv * dotv;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) Bt[r][c] = fma(-f, V[k][r], Bt[r][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[k][c] = c < k ? 0.0 : Bt[k][c];
+    V[k][0] *= sqrt(inv);  // scale so that H_k = I - v v^T
+#pragma unroll
+    for (int r = 1; r < 6; ++r) V[k][r] *= sqrt(inv);
+  }
+  // Q = H_0 H_1 H_2 applied to the first three columns of I6
+  double Q[6][3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Q[r][c] = r == c ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 2; k >= 0; --k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double dotv = 0.0;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) dotv = fma(V[k][r], Q[r][c], dotv);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) Q[r][c] = fma(-dotv, V[k][r], Q[r][c]);
+    }
+  // the reduced matrix and its projection
+  Sym<6, double> M6;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) M6(i, j) = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) M6(i, 3 + J) = R[i][J];
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = I; J < 3; ++J) M6(3 + I, 3 + J) = 0.5 * (Cn[I][J] + Cn[J][I]);
+  psd_project<6, double>(M6);
+  // back to frame coordinates: P'_SS = Q P11 Q^T, P'_SN = Q P12, P'_NN = P22
+  double QP11[6][3], PSN[6][3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a1 = fma(Q[r][k], M6(k, c), a1);
+        a2 = fma(Q[r][k], M6(k, 3 + c), a2);
+      }
+      QP11[r][c] = a1;
+      PSN[r][c] = a2;
+    }
+  // vertex blocks in frame coordinates, then back: A_IJ = Fr^T P'_IJ Fr
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = I; J < 3; ++J) {
+      double P[3][3];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc = fma(QP11[2 * I + a][k], Q[2 * J + b][k], acc);
+          P[a][b] = acc;
+        }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        P[a][2] = PSN[2 * I + a][J];
+        P[2][a] = PSN[2 * J + a][I];
+      }
+      P[2][2] = M6(3 + I, 3 + J);
+      double T[3][3];  // P Fr
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) acc = fma(P[a][b], Fr[b][j], acc);
+          T[a][j] = acc;
+        }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (I == J && j < i) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) acc = fma(Fr[a][i], T[a][j], acc);
+          A(3 * I + i, 3 * J + j) = acc;
+        }
+    }
+}
+
 // Maps a u-space gradient gu (3 NU) and Hessian Hu (3 NU x 3 NU, upper) of an
 // energy of the difference variables u_U = sum_a TOPO::M(U, a) x_a to the
 // stencil's K free vertices (fl[k] = local index of the k-th free vertex,
@@ -260,9 +424,13 @@ YHD bool diff_vars(const double (&xv)[4][3], double (&u)[Topo<TYPE>::NU][3]) {
 // vertex fl[I]).  Unless EXACT the Hessian is projected to the PSD cone: in the
 // Helmert basis when every vertex is free (exact reduction, the energy is
 // translation invariant), else on the free principal submatrix.
-template <class TOPO, int K, bool EXACT, class GS, class BS>
+//
+// PT_FIXED_POINT (point-triangle stencils whose free vertices are exactly the
+// triangle's): the projection takes the reduced path of
+// project_pt_fixed_point in the frame Fr (rows t1, t2, n of the triangle).
+template <class TOPO, int K, bool EXACT, bool PT_FIXED_POINT = false, class GS, class BS>
 YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double>& Hu, const int (&fl)[4],
-                      GS&& grad_sink, BS&& block_sink) {
+                      GS&& grad_sink, BS&& block_sink, const double (*Fr)[3] = nullptr) {
   constexpr int NV = TOPO::NV, NU = TOPO::NU;
   // coefficients M[U][fl[k]] selected at run time from the compile-time table
   double Mf[NU][K];
@@ -365,7 +533,14 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
               for (int W = 0; W < NU; ++W) acc = fma(Mf[U][I] * Mf[W][J], Hu(3 * U + i, 3 * W + l), acc);
             A(3 * I + i, 3 * J + l) = acc;
           }
-    if (!EXACT) psd_project<3 * K, double>(A);
+    if constexpr (!EXACT) {
+      if constexpr (PT_FIXED_POINT) {
+        static_assert(K == 3 && NV == 4, "point-triangle stencils with the triangle free");
+        project_pt_fixed_point(A, *reinterpret_cast<const double(*)[3][3]>(Fr));
+      } else {
+        psd_project<3 * K, double>(A);
+      }
+    }
 #pragma unroll
     for (int I = 0; I < K; ++I)
 #pragma unroll
@@ -383,8 +558,11 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
 // Energy, free-vertex gradient rows and free-vertex upper Hessian blocks of one
 // contact stencil with K free vertices (sinks as in emit_reduced).  Returns
 // false when an input is not finite.  d receives the squared distance;
-// e = kappa b(d) (0 when d >= dhat or d <= 0).
-template <int TYPE, int K, bool EXACT, class GS, class BS>
+// e = kappa b(d) (0 when d >= dhat or d <= 0).  PT_FIXED_POINT: a
+// point-triangle stencil whose point is fixed and whose triangle is free
+// (fl = 1, 2, 3), projected through project_pt_fixed_point.  Its frame is
+// degenerate only with the triangle, and then d is not finite either.
+template <int TYPE, int K, bool EXACT, bool PT_FIXED_POINT = false, class GS, class BS>
 YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
                          double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink) {
   constexpr int NU = Topo<TYPE>::NU;
@@ -406,7 +584,25 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
   for (int r = 0; r < 3 * NU; ++r)
 #pragma unroll
     for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
-  emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
+  if constexpr (PT_FIXED_POINT && !EXACT) {
+    static_assert(TYPE == 0 && K == 3, "point-triangle stencils with the triangle free");
+    // the triangle's frame: t1 along e1, n along e1 x e2, t2 = n x t1
+    double n[3], t2[3];
+    cross(u[1], u[2], n);
+    const double l1 = sqrt(dot(u[1], u[1])), ln = sqrt(dot(n, n));
+    double Fr[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Fr[0][i] = u[1][i] / l1;
+      Fr[2][i] = n[i] / ln;
+    }
+    cross(Fr[2], Fr[0], t2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Fr[1][i] = t2[i];
+    emit_reduced<Topo<TYPE>, K, EXACT, true>(gu, D.H, fl, grad_sink, block_sink, Fr);
+  } else {
+    emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
+  }
   return ok;
 }
 

@@ -118,6 +118,10 @@ struct ContactArgs {
   double* nact_part;     // per workgroup count of active stencils
   uint32_t* flags;
 };
+// `nfree` is the number of free vertices of the group's stencils, or
+// PT_TRIANGLE_FREE for point-triangle stencils whose point is fixed and whose
+// three triangle vertices are free (a kernel with a reduced projection).
+constexpr int PT_TRIANGLE_FREE = 5;
 void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, hipStream_t s);
 // Line-search trial at y = x + alpha p: energy partials, feasibility (d > 0 and
 // PT/EE side kept) per workgroup.
