@@ -149,7 +149,8 @@ struct yasps_ctx {
   uint32_t* flags = nullptr;
   void* pcg_work = nullptr;
   double *p_dir = nullptr, *x_trial = nullptr, *b_tmp = nullptr;
-  double* host_scal = nullptr;  // pinned
+  double* host_scal = nullptr;  // pinned: [0, 16) scalars and flags, [16, 32) the PCG's polled state
+  int pcg_hint = 0;             // iterations of the last PCG solve (sizes the next one's launch batches)
   int nparts_alloc = 0;
   bool evaluated = false;
   bool assembled = false;  // the SpMV matrix holds the values of the last assembly
@@ -863,7 +864,7 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
   int status = 0;
   const int it =
       pcg_solve(pcg_matrix(c), b, x, rtol, max_iter, c->prm.precision == YASPS_MIXED, c->pcg_work, &rel, &status,
-                c->stream, &c->prof);
+                c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipGetLastError());
@@ -904,8 +905,8 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);
   double rel = 0.0;
   int status = 0;
-  const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter,
-                           c->prm.precision == YASPS_MIXED, c->pcg_work, &rel, &status, c->stream, &c->prof);
+  const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter, c->prm.precision == YASPS_MIXED,
+                           c->pcg_work, &rel, &status, c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipEventRecord(ev[3], c->stream));

@@ -195,9 +195,14 @@ struct LaunchTimer {
   virtual void end() = 0;
   virtual bool kernel_events(int cls, hipEvent_t* start, hipEvent_t* stop) = 0;
 };
+// host_state: pinned host memory of at least 128 bytes that the solver polls
+// its device scalars into.  hint: in, the iteration count the caller expects
+// (0 = unknown); out, the count of this solve.  It only sizes the batches of
+// launches between two polls (a full batch first, up to just below the hint),
+// never the arithmetic.
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter,
               bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
-              LaunchTimer* tm);
+              LaunchTimer* tm, void* host_state, int* hint);
 size_t pcg_workspace_bytes(int n);
 // y = H x (both parts, symmetric upper storage) through the solver's SpMV kernel.
 void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s);

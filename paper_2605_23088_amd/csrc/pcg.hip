@@ -440,7 +440,8 @@ void timed_launch(LaunchTimer* tm, int cls, KERNEL kernel, int grid, int block, 
 
 template <class VT>
 int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, void* work, double* rel_out,
-            int* status_out, hipStream_t s, LaunchTimer* tm) {
+            int* status_out, hipStream_t s, LaunchTimer* tm, PcgState& hs, int* hint) {
+  static_assert(sizeof(PcgState) <= 128, "the pinned polling buffer holds 128 bytes");
   constexpr bool MIXED = sizeof(VT) == 4;
   constexpr int REPLACE_EVERY = 50;  // float64 residual replacement period (precision form)
   const int n = A.n;
@@ -458,9 +459,11 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
     return 0;
   }
   timed_launch(tm, 6, pcg_init_kernel<VT>, nb_c, RED_BLOCK, s, A, b, x, V, st);
-  int batch = 8;
+  // launches between polls: up to just below the expected count first, then 8
+  // at a time; without a hint 8, 16, 32, 64, 64, ...
+  const bool hinted = hint && *hint > 16;
+  int batch = hinted ? *hint - 8 : 8;
   long long launched = 0;  // (SpMV, update) pairs issued = iteration index while not done
-  PcgState hs{};
   int verified_at = -1;
   int restarts = 0;
   constexpr int MAX_RESTARTS = 32;
@@ -500,19 +503,21 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       batch = 8;
       continue;
     }
-    batch = std::min(batch * 2, 64);
+    batch = hinted ? 8 : std::min(batch * 2, 64);
   }
   *rel_out = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
   *status_out = hs.status;
+  if (hint) *hint = hs.iter_b;
   return hs.iter_b;
 }
 
 }  // namespace
 
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, bool mixed, void* work,
-              double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm) {
-  return mixed ? pcg_run<float>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm)
-               : pcg_run<double>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm);
+              double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm, void* host_state, int* hint) {
+  PcgState& hs = *static_cast<PcgState*>(host_state);
+  return mixed ? pcg_run<float>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
+               : pcg_run<double>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
 }
 
 }  // namespace yasps
