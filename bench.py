@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profiled-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-index-timing", dest="index_timing", action="store_false",
+                    help="skip timing the contact index rebuild (device and host builds)")
     ap.add_argument("--cells", type=int, default=40, help="block size of the block40 workload")
     ap.add_argument("--workload", choices=["block40", "cloth", "block80", "static"], default="block40")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
@@ -382,6 +384,24 @@ def main():
         kernels, roofline = kernel_table(stats, algorithmic(prob, g, view), args.profiled_steps, cg_work,
                                          args.workload, args.precision)
 
+    # rebuild of the contact index (yasps_set_contacts), outside the timed step:
+    # the device build of this context against a host-build context
+    index_ms = {}
+    if args.index_timing:
+        from paper_2605_23088_amd.yasps import INDEX_HOST
+        gh = Yasps(prob, precision=MIXED if args.precision == "mixed" else FP64, index_build=INDEX_HOST)
+        for name, ctx in (("device", g), ("host", gh)):
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.set_contacts(prob["ctype"], prob["cidx"])
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            index_ms[name] = 1e3 * min(ts)
+        gh.close()
+        log(f"[bench] contact index rebuild: device {index_ms['device']:.2f} ms, host {index_ms['host']:.2f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -413,6 +433,7 @@ def main():
         "line_search_trials": int(np.mean([i["ls_trials"] for i in infos])),
         "roofline": roofline,
         "kernels": kernels,
+        "contact_index_ms": index_ms or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

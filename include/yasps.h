@@ -77,6 +77,11 @@ typedef int32_t yasps_status;
 /* yasps_params.barrier */
 #define YASPS_SQLOG 0       /* kappa (d - dhat)^2 log(d/dhat)^2, as printed in the paper */
 #define YASPS_IPC_CLASSIC 1 /* -kappa (d - dhat)^2 log(d/dhat) */
+/* yasps_params.index_build: where yasps_set_contacts builds the dynamic part's
+   pattern, slot map, staging layout and SpMV rows (identical results; the paper
+   rebuilds only this part when the contacts change, section "Implementation") */
+#define YASPS_INDEX_DEVICE 0 /* on the GPU: stable radix sorts and scans */
+#define YASPS_INDEX_HOST 1   /* on the host (reference) */
 
 typedef struct yasps_ctx yasps_ctx;
 
@@ -129,6 +134,7 @@ typedef struct {
   int32_t precision; /* YASPS_FP64 or YASPS_MIXED */
   int32_t proj;      /* YASPS_F_SPACE or YASPS_X_SPACE */
   int32_t barrier;   /* YASPS_SQLOG or YASPS_IPC_CLASSIC */
+  int32_t index_build; /* YASPS_INDEX_DEVICE or YASPS_INDEX_HOST */
 } yasps_params;
 
 typedef struct {
@@ -202,9 +208,14 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
 
 /* Replaces the contact stencil list (the paper's dynamic primitives, section
  * "Index Generator" and the static/dynamic split of the index-computation
- * evaluation) and rebuilds the dynamic pattern and slot map.  The arrays are
- * copied; the caller may free them after the call.  Errors: YASPS_E_ARG
- * (bad type, id out of range, repeated vertex), YASPS_E_HIP. */
+ * evaluation) and rebuilds the dynamic pattern, slot map, staging layout and
+ * SpMV rows: on the GPU by default (YASPS_INDEX_DEVICE), on the host with
+ * YASPS_INDEX_HOST; both give the same arrays.  `type` and `idx` are device
+ * arrays; they are copied, and the caller may free them after the call.  The
+ * call synchronises the context stream.  Errors: YASPS_E_ARG (the first
+ * stencil with an unknown type, an id out of range, a repeated or misplaced
+ * vertex, or no free vertex; the context is then left without contacts),
+ * YASPS_E_HIP. */
 yasps_status yasps_set_contacts(yasps_ctx* ctx, const yasps_contacts* C);
 
 /* Evaluates every stencil at positions x (n_free, 3): energies, gradients and

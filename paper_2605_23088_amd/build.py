@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libyasps.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("YASPS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "elastic.hip", "contact.hip", "cloth.hip", "assembly.hip", "pcg.hip", "pattern.cpp"]
+SOURCES = ["api.hip", "elastic.hip", "contact.hip", "cloth.hip", "assembly.hip", "pcg.hip", "dynindex.hip",
+           "pattern.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",
@@ -51,7 +52,8 @@ def build(verbose=True):
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # every symbol must resolve at link time (a missing source is a build error)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -125,8 +125,15 @@ struct yasps_ctx {
   double* h_rest = nullptr;
   std::vector<Group> hgroups;
 
+  // static share of every full SpMV row (the static-only FullPattern), for the
+  // device build of the dynamic part
+  int32_t *sf_ptr = nullptr, *sf_col = nullptr, *sf_src = nullptr;
+  long long sf_nnz = 0;
+
   // dynamic part
   PartPattern hpat_d;
+  bool hpat_d_current = true;  // false after a device build until yasps_get_pattern downloads it
+  int32_t* dslot = nullptr;    // device slot map of a device build [nc][10]
   Part pd;
   std::vector<Group> groups;
   int32_t *c_idx = nullptr, *spos_c = nullptr, *gpos_c = nullptr, *cptr_d = nullptr, *gptr_d = nullptr,
@@ -207,6 +214,10 @@ yasps_status upload_part(yasps_ctx* c, std::vector<void*>& list, const PartPatte
   return YASPS_OK;
 }
 
+// XCD row ranges of equal work: a row costs its blocks plus about two blocks'
+// worth of fixed work (row pointers, the lane-group reduction, the output).
+constexpr int XCD_ROW_COST = 2;
+
 // (Re)builds the SpMV matrix layout over the current parts; synchronises the
 // stream so the host pattern can go out of scope.
 yasps_status build_full_matrix(yasps_ctx* c) {
@@ -215,9 +226,7 @@ yasps_status build_full_matrix(yasps_ctx* c) {
   FullPattern fp;
   build_full(c->n, c->hpat_s, c->nc ? &c->hpat_d : nullptr, fp);
   c->f_nnz = (long long)fp.col.size();
-  // XCD row ranges of equal work: a row costs its blocks plus about two blocks'
-  // worth of fixed work (row pointers, the lane-group reduction, the output)
-  constexpr long long ROW_COST = 2;
+  const long long ROW_COST = XCD_ROW_COST;
   const long long work = c->f_nnz + ROW_COST * c->n;
   int r = 0;
   for (int x = 0; x <= PCG_XCDS; ++x) {
@@ -445,8 +454,10 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (P->n_hinges > 0 && (!P->hinge_idx || !P->hinge_rest)) return fail(nullptr, YASPS_E_ARG, "hinge arrays missing");
   if (!(P->dhat > 0.0) || !(P->kappa >= 0.0) || !(P->h > 0.0))
     return fail(nullptr, YASPS_E_ARG, "dhat, kappa and h must be positive");
-  yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_SQLOG};
+  yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_SQLOG, YASPS_INDEX_DEVICE};
   if (opt) prm = *opt;
+  if (prm.index_build != YASPS_INDEX_DEVICE && prm.index_build != YASPS_INDEX_HOST)
+    return fail(nullptr, YASPS_E_ARG, "unknown index_build");
   if (prm.precision != YASPS_FP64 && prm.precision != YASPS_MIXED)
     return fail(nullptr, YASPS_E_ARG, "unknown precision");
   if (prm.proj != YASPS_F_SPACE) return fail(nullptr, YASPS_E_UNIMPL, "only F-space Neo-Hookean projection is built");
@@ -531,6 +542,15 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   build_staging(c->n, hst.data(), ns, c->hpat_s, order, dyn, true, st);
   yasps_status s = upload_part(c, c->allocs, c->hpat_s, c->ps);
   if (s) return bail(s);
+  {
+    FullPattern sf;
+    build_full(c->n, c->hpat_s, nullptr, sf);
+    c->sf_nnz = (long long)sf.col.size();
+    if (upload(c->allocs, &c->sf_ptr, sf.row_ptr, c->stream) != hipSuccess ||
+        upload(c->allocs, &c->sf_col, sf.col, c->stream) != hipSuccess ||
+        upload(c->allocs, &c->sf_src, sf.src, c->stream) != hipSuccess)
+      return bail(fail(c, YASPS_E_HIP, "upload of the static SpMV rows"));
+  }
   // per-class staging positions (storage order) and the hinge arrays in storage order
   auto rows = [&](const std::vector<int32_t>& src, int nrows, int j0, int cnt) {
     std::vector<int32_t> out((size_t)nrows * cnt);
@@ -599,6 +619,106 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   return YASPS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+const char* contact_error(int reason) {
+  return reason == 1 ? "unknown type" : reason == 2 ? "vertex id out of range, repeated or misplaced" : "no free vertex";
+}
+
+// Device build of the dynamic part (build_dynamic_index): the same arrays as the
+// host path below, without the round trip through host memory.
+yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
+  const int nc = C->n_contacts;
+  DynIndexIn in{};
+  in.n = c->n;
+  in.nall = c->P.n_free + c->P.n_fixed;
+  in.nc = nc;
+  in.type = C->type;
+  in.idx = C->idx;
+  in.nnzb_s = c->ps.nnzb;
+  in.sf_ptr = c->sf_ptr;
+  in.sf_col = c->sf_col;
+  in.sf_src = c->sf_src;
+  in.sf_nnz = c->sf_nnz;
+  in.row_cost = XCD_ROW_COST;
+  bool oom = false;
+  auto alloc_into = [&](std::vector<void*>& list) {
+    return [&list, &oom](size_t bytes) -> void* {
+      void* p = nullptr;
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        oom = true;
+        return nullptr;
+      }
+      list.push_back(p);
+      return p;
+    };
+  };
+  // the full rows go to full_allocs, everything else to dyn_allocs
+  std::vector<void*> made;
+  DynIndexOut o;
+  const int r = build_dynamic_index(in, o, alloc_into(made), c->stream);
+  if (r == 1) {
+    free_list(made);
+    c->nc = 0;
+    return fail(c, YASPS_E_ARG, "contact " + std::to_string(o.err_stencil) + ": " + contact_error(o.err_reason));
+  }
+  if (r != 0 || oom) {
+    free_list(made);
+    c->nc = 0;
+    return fail(c, YASPS_E_HIP, oom ? "out of device memory in the contact index build" : "device build of the contact index");
+  }
+  for (void* p : made) (o.f_rp == p || o.f_col == p || o.f_src == p ? c->full_allocs : c->dyn_allocs).push_back(p);
+  c->nc = nc;
+  for (int key = 0, j = 0; key < 32; ++key)
+    if (o.gcount[key]) {
+      c->groups.push_back(Group{key / 8, key % 8, j, j + o.gcount[key]});
+      j += o.gcount[key];
+    }
+  c->pd.nnzb = o.nnzb;
+  c->pd.rp = o.rp;
+  c->pd.ci = o.col;
+  c->hpat_d.nnzb = o.nnzb;
+  c->hpat_d_current = false;
+  c->dslot = o.slot;
+  c->nblk_d = o.nent;
+  c->ngrd_d = o.ngrad;
+  c->c_idx = o.sidx;
+  c->spos_c = o.spos;
+  c->gpos_c = o.gpos;
+  c->cptr_d = o.cptr;
+  c->gptr_d = o.gptr;
+  c->ddiag = o.ddiag;
+  if (c->prm.precision == YASPS_MIXED) {
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)o.nent));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)o.nnzb));
+  } else {
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)o.nent));
+    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)o.nnzb));
+  }
+  HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)o.ngrad));
+  HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
+  yasps_status s = ensure_parts(c);
+  if (s) return s;
+  // SpMV rows
+  c->f_rp = o.f_rp;
+  c->f_col = o.f_col;
+  c->f_src = o.f_src;
+  c->f_nnz = o.f_nnz;
+  for (int x = 0; x <= PCG_XCDS; ++x) c->f_xsplit[x] = o.xsplit[x];
+  if (c->prm.precision == YASPS_MIXED)
+    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
+  else
+    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals, 9 * (size_t)c->f_nnz));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return YASPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   if (!c || !C) return fail(c, YASPS_E_ARG, "NULL argument");
   if (C->n_contacts < 0 || (C->n_contacts > 0 && (!C->type || !C->idx)))
@@ -614,9 +734,12 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   c->groups.clear();
   c->pd = Part{};
   c->hpat_d = PartPattern{};
+  c->hpat_d_current = true;
+  c->dslot = nullptr;
   c->evaluated = false;
   c->assembled = false;
   const int nc = C->n_contacts;
+  if (c->prm.index_build == YASPS_INDEX_DEVICE) return set_contacts_device(c, C);
   std::vector<int32_t> ty(nc), idx((size_t)4 * nc);
   if (nc) {
     HIPCHK(c, hipMemcpy(ty.data(), C->type, (size_t)nc * 4, hipMemcpyDeviceToHost));
@@ -977,6 +1100,17 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
 
 yasps_status yasps_get_pattern(yasps_ctx* c, int32_t part, int32_t* row_ptr, int32_t* col_idx, int32_t* slot) {
   if (!c || (part != 0 && part != 1)) return fail(c, YASPS_E_ARG, "bad context or part");
+  if (part == 1 && !c->hpat_d_current) {  // device build: copy its pattern and slot map to the host once
+    PartPattern& d = c->hpat_d;
+    d.row_ptr.resize(c->n + 1);
+    d.col_idx.resize(d.nnzb);
+    d.slot.resize((size_t)10 * c->nc);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpy(d.row_ptr.data(), c->pd.rp, sizeof(int32_t) * (c->n + 1), hipMemcpyDeviceToHost));
+    if (d.nnzb) HIPCHK(c, hipMemcpy(d.col_idx.data(), c->pd.ci, sizeof(int32_t) * d.nnzb, hipMemcpyDeviceToHost));
+    if (c->nc) HIPCHK(c, hipMemcpy(d.slot.data(), c->dslot, sizeof(int32_t) * 10 * (size_t)c->nc, hipMemcpyDeviceToHost));
+    c->hpat_d_current = true;
+  }
   const PartPattern& h = part == 0 ? c->hpat_s : c->hpat_d;
   const int n = c->n;
   if (row_ptr) {

@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 namespace yasps {
 
 constexpr int EVAL_BLOCK = 128;   // threads per workgroup of the stencil kernels
+// XCDs of the part: the SpMV-shaped kernels give each a contiguous row range.
+constexpr int PCG_XCDS = 8;
 constexpr int RED_BLOCK = 256;    // threads per workgroup of reductions / vector kernels
 
 // Elastic (stable Neo-Hookean) tets.
@@ -123,6 +127,36 @@ struct ContactArgs {
 // three triangle vertices are free (a kernel with a reduced projection).
 constexpr int PT_TRIANGLE_FREE = 5;
 void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, hipStream_t s);
+// Device build of the dynamic part's index structures (dynindex.hip); every
+// array equals the host builder's (pattern.cpp).  Input arrays are device
+// memory; the static share of the full rows is the static-only FullPattern.
+struct DynIndexIn {
+  int n, nall, nc;
+  const int32_t* type;     // [nc]
+  const int32_t* idx;      // [4][nc], API order
+  int nnzb_s;              // static blocks (the dynamic ones follow them in src numbering)
+  const int32_t* sf_ptr;   // [n + 1] static share of each full row
+  const int32_t* sf_col;
+  const int32_t* sf_src;
+  long long sf_nnz;
+  int row_cost;            // per-row work in blocks for the XCD split
+};
+struct DynIndexOut {
+  int err_stencil = -1, err_reason = 0;  // first invalid stencil: 1 type, 2 vertex ids, 3 no free vertex
+  int gcount[32] = {};                    // stencils per group key type * 8 + nfree (or PT_TRIANGLE_FREE)
+  int nnzb = 0, nent = 0, ngrad = 0;      // dynamic blocks, staged block / gradient contributions
+  long long f_nnz = 0;
+  int xsplit[PCG_XCDS + 1] = {};
+  // device arrays from `alloc` (owned by the caller): storage-order vertex ids
+  // [4][nc], pattern rows [n + 1] / columns, slot map [nc][10] (API order),
+  // staging (spos [10][nc], gpos [4][nc], cptr [nnzb + 1], gptr [n + 1]),
+  // dynamic diagonal block per vertex [n], full rows (row_ptr [n + 1], col, src)
+  int32_t *sidx = nullptr, *rp = nullptr, *col = nullptr, *slot = nullptr, *spos = nullptr, *gpos = nullptr,
+          *cptr = nullptr, *gptr = nullptr, *ddiag = nullptr, *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
+};
+// 0 built, 1 invalid contacts (err_* set), -1 HIP failure.  Synchronises s.
+int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(size_t)>& alloc,
+                        hipStream_t s);
 // Line-search trial at y = x + alpha p: energy partials, feasibility (d > 0 and
 // PT/EE side kept) per workgroup.
 void launch_contact_energy(int type, const ContactArgs& a, const double* x0, double* bad_part,
@@ -167,8 +201,6 @@ void launch_max_norm3(int n, const double* p, double* part, int nblk, hipStream_
 void launch_dot(int n3, const double* a, const double* b, double* part, int nblk, hipStream_t s);
 
 // PCG.
-// XCDs of the part: the SpMV-shaped kernels give each a contiguous row range.
-constexpr int PCG_XCDS = 8;
 struct PcgMatrix {
   int n;
   // first row of each XCD's range (xsplit[PCG_XCDS] = n), chosen on the host so

@@ -24,6 +24,7 @@ FP64, MIXED = 0, 1
 F_SPACE, X_SPACE = 0, 1
 PROJECTED, EXACT = 0, 1
 SQLOG, IPC_CLASSIC = 0, 1
+INDEX_DEVICE, INDEX_HOST = 0, 1  # yasps_params.index_build
 
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
            "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
@@ -49,7 +50,7 @@ class Contacts(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("proj", C.c_int32), ("barrier", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("proj", C.c_int32), ("barrier", C.c_int32), ("index_build", C.c_int32)]
 
 
 class EvalInfo(C.Structure):
@@ -137,7 +138,8 @@ class Yasps:
     :mod:`paper_2605_23088_amd.synth`).  Problem arrays are uploaded once and
     kept alive here; positions are (n_free, 3) float64 CUDA tensors."""
 
-    def __init__(self, prob, device="cuda", precision=FP64, proj=F_SPACE, barrier=SQLOG, contacts=True):
+    def __init__(self, prob, device="cuda", precision=FP64, proj=F_SPACE, barrier=SQLOG, contacts=True,
+                 index_build=INDEX_DEVICE):
         if not torch.cuda.is_available():
             raise RuntimeError("the yasps library needs a ROCm GPU")
         self.dev = torch.device(device)
@@ -201,7 +203,7 @@ class Yasps:
             P.n_hinges = nh
             P.hinge_idx = _ptr(self._hin)
             P.hinge_rest = _ptr(self._hrest)
-        self.params = Params(precision, proj, barrier)
+        self.params = Params(precision, proj, barrier, index_build)
         self.stream = torch.cuda.current_stream(d)
         ctx = C.c_void_p()
         rc = L.yasps_create(C.byref(ctx), C.c_void_p(self.stream.cuda_stream), C.byref(P), C.byref(self.params))

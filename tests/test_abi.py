@@ -54,3 +54,17 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(yasps, "_lib", None)
     with pytest.raises(RuntimeError):
         yasps.lib()
+
+
+def _header_struct_fields(name):
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    return [re.findall(r"(\w+)\s*(?:\[[^\]]*\])?\s*$", d.strip())[0] for d in body.split(";") if d.strip()]
+
+
+@pytest.mark.parametrize("name,cls", [("yasps_params", "Params"), ("yasps_newton_params", "NewtonParams"),
+                                      ("yasps_eval_info", "EvalInfo")])
+def test_binding_structs_match_header(name, cls):
+    from paper_2605_23088_amd import yasps
+    fields = [f[0] for f in getattr(yasps, cls)._fields_]
+    assert fields == _header_struct_fields(name)

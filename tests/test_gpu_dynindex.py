@@ -1,0 +1,131 @@
+"""The contact index built on the GPU (the default) against the host build:
+pattern, slot map, and every result that depends on the staging order and
+the SpMV rows (assembled values, gradient, SpMV, PCG) bit for bit, on small
+volumetric and cloth scenes, the two cubes, an empty and an invalid contact
+set, and the full-size 40^3 block and cloth scene."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_23088_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def xdev(x):
+    return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+
+
+def pair(p, **kw):
+    from paper_2605_23088_amd.yasps import INDEX_DEVICE, INDEX_HOST, Yasps
+    return Yasps(p, index_build=INDEX_DEVICE, **kw), Yasps(p, index_build=INDEX_HOST, **kw)
+
+
+def same(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape and np.array_equal(a, b), (a.shape, b.shape)
+
+
+def compare(p, gd, gh, solve=True):
+    for part in (0, 1):
+        for u, v in zip(gd.pattern(part), gh.pattern(part)):
+            same(u, v)
+    x = xdev(p["x0"])
+    idd, ihh = gd.eval(x), gh.eval(x)
+    assert idd["energy"] == ihh["energy"] and idd["min_d"] == ihh["min_d"]
+    od, oh = gd.assemble(), gh.assemble()
+    assert set(od) == set(oh)
+    for key in ("values_s", "values_d", "grad"):
+        if key in od:  # no dynamic values without contacts
+            same(od[key].cpu().numpy(), oh[key].cpu().numpy())
+    rng = np.random.default_rng(3)
+    v = xdev(rng.standard_normal((p["n_free"], 3)))
+    same(gd.spmv(v).cpu().numpy(), gh.spmv(v).cpu().numpy())
+    if solve:
+        b = -od["grad"].contiguous()
+        xd, infd = gd.pcg(b, rtol=1e-8)
+        xh, infh = gh.pcg(b, rtol=1e-8)
+        assert infd["iters"] == infh["iters"]
+        same(xd.cpu().numpy(), xh.cpu().numpy())
+
+
+CASES = {
+    "two_cubes": lambda: synth.c1_two_cubes(),
+    "block_10x9x8": lambda: synth.small_block(seed=11, nx=10, ny=9, nz=8, n_pt=700, n_ee=400),
+    "cloth_small": lambda: synth.small_cloth(),
+    "static_corners": lambda: synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200, kappa=1e4, pin="corners"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_device_index_matches_host(name):
+    p = CASES[name]()
+    gd, gh = pair(p)
+    compare(p, gd, gh)
+    # a different contact set on the same contexts, then an empty one
+    q = dict(p)
+    q["ctype"], q["cidx"] = p["ctype"][1::2].copy(), p["cidx"][1::2].copy()
+    for g in (gd, gh):
+        g.set_contacts(q["ctype"], q["cidx"])
+    compare(q, gd, gh)
+    for g in (gd, gh):
+        g.set_contacts(p["ctype"][:0], p["cidx"][:0])
+    compare(dict(p, ctype=p["ctype"][:0], cidx=p["cidx"][:0]), gd, gh)
+    gd.close()
+    gh.close()
+
+
+def test_device_index_rejects_like_host():
+    from paper_2605_23088_amd.yasps import YaspsError
+    p = synth.small_block(seed=12, nx=6, ny=5, nz=4, n_pt=200, n_ee=200)
+    gd, gh = pair(p)
+    n_all = p["n_free"] + len(p["x_fixed"])
+    bad_sets = []
+    c = p["cidx"].copy()
+    c[17, 2] = c[17, 1]  # repeated vertex
+    bad_sets.append((p["ctype"].copy(), c))
+    t = p["ctype"].copy()
+    t[5] = 7  # unknown type
+    bad_sets.append((t, p["cidx"].copy()))
+    c = p["cidx"].copy()
+    c[40, 0] = n_all  # out of range
+    c[3, 3] = -1  # a PT stencil missing a vertex (earlier index: reported first)
+    bad_sets.append((p["ctype"].copy(), c))
+    c = p["cidx"].copy()
+    fixed_ids = np.arange(p["n_free"], p["n_free"] + 4)
+    c[9, :4] = fixed_ids if p["ctype"][9] in (0, 1) else c[9, :4]  # no free vertex
+    bad_sets.append((p["ctype"].copy(), c))
+    for ty, ci in bad_sets:
+        msgs = []
+        for g in (gd, gh):
+            with pytest.raises(YaspsError) as e:
+                g.set_contacts(ty, ci)
+            msgs.append((e.value.status, str(e.value)))
+        assert msgs[0] == msgs[1], msgs
+        # both contexts continue without contacts
+        compare(dict(p, ctype=p["ctype"][:0], cidx=p["cidx"][:0]), gd, gh, solve=False)
+    gd.close()
+    gh.close()
+
+
+@pytest.mark.parametrize("workload", ["block40", "cloth"])
+def test_device_index_full_size(workload):
+    import time
+    p = synth.c2_block() if workload == "block40" else synth.c3_cloth()
+    gd, gh = pair(p)
+    compare(p, gd, gh, solve=False)
+    times = {}
+    for name, g in (("device", gd), ("host", gh)):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.set_contacts(p["ctype"], p["cidx"])
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        times[name] = min(ts)
+    print(f"{workload}: set_contacts {len(p['ctype'])} stencils, device {1e3 * times['device']:.2f} ms, "
+          f"host {1e3 * times['host']:.2f} ms", flush=True)
+    compare(p, gd, gh, solve=False)
+    gd.close()
+    gh.close()
