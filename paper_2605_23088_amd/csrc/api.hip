@@ -134,6 +134,8 @@ struct yasps_ctx {
   PartPattern hpat_d;
   bool hpat_d_current = true;  // false after a device build until yasps_get_pattern downloads it
   int32_t* dslot = nullptr;    // device slot map of a device build [nc][10]
+  void* di_arena = nullptr;    // scratch of the device build, grown to the largest build seen
+  size_t di_arena_bytes = 0;
   Part pd;
   std::vector<Group> groups;
   int32_t *c_idx = nullptr, *spos_c = nullptr, *gpos_c = nullptr, *cptr_d = nullptr, *gptr_d = nullptr,
@@ -436,6 +438,7 @@ void yasps_destroy(yasps_ctx* ctx) {
   free_list(ctx->dyn_allocs);
   free_list(ctx->allocs);
   if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
+  if (ctx->di_arena) (void)hipFree(ctx->di_arena);
   delete ctx;
 }
 
@@ -643,6 +646,8 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   in.sf_src = c->sf_src;
   in.sf_nnz = c->sf_nnz;
   in.row_cost = XCD_ROW_COST;
+  in.arena = c->di_arena;
+  in.arena_bytes = c->di_arena_bytes;
   bool oom = false;
   auto alloc_into = [&](std::vector<void*>& list) {
     return [&list, &oom](size_t bytes) -> void* {
@@ -659,6 +664,13 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   std::vector<void*> made;
   DynIndexOut o;
   const int r = build_dynamic_index(in, o, alloc_into(made), c->stream);
+  if (o.arena_needed > c->di_arena_bytes) {  // the next build with this many contacts needs no allocation
+    if (c->di_arena) (void)hipFree(c->di_arena);
+    c->di_arena = nullptr;
+    c->di_arena_bytes = 0;
+    const size_t want = o.arena_needed + o.arena_needed / 4;
+    if (hipMalloc(&c->di_arena, want) == hipSuccess) c->di_arena_bytes = want;
+  }
   if (r == 1) {
     free_list(made);
     c->nc = 0;

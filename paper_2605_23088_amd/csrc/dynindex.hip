@@ -39,10 +39,8 @@ int bits_for(long long v) {  // bits needed for values 0 .. v
 // Per stencil (API order): the first failing check (1 unknown type, 2 bad or
 // repeated vertex ids, 3 no free vertex) folded into err = min((s << 2) | reason),
 // else the group key type * 8 + (free count, or PT_TRIANGLE_FREE).
-__global__ void classify_kernel(int nc, int n, int nall, const int32_t* __restrict__ type,
-                                const int32_t* __restrict__ idx, uint32_t* __restrict__ gkey, int* err,
-                                int* gcount) {
-  const int s = blockIdx.x * DI_BLOCK + threadIdx.x;
+YDEV void classify_one(int s, int nc, int n, int nall, const int32_t* __restrict__ type,
+                       const int32_t* __restrict__ idx, uint32_t* __restrict__ gkey, int* err, int* hist) {
   if (s >= nc) return;
   const int t = type[s];
   int reason = 0, nf = 0;
@@ -75,7 +73,20 @@ __global__ void classify_kernel(int nc, int n, int nall, const int32_t* __restri
   const bool pt_fixed_point = t == 0 && nf == 3 && idx[s] >= n;
   const uint32_t key = (uint32_t)(t * 8 + (pt_fixed_point ? PT_TRIANGLE_FREE : nf));
   gkey[s] = key;
-  atomicAdd(&gcount[key], 1);
+  atomicAdd(&hist[key], 1);
+}
+
+__global__ __launch_bounds__(DI_BLOCK) void classify_kernel(int nc, int n, int nall, const int32_t* __restrict__ type,
+                                                            const int32_t* __restrict__ idx,
+                                                            uint32_t* __restrict__ gkey, int* err, int* gcount) {
+  // group counts: a workgroup histogram in LDS, one global add per nonzero bin
+  __shared__ int hist[32];
+  if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int s = blockIdx.x * DI_BLOCK + threadIdx.x;
+  classify_one(s, nc, n, nall, type, idx, gkey, err, hist);
+  __syncthreads();
+  if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&gcount[threadIdx.x], hist[threadIdx.x]);
 }
 
 // Per stencil in storage order j (s = order[j]): its vertex ids in storage
@@ -158,13 +169,27 @@ __global__ void blocks_kernel(int ne, int nc, const uint64_t* __restrict__ key, 
 }
 
 // Gradient entries (sorted by vertex, i < ng): staged positions, per-vertex counts.
-__global__ void grads_kernel(int ng, int nc, const uint32_t* __restrict__ key, const int32_t* __restrict__ val,
-                             int32_t* __restrict__ gpos, int32_t* __restrict__ vcnt) {
+__global__ void grads_kernel(int ng, int nc, const int32_t* __restrict__ val, int32_t* __restrict__ gpos) {
   const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i >= ng) return;
   const int ja = val[i], j = ja / 4, a = ja - 4 * (ja / 4);
   gpos[(size_t)a * nc + j] = i;
-  atomicAdd(&vcnt[key[i]], 1);
+}
+
+// gptr[v] = first sorted gradient entry of vertex v (v = 0 .. n; entries of
+// vertex v are [gptr[v], gptr[v + 1]))
+__global__ void gptr_kernel(int n, int ng, const uint32_t* __restrict__ key, int32_t* __restrict__ gptr) {
+  const int v = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (v > n) return;
+  int lo = 0, hi = ng;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (key[mid] < (uint32_t)v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  gptr[v] = lo;
 }
 
 // Off-diagonal dynamic blocks keyed by (column, row) for the transposed
@@ -246,15 +271,25 @@ __global__ void iota_kernel(int m, int32_t* __restrict__ p) {
 
 int grid_of(long long m) { return (int)std::max<long long>(1, (m + DI_BLOCK - 1) / DI_BLOCK); }
 
-// Owns the temporaries of one build; frees them when done.
+// Temporaries of one build, carved from the caller's arena while it lasts
+// (256-byte aligned), else allocated and freed when done; `used` is the arena
+// size the whole build needs.
 struct Temp {
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   std::vector<void*> ptrs;
   hipError_t err = hipSuccess;
   template <class T>
   T* get(size_t count) {
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
     void* p = nullptr;
-    if (err == hipSuccess) err = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
-    if (p) ptrs.push_back(p);
+    if (used + bytes <= cap) {
+      p = arena + used;
+    } else if (err == hipSuccess) {
+      err = hipMalloc(&p, bytes);
+      if (p) ptrs.push_back(p);
+    }
+    used += bytes;
     return static_cast<T*>(p);
   }
   ~Temp() {
@@ -307,7 +342,14 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
                         hipStream_t s) {
   const int n = in.n, nc = in.nc;
   Temp tmp;
+  tmp.arena = static_cast<char*>(in.arena);
+  tmp.cap = in.arena_bytes;
   out = DynIndexOut{};
+  struct Need {  // reports the arena size the build needed, on every return path
+    Temp& t;
+    DynIndexOut& o;
+    ~Need() { o.arena_needed = t.used; }
+  } need{tmp, out};
   // small device scalars: err, counts[2] (block / gradient entries), offdiag, gcount[32], xsplit[9]
   int* scal = tmp.get<int>(48);
   DI_CHECK(tmp.err);
@@ -391,10 +433,8 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   out.sidx = sidx;
   if (!out.rp || !out.col || !out.cptr || !out.slot || !out.spos || !out.gpos || !out.gptr || !out.ddiag) return -1;
   int32_t* rowcnt = tmp.get<int32_t>(n);
-  int32_t* vcnt = tmp.get<int32_t>(n);
   DI_CHECK(tmp.err);
   DI_CHECK(hipMemsetAsync(rowcnt, 0, sizeof(int32_t) * std::max(n, 1), s));
-  DI_CHECK(hipMemsetAsync(vcnt, 0, sizeof(int32_t) * std::max(n, 1), s));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.slot);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.spos);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(4ll * nc)), dim3(DI_BLOCK), 0, s, 4ll * nc, -1, out.gpos);
@@ -404,8 +444,8 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
                        order, out.spos, out.col, out.cptr, out.slot, rowcnt, out.ddiag, offdiag);
   DI_CHECK(hipMemcpyAsync(out.cptr + nnzb, &ne, sizeof(int), hipMemcpyHostToDevice, s));
   DI_CHECK(prefix(tmp, rowcnt, out.rp, n, s));
-  if (ng) hipLaunchKernelGGL(grads_kernel, dim3(grid_of(ng)), dim3(DI_BLOCK), 0, s, ng, nc, gkey_s, gval_s, out.gpos, vcnt);
-  DI_CHECK(prefix(tmp, vcnt, out.gptr, n, s));
+  if (ng) hipLaunchKernelGGL(grads_kernel, dim3(grid_of(ng)), dim3(DI_BLOCK), 0, s, ng, nc, gval_s, out.gpos);
+  hipLaunchKernelGGL(gptr_kernel, dim3(grid_of(n + 1)), dim3(DI_BLOCK), 0, s, n, ng, gkey_s, out.gptr);
 
   // 4. transposed dynamic blocks (sorted by column, then row) and the full rows
   uint64_t* tkey = tmp.get<uint64_t>(nnzb);

@@ -140,6 +140,8 @@ struct DynIndexIn {
   const int32_t* sf_src;
   long long sf_nnz;
   int row_cost;            // per-row work in blocks for the XCD split
+  void* arena;             // device scratch for the temporaries (may be null)
+  size_t arena_bytes;
 };
 struct DynIndexOut {
   int err_stencil = -1, err_reason = 0;  // first invalid stencil: 1 type, 2 vertex ids, 3 no free vertex
@@ -147,6 +149,7 @@ struct DynIndexOut {
   int nnzb = 0, nent = 0, ngrad = 0;      // dynamic blocks, staged block / gradient contributions
   long long f_nnz = 0;
   int xsplit[PCG_XCDS + 1] = {};
+  size_t arena_needed = 0;                // scratch the temporaries took (to size the next arena)
   // device arrays from `alloc` (owned by the caller): storage-order vertex ids
   // [4][nc], pattern rows [n + 1] / columns, slot map [nc][10] (API order),
   // staging (spos [10][nc], gpos [4][nc], cptr [nnzb + 1], gptr [n + 1]),

@@ -232,17 +232,24 @@ class Yasps:
 
     # ------------------------------------------------------------ calls
     def set_contacts(self, ctype, cidx):
+        """Host arrays: types (n_c) and vertex ids (n_c, 4)."""
         ctype = np.asarray(ctype, np.int32)
         cidx = np.asarray(cidx, np.int32).reshape(-1, 4)
         t = torch.as_tensor(ctype, device=self.dev).contiguous()
         i = torch.as_tensor(np.ascontiguousarray(cidx.T), device=self.dev).contiguous()
-        Cs = Contacts(int(ctype.shape[0]), _ptr(t), _ptr(i))
+        self.set_contacts_device(t, i)
+
+    def set_contacts_device(self, t, i):
+        """Device int32 tensors in the library's layout: types [n_c], ids [4][n_c]."""
+        assert t.dtype == torch.int32 and i.dtype == torch.int32 and i.shape == (4, t.shape[0])
+        t, i = t.contiguous(), i.contiguous()  # kept alive through the call
+        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i))
         try:
             self._check(lib().yasps_set_contacts(self.ctx, C.byref(Cs)))
         except YaspsError:
             self.nc = 0  # a rejected set leaves the context without contacts
             raise
-        self.nc = int(ctype.shape[0])
+        self.nc = int(t.shape[0])
 
     def eval(self, x, exact=False, allow=()):
         info = EvalInfo()

