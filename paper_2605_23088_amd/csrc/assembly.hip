@@ -15,11 +15,77 @@ namespace yasps {
 
 namespace {
 
-// A group of G lanes per segment: lane l sums contributions l, l + G, ... of
-// its segment (W values each, contiguous, so a group reads G consecutive
-// contributions per step), then the group combines its partial sums with a
-// fixed butterfly and lane 0 writes the W results.  Two ranges (static and
-// dynamic parts of the gradient) may be chained per segment.
+// Short segments (the static blocks: bounded valence): a workgroup takes SPW
+// consecutive segments, whose contributions are contiguous in the staging
+// array.  It copies them to LDS in rounds of CAP contributions with plain
+// coalesced loads (every thread issues its share of a round before any is
+// stored), and thread (segment, component) then adds its segment's values in
+// contribution order.  Every output is a sequential sum over its segment, so
+// the result does not depend on SPW or CAP.
+template <class T, int W, int SPW, int CAP>
+__global__ __launch_bounds__(RED_BLOCK) void segsum_lds_kernel(int nseg, const int32_t* __restrict__ ptr,
+                                                               const T* __restrict__ stg, T* __restrict__ out) {
+  static_assert(SPW * W <= RED_BLOCK, "one output per thread");
+  constexpr int PER = (CAP * W + RED_BLOCK - 1) / RED_BLOCK;
+  __shared__ T buf[CAP * W];
+  const int t = threadIdx.x;
+  const int s_lo = blockIdx.x * SPW;
+  const int s_hi = min(s_lo + SPW, nseg);
+  const int seg = s_lo + t / W, comp = t - W * (t / W);
+  const bool mine = t < SPW * W && seg < s_hi;
+  const int c0 = ptr[s_lo], c1 = ptr[s_hi];
+  int j = mine ? ptr[seg] : 0;
+  const int je = mine ? ptr[seg + 1] : 0;
+  double acc = 0.0;
+  for (int base = c0; base < c1; base += CAP) {
+    const int m = W * min(CAP, c1 - base);
+    const T* src = stg + (size_t)W * base;
+    T v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = t + i * RED_BLOCK;
+      v[i] = q < m ? src[q] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = t + i * RED_BLOCK;
+      if (q < m) buf[q] = v[i];
+    }
+    __syncthreads();
+    const int lim = min(je, base + CAP);
+    for (; j < lim; ++j) acc += double(buf[W * (j - base) + comp]);
+    __syncthreads();  // buf is refilled by the next round
+  }
+  if (mine) out[(size_t)W * seg + comp] = T(acc);
+}
+
+// acc += contributions j, j + G, ... below e, in that order; four are loaded
+// before any is added (more loads in flight on long segments).
+template <class T, int W, int G>
+YDEV void lane_sum(int j, int e, const T* __restrict__ stg, double acc[W]) {
+  for (; j + 3 * G < e; j += 4 * G) {
+    T v[4][W];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < W; ++c) v[u][c] = stg[(size_t)W * (j + u * G) + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] += double(v[u][c]);
+  }
+  for (; j < e; j += G) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] += double(stg[(size_t)W * j + c]);
+  }
+}
+
+// Long or skewed segments (contacts, gradient rows): a group of G lanes per
+// segment: lane l sums contributions l, l + G, ... of its segment (W values
+// each, contiguous, so a group reads G consecutive contributions per step),
+// then the group combines its partial sums with a fixed butterfly and lane 0
+// writes the W results.  Two ranges (static and dynamic parts of the
+// gradient) may be chained per segment.
 template <class T, int W, int G>
 __global__ __launch_bounds__(RED_BLOCK) void segsum_kernel(int nseg, const int32_t* __restrict__ p1,
                                                            const T* __restrict__ s1, const int32_t* __restrict__ p2,
@@ -30,18 +96,8 @@ __global__ __launch_bounds__(RED_BLOCK) void segsum_kernel(int nseg, const int32
 #pragma unroll
   for (int c = 0; c < W; ++c) acc[c] = 0.0;
   if (seg < nseg) {
-    for (int j = p1[seg] + lane, e = p1[seg + 1]; j < e; j += G) {
-      const T* src = s1 + (size_t)W * j;
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc[c] += double(src[c]);
-    }
-    if (p2) {
-      for (int j = p2[seg] + lane, e = p2[seg + 1]; j < e; j += G) {
-        const T* src = s2 + (size_t)W * j;
-#pragma unroll
-        for (int c = 0; c < W; ++c) acc[c] += double(src[c]);
-      }
-    }
+    lane_sum<T, W, G>(p1[seg] + lane, p1[seg + 1], s1, acc);
+    if (p2) lane_sum<T, W, G>(p2[seg] + lane, p2[seg + 1], s2, acc);
   }
 #pragma unroll
   for (int m = G / 2; m > 0; m >>= 1) {
@@ -74,6 +130,22 @@ void launch_segsum(int nseg, const int32_t* p1, const T* s1, const int32_t* p2, 
     case 16: hipLaunchKernelGGL((segsum_kernel<T, W, 16>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
     case 32: hipLaunchKernelGGL((segsum_kernel<T, W, 32>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
     default: hipLaunchKernelGGL((segsum_kernel<T, W, 64>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+  }
+}
+
+// Slots of at most this mean number of contributions go to the LDS kernel.
+constexpr double LDS_MEAN_MAX = 24.0;
+constexpr int BLK_SPW = RED_BLOCK / 9, BLK_CAP = 256;  // 28 slots, 18 KiB (float64) per round
+
+template <class T>
+void launch_block_sums(int nslots, long long ncontrib, const int32_t* cptr, const T* staged, T* out,
+                       hipStream_t s) {
+  if (nslots == 0) return;
+  if (ncontrib <= LDS_MEAN_MAX * nslots) {
+    hipLaunchKernelGGL((segsum_lds_kernel<T, 9, BLK_SPW, BLK_CAP>), dim3((nslots + BLK_SPW - 1) / BLK_SPW),
+                       dim3(RED_BLOCK), 0, s, nslots, cptr, staged, out);
+  } else {
+    launch_segsum<T, 9>(nslots, cptr, staged, nullptr, nullptr, out, group_for(ncontrib, nslots), s);
   }
 }
 
@@ -225,12 +297,12 @@ void launch_dot(int n3, const double* a, const double* b, double* part, int nblk
 
 void launch_segsum_blocks(int nslots, long long ncontrib, const int32_t* cptr, const double* staged, double* out,
                           hipStream_t s) {
-  launch_segsum<double, 9>(nslots, cptr, staged, nullptr, nullptr, out, group_for(ncontrib, nslots), s);
+  launch_block_sums<double>(nslots, ncontrib, cptr, staged, out, s);
 }
 
 void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cptr, const float* staged, float* out,
                               hipStream_t s) {
-  launch_segsum<float, 9>(nslots, cptr, staged, nullptr, nullptr, out, group_for(ncontrib, nslots), s);
+  launch_block_sums<float>(nslots, ncontrib, cptr, staged, out, s);
 }
 
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
