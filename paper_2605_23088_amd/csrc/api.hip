@@ -149,12 +149,11 @@ struct yasps_ctx {
   double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
   float *stg_d32 = nullptr, *vals_d32 = nullptr;
 
-  // SpMV matrix: both triangles of both parts, structure of arrays (rebuilt
-  // with the contacts)
+  // SpMV rows: both triangles of both parts, each entry naming its stored
+  // upper block (rebuilt with the contacts; the values are vals_s / vals_d)
   std::vector<void*> full_allocs;
   int32_t *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
-  double* f_vals = nullptr;
-  float* f_vals32 = nullptr;
+  float* f_vals32 = nullptr;  // precision form: float32 values per entry, structure of arrays
   long long f_nnz = 0;
   int f_xsplit[PCG_XCDS + 1] = {};
 
@@ -167,7 +166,7 @@ struct yasps_ctx {
   int pcg_hint = 0;             // iterations of the last PCG solve (sizes the next one's launch batches)
   int nparts_alloc = 0;
   bool evaluated = false;
-  bool assembled = false;  // the SpMV matrix holds the values of the last assembly
+  bool assembled = false;  // the stored blocks hold the values of the last assembly
   Profiler prof;
 };
 
@@ -244,12 +243,8 @@ yasps_status build_full_matrix(yasps_ctx* c) {
   HIPCHK(c, upload(c->full_allocs, &c->f_rp, fp.row_ptr, c->stream));
   HIPCHK(c, upload(c->full_allocs, &c->f_col, fp.col, c->stream));
   HIPCHK(c, upload(c->full_allocs, &c->f_src, fp.src, c->stream));
-  c->f_vals = nullptr;
   c->f_vals32 = nullptr;
-  if (c->prm.precision == YASPS_MIXED)
-    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
-  else
-    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals, 9 * (size_t)c->f_nnz));
+  if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return YASPS_OK;
 }
@@ -401,10 +396,13 @@ PcgMatrix pcg_matrix(const yasps_ctx* c) {
   A.n = c->n;
   A.rp = c->f_rp;
   A.col = c->f_col;
-  A.v = c->f_vals;
-  A.v32 = c->f_vals32;
   A.nnz = c->f_nnz;
   A.minv = c->minv;
+  A.src = c->f_src;
+  A.nnzb_s = c->ps.nnzb;
+  A.vs = c->vals_s;
+  A.vd = c->nc ? c->vals_d : nullptr;
+  A.v32 = c->f_vals32;
   for (int x = 0; x <= PCG_XCDS; ++x) A.xsplit[x] = c->f_xsplit[x];
   return A;
 }
@@ -735,10 +733,7 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   c->f_src = o.f_src;
   c->f_nnz = o.f_nnz;
   for (int x = 0; x <= PCG_XCDS; ++x) c->f_xsplit[x] = o.xsplit[x];
-  if (c->prm.precision == YASPS_MIXED)
-    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
-  else
-    HIPCHK(c, dalloc(c->full_allocs, &c->f_vals, 9 * (size_t)c->f_nnz));
+  if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return YASPS_OK;
 }
@@ -756,7 +751,6 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   free_list(c->dyn_allocs);
   free_list(c->full_allocs);  // rebuilt below, or at the next assembly if this call fails
   c->f_rp = c->f_col = c->f_src = nullptr;
-  c->f_vals = nullptr;
   c->f_vals32 = nullptr;
   c->f_nnz = 0;
   c->groups.clear();
@@ -926,12 +920,9 @@ yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
                      dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
   launch_add_mass_shift(c->n, c->ps.rp, c->P.mass, shift, c->vals_s, mixed ? c->vals_s32 : nullptr, c->stream);
-  // both triangles, row by row, structure of arrays, for the SpMV
   if (mixed)
     launch_full_gather_f32(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s32, dyn ? c->vals_d32 : nullptr, c->f_vals32,
                            c->stream);
-  else
-    launch_full_gather(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s, dyn ? c->vals_d : nullptr, c->f_vals, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)

@@ -149,20 +149,20 @@ void launch_block_sums(int nslots, long long ncontrib, const int32_t* cptr, cons
   }
 }
 
-// vf[q * nnz + k] = entry q of the source block of k (transposed when src < 0):
-// one thread per block; each thread reads its source block's 72 (36) contiguous
-// bytes, and for every q the lanes write consecutive addresses.
-template <class T>
-__global__ __launch_bounds__(RED_BLOCK) void full_gather_kernel(long long nnz, const int32_t* __restrict__ src,
-                                                                int nnzb_s, const T* __restrict__ vs,
-                                                                const T* __restrict__ vd, T* __restrict__ vf) {
+// Precision form: vf[q * nnz + k] = entry q of the float32 source block of
+// full-row entry k (transposed when src < 0), one thread per entry; the lanes
+// write consecutive addresses for every q.
+__global__ __launch_bounds__(RED_BLOCK) void full_gather_f32_kernel(long long nnz, const int32_t* __restrict__ src,
+                                                                    int nnzb_s, const float* __restrict__ vs,
+                                                                    const float* __restrict__ vd,
+                                                                    float* __restrict__ vf) {
   const long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
   if (k >= nnz) return;
   const int32_t sk = src[k];
   const bool tr = sk < 0;
   const int b = tr ? -sk - 1 : sk;
-  const T* base = b < nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - nnzb_s);
-  T B[9];
+  const float* base = b < nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - nnzb_s);
+  float B[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) B[q] = base[q];
 #pragma unroll
@@ -310,18 +310,11 @@ void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const 
   launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s);
 }
 
-void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const double* vs, const double* vd,
-                        double* vf, hipStream_t s) {
-  if (nnz <= 0) return;
-  hipLaunchKernelGGL((full_gather_kernel<double>), dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)),
-                     dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
-}
-
 void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
                             float* vf, hipStream_t s) {
   if (nnz <= 0) return;
-  hipLaunchKernelGGL((full_gather_kernel<float>), dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)),
-                     dim3(RED_BLOCK), 0, s, nnz, src, nnzb_s, vs, vd, vf);
+  hipLaunchKernelGGL(full_gather_f32_kernel, dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)), dim3(RED_BLOCK),
+                     0, s, nnz, src, nnzb_s, vs, vd, vf);
 }
 
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,

@@ -173,10 +173,8 @@ void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cpt
                               float* out, hipStream_t s);
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
                         const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s);
-// Fills the SpMV matrix values vf[q * nnz + k] from the stored upper blocks
-// (src as in FullPattern: static blocks vs, then dynamic blocks vd).
-void launch_full_gather(long long nnz, const int32_t* src, int nnzb_s, const double* vs, const double* vd,
-                        double* vf, hipStream_t s);
+// Precision form: the float32 values of every full-row entry as structure of
+// arrays vf[q * nnz + k] (from the stored blocks through src, as in PcgMatrix).
 void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
                             float* vf, hipStream_t s);
 // vals_s[row_ptr_s[v]] += shift m_v I (the diagonal block is first in its static row).
@@ -209,14 +207,20 @@ struct PcgMatrix {
   // first row of each XCD's range (xsplit[PCG_XCDS] = n), chosen on the host so
   // that the ranges hold equal work (blocks plus a per-row overhead)
   int xsplit[PCG_XCDS + 1];
-  // both triangles of H_static + H_dynamic, row by row (see FullPattern),
-  // block values as structure of arrays [9][nnz] (entry q of block k at
-  // v[q * nnz + k]), float64 or, in the precision form, float32
+  // both triangles of H_static + H_dynamic, row by row (FullPattern): per
+  // entry its column and the stored upper block it is (src: static blocks
+  // first, then dynamic; negative = transposed).  Float64: the values are
+  // the assembled upper blocks themselves (9 contiguous values each), with no
+  // second copy.  Precision form: a float32 copy of every entry's values as
+  // structure of arrays, v32[q * nnz + k] (measured faster for 36-byte
+  // blocks than reading the stored ones).
   const int32_t* rp;
   const int32_t* col;
-  const double* v;
-  const float* v32;
+  const int32_t* src;
   long long nnz;
+  int nnzb_s;
+  const double *vs, *vd;
+  const float* v32;
   const double* minv;  // (n, 9)
 };
 struct PcgState;  // device-side scalars, defined in pcg.hip

@@ -66,23 +66,6 @@ struct PcgState {
 
 namespace {
 
-// (H x)_row for the row owned by this lane group: each lane takes every
-// SPMV_G-th block of the row (structure-of-arrays values, so the lanes of a
-// group read consecutive addresses); the sum is valid in every lane of the
-// group after the butterfly.
-template <class T, class X>
-YDEV void row_blocks(const PcgMatrix& A, const T* __restrict__ v, int row, int lane, const X* x, double acc[3]) {
-  const size_t nnz = (size_t)A.nnz;
-  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
-    const X* xc = x + 3 * (size_t)A.col[k];
-    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
-    const T* b = v + k;
-    acc[0] = fma(double(b[0]), x0, fma(double(b[nnz]), x1, fma(double(b[2 * nnz]), x2, acc[0])));
-    acc[1] = fma(double(b[3 * nnz]), x0, fma(double(b[4 * nnz]), x1, fma(double(b[5 * nnz]), x2, acc[1])));
-    acc[2] = fma(double(b[6 * nnz]), x0, fma(double(b[7 * nnz]), x1, fma(double(b[8 * nnz]), x2, acc[2])));
-  }
-}
-
 // The block rows of the SpMV-shaped kernels are split into NXCD contiguous
 // ranges of equal work (A.xsplit), one per XCD: workgroups are dispatched to
 // the XCDs round robin by index, so workgroup b runs on XCD b % NXCD and makes
@@ -103,14 +86,60 @@ YDEV RowRange xcd_rows(const PcgMatrix& A) {
   return r;
 }
 
+// (H x)_row for the row owned by this lane group: each lane takes every
+// SPMV_G-th entry of the full row, reads the stored upper block that the
+// entry names (9 contiguous values; transposed for an entry below the
+// diagonal, so every stored block is read by its own row and by its
+// column's row, the second time mostly from L2: the rows that share a block
+// are near each other and run on the same XCD) and the gathered x; the sum is
+// valid in every lane of the group after the butterfly.
 template <class X>
+YDEV void row_blocks(const PcgMatrix& A, const double* __restrict__ vs, const double* __restrict__ vd, int row,
+                     int lane, const X* x, double acc[3]) {
+  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
+    const int32_t sk = A.src[k];
+    const bool tr = sk < 0;
+    const int b = tr ? -sk - 1 : sk;
+    const double* p = b < A.nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - A.nnzb_s);
+    const X* xc = x + 3 * (size_t)A.col[k];
+    double B[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) B[q] = p[q];
+    const double b01 = tr ? B[3] : B[1], b02 = tr ? B[6] : B[2], b10 = tr ? B[1] : B[3];
+    const double b12 = tr ? B[7] : B[5], b20 = tr ? B[2] : B[6], b21 = tr ? B[5] : B[7];
+    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
+    acc[0] = fma(B[0], x0, fma(b01, x1, fma(b02, x2, acc[0])));
+    acc[1] = fma(b10, x0, fma(B[4], x1, fma(b12, x2, acc[1])));
+    acc[2] = fma(b20, x0, fma(b21, x1, fma(B[8], x2, acc[2])));
+  }
+}
+
+// Precision form: each lane takes every SPMV_G-th entry of the row from the
+// float32 structure-of-arrays copy (the lanes of a group read consecutive
+// addresses).
+template <class X>
+YDEV void row_blocks_f32(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
+  const size_t nnz = (size_t)A.nnz;
+  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
+    const X* xc = x + 3 * (size_t)A.col[k];
+    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
+    const float* b = A.v32 + k;
+    acc[0] = fma(double(b[0]), x0, fma(double(b[nnz]), x1, fma(double(b[2 * nnz]), x2, acc[0])));
+    acc[1] = fma(double(b[3 * nnz]), x0, fma(double(b[4 * nnz]), x1, fma(double(b[5 * nnz]), x2, acc[1])));
+    acc[2] = fma(double(b[6 * nnz]), x0, fma(double(b[7 * nnz]), x1, fma(double(b[8 * nnz]), x2, acc[2])));
+  }
+}
+
+// MF32: the precision form's float32 copy (a compile-time choice, so that
+// each kernel carries the registers of one layout only).
+template <bool MF32, class X>
 YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
   if (row < A.n) {
-    if (A.v32)
-      row_blocks(A, A.v32, row, lane, x, acc);
+    if constexpr (MF32)
+      row_blocks_f32(A, row, lane, x, acc);
     else
-      row_blocks(A, A.v, row, lane, x, acc);
+      row_blocks(A, A.vs, A.vd, row, lane, x, acc);
   }
 #pragma unroll
   for (int m = SPMV_G / 2; m > 0; m >>= 1) {
@@ -172,7 +201,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
 // replacing what the float32 recurrence carried.  Launched on the update
 // kernel's grid: its partials take the same [gamma | |r|^2] layout of gridDim.x
 // entries each that the next SpMV kernel sums.
-template <class VT>
+template <class VT, bool MF32 = sizeof(VT) == 4>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
                                                                 const double* __restrict__ x, Vecs<VT> V,
                                                                 PcgState* st) {
@@ -185,7 +214,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
     const int row = base + threadIdx.x / SPMV_G;
     const bool live = row < R.end;
     double acc[3];
-    spmv_row(A, live ? row : A.n, lane, x, acc);
+    spmv_row<MF32>(A, live ? row : A.n, lane, x, acc);
     if (lane == 0 && live) {
       double r[3], u[3];
 #pragma unroll
@@ -217,7 +246,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
 // this launch's w is not used: `done` stops the update kernel and every later
 // launch.  `nb_c` is the update kernel's grid (number of gamma / |r|^2
 // partials).  standalone: plain y = H x (no solver bookkeeping).
-template <class VT>
+template <class VT, bool MF32 = sizeof(VT) == 4>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
                                                              int standalone) {
   __shared__ double lds[RED_BLOCK];
@@ -239,7 +268,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
     const int row = base + threadIdx.x / SPMV_G;
     const bool live = row < R.end;
     double acc[3];
-    spmv_row(A, live ? row : A.n, lane, V.u, acc);
+    spmv_row<MF32>(A, live ? row : A.n, lane, V.u, acc);
     if (lane == 0 && live) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -423,7 +452,10 @@ void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hip
   carve(work, A.n, st, V);
   V.u = const_cast<double*>(x);
   V.w = y;
-  hipLaunchKernelGGL(pcg_spmv_kernel<double>, dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
+  if (A.v32)  // precision form: the float32 copy with float64 vectors
+    hipLaunchKernelGGL((pcg_spmv_kernel<double, true>), dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
+  else
+    hipLaunchKernelGGL((pcg_spmv_kernel<double, false>), dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
 }
 
 namespace {
