@@ -35,8 +35,8 @@ namespace yasps {
 
 // Launch shapes (compile-time; the defaults come from sweeps on the 40^3 and
 // 80x80x52 workloads).
-#ifndef YASPS_SPMV_G
-#define YASPS_SPMV_G 16
+#ifndef YASPS_SPMV_NARROW_MEAN
+#define YASPS_SPMV_NARROW_MEAN 20
 #endif
 #ifndef YASPS_MAX_WG_B
 #define YASPS_MAX_WG_B 4096
@@ -47,8 +47,11 @@ namespace yasps {
 #ifndef YASPS_UPD_VERTS
 #define YASPS_UPD_VERTS 128
 #endif
-constexpr int SPMV_G = YASPS_SPMV_G;            // lanes per block row
-constexpr int SPMV_ROWS = RED_BLOCK / SPMV_G;  // block rows per workgroup and pass
+// Lanes per block row of the SpMV-shaped kernels: 8 when the full rows hold at
+// most SPMV_NARROW_MEAN blocks on average (tet meshes: about 15), else 16
+// (cloth with contacts: about 29); block rows per workgroup and pass =
+// RED_BLOCK / lanes.
+constexpr int SPMV_NARROW_MEAN = YASPS_SPMV_NARROW_MEAN;
 constexpr int MAX_WG_B = YASPS_MAX_WG_B;        // workgroups of the SpMV kernel
 constexpr int MAX_WG_C = YASPS_MAX_WG_C;        // workgroups of the update kernel
 constexpr int UPD_VERTS = YASPS_UPD_VERTS;      // vertices per update-kernel workgroup pass
@@ -77,26 +80,28 @@ static_assert(MAX_WG_B % NXCD == 0 && MAX_WG_C % NXCD == 0, "partial-sum arrays 
 struct RowRange {
   int end, first, stride;
 };
+template <int G>
 YDEV RowRange xcd_rows(const PcgMatrix& A) {
+  constexpr int ROWS = RED_BLOCK / G;
   const int xcd = blockIdx.x % NXCD, j = blockIdx.x / NXCD, per = gridDim.x / NXCD;
   RowRange r;
   r.end = A.xsplit[xcd + 1];
-  r.first = A.xsplit[xcd] + j * SPMV_ROWS;
-  r.stride = per * SPMV_ROWS;
+  r.first = A.xsplit[xcd] + j * ROWS;
+  r.stride = per * ROWS;
   return r;
 }
 
 // (H x)_row for the row owned by this lane group: each lane takes every
-// SPMV_G-th entry of the full row, reads the stored upper block that the
+// G-th entry of the full row, reads the stored upper block that the
 // entry names (9 contiguous values; transposed for an entry below the
 // diagonal, so every stored block is read by its own row and by its
 // column's row, the second time mostly from L2: the rows that share a block
 // are near each other and run on the same XCD) and the gathered x; the sum is
 // valid in every lane of the group after the butterfly.
-template <class X>
+template <int G, class X>
 YDEV void row_blocks(const PcgMatrix& A, const double* __restrict__ vs, const double* __restrict__ vd, int row,
                      int lane, const X* x, double acc[3]) {
-  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
+  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += G) {
     const int32_t sk = A.src[k];
     const bool tr = sk < 0;
     const int b = tr ? -sk - 1 : sk;
@@ -114,13 +119,13 @@ YDEV void row_blocks(const PcgMatrix& A, const double* __restrict__ vs, const do
   }
 }
 
-// Precision form: each lane takes every SPMV_G-th entry of the row from the
+// Precision form: each lane takes every G-th entry of the row from the
 // float32 structure-of-arrays copy (the lanes of a group read consecutive
 // addresses).
-template <class X>
+template <int G, class X>
 YDEV void row_blocks_f32(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   const size_t nnz = (size_t)A.nnz;
-  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += SPMV_G) {
+  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += G) {
     const X* xc = x + 3 * (size_t)A.col[k];
     const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
     const float* b = A.v32 + k;
@@ -132,19 +137,19 @@ YDEV void row_blocks_f32(const PcgMatrix& A, int row, int lane, const X* x, doub
 
 // MF32: the precision form's float32 copy (a compile-time choice, so that
 // each kernel carries the registers of one layout only).
-template <bool MF32, class X>
+template <bool MF32, int G, class X>
 YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
   acc[0] = acc[1] = acc[2] = 0.0;
   if (row < A.n) {
     if constexpr (MF32)
-      row_blocks_f32(A, row, lane, x, acc);
+      row_blocks_f32<G>(A, row, lane, x, acc);
     else
-      row_blocks(A, A.vs, A.vd, row, lane, x, acc);
+      row_blocks<G>(A, A.vs, A.vd, row, lane, x, acc);
   }
 #pragma unroll
-  for (int m = SPMV_G / 2; m > 0; m >>= 1) {
+  for (int m = G / 2; m > 0; m >>= 1) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], m, SPMV_G);
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], m, G);
   }
 }
 
@@ -201,20 +206,20 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
 // replacing what the float32 recurrence carried.  Launched on the update
 // kernel's grid: its partials take the same [gamma | |r|^2] layout of gridDim.x
 // entries each that the next SpMV kernel sums.
-template <class VT, bool MF32 = sizeof(VT) == 4>
+template <class VT, int G, bool MF32 = sizeof(VT) == 4>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
                                                                 const double* __restrict__ x, Vecs<VT> V,
                                                                 PcgState* st) {
   if (st->done) return;
   __shared__ double lds[RED_BLOCK];
-  const int lane = threadIdx.x % SPMV_G;
+  const int lane = threadIdx.x % G;
   double g = 0.0, rr = 0.0;
-  const RowRange R = xcd_rows(A);
+  const RowRange R = xcd_rows<G>(A);
   for (int base = R.first; base < R.end; base += R.stride) {
-    const int row = base + threadIdx.x / SPMV_G;
+    const int row = base + threadIdx.x / G;
     const bool live = row < R.end;
     double acc[3];
-    spmv_row<MF32>(A, live ? row : A.n, lane, x, acc);
+    spmv_row<MF32, G>(A, live ? row : A.n, lane, x, acc);
     if (lane == 0 && live) {
       double r[3], u[3];
 #pragma unroll
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
 // this launch's w is not used: `done` stops the update kernel and every later
 // launch.  `nb_c` is the update kernel's grid (number of gamma / |r|^2
 // partials).  standalone: plain y = H x (no solver bookkeeping).
-template <class VT, bool MF32 = sizeof(VT) == 4>
+template <class VT, int G, bool MF32 = sizeof(VT) == 4>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
                                                              int standalone) {
   __shared__ double lds[RED_BLOCK];
@@ -261,14 +266,14 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
     gp[q] = in ? V.part_c[j] : 0.0;
     rp[q] = in ? V.part_c[nb_c + j] : 0.0;
   }
-  const int lane = threadIdx.x % SPMV_G;
+  const int lane = threadIdx.x % G;
   double d = 0.0;
-  const RowRange R = xcd_rows(A);
+  const RowRange R = xcd_rows<G>(A);
   for (int base = R.first; base < R.end; base += R.stride) {
-    const int row = base + threadIdx.x / SPMV_G;
+    const int row = base + threadIdx.x / G;
     const bool live = row < R.end;
     double acc[3];
-    spmv_row<MF32>(A, live ? row : A.n, lane, V.u, acc);
+    spmv_row<MF32, G>(A, live ? row : A.n, lane, V.u, acc);
     if (lane == 0 && live) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -288,13 +293,13 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<V
     ga += gp[q];
     ra += rp[q];
   }
-  const double G = block_sum<RED_BLOCK>(ga, lds);
+  const double gamma = block_sum<RED_BLOCK>(ga, lds);
   const double Rr = block_sum<RED_BLOCK>(ra, lds);
   if (threadIdx.x == 0) {
     const int i = st->iter;
     const double bb = i == 0 ? Rr : st->bb;
     const bool conv = Rr <= st->tol2 * bb;
-    st->gamma[i & 1] = G;
+    st->gamma[i & 1] = gamma;
     st->rr = Rr;
     st->iter_b = i;
     if (i == 0) st->bb = bb;
@@ -419,7 +424,11 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
 // Grids are multiples of NXCD (the SpMV-shaped kernels split rows per XCD; the
 // replacement kernel runs on the update kernel's grid).
 int round_xcd(int g) { return (g + NXCD - 1) / NXCD * NXCD; }
-int grid_b(int n) { return round_xcd(std::max(1, std::min((n + SPMV_ROWS - 1) / SPMV_ROWS, MAX_WG_B))); }
+bool narrow_rows(const PcgMatrix& A) { return A.nnz <= (long long)SPMV_NARROW_MEAN * A.n; }
+int grid_b(int n, int g) {
+  const int rows = RED_BLOCK / g;
+  return round_xcd(std::max(1, std::min((n + rows - 1) / rows, MAX_WG_B)));
+}
 int grid_c(int n) { return round_xcd(std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C))); }
 
 template <class VT>
@@ -452,10 +461,19 @@ void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hip
   carve(work, A.n, st, V);
   V.u = const_cast<double*>(x);
   V.w = y;
-  if (A.v32)  // precision form: the float32 copy with float64 vectors
-    hipLaunchKernelGGL((pcg_spmv_kernel<double, true>), dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
-  else
-    hipLaunchKernelGGL((pcg_spmv_kernel<double, false>), dim3(grid_b(A.n)), dim3(RED_BLOCK), 0, s, A, V, st, 1, 1);
+  // the precision form's float32 copy with float64 vectors, or the stored blocks
+  const dim3 b(RED_BLOCK);
+  if (narrow_rows(A)) {
+    if (A.v32)
+      hipLaunchKernelGGL((pcg_spmv_kernel<double, 8, true>), dim3(grid_b(A.n, 8)), b, 0, s, A, V, st, 1, 1);
+    else
+      hipLaunchKernelGGL((pcg_spmv_kernel<double, 8, false>), dim3(grid_b(A.n, 8)), b, 0, s, A, V, st, 1, 1);
+  } else {
+    if (A.v32)
+      hipLaunchKernelGGL((pcg_spmv_kernel<double, 16, true>), dim3(grid_b(A.n, 16)), b, 0, s, A, V, st, 1, 1);
+    else
+      hipLaunchKernelGGL((pcg_spmv_kernel<double, 16, false>), dim3(grid_b(A.n, 16)), b, 0, s, A, V, st, 1, 1);
+  }
 }
 
 namespace {
@@ -470,7 +488,7 @@ void timed_launch(LaunchTimer* tm, int cls, KERNEL kernel, int grid, int block, 
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, args...);
 }
 
-template <class VT>
+template <class VT, int G>
 int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, void* work, double* rel_out,
             int* status_out, hipStream_t s, LaunchTimer* tm, PcgState& hs, int* hint) {
   static_assert(sizeof(PcgState) <= 128, "the pinned polling buffer holds 128 bytes");
@@ -480,7 +498,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   PcgState* st;
   Vecs<VT> V;
   carve(work, n, st, V);
-  const int nb_b = grid_b(n), nb_c = grid_c(n);
+  const int nb_b = grid_b(n, G), nb_c = grid_c(n);
   PcgState h{};
   h.tol2 = rtol * rtol;
   h.max_iter = max_iter;
@@ -501,11 +519,11 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   constexpr int MAX_RESTARTS = 32;
   for (;;) {
     for (int k = 0; k < batch; ++k) {
-      timed_launch(tm, 5, pcg_spmv_kernel<VT>, nb_b, RED_BLOCK, s, A, V, st, nb_c, 0);
+      timed_launch(tm, 5, pcg_spmv_kernel<VT, G>, nb_b, RED_BLOCK, s, A, V, st, nb_c, 0);
       timed_launch(tm, 6, pcg_update_kernel<VT>, nb_c, UPD_BLOCK, s, A, x, V, st, nb_b);
       ++launched;
       if (MIXED && launched % REPLACE_EVERY == 0)
-        timed_launch(tm, 5, pcg_replace_kernel<VT>, nb_c, RED_BLOCK, s, A, b, x, V, st);
+        timed_launch(tm, 5, pcg_replace_kernel<VT, G>, nb_c, RED_BLOCK, s, A, b, x, V, st);
     }
     if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
@@ -519,7 +537,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       fix.restart_at = hs.iter_b;
       fix.iter = hs.iter_b;
       if (hipMemcpyAsync(st, &fix, sizeof(fix), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      hipLaunchKernelGGL((pcg_replace_kernel<VT, G>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
       launched = hs.iter_b;
       batch = 8;
       continue;
@@ -530,7 +548,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       verified_at = hs.iter_b;
       const int zero = 0;
       if (hipMemcpyAsync(&st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL(pcg_replace_kernel<VT>, dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      hipLaunchKernelGGL((pcg_replace_kernel<VT, G>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
       launched = hs.iter_b;
       batch = 8;
       continue;
@@ -548,8 +566,11 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, bool mixed, void* work,
               double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm, void* host_state, int* hint) {
   PcgState& hs = *static_cast<PcgState*>(host_state);
-  return mixed ? pcg_run<float>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
-               : pcg_run<double>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
+  if (narrow_rows(A))
+    return mixed ? pcg_run<float, 8>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
+                 : pcg_run<double, 8>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
+  return mixed ? pcg_run<float, 16>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
+               : pcg_run<double, 16>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
 }
 
 }  // namespace yasps
