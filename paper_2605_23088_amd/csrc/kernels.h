@@ -237,8 +237,8 @@ struct LaunchTimer {
 // host_state: pinned host memory of at least 128 bytes that the solver polls
 // its device scalars into.  hint: in, the iteration count the caller expects
 // (0 = unknown); out, the count of this solve.  It only sizes the batches of
-// launches between two polls (a full batch first, up to just below the hint),
-// never the arithmetic.
+// launches between two polls (a first batch just past the hint), never the
+// arithmetic.
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter,
               bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
               LaunchTimer* tm, void* host_state, int* hint);

@@ -509,10 +509,13 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
     return 0;
   }
   timed_launch(tm, 6, pcg_init_kernel<VT>, nb_c, RED_BLOCK, s, A, b, x, V, st);
-  // launches between polls: up to just below the expected count first, then 8
-  // at a time; without a hint 8, 16, 32, 64, 64, ...
+  // Launches between polls.  The launch that finds convergence after k
+  // iterations is the (k + 1)-th: with a hint k the first batch is k + 2
+  // launches (one poll when the count repeats or drops a little; launches past
+  // convergence exit at once, a few microseconds each, against tens for a
+  // poll), then batches of 8; without a hint 8, 16, 32, 64, 64, ...
   const bool hinted = hint && *hint > 16;
-  int batch = hinted ? *hint - 8 : 8;
+  int batch = hinted ? *hint + 2 : 8;
   long long launched = 0;  // (SpMV, update) pairs issued = iteration index while not done
   int verified_at = -1;
   int restarts = 0;
