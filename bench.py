@@ -381,8 +381,10 @@ def main():
         # PCG launches that do work: one SpMV and one update per iteration (the
         # last polling batch also issues launches that exit at once)
         cg_work = args.profiled_steps * float(np.mean([i["cg_iters"] for i in pinfos]))
+        # counter records are per workload: the block workload at another size has none
+        traffic_key = args.workload if args.workload != "block40" or args.cells == 40 else f"block{args.cells}cube"
         kernels, roofline = kernel_table(stats, algorithmic(prob, g, view), args.profiled_steps, cg_work,
-                                         args.workload, args.precision)
+                                         traffic_key, args.precision)
 
     # rebuild of the contact index (yasps_set_contacts), outside the timed step:
     # the device build of this context against a host-build context

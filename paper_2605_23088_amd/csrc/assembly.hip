@@ -236,7 +236,7 @@ struct FinalizeArgs {
 __global__ __launch_bounds__(RED_BLOCK) void finalize_kernel(FinalizeArgs f, const double* __restrict__ parts,
                                                              double* __restrict__ out) {
   __shared__ double lds[RED_BLOCK];
-  for (int k = 0; k < f.nseg; ++k) {
+  for (int k = blockIdx.x; k < f.nseg; k += gridDim.x) {  // one workgroup per segment
     const int kind = f.kind[k];
     double acc = kind == 0 ? 0.0 : (kind == 1 ? __builtin_inf() : -__builtin_inf());
     for (int j = f.off[k] + threadIdx.x; j < f.off[k + 1]; j += RED_BLOCK) {
@@ -347,7 +347,7 @@ void launch_finalize(int nseg, const int* off_host, const double* parts, const i
   f.nseg = nseg;
   for (int k = 0; k <= nseg; ++k) f.off[k] = off_host[k];
   for (int k = 0; k < nseg; ++k) f.kind[k] = kind_host[k];
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RED_BLOCK), 0, s, f, parts, out);
+  hipLaunchKernelGGL(finalize_kernel, dim3(std::max(nseg, 1)), dim3(RED_BLOCK), 0, s, f, parts, out);
 }
 
 void launch_axpy_to(int n3, const double* x, double alpha, const double* p, double* y, hipStream_t s) {
