@@ -154,6 +154,11 @@ struct yasps_ctx {
   std::vector<void*> full_allocs;
   int32_t *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
   float* f_vals32 = nullptr;  // precision form: float32 values per entry, structure of arrays
+  // float64: the stored blocks live in one array (static, dynamic, then the
+  // transposed copies of the far SpMV entries), reallocated with the rows
+  std::vector<void*> val_allocs;
+  int32_t* far_src = nullptr;
+  int nfar = 0, nnzb_sd = 0;
   long long f_nnz = 0;
   int f_xsplit[PCG_XCDS + 1] = {};
 
@@ -226,6 +231,38 @@ constexpr int XCD_ROW_COST = 2;
 
 // (Re)builds the SpMV matrix layout over the current parts; synchronises the
 // stream so the host pattern can go out of scope.
+// Float64: marks the far entries of the SpMV rows and (re)allocates the one
+// array of stored blocks and far copies that vals_s / vals_d point into (its
+// values are written by the next assembly).  The precision form keeps its
+// separate arrays.
+yasps_status split_far(yasps_ctx* c) {
+  c->far_src = nullptr;
+  c->nfar = 0;
+  const int nd = c->nc ? c->pd.nnzb : 0;
+  c->nnzb_sd = c->ps.nnzb + nd;
+  if (c->prm.precision == YASPS_MIXED) return YASPS_OK;
+  if (c->f_src) {
+    auto alloc = [c](size_t bytes) -> void* {
+      void* p = nullptr;
+      if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+      c->full_allocs.push_back(p);
+      return p;
+    };
+    if (split_far_entries(c->n, c->f_rp, c->f_col, c->f_src, c->ps.nnzb, c->nnzb_sd, FAR_ROWS, &c->far_src,
+                          &c->nfar, alloc, c->stream))
+      return fail(c, YASPS_E_HIP, "far entries of the SpMV rows");
+  }
+  std::vector<void*> fresh;
+  double* all = nullptr;
+  HIPCHK(c, dalloc(fresh, &all, 9 * ((size_t)c->nnzb_sd + c->nfar)));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_list(c->val_allocs);
+  c->val_allocs = fresh;
+  c->vals_s = all;
+  c->vals_d = nd ? all + 9 * (size_t)c->ps.nnzb : nullptr;
+  return YASPS_OK;
+}
+
 yasps_status build_full_matrix(yasps_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_list(c->full_allocs);
@@ -246,7 +283,7 @@ yasps_status build_full_matrix(yasps_ctx* c) {
   c->f_vals32 = nullptr;
   if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return YASPS_OK;
+  return split_far(c);
 }
 
 // Partials layout: [inertia | tets, membranes, hinge groups | contact energy |
@@ -399,9 +436,7 @@ PcgMatrix pcg_matrix(const yasps_ctx* c) {
   A.nnz = c->f_nnz;
   A.minv = c->minv;
   A.src = c->f_src;
-  A.nnzb_s = c->ps.nnzb;
-  A.vs = c->vals_s;
-  A.vd = c->nc ? c->vals_d : nullptr;
+  A.vals = c->vals_s;  // float64: the one array of stored blocks and far copies
   A.v32 = c->f_vals32;
   for (int x = 0; x <= PCG_XCDS; ++x) A.xsplit[x] = c->f_xsplit[x];
   return A;
@@ -439,6 +474,7 @@ void yasps_destroy(yasps_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   free_list(ctx->full_allocs);
   free_list(ctx->dyn_allocs);
+  free_list(ctx->val_allocs);
   free_list(ctx->allocs);
   if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
   if (ctx->di_arena) (void)hipFree(ctx->di_arena);
@@ -606,9 +642,8 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (prm.precision == YASPS_MIXED) {
     AL(c->stg_s32, 9 * (size_t)st.nblocks);
     AL(c->vals_s32, 9 * (size_t)c->hpat_s.nnzb);
-  } else {
+  } else {  // vals_s: allocated with the SpMV rows (split_far)
     AL(c->stg_s, 9 * (size_t)st.nblocks);
-    AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
   }
   AL(c->gstg_s, 3 * (size_t)st.ngrads);
   AL(c->grad, 3 * (size_t)c->n);
@@ -719,9 +754,8 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   if (c->prm.precision == YASPS_MIXED) {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)o.nent));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)o.nnzb));
-  } else {
+  } else {  // vals_d: allocated with the SpMV rows (split_far)
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)o.nent));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)o.nnzb));
   }
   HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)o.ngrad));
   HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
@@ -735,7 +769,7 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   for (int x = 0; x <= PCG_XCDS; ++x) c->f_xsplit[x] = o.xsplit[x];
   if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return YASPS_OK;
+  return split_far(c);
 }
 
 }  // namespace
@@ -752,6 +786,8 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   free_list(c->full_allocs);  // rebuilt below, or at the next assembly if this call fails
   c->f_rp = c->f_col = c->f_src = nullptr;
   c->f_vals32 = nullptr;
+  c->far_src = nullptr;
+  c->nfar = 0;
   c->f_nnz = 0;
   c->groups.clear();
   c->pd = Part{};
@@ -824,9 +860,8 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   if (c->prm.precision == YASPS_MIXED) {
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)st.nblocks));
     HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)c->hpat_d.nnzb));
-  } else {
+  } else {  // vals_d: allocated with the SpMV rows (split_far)
     HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d, 9 * (size_t)c->hpat_d.nnzb));
   }
   HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)st.ngrads));
   HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
@@ -923,6 +958,8 @@ yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   if (mixed)
     launch_full_gather_f32(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s32, dyn ? c->vals_d32 : nullptr, c->f_vals32,
                            c->stream);
+  else
+    launch_far_gather(c->nfar, c->far_src, c->nnzb_sd, c->vals_s, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)

@@ -171,6 +171,21 @@ __global__ __launch_bounds__(RED_BLOCK) void full_gather_f32_kernel(long long nn
     for (int j = 0; j < 3; ++j) vf[(size_t)(3 * i + j) * nnz + k] = tr ? B[3 * j + i] : B[3 * i + j];
 }
 
+__global__ __launch_bounds__(RED_BLOCK) void far_gather_kernel(int nfar, const int32_t* __restrict__ far_src,
+                                                               int nnzb_total, double* __restrict__ vals) {
+  const int j = blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (j >= nfar) return;
+  const double* B = vals + 9 * (size_t)far_src[j];
+  double v[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) v[q] = B[q];
+  double* D = vals + 9 * ((size_t)nnzb_total + j);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) D[3 * i + k] = v[3 * k + i];
+}
+
 template <class T>
 __global__ __launch_bounds__(RED_BLOCK) void mass_shift_kernel(int n, const int32_t* __restrict__ rp,
                                                                const double* __restrict__ mass, double shift,
@@ -315,6 +330,12 @@ void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const
   if (nnz <= 0) return;
   hipLaunchKernelGGL(full_gather_f32_kernel, dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)), dim3(RED_BLOCK),
                      0, s, nnz, src, nnzb_s, vs, vd, vf);
+}
+
+void launch_far_gather(int nfar, const int32_t* far_src, int nnzb_total, double* vals, hipStream_t s) {
+  if (nfar <= 0) return;
+  hipLaunchKernelGGL(far_gather_kernel, dim3((nfar + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s, nfar,
+                     far_src, nnzb_total, vals);
 }
 
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,

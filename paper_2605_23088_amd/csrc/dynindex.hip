@@ -330,6 +330,45 @@ hipError_t inclusive(Temp& tmp, const int32_t* in, int32_t* out, long long m, hi
   return rocprim::inclusive_scan(store, bytes, in, out, (size_t)m, rocprim::plus<int32_t>(), s);
 }
 
+// Far entries: per row, the entries below the diagonal whose stored block is
+// a contact block (at or above nnzb_s) more than far_rows rows back.
+YDEV bool far_entry(int32_t sk, int r, int c, int nnzb_s, int far_rows) {
+  return sk < 0 && -sk - 1 >= nnzb_s && r - c > far_rows;
+}
+
+__global__ __launch_bounds__(DI_BLOCK) void far_count_kernel(int n, int nnzb_s, int far_rows,
+                                                             const int32_t* __restrict__ f_rp,
+                                                             const int32_t* __restrict__ f_col,
+                                                             const int32_t* __restrict__ f_src,
+                                                             int32_t* __restrict__ cnt) {
+  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (r >= n) return;
+  int c = 0;
+  for (int k = f_rp[r]; k < f_rp[r + 1]; ++k) c += far_entry(f_src[k], r, f_col[k], nnzb_s, far_rows);
+  cnt[r] = c;
+}
+
+// Row by row, in entry order: far copy j gets the stored block, the entry
+// the code nnzb_total + j.
+__global__ __launch_bounds__(DI_BLOCK) void far_fill_kernel(int n, int nnzb_s, int far_rows, int nnzb_total,
+                                                            const int32_t* __restrict__ f_rp,
+                                                            const int32_t* __restrict__ f_col,
+                                                            int32_t* __restrict__ f_src,
+                                                            const int32_t* __restrict__ ptr,
+                                                            int32_t* __restrict__ far_src) {
+  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (r >= n) return;
+  int j = ptr[r];
+  for (int k = f_rp[r]; k < f_rp[r + 1]; ++k) {
+    const int32_t sk = f_src[k];
+    if (far_entry(sk, r, f_col[k], nnzb_s, far_rows)) {
+      far_src[j] = -sk - 1;
+      f_src[k] = nnzb_total + j;
+      ++j;
+    }
+  }
+}
+
 }  // namespace
 
 #define DI_CHECK(expr)                       \
@@ -337,6 +376,33 @@ hipError_t inclusive(Temp& tmp, const int32_t* in, int32_t* out, long long m, hi
     const hipError_t e_ = (expr);            \
     if (e_ != hipSuccess) return -1;         \
   } while (0)
+
+int split_far_entries(int n, const int32_t* f_rp, const int32_t* f_col, int32_t* f_src, int nnzb_s, int nnzb_total,
+                      int far_rows, int32_t** far_src, int* nfar, const std::function<void*(size_t)>& alloc,
+                      hipStream_t s) {
+  *far_src = nullptr;
+  *nfar = 0;
+  if (n == 0) return 0;
+  Temp tmp;
+  int32_t* cnt = tmp.get<int32_t>(n);
+  int32_t* ptr = tmp.get<int32_t>((size_t)n + 1);
+  if (tmp.err != hipSuccess) return -1;
+  hipLaunchKernelGGL(far_count_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, nnzb_s, far_rows, f_rp, f_col,
+                     f_src, cnt);
+  DI_CHECK(prefix(tmp, cnt, ptr, n, s));
+  int total = 0;
+  DI_CHECK(hipMemcpyAsync(&total, ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  DI_CHECK(hipStreamSynchronize(s));
+  if (total == 0) return 0;
+  *far_src = static_cast<int32_t*>(alloc((size_t)total * sizeof(int32_t)));
+  if (!*far_src) return -1;
+  hipLaunchKernelGGL(far_fill_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, nnzb_s, far_rows, nnzb_total, f_rp,
+                     f_col, f_src, ptr, *far_src);
+  DI_CHECK(hipGetLastError());
+  DI_CHECK(hipStreamSynchronize(s));  // the temporaries are freed on return
+  *nfar = total;
+  return 0;
+}
 
 int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(size_t)>& alloc,
                         hipStream_t s) {

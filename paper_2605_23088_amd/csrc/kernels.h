@@ -157,6 +157,25 @@ struct DynIndexOut {
   int32_t *sidx = nullptr, *rp = nullptr, *col = nullptr, *slot = nullptr, *spos = nullptr, *gpos = nullptr,
           *cptr = nullptr, *gptr = nullptr, *ddiag = nullptr, *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
 };
+// Far entries of the SpMV rows (float64): an entry below the diagonal of row r
+// whose stored block is a contact block (index >= nnzb_s) in row c < r -
+// far_rows (contact partners far apart in the vertex order: its second read
+// would miss L2, and a miss fetches whole cache lines for 72 bytes) reads a
+// transposed copy instead, kept after the stored blocks and refilled at every
+// assembly (launch_far_gather).  Mesh blocks are never copied: their second
+// read hits L2 often enough that a copy only adds bytes (measured).  Rewrites
+// those entries' src to nnzb_total + j and returns far_src[j] = the stored
+// block of copy j (nfar copies; memory from `alloc`).  0 done, -1 HIP
+// failure; synchronises s.
+#ifndef YASPS_FAR_ROWS
+#define YASPS_FAR_ROWS 8192
+#endif
+constexpr int FAR_ROWS = YASPS_FAR_ROWS;
+int split_far_entries(int n, const int32_t* f_rp, const int32_t* f_col, int32_t* f_src, int nnzb_s, int nnzb_total,
+                      int far_rows, int32_t** far_src, int* nfar, const std::function<void*(size_t)>& alloc,
+                      hipStream_t s);
+// vals[9 (nnzb_total + j) ...] = transpose of stored block far_src[j]
+void launch_far_gather(int nfar, const int32_t* far_src, int nnzb_total, double* vals, hipStream_t s);
 // 0 built, 1 invalid contacts (err_* set), -1 HIP failure.  Synchronises s.
 int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(size_t)>& alloc,
                         hipStream_t s);
@@ -211,15 +230,14 @@ struct PcgMatrix {
   // entry its column and the stored upper block it is (src: static blocks
   // first, then dynamic; negative = transposed).  Float64: the values are
   // the assembled upper blocks themselves (9 contiguous values each), with no
-  // second copy.  Precision form: a float32 copy of every entry's values as
+  // second copy but the far entries' transposed copies.  Precision form: a float32 copy of every entry's values as
   // structure of arrays, v32[q * nnz + k] (measured faster for 36-byte
   // blocks than reading the stored ones).
   const int32_t* rp;
   const int32_t* col;
   const int32_t* src;
   long long nnz;
-  int nnzb_s;
-  const double *vs, *vd;
+  const double* vals;  // float64: static blocks, dynamic blocks, far copies, contiguous
   const float* v32;
   const double* minv;  // (n, 9)
 };

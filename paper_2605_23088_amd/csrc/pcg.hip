@@ -92,20 +92,19 @@ YDEV RowRange xcd_rows(const PcgMatrix& A) {
 }
 
 // (H x)_row for the row owned by this lane group: each lane takes every
-// G-th entry of the full row, reads the stored upper block that the
-// entry names (9 contiguous values; transposed for an entry below the
-// diagonal, so every stored block is read by its own row and by its
-// column's row, the second time mostly from L2: the rows that share a block
-// are near each other and run on the same XCD) and the gathered x; the sum is
-// valid in every lane of the group after the butterfly.
+// G-th entry of the full row, reads the stored upper block that the entry
+// names (9 contiguous values; transposed for an entry below the diagonal, so
+// every stored block is read by its own row and by its column's row, the
+// second time from L2 when the rows are near each other; a far entry names
+// its transposed copy instead) and the gathered x; the sum is valid in every
+// lane of the group after the butterfly.
 template <int G, class X>
-YDEV void row_blocks(const PcgMatrix& A, const double* __restrict__ vs, const double* __restrict__ vd, int row,
-                     int lane, const X* x, double acc[3]) {
+YDEV void row_blocks(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
+  const double* __restrict__ vals = A.vals;
   for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += G) {
     const int32_t sk = A.src[k];
     const bool tr = sk < 0;
-    const int b = tr ? -sk - 1 : sk;
-    const double* p = b < A.nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - A.nnzb_s);
+    const double* p = vals + 9 * (size_t)(tr ? -sk - 1 : sk);
     const X* xc = x + 3 * (size_t)A.col[k];
     double B[9];
 #pragma unroll
@@ -144,7 +143,7 @@ YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc
     if constexpr (MF32)
       row_blocks_f32<G>(A, row, lane, x, acc);
     else
-      row_blocks<G>(A, A.vs, A.vd, row, lane, x, acc);
+      row_blocks<G>(A, row, lane, x, acc);
   }
 #pragma unroll
   for (int m = G / 2; m > 0; m >>= 1) {
