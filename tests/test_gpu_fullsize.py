@@ -103,6 +103,13 @@ def test_cloth_scene_sampled_parity_and_step():
     g = Yasps(p)
     out, view = sampled_rows_parity(p, g, p["x0"], 3)
     assert view.nnzb_static == 2_170_245
+    # every row of the SpMV (its contact blocks between sheets, far apart in
+    # the vertex order, are read below the diagonal from transposed copies)
+    # against the product with the assembled upper blocks on the host
+    H = gpu_csr(g, out)
+    v = np.random.default_rng(8).standard_normal((p["n_free"], 3))
+    y = g.spmv(xdev(v)).cpu().numpy().ravel()
+    assert np.all(np.abs(y - H @ v.ravel()) <= 1e-14 * (abs(H) @ np.abs(v.ravel())) + 1e-300)
     step_properties(p, g, out)
     g.close()
 
