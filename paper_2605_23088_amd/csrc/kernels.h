@@ -228,11 +228,12 @@ struct PcgMatrix {
   int xsplit[PCG_XCDS + 1];
   // both triangles of H_static + H_dynamic, row by row (FullPattern): per
   // entry its column and the stored upper block it is (src: static blocks
-  // first, then dynamic; negative = transposed).  Float64: the values are
-  // the assembled upper blocks themselves (9 contiguous values each), with no
-  // second copy but the far entries' transposed copies.  Precision form: a float32 copy of every entry's values as
-  // structure of arrays, v32[q * nnz + k] (measured faster for 36-byte
-  // blocks than reading the stored ones).
+  // first, then dynamic, then the far copies; negative = transposed).
+  // Float64: the values are the assembled upper blocks themselves (9
+  // contiguous values each) and, for the far entries only, transposed copies
+  // (split_far_entries).  Precision form: a float32 copy of every entry's
+  // values as structure of arrays, v32[q * nnz + k] (measured faster for
+  // 36-byte blocks than reading the stored ones).
   const int32_t* rp;
   const int32_t* col;
   const int32_t* src;
