@@ -254,8 +254,11 @@ yasps_status split_far(yasps_ctx* c) {
   }
   std::vector<void*> fresh;
   double* all = nullptr;
-  HIPCHK(c, dalloc(fresh, &all, 9 * ((size_t)c->nnzb_sd + c->nfar)));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (dalloc(fresh, &all, 9 * ((size_t)c->nnzb_sd + c->nfar)) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_list(fresh);
+    return fail(c, YASPS_E_HIP, "array of the stored blocks");
+  }
   free_list(c->val_allocs);
   c->val_allocs = fresh;
   c->vals_s = all;
