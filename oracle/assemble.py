@@ -83,6 +83,8 @@ class Oracle:
         return 0.5 * np.sum(self.mass[:, None] * dx * dx), self.mass[:, None] * dx
 
     def tets(self, x, hess=PROJECTED, mu=None, lam=None):
+        if not len(self.tet_idx):  # an empty sum
+            return torch.zeros(0), torch.zeros(0, 4, 3), torch.zeros(0, 12, 12)
         xt, free = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
         return local.snh_local(xt, self.dm_inv, self.mu if mu is None else mu,
                                self.lam if lam is None else lam, self.vol,
@@ -168,7 +170,8 @@ class Oracle:
         e_i, _ = self.inertia(x)
         xt, _ = local.gather_positions(local.T(x), self.x_fixed, self.tet_idx, self.n)
         h2 = float(self.p["h"]) ** 2
-        Et = h2 * float(torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol).sum())
+        Et = h2 * float(torch.vmap(en.snh_tet_energy)(xt, self.dm_inv, self.mu, self.lam, self.vol).sum()) \
+            if len(self.tet_idx) else 0.0
         Ef = Eh = 0.0
         if len(self.tri_idx):
             p = self.p

@@ -47,7 +47,8 @@ def initial_step(orc, x, p):
 def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
     """tie_rtol > 0: a trial whose energy differs from E0 by at most
     tie_rtol |E0| also counts as sufficient decrease (solves driven to the
-    rounding floor of E, where Armijo can no longer decide)."""
+    rounding floor of E, where Armijo can no longer decide); tie_rtol = 0 is
+    plain Armijo."""
     alpha = initial_step(orc, x, p)
     gp = float(g.ravel() @ p.ravel())
     if gp >= 0.0 and np.abs(p).max() > 0.0:
@@ -64,7 +65,7 @@ def line_search(orc, x, p, E0, g, max_halvings=40, tie_rtol=0.0):
             ok = bool((d > 0).all()) and bool((st == s0).all())
         if ok:
             E1 = orc.energy(xt)
-            if E1 <= E0 + 1e-4 * alpha * gp or abs(E1 - E0) <= tie_rtol * abs(E0):
+            if E1 <= E0 + 1e-4 * alpha * gp or (tie_rtol > 0 and abs(E1 - E0) <= tie_rtol * abs(E0)):
                 return alpha, xt, E1, trials
         alpha *= 0.5
     return 0.0, x, E0, trials

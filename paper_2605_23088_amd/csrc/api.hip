@@ -1144,7 +1144,8 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     ++trials;
     s = trial_energy(c, x, c->x_trial, &E, &feas);
     if (s) return s;
-    if (feas && (E <= ei.energy + p.armijo * alpha * gp || std::fabs(E - ei.energy) <= p.tie_rtol * std::fabs(ei.energy))) {
+    const bool tie = p.tie_rtol > 0.0 && std::fabs(E - ei.energy) <= p.tie_rtol * std::fabs(ei.energy);
+    if (feas && (E <= ei.energy + p.armijo * alpha * gp || tie)) {
       accepted = true;
       E1 = E;
       break;

@@ -228,11 +228,13 @@ def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, t
 
 
 def block_problem(nx, ny, nz, a, n_pt, n_ee, seed, E=1e5, nu=0.4, rho=1000.0, h=1e-2,
-                  kappa=1e4, dhat=1e-3, random_F=True, name="block"):
+                  kappa=1e4, dhat=1e-3, random_F=True, name="block", dlo=1e-4, dhi=1e-3):
     """A Kuhn block [0, nx a] x [0, ny a] x [0, nz a] at its exact grid positions,
     with seeded per-tet rest shapes (so x0 carries random deformation gradients
     with singular values in [0.7, 1.4]) and n_pt + n_ee contact stencils against
-    a fixed collider under the bottom face.  All block vertices are free."""
+    a fixed collider under the bottom face, squared distances U(dlo, dhi) (a
+    range reaching past dhat gives inactive stencils).  All block vertices are
+    free."""
     r_pos, r_con, _, _ = _streams(seed)
     X = grid_vertices(nx, ny, nz, a)
     tets = kuhn_tets(nx, ny, nz)
@@ -243,7 +245,7 @@ def block_problem(nx, ny, nz, a, n_pt, n_ee, seed, E=1e5, nu=0.4, rho=1000.0, h=
         dm_inv, vol = np.linalg.inv(Ds), np.abs(np.linalg.det(Ds)) / 6.0
     n = X.shape[0]
     mass = _lumped_mass(n, tets, vol, rho)
-    ctype, cidx, x_fixed = _collider_contacts(r_con, X, nx, ny, n_pt, n_ee, n)
+    ctype, cidx, x_fixed = _collider_contacts(r_con, X, nx, ny, n_pt, n_ee, n, dlo, dhi)
     mu, lam = lame(E, nu)
     x_tilde = X + h * h * GRAVITY
     return _pack(n, X, x_fixed, mass, x_tilde, tets, dm_inv, vol, ctype, cidx,

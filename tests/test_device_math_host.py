@@ -41,13 +41,13 @@ def stencils(t, n, seed):
     return x
 
 
-def run_host(L, t, K, exact, x, fl):
+def run_host(L, t, K, exact, x, fl, classic=0):
     e, d = C.c_double(), C.c_double()
     g = np.zeros(12)
     H = np.zeros(144)
     xs = np.ascontiguousarray(x, np.float64)
     f = np.ascontiguousarray(fl, np.int32)
-    rc = L.contact_host(t, K, int(exact), xs.ctypes.data, f.ctypes.data, KAPPA, DHAT, 0, C.byref(e), C.byref(d),
+    rc = L.contact_host(t, K, int(exact), xs.ctypes.data, f.ctypes.data, KAPPA, DHAT, classic, C.byref(e), C.byref(d),
                         g.ctypes.data, H.ctypes.data)
     assert rc == 0
     return e.value, d.value, g.reshape(4, 3), H.reshape(12, 12)
@@ -55,7 +55,8 @@ def run_host(L, t, K, exact, x, fl):
 
 @pytest.mark.parametrize("t", [0, 1, 2, 3])
 @pytest.mark.parametrize("exact", [False, True])
-def test_contact_math_matches_oracle(harness, t, exact):
+@pytest.mark.parametrize("classic", [0, 1])
+def test_contact_math_matches_oracle(harness, t, exact, classic):
     n = 6
     x = stencils(t, n, 100 + t)
     for K in range(1, NV[t] + 1):
@@ -64,12 +65,41 @@ def test_contact_math_matches_oracle(harness, t, exact):
             free = torch.zeros(n, 4, dtype=torch.bool)
             free[:, list(freeset)] = True
             Eo, go, Ho, do = local.contact_local(torch.tensor(x), torch.full((n,), t), free, KAPPA, DHAT,
-                                                 local.EXACT if exact else local.PROJECTED)
+                                                 local.EXACT if exact else local.PROJECTED,
+                                                 classic=bool(classic))
             for s in range(n):
-                e, d, g, H = run_host(harness, t, K, exact, x[s], fl)
+                e, d, g, H = run_host(harness, t, K, exact, x[s], fl, classic)
                 sc = np.abs(Ho[s].numpy()).max() + 1e-300
                 assert abs(d - float(do[s])) <= 1e-12 * float(do[s])
                 assert abs(e - float(Eo[s])) <= 1e-10 * abs(float(Eo[s])) + 1e-300
                 assert np.abs(g - go[s].numpy()).max() <= 1e-10 * np.abs(go[s].numpy()).max()
                 err = np.abs(H - Ho[s].numpy()).max()
                 assert err <= 1e-10 * sc, (t, K, freeset, exact, s, err, sc)
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3])
+@pytest.mark.parametrize("classic", [0, 1])
+def test_contact_math_inactive_beyond_dhat(harness, t, classic):
+    """Stencils at d >= dhat (the stencils above scaled by 3, and one placed
+    exactly at dhat): energy, gradient and Hessian exactly zero for every free
+    set, projected or not, and the distance still reported (the stencil keeps
+    its slots; its staged blocks are zeros)."""
+    n = 6
+    x = 3.0 * stencils(t, n, 200 + t)
+    xs = [x[s] for s in range(n)]
+    if t == 3:  # at the cutoff: the smallest separation whose square rounds to >= dhat
+        s = np.sqrt(DHAT)
+        while s * s < DHAT:
+            s = np.nextafter(s, np.inf)
+        xe = np.zeros((4, 3))
+        xe[1, 0] = s
+        xs.append(xe)
+    for xv in xs:
+        for K in range(1, NV[t] + 1):
+            for freeset in itertools.combinations(range(NV[t]), K):
+                fl = list(freeset) + [0] * (4 - K)
+                for exact in (False, True):
+                    e, d, g, H = run_host(harness, t, K, exact, xv, fl, classic)
+                    d_o = float(en.DIST[t](torch.tensor(xv)))
+                    assert d >= DHAT and abs(d - d_o) <= 1e-12 * d_o
+                    assert e == 0.0 and not g.any() and not H.any(), (t, K, freeset, exact, d)

@@ -34,8 +34,13 @@ def test_adjoint_matches_oracle():
     xt = torch.as_tensor(p["x_tgt"], dtype=torch.float64, device="cuda")
     L, g, xs = loss_and_grad(s, p["theta"], x0, xt)
     disp = np.abs(xs_o - p["x0"]).max()
-    assert np.abs(xs.cpu().numpy() - xs_o).max() <= 1e-8 * disp
-    assert np.abs(g - g_o).max() <= 1e-4 * np.abs(g_o).max()
+    err_x = np.abs(xs.cpu().numpy() - xs_o).max() / disp
+    err_g = np.abs(g - g_o).max() / np.abs(g_o).max()
+    print(f"adjoint vs oracle: |x* - x*_o| / disp = {err_x:.3e}, |g - g_o| / max|g_o| = {err_g:.3e}")
+    assert err_x <= 1e-8
+    # both equilibria meet the same gradient tolerance (not the same point) and the
+    # adjoint solve runs to rtol 1e-12: the gradient agrees far below 1e-6
+    assert err_g <= 1e-6
     # special case: the target at the equilibrium gives a zero gradient
     _, g0, _ = loss_and_grad(s, p["theta"], x0, xs)
     assert np.abs(g0).max() <= 1e-12 * np.abs(g_o).max()

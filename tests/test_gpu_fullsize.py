@@ -97,6 +97,36 @@ def test_block40_sampled_parity_and_step(block40):
     step_properties(p, g, out)
 
 
+def test_block40_full_pattern_and_newton_step_against_oracle(block40):
+    """The metric workload end to end against the oracle: every row of the
+    static and dynamic pattern and every slot of every stencil bit for bit, then
+    the whole Newton step (the oracle's eval, assembly, PCG and line search at
+    full size): PCG iterations within 2, the same alpha_0 and number of
+    halvings, E1 within 1e-8 |E0| and x1 within 1e-7 max |p_v|."""
+    from oracle import newton as onewton
+    p, g = block40
+    o = oasm.Oracle(p)
+    for part, ref in ((0, (o.rp_s, o.ci_s, o.slot_t)), (1, (o.rp_d, o.ci_d, o.slot_c))):
+        got = g.pattern(part)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), part
+    x1_o, info_o = onewton.newton_step(o, p["x0"], rtol=1e-10)
+    x = xdev(p["x0"])
+    ni = g.newton_step(x, rtol=1e-10)
+    assert ni["status"] == 0 and info_o["cg_status"] == "ok"
+    assert abs(ni["cg_iters"] - info_o["cg_iters"]) <= 2, (ni["cg_iters"], info_o["cg_iters"])
+    a0 = onewton.initial_step(o, p["x0"], info_o["p"])
+    assert ni["alpha0"] == pytest.approx(a0, rel=1e-8)
+    assert round(np.log2(ni["alpha0"] / ni["alpha"])) == round(np.log2(a0 / info_o["alpha"]))
+    mag = abs(info_o["E0"])
+    assert abs(ni["e0"] - info_o["E0"]) <= 1e-10 * mag
+    assert abs(ni["e1"] - info_o["E1"]) <= 1e-8 * mag
+    err = np.abs(x.cpu().numpy() - x1_o).max() / np.abs(info_o["p"]).max()
+    print(f"block40 Newton step: {ni['cg_iters']} vs {info_o['cg_iters']} PCG iterations, "
+          f"alpha {ni['alpha']:.6g}, |x1 - x1_oracle| / max|p| = {err:.3e}")
+    assert err <= 1e-7
+
+
 def test_cloth_scene_sampled_parity_and_step():
     from paper_2605_23088_amd.yasps import Yasps
     p = synth.c3_cloth()

@@ -18,9 +18,16 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
+# the classic IPC barrier, with the squared distances reaching 1.25 dhat so that
+# about a fifth of the stencils are inactive (exact zeros that keep their slots)
+CLASSIC = ("classic",)
+
+
 def case(name):
     if name == "C1":
         return synth.c1_two_cubes()
+    if name == "classic":
+        return synth.small_block(seed=14, nx=6, ny=5, nz=4, n_pt=300, n_ee=300, dhi=1.25e-3)
     if name == "block":
         return synth.small_block(seed=11, nx=5, ny=4, nz=3, n_pt=150, n_ee=150)
     if name == "block_mid":
@@ -30,18 +37,26 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["C1", "block", "block_mid", "static"]
+CASES = ["C1", "block", "block_mid", "static", "classic"]
 _cache = {}
 
 
 def setup(name):
     if name not in _cache:
-        from paper_2605_23088_amd.yasps import Yasps
+        from paper_2605_23088_amd.yasps import IPC_CLASSIC, SQLOG, Yasps
         p = case(name)
-        o = oasm.Oracle(p)
-        g = Yasps(p)
+        classic = name in CLASSIC
+        o = oasm.Oracle(p, classic=classic)
+        g = Yasps(p, barrier=IPC_CLASSIC if classic else SQLOG)
         _cache[name] = (p, o, g)
     return _cache[name]
+
+
+def test_classic_case_has_inactive_stencils():
+    p = case("classic")
+    d = oasm.Oracle(p).distances(p["x0"])
+    frac = float((d >= p["dhat"]).mean())
+    assert 0.15 <= frac <= 0.3, frac
 
 
 def xdev(p, x=None):

@@ -205,3 +205,100 @@ def test_rigid_motion_invariance_of_distances():
         for i in range(5):
             a, b = float(en.DIST[t](x[i])), float(en.DIST[t](y[i]))
             assert abs(a - b) <= 1e-11 * a
+
+
+# ---------------------------------------------------------------- classic IPC barrier
+# The alternative reading of the printed barrier (section "Eigendecomposition:
+# Automatic Optimization"): b(d) = -(d - dhat)^2 log(d / dhat), d squared.
+
+
+def b_classic_closed(d):
+    """b, b', b'' of -(d - dhat)^2 log(d/dhat) derived by hand: with u = d - dhat
+    and L = log(d/dhat), b' = -2uL - u^2/d and b'' = -2L - 4u/d + u^2/d^2."""
+    u, L = d - DHAT, np.log(d / DHAT)
+    return -u * u * L, -2 * u * L - u * u / d, -2 * L - 4 * u / d + u * u / (d * d)
+
+
+def _derivs(fun, dv):
+    d = torch.tensor(dv, requires_grad=True)
+    b = fun(d, DHAT, 1.0)
+    (g,) = torch.autograd.grad(b, d, create_graph=True)
+    (h,) = torch.autograd.grad(g, d)
+    return float(b.detach()), float(g.detach()), float(h)
+
+
+def test_classic_barrier_vanishes_to_second_order_at_dhat():
+    assert b_classic_closed(DHAT) == (0.0, 0.0, 0.0)
+    assert _derivs(en.barrier_ipc_classic, DHAT) == (0.0, 0.0, 0.0)
+    # near dhat it vanishes like (d - dhat)^3: b / u^3 -> -1 / dhat
+    for u in (1e-7, -1e-7, 1e-8):
+        b = float(en.barrier_ipc_classic(torch.tensor(DHAT + u), DHAT, 1.0))
+        assert abs(b / u ** 3 + 1.0 / DHAT) <= 1e-3 / DHAT
+
+
+def test_classic_barrier_closed_forms_monotone_convex():
+    for dv in np.geomspace(1e-7, 0.999 * DHAT, 40):
+        b, g, h = _derivs(en.barrier_ipc_classic, dv)
+        b0, b1, b2 = b_classic_closed(dv)
+        assert abs(b - b0) <= 1e-13 * abs(b0)
+        assert abs(g - b1) <= 1e-12 * abs(b1)
+        assert abs(h - b2) <= 1e-12 * abs(b2)
+        assert b0 > 0 and b1 < 0 and b2 > 0  # positive, decreasing and convex on (0, dhat)
+
+
+def test_classic_barrier_special_value_and_kappa_scaling():
+    # at d = dhat / e the log is -1 and b = (dhat (1 - 1/e))^2
+    d = DHAT / np.e
+    b = float(en.barrier_ipc_classic(torch.tensor(d), DHAT, 1.0))
+    assert abs(b - (DHAT * (1 - 1 / np.e)) ** 2) <= 1e-15 * b
+    assert float(en.barrier_ipc_classic(torch.tensor(d), DHAT, KAPPA)) == pytest.approx(KAPPA * b, rel=1e-15)
+
+
+def test_classic_barrier_finite_differences():
+    for dv in (2e-5, 3e-4, 9e-4):
+        eps = 1e-6 * dv
+        f = lambda t: float(en.barrier_ipc_classic(torch.tensor(t), DHAT, 1.0))
+        _, b1, b2 = b_classic_closed(dv)
+        assert abs((f(dv + eps) - f(dv - eps)) / (2 * eps) - b1) <= 1e-7 * abs(b1)
+        g = lambda t: b_classic_closed(t)[1]
+        assert abs((g(dv + eps) - g(dv - eps)) / (2 * eps) - b2) <= 1e-7 * abs(b2)
+
+
+def test_classic_pp_gradient_closed_form_and_cutoff():
+    n = 30
+    x = rand_stencils(n, 3, 41)
+    free = torch.zeros(n, 4, dtype=torch.bool)
+    free[:, :2] = True
+    E, g, H, d = local.contact_local(x, torch.full((n,), 3), free, KAPPA, DHAT, classic=True)
+    for i in range(n):
+        dv = float(d[i])
+        b0, b1, _ = b_classic_closed(dv)
+        assert float(E[i]) == pytest.approx(KAPPA * b0, rel=1e-12)
+        ref = KAPPA * b1 * 2 * (x[i, 1] - x[i, 0]).numpy()
+        assert np.allclose(g[i, 1].numpy(), ref, rtol=1e-12, atol=0)
+        assert np.allclose(g[i, 0].numpy(), -ref, rtol=1e-12, atol=0)
+    x[:, 1] = x[:, 0] + torch.tensor([0.0316227766016838 + 1e-4, 0.0, 0.0])
+    E, g, H, d = local.contact_local(x, torch.full((n,), 3), free, KAPPA, DHAT, classic=True)
+    assert bool((d >= DHAT).all())
+    assert float(E.abs().max()) == 0 and float(g.abs().max()) == 0 and float(H.abs().max()) == 0
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3])
+def test_classic_finite_differences_contact(t):
+    n = 12
+    x = rand_stencils(n, t, 50 + t)
+    ct = torch.full((n,), t)
+    nv = en.N_VERTS[t]
+    free = torch.zeros(n, 4, dtype=torch.bool)
+    free[:, :nv] = True
+    E, g, H, d = local.contact_local(x, ct, free, KAPPA, DHAT, local.EXACT, classic=True)
+    eps = 1e-7
+    for k in range(3 * nv):
+        dx = torch.zeros(n, 12)
+        dx[:, k] = eps
+        Ep, gp, _, _ = local.contact_local(x + dx.view(n, 4, 3), ct, free, KAPPA, DHAT, local.EXACT, classic=True)
+        Em, gm, _, _ = local.contact_local(x - dx.view(n, 4, 3), ct, free, KAPPA, DHAT, local.EXACT, classic=True)
+        gs = g.reshape(n, 12).abs().amax(1)
+        Hs = H.abs().amax((1, 2))
+        assert float((((Ep - Em) / (2 * eps) - g.reshape(n, 12)[:, k]).abs() / gs).max()) < 1e-5
+        assert float((((gp - gm).reshape(n, 12) / (2 * eps) - H[:, :, k]).abs() / Hs[:, None]).max()) < 1e-5
