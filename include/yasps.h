@@ -241,6 +241,22 @@ yasps_status yasps_assemble_bsr(yasps_ctx* ctx, yasps_bsr_view* view);
 yasps_status yasps_pcg(yasps_ctx* ctx, const double* b, double* x, double rtol, int32_t max_iter,
                        yasps_pcg_info* info);
 
+/* yasps_pcg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, bit for bit, with the solver's workspace (Krylov vectors,
+ * per-workgroup partials, device scalars) in one fixed array per GPU instead of
+ * the context's.  The call makes no hipMalloc / hipFree and no allocating
+ * library call.  The array is 16 MiB (NOALLOC_SCRATCH_BYTES), enough for
+ * systems of up to 139,464 free vertices; larger systems are rejected with
+ * YASPS_E_ARG before anything is launched.  Each GPU the library runs on
+ * holds its own array until the process ends; every call on one GPU shares
+ * it and leaves the last solve's contents there (no call reads what an earlier
+ * one left: the solver writes its state and vectors before reading them), so
+ * calls that overlap on one GPU (contexts on different streams or host
+ * threads) race.  Arguments, results and the other errors are yasps_pcg's. */
+yasps_status yasps_pcg_noalloc(yasps_ctx* ctx, const double* b, double* x, double rtol, int32_t max_iter,
+                               yasps_pcg_info* info);
+
 /* One Newton step on the current stencil set (projected local Hessians unless
  * prm->hessian = YASPS_EXACT): evaluate, assemble, solve H p = -g, then
  * backtrack from alpha0 = min(1, 0.4 min_s sqrt(d_s) /

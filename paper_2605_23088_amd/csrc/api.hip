@@ -532,6 +532,11 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
     return bail(fail(c, YASPS_E_HIP, "stream / event creation"));
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "hipGetDevice failed"));
+  {  // device address of the fixed workspace of yasps_pcg_noalloc (once per device; a
+     // failure here is reported by that call, which tries again)
+    void* sp = nullptr;
+    (void)noalloc_scratch(c->device, &sp);
+  }
   c->prof.stream = c->stream;
 
   // validate tets on the host
@@ -1047,17 +1052,18 @@ yasps_status yasps_assemble_bsr(yasps_ctx* c, yasps_bsr_view* view) {
   return check_flags(c, f);
 }
 
-yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter,
-                       yasps_pcg_info* info) {
-  if (!c || !b || !x) return fail(c, YASPS_E_ARG, "NULL argument");
-  if (!(rtol >= 0.0) || max_iter < 0) return fail(c, YASPS_E_ARG, "bad rtol / max_iter");
-  if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "pcg called before assembly");
-  HIPCHK(c, hipSetDevice(c->device));
+}  // extern "C"
+
+namespace {
+
+// yasps_pcg with the solver workspace `work` (the context's, or the fixed
+// per-GPU array of yasps_pcg_noalloc).
+yasps_status pcg_call(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter, yasps_pcg_info* info,
+                      void* work) {
   double rel = 0.0;
   int status = 0;
-  const int it =
-      pcg_solve(pcg_matrix(c), b, x, rtol, max_iter, c->prm.precision == YASPS_MIXED, c->pcg_work, &rel, &status,
-                c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
+  const int it = pcg_solve(pcg_matrix(c), b, x, rtol, max_iter, c->prm.precision == YASPS_MIXED, work, &rel,
+                           &status, c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipGetLastError());
@@ -1069,6 +1075,40 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
   if (status == YASPS_E_NOCONV) return fail(c, YASPS_E_NOCONV, "PCG reached max_iter");
   if (status == YASPS_E_BREAKDOWN) return fail(c, YASPS_E_BREAKDOWN, "PCG breakdown: p^T H p <= 0");
   return YASPS_OK;
+}
+
+yasps_status pcg_args(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter) {
+  if (!c || !b || !x) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (!(rtol >= 0.0) || max_iter < 0) return fail(c, YASPS_E_ARG, "bad rtol / max_iter");
+  if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "pcg called before assembly");
+  return YASPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter,
+                       yasps_pcg_info* info) {
+  const yasps_status s = pcg_args(c, b, x, rtol, max_iter);
+  if (s) return s;
+  HIPCHK(c, hipSetDevice(c->device));
+  return pcg_call(c, b, x, rtol, max_iter, info, c->pcg_work);
+}
+
+yasps_status yasps_pcg_noalloc(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter,
+                               yasps_pcg_info* info) {
+  const yasps_status s = pcg_args(c, b, x, rtol, max_iter);
+  if (s) return s;
+  const size_t need = pcg_workspace_bytes(c->n);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(c, YASPS_E_ARG, "yasps_pcg_noalloc: " + std::to_string(c->n) + " free vertices need " +
+                                    std::to_string(need) + " bytes of solver workspace, more than the fixed " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte array (use yasps_pcg)");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* work = nullptr;
+  HIPCHK(c, noalloc_scratch(c->device, &work));
+  return pcg_call(c, b, x, rtol, max_iter, info, work);
 }
 
 yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_params* prm, yasps_newton_info* info) {

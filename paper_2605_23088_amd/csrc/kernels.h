@@ -262,6 +262,12 @@ int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int m
               bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
               LaunchTimer* tm, void* host_state, int* hint);
 size_t pcg_workspace_bytes(int n);
+// Size of the fixed per-GPU workspace array of the non-allocating solve
+// (pcg_workspace_bytes(n) <= this for n <= 139,464 free vertices).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+// Device address of that array on `device`, which must be the current device;
+// resolved with hipGetSymbolAddress on the first call per device and kept.
+hipError_t noalloc_scratch(int device, void** ptr);
 // y = H x (both parts, symmetric upper storage) through the solver's SpMV kernel.
 void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s);
 

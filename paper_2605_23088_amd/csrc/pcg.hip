@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "blockreduce.h"
 #include "kernels.h"
@@ -452,6 +453,36 @@ size_t pcg_workspace_bytes(int n) {
   const size_t n3 = 3 * (size_t)std::max(n, 1);
   return 256 + ((sizeof(PcgState) + 255) / 256) * 256 + sizeof(double) * (5 * n3 + MAX_WG_B + 2 * MAX_WG_C);
 }  // float64 vectors; the float32 form uses half of the vector part
+
+// Fixed solver workspace for callers that cannot allocate (yasps_pcg_noalloc):
+// one array per GPU, held from the module's load until the process ends.  Its
+// name is a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s) {
   if (A.n == 0) return;

@@ -27,7 +27,7 @@ SQLOG, IPC_CLASSIC = 0, 1
 INDEX_DEVICE, INDEX_HOST = 0, 1  # yasps_params.index_build
 
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
-           "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
+           "yasps_pcg_noalloc", "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
            "yasps_profile_query", "yasps_spmv", "yasps_destroy", "yasps_last_error"]
 K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH, K_CLOTH = range(9)
 KERNEL_CLASSES = ["inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "pcg_spmv", "pcg_update",
@@ -98,6 +98,7 @@ def lib():
         L.yasps_eval_stencils.argtypes = [P, P, C.c_int32, C.POINTER(EvalInfo)]
         L.yasps_assemble_bsr.argtypes = [P, C.POINTER(BsrView)]
         L.yasps_pcg.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(PcgInfo)]
+        L.yasps_pcg_noalloc.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(PcgInfo)]
         L.yasps_newton_step.argtypes = [P, P, C.POINTER(NewtonParams), C.POINTER(NewtonInfo)]
         L.yasps_get_pattern.argtypes = [P, C.c_int32, P, P, P]
         L.yasps_theta_adjoint.argtypes = [P, P, P, P, P]
@@ -300,6 +301,12 @@ class Yasps:
         info = PcgInfo()
         rc = self._check(lib().yasps_pcg(self.ctx, _ptr(b), _ptr(x), rtol, max_iter, C.byref(info)), allow)
         return x, dict(iters=info.iters, rel_residual=info.rel_residual, status=info.status, rc=rc)
+
+    def pcg_noalloc(self, b, x, rtol=1e-8, max_iter=20000, allow=(E_NOCONV,)):
+        """yasps_pcg_noalloc into a caller-provided x (no device allocation in the call)."""
+        info = PcgInfo()
+        rc = self._check(lib().yasps_pcg_noalloc(self.ctx, _ptr(b), _ptr(x), rtol, max_iter, C.byref(info)), allow)
+        return dict(iters=info.iters, rel_residual=info.rel_residual, status=info.status, rc=rc)
 
     def newton_step(self, x, rtol=1e-8, max_iter=20000, max_halvings=40, armijo=1e-4, tie_rtol=0.0,
                     hessian=PROJECTED, shift=0.0, allow=(E_NOCONV,)):
