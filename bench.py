@@ -18,8 +18,11 @@ the device), so every step does the same work.  Workloads:
 Prints ONE JSON line.  `value` is stencils processed per second of Newton
 iteration (Mstencils/s); `ms_per_step` is the Newton-iteration time.  After the
 timed steps a profiled pass times every kernel class with HIP events on the
-library's stream (the `roofline` object), and the CPU oracle runs one Newton
-step of the same workload (`cpu_baseline`).
+library's stream (the `roofline` object), the contact index is rebuilt a few
+times (`contact_index_ms`; `full_ms` = Newton iteration + one rebuild), and the
+CPU oracle runs Newton steps (or, on the large workloads, evaluation + assembly)
+on a seeded sample of the workload's stencils: the median of five runs on the
+host's threads and one run on a single thread (`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -45,10 +48,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic(prob, g, view, projected=True):
-    """Per-launch algorithmic bytes / flops of each kernel class.  The flop
-    models count the eigen-projections; with projected=False (exact Hessians,
-    no projection) the evaluation kernels are left unmodelled."""
+def algorithmic(prob, g, view, projected=True, mixed=False):
+    """Per-launch algorithmic bytes / flops of each kernel class: what the
+    method must move or compute, with staging and re-reads counted against the
+    kernel.  The flop models count the eigen-projections; with projected=False
+    (exact Hessians, no projection) the evaluation kernels are left
+    unmodelled.  mixed: the precision form (float32 BSR values and Krylov
+    vectors; float64 positions, gradient, solution and block inverses)."""
     import numpy as np
     n = g.n
     nt = g.nt
@@ -58,6 +64,37 @@ def algorithmic(prob, g, view, projected=True):
     pt_fp = (ct == 0) & (ci[:, 0] >= n) & (ci[:, 1:] < n).all(axis=1) if len(ct) else np.zeros(0, bool)
     c_flops = (sum(CONTACT_FLOPS[int(t)] * int(((ct == t) & ~pt_fp).sum()) for t in range(4)) +
                PT_FIXED_POINT_FLOPS * int(pt_fp.sum()))
+    vb = 36.0 if mixed else 72.0   # bytes of one stored 3x3 block
+    vv = 12.0 if mixed else 24.0   # bytes of one vertex of a Krylov vector
+    cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))
+    model = {
+        "cloth_eval": ("alu", cl_flops, "TFLOP/s"),
+        # FP64 ALU bound
+        "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
+        "contact_eval": ("alu", c_flops, "TFLOP/s"),
+        # HBM bound.  Assembly: every stored upper block written once and the
+        # gradient written once; reading staged contributions is overhead
+        "assemble": ("hbm", vb * nnzb + 24.0 * n, "GB/s"),
+        "block_inverse": ("hbm", 2 * 72.0 * n, "GB/s"),
+        # values + column index once per stored block, row pointers, u read, w written
+        "pcg_spmv": ("hbm", (vb + 4.0) * nnzb + 8.0 * (n + 1) + 2 * vv * n, "GB/s"),
+        # p, s, w, u, r (Krylov, vv each), x (24) and M^-1 (72) read; p, s, r, u and x written
+        "pcg_update": ("hbm", n * (5 * vv + 24.0 + 72.0 + 4 * vv + 24.0), "GB/s"),
+        "inertia": ("hbm", n * (24.0 * 2 + 8.0 + 72.0 + 24.0), "GB/s"),
+    }
+    if not projected:
+        for k in ("cloth_eval", "snh_eval", "contact_eval"):
+            del model[k]
+    return model
+
+
+def staged_bytes(prob, g, view, mixed=False):
+    """Bytes the staged assembly moves: every staged block contribution written
+    by the evaluation kernels and read by the segmented sums, every staged
+    gradient row likewise, plus the stored blocks and gradient written."""
+    import numpy as np
+    n = g.n
+    vb = 36.0 if mixed else 72.0
 
     def contributions(idx):  # (upper blocks, gradient rows) one stencil class contributes
         if len(idx) == 0:
@@ -69,27 +106,8 @@ def algorithmic(prob, g, view, projected=True):
     for key in ("tet_idx", "tri_idx", "hinge_idx", "cidx"):
         b, r = contributions(prob.get(key, []))
         nb, ng = nb + b, ng + r
-    cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))
-    model = {
-        "cloth_eval": ("alu", cl_flops, "TFLOP/s"),
-        # FP64 ALU bound
-        "snh_eval": ("alu", SNH_FLOPS_PER_TET * nt, "TFLOP/s"),
-        "contact_eval": ("alu", c_flops, "TFLOP/s"),
-        # HBM bound: what the method must move.  Assembly reads every staged
-        # contribution (72 B per block, 24 B per gradient row) and writes the
-        # upper blocks and the gradient
-        "assemble": ("hbm", 72.0 * (nb + nnzb) + 24.0 * (ng + n), "GB/s"),
-        "block_inverse": ("hbm", 2 * 72.0 * n, "GB/s"),
-        # values + column index once per stored block, row pointers, u read, w written
-        "pcg_spmv": ("hbm", 76.0 * nnzb + 8.0 * (n + 1) + 48.0 * n, "GB/s"),
-        # p, s, w, u, x, r and M^-1 read; p, s, x, r, u written
-        "pcg_update": ("hbm", n * (6 * 24.0 + 72.0 + 5 * 24.0), "GB/s"),
-        "inertia": ("hbm", n * (24.0 * 2 + 8.0 + 72.0 + 24.0), "GB/s"),
-    }
-    if not projected:
-        for k in ("cloth_eval", "snh_eval", "contact_eval"):
-            del model[k]
-    return model
+    nnzb = view.nnzb_static + view.nnzb_dynamic
+    return 2 * (vb * nb + 24.0 * ng) + vb * nnzb + 24.0 * n
 
 
 KERNEL_SOURCES = {"pcg_spmv": "pcg.hip", "pcg_update": "pcg.hip", "assemble": "assembly.hip",
@@ -142,10 +160,24 @@ def subsample(prob, frac, seed=1):
     return q
 
 
-def cpu_baseline(prob, frac=1.0, solve=True):
-    """The oracle on the workload or on a seeded fraction of its stencils (host
-    cores): one Newton step (eval + assembly + PCG to 1e-8 + line search), or
-    with solve=False only the evaluation and assembly."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(prob, frac=1.0, solve=True, runs=5):
+    """The oracle on a seeded fraction of the workload's stencils (host cores):
+    one Newton step (eval + assembly + PCG to 1e-8 + line search), or with
+    solve=False only the evaluation and assembly.  Median of `runs` runs on
+    torch's thread count, then one run on a single thread."""
+    import numpy as np
     import torch
     from oracle import assemble as oasm
     from oracle import newton as onewton
@@ -153,20 +185,38 @@ def cpu_baseline(prob, frac=1.0, solve=True):
     t0 = time.perf_counter()
     o = oasm.Oracle(q)
     t1 = time.perf_counter()
-    log(f"[bench] oracle set up in {t1 - t0:.1f} s; {'Newton step' if solve else 'eval + assembly'} on "
-        f"{n_stencils(q)} stencils")
-    if solve:
-        _, info = onewton.newton_step(o, q["x0"], rtol=1e-8)
-        what = f"one Newton step (eval + assembly + PCG to 1e-8 + line search, {info['cg_iters']} PCG iterations)"
-    else:
-        o.assemble(o.eval(q["x0"]))
-        what = "evaluation + assembly only (the PCG takes thousands of iterations here)"
-    t2 = time.perf_counter()
-    log(f"[bench] oracle {t2 - t1:.1f} s")
+    ns = n_stencils(q)
+    log(f"[bench] oracle set up in {t1 - t0:.1f} s; {'Newton step' if solve else 'eval + assembly'} on {ns} stencils")
+
+    def once():
+        t = time.perf_counter()
+        if solve:
+            _, info = onewton.newton_step(o, q["x0"], rtol=1e-8)
+        else:
+            o.assemble(o.eval(q["x0"]))
+            info = {}
+        return time.perf_counter() - t, info
+
+    threads = torch.get_num_threads()
+    ts, info = [], {}
+    for _ in range(runs):
+        dt, info = once()
+        ts.append(dt)
+    torch.set_num_threads(1)
+    try:
+        t_single, _ = once()
+    finally:
+        torch.set_num_threads(threads)
+    med = float(np.median(ts))
+    log(f"[bench] oracle median {med:.2f} s over {runs} runs ({threads} threads), {t_single:.2f} s on 1 thread")
+    what = (f"one Newton step (eval + assembly + PCG to 1e-8 + line search, {info['cg_iters']} PCG iterations)"
+            if solve else "evaluation + assembly only (the PCG takes thousands of iterations here)")
     part = "the full workload" if frac >= 1.0 else f"a seeded {frac:g} fraction of every stencil class"
-    return {"value": n_stencils(q) / (t2 - t1) / 1e6, "unit": "Mstencils/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{part}: {what}; {t2 - t1:.2f} s, pattern set-up {t1 - t0:.2f} s excluded"}
+    return {"value": ns / med / 1e6, "unit": "Mstencils/s", "cores": threads, "kind": "oracle",
+            "sample": f"{part} ({ns} stencils): {what}; median of {runs} runs {med:.2f} s "
+                      f"(runs {', '.join(f'{t:.2f}' for t in ts)} s), pattern set-up {t1 - t0:.2f} s excluded",
+            "single_thread": {"value": ns / t_single / 1e6, "unit": "Mstencils/s", "seconds": t_single},
+            "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count()}
 
 
 def kernel_table(stats, model, steps, cg_work, workload, precision):
@@ -251,7 +301,7 @@ def bench_static(args):
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(prob, 0.5, False)
+        cpu = cpu_baseline(prob, 0.125, False)
 
     stencils = n_stencils(prob)
     line = {
@@ -326,15 +376,15 @@ def main():
         return bench_static(args)
 
     log(f"[bench] generating workload {args.workload}")
-    cpu_frac, cpu_solve = 1.0, True
+    cpu_frac, cpu_solve = 0.25, True
     if args.workload == "cloth":
         prob = synth.c3_cloth()
-        cpu_frac, cpu_solve = 1.0 / 8, False
+        cpu_frac, cpu_solve = 1.0 / 32, False
         desc = ("heterogeneous scene: 50x50x20-cell tet block + four 250x250 cloth sheets (StVK membranes, "
                 "dihedral hinges), 1M PT/EE/PE/PP contacts 40/40/15/5 %")
     elif args.workload == "block80":
         prob = synth.c4_block()
-        cpu_frac = 0.125
+        cpu_frac, cpu_solve = 1.0 / 32, False
         desc = "80x80x52-cell Kuhn block + 750k PT + 750k EE collider stencils"
     elif args.cells == 40:
         prob = synth.c2_block()
@@ -383,8 +433,13 @@ def main():
         cg_work = args.profiled_steps * float(np.mean([i["cg_iters"] for i in pinfos]))
         # counter records are per workload: the block workload at another size has none
         traffic_key = args.workload if args.workload != "block40" or args.cells == 40 else f"block{args.cells}cube"
-        kernels, roofline = kernel_table(stats, algorithmic(prob, g, view), args.profiled_steps, cg_work,
-                                         traffic_key, args.precision)
+        mixed = args.precision == "mixed"
+        kernels, roofline = kernel_table(stats, algorithmic(prob, g, view, mixed=mixed), args.profiled_steps,
+                                         cg_work, traffic_key, args.precision)
+        if "assemble" in kernels:  # the staged design's bytes against the method's minimum
+            a = kernels["assemble"]
+            a["staged_bytes"] = staged_bytes(prob, g, view, mixed)
+            a["staged_to_min_ratio"] = a["staged_bytes"] / a["algorithmic_bytes"]
 
     # rebuild of the contact index (yasps_set_contacts), outside the timed step:
     # the device build of this context against a host-build context
@@ -432,6 +487,8 @@ def main():
                    "tets": nt, "triangles": nf, "hinges": nh, "contacts": nc, "free_vertices": int(prob["n_free"]),
                    "nnzb_static": view.nnzb_static, "nnzb_dynamic": view.nnzb_dynamic},
         "newton_iter_ms": ms,
+        # the Newton iteration plus a rebuild of the contact index (yasps_set_contacts)
+        "full_ms": ms + index_ms["device"] if index_ms else None,
         "phases_ms": phases,
         "pcg_iters": int(np.mean([i["cg_iters"] for i in infos])),
         "line_search_trials": int(np.mean([i["ls_trials"] for i in infos])),
