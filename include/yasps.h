@@ -246,9 +246,11 @@ yasps_status yasps_pcg(yasps_ctx* ctx, const double* b, double* x, double rtol, 
  * same solve, bit for bit, with the solver's workspace (Krylov vectors,
  * per-workgroup partials, device scalars) in one fixed array per GPU instead of
  * the context's.  The call makes no hipMalloc / hipFree and no allocating
- * library call.  The array is 16 MiB (NOALLOC_SCRATCH_BYTES), enough for
- * systems of up to 139,464 free vertices; larger systems are rejected with
- * YASPS_E_ARG before anything is launched.  Each GPU the library runs on
+ * library call.  The array is 32 MiB; a solve needs 96 bytes per free vertex
+ * plus 24 bytes per SpMV slot (one per chunk of stored blocks and row it
+ * reaches: about 3 per vertex on tet meshes) plus 25 KiB, so the 40^3-cell
+ * block (68,921 free vertices) fits with room to spare; larger systems are
+ * rejected with YASPS_E_ARG before anything is launched.  Each GPU the library runs on
  * holds its own array until the process ends; every call on one GPU shares
  * it and leaves the last solve's contents there (no call reads what an earlier
  * one left: the solver writes its state and vectors before reading them), so
@@ -284,6 +286,16 @@ yasps_status yasps_get_pattern(yasps_ctx* ctx, int32_t part, int32_t* row_ptr, i
  * Errors: YASPS_E_ARG, YASPS_E_HIP. */
 yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* lambda,
                                  const double* theta, double* grad_theta);
+
+/* Levenberg-Marquardt damping scale for the damped Newton steps of the static
+ * equilibrium of the differentiation form (yasps_newton_params.shift; the
+ * paper's own solver, section "Solver", takes plain projected Newton steps):
+ * *out = frac * median over the free vertices v of |tr(H_vv)| / (3 m_v), with
+ * H_vv the diagonal block (static + dynamic parts) of the last assembly,
+ * including any shift that assembly added, and m_v the lumped masses.  For an
+ * even vertex count the median is the mean of the two middle values.
+ * Errors: YASPS_E_ARG (before any assembly, frac < 0), YASPS_E_HIP. */
+yasps_status yasps_lm_shift(yasps_ctx* ctx, double frac, double* out);
 
 /* Kernel classes timed by the opt-in profiler (yasps_profile_*). */
 #define YASPS_K_INERTIA 0       /* inertia / gravity term per vertex */

@@ -63,14 +63,9 @@ class StaticEquilibrium:
                                     shift=shift)
 
     def _shift_scale(self):
-        """A Levenberg-Marquardt shift of ~1 % of the typical diagonal of the
-        last assembled Hessian, in units of the mass (the shift multiplies m_v)."""
-        out = self.lib.assemble()
-        rp = out["row_ptr_s"].cpu().numpy()
-        diag = out["values_s"][torch.as_tensor(rp[:-1], device=out["values_s"].device)]
-        tr = torch.diagonal(diag, dim1=1, dim2=2).sum(dim=1).abs().cpu().numpy() / 3.0
-        m = np.asarray(self.prob["mass"])
-        return 1e-2 * float(np.median(tr / m))
+        """A Levenberg-Marquardt shift of 1 % of the median diagonal of the last
+        assembled Hessian, in units of the mass (the shift multiplies m_v)."""
+        return self.lib.lm_shift(1e-2)
 
     def solve(self, x0):
         """Damped exact Newton: each step solves (H_exact + mu M) p = -g and

@@ -12,6 +12,7 @@
 
 #include "../../include/yasps.h"
 #include "common.h"
+#include "devsort.h"
 #include "kernels.h"
 #include "pattern.h"
 
@@ -100,6 +101,28 @@ struct Part {  // device copy of one pattern part
   int32_t *rp = nullptr, *ci = nullptr;
 };
 
+// Device buffer that only grows: reused across contact changes while large enough.
+struct GrowBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  void* ensure(size_t bytes) {
+    if (bytes <= cap && p) return p;
+    release();
+    const size_t want = std::max<size_t>(256, bytes + bytes / 4);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      return nullptr;
+    }
+    cap = want;
+    return p;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
 }  // namespace
 
 struct yasps_ctx {
@@ -110,7 +133,6 @@ struct yasps_ctx {
   int n = 0, nt = 0, nc = 0, nf = 0, nh = 0;
   std::string err;
   std::vector<void*> allocs;      // everything allocated for the static part / workspace
-  std::vector<void*> dyn_allocs;  // everything allocated for the current contacts
 
   // static part
   PartPattern hpat_s;
@@ -124,18 +146,19 @@ struct yasps_ctx {
   int32_t *spos_f = nullptr, *gpos_f = nullptr, *spos_h = nullptr, *gpos_h = nullptr, *h_idx = nullptr;
   double* h_rest = nullptr;
   std::vector<Group> hgroups;
-
-  // static share of every full SpMV row (the static-only FullPattern), for the
-  // device build of the dynamic part
-  int32_t *sf_ptr = nullptr, *sf_col = nullptr, *sf_src = nullptr;
-  long long sf_nnz = 0;
+  // SpMV plans of the two parts (spmvplan.hip); their arrays live in the grow-only buffers
+  SpmvPart plan_s, plan_d;
+  GrowBuf plan_s_buf[PL_COUNT], plan_d_buf[PL_COUNT];
 
   // dynamic part
   PartPattern hpat_d;
   bool hpat_d_current = true;  // false after a device build until yasps_get_pattern downloads it
   int32_t* dslot = nullptr;    // device slot map of a device build [nc][10]
-  void* di_arena = nullptr;    // scratch of the device build, grown to the largest build seen
+  void* di_arena = nullptr;    // scratch of the index and plan builds, grown to the largest build seen
   size_t di_arena_bytes = 0;
+  // the dynamic part's arrays: grow-only, reused by every contact set that fits
+  GrowBuf di_buf[DI_COUNT];
+  GrowBuf stg_d_buf, gstg_d_buf, vals_d_buf, d_c_buf;
 
   // a second stream for the contact kernels, which run beside the elastic ones
   // during an evaluation (fork / join through the two events)
@@ -149,23 +172,10 @@ struct yasps_ctx {
   double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
   float *stg_d32 = nullptr, *vals_d32 = nullptr;
 
-  // SpMV rows: both triangles of both parts, each entry naming its stored
-  // upper block (rebuilt with the contacts; the values are vals_s / vals_d)
-  std::vector<void*> full_allocs;
-  int32_t *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
-  float* f_vals32 = nullptr;  // precision form: float32 values per entry, structure of arrays
-  // float64: the stored blocks live in one array (static, dynamic, then the
-  // transposed copies of the far SpMV entries), reallocated with the rows
-  std::vector<void*> val_allocs;
-  int32_t* far_src = nullptr;
-  int nfar = 0, nnzb_sd = 0;
-  long long f_nnz = 0;
-  int f_xsplit[PCG_XCDS + 1] = {};
-
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
   uint32_t* flags = nullptr;
-  void* pcg_work = nullptr;
+  GrowBuf pcg_work;             // solver workspace (vectors, partials, SpMV slots)
   double *p_dir = nullptr, *x_trial = nullptr, *b_tmp = nullptr;
   double* host_scal = nullptr;  // pinned: [0, 16) scalars and flags, [16, 32) the PCG's polled state
   int pcg_hint = 0;             // iterations of the last PCG solve (sizes the next one's launch batches)
@@ -173,6 +183,7 @@ struct yasps_ctx {
   bool evaluated = false;
   bool assembled = false;  // the stored blocks hold the values of the last assembly
   Profiler prof;
+  hipEvent_t ev[5] = {};        // phase events of yasps_newton_step
 };
 
 namespace {
@@ -225,68 +236,59 @@ yasps_status upload_part(yasps_ctx* c, std::vector<void*>& list, const PartPatte
   return YASPS_OK;
 }
 
-// XCD row ranges of equal work: a row costs its blocks plus about two blocks'
-// worth of fixed work (row pointers, the lane-group reduction, the output).
-constexpr int XCD_ROW_COST = 2;
+// Grows the context's index / plan scratch arena to `need` bytes (plus a
+// quarter), so the next build of that size allocates no temporaries.
+void grow_arena(yasps_ctx* c, size_t need) {
+  if (need <= c->di_arena_bytes) return;
+  if (c->di_arena) (void)hipFree(c->di_arena);
+  c->di_arena = nullptr;
+  c->di_arena_bytes = 0;
+  const size_t want = need + need / 4;
+  if (hipMalloc(&c->di_arena, want) == hipSuccess) c->di_arena_bytes = want;
+}
 
-// (Re)builds the SpMV matrix layout over the current parts; synchronises the
-// stream so the host pattern can go out of scope.
-// Float64: marks the far entries of the SpMV rows and (re)allocates the one
-// array of stored blocks and far copies that vals_s / vals_d point into (its
-// values are written by the next assembly).  The precision form keeps its
-// separate arrays.
-yasps_status split_far(yasps_ctx* c) {
-  c->far_src = nullptr;
-  c->nfar = 0;
-  const int nd = c->nc ? c->pd.nnzb : 0;
-  c->nnzb_sd = c->ps.nnzb + nd;
-  if (c->prm.precision == YASPS_MIXED) return YASPS_OK;
-  if (c->f_src) {
-    auto alloc = [c](size_t bytes) -> void* {
-      void* p = nullptr;
-      if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-      c->full_allocs.push_back(p);
-      return p;
-    };
-    if (split_far_entries(c->n, c->f_rp, c->f_col, c->f_src, c->ps.nnzb, c->nnzb_sd, FAR_ROWS, &c->far_src,
-                          &c->nfar, alloc, c->stream))
-      return fail(c, YASPS_E_HIP, "far entries of the SpMV rows");
+// SpMV plan of one part (0 static, 1 dynamic) into the context's grow-only buffers.
+yasps_status build_plan(yasps_ctx* c, int part, const int32_t* rp, const int32_t* col, int nblk, const void* vals) {
+  GrowBuf* bufs = part ? c->plan_d_buf : c->plan_s_buf;
+  SpmvPart& out = part ? c->plan_d : c->plan_s;
+  auto alloc = [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
+  size_t need = 0;
+  const int r = build_spmv_plan(c->n, rp, col, nblk, vals, out, alloc, c->di_arena, c->di_arena_bytes, &need,
+                                c->stream);
+  grow_arena(c, need);
+  if (r != 0) {
+    out = SpmvPart{};
+    return fail(c, YASPS_E_HIP, "building the SpMV plan");
   }
-  std::vector<void*> fresh;
-  double* all = nullptr;
-  if (dalloc(fresh, &all, 9 * ((size_t)c->nnzb_sd + c->nfar)) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    free_list(fresh);
-    return fail(c, YASPS_E_HIP, "array of the stored blocks");
+  if (3 * sizeof(double) * (size_t)out.max_entries > spmv_max_lds_bytes()) {
+    out = SpmvPart{};
+    return fail(c, YASPS_E_ARG, "an SpMV chunk needs more LDS than a workgroup has");
   }
-  free_list(c->val_allocs);
-  c->val_allocs = fresh;
-  c->vals_s = all;
-  c->vals_d = nd ? all + 9 * (size_t)c->ps.nnzb : nullptr;
   return YASPS_OK;
 }
 
-yasps_status build_full_matrix(yasps_ctx* c) {
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  free_list(c->full_allocs);
-  FullPattern fp;
-  build_full(c->n, c->hpat_s, c->nc ? &c->hpat_d : nullptr, fp);
-  c->f_nnz = (long long)fp.col.size();
-  const long long ROW_COST = XCD_ROW_COST;
-  const long long work = c->f_nnz + ROW_COST * c->n;
-  int r = 0;
-  for (int x = 0; x <= PCG_XCDS; ++x) {
-    const long long target = work * x / PCG_XCDS;
-    while (r < c->n && (long long)fp.row_ptr[r] + ROW_COST * r < target) ++r;
-    c->f_xsplit[x] = x == PCG_XCDS ? c->n : r;
-  }
-  HIPCHK(c, upload(c->full_allocs, &c->f_rp, fp.row_ptr, c->stream));
-  HIPCHK(c, upload(c->full_allocs, &c->f_col, fp.col, c->stream));
-  HIPCHK(c, upload(c->full_allocs, &c->f_src, fp.src, c->stream));
-  c->f_vals32 = nullptr;
-  if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return split_far(c);
+// The solver workspace for the current plans (grow-only).
+yasps_status ensure_pcg_work(yasps_ctx* c) {
+  const long long slots = (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0);
+  if (!c->pcg_work.ensure(pcg_workspace_bytes(c->n, slots))) return fail(c, YASPS_E_HIP, "hipMalloc of the PCG workspace");
+  return YASPS_OK;
+}
+
+// Leaves the context without contacts (after a failed or before a new contact set).
+void clear_contacts(yasps_ctx* c) {
+  c->nc = 0;
+  c->groups.clear();
+  c->pd = Part{};
+  c->plan_d = SpmvPart{};
+  c->hpat_d = PartPattern{};
+  c->hpat_d_current = true;
+  c->dslot = nullptr;
+  c->c_idx = c->spos_c = c->gpos_c = c->cptr_d = c->gptr_d = c->ddiag = nullptr;
+  c->stg_d = c->gstg_d = c->vals_d = c->d_c = nullptr;
+  c->stg_d32 = c->vals_d32 = nullptr;
+  c->nblk_d = c->ngrd_d = 0;
+  c->evaluated = false;
+  c->assembled = false;
 }
 
 // Partials layout: [inertia | tets, membranes, hinge groups | contact energy |
@@ -434,14 +436,10 @@ ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, in
 PcgMatrix pcg_matrix(const yasps_ctx* c) {
   PcgMatrix A{};
   A.n = c->n;
-  A.rp = c->f_rp;
-  A.col = c->f_col;
-  A.nnz = c->f_nnz;
+  A.part[0] = c->plan_s;
+  if (c->nc) A.part[1] = c->plan_d;
   A.minv = c->minv;
-  A.src = c->f_src;
-  A.vals = c->vals_s;  // float64: the one array of stored blocks and far copies
-  A.v32 = c->f_vals32;
-  for (int x = 0; x <= PCG_XCDS; ++x) A.xsplit[x] = c->f_xsplit[x];
+  A.f32 = c->prm.precision == YASPS_MIXED;
   return A;
 }
 
@@ -475,10 +473,13 @@ void yasps_destroy(yasps_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  free_list(ctx->full_allocs);
-  free_list(ctx->dyn_allocs);
-  free_list(ctx->val_allocs);
   free_list(ctx->allocs);
+  for (GrowBuf* set : {ctx->plan_s_buf, ctx->plan_d_buf})
+    for (int k = 0; k < PL_COUNT; ++k) set[k].release();
+  for (GrowBuf& b : ctx->di_buf) b.release();
+  for (GrowBuf* b : {&ctx->stg_d_buf, &ctx->gstg_d_buf, &ctx->vals_d_buf, &ctx->d_c_buf, &ctx->pcg_work}) b->release();
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
   if (ctx->di_arena) (void)hipFree(ctx->di_arena);
   if (ctx->side) {
@@ -511,7 +512,7 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
     return fail(nullptr, YASPS_E_ARG, "unknown index_build");
   if (prm.precision != YASPS_FP64 && prm.precision != YASPS_MIXED)
     return fail(nullptr, YASPS_E_ARG, "unknown precision");
-  if (prm.proj != YASPS_F_SPACE) return fail(nullptr, YASPS_E_UNIMPL, "only F-space Neo-Hookean projection is built");
+  if (prm.proj != YASPS_F_SPACE && prm.proj != YASPS_X_SPACE) return fail(nullptr, YASPS_E_ARG, "unknown proj");
   if (prm.barrier != YASPS_SQLOG && prm.barrier != YASPS_IPC_CLASSIC) return fail(nullptr, YASPS_E_ARG, "unknown barrier");
 
   yasps_ctx* c = new (std::nothrow) yasps_ctx();
@@ -603,15 +604,6 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   build_staging(c->n, hst.data(), ns, c->hpat_s, order, dyn, true, st);
   yasps_status s = upload_part(c, c->allocs, c->hpat_s, c->ps);
   if (s) return bail(s);
-  {
-    FullPattern sf;
-    build_full(c->n, c->hpat_s, nullptr, sf);
-    c->sf_nnz = (long long)sf.col.size();
-    if (upload(c->allocs, &c->sf_ptr, sf.row_ptr, c->stream) != hipSuccess ||
-        upload(c->allocs, &c->sf_col, sf.col, c->stream) != hipSuccess ||
-        upload(c->allocs, &c->sf_src, sf.src, c->stream) != hipSuccess)
-      return bail(fail(c, YASPS_E_HIP, "upload of the static SpMV rows"));
-  }
   // per-class staging positions (storage order) and the hinge arrays in storage order
   auto rows = [&](const std::vector<int32_t>& src, int nrows, int j0, int cnt) {
     std::vector<int32_t> out((size_t)nrows * cnt);
@@ -650,8 +642,9 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (prm.precision == YASPS_MIXED) {
     AL(c->stg_s32, 9 * (size_t)st.nblocks);
     AL(c->vals_s32, 9 * (size_t)c->hpat_s.nnzb);
-  } else {  // vals_s: allocated with the SpMV rows (split_far)
+  } else {
     AL(c->stg_s, 9 * (size_t)st.nblocks);
+    AL(c->vals_s, 9 * (size_t)c->hpat_s.nnzb);
   }
   AL(c->gstg_s, 3 * (size_t)st.ngrads);
   AL(c->grad, 3 * (size_t)c->n);
@@ -661,17 +654,17 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   AL(c->p_dir, 3 * (size_t)c->n);
   AL(c->x_trial, 3 * (size_t)c->n);
   AL(c->b_tmp, 3 * (size_t)c->n);
-  {
-    char* w = nullptr;
-    AL(w, pcg_workspace_bytes(c->n));
-    c->pcg_work = w;
-  }
+  for (hipEvent_t& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "hipEventCreate"));
   if (hipHostMalloc((void**)&c->host_scal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(c, YASPS_E_HIP, "hipHostMalloc"));
   s = ensure_parts(c);
   if (s) return bail(s);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "stream sync"));
-  s = build_full_matrix(c);
+  s = build_plan(c, 0, c->ps.rp, c->ps.ci, c->ps.nnzb,
+                 prm.precision == YASPS_MIXED ? (const void*)c->vals_s32 : (const void*)c->vals_s);
+  if (s) return bail(s);
+  s = ensure_pcg_work(c);
   if (s) return bail(s);
 #undef UP
 #undef AL
@@ -687,6 +680,32 @@ const char* contact_error(int reason) {
   return reason == 1 ? "unknown type" : reason == 2 ? "vertex id out of range, repeated or misplaced" : "no free vertex";
 }
 
+// After the dynamic pattern and staging layout are on the device: the staged
+// and assembled value arrays, the distances, the dynamic SpMV plan and the
+// workspace, all in grow-only buffers.  On failure the caller clears the
+// contacts.
+yasps_status finish_dynamic(yasps_ctx* c) {
+  const bool mixed = c->prm.precision == YASPS_MIXED;
+  const size_t vsz = mixed ? sizeof(float) : sizeof(double);
+  void* stg = c->stg_d_buf.ensure(9 * vsz * (size_t)std::max(c->nblk_d, 1));
+  void* vals = c->vals_d_buf.ensure(9 * vsz * (size_t)std::max(c->pd.nnzb, 1));
+  c->gstg_d = static_cast<double*>(c->gstg_d_buf.ensure(3 * sizeof(double) * (size_t)std::max(c->ngrd_d, 1)));
+  c->d_c = static_cast<double*>(c->d_c_buf.ensure(sizeof(double) * (size_t)std::max(c->nc, 1)));
+  if (!stg || !vals || !c->gstg_d || !c->d_c) return fail(c, YASPS_E_HIP, "hipMalloc of the contact arrays");
+  if (mixed) {
+    c->stg_d32 = static_cast<float*>(stg);
+    c->vals_d32 = static_cast<float*>(vals);
+  } else {
+    c->stg_d = static_cast<double*>(stg);
+    c->vals_d = static_cast<double*>(vals);
+  }
+  yasps_status s = ensure_parts(c);
+  if (s) return s;
+  s = build_plan(c, 1, c->pd.rp, c->pd.ci, c->pd.nnzb, vals);
+  if (s) return s;
+  return ensure_pcg_work(c);
+}
+
 // Device build of the dynamic part (build_dynamic_index): the same arrays as the
 // host path below, without the round trip through host memory.
 yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
@@ -697,48 +716,16 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   in.nc = nc;
   in.type = C->type;
   in.idx = C->idx;
-  in.nnzb_s = c->ps.nnzb;
-  in.sf_ptr = c->sf_ptr;
-  in.sf_col = c->sf_col;
-  in.sf_src = c->sf_src;
-  in.sf_nnz = c->sf_nnz;
-  in.row_cost = XCD_ROW_COST;
   in.arena = c->di_arena;
   in.arena_bytes = c->di_arena_bytes;
-  bool oom = false;
-  auto alloc_into = [&](std::vector<void*>& list) {
-    return [&list, &oom](size_t bytes) -> void* {
-      void* p = nullptr;
-      if (hipMalloc(&p, bytes) != hipSuccess) {
-        oom = true;
-        return nullptr;
-      }
-      list.push_back(p);
-      return p;
-    };
-  };
-  // the full rows go to full_allocs, everything else to dyn_allocs
-  std::vector<void*> made;
+  GrowBuf* bufs = c->di_buf;
+  auto alloc = [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
   DynIndexOut o;
-  const int r = build_dynamic_index(in, o, alloc_into(made), c->stream);
-  if (o.arena_needed > c->di_arena_bytes) {  // the next build with this many contacts needs no allocation
-    if (c->di_arena) (void)hipFree(c->di_arena);
-    c->di_arena = nullptr;
-    c->di_arena_bytes = 0;
-    const size_t want = o.arena_needed + o.arena_needed / 4;
-    if (hipMalloc(&c->di_arena, want) == hipSuccess) c->di_arena_bytes = want;
-  }
-  if (r == 1) {
-    free_list(made);
-    c->nc = 0;
+  const int r = build_dynamic_index(in, o, alloc, c->stream);
+  grow_arena(c, o.arena_needed);  // the next build with this many contacts takes no temporaries
+  if (r == 1)
     return fail(c, YASPS_E_ARG, "contact " + std::to_string(o.err_stencil) + ": " + contact_error(o.err_reason));
-  }
-  if (r != 0 || oom) {
-    free_list(made);
-    c->nc = 0;
-    return fail(c, YASPS_E_HIP, oom ? "out of device memory in the contact index build" : "device build of the contact index");
-  }
-  for (void* p : made) (o.f_rp == p || o.f_col == p || o.f_src == p ? c->full_allocs : c->dyn_allocs).push_back(p);
+  if (r != 0) return fail(c, YASPS_E_HIP, "device build of the contact index");
   c->nc = nc;
   for (int key = 0, j = 0; key < 32; ++key)
     if (o.gcount[key]) {
@@ -759,25 +746,80 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   c->cptr_d = o.cptr;
   c->gptr_d = o.gptr;
   c->ddiag = o.ddiag;
-  if (c->prm.precision == YASPS_MIXED) {
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)o.nent));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)o.nnzb));
-  } else {  // vals_d: allocated with the SpMV rows (split_far)
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)o.nent));
+  return finish_dynamic(c);
+}
+
+// Host build of the dynamic part (YASPS_INDEX_HOST), uploaded into the same
+// grow-only buffers as the device build.
+yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
+  const int nc = C->n_contacts;
+  std::vector<int32_t> ty(nc), idx((size_t)4 * nc);
+  if (nc) {
+    HIPCHK(c, hipMemcpy(ty.data(), C->type, (size_t)nc * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(idx.data(), C->idx, idx.size() * 4, hipMemcpyDeviceToHost));
   }
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)o.ngrad));
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
-  yasps_status s = ensure_parts(c);
-  if (s) return s;
-  // SpMV rows
-  c->f_rp = o.f_rp;
-  c->f_col = o.f_col;
-  c->f_src = o.f_src;
-  c->f_nnz = o.f_nnz;
-  for (int x = 0; x <= PCG_XCDS; ++x) c->f_xsplit[x] = o.xsplit[x];
-  if (c->prm.precision == YASPS_MIXED) HIPCHK(c, dalloc(c->full_allocs, &c->f_vals32, 9 * (size_t)c->f_nnz));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return split_far(c);
+  const int nall = c->P.n_free + c->P.n_fixed;
+  static const int NV[4] = {4, 4, 3, 2};
+  std::vector<int> key(nc);
+  for (int s = 0; s < nc; ++s) {
+    if (ty[s] < 0 || ty[s] > 3) return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": unknown type");
+    if (!valid_ids(idx.data(), nc, s, NV[ty[s]], nall))
+      return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": vertex id out of range, repeated or misplaced");
+    int nf = 0;
+    for (int a = 0; a < NV[ty[s]]; ++a) nf += idx[a * (size_t)nc + s] < c->n ? 1 : 0;
+    if (nf == 0) return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": no free vertex");
+    // point-triangle stencils against a fixed point get their own group (and
+    // kernel): their projection reduces to a 6 x 6 eigenproblem
+    const bool pt_fixed_point = ty[s] == 0 && nf == 3 && idx[s] >= c->n;
+    key[s] = ty[s] * 8 + (pt_fixed_point ? PT_TRIANGLE_FREE : nf);
+  }
+  PartPattern pat;
+  build_pattern(c->n, idx.data(), nc, false, pat);
+  // storage order: stable sort by (type, number of free vertices)
+  std::vector<int32_t> order(nc);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+  std::vector<Group> groups;
+  for (int j = 0; j < nc;) {
+    int e = j;
+    while (e < nc && key[order[e]] == key[order[j]]) ++e;
+    groups.push_back(Group{key[order[j]] / 8, key[order[j]] % 8, j, e});
+    j = e;
+  }
+  std::vector<int32_t> sidx((size_t)4 * nc);
+  for (int j = 0; j < nc; ++j)
+    for (int a = 0; a < 4; ++a) sidx[(size_t)a * nc + j] = idx[(size_t)a * nc + order[j]];
+  Staging st;
+  build_staging(c->n, idx.data(), nc, pat, order, false, false, st);
+  std::vector<int32_t> ddiag(c->n, -1);
+  for (int v = 0; v < c->n; ++v)
+    for (int k = pat.row_ptr[v]; k < pat.row_ptr[v + 1]; ++k)
+      if (pat.col_idx[k] == v) ddiag[v] = k;
+  auto up = [c](int which, const std::vector<int32_t>& h) -> int32_t* {
+    int32_t* d = static_cast<int32_t*>(c->di_buf[which].ensure(sizeof(int32_t) * std::max<size_t>(h.size(), 1)));
+    if (d && !h.empty() &&
+        hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return nullptr;
+    return d;
+  };
+  c->pd.nnzb = pat.nnzb;
+  c->pd.rp = up(DI_RP, pat.row_ptr);
+  c->pd.ci = up(DI_COL, pat.col_idx);
+  c->c_idx = up(DI_SIDX, sidx);
+  c->spos_c = up(DI_SPOS, st.spos);
+  c->gpos_c = up(DI_GPOS, st.gpos);
+  c->cptr_d = up(DI_CPTR, st.cptr);
+  c->gptr_d = up(DI_GPTR, st.gptr);
+  c->ddiag = up(DI_DDIAG, ddiag);
+  if (!c->pd.rp || !c->pd.ci || !c->c_idx || !c->spos_c || !c->gpos_c || !c->cptr_d || !c->gptr_d || !c->ddiag)
+    return fail(c, YASPS_E_HIP, "upload of the contact index");
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the host arrays go out of scope
+  c->nc = nc;
+  c->groups = std::move(groups);
+  c->hpat_d = std::move(pat);
+  c->nblk_d = st.nblocks;
+  c->ngrd_d = st.ngrads;
+  return finish_dynamic(c);
 }
 
 }  // namespace
@@ -790,93 +832,11 @@ yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
     return fail(c, YASPS_E_ARG, "bad contact arrays");
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  free_list(c->dyn_allocs);
-  free_list(c->full_allocs);  // rebuilt below, or at the next assembly if this call fails
-  c->f_rp = c->f_col = c->f_src = nullptr;
-  c->f_vals32 = nullptr;
-  c->far_src = nullptr;
-  c->nfar = 0;
-  c->f_nnz = 0;
-  c->groups.clear();
-  c->pd = Part{};
-  c->hpat_d = PartPattern{};
-  c->hpat_d_current = true;
-  c->dslot = nullptr;
-  c->evaluated = false;
-  c->assembled = false;
-  const int nc = C->n_contacts;
-  if (c->prm.index_build == YASPS_INDEX_DEVICE) return set_contacts_device(c, C);
-  std::vector<int32_t> ty(nc), idx((size_t)4 * nc);
-  if (nc) {
-    HIPCHK(c, hipMemcpy(ty.data(), C->type, (size_t)nc * 4, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(idx.data(), C->idx, idx.size() * 4, hipMemcpyDeviceToHost));
-  }
-  const int nall = c->P.n_free + c->P.n_fixed;
-  static const int NV[4] = {4, 4, 3, 2};
-  std::vector<int> key(nc);
-  for (int s = 0; s < nc; ++s) {
-    if (ty[s] < 0 || ty[s] > 3) {
-      c->nc = 0;
-      return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": unknown type");
-    }
-    if (!valid_ids(idx.data(), nc, s, NV[ty[s]], nall)) {
-      c->nc = 0;
-      return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": vertex id out of range, repeated or misplaced");
-    }
-    int nf = 0;
-    for (int a = 0; a < NV[ty[s]]; ++a) nf += idx[a * (size_t)nc + s] < c->n ? 1 : 0;
-    if (nf == 0) {
-      c->nc = 0;
-      return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": no free vertex");
-    }
-    // point-triangle stencils against a fixed point get their own group (and
-    // kernel): their projection reduces to a 6 x 6 eigenproblem
-    const bool pt_fixed_point = ty[s] == 0 && nf == 3 && idx[s] >= c->n;
-    key[s] = ty[s] * 8 + (pt_fixed_point ? PT_TRIANGLE_FREE : nf);
-  }
-  c->nc = nc;
-  build_pattern(c->n, idx.data(), nc, false, c->hpat_d);
-  // storage order: stable sort by (type, number of free vertices)
-  std::vector<int32_t> order(nc);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-  for (int j = 0; j < nc;) {
-    int e = j;
-    while (e < nc && key[order[e]] == key[order[j]]) ++e;
-    c->groups.push_back(Group{key[order[j]] / 8, key[order[j]] % 8, j, e});
-    j = e;
-  }
-  std::vector<int32_t> sidx((size_t)4 * nc);
-  for (int j = 0; j < nc; ++j)
-    for (int a = 0; a < 4; ++a) sidx[(size_t)a * nc + j] = idx[(size_t)a * nc + order[j]];
-  Staging st;
-  build_staging(c->n, idx.data(), nc, c->hpat_d, order, false, false, st);
-  std::vector<int32_t> ddiag(c->n, -1);
-  for (int v = 0; v < c->n; ++v)
-    for (int k = c->hpat_d.row_ptr[v]; k < c->hpat_d.row_ptr[v + 1]; ++k)
-      if (c->hpat_d.col_idx[k] == v) ddiag[v] = k;
-  yasps_status s = upload_part(c, c->dyn_allocs, c->hpat_d, c->pd);
-  if (s) return s;
-  c->nblk_d = st.nblocks;
-  c->ngrd_d = st.ngrads;
-  HIPCHK(c, upload(c->dyn_allocs, &c->c_idx, sidx, c->stream));
-  HIPCHK(c, upload(c->dyn_allocs, &c->spos_c, st.spos, c->stream));
-  HIPCHK(c, upload(c->dyn_allocs, &c->gpos_c, st.gpos, c->stream));
-  HIPCHK(c, upload(c->dyn_allocs, &c->cptr_d, st.cptr, c->stream));
-  HIPCHK(c, upload(c->dyn_allocs, &c->gptr_d, st.gptr, c->stream));
-  HIPCHK(c, upload(c->dyn_allocs, &c->ddiag, ddiag, c->stream));
-  if (c->prm.precision == YASPS_MIXED) {
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d32, 9 * (size_t)st.nblocks));
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->vals_d32, 9 * (size_t)c->hpat_d.nnzb));
-  } else {  // vals_d: allocated with the SpMV rows (split_far)
-    HIPCHK(c, dalloc(c->dyn_allocs, &c->stg_d, 9 * (size_t)st.nblocks));
-  }
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->gstg_d, 3 * (size_t)st.ngrads));
-  HIPCHK(c, dalloc(c->dyn_allocs, &c->d_c, (size_t)nc));
-  s = ensure_parts(c);
-  if (s) return s;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return build_full_matrix(c);
+  clear_contacts(c);
+  const yasps_status s =
+      c->prm.index_build == YASPS_INDEX_DEVICE ? set_contacts_device(c, C) : set_contacts_host(c, C);
+  if (s) clear_contacts(c);  // a rejected or failed set leaves the context without contacts
+  return s;
 }
 
 namespace {
@@ -891,7 +851,7 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
   launch_inertia(inertia_args(c, x), c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_SNH);
-  launch_snh_eval(snh_args(c, x), exact, c->prm.precision == YASPS_MIXED, c->stream);
+  launch_snh_eval(snh_args(c, x), exact, c->prm.precision == YASPS_MIXED, c->prm.proj == YASPS_X_SPACE, c->stream);
   c->prof.end();
   if (c->nf || c->nh) {
     c->prof.begin(YASPS_K_CLOTH);
@@ -945,10 +905,6 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
 
 // shift > 0 adds shift m_v I to the diagonal blocks (Newton steps with damping).
 yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
-  if (!c->f_rp) {
-    const yasps_status s = build_full_matrix(c);
-    if (s) return s;
-  }
   HIPCHK(c, hipMemsetAsync(c->flags, 0, 4, c->stream));
   c->prof.begin(YASPS_K_ASSEMBLE);
   const bool mixed = c->prm.precision == YASPS_MIXED;
@@ -963,11 +919,6 @@ yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
                      dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
   launch_add_mass_shift(c->n, c->ps.rp, c->P.mass, shift, c->vals_s, mixed ? c->vals_s32 : nullptr, c->stream);
-  if (mixed)
-    launch_full_gather_f32(c->f_nnz, c->f_src, c->ps.nnzb, c->vals_s32, dyn ? c->vals_d32 : nullptr, c->f_vals32,
-                           c->stream);
-  else
-    launch_far_gather(c->nfar, c->far_src, c->nnzb_sd, c->vals_s, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)
@@ -1093,17 +1044,19 @@ yasps_status yasps_pcg(yasps_ctx* c, const double* b, double* x, double rtol, in
   const yasps_status s = pcg_args(c, b, x, rtol, max_iter);
   if (s) return s;
   HIPCHK(c, hipSetDevice(c->device));
-  return pcg_call(c, b, x, rtol, max_iter, info, c->pcg_work);
+  return pcg_call(c, b, x, rtol, max_iter, info, c->pcg_work.p);
 }
 
 yasps_status yasps_pcg_noalloc(yasps_ctx* c, const double* b, double* x, double rtol, int32_t max_iter,
                                yasps_pcg_info* info) {
   const yasps_status s = pcg_args(c, b, x, rtol, max_iter);
   if (s) return s;
-  const size_t need = pcg_workspace_bytes(c->n);
+  const long long slots = (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0);
+  const size_t need = pcg_workspace_bytes(c->n, slots);
   if (need > NOALLOC_SCRATCH_BYTES)
-    return fail(c, YASPS_E_ARG, "yasps_pcg_noalloc: " + std::to_string(c->n) + " free vertices need " +
-                                    std::to_string(need) + " bytes of solver workspace, more than the fixed " +
+    return fail(c, YASPS_E_ARG, "yasps_pcg_noalloc: " + std::to_string(c->n) + " free vertices and " +
+                                    std::to_string(slots) + " SpMV slots need " + std::to_string(need) +
+                                    " bytes of solver workspace, more than the fixed " +
                                     std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte array (use yasps_pcg)");
   HIPCHK(c, hipSetDevice(c->device));
   void* work = nullptr;
@@ -1118,14 +1071,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   if (!(p.shift >= 0.0)) return fail(c, YASPS_E_ARG, "shift must be >= 0");
   if (p.hessian != YASPS_PROJECTED && p.hessian != YASPS_EXACT) return fail(c, YASPS_E_ARG, "unknown hessian mode");
   HIPCHK(c, hipSetDevice(c->device));
-  hipEvent_t ev[5];
-  for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
-    }
-  } guard{ev};
+  hipEvent_t* ev = c->ev;  // created once with the context
   yasps_newton_info ni{};
   HIPCHK(c, hipEventRecord(ev[0], c->stream));
   yasps_eval_info ei{};
@@ -1139,7 +1085,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   double rel = 0.0;
   int status = 0;
   const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter, c->prm.precision == YASPS_MIXED,
-                           c->pcg_work, &rel, &status, c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
+                           c->pcg_work.p, &rel, &status, c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
   c->prof.collect();
   if (it < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
   HIPCHK(c, hipEventRecord(ev[3], c->stream));
@@ -1257,10 +1203,38 @@ yasps_status yasps_spmv(yasps_ctx* c, const double* x, double* y) {
   if (!c || !x || !y) return fail(c, YASPS_E_ARG, "NULL argument");
   if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "spmv called before assembly");
   HIPCHK(c, hipSetDevice(c->device));
-  c->prof.begin(YASPS_K_SPMV);
-  launch_spmv(pcg_matrix(c), x, y, c->pcg_work, c->stream);
-  c->prof.end();
+  launch_spmv(pcg_matrix(c), x, y, c->pcg_work.p, c->stream, &c->prof);
   HIPCHK(c, hipGetLastError());
+  return YASPS_OK;
+}
+
+yasps_status yasps_lm_shift(yasps_ctx* c, double frac, double* out) {
+  if (!c || !out) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (!(frac >= 0.0)) return fail(c, YASPS_E_ARG, "frac must be >= 0");
+  if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "lm_shift called before assembly");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int n = c->n;
+  if (n == 0) {
+    *out = 0.0;
+    return YASPS_OK;
+  }
+  const bool mixed = c->prm.precision == YASPS_MIXED;
+  const bool dyn = c->nc > 0;
+  // ratios into x_trial, sorted into b_tmp (both (n, 3) work vectors of the context)
+  launch_diag_ratio(n, c->ps.rp, mixed ? (const void*)c->vals_s32 : (const void*)c->vals_s, dyn ? c->ddiag : nullptr,
+                    dyn ? (mixed ? (const void*)c->vals_d32 : (const void*)c->vals_d) : nullptr, mixed, c->P.mass,
+                    c->x_trial, c->stream);
+  HIPCHK(c, hipGetLastError());
+  size_t bytes = 0;
+  HIPCHK(c, rocprim::radix_sort_keys(nullptr, bytes, c->x_trial, c->b_tmp, (size_t)n, 0u, 64u, c->stream));
+  grow_arena(c, bytes);
+  if (bytes > c->di_arena_bytes) return fail(c, YASPS_E_HIP, "hipMalloc of the sort scratch");
+  HIPCHK(c, rocprim::radix_sort_keys(c->di_arena, bytes, c->x_trial, c->b_tmp, (size_t)n, 0u, 64u, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->b_tmp + (n - 1) / 2, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double med = n % 2 ? c->host_scal[0] : 0.5 * (c->host_scal[0] + c->host_scal[1]);
+  *out = frac * med;
   return YASPS_OK;
 }
 

@@ -149,43 +149,6 @@ void launch_block_sums(int nslots, long long ncontrib, const int32_t* cptr, cons
   }
 }
 
-// Precision form: vf[q * nnz + k] = entry q of the float32 source block of
-// full-row entry k (transposed when src < 0), one thread per entry; the lanes
-// write consecutive addresses for every q.
-__global__ __launch_bounds__(RED_BLOCK) void full_gather_f32_kernel(long long nnz, const int32_t* __restrict__ src,
-                                                                    int nnzb_s, const float* __restrict__ vs,
-                                                                    const float* __restrict__ vd,
-                                                                    float* __restrict__ vf) {
-  const long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (k >= nnz) return;
-  const int32_t sk = src[k];
-  const bool tr = sk < 0;
-  const int b = tr ? -sk - 1 : sk;
-  const float* base = b < nnzb_s ? vs + 9 * (size_t)b : vd + 9 * (size_t)(b - nnzb_s);
-  float B[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) B[q] = base[q];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) vf[(size_t)(3 * i + j) * nnz + k] = tr ? B[3 * j + i] : B[3 * i + j];
-}
-
-__global__ __launch_bounds__(RED_BLOCK) void far_gather_kernel(int nfar, const int32_t* __restrict__ far_src,
-                                                               int nnzb_total, double* __restrict__ vals) {
-  const int j = blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (j >= nfar) return;
-  const double* B = vals + 9 * (size_t)far_src[j];
-  double v[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) v[q] = B[q];
-  double* D = vals + 9 * ((size_t)nnzb_total + j);
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) D[3 * i + k] = v[3 * k + i];
-}
-
 template <class T>
 __global__ __launch_bounds__(RED_BLOCK) void mass_shift_kernel(int n, const int32_t* __restrict__ rp,
                                                                const double* __restrict__ mass, double shift,
@@ -325,19 +288,6 @@ void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const 
   launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s);
 }
 
-void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
-                            float* vf, hipStream_t s) {
-  if (nnz <= 0) return;
-  hipLaunchKernelGGL(full_gather_f32_kernel, dim3((unsigned)((nnz + RED_BLOCK - 1) / RED_BLOCK)), dim3(RED_BLOCK),
-                     0, s, nnz, src, nnzb_s, vs, vd, vf);
-}
-
-void launch_far_gather(int nfar, const int32_t* far_src, int nnzb_total, double* vals, hipStream_t s) {
-  if (nfar <= 0) return;
-  hipLaunchKernelGGL(far_gather_kernel, dim3((nfar + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s, nfar,
-                     far_src, nnzb_total, vals);
-}
-
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
                            float* vals_s32, hipStream_t s) {
   if (n == 0 || shift == 0.0) return;
@@ -346,6 +296,41 @@ void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, 
     hipLaunchKernelGGL((mass_shift_kernel<float>), grid, dim3(RED_BLOCK), 0, s, n, row_ptr_s, mass, shift, vals_s32);
   else
     hipLaunchKernelGGL((mass_shift_kernel<double>), grid, dim3(RED_BLOCK), 0, s, n, row_ptr_s, mass, shift, vals_s);
+}
+
+namespace {
+
+// ratio[v] = |tr(D_v)| / (3 m_v), D_v the assembled diagonal block (static + dynamic)
+template <class T>
+__global__ __launch_bounds__(RED_BLOCK) void diag_ratio_kernel(int n, const int32_t* __restrict__ rp_s,
+                                                               const T* __restrict__ vs,
+                                                               const int32_t* __restrict__ ddiag,
+                                                               const T* __restrict__ vd,
+                                                               const double* __restrict__ mass,
+                                                               double* __restrict__ ratio) {
+  const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (v >= n) return;
+  const T* d = vs + 9 * (size_t)rp_s[v];
+  double tr = double(d[0]) + double(d[4]) + double(d[8]);
+  if (ddiag && ddiag[v] >= 0) {
+    const T* e = vd + 9 * (size_t)ddiag[v];
+    tr += double(e[0]) + double(e[4]) + double(e[8]);
+  }
+  ratio[v] = fabs(tr) / (3.0 * mass[v]);
+}
+
+}  // namespace
+
+void launch_diag_ratio(int n, const int32_t* row_ptr_s, const void* vals_s, const int32_t* ddiag, const void* vals_d,
+                       bool f32, const double* mass, double* ratio, hipStream_t s) {
+  if (n == 0) return;
+  const dim3 g((n + RED_BLOCK - 1) / RED_BLOCK), b(RED_BLOCK);
+  if (f32)
+    hipLaunchKernelGGL((diag_ratio_kernel<float>), g, b, 0, s, n, row_ptr_s, static_cast<const float*>(vals_s), ddiag,
+                       static_cast<const float*>(vals_d), mass, ratio);
+  else
+    hipLaunchKernelGGL((diag_ratio_kernel<double>), g, b, 0, s, n, row_ptr_s, static_cast<const double*>(vals_s),
+                       ddiag, static_cast<const double*>(vals_d), mass, ratio);
 }
 
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s, const int32_t* ddiag,

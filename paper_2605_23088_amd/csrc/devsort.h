@@ -1,0 +1,86 @@
+// Device sort / scan helpers of the index builders (rocPRIM), and the
+// temporary-memory arena they draw from.  No paper arithmetic here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <vector>
+
+namespace yasps {
+namespace devsort {
+
+constexpr int DI_BLOCK = 256;
+
+inline int bits_for(long long v) {  // bits needed for values 0 .. v
+  int b = 1;
+  while ((1ll << b) <= v) ++b;
+  return b;
+}
+
+inline int grid_of(long long m) { return (int)std::max<long long>(1, (m + DI_BLOCK - 1) / DI_BLOCK); }
+
+// Temporaries of one build, carved from the caller's arena while it lasts
+// (256-byte aligned), else allocated and freed when done; `used` is the arena
+// size the whole build needs.
+struct Temp {
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
+  std::vector<void*> ptrs;
+  hipError_t err = hipSuccess;
+  template <class T>
+  T* get(size_t count) {
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+    void* p = nullptr;
+    if (used + bytes <= cap) {
+      p = arena + used;
+    } else if (err == hipSuccess) {
+      err = hipMalloc(&p, bytes);
+      if (p) ptrs.push_back(p);
+    }
+    used += bytes;
+    return static_cast<T*>(p);
+  }
+  ~Temp() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <class K, class V>
+hipError_t sort_pairs(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long long m, int end_bit, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  size_t bytes = 0;
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
+  if (e != hipSuccess) return e;
+  void* store = tmp.get<char>(bytes);
+  if (tmp.err != hipSuccess) return tmp.err;
+  return rocprim::radix_sort_pairs(store, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
+}
+
+// out[0] = 0, out[k + 1] = in[0] + ... + in[k]  (k < m)
+inline hipError_t prefix(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(int32_t), s);
+  if (e != hipSuccess || m == 0) return e;
+  size_t bytes = 0;
+  e = rocprim::inclusive_scan(nullptr, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  void* store = tmp.get<char>(bytes);
+  if (tmp.err != hipSuccess) return tmp.err;
+  return rocprim::inclusive_scan(store, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
+}
+
+inline hipError_t inclusive(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  size_t bytes = 0;
+  hipError_t e = rocprim::inclusive_scan(nullptr, bytes, in, out, (size_t)m, rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  void* store = tmp.get<char>(bytes);
+  if (tmp.err != hipSuccess) return tmp.err;
+  return rocprim::inclusive_scan(store, bytes, in, out, (size_t)m, rocprim::plus<int32_t>(), s);
+}
+
+}  // namespace devsort
+}  // namespace yasps

@@ -1,6 +1,6 @@
 // Device build of the dynamic (contact) part's index structures: validation,
-// storage order, block pattern and slot map, staging layout, and the SpMV's
-// full row layout over the static and dynamic parts.
+// storage order, block pattern and slot map, and staging layout (the SpMV plan
+// of the part is built from the pattern afterwards, spmvplan.hip).
 //
 // The rules are those of the host builder (pattern.h / pattern.cpp, appendix
 // "Global Hessian Compression"): the block pattern is the sorted, deduplicated
@@ -13,28 +13,20 @@
 // change (section "Implementation", static / dynamic split).
 #include <hip/hip_runtime.h>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include <algorithm>
 #include <vector>
 
 #include "common.h"
+#include "devsort.h"
 #include "kernels.h"
 
 namespace yasps {
 
+using namespace devsort;
+
 namespace {
 
-constexpr int DI_BLOCK = 256;
-
 YDEV int verts_of(int t) { return t == 3 ? 2 : (t == 2 ? 3 : 4); }
-
-int bits_for(long long v) {  // bits needed for values 0 .. v
-  int b = 1;
-  while ((1ll << b) <= v) ++b;
-  return b;
-}
 
 // Per stencil (API order): the first failing check (1 unknown type, 2 bad or
 // repeated vertex ids, 3 no free vertex) folded into err = min((s << 2) | reason),
@@ -192,73 +184,6 @@ __global__ void gptr_kernel(int n, int ng, const uint32_t* __restrict__ key, int
   gptr[v] = lo;
 }
 
-// Off-diagonal dynamic blocks keyed by (column, row) for the transposed
-// entries of the full rows; the pad sorts last.
-__global__ void transpose_keys_kernel(int nnzb, int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                      uint64_t pad, uint64_t* __restrict__ tkey, int32_t* __restrict__ tval) {
-  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (r >= n) return;
-  for (int k = rp[r]; k < rp[r + 1]; ++k) {
-    const int c = col[k];
-    tkey[k] = c != r ? (((uint64_t)c << 32) | (uint64_t)r) : pad;
-    tval[k] = k;
-  }
-}
-
-__global__ void transpose_count_kernel(int nt, const uint64_t* __restrict__ tkey, int32_t* __restrict__ tcnt) {
-  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (i >= nt) return;
-  atomicAdd(&tcnt[(int)(tkey[i] >> 32)], 1);
-}
-
-// full row r: static share, dynamic upper blocks, dynamic transposed blocks
-__global__ void full_count_kernel(int n, const int32_t* __restrict__ sf_ptr, const int32_t* __restrict__ rp,
-                                  const int32_t* __restrict__ tptr, int32_t* __restrict__ fcnt) {
-  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (r >= n) return;
-  fcnt[r] = (sf_ptr[r + 1] - sf_ptr[r]) + (rp[r + 1] - rp[r]) + (tptr[r + 1] - tptr[r]);
-}
-
-__global__ void full_fill_kernel(int n, int nnzb_s, const int32_t* __restrict__ sf_ptr,
-                                 const int32_t* __restrict__ sf_col, const int32_t* __restrict__ sf_src,
-                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                 const int32_t* __restrict__ tptr, const uint64_t* __restrict__ tkey,
-                                 const int32_t* __restrict__ tval, const int32_t* __restrict__ f_rp,
-                                 int32_t* __restrict__ f_col, int32_t* __restrict__ f_src) {
-  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (r >= n) return;
-  int p = f_rp[r];
-  for (int k = sf_ptr[r]; k < sf_ptr[r + 1]; ++k, ++p) {
-    f_col[p] = sf_col[k];
-    f_src[p] = sf_src[k];
-  }
-  for (int k = rp[r]; k < rp[r + 1]; ++k, ++p) {
-    f_col[p] = col[k];
-    f_src[p] = nnzb_s + k;
-  }
-  for (int t = tptr[r]; t < tptr[r + 1]; ++t, ++p) {
-    f_col[p] = (int)(tkey[t] & 0xffffffffu);
-    f_src[p] = -(nnzb_s + tval[t]) - 1;
-  }
-}
-
-// first row of each XCD range: work(r) = f_rp[r] + row_cost r reaches x / PCG_XCDS of the total
-__global__ void xsplit_kernel(int n, const int32_t* __restrict__ f_rp, int row_cost, int* xsplit) {
-  const int x = threadIdx.x;
-  if (x > PCG_XCDS) return;
-  const long long work = (long long)f_rp[n] + (long long)row_cost * n;
-  const long long target = work * x / PCG_XCDS;
-  int lo = 0, hi = n;  // smallest r with f_rp[r] + row_cost r >= target
-  while (lo < hi) {
-    const int mid = (lo + hi) / 2;
-    if ((long long)f_rp[mid] + (long long)row_cost * mid < target)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  xsplit[x] = x == PCG_XCDS ? n : lo;
-}
-
 __global__ void fill_i32_kernel(long long m, int32_t v, int32_t* __restrict__ p) {
   const long long i = (long long)blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i < m) p[i] = v;
@@ -269,106 +194,6 @@ __global__ void iota_kernel(int m, int32_t* __restrict__ p) {
   if (i < m) p[i] = i;
 }
 
-int grid_of(long long m) { return (int)std::max<long long>(1, (m + DI_BLOCK - 1) / DI_BLOCK); }
-
-// Temporaries of one build, carved from the caller's arena while it lasts
-// (256-byte aligned), else allocated and freed when done; `used` is the arena
-// size the whole build needs.
-struct Temp {
-  char* arena = nullptr;
-  size_t cap = 0, used = 0;
-  std::vector<void*> ptrs;
-  hipError_t err = hipSuccess;
-  template <class T>
-  T* get(size_t count) {
-    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
-    void* p = nullptr;
-    if (used + bytes <= cap) {
-      p = arena + used;
-    } else if (err == hipSuccess) {
-      err = hipMalloc(&p, bytes);
-      if (p) ptrs.push_back(p);
-    }
-    used += bytes;
-    return static_cast<T*>(p);
-  }
-  ~Temp() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-};
-
-template <class K, class V>
-hipError_t sort_pairs(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long long m, int end_bit, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  size_t bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
-  if (e != hipSuccess) return e;
-  void* store = tmp.get<char>(bytes);
-  if (tmp.err != hipSuccess) return tmp.err;
-  return rocprim::radix_sort_pairs(store, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
-}
-
-// out[0] = 0, out[k + 1] = in[0] + ... + in[k]  (k < m)
-hipError_t prefix(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(out, 0, sizeof(int32_t), s);
-  if (e != hipSuccess || m == 0) return e;
-  size_t bytes = 0;
-  e = rocprim::inclusive_scan(nullptr, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
-  if (e != hipSuccess) return e;
-  void* store = tmp.get<char>(bytes);
-  if (tmp.err != hipSuccess) return tmp.err;
-  return rocprim::inclusive_scan(store, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
-}
-
-hipError_t inclusive(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  size_t bytes = 0;
-  hipError_t e = rocprim::inclusive_scan(nullptr, bytes, in, out, (size_t)m, rocprim::plus<int32_t>(), s);
-  if (e != hipSuccess) return e;
-  void* store = tmp.get<char>(bytes);
-  if (tmp.err != hipSuccess) return tmp.err;
-  return rocprim::inclusive_scan(store, bytes, in, out, (size_t)m, rocprim::plus<int32_t>(), s);
-}
-
-// Far entries: per row, the entries below the diagonal whose stored block is
-// a contact block (at or above nnzb_s) more than far_rows rows back.
-YDEV bool far_entry(int32_t sk, int r, int c, int nnzb_s, int far_rows) {
-  return sk < 0 && -sk - 1 >= nnzb_s && r - c > far_rows;
-}
-
-__global__ __launch_bounds__(DI_BLOCK) void far_count_kernel(int n, int nnzb_s, int far_rows,
-                                                             const int32_t* __restrict__ f_rp,
-                                                             const int32_t* __restrict__ f_col,
-                                                             const int32_t* __restrict__ f_src,
-                                                             int32_t* __restrict__ cnt) {
-  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (r >= n) return;
-  int c = 0;
-  for (int k = f_rp[r]; k < f_rp[r + 1]; ++k) c += far_entry(f_src[k], r, f_col[k], nnzb_s, far_rows);
-  cnt[r] = c;
-}
-
-// Row by row, in entry order: far copy j gets the stored block, the entry
-// the code nnzb_total + j.
-__global__ __launch_bounds__(DI_BLOCK) void far_fill_kernel(int n, int nnzb_s, int far_rows, int nnzb_total,
-                                                            const int32_t* __restrict__ f_rp,
-                                                            const int32_t* __restrict__ f_col,
-                                                            int32_t* __restrict__ f_src,
-                                                            const int32_t* __restrict__ ptr,
-                                                            int32_t* __restrict__ far_src) {
-  const int r = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (r >= n) return;
-  int j = ptr[r];
-  for (int k = f_rp[r]; k < f_rp[r + 1]; ++k) {
-    const int32_t sk = f_src[k];
-    if (far_entry(sk, r, f_col[k], nnzb_s, far_rows)) {
-      far_src[j] = -sk - 1;
-      f_src[k] = nnzb_total + j;
-      ++j;
-    }
-  }
-}
-
 }  // namespace
 
 #define DI_CHECK(expr)                       \
@@ -377,34 +202,7 @@ __global__ __launch_bounds__(DI_BLOCK) void far_fill_kernel(int n, int nnzb_s, i
     if (e_ != hipSuccess) return -1;         \
   } while (0)
 
-int split_far_entries(int n, const int32_t* f_rp, const int32_t* f_col, int32_t* f_src, int nnzb_s, int nnzb_total,
-                      int far_rows, int32_t** far_src, int* nfar, const std::function<void*(size_t)>& alloc,
-                      hipStream_t s) {
-  *far_src = nullptr;
-  *nfar = 0;
-  if (n == 0) return 0;
-  Temp tmp;
-  int32_t* cnt = tmp.get<int32_t>(n);
-  int32_t* ptr = tmp.get<int32_t>((size_t)n + 1);
-  if (tmp.err != hipSuccess) return -1;
-  hipLaunchKernelGGL(far_count_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, nnzb_s, far_rows, f_rp, f_col,
-                     f_src, cnt);
-  DI_CHECK(prefix(tmp, cnt, ptr, n, s));
-  int total = 0;
-  DI_CHECK(hipMemcpyAsync(&total, ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
-  DI_CHECK(hipStreamSynchronize(s));
-  if (total == 0) return 0;
-  *far_src = static_cast<int32_t*>(alloc((size_t)total * sizeof(int32_t)));
-  if (!*far_src) return -1;
-  hipLaunchKernelGGL(far_fill_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, nnzb_s, far_rows, nnzb_total, f_rp,
-                     f_col, f_src, ptr, *far_src);
-  DI_CHECK(hipGetLastError());
-  DI_CHECK(hipStreamSynchronize(s));  // the temporaries are freed on return
-  *nfar = total;
-  return 0;
-}
-
-int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(size_t)>& alloc,
+int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(int, size_t)>& alloc,
                         hipStream_t s) {
   const int n = in.n, nc = in.nc;
   Temp tmp;
@@ -416,14 +214,13 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
     DynIndexOut& o;
     ~Need() { o.arena_needed = t.used; }
   } need{tmp, out};
-  // small device scalars: err, counts[2] (block / gradient entries), offdiag, gcount[32], xsplit[9]
+  // small device scalars: err, counts[2] (block / gradient entries), offdiag, gcount[32]
   int* scal = tmp.get<int>(48);
   DI_CHECK(tmp.err);
   int* err = scal;
   int* counts = scal + 1;
   int* offdiag = scal + 3;
   int* gcount = scal + 4;
-  int* xsplit = scal + 36;
   const int init[4] = {0x7fffffff, 0, 0, 0};
   DI_CHECK(hipMemsetAsync(scal, 0, 48 * sizeof(int), s));
   DI_CHECK(hipMemcpyAsync(scal, init, sizeof(init), hipMemcpyHostToDevice, s));
@@ -462,7 +259,7 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   uint32_t* gkey_s = tmp.get<uint32_t>(nge);
   int32_t* gval = tmp.get<int32_t>(nge);
   int32_t* gval_s = tmp.get<int32_t>(nge);
-  int32_t* sidx = static_cast<int32_t*>(alloc(sizeof(int32_t) * std::max<long long>(nge, 1)));
+  int32_t* sidx = static_cast<int32_t*>(alloc(DI_SIDX, sizeof(int32_t) * std::max<long long>(nge, 1)));
   DI_CHECK(tmp.err);
   if (!sidx) return -1;
   if (nc) {
@@ -487,15 +284,17 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
     DI_CHECK(hipMemcpyAsync(&nnzb, blk + ne - 1, sizeof(int), hipMemcpyDeviceToHost, s));
     DI_CHECK(hipStreamSynchronize(s));
   }
-  auto ialloc = [&](long long m) { return static_cast<int32_t*>(alloc(sizeof(int32_t) * std::max<long long>(m, 1))); };
-  out.rp = ialloc(n + 1);
-  out.col = ialloc(nnzb);
-  out.cptr = ialloc(nnzb + 1);
-  out.slot = ialloc(10ll * nc);
-  out.spos = ialloc(10ll * nc);
-  out.gpos = ialloc(4ll * nc);
-  out.gptr = ialloc(n + 1);
-  out.ddiag = ialloc(n);
+  auto ialloc = [&](int which, long long m) {
+    return static_cast<int32_t*>(alloc(which, sizeof(int32_t) * std::max<long long>(m, 1)));
+  };
+  out.rp = ialloc(DI_RP, n + 1);
+  out.col = ialloc(DI_COL, nnzb);
+  out.cptr = ialloc(DI_CPTR, nnzb + 1);
+  out.slot = ialloc(DI_SLOT, 10ll * nc);
+  out.spos = ialloc(DI_SPOS, 10ll * nc);
+  out.gpos = ialloc(DI_GPOS, 4ll * nc);
+  out.gptr = ialloc(DI_GPTR, n + 1);
+  out.ddiag = ialloc(DI_DDIAG, n);
   out.sidx = sidx;
   if (!out.rp || !out.col || !out.cptr || !out.slot || !out.spos || !out.gpos || !out.gptr || !out.ddiag) return -1;
   int32_t* rowcnt = tmp.get<int32_t>(n);
@@ -513,45 +312,11 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   if (ng) hipLaunchKernelGGL(grads_kernel, dim3(grid_of(ng)), dim3(DI_BLOCK), 0, s, ng, nc, gval_s, out.gpos);
   hipLaunchKernelGGL(gptr_kernel, dim3(grid_of(n + 1)), dim3(DI_BLOCK), 0, s, n, ng, gkey_s, out.gptr);
 
-  // 4. transposed dynamic blocks (sorted by column, then row) and the full rows
-  uint64_t* tkey = tmp.get<uint64_t>(nnzb);
-  uint64_t* tkey_s = tmp.get<uint64_t>(nnzb);
-  int32_t* tval = tmp.get<int32_t>(nnzb);
-  int32_t* tval_s = tmp.get<int32_t>(nnzb);
-  int32_t* tcnt = tmp.get<int32_t>(n);
-  int32_t* tptr = tmp.get<int32_t>(n + 1);
-  int32_t* fcnt = tmp.get<int32_t>(n);
-  DI_CHECK(tmp.err);
-  DI_CHECK(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * std::max(n, 1), s));
-  int noff = 0;
-  DI_CHECK(hipMemcpyAsync(&noff, offdiag, sizeof(int), hipMemcpyDeviceToHost, s));
-  DI_CHECK(hipStreamSynchronize(s));
-  if (nnzb) {
-    hipLaunchKernelGGL(transpose_keys_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, nnzb, n, out.rp, out.col, bpad,
-                       tkey, tval);
-    DI_CHECK(sort_pairs(tmp, tkey, tkey_s, tval, tval_s, nnzb, 32 + nbits, s));
-    if (noff) hipLaunchKernelGGL(transpose_count_kernel, dim3(grid_of(noff)), dim3(DI_BLOCK), 0, s, noff, tkey_s, tcnt);
-  }
-  DI_CHECK(prefix(tmp, tcnt, tptr, n, s));
-  if (n) hipLaunchKernelGGL(full_count_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, in.sf_ptr, out.rp, tptr, fcnt);
-  out.f_rp = ialloc(n + 1);
-  if (!out.f_rp) return -1;
-  DI_CHECK(prefix(tmp, fcnt, out.f_rp, n, s));
-  const long long f_nnz = (long long)in.sf_nnz + nnzb + noff;
-  out.f_col = ialloc(f_nnz);
-  out.f_src = ialloc(f_nnz);
-  if (!out.f_col || !out.f_src) return -1;
-  if (n)
-    hipLaunchKernelGGL(full_fill_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, in.nnzb_s, in.sf_ptr, in.sf_col,
-                       in.sf_src, out.rp, out.col, tptr, tkey_s, tval_s, out.f_rp, out.f_col, out.f_src);
-  hipLaunchKernelGGL(xsplit_kernel, dim3(1), dim3(64), 0, s, n, out.f_rp, in.row_cost, xsplit);
   DI_CHECK(hipGetLastError());
-  DI_CHECK(hipMemcpyAsync(out.xsplit, xsplit, sizeof(out.xsplit), hipMemcpyDeviceToHost, s));
-  DI_CHECK(hipStreamSynchronize(s));
+  DI_CHECK(hipStreamSynchronize(s));  // the temporaries go out of scope
   out.nnzb = nnzb;
   out.nent = ne;
   out.ngrad = ng;
-  out.f_nnz = f_nnz;
   return 0;
 }
 

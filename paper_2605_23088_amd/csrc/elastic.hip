@@ -17,6 +17,7 @@
 // so block (a, b) = sum_jk D'_aj D'_bk [P]_(jk) with [P]_(jk) the 3x3 block of
 // the projected matrix at column blocks (j, k).
 #include "blockreduce.h"
+#include "contact_math.h"
 #include "eigen.h"
 #include "kernels.h"
 #include "snh_math.h"
@@ -270,7 +271,62 @@ YDEV void scatter_tet(const SnhArgs& a, int t, const Tet<R>& T, const Sym<9, R>&
   }
 }
 
-template <class R, bool EXACT>
+// X-space projection (the paper's plain "YASPS" rows of Table 1): Proj of
+// the x-space Hessian J_F^T A J_F (A = d2Psi/dF2, exact) over the tet's free
+// vertices.  With a 4 x 3 matrix S whose columns span the free directions,
+// C = D'^T S and Y = (C (x) I3)^T A (C (x) I3) is that Hessian in the basis
+// S (x) I3, so the x-space blocks are sum_pq S_ap S_bq Proj(Y)_(pq): the
+// same map as the F-space scatter with D' replaced by S.
+//  * all four vertices free: S = the Helmert basis (the energy is translation
+//    invariant, so the 12 x 12 Hessian annihilates the translations and the
+//    projection reduces exactly to this 9 x 9 one);
+//  * otherwise S selects the free vertices (columns of the fixed ones stay
+//    zero, and Proj of a matrix padded with zero rows and columns is the
+//    padded projection), which is the projection of the free principal
+//    submatrix.
+template <class R>
+YDEV void xspace_projection(Tet<R>& T, const Sym<9, R>& A, int n_free, Sym<9, R>& Y) {
+  R S[4][3];
+  const bool all_free = T.v[0] < n_free && T.v[1] < n_free && T.v[2] < n_free && T.v[3] < n_free;
+  int nf = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const bool fr = T.v[a] < n_free;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      S[a][p] = all_free ? R(cmath::helmert(a, p)) : ((fr && nf == p) ? R(1) : R(0));
+    nf += fr ? 1 : 0;
+  }
+  R C[3][3];  // C[j][p] = sum_a D'_aj S_ap
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      R acc = R(0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc = fmaR(T.Dp[a][j], S[a][p], acc);
+      C[j][p] = acc;
+    }
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int c = r; c < 9; ++c) {
+      const int i = r % 3, p = r / 3, l = c % 3, q = c / 3;
+      R acc = R(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc = fmaR(C[j][p] * C[k][q], A(i + 3 * j, l + 3 * k), acc);
+      Y(r, c) = acc;
+    }
+  psd_project<9, R>(Y);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) T.Dp[a][p] = S[a][p];
+}
+
+template <class R, bool EXACT, bool XSPACE>
 __global__ __launch_bounds__(EVAL_BLOCK) void snh_eval_kernel(SnhArgs a) {
   __shared__ double lds[EVAL_BLOCK];
   const int t = blockIdx.x * EVAL_BLOCK + threadIdx.x;
@@ -286,21 +342,34 @@ __global__ __launch_bounds__(EVAL_BLOCK) void snh_eval_kernel(SnhArgs a) {
     }
     if (!ok || !finite(e)) atomicOr(a.flags, FLAG_NONFINITE);
     // projected: closed-form eigensystem of d2Psi/dF2 (snh_math.h); exact: the Hessian itself
+    // x-space: Proj of the free-vertex x-space Hessian (xspace_projection)
     Sym<9, R> H;
     if constexpr (sizeof(R) == 8) {
-      if (EXACT)
+      if (EXACT || XSPACE)
         snh_hessian<double>(T, H);
       else
         snh::projected_hessian<double>(T.F, T.mu, T.lam, T.vol, H);
-      scatter_tet<double, double>(a, t, T, H, a.blk);
+      if (XSPACE && !EXACT) {
+        Sym<9, double> Y;
+        xspace_projection<double>(T, H, a.n_free, Y);
+        scatter_tet<double, double>(a, t, T, Y, a.blk);
+      } else {
+        scatter_tet<double, double>(a, t, T, H, a.blk);
+      }
     } else {
       Tet<R> TR;
       convert_tet<R>(T, TR);
-      if (EXACT)
+      if (EXACT || XSPACE)
         snh_hessian<R>(TR, H);
       else
         snh::projected_hessian<R>(TR.F, TR.mu, TR.lam, TR.vol, H);
-      scatter_tet<R, float>(a, t, TR, H, a.blk32);
+      if (XSPACE && !EXACT) {
+        Sym<9, R> Y;
+        xspace_projection<R>(TR, H, a.n_free, Y);
+        scatter_tet<R, float>(a, t, TR, Y, a.blk32);
+      } else {
+        scatter_tet<R, float>(a, t, TR, H, a.blk32);
+      }
     }
   }
   const double s = block_sum<EVAL_BLOCK>(e, lds);
@@ -348,19 +417,24 @@ __global__ __launch_bounds__(EVAL_BLOCK) void snh_theta_kernel(SnhArgs a, const 
 
 }  // namespace
 
-void launch_snh_eval(const SnhArgs& a, bool exact, bool mixed, hipStream_t s) {
+void launch_snh_eval(const SnhArgs& a, bool exact, bool mixed, bool xspace, hipStream_t s) {
   if (a.nt == 0) return;
   const int grid = (a.nt + EVAL_BLOCK - 1) / EVAL_BLOCK;
+  const dim3 g(grid), b(EVAL_BLOCK);
   if (mixed) {
     if (exact)
-      hipLaunchKernelGGL((snh_eval_kernel<float, true>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+      hipLaunchKernelGGL((snh_eval_kernel<float, true, false>), g, b, 0, s, a);
+    else if (xspace)
+      hipLaunchKernelGGL((snh_eval_kernel<float, false, true>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((snh_eval_kernel<float, false>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+      hipLaunchKernelGGL((snh_eval_kernel<float, false, false>), g, b, 0, s, a);
   } else {
     if (exact)
-      hipLaunchKernelGGL((snh_eval_kernel<double, true>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+      hipLaunchKernelGGL((snh_eval_kernel<double, true, false>), g, b, 0, s, a);
+    else if (xspace)
+      hipLaunchKernelGGL((snh_eval_kernel<double, false, true>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((snh_eval_kernel<double, false>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+      hipLaunchKernelGGL((snh_eval_kernel<double, false, false>), g, b, 0, s, a);
   }
 }
 

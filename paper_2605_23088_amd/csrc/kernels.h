@@ -33,7 +33,8 @@ struct SnhArgs {
   double* e_part;         // one energy partial per workgroup
   uint32_t* flags;
 };
-void launch_snh_eval(const SnhArgs& a, bool exact, bool mixed, hipStream_t s);
+// xspace: project the x-space Hessian over the free vertices instead of d2Psi/dF2.
+void launch_snh_eval(const SnhArgs& a, bool exact, bool mixed, bool xspace, hipStream_t s);
 // Energy only at x (line search); writes one partial per workgroup.
 void launch_snh_energy(const SnhArgs& a, hipStream_t s);
 // grad_theta[t] = -lambda_t . d/dx (Psi_t / theta_t)
@@ -134,12 +135,6 @@ struct DynIndexIn {
   int n, nall, nc;
   const int32_t* type;     // [nc]
   const int32_t* idx;      // [4][nc], API order
-  int nnzb_s;              // static blocks (the dynamic ones follow them in src numbering)
-  const int32_t* sf_ptr;   // [n + 1] static share of each full row
-  const int32_t* sf_col;
-  const int32_t* sf_src;
-  long long sf_nnz;
-  int row_cost;            // per-row work in blocks for the XCD split
   void* arena;             // device scratch for the temporaries (may be null)
   size_t arena_bytes;
 };
@@ -147,37 +142,18 @@ struct DynIndexOut {
   int err_stencil = -1, err_reason = 0;  // first invalid stencil: 1 type, 2 vertex ids, 3 no free vertex
   int gcount[32] = {};                    // stencils per group key type * 8 + nfree (or PT_TRIANGLE_FREE)
   int nnzb = 0, nent = 0, ngrad = 0;      // dynamic blocks, staged block / gradient contributions
-  long long f_nnz = 0;
-  int xsplit[PCG_XCDS + 1] = {};
   size_t arena_needed = 0;                // scratch the temporaries took (to size the next arena)
-  // device arrays from `alloc` (owned by the caller): storage-order vertex ids
-  // [4][nc], pattern rows [n + 1] / columns, slot map [nc][10] (API order),
-  // staging (spos [10][nc], gpos [4][nc], cptr [nnzb + 1], gptr [n + 1]),
-  // dynamic diagonal block per vertex [n], full rows (row_ptr [n + 1], col, src)
+  // device arrays from `alloc` (owned by the caller; `alloc(which, bytes)` with
+  // which = the DI_* id below): storage-order vertex ids [4][nc], pattern rows
+  // [n + 1] / columns, slot map [nc][10] (API order), staging (spos [10][nc],
+  // gpos [4][nc], cptr [nnzb + 1], gptr [n + 1]), dynamic diagonal block per
+  // vertex [n]
   int32_t *sidx = nullptr, *rp = nullptr, *col = nullptr, *slot = nullptr, *spos = nullptr, *gpos = nullptr,
-          *cptr = nullptr, *gptr = nullptr, *ddiag = nullptr, *f_rp = nullptr, *f_col = nullptr, *f_src = nullptr;
+          *cptr = nullptr, *gptr = nullptr, *ddiag = nullptr;
 };
-// Far entries of the SpMV rows (float64): an entry below the diagonal of row r
-// whose stored block is a contact block (index >= nnzb_s) in row c < r -
-// far_rows (contact partners far apart in the vertex order: its second read
-// would miss L2, and a miss fetches whole cache lines for 72 bytes) reads a
-// transposed copy instead, kept after the stored blocks and refilled at every
-// assembly (launch_far_gather).  Mesh blocks are never copied: their second
-// read hits L2 often enough that a copy only adds bytes (measured).  Rewrites
-// those entries' src to nnzb_total + j and returns far_src[j] = the stored
-// block of copy j (nfar copies; memory from `alloc`).  0 done, -1 HIP
-// failure; synchronises s.
-#ifndef YASPS_FAR_ROWS
-#define YASPS_FAR_ROWS 8192
-#endif
-constexpr int FAR_ROWS = YASPS_FAR_ROWS;
-int split_far_entries(int n, const int32_t* f_rp, const int32_t* f_col, int32_t* f_src, int nnzb_s, int nnzb_total,
-                      int far_rows, int32_t** far_src, int* nfar, const std::function<void*(size_t)>& alloc,
-                      hipStream_t s);
-// vals[9 (nnzb_total + j) ...] = transpose of stored block far_src[j]
-void launch_far_gather(int nfar, const int32_t* far_src, int nnzb_total, double* vals, hipStream_t s);
+enum { DI_SIDX, DI_RP, DI_COL, DI_CPTR, DI_SLOT, DI_SPOS, DI_GPOS, DI_GPTR, DI_DDIAG, DI_COUNT };
 // 0 built, 1 invalid contacts (err_* set), -1 HIP failure.  Synchronises s.
-int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(size_t)>& alloc,
+int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(int, size_t)>& alloc,
                         hipStream_t s);
 // Line-search trial at y = x + alpha p: energy partials, feasibility (d > 0 and
 // PT/EE side kept) per workgroup.
@@ -192,13 +168,12 @@ void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cpt
                               float* out, hipStream_t s);
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
                         const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s);
-// Precision form: the float32 values of every full-row entry as structure of
-// arrays vf[q * nnz + k] (from the stored blocks through src, as in PcgMatrix).
-void launch_full_gather_f32(long long nnz, const int32_t* src, int nnzb_s, const float* vs, const float* vd,
-                            float* vf, hipStream_t s);
 // vals_s[row_ptr_s[v]] += shift m_v I (the diagonal block is first in its static row).
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
                            float* vals_s32, hipStream_t s);
+// ratio[v] = |tr(D_v)| / (3 m_v) for the assembled diagonal blocks D_v (static + dynamic).
+void launch_diag_ratio(int n, const int32_t* row_ptr_s, const void* vals_s, const int32_t* ddiag, const void* vals_d,
+                       bool f32, const double* mass, double* ratio, hipStream_t s);
 // Block-Jacobi inverse of static + dynamic diagonal blocks.
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
                           const int32_t* ddiag, const double* vals_d, double* inv,
@@ -221,27 +196,39 @@ void launch_max_norm3(int n, const double* p, double* part, int nblk, hipStream_
 void launch_dot(int n3, const double* a, const double* b, double* part, int nblk, hipStream_t s);
 
 // PCG.
-struct PcgMatrix {
-  int n;
-  // first row of each XCD's range (xsplit[PCG_XCDS] = n), chosen on the host so
-  // that the ranges hold equal work (blocks plus a per-row overhead)
-  int xsplit[PCG_XCDS + 1];
-  // both triangles of H_static + H_dynamic, row by row (FullPattern): per
-  // entry its column and the stored upper block it is (src: static blocks
-  // first, then dynamic, then the far copies; negative = transposed).
-  // Float64: the values are the assembled upper blocks themselves (9
-  // contiguous values each) and, for the far entries only, transposed copies
-  // (split_far_entries).  Precision form: a float32 copy of every entry's
-  // values as structure of arrays, v32[q * nnz + k] (measured faster for
-  // 36-byte blocks than reading the stored ones).
-  const int32_t* rp;
-  const int32_t* col;
-  const int32_t* src;
-  long long nnz;
-  const double* vals;  // float64: static blocks, dynamic blocks, far copies, contiguous
-  const float* v32;
-  const double* minv;  // (n, 9)
+// Plan of the chunked symmetric SpMV over one part of the upper-triangular
+// matrix (spmvplan.hip): the stored blocks in chunks of `chunk` consecutive
+// blocks; per block a packed word (its local row, the LDS entries of its two
+// products), per (chunk, target row) a slot of W, per row its slots
+// [hptr[j], hptr[j + 1]).
+constexpr int SPMV_MAX_CHUNK = 1024;  // the packed word holds 10-bit rows and 11-bit entries
+struct SpmvPart {
+  int nblk = 0, nrows = 0, nchunk = 0, ntarget = 0, chunk = 0;
+  int max_entries = 0;  // LDS entries (products) of the fullest chunk
+  // rl: row of each compressed row (rows holding blocks), null when that is every row
+  const int32_t *rl = nullptr, *col = nullptr, *m0 = nullptr, *tb = nullptr, *wslot = nullptr, *hptr = nullptr;
+  const uint32_t* meta = nullptr;
+  const uint16_t* tend = nullptr;
+  const void* vals = nullptr;  // stored blocks [nblk][9]: double, or float in the precision form
 };
+// Chunk size of a part with nblk stored blocks (a power of two, 256 .. SPMV_MAX_CHUNK).
+int spmv_chunk_for(long long nblk);
+enum { PL_RL, PL_M0, PL_TB, PL_META, PL_TEND, PL_WSLOT, PL_HPTR, PL_COUNT };
+// Builds one part's plan on the device from its row pointers [n + 1] and
+// columns [nblk] (device arrays).  Plan arrays come from alloc(PL_* id,
+// bytes); temporaries from the arena (or allocated and freed), *arena_needed =
+// what they took.  0 built, -1 HIP failure.  Synchronises s.
+int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, const void* vals, SpmvPart& out,
+                    const std::function<void*(int, size_t)>& alloc, void* arena, size_t arena_bytes,
+                    size_t* arena_needed, hipStream_t s);
+struct PcgMatrix {
+  int n = 0;
+  SpmvPart part[2];          // static, dynamic (nblk = 0 without contacts)
+  const double* minv = nullptr;  // (n, 9) block-Jacobi inverse
+  bool f32 = false;          // stored blocks in float32 (precision form)
+};
+// LDS bytes the SpMV kernel may take (chunks of SPMV_MAX_CHUNK blocks).
+size_t spmv_max_lds_bytes();
 struct PcgState;  // device-side scalars, defined in pcg.hip
 // Optional per-launch timing hook (kernel class ids as in yasps.h).  begin /
 // end bracket a group of launches with stream events; kernel_events hands out
@@ -261,14 +248,14 @@ struct LaunchTimer {
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter,
               bool mixed, void* work, double* rel_out, int* status_out, hipStream_t s,
               LaunchTimer* tm, void* host_state, int* hint);
-size_t pcg_workspace_bytes(int n);
-// Size of the fixed per-GPU workspace array of the non-allocating solve
-// (pcg_workspace_bytes(n) <= this for n <= 139,464 free vertices).
-constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+// Solver workspace (state, partials, Krylov vectors, nslots SpMV slots).
+size_t pcg_workspace_bytes(int n, long long nslots);
+// Size of the fixed per-GPU workspace array of the non-allocating solve.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
 // Device address of that array on `device`, which must be the current device;
 // resolved with hipGetSymbolAddress on the first call per device and kept.
 hipError_t noalloc_scratch(int device, void** ptr);
 // y = H x (both parts, symmetric upper storage) through the solver's SpMV kernel.
-void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s);
+void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s, LaunchTimer* tm);
 
 }  // namespace yasps

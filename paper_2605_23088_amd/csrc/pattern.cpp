@@ -54,23 +54,6 @@ void build_pattern(int n, const int32_t* idx, int ns, bool diag, PartPattern& ou
         }
       }
   }
-  // transpose index
-  out.tptr.assign(n + 1, 0);
-  for (int r = 0; r < n; ++r)
-    for (int k = out.row_ptr[r]; k < out.row_ptr[r + 1]; ++k)
-      if (out.col_idx[k] != r) out.tptr[out.col_idx[k] + 1]++;
-  for (int v = 0; v < n; ++v) out.tptr[v + 1] += out.tptr[v];
-  out.tslot.resize(out.tptr[n]);
-  out.trow.resize(out.tptr[n]);
-  std::vector<int32_t> fill(out.tptr.begin(), out.tptr.end() - 1);
-  for (int r = 0; r < n; ++r)
-    for (int k = out.row_ptr[r]; k < out.row_ptr[r + 1]; ++k) {
-      const int c = out.col_idx[k];
-      if (c == r) continue;
-      out.tslot[fill[c]] = k;
-      out.trow[fill[c]] = r;
-      fill[c]++;
-    }
 }
 
 void build_staging(int n, const int32_t* idx, int ns, const PartPattern& pat, const std::vector<int32_t>& order,
@@ -117,31 +100,6 @@ void build_staging(int n, const int32_t* idx, int ns, const PartPattern& pat, co
       const int v = idx[a * (size_t)ns + s];
       if (v >= 0 && v < n) st.gpos[(size_t)a * ns + j] = gfill[v]++;
     }
-  }
-}
-
-void build_full(int n, const PartPattern& stat, const PartPattern* dyn, FullPattern& out) {
-  out.row_ptr.assign(n + 1, 0);
-  out.col.clear();
-  out.src.clear();
-  const size_t total = 2 * (size_t)stat.nnzb + (dyn ? 2 * (size_t)dyn->nnzb : 0);
-  out.col.reserve(total);
-  out.src.reserve(total);
-  auto add_part = [&](const PartPattern& p, int r, int32_t base) {
-    if (p.row_ptr.empty()) return;
-    for (int k = p.row_ptr[r]; k < p.row_ptr[r + 1]; ++k) {
-      out.col.push_back(p.col_idx[k]);
-      out.src.push_back(base + k);
-    }
-    for (int j = p.tptr[r]; j < p.tptr[r + 1]; ++j) {
-      out.col.push_back(p.trow[j]);
-      out.src.push_back(-(base + p.tslot[j]) - 1);
-    }
-  };
-  for (int r = 0; r < n; ++r) {
-    add_part(stat, r, 0);
-    if (dyn) add_part(*dyn, r, stat.nnzb);
-    out.row_ptr[r + 1] = (int32_t)out.col.size();
   }
 }
 

@@ -24,9 +24,6 @@ struct PartPattern {
   std::vector<int32_t> row_ptr;   // n + 1
   std::vector<int32_t> col_idx;   // nnzb
   std::vector<int32_t> slot;      // [n_stencils][10], stencil-major (API order)
-  // transpose index for the symmetric SpMV: for every row, the off-diagonal
-  // slots whose column is that row, ordered by their row
-  std::vector<int32_t> tptr, tslot, trow;
 };
 
 // Builds the pattern of one part from stencils given as [4][ns] vertex ids.
@@ -51,15 +48,5 @@ void build_staging(int n_free, const int32_t* idx_soa, int ns, const PartPattern
                    const std::vector<int32_t>& order, bool lead_block, bool lead_grad, Staging& out);
 
 int used_vertices(const int32_t* idx_soa, int ns, int s);
-
-// Both triangles of H = H_static + H_dynamic, row by row, for the SpMV: row r
-// lists its static upper blocks, the static blocks whose column is r
-// (transposed), then the same for the dynamic part.  src[k] >= 0 names stored
-// block src[k] as is, src[k] < 0 names stored block -src[k] - 1 transposed;
-// stored blocks are numbered static first, then dynamic.
-struct FullPattern {
-  std::vector<int32_t> row_ptr, col, src;
-};
-void build_full(int n_free, const PartPattern& stat, const PartPattern* dyn, FullPattern& out);
 
 }  // namespace yasps

@@ -2,27 +2,31 @@
 // Hessian (section "Solver", appendices "SpMV" and "Preconditioner").
 //
 // SpMV.  The Hessian is assembled once, as its upper triangle (appendix
-// "Global Hessian Compression"); the paper's SpMV adds, for every off-diagonal
-// block, the transposed product with atomics (Algorithm "CUDA Block Level
-// SpMV").  Here, after each assembly, a gather pass writes both triangles of
-// H_static + H_dynamic row by row in structure-of-arrays form; a group of G
-// lanes owns one block row, the lanes read consecutive blocks (coalesced), and
-// their partial 3-vectors are combined by a fixed butterfly.  No atomics,
-// deterministic; every off-diagonal block is read twice per product (once per
-// side), as with full symmetric storage.
+// "Global Hessian Compression"), in two parts (static and dynamic).  The
+// paper's SpMV adds, for every off-diagonal block, the transposed product with
+// atomics (Algorithm "CUDA Block Level SpMV").  Here every stored block is
+// read once: the blocks of each part are cut into chunks of consecutive blocks
+// (spmvplan.hip); the workgroup of a chunk forms B x_j for the block's row i
+// and, off the diagonal, B^T x_i for row j, and sums the products of each
+// target row in LDS in a fixed order (the LDS entries come from the plan);
+// the sum of every (chunk, target row) is written to its slot of W.  A row's
+// slots are contiguous and few (its own chunk, plus the chunks of earlier rows
+// that reach it), and the next kernel adds them in order.  No atomics; the
+// results are bitwise reproducible.  The values are read from the assembled
+// blocks themselves, float64 or (precision form) float32.
 //
 // Iteration.  PCG with one global reduction phase per iteration (the
 // Chronopoulos-Gear arrangement, equal to standard PCG in exact arithmetic):
 //   u = M^-1 r, w = H u, gamma = r.u, delta = u.w
 //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
 //   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
-// Two kernels per iteration: (B) the convergence test and w = H u with the
-// delta partials, and (C) the scalar recurrences, vector updates,
-// preconditioning and the next gamma and |r|^2 partials.  Each kernel runs a
-// bounded grid (grid-stride loops) and every workgroup re-sums the previous
-// kernel's partials in the same fixed order, so there are no atomics and the
-// results are bitwise reproducible.  Convergence is tested on the device; the
-// host only polls a flag every few iterations.
+// Two kernels per iteration: (B) the chunked product into W with the delta
+// partials (delta = u^T H u summed block by block: u_i . B u_j, twice off the
+// diagonal) and, in workgroup 0, the convergence test; (C) w from the W slots,
+// the scalar recurrences, vector updates, preconditioning and the next gamma
+// and |r|^2 partials.  Each kernel re-sums the previous kernel's partials in a
+// fixed order (workgroup 0 of B only, every workgroup of C); convergence is
+// tested on the device and the host polls a flag between batches of launches.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -36,11 +40,8 @@ namespace yasps {
 
 // Launch shapes (compile-time; the defaults come from sweeps on the 40^3 and
 // 80x80x52 workloads).
-#ifndef YASPS_SPMV_NARROW_MEAN
-#define YASPS_SPMV_NARROW_MEAN 20
-#endif
 #ifndef YASPS_MAX_WG_B
-#define YASPS_MAX_WG_B 4096
+#define YASPS_MAX_WG_B 2048
 #endif
 #ifndef YASPS_MAX_WG_C
 #define YASPS_MAX_WG_C 512
@@ -48,15 +49,12 @@ namespace yasps {
 #ifndef YASPS_UPD_VERTS
 #define YASPS_UPD_VERTS 128
 #endif
-// Lanes per block row of the SpMV-shaped kernels: 8 when the full rows hold at
-// most SPMV_NARROW_MEAN blocks on average (tet meshes: about 15), else 16
-// (cloth with contacts: about 29); block rows per workgroup and pass =
-// RED_BLOCK / lanes.
-constexpr int SPMV_NARROW_MEAN = YASPS_SPMV_NARROW_MEAN;
-constexpr int MAX_WG_B = YASPS_MAX_WG_B;        // workgroups of the SpMV kernel
+constexpr int MAX_WG_B = YASPS_MAX_WG_B;        // workgroups of the SpMV kernel (chunks are shared out)
 constexpr int MAX_WG_C = YASPS_MAX_WG_C;        // workgroups of the update kernel
 constexpr int UPD_VERTS = YASPS_UPD_VERTS;      // vertices per update-kernel workgroup pass
 constexpr int UPD_BLOCK = 3 * UPD_VERTS;        // update kernel: one thread per vertex component
+// kernel classes of the profiler (yasps.h): the SpMV and the PCG update
+constexpr int SPMV_CLASS = 5, UPDATE_CLASS = 6;
 
 // Device scalars.  gamma / alpha are double-buffered by iteration parity;
 // `iter` is written only by the update kernel and `iter_b` only by the SpMV
@@ -70,96 +68,166 @@ struct PcgState {
 
 namespace {
 
-// The block rows of the SpMV-shaped kernels are split into NXCD contiguous
-// ranges of equal work (A.xsplit), one per XCD: workgroups are dispatched to
-// the XCDs round robin by index, so workgroup b runs on XCD b % NXCD and makes
-// passes over that XCD's range.  The column gathers of one XCD then stay near
-// its own rows (mesh locality) and in its own L2.  These kernels' grids are
-// multiples of NXCD.
+// The chunks (static part first, then dynamic) are split into NXCD contiguous
+// ranges, one per XCD: workgroups are dispatched to the XCDs round robin by
+// index, so workgroup b runs on XCD b % NXCD and takes chunks of that XCD's
+// range; the vector gathers of one XCD stay near its own rows (mesh locality)
+// and in its own L2.  The SpMV grid is a multiple of NXCD.
 constexpr int NXCD = PCG_XCDS;
 static_assert(MAX_WG_B % NXCD == 0 && MAX_WG_C % NXCD == 0, "partial-sum arrays hold the rounded grids");
-struct RowRange {
-  int end, first, stride;
-};
-template <int G>
-YDEV RowRange xcd_rows(const PcgMatrix& A) {
-  constexpr int ROWS = RED_BLOCK / G;
-  const int xcd = blockIdx.x % NXCD, j = blockIdx.x / NXCD, per = gridDim.x / NXCD;
-  RowRange r;
-  r.end = A.xsplit[xcd + 1];
-  r.first = A.xsplit[xcd] + j * ROWS;
-  r.stride = per * ROWS;
-  return r;
-}
 
-// (H x)_row for the row owned by this lane group: each lane takes every
-// G-th entry of the full row, reads the stored upper block that the entry
-// names (9 contiguous values; transposed for an entry below the diagonal, so
-// every stored block is read by its own row and by its column's row, the
-// second time from L2 when the rows are near each other; a far entry names
-// its transposed copy instead) and the gathered x; the sum is valid in every
-// lane of the group after the butterfly.
-template <int G, class X>
-YDEV void row_blocks(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
-  const double* __restrict__ vals = A.vals;
-  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += G) {
-    const int32_t sk = A.src[k];
-    const bool tr = sk < 0;
-    const double* p = vals + 9 * (size_t)(tr ? -sk - 1 : sk);
-    const X* xc = x + 3 * (size_t)A.col[k];
-    double B[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) B[q] = p[q];
-    const double b01 = tr ? B[3] : B[1], b02 = tr ? B[6] : B[2], b10 = tr ? B[1] : B[3];
-    const double b12 = tr ? B[7] : B[5], b20 = tr ? B[2] : B[6], b21 = tr ? B[5] : B[7];
-    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
-    acc[0] = fma(B[0], x0, fma(b01, x1, fma(b02, x2, acc[0])));
-    acc[1] = fma(b10, x0, fma(B[4], x1, fma(b12, x2, acc[1])));
-    acc[2] = fma(b20, x0, fma(b21, x1, fma(B[8], x2, acc[2])));
-  }
-}
-
-// Precision form: each lane takes every G-th entry of the row from the
-// float32 structure-of-arrays copy (the lanes of a group read consecutive
-// addresses).
-template <int G, class X>
-YDEV void row_blocks_f32(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
-  const size_t nnz = (size_t)A.nnz;
-  for (int k = A.rp[row] + lane, e = A.rp[row + 1]; k < e; k += G) {
-    const X* xc = x + 3 * (size_t)A.col[k];
-    const double x0 = double(xc[0]), x1 = double(xc[1]), x2 = double(xc[2]);
-    const float* b = A.v32 + k;
-    acc[0] = fma(double(b[0]), x0, fma(double(b[nnz]), x1, fma(double(b[2 * nnz]), x2, acc[0])));
-    acc[1] = fma(double(b[3 * nnz]), x0, fma(double(b[4 * nnz]), x1, fma(double(b[5 * nnz]), x2, acc[1])));
-    acc[2] = fma(double(b[6 * nnz]), x0, fma(double(b[7 * nnz]), x1, fma(double(b[8 * nnz]), x2, acc[2])));
-  }
-}
-
-// MF32: the precision form's float32 copy (a compile-time choice, so that
-// each kernel carries the registers of one layout only).
-template <bool MF32, int G, class X>
-YDEV void spmv_row(const PcgMatrix& A, int row, int lane, const X* x, double acc[3]) {
-  acc[0] = acc[1] = acc[2] = 0.0;
-  if (row < A.n) {
-    if constexpr (MF32)
-      row_blocks_f32<G>(A, row, lane, x, acc);
-    else
-      row_blocks<G>(A, row, lane, x, acc);
-  }
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], m, G);
-  }
-}
+enum SpmvMode { SPMV_PCG = 0, SPMV_PLAIN = 1, SPMV_REPLACE = 2 };
 
 // Krylov vectors in VT (float64, or float32 in the precision form); the
-// solution x is always float64.
+// solution x is always float64.  W0 / W1: the SpMV slots of the static and
+// dynamic parts (float64, 3 per slot).
 template <class VT>
 struct Vecs {
-  VT *r, *u, *w, *p, *s;
+  VT *r, *u, *p, *s;
   double *part_b, *part_c;  // part_c holds 2 * MAX_WG_C partials
+  double *W0, *W1;
 };
+
+// Adds the slots [e, f) of one part to w in slot order; four loads are issued
+// before they are added (a missing slot adds +0, which leaves w unchanged).
+YDEV double add_slots(double w, const double* __restrict__ W, int e, int f, int c) {
+  for (; e < f; e += 4) {
+    const double a0 = W[3 * (size_t)e + c];
+    const double a1 = e + 1 < f ? W[3 * (size_t)(e + 1) + c] : 0.0;
+    const double a2 = e + 2 < f ? W[3 * (size_t)(e + 2) + c] : 0.0;
+    const double a3 = e + 3 < f ? W[3 * (size_t)(e + 3) + c] : 0.0;
+    w += a0;
+    w += a1;
+    w += a2;
+    w += a3;
+  }
+  return w;
+}
+
+// w_v[c] = sum of the SpMV slots of vertex v, static part then dynamic, in slot order
+YDEV double w_sum(const PcgMatrix& A, const double* __restrict__ W0, const double* __restrict__ W1, int v, int c) {
+  const int32_t* h0 = A.part[0].hptr;
+  const int32_t* h1 = A.part[1].hptr;
+  const int e0 = h0 ? h0[v] : 0, f0 = h0 ? h0[v + 1] : 0;
+  const int e1 = h1 ? h1[v] : 0, f1 = h1 ? h1[v + 1] : 0;
+  return add_slots(add_slots(0.0, W0, e0, f0, c), W1, e1, f1, c);
+}
+
+// Chunked product W = slots of H u (see the file comment).  BT: stored block
+// type, XT: vector type.  The threads of a workgroup take the blocks of its
+// chunk in turn (coalesced value and index loads, independent of each other),
+// write both products of every block to their LDS entries, and after a
+// barrier sum each target row's entries into its W slot.  Modes: SPMV_PCG
+// (delta partials into part_b; workgroup 0 also runs the convergence test on
+// the update kernel's gamma / |r|^2 partials, loaded before the product and
+// summed after it), SPMV_PLAIN (product only), SPMV_REPLACE (product only,
+// skipped once the solver is done).
+template <class BT, class XT>
+__global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, const XT* __restrict__ u,
+                                                               double* __restrict__ W0, double* __restrict__ W1,
+                                                               double* __restrict__ part_b,
+                                                               const double* __restrict__ part_c, PcgState* st,
+                                                               int nb_c, int mode) {
+  extern __shared__ double E[];  // [entries][3] products of one chunk, grouped by target row
+  __shared__ double lds[RED_BLOCK];
+  if (mode != SPMV_PLAIN && st->done) return;
+  const bool book = mode == SPMV_PCG && blockIdx.x == 0;  // uniform per workgroup
+  constexpr int PC = (MAX_WG_C + RED_BLOCK - 1) / RED_BLOCK;
+  double gp[PC], rp[PC];
+#pragma unroll
+  for (int q = 0; q < PC; ++q) {
+    const int j = threadIdx.x + q * RED_BLOCK;
+    const bool in = book && j < nb_c;
+    gp[q] = in ? part_c[j] : 0.0;
+    rp[q] = in ? part_c[nb_c + j] : 0.0;
+  }
+  const int C0 = A.part[0].nchunk, C = C0 + A.part[1].nchunk;
+  const int xcd = blockIdx.x % NXCD, per = gridDim.x / NXCD;
+  const int cend = (int)((long long)C * (xcd + 1) / NXCD);
+  double dlt = 0.0;
+  for (int c = (int)((long long)C * xcd / NXCD) + (int)blockIdx.x / NXCD; c < cend; c += per) {
+    const bool dyn = c >= C0;
+    const SpmvPart& P = dyn ? A.part[1] : A.part[0];
+    const int cc = dyn ? c - C0 : c;
+    const int b0 = cc * P.chunk, b1 = min(b0 + P.chunk, P.nblk);
+    const int m0 = P.m0[cc];
+    const int32_t* __restrict__ rl = P.rl;  // null when every row holds blocks (row = compressed row)
+    const BT* __restrict__ vals = static_cast<const BT*>(P.vals);
+    for (int k = b0 + (int)threadIdx.x; k < b1; k += RED_BLOCK) {
+      const uint32_t meta = P.meta[k];
+      const int j = P.col[k];
+      const int m = m0 + (int)(meta & 1023u);
+      const int r = rl ? rl[m] : m;
+      const int ey = (int)((meta >> 10) & 2047u), et = (int)(meta >> 21);
+      const BT* bp = vals + 9 * (size_t)k;
+      double B[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) B[q] = double(bp[q]);
+      const XT* xj = u + 3 * (size_t)j;
+      const XT* xr = u + 3 * (size_t)r;
+      const double x0 = double(xj[0]), x1 = double(xj[1]), x2 = double(xj[2]);
+      const double u0 = double(xr[0]), u1 = double(xr[1]), u2 = double(xr[2]);
+      const double y0 = fma(B[0], x0, fma(B[1], x1, B[2] * x2));
+      const double y1 = fma(B[3], x0, fma(B[4], x1, B[5] * x2));
+      const double y2 = fma(B[6], x0, fma(B[7], x1, B[8] * x2));
+      E[3 * ey] = y0;
+      E[3 * ey + 1] = y1;
+      E[3 * ey + 2] = y2;
+      const double uy = fma(u0, y0, fma(u1, y1, u2 * y2));
+      if (j != r) {
+        E[3 * et] = fma(B[0], u0, fma(B[3], u1, B[6] * u2));
+        E[3 * et + 1] = fma(B[1], u0, fma(B[4], u1, B[7] * u2));
+        E[3 * et + 2] = fma(B[2], u0, fma(B[5], u1, B[8] * u2));
+        dlt = fma(2.0, uy, dlt);
+      } else {
+        dlt += uy;
+      }
+    }
+    __syncthreads();
+    const int t0 = P.tb[cc], nt = P.tb[cc + 1] - t0;
+    double* __restrict__ W = dyn ? W1 : W0;
+    for (int q = threadIdx.x; q < nt; q += RED_BLOCK) {
+      const int e1 = P.tend[t0 + q], e0 = q ? P.tend[t0 + q - 1] : 0;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        s0 += E[3 * e];
+        s1 += E[3 * e + 1];
+        s2 += E[3 * e + 2];
+      }
+      double* w = W + 3 * (size_t)P.wslot[t0 + q];
+      w[0] = s0;
+      w[1] = s1;
+      w[2] = s2;
+    }
+    __syncthreads();  // E is refilled by the next chunk
+  }
+  if (mode != SPMV_PCG) return;
+  const double ds = block_sum<RED_BLOCK>(dlt, lds);
+  if (threadIdx.x == 0) part_b[blockIdx.x] = ds;
+  if (!book) return;
+  // the same association as a strided per-thread sum followed by block_sum
+  double ga = 0.0, ra = 0.0;
+#pragma unroll
+  for (int q = 0; q < PC; ++q) {
+    ga += gp[q];
+    ra += rp[q];
+  }
+  const double gamma = block_sum<RED_BLOCK>(ga, lds);
+  const double Rr = block_sum<RED_BLOCK>(ra, lds);
+  if (threadIdx.x == 0) {
+    const int i = st->iter;
+    const double bb = i == 0 ? Rr : st->bb;
+    const bool conv = Rr <= st->tol2 * bb;
+    st->gamma[i & 1] = gamma;
+    st->rr = Rr;
+    st->iter_b = i;
+    if (i == 0) st->bb = bb;
+    if (conv || i >= st->max_iter) {
+      st->status = conv ? 0 : -5;
+      st->done = 1;
+    }
+  }
+}
 
 YDEV void precondition(const double* minv, int v, const double r[3], double u[3]) {  // u = M^-1 r
   const double* M = minv + 9 * (size_t)v;
@@ -201,38 +269,29 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_init_kernel(PcgMatrix A, const 
   }
 }
 
-// Residual replacement (precision form): r = b - H x evaluated with float64
-// vectors and accumulation, then u = M^-1 r and the gamma / |r|^2 partials,
-// replacing what the float32 recurrence carried.  Launched on the update
-// kernel's grid: its partials take the same [gamma | |r|^2] layout of gridDim.x
-// entries each that the next SpMV kernel sums.
-template <class VT, int G, bool MF32 = sizeof(VT) == 4>
+// Residual replacement (precision form), after a SPMV_REPLACE product of the
+// float64 x: r = b - H x in float64, then u = M^-1 r and the gamma / |r|^2
+// partials, replacing what the float32 recurrence carried.  Launched on the
+// update kernel's grid: its partials take the same [gamma | |r|^2] layout of
+// gridDim.x entries each that the next SpMV kernel sums.
+template <class VT>
 __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, const double* __restrict__ b,
-                                                                const double* __restrict__ x, Vecs<VT> V,
-                                                                PcgState* st) {
+                                                                Vecs<VT> V, PcgState* st) {
   if (st->done) return;
   __shared__ double lds[RED_BLOCK];
-  const int lane = threadIdx.x % G;
   double g = 0.0, rr = 0.0;
-  const RowRange R = xcd_rows<G>(A);
-  for (int base = R.first; base < R.end; base += R.stride) {
-    const int row = base + threadIdx.x / G;
-    const bool live = row < R.end;
-    double acc[3];
-    spmv_row<MF32, G>(A, live ? row : A.n, lane, x, acc);
-    if (lane == 0 && live) {
-      double r[3], u[3];
+  for (int v = blockIdx.x * RED_BLOCK + threadIdx.x; v < A.n; v += gridDim.x * RED_BLOCK) {
+    double r[3], u[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)row + c] - acc[c];
-      precondition(A.minv, row, r, u);
+    for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)v + c] - w_sum(A, V.W0, V.W1, v, c);
+    precondition(A.minv, v, r, u);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const VT rc = VT(r[c]), uc = VT(u[c]);
-        V.r[3 * (size_t)row + c] = rc;
-        V.u[3 * (size_t)row + c] = uc;
-        g = fma(double(rc), double(uc), g);
-        rr = fma(r[c], r[c], rr);
-      }
+    for (int c = 0; c < 3; ++c) {
+      const VT rc = VT(r[c]), uc = VT(u[c]);
+      V.r[3 * (size_t)v + c] = rc;
+      V.u[3 * (size_t)v + c] = uc;
+      g = fma(double(rc), double(uc), g);
+      rr = fma(r[c], r[c], rr);
     }
   }
   const double gs = block_sum<RED_BLOCK>(g, lds);
@@ -243,96 +302,37 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   }
 }
 
-// Iteration i: w = H u with the u.w partials, then (workgroup 0) the
-// convergence test on |r_i| from the update kernel's partials.  Only workgroup
-// 0 needs gamma_i and |r_i|^2, so no other workgroup reduces them; their
-// partials are loaded before the product and summed after it, so the loads
-// overlap the matrix stream.  When the test finds convergence (or max_iter),
-// this launch's w is not used: `done` stops the update kernel and every later
-// launch.  `nb_c` is the update kernel's grid (number of gamma / |r|^2
-// partials).  standalone: plain y = H x (no solver bookkeeping).
-template <class VT, int G, bool MF32 = sizeof(VT) == 4>
-__global__ __launch_bounds__(RED_BLOCK) void pcg_spmv_kernel(PcgMatrix A, Vecs<VT> V, PcgState* st, int nb_c,
-                                                             int standalone) {
-  __shared__ double lds[RED_BLOCK];
-  if (!standalone && st->done) return;
-  const bool book = !standalone && blockIdx.x == 0;  // uniform per workgroup
-  constexpr int PC = (MAX_WG_C + RED_BLOCK - 1) / RED_BLOCK;
-  double gp[PC], rp[PC];
-#pragma unroll
-  for (int q = 0; q < PC; ++q) {
-    const int j = threadIdx.x + q * RED_BLOCK;
-    const bool in = book && j < nb_c;
-    gp[q] = in ? V.part_c[j] : 0.0;
-    rp[q] = in ? V.part_c[nb_c + j] : 0.0;
-  }
-  const int lane = threadIdx.x % G;
-  double d = 0.0;
-  const RowRange R = xcd_rows<G>(A);
-  for (int base = R.first; base < R.end; base += R.stride) {
-    const int row = base + threadIdx.x / G;
-    const bool live = row < R.end;
-    double acc[3];
-    spmv_row<MF32, G>(A, live ? row : A.n, lane, V.u, acc);
-    if (lane == 0 && live) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const VT wc = VT(acc[c]);
-        V.w[3 * (size_t)row + c] = wc;
-        d = fma(double(V.u[3 * (size_t)row + c]), double(wc), d);
-      }
-    }
-  }
-  const double ds = block_sum<RED_BLOCK>(d, lds);
-  if (threadIdx.x == 0) V.part_b[blockIdx.x] = ds;
-  if (!book) return;
-  // the same association as a strided per-thread sum followed by block_sum
-  double ga = 0.0, ra = 0.0;
-#pragma unroll
-  for (int q = 0; q < PC; ++q) {
-    ga += gp[q];
-    ra += rp[q];
-  }
-  const double gamma = block_sum<RED_BLOCK>(ga, lds);
-  const double Rr = block_sum<RED_BLOCK>(ra, lds);
-  if (threadIdx.x == 0) {
-    const int i = st->iter;
-    const double bb = i == 0 ? Rr : st->bb;
-    const bool conv = Rr <= st->tol2 * bb;
-    st->gamma[i & 1] = gamma;
-    st->rr = Rr;
-    st->iter_b = i;
-    if (i == 0) st->bb = bb;
-    if (conv || i >= st->max_iter) {
-      st->status = conv ? 0 : -5;
-      st->done = 1;
-    }
-  }
+// y = H x from the slots of a SPMV_PLAIN product
+__global__ __launch_bounds__(RED_BLOCK) void spmv_finish_kernel(PcgMatrix A, const double* __restrict__ W0,
+                                                                const double* __restrict__ W1, double* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (i >= 3ll * A.n) return;
+  const int v = (int)(i / 3), c = (int)(i - 3ll * v);
+  y[i] = w_sum(A, W0, W1, v, c);
 }
 
 // One pass of the update kernel: the values a thread reads, loaded before the
-// scalars that combine them are known.
-template <class VT>
+// scalars that combine them are known (w summed from the SpMV slots).
 struct UpdLoads {
   double p, s, u, w, x, r, m0, m1, m2;
 };
 
 template <class VT>
-YDEV UpdLoads<VT> upd_load(const PcgMatrix& A, const double* x, const Vecs<VT>& V, int base, int t, int vl, int c) {
-  UpdLoads<VT> L{};
+YDEV UpdLoads upd_load(const PcgMatrix& A, const double* x, const Vecs<VT>& V, int base, int t, int vl, int c) {
+  UpdLoads L{};
   const int v = base + vl;
   if (v < A.n) {
     const size_t k = 3 * (size_t)base + t;  // = 3 v + c
     L.p = double(V.p[k]);
     L.s = double(V.s[k]);
     L.u = double(V.u[k]);
-    L.w = double(V.w[k]);
     L.x = x[k];
     L.r = double(V.r[k]);
     const double* M = A.minv + 9 * (size_t)v + 3 * c;  // row c of the vertex's M^-1
     L.m0 = M[0];
     L.m1 = M[1];
     L.m2 = M[2];
+    L.w = double(VT(w_sum(A, V.W0, V.W1, v, c)));
   }
   return L;
 }
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     const int j = t + q * UPD_BLOCK;
     bp[q] = j < nb_b ? V.part_b[j] : 0.0;
   }
-  UpdLoads<VT> cur = upd_load(A, x, V, base, t, vl, c);
+  UpdLoads cur = upd_load(A, x, V, base, t, vl, c);
   const int i = st->iter_b;
   const double gamma = st->gamma[i & 1];
   double dacc = 0.0;  // the association of a strided per-thread sum
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
   const double alpha = gamma / pAp;
   double g = 0.0, rr = 0.0;
   for (; base < A.n; base += stride) {
-    const UpdLoads<VT> nxt = upd_load(A, x, V, base + stride, t, vl, c);
+    const UpdLoads nxt = upd_load(A, x, V, base + stride, t, vl, c);
     const int v = base + vl;
     const bool live = v < A.n;
     const size_t k = 3 * (size_t)base + t;  // = 3 v + c
@@ -421,38 +421,61 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
   }
 }
 
-// Grids are multiples of NXCD (the SpMV-shaped kernels split rows per XCD; the
-// replacement kernel runs on the update kernel's grid).
 int round_xcd(int g) { return (g + NXCD - 1) / NXCD * NXCD; }
-bool narrow_rows(const PcgMatrix& A) { return A.nnz <= (long long)SPMV_NARROW_MEAN * A.n; }
-int grid_b(int n, int g) {
-  const int rows = RED_BLOCK / g;
-  return round_xcd(std::max(1, std::min((n + rows - 1) / rows, MAX_WG_B)));
+int grid_b(const PcgMatrix& A) {
+  return round_xcd(std::max(1, std::min(A.part[0].nchunk + A.part[1].nchunk, MAX_WG_B)));
 }
 int grid_c(int n) { return round_xcd(std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C))); }
+// LDS of the chunk kernel: the larger chunk's products
+size_t spmv_lds_bytes(const PcgMatrix& A) {
+  return 3 * sizeof(double) * (size_t)std::max(1, std::max(A.part[0].max_entries, A.part[1].max_entries));
+}
 
 template <class VT>
-void carve(void* work, int n, PcgState*& st, Vecs<VT>& V) {
-  const size_t n3 = 3 * (size_t)n;
+void carve(void* work, const PcgMatrix& A, PcgState*& st, Vecs<VT>& V) {
+  const size_t n3 = 3 * (size_t)A.n;
   char* w = static_cast<char*>(work);
   st = reinterpret_cast<PcgState*>(w);
   double* parts = reinterpret_cast<double*>(w + ((sizeof(PcgState) + 255) / 256) * 256);
   V.part_b = parts;
   V.part_c = parts + MAX_WG_B;
-  VT* base = reinterpret_cast<VT*>(parts + MAX_WG_B + 2 * MAX_WG_C);
+  V.W0 = parts + MAX_WG_B + 2 * MAX_WG_C;
+  V.W1 = V.W0 + 3 * (size_t)A.part[0].ntarget;
+  VT* base = reinterpret_cast<VT*>(V.W1 + 3 * (size_t)A.part[1].ntarget);
   V.r = base;
   V.u = V.r + n3;
-  V.w = V.u + n3;
-  V.p = V.w + n3;
+  V.p = V.u + n3;
   V.s = V.p + n3;
+}
+
+// Launch, timed by events that the launch itself carries when a profiler asks.
+template <class KERNEL, class... ARGS>
+void timed_launch(LaunchTimer* tm, int cls, KERNEL kernel, int grid, int block, size_t shmem, hipStream_t s,
+                  ARGS... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm && tm->kernel_events(cls, &a, &b))
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, s, a, b, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, s, args...);
+}
+
+// The chunked product.
+template <class BT, class XT>
+void launch_chunks(LaunchTimer* tm, const PcgMatrix& A, const XT* u, double* W0, double* W1, double* part_b,
+                   const double* part_c, PcgState* st, int nb_c, int mode, hipStream_t s) {
+  timed_launch(tm, SPMV_CLASS, spmv_chunk_kernel<BT, XT>, grid_b(A), RED_BLOCK, spmv_lds_bytes(A), s, A, u, W0, W1,
+               part_b, part_c, st, nb_c, mode);
 }
 
 }  // namespace
 
-size_t pcg_workspace_bytes(int n) {
+size_t pcg_workspace_bytes(int n, long long nslots) {
   const size_t n3 = 3 * (size_t)std::max(n, 1);
-  return 256 + ((sizeof(PcgState) + 255) / 256) * 256 + sizeof(double) * (5 * n3 + MAX_WG_B + 2 * MAX_WG_C);
+  return 256 + ((sizeof(PcgState) + 255) / 256) * 256 +
+         sizeof(double) * (4 * n3 + MAX_WG_B + 2 * MAX_WG_C + 3 * (size_t)std::max(nslots, 0ll));
 }  // float64 vectors; the float32 form uses half of the vector part
+
+size_t spmv_max_lds_bytes() { return 3 * sizeof(double) * 2 * SPMV_MAX_CHUNK; }
 
 // Fixed solver workspace for callers that cannot allocate (yasps_pcg_noalloc):
 // one array per GPU, held from the module's load until the process ends.  Its
@@ -484,51 +507,34 @@ hipError_t noalloc_scratch(int device, void** ptr) {
   return hipSuccess;
 }
 
-void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s) {
+void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s, LaunchTimer* tm) {
   if (A.n == 0) return;
   PcgState* st;
   Vecs<double> V;
-  carve(work, A.n, st, V);
-  V.u = const_cast<double*>(x);
-  V.w = y;
-  // the precision form's float32 copy with float64 vectors, or the stored blocks
-  const dim3 b(RED_BLOCK);
-  if (narrow_rows(A)) {
-    if (A.v32)
-      hipLaunchKernelGGL((pcg_spmv_kernel<double, 8, true>), dim3(grid_b(A.n, 8)), b, 0, s, A, V, st, 1, 1);
-    else
-      hipLaunchKernelGGL((pcg_spmv_kernel<double, 8, false>), dim3(grid_b(A.n, 8)), b, 0, s, A, V, st, 1, 1);
-  } else {
-    if (A.v32)
-      hipLaunchKernelGGL((pcg_spmv_kernel<double, 16, true>), dim3(grid_b(A.n, 16)), b, 0, s, A, V, st, 1, 1);
-    else
-      hipLaunchKernelGGL((pcg_spmv_kernel<double, 16, false>), dim3(grid_b(A.n, 16)), b, 0, s, A, V, st, 1, 1);
-  }
+  carve(work, A, st, V);
+  if (A.f32)
+    launch_chunks<float, double>(tm, A, x, V.W0, V.W1, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
+  else
+    launch_chunks<double, double>(tm, A, x, V.W0, V.W1, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
+  const long long n3 = 3ll * A.n;
+  timed_launch(tm, SPMV_CLASS, spmv_finish_kernel, (int)((n3 + RED_BLOCK - 1) / RED_BLOCK), RED_BLOCK, 0, s, A,
+               (const double*)V.W0, (const double*)V.W1, y);
 }
 
 namespace {
 
-// Launch, timed by events that the launch itself carries when a profiler asks.
-template <class KERNEL, class... ARGS>
-void timed_launch(LaunchTimer* tm, int cls, KERNEL kernel, int grid, int block, hipStream_t s, ARGS... args) {
-  hipEvent_t a = nullptr, b = nullptr;
-  if (tm && tm->kernel_events(cls, &a, &b))
-    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, a, b, 0, args...);
-  else
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, args...);
-}
-
-template <class VT, int G>
+template <class VT>
 int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, void* work, double* rel_out,
             int* status_out, hipStream_t s, LaunchTimer* tm, PcgState& hs, int* hint) {
   static_assert(sizeof(PcgState) <= 128, "the pinned polling buffer holds 128 bytes");
   constexpr bool MIXED = sizeof(VT) == 4;
+  using BT = VT;  // stored blocks: float32 in the precision form
   constexpr int REPLACE_EVERY = 50;  // float64 residual replacement period (precision form)
   const int n = A.n;
   PcgState* st;
   Vecs<VT> V;
-  carve(work, n, st, V);
-  const int nb_b = grid_b(n, G), nb_c = grid_c(n);
+  carve(work, A, st, V);
+  const int nb_b = grid_b(A), nb_c = grid_c(n);
   PcgState h{};
   h.tol2 = rtol * rtol;
   h.max_iter = max_iter;
@@ -538,7 +544,11 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
     *status_out = 0;
     return 0;
   }
-  timed_launch(tm, 6, pcg_init_kernel<VT>, nb_c, RED_BLOCK, s, A, b, x, V, st);
+  auto replace = [&]() {  // r = b - H x in float64 (precision form)
+    launch_chunks<BT, double>(nullptr, A, x, V.W0, V.W1, nullptr, nullptr, st, 0, SPMV_REPLACE, s);
+    hipLaunchKernelGGL((pcg_replace_kernel<VT>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, V, st);
+  };
+  timed_launch(tm, UPDATE_CLASS, pcg_init_kernel<VT>, nb_c, RED_BLOCK, 0, s, A, b, x, V, st);
   // Launches between polls.  The launch that finds convergence after k
   // iterations is the (k + 1)-th: with a hint k the first batch is k + 2
   // launches (one poll when the count repeats or drops a little; launches past
@@ -552,11 +562,10 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   constexpr int MAX_RESTARTS = 32;
   for (;;) {
     for (int k = 0; k < batch; ++k) {
-      timed_launch(tm, 5, pcg_spmv_kernel<VT, G>, nb_b, RED_BLOCK, s, A, V, st, nb_c, 0);
-      timed_launch(tm, 6, pcg_update_kernel<VT>, nb_c, UPD_BLOCK, s, A, x, V, st, nb_b);
+      launch_chunks<BT, VT>(tm, A, V.u, V.W0, V.W1, V.part_b, V.part_c, st, nb_c, SPMV_PCG, s);
+      timed_launch(tm, UPDATE_CLASS, pcg_update_kernel<VT>, nb_c, UPD_BLOCK, 0, s, A, x, V, st, nb_b);
       ++launched;
-      if (MIXED && launched % REPLACE_EVERY == 0)
-        timed_launch(tm, 5, pcg_replace_kernel<VT, G>, nb_c, RED_BLOCK, s, A, b, x, V, st);
+      if (MIXED && launched % REPLACE_EVERY == 0) replace();
     }
     if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
@@ -570,7 +579,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       fix.restart_at = hs.iter_b;
       fix.iter = hs.iter_b;
       if (hipMemcpyAsync(st, &fix, sizeof(fix), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL((pcg_replace_kernel<VT, G>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      replace();
       launched = hs.iter_b;
       batch = 8;
       continue;
@@ -581,7 +590,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
       verified_at = hs.iter_b;
       const int zero = 0;
       if (hipMemcpyAsync(&st->done, &zero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
-      hipLaunchKernelGGL((pcg_replace_kernel<VT, G>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, x, V, st);
+      replace();
       launched = hs.iter_b;
       batch = 8;
       continue;
@@ -599,11 +608,9 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
 int pcg_solve(const PcgMatrix& A, const double* b, double* x, double rtol, int max_iter, bool mixed, void* work,
               double* rel_out, int* status_out, hipStream_t s, LaunchTimer* tm, void* host_state, int* hint) {
   PcgState& hs = *static_cast<PcgState*>(host_state);
-  if (narrow_rows(A))
-    return mixed ? pcg_run<float, 8>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
-                 : pcg_run<double, 8>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
-  return mixed ? pcg_run<float, 16>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
-               : pcg_run<double, 16>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
+  if (mixed != A.f32) return -2;
+  return mixed ? pcg_run<float>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint)
+               : pcg_run<double>(A, b, x, rtol, max_iter, work, rel_out, status_out, s, tm, hs, hint);
 }
 
 }  // namespace yasps

@@ -28,7 +28,7 @@ INDEX_DEVICE, INDEX_HOST = 0, 1  # yasps_params.index_build
 
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
            "yasps_pcg_noalloc", "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
-           "yasps_profile_query", "yasps_spmv", "yasps_destroy", "yasps_last_error"]
+           "yasps_profile_query", "yasps_spmv", "yasps_lm_shift", "yasps_destroy", "yasps_last_error"]
 K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH, K_CLOTH = range(9)
 KERNEL_CLASSES = ["inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "pcg_spmv", "pcg_update",
                   "linesearch", "cloth_eval"]
@@ -105,6 +105,7 @@ def lib():
         L.yasps_profile_enable.argtypes = [P, C.c_int32]
         L.yasps_profile_query.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.yasps_spmv.argtypes = [P, P, P]
+        L.yasps_lm_shift.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
         L.yasps_destroy.argtypes = [P]
         L.yasps_destroy.restype = None
         L.yasps_last_error.argtypes = [P]
@@ -332,6 +333,12 @@ class Yasps:
         y = torch.empty_like(x) if y is None else y
         self._check(lib().yasps_spmv(self.ctx, _ptr(x), _ptr(y)))
         return y
+
+    def lm_shift(self, frac):
+        """frac * median_v |tr(H_vv)| / (3 m_v) of the last assembly (yasps_lm_shift)."""
+        out = C.c_double()
+        self._check(lib().yasps_lm_shift(self.ctx, frac, C.byref(out)))
+        return out.value
 
     def profile(self, enable=True):
         self._check(lib().yasps_profile_enable(self.ctx, int(bool(enable))))

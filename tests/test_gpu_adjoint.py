@@ -70,3 +70,23 @@ def test_adjoint_matches_finite_differences():
         if abs(g[t] - fd) > 1e-3 * abs(fd) + 1e-8 * gmax:
             bad.append((int(t), g[t], fd))
     assert not bad, bad
+
+
+def test_lm_shift_matches_oracle():
+    """yasps_lm_shift (the first Levenberg-Marquardt shift of the damped
+    equilibrium solve) against the oracle's: 1 % of the median of
+    |tr H_vv| / (3 m_v) over the exact Hessian's diagonal blocks, with
+    contacts (dynamic diagonal blocks) and an odd and an even vertex count."""
+    from paper_2605_23088_amd.yasps import Yasps
+    for ny in (3, 2):  # 76 and 41 free vertices
+        p = synth.c5_static(seed=22, nx=4, ny=ny, nz=ny, a=0.05, n_pt=40, kappa=1e4, pin="corners")
+        o = oasm.Oracle(p)
+        oadj.set_theta(o, p["theta"])
+        ref = oadj.shift_scale(o, p["x0"])
+        g = Yasps(p)
+        g._ml[0].copy_(torch.as_tensor(p["theta"] * p["mu1"], device="cuda"))
+        g._ml[1].copy_(torch.as_tensor(p["theta"] * p["lam1"], device="cuda"))
+        g.eval(torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda").contiguous(), exact=True)
+        g.view()
+        assert g.lm_shift(1e-2) == pytest.approx(ref, rel=1e-10)
+        g.close()

@@ -21,6 +21,10 @@ TOL = 1e-10
 # the classic IPC barrier, with the squared distances reaching 1.25 dhat so that
 # about a fifth of the stencils are inactive (exact zeros that keep their slots)
 CLASSIC = ("classic",)
+# Neo-Hookean Hessians projected in x-space over the free vertices (the paper's
+# plain rows of Table 1): all four vertices free (the Helmert-reduced 9 x 9),
+# and tets at the fixed corners of the static block (free principal submatrix)
+XSPACE = ("xspace_block", "xspace_static")
 
 
 def case(name):
@@ -34,22 +38,52 @@ def case(name):
         return synth.small_block(seed=12, nx=10, ny=9, nz=8, n_pt=600, n_ee=500)
     if name == "static":
         return synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200, kappa=1e4, pin="corners")
+    if name == "xspace_static":
+        return shaken(synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200, kappa=1e4, pin="corners"), 0.05)
+    if name == "xspace_block":
+        return shaken(synth.small_block(seed=15, nx=5, ny=4, nz=3, n_pt=150, n_ee=150), 0.2)
     raise KeyError(name)
 
 
-CASES = ["C1", "block", "block_mid", "static", "classic"]
+def shaken(p, a, frac=0.2, seed=5):
+    """x0 moved by N(0, (frac a)^2) per coordinate so that element Hessians turn
+    indefinite (where the two projection spaces differ); the bottom face only
+    moves within its plane, which keeps every collider distance."""
+    q = dict(p)
+    x = np.array(p["x0"], dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    dx = rng.normal(0.0, frac * a, x.shape)
+    dx[x[:, 2] < 1e-9, 2] = 0.0
+    q["x0"] = x + dx
+    return q
+
+
+CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static"]
 _cache = {}
 
 
 def setup(name):
     if name not in _cache:
-        from paper_2605_23088_amd.yasps import IPC_CLASSIC, SQLOG, Yasps
+        from paper_2605_23088_amd.yasps import F_SPACE, IPC_CLASSIC, SQLOG, X_SPACE, Yasps
         p = case(name)
         classic = name in CLASSIC
-        o = oasm.Oracle(p, classic=classic)
-        g = Yasps(p, barrier=IPC_CLASSIC if classic else SQLOG)
+        xs = name in XSPACE
+        o = oasm.Oracle(p, classic=classic, proj=oasm.X_SPACE if xs else oasm.F_SPACE)
+        g = Yasps(p, barrier=IPC_CLASSIC if classic else SQLOG, proj=X_SPACE if xs else F_SPACE)
         _cache[name] = (p, o, g)
     return _cache[name]
+
+
+def test_xspace_cases_cover_both_reductions():
+    """The x-space cases hold all-free tets and tets with fixed vertices, and
+    the x-space projection differs from the F-space one there."""
+    p = case("xspace_static")
+    free = (p["tet_idx"] < p["n_free"]).sum(axis=1)
+    assert (free == 4).any() and (free < 4).any()
+    ox = oasm.Oracle(p, proj=oasm.X_SPACE)
+    of = oasm.Oracle(p)
+    hx, hf = ox.eval(p["x0"])["H_t"], of.eval(p["x0"])["H_t"]
+    assert np.abs(hx - hf).max() > 1e-6 * np.abs(hf).max()
 
 
 def test_classic_case_has_inactive_stencils():

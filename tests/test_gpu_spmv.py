@@ -2,9 +2,10 @@
 the product with the assembled matrix the library exposes (both precisions),
 and in float64 against the oracle's H: static and dynamic parts, after the
 contact set is replaced, and after a rejected contact set (the product then
-covers the static part only).  The kernel takes 8 lanes per block row when the
-full rows hold at most 20 blocks on average (the small block: about 13) and
-16 otherwise (the dense cloth case: about 23): both are covered."""
+covers the static part only).  The product reads every stored upper block once
+in chunks of consecutive blocks and sums each target row's products in LDS;
+tiny chunks (64 blocks, set through YASPS_SPMV_CHUNK) split rows across many
+chunks, and the largest ones fill the most LDS: both are covered."""
 import numpy as np
 import pytest
 import torch
@@ -57,11 +58,21 @@ def test_spmv_long_rows_matches_oracle(precision):
     rng = np.random.default_rng(6)
     x = rng.standard_normal((p["n_free"], 3))
     check_product(o, g, p, x, 1e-12 if precision == "fp64" else None)
-    # full-row entries: both triangles of both parts (dynamic diagonal blocks once)
-    n, v = p["n_free"], g.view()
-    rp, ci, _ = g.pattern(1)
-    nd = int(sum((ci[rp[r]:rp[r + 1]] == r).any() for r in range(n)))
-    assert 2 * v.nnzb_static - n + 2 * v.nnzb_dynamic - nd > 20 * n  # the 16-lane kernel ran
+    g.close()
+
+
+@pytest.mark.parametrize("chunk", ["64", "1024"])
+@pytest.mark.parametrize("case", ["block", "cloth"])
+def test_spmv_chunk_sizes_match_oracle(case, chunk, monkeypatch):
+    """64-block chunks (rows split across chunks, many W slots per row) and
+    the largest chunks (up to 2048 LDS entries per workgroup)."""
+    from paper_2605_23088_amd.yasps import Yasps
+    monkeypatch.setenv("YASPS_SPMV_CHUNK", chunk)
+    p = (synth.small_block(seed=23, nx=7, ny=6, nz=5, n_pt=300, n_ee=250) if case == "block"
+         else synth.small_cloth(counts=(300, 300, 100, 40)))
+    g = Yasps(p)
+    x = np.random.default_rng(9).standard_normal((p["n_free"], 3))
+    check_product(oasm.Oracle(p), g, p, x, 1e-12)
     g.close()
 
 

@@ -50,7 +50,7 @@ def test_noalloc_equals_pcg_twice_then_smaller(precision):
 
 def test_noalloc_rejects_a_system_beyond_its_array():
     from paper_2605_23088_amd.yasps import E_ARG, OK, Yasps, lib
-    n = 150_000  # the fixed array holds the workspace of at most 139,464 free vertices
+    n = 320_000  # inertia only: 120 bytes of workspace per free vertex, more than the fixed 32 MiB
     rng = np.random.default_rng(3)
     x0 = rng.uniform(0.0, 1.0, (n, 3))
     p = dict(n_free=n, x0=x0, x_fixed=np.zeros((0, 3)), mass=np.full(n, 0.5), x_tilde=x0 + 1e-3,
