@@ -10,7 +10,9 @@ Placement indices are 0-based with -1 for "no contribution" (the paper's
 Rule, fixed so that two independent builders agree bit for bit:
 
 * a stencil with k used vertices enumerates local pairs (a, b), a = 0..k-1,
-  b = a..k-1 (10 / 6 / 3 pairs for k = 4 / 3 / 2), padded to 10 entries;
+  b = a..k-1 (10 / 6 / 3 pairs for k = 4 / 3 / 2), padded to w (w + 1) / 2
+  entries for stencils given w entries wide (10 for w = 4; the row lists of
+  stencils touching affine bodies are up to 8 wide, 36 pairs);
 * a pair whose two vertices are both free has key (min(v_a, v_b), max(v_a, v_b));
   otherwise its slot is -1;
 * the static part also holds (v, v) for every free vertex;
@@ -32,11 +34,13 @@ def used_vertices(idx):
 
 
 def stencil_pairs(idx):
-    """(n_s, 10, 2) local vertex positions (a, b) of every pair slot, -1 padded."""
+    """(n_s, w (w + 1) / 2, 2) local vertex positions (a, b) of every pair slot,
+    -1 padded (w = the width of idx)."""
     idx = np.asarray(idx)
-    k = used_vertices(idx)
-    out = -np.ones((idx.shape[0], 10, 2), np.int64)
-    for kk in (2, 3, 4):
+    w = idx.shape[1] if idx.ndim == 2 else 4
+    k = used_vertices(idx) if idx.size else np.zeros(0, np.int64)
+    out = -np.ones((idx.shape[0], w * (w + 1) // 2, 2), np.int64)
+    for kk in range(1, w + 1):
         rows = np.flatnonzero(k == kk)
         pr = np.array(local_pairs(kk))
         out[rows[:, None], np.arange(len(pr))[None, :]] = pr[None, :, :]
@@ -44,9 +48,9 @@ def stencil_pairs(idx):
 
 
 def build(n_free, idx_list, add_diagonal):
-    """Pattern of one part.  idx_list: list of (n_s, 4) int arrays (free ids
+    """Pattern of one part.  idx_list: list of (n_s, w) int arrays (free ids
     < n_free, fixed ids >= n_free, -1 unused).  Returns row_ptr, col_idx and a
-    list of (n_s, 10) int32 slot arrays, one per input array."""
+    list of (n_s, w (w + 1) / 2) int32 slot arrays, one per input array."""
     rows_all, cols_all, per = [], [], []
     for idx in idx_list:
         idx = np.asarray(idx, dtype=np.int64)

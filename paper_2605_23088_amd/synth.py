@@ -742,3 +742,122 @@ def small_cloth(seed=31, counts=(250, 250, 100, 40)):
     block under two 14x14 sheets."""
     return c3_cloth(seed=seed, block=(6, 6, 2), a=1.0 / 6, sheet_cells=14, n_sheets=2, counts=counts,
                     name="cloth_small")
+
+
+# --------------------------------------------------------------------------
+# Affine bodies mixed with free vertices
+# --------------------------------------------------------------------------
+
+def affine_block(seed=41, nx=5, ny=4, nz=3, n_pt=120, n_ee=120, n_pp=40, n_pt1=60, n_pp2=30, n_ee2=30,
+                 n_fixed_pt=20, k_orth=1e5, body_mass=1.0, dhi=1e-3, **kw):
+    """A free Kuhn block between two affine bodies (p = A r + t per body
+    vertex), with contact stencils of every parameterisation mix:
+
+    * body 0 under the block: n_pt points below bottom triangles (PT: body
+      point, free triangle) and n_ee edges below bottom edges (EE: free edge,
+      body edge), placed like the fixed collider of ``block_problem``;
+    * body 1 above the block: n_pt1 points above top triangles (PT), n_pp
+      points above top vertices (PP: free point, body point);
+    * body 0 against body 1: n_pp2 PP and n_ee2 EE stencils (two bodies);
+    * n_fixed_pt ordinary PT stencils (fixed point, free bottom triangle).
+
+    Squared distances U(1e-4, dhi).  Each body's A starts as a seeded small
+    perturbation of the identity (rest positions chosen so the vertices sit
+    where placed), t = 0; its mass matrix is M4 = sum_v m_v w_v w_v^T,
+    w = (r, 1), with the body's mass spread evenly over its vertices; the
+    inertial target moves t by h^2 g.  The degree-of-freedom vector is
+    X0 = [free x0; a_1, a_2, a_3, t of each body]."""
+    r_pos, r_con, r_body, _ = _streams(seed)
+    p = block_problem(nx, ny, nz, 1.0 / max(nx, ny, nz), n_pt + n_fixed_pt, n_ee, seed, dhi=dhi, **kw)
+    X = p["x0"]
+    n = p["n_free"]
+    a = p["spacing"]
+    ztop = nz * a
+    ct, ci, xf = p["ctype"], p["cidx"].copy(), p["x_fixed"]
+    # the collider features of the first n_pt PT and of every EE become body-0 vertices
+    pt_rows = np.flatnonzero(ct == PT)
+    ee_rows = np.flatnonzero(ct == EE)
+    to_body = np.concatenate([pt_rows[:n_pt], ee_rows])
+    keep = np.setdiff1d(np.arange(len(ct)), to_body)
+    body_pts, body_of = [], []
+    bct, bci = [], []
+
+    def add_vertex(x, b):
+        body_pts.append(np.asarray(x, np.float64))
+        body_of.append(b)
+        return len(body_pts) - 1
+
+    for s in to_body:
+        ids = ci[s].copy()
+        for j in range(4):
+            v = ids[j]
+            if v >= n:  # a collider vertex: move it to body 0
+                ids[j] = -2 - add_vertex(xf[v - n], 0)
+        bct.append(ct[s])
+        bci.append(ids)
+    # ordinary contacts keep their own fixed points (renumbered compactly)
+    fx_old = sorted({int(v) for s in keep for v in ci[s] if v >= n})
+    remap = {v: n + i for i, v in enumerate(fx_old)}
+    ct_o = ct[keep].astype(np.int32)
+    ci_o = np.array([[remap.get(int(v), int(v)) for v in ci[s]] for s in keep], np.int32).reshape(-1, 4)
+    x_fixed = xf[np.array(fx_old, np.int64) - n] if fx_old else np.zeros((0, 3))
+    # body 1 above the top face
+    tris = face_triangles(nx, ny, nz)
+    verts_top = np.flatnonzero(np.abs(X[:, 2] - ztop) < 1e-12)
+    d = r_con.uniform(1e-4, dhi, size=n_pt1)
+    t = tris[r_con.integers(0, tris.shape[0], size=n_pt1)]
+    for s in range(n_pt1):
+        c = X[t[s]].mean(axis=0) + np.array([0.0, 0.0, np.sqrt(d[s])])
+        bct.append(PT)
+        bci.append(np.array([-2 - add_vertex(c, 1), t[s][0], t[s][1], t[s][2]]))
+    d = r_con.uniform(1e-4, dhi, size=n_pp)
+    vv = verts_top[r_con.integers(0, verts_top.size, size=n_pp)]
+    for s in range(n_pp):
+        bct.append(PP)
+        bci.append(np.array([vv[s], -2 - add_vertex(X[vv[s]] + [0.0, 0.0, np.sqrt(d[s])], 1), -1, -1]))
+    # body 0 against body 1: PP next to body-0 points, EE crossing under body-0 edges
+    b0 = [k for k in range(len(body_pts)) if body_of[k] == 0]
+    d = r_con.uniform(1e-4, dhi, size=n_pp2)
+    for s in range(n_pp2):
+        k0 = b0[r_con.integers(0, len(b0))]
+        ang = r_con.uniform(0.0, 2 * np.pi)
+        off = np.sqrt(d[s]) * np.array([np.cos(ang), np.sin(ang), 0.0])
+        bct.append(PP)
+        bci.append(np.array([-2 - k0, -2 - add_vertex(body_pts[k0] + off, 1), -1, -1]))
+    ee_body = [s for s in range(len(bct)) if bct[s] == EE]
+    d = r_con.uniform(1e-4, dhi, size=n_ee2)
+    for s in range(n_ee2):
+        src = bci[ee_body[r_con.integers(0, len(ee_body))]]
+        k0, k1 = -2 - src[2], -2 - src[3]  # the body-0 edge of a free/body EE stencil
+        q0, q1 = body_pts[k0], body_pts[k1]
+        mid = 0.5 * (q0 + q1) - np.array([0.0, 0.0, np.sqrt(d[s])])
+        dirn = q1 - q0
+        perp = np.array([-dirn[1], dirn[0], 0.0]) / np.linalg.norm(dirn[:2])
+        e0 = add_vertex(mid - 0.5 * a * perp, 1)
+        e1 = add_vertex(mid + 0.5 * a * perp, 1)
+        bct.append(EE)
+        bci.append(np.array([-2 - k0, -2 - k1, -2 - e0, -2 - e1]))
+    body_pts = np.array(body_pts)
+    body_of = np.array(body_of, np.int64)
+    nfix = x_fixed.shape[0]
+    bci = np.array(bci, np.int64)
+    bci = np.where(bci <= -2, n + nfix + (-2 - bci), bci).astype(np.int32)
+    # body degrees of freedom: A = I + small seeded perturbation, t = 0; rest r = A^-1 p
+    nb = 2
+    q0 = np.zeros((nb, 4, 3))
+    rest = np.zeros_like(body_pts)
+    M4 = np.zeros((nb, 4, 4))
+    for b in range(nb):
+        A = np.eye(3) + r_body.normal(0.0, 1e-3, (3, 3))
+        q0[b, :3] = A.T  # rows a_j = columns of A
+        sel = np.flatnonzero(body_of == b)
+        rest[sel] = np.linalg.solve(A, body_pts[sel].T).T
+        w = np.concatenate([rest[sel], np.ones((sel.size, 1))], 1)
+        M4[b] = (body_mass / sel.size) * (w.T @ w)
+    qt = q0.copy()
+    qt[:, 3] += p["h"] ** 2 * GRAVITY
+    p.update(ctype=ct_o, cidx=ci_o, x_fixed=x_fixed, n_bodies=nb, body_q0=q0, body_qt=qt, body_M4=M4,
+             body_k=np.full(nb, k_orth), abd_body=body_of, abd_rest=rest,
+             bctype=np.array(bct, np.int32), bcidx=bci,
+             X0=np.concatenate([X, q0.reshape(-1, 3)]), name=f"affine{nx}x{ny}x{nz}")
+    return p
