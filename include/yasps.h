@@ -26,7 +26,9 @@
  *   n_free + n_fixed is fixed vertex i - n_free (no DoF; the paper's
  *   "special primitive whose degrees of freedom are excluded from
  *   differentiation", Table 1 caption); -1 marks an unused stencil entry.
- * - Positions and vectors over free vertices are (n_free, 3) row-major f64.
+ * - Positions and vectors are (n_rows, 3) row-major f64 over the rows of degrees
+ *   of freedom: the free vertices, then four rows per affine body (n_rows =
+ *   n_free + 4 n_bodies; n_rows = n_free without bodies).
  * - Per-stencil arrays are structure-of-arrays: tet_idx is [4][n_tets]
  *   (entry k of tet t at tet_idx[k * n_tets + t]), dm_inv is [9][n_tets]
  *   (row-major 3x3 components), contact idx is [4][n_contacts].
@@ -90,7 +92,8 @@ typedef struct {
   int32_t n_fixed;         /* fixed vertices */
   const double* x_fixed;   /* (n_fixed, 3) positions of fixed vertices; may be NULL if n_fixed == 0 */
   const double* mass;      /* (n_free) lumped masses */
-  const double* x_tilde;   /* (n_free, 3) inertial target x0 + h v0 + h^2 g; ignored if is_static */
+  const double* x_tilde;   /* (n_rows, 3) inertial target x0 + h v0 + h^2 g (a body's rows: its q~);
+                              ignored if is_static */
   int32_t n_tets;
   const int32_t* tet_idx;  /* [4][n_tets] vertex ids, positively oriented at rest */
   const double* dm_inv;    /* [9][n_tets] inverse rest edge matrices Dm^-1, row-major components */
@@ -122,6 +125,21 @@ typedef struct {
                                free vertex each */
   const double* hinge_rest; /* [2][n_hinges]: rest angle theta_bar, stiffness k (E = k (theta -
                                theta_bar)^2, k = k_b 3 |e_bar|^2 / (A1 + A2) for discrete shells) */
+  /* Affine bodies (all optional; n_bodies = 0 without): a body vertex sits at
+   * p = A r + t (the paper's mixed parameterisation, section "UNION").  Each
+   * body adds four rows of degrees of freedom after the free vertices: the
+   * columns a_1, a_2, a_3 of A, then t; so x, x_tilde and every vector are
+   * (n_free + 4 n_bodies, 3).  Energies per body: inertia 1/2 (q - q~)^T
+   * (M4 (x) I3) (q - q~) and the orthogonality regulariser
+   * h^2 k_b 1/2 |A^T A - I|_F^2 (the paper's E_affine), its 9x9 Hessian
+   * projected.  Body vertices have ids n_free + n_fixed + k and appear only in
+   * the stencils given to yasps_set_body_contacts. */
+  int32_t n_bodies;
+  const double* body_mass;  /* [n_bodies][16] row-major 4x4 M4 = sum_v m_v w_v w_v^T, w = (r, 1) */
+  const double* body_k;     /* [n_bodies] orthogonality stiffness k_b */
+  int32_t n_body_verts;
+  const int32_t* body_of;   /* [n_body_verts] body of each body vertex */
+  const double* body_rest;  /* [n_body_verts][3] rest position r */
 } yasps_problem;
 
 typedef struct {
@@ -146,18 +164,21 @@ typedef struct {
   int32_t n_active; /* contact stencils with d < dhat */
 } yasps_eval_info;
 
-/* Device views of context-owned storage, valid until the next yasps_set_contacts
- * or yasps_destroy.  Upper-triangular BSR with row-major 3x3 blocks; the diagonal
- * block is the first block of every static row.  H = H_static + H_dynamic. */
+/* Device views of context-owned storage, valid until the next yasps_set_contacts,
+ * yasps_set_body_contacts or yasps_destroy.  Upper-triangular BSR with row-major
+ * 3x3 blocks over n_rows = n_free + 4 n_bodies rows; the diagonal block is the
+ * first block of every static row.  H = H_static + H_dynamic + H_body. */
 typedef struct {
-  int32_t n_rows;       /* = n_free */
-  int32_t nnzb_static;  /* elastic pairs + every free diagonal */
+  int32_t n_rows;       /* n_free + 4 n_bodies */
+  int32_t nnzb_static;  /* elastic pairs, body blocks and every diagonal */
   int32_t nnzb_dynamic; /* contact pairs */
   const int32_t* row_ptr_s; const int32_t* col_idx_s; const void* values_s;
   const int32_t* row_ptr_d; const int32_t* col_idx_d; const void* values_d;
   int32_t values_are_f32; /* 1 in the MIXED precision form, else float64 */
-  const double* grad;     /* (n_free, 3) float64 gradient */
-  const double* block_inv;/* (n_free, 9) float64 inverses of the diagonal blocks of H */
+  const double* grad;     /* (n_rows, 3) float64 gradient */
+  const double* block_inv;/* (n_rows, 9) float64 inverses of the diagonal blocks of H */
+  int32_t nnzb_body;      /* pairs of the stencils touching bodies (third part) */
+  const int32_t* row_ptr_b; const int32_t* col_idx_b; const void* values_b;
 } yasps_bsr_view;
 
 typedef struct {
@@ -218,7 +239,22 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
  * YASPS_E_HIP. */
 yasps_status yasps_set_contacts(yasps_ctx* ctx, const yasps_contacts* C);
 
-/* Evaluates every stencil at positions x (n_free, 3): energies, gradients and
+/* Replaces the list of contact stencils that touch affine bodies (vertex ids
+ * as in yasps_contacts, body vertices allowed; each side of a stencil should
+ * come from one body or from free / fixed vertices: a stencil may reach at
+ * most 8 rows of degrees of freedom).  Their derivatives follow the chain
+ * rule through the union of free, fixed and body vertices (section
+ * "Differentiation of Unioned Attributes"); the local Hessian is projected
+ * over the stencil's movable positions and mapped to the degrees of freedom,
+ * J^T Proj(H_p) J (the reduced-coordinate projection of section
+ * "Eigendecomposition (EVD) and PSD Projection": 6x6 for a point-point
+ * stencil whatever the bodies).  They form a third part of the matrix, built
+ * on the host.  Arrays are device arrays, copied.  Errors: YASPS_E_ARG (bad
+ * type or id, a repeated vertex, no movable vertex, more than 8 rows; the
+ * context is then left without body contacts), YASPS_E_HIP. */
+yasps_status yasps_set_body_contacts(yasps_ctx* ctx, const yasps_contacts* C);
+
+/* Evaluates every stencil at positions x (n_rows, 3): energies, gradients and
  * local Hessians (flags: YASPS_PROJECTED or YASPS_EXACT), staged for assembly.
  * Fills *info (may be NULL).  Errors: YASPS_E_DOMAIN (some contact d <= 0),
  * YASPS_E_NONFINITE, YASPS_E_HIP. */
@@ -234,7 +270,7 @@ yasps_status yasps_assemble_bsr(yasps_ctx* ctx, yasps_bsr_view* view);
 
 /* Solves H x = b with block-Jacobi preconditioned CG on the assembled H
  * (x0 = 0, stop when |r| <= rtol |b| or after max_iter products).  b and x
- * are (n_free, 3) device arrays; x is overwritten.  The system is solved as
+ * are (n_rows, 3) device arrays; x is overwritten.  The system is solved as
  * given (the paper's convention, section "Solution Extraction").
  * Errors: YASPS_E_NOCONV (x holds the last iterate), YASPS_E_BREAKDOWN,
  * YASPS_E_ARG, YASPS_E_HIP. */
@@ -264,16 +300,19 @@ yasps_status yasps_pcg_noalloc(yasps_ctx* ctx, const double* b, double* x, doubl
  * backtrack from alpha0 = min(1, 0.4 min_s sqrt(d_s) /
  * max_v |p_v|) by halving until every contact d > 0, every PT/EE stencil keeps
  * its side of the plane/line, and E(x + alpha p) <= E(x) + armijo alpha g.p.
- * x (n_free, 3) is updated in place.  `prm` may be NULL for defaults.
+ * x (n_rows, 3) is updated in place.  `prm` may be NULL for defaults.
  * Errors: as eval / pcg, plus YASPS_E_LINESEARCH (x unchanged). */
 yasps_status yasps_newton_step(yasps_ctx* ctx, double* x, const yasps_newton_params* prm,
                                yasps_newton_info* info);
 
 /* Copies one part of the pattern to HOST arrays for inspection (bit-exact tests):
- * part 0 = static, 1 = dynamic.  row_ptr has n_free + 1 entries, col_idx nnzb,
- * slot [n_stencils][10] (part 0: tets, then triangles, then hinges, each in the
- * order given at create; part 1: contacts in the order given; local pair (a, b),
- * a <= b, enumerated row by row over the stencil's used vertices; -1 = no block).
+ * part 0 = static, 1 = dynamic, 2 = body contacts.  row_ptr has n_rows + 1
+ * entries (n_rows = n_free + 4 n_bodies), col_idx nnzb, slot [n_stencils][10]
+ * (part 0: tets, then triangles, then hinges, then bodies (their 4 rows), each
+ * in the order given at create; part 1: contacts in the order given; local
+ * pair (a, b), a <= b, enumerated row by row over the stencil's used vertices;
+ * -1 = no block), for part 2 [n_stencils][36] over each stencil's row list
+ * (its vertices' rows in vertex order, a body's four rows once).
  * Any output pointer may be NULL.  Errors: YASPS_E_ARG. */
 yasps_status yasps_get_pattern(yasps_ctx* ctx, int32_t part, int32_t* row_ptr, int32_t* col_idx,
                                int32_t* slot);
@@ -281,7 +320,7 @@ yasps_status yasps_get_pattern(yasps_ctx* ctx, int32_t part, int32_t* row_ptr, i
 /* Adjoint of the static-equilibrium solve with per-tet Young's modulus theta_t
  * (mu_t, lambda_t proportional to theta_t): for every tet writes
  * grad_theta[t] = -lambda_t^T d/dx (Psi_t(x) / theta_t), the mixed partial
- * d2E/dx dtheta_t contracted with the adjoint vector lambda (n_free, 3).
+ * d2E/dx dtheta_t contracted with the adjoint vector lambda (x, lambda: (n_rows, 3)).
  * theta (n_tets) and grad_theta (n_tets) are device arrays.
  * Errors: YASPS_E_ARG, YASPS_E_HIP. */
 yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* lambda,
@@ -291,7 +330,7 @@ yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* 
  * equilibrium of the differentiation form (yasps_newton_params.shift; the
  * paper's own solver, section "Solver", takes plain projected Newton steps):
  * *out = frac * median over the free vertices v of |tr(H_vv)| / (3 m_v), with
- * H_vv the diagonal block (static + dynamic parts) of the last assembly,
+ * H_vv the diagonal block (all matrix parts) of the last assembly,
  * including any shift that assembly added, and m_v the lumped masses.  For an
  * even vertex count the median is the mean of the two middle values.
  * Errors: YASPS_E_ARG (before any assembly, frac < 0), YASPS_E_HIP. */
@@ -318,7 +357,7 @@ yasps_status yasps_profile_enable(yasps_ctx* ctx, int32_t enable);
 yasps_status yasps_profile_query(yasps_ctx* ctx, int32_t kernel_class, int32_t* launches, double* total_ms);
 
 /* y = H x with the assembled H (both parts), through the same SpMV kernel the
- * solver uses (appendix "SpMV"); x, y (n_free, 3) device arrays.
+ * solver uses (appendix "SpMV"); x, y (n_rows, 3) device arrays.
  * Errors: YASPS_E_ARG (before assembly), YASPS_E_HIP. */
 yasps_status yasps_spmv(yasps_ctx* ctx, const double* x, double* y);
 

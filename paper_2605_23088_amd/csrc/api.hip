@@ -130,7 +130,8 @@ struct yasps_ctx {
   hipStream_t stream = nullptr;
   yasps_problem P{};
   yasps_params prm{};
-  int n = 0, nt = 0, nc = 0, nf = 0, nh = 0;
+  int n = 0, nt = 0, nc = 0, nf = 0, nh = 0;  // n: rows of degrees of freedom (nv + 4 nb)
+  int nv = 0, nb = 0, nbv = 0;                // free vertices, affine bodies, body vertices
   std::string err;
   std::vector<void*> allocs;      // everything allocated for the static part / workspace
 
@@ -146,6 +147,7 @@ struct yasps_ctx {
   int32_t *spos_f = nullptr, *gpos_f = nullptr, *spos_h = nullptr, *gpos_h = nullptr, *h_idx = nullptr;
   double* h_rest = nullptr;
   std::vector<Group> hgroups;
+  int32_t *spos_bd = nullptr, *gpos_bd = nullptr;  // the bodies' 10 blocks / 4 gradient rows (static staging)
   // SpMV plans of the two parts (spmvplan.hip); their arrays live in the grow-only buffers
   SpmvPart plan_s, plan_d;
   GrowBuf plan_s_buf[PL_COUNT], plan_d_buf[PL_COUNT];
@@ -159,6 +161,22 @@ struct yasps_ctx {
   // the dynamic part's arrays: grow-only, reused by every contact set that fits
   GrowBuf di_buf[DI_COUNT];
   GrowBuf stg_d_buf, gstg_d_buf, vals_d_buf, d_c_buf;
+
+  // contacts touching affine bodies (third part, built on the host)
+  enum { BC_IDX, BC_VPOS, BC_ROWS, BC_SPOS, BC_GPOS, BC_CPTR, BC_GPTR, BC_RP, BC_COL, BC_BDIAG, BC_STG, BC_GSTG,
+         BC_VALS, BC_D, BC_PBLK, BC_PGRD, BC_COUNT };
+  GrowBuf bc_buf[BC_COUNT];
+  int nbc = 0, nblk_b = 0, ngrd_b = 0;
+  std::vector<Group> bgroups;
+  PartPattern hpat_b;
+  Part pb;
+  int32_t *bc_idx = nullptr, *bc_vpos = nullptr, *bc_rows = nullptr, *bc_spos = nullptr, *bc_gpos = nullptr,
+          *bc_cptr = nullptr, *bc_gptr = nullptr, *bc_bdiag = nullptr;
+  double *stg_b = nullptr, *gstg_b = nullptr, *vals_b = nullptr, *d_b = nullptr, *pos_blk = nullptr,
+         *pos_grd = nullptr;
+  float *stg_b32 = nullptr, *vals_b32 = nullptr;
+  SpmvPart plan_b;
+  GrowBuf plan_b_buf[PL_COUNT];
 
   // a second stream for the contact kernels, which run beside the elastic ones
   // during an evaluation (fork / join through the two events)
@@ -249,8 +267,8 @@ void grow_arena(yasps_ctx* c, size_t need) {
 
 // SpMV plan of one part (0 static, 1 dynamic) into the context's grow-only buffers.
 yasps_status build_plan(yasps_ctx* c, int part, const int32_t* rp, const int32_t* col, int nblk, const void* vals) {
-  GrowBuf* bufs = part ? c->plan_d_buf : c->plan_s_buf;
-  SpmvPart& out = part ? c->plan_d : c->plan_s;
+  GrowBuf* bufs = part == 0 ? c->plan_s_buf : (part == 1 ? c->plan_d_buf : c->plan_b_buf);
+  SpmvPart& out = part == 0 ? c->plan_s : (part == 1 ? c->plan_d : c->plan_b);
   auto alloc = [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
   size_t need = 0;
   const int r = build_spmv_plan(c->n, rp, col, nblk, vals, out, alloc, c->di_arena, c->di_arena_bytes, &need,
@@ -269,7 +287,8 @@ yasps_status build_plan(yasps_ctx* c, int part, const int32_t* rp, const int32_t
 
 // The solver workspace for the current plans (grow-only).
 yasps_status ensure_pcg_work(yasps_ctx* c) {
-  const long long slots = (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0);
+  const long long slots =
+      (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0) + (c->nbc ? c->plan_b.ntarget : 0);
   if (!c->pcg_work.ensure(pcg_workspace_bytes(c->n, slots))) return fail(c, YASPS_E_HIP, "hipMalloc of the PCG workspace");
   return YASPS_OK;
 }
@@ -291,20 +310,30 @@ void clear_contacts(yasps_ctx* c) {
   c->assembled = false;
 }
 
-// Partials layout: [inertia | tets, membranes, hinge groups | contact energy |
-// contact min d | contact active count]
+// Partials layout: [inertia: free vertices, bodies | tets, membranes, hinge
+// groups, bodies (orthogonality) | contact energy | contact min d | contact
+// active count]; the contact segments hold the ordinary contact groups, then
+// the body-contact groups.
 struct PartsLayout {
   int off[6];
+  int body_in, body_or;  // the bodies' inertia and orthogonality partials
+  int bc;                // first body-contact partial within each contact segment
 };
 
 PartsLayout parts_layout(const yasps_ctx* c) {
   PartsLayout L;
   int nce = 0;
   for (const Group& g : c->groups) nce += grid_of(g.end - g.begin, EVAL_BLOCK);
+  L.bc = nce;
+  for (const Group& g : c->bgroups) nce += grid_of(g.end - g.begin, EVAL_BLOCK);
   int nel = grid_of(c->nt, EVAL_BLOCK) + grid_of(c->nf, EVAL_BLOCK);
   for (const Group& g : c->hgroups) nel += grid_of(g.end - g.begin, EVAL_BLOCK);
+  const int nbp = c->nb ? grid_of(c->nb, EVAL_BLOCK) : 0;
   L.off[0] = 0;
-  L.off[1] = L.off[0] + grid_of(c->n, EVAL_BLOCK);
+  L.body_in = grid_of(c->nv, EVAL_BLOCK);
+  L.off[1] = L.off[0] + L.body_in + nbp;
+  L.body_or = L.off[1] + nel;
+  nel += nbp;
   L.off[2] = L.off[1] + nel;
   L.off[3] = L.off[2] + nce;
   L.off[4] = L.off[3] + nce;
@@ -323,7 +352,7 @@ yasps_status ensure_parts(yasps_ctx* c) {
 
 SnhArgs snh_args(const yasps_ctx* c, const double* x) {
   SnhArgs a{};
-  a.n_free = c->n;
+  a.n_free = c->nv;
   a.x = x;
   a.x_fixed = c->P.x_fixed;
   a.nt = c->nt;
@@ -346,7 +375,7 @@ SnhArgs snh_args(const yasps_ctx* c, const double* x) {
 
 MembraneArgs membrane_args(const yasps_ctx* c, const double* x) {
   MembraneArgs a{};
-  a.n_free = c->n;
+  a.n_free = c->nv;
   a.x = x;
   a.x_fixed = c->P.x_fixed;
   a.nf = c->nf;
@@ -370,7 +399,7 @@ MembraneArgs membrane_args(const yasps_ctx* c, const double* x) {
 // part_off: partials before this group within the hinge partials
 HingeArgs hinge_args(const yasps_ctx* c, const double* x, const Group& g, int part_off) {
   HingeArgs a{};
-  a.n_free = c->n;
+  a.n_free = c->nv;
   a.x = x;
   a.x_fixed = c->P.x_fixed;
   a.begin = g.begin;
@@ -391,7 +420,7 @@ HingeArgs hinge_args(const yasps_ctx* c, const double* x, const Group& g, int pa
 
 InertiaArgs inertia_args(const yasps_ctx* c, const double* x) {
   InertiaArgs a{};
-  a.n = c->n;
+  a.n = c->nv;
   a.x = x;
   a.x_tilde = c->P.x_tilde;
   a.mass = c->P.mass;
@@ -409,7 +438,7 @@ InertiaArgs inertia_args(const yasps_ctx* c, const double* x) {
 
 ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, int part_off) {
   ContactArgs a{};
-  a.n_free = c->n;
+  a.n_free = c->nv;
   a.x = x;
   a.x_fixed = c->P.x_fixed;
   a.begin = g.begin;
@@ -433,11 +462,69 @@ ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, in
   return a;
 }
 
+BodyArgs body_args(const yasps_ctx* c, const double* x) {
+  BodyArgs a{};
+  a.nv = c->nv;
+  a.nb = c->nb;
+  a.x = x;
+  a.x_tilde = c->P.x_tilde;
+  a.M4 = c->P.body_mass;
+  a.k = c->P.body_k;
+  a.h2 = c->P.h * c->P.h;
+  a.is_static = c->P.is_static;
+  for (int i = 0; i < 3; ++i) a.g[i] = c->P.gravity[i];
+  a.spos = c->spos_bd;
+  a.gpos = c->gpos_bd;
+  a.blk = c->stg_s;
+  a.blk32 = c->prm.precision == YASPS_MIXED ? c->stg_s32 : nullptr;
+  a.grd = c->gstg_s;
+  const PartsLayout L = parts_layout(c);
+  a.e_inertia = c->parts + L.body_in;
+  a.e_orth = c->parts + L.body_or;
+  a.flags = c->flags;
+  return a;
+}
+
+// part_off: partials before this group within the body-contact partials
+BodyContactArgs body_contact_args(const yasps_ctx* c, const double* x, const Group& g, int part_off) {
+  BodyContactArgs a{};
+  a.nv = c->nv;
+  a.nfix = c->P.n_fixed;
+  a.x = x;
+  a.x_fixed = c->P.x_fixed;
+  a.body_of = c->P.body_of;
+  a.body_rest = c->P.body_rest;
+  a.begin = g.begin;
+  a.end = g.end;
+  a.ns = c->nbc;
+  a.idx = c->bc_idx;
+  a.vpos = c->bc_vpos;
+  a.rows = c->bc_rows;
+  a.spos = c->bc_spos;
+  a.gpos = c->bc_gpos;
+  a.kappa = c->P.kappa;
+  a.dhat = c->P.dhat;
+  a.barrier = c->prm.barrier;
+  a.pos_blk = c->pos_blk;
+  a.pos_grd = c->pos_grd;
+  a.blk = c->stg_b;
+  a.blk32 = c->stg_b32;
+  a.grd = c->gstg_b;
+  const PartsLayout L = parts_layout(c);
+  a.e_part = c->parts + L.off[2] + L.bc + part_off;
+  a.dmin_part = c->parts + L.off[3] + L.bc + part_off;
+  a.nact_part = c->parts + L.off[4] + L.bc + part_off;
+  a.d_out = c->d_b;
+  a.flags = c->flags;
+  return a;
+}
+
 PcgMatrix pcg_matrix(const yasps_ctx* c) {
   PcgMatrix A{};
   A.n = c->n;
   A.part[0] = c->plan_s;
   if (c->nc) A.part[1] = c->plan_d;
+  if (c->nbc) A.part[2] = c->plan_b;
   A.minv = c->minv;
   A.f32 = c->prm.precision == YASPS_MIXED;
   return A;
@@ -474,7 +561,8 @@ void yasps_destroy(yasps_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   free_list(ctx->allocs);
-  for (GrowBuf* set : {ctx->plan_s_buf, ctx->plan_d_buf})
+  for (GrowBuf& b : ctx->bc_buf) b.release();
+  for (GrowBuf* set : {ctx->plan_s_buf, ctx->plan_d_buf, ctx->plan_b_buf})
     for (int k = 0; k < PL_COUNT; ++k) set[k].release();
   for (GrowBuf& b : ctx->di_buf) b.release();
   for (GrowBuf* b : {&ctx->stg_d_buf, &ctx->gstg_d_buf, &ctx->vals_d_buf, &ctx->d_c_buf, &ctx->pcg_work}) b->release();
@@ -506,6 +594,11 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   if (P->n_hinges > 0 && (!P->hinge_idx || !P->hinge_rest)) return fail(nullptr, YASPS_E_ARG, "hinge arrays missing");
   if (!(P->dhat > 0.0) || !(P->kappa >= 0.0) || !(P->h > 0.0))
     return fail(nullptr, YASPS_E_ARG, "dhat, kappa and h must be positive");
+  if (P->n_bodies < 0 || P->n_body_verts < 0) return fail(nullptr, YASPS_E_ARG, "negative body size");
+  if (P->n_bodies > 0 && (!P->body_mass || !P->body_k || (!P->is_static && !P->x_tilde)))
+    return fail(nullptr, YASPS_E_ARG, "body arrays missing");
+  if (P->n_body_verts > 0 && (!P->body_of || !P->body_rest || P->n_bodies == 0))
+    return fail(nullptr, YASPS_E_ARG, "body vertex arrays missing");
   yasps_params prm{YASPS_FP64, YASPS_F_SPACE, YASPS_SQLOG, YASPS_INDEX_DEVICE};
   if (opt) prm = *opt;
   if (prm.index_build != YASPS_INDEX_DEVICE && prm.index_build != YASPS_INDEX_HOST)
@@ -524,7 +617,10 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   };
   c->P = *P;
   c->prm = prm;
-  c->n = P->n_free;
+  c->nv = P->n_free;
+  c->nb = P->n_bodies;
+  c->nbv = P->n_body_verts;
+  c->n = c->nv + 4 * c->nb;
   c->nt = P->n_tets;
   c->stream = static_cast<hipStream_t>(hip_stream);
   // default priority, non-blocking: ordered against c->stream by events only
@@ -550,11 +646,20 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
       if (!valid_ids(htet.data(), c->nt, t, 4, nall))
         return bail(fail(c, YASPS_E_ARG, "tet " + std::to_string(t) + ": vertex id out of range or repeated"));
   }
+  if (c->nbv) {  // every body vertex names a body
+    std::vector<int32_t> hb(c->nbv);
+    if (hipMemcpy(hb.data(), P->body_of, hb.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(fail(c, YASPS_E_HIP, "copying body_of failed"));
+    for (int k = 0; k < c->nbv; ++k)
+      if (hb[k] < 0 || hb[k] >= c->nb)
+        return bail(fail(c, YASPS_E_ARG, "body vertex " + std::to_string(k) + ": body out of range"));
+  }
   // static stencils: tets, then membrane triangles (4th entry -1), then hinges,
-  // in API order for the pattern and slot map
+  // then the bodies (their 4 rows), in API order for the pattern and slot map;
+  // fixed ids move past the body rows (ids >= n have no row)
   c->nf = P->n_tris;
   c->nh = P->n_hinges;
-  const int nt = c->nt, nf = c->nf, nh = c->nh, ns = nt + nf + nh;
+  const int nt = c->nt, nf = c->nf, nh = c->nh, nbd = c->nb, ns = nt + nf + nh + nbd;
   std::vector<int32_t> hst((size_t)4 * ns, -1);
   std::vector<int32_t> htri((size_t)3 * nf), hhin((size_t)4 * nh);
   std::vector<double> hrest((size_t)2 * nh);
@@ -578,11 +683,18 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
       if (!valid_ids(hst.data(), ns, nt + nf + h, 4, nall))
         return bail(fail(c, YASPS_E_ARG, "hinge " + std::to_string(h) + ": vertex id out of range or repeated"));
   }
+  for (int a = 0; a < 4; ++a)
+    for (int j = 0; j < nt + nf + nh; ++j) {
+      int32_t& v = hst[(size_t)a * ns + j];
+      if (v >= c->nv) v += 4 * nbd;
+    }
+  for (int b = 0; b < nbd; ++b)
+    for (int a = 0; a < 4; ++a) hst[(size_t)a * ns + nt + nf + nh + b] = c->nv + 4 * b + a;
   // hinge storage order: stable by number of free vertices
   std::vector<int> hfree(nh);
   for (int h = 0; h < nh; ++h) {
     int k = 0;
-    for (int a = 0; a < 4; ++a) k += hhin[(size_t)a * nh + h] < c->n ? 1 : 0;
+    for (int a = 0; a < 4; ++a) k += hhin[(size_t)a * nh + h] < c->nv ? 1 : 0;
     if (k == 0) return bail(fail(c, YASPS_E_ARG, "hinge " + std::to_string(h) + ": no free vertex"));
     hfree[h] = k;
   }
@@ -600,8 +712,9 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   std::vector<int32_t> order(ns);
   std::iota(order.begin(), order.begin() + nt + nf, 0);
   for (int j = 0; j < nh; ++j) order[nt + nf + j] = nt + nf + horder[j];
+  for (int b = 0; b < nbd; ++b) order[nt + nf + nh + b] = nt + nf + nh + b;
   const bool dyn = !P->is_static;
-  build_staging(c->n, hst.data(), ns, c->hpat_s, order, dyn, true, st);
+  build_staging(c->n, hst.data(), ns, c->hpat_s, order, dyn, true, st, 4, c->nv);
   yasps_status s = upload_part(c, c->allocs, c->hpat_s, c->ps);
   if (s) return bail(s);
   // per-class staging positions (storage order) and the hinge arrays in storage order
@@ -627,6 +740,10 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   const std::vector<int32_t> spos_t = rows(st.spos, 10, 0, nt), gpos_t = rows(st.gpos, 4, 0, nt);
   const std::vector<int32_t> spos_f = rows(st.spos, 6, nt, nf), gpos_f = rows(st.gpos, 3, nt, nf);
   const std::vector<int32_t> spos_h = rows(st.spos, 10, nt + nf, nh), gpos_h = rows(st.gpos, 4, nt + nf, nh);
+  const std::vector<int32_t> spos_b = rows(st.spos, 10, nt + nf + nh, nbd),
+                             gpos_b = rows(st.gpos, 4, nt + nf + nh, nbd);
+  UP(c->spos_bd, spos_b);
+  UP(c->gpos_bd, gpos_b);
   UP(c->spos_t, spos_t);
   UP(c->gpos_t, gpos_t);
   UP(c->spos_f, spos_f);
@@ -711,7 +828,8 @@ yasps_status finish_dynamic(yasps_ctx* c) {
 yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   const int nc = C->n_contacts;
   DynIndexIn in{};
-  in.n = c->n;
+  in.n = c->nv;
+  in.nrows = c->n;
   in.nall = c->P.n_free + c->P.n_fixed;
   in.nc = nc;
   in.type = C->type;
@@ -766,15 +884,19 @@ yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
     if (!valid_ids(idx.data(), nc, s, NV[ty[s]], nall))
       return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": vertex id out of range, repeated or misplaced");
     int nf = 0;
-    for (int a = 0; a < NV[ty[s]]; ++a) nf += idx[a * (size_t)nc + s] < c->n ? 1 : 0;
+    for (int a = 0; a < NV[ty[s]]; ++a) nf += idx[a * (size_t)nc + s] < c->nv ? 1 : 0;
     if (nf == 0) return fail(c, YASPS_E_ARG, "contact " + std::to_string(s) + ": no free vertex");
     // point-triangle stencils against a fixed point get their own group (and
     // kernel): their projection reduces to a 6 x 6 eigenproblem
-    const bool pt_fixed_point = ty[s] == 0 && nf == 3 && idx[s] >= c->n;
+    const bool pt_fixed_point = ty[s] == 0 && nf == 3 && idx[s] >= c->nv;
     key[s] = ty[s] * 8 + (pt_fixed_point ? PT_TRIANGLE_FREE : nf);
   }
+  // the pattern over every row: fixed ids move past the affine-body rows
+  std::vector<int32_t> ridx(idx);
+  for (int32_t& v : ridx)
+    if (v >= c->nv) v += c->n - c->nv;
   PartPattern pat;
-  build_pattern(c->n, idx.data(), nc, false, pat);
+  build_pattern(c->n, ridx.data(), nc, false, pat);
   // storage order: stable sort by (type, number of free vertices)
   std::vector<int32_t> order(nc);
   std::iota(order.begin(), order.end(), 0);
@@ -790,7 +912,7 @@ yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   for (int j = 0; j < nc; ++j)
     for (int a = 0; a < 4; ++a) sidx[(size_t)a * nc + j] = idx[(size_t)a * nc + order[j]];
   Staging st;
-  build_staging(c->n, idx.data(), nc, pat, order, false, false, st);
+  build_staging(c->n, ridx.data(), nc, pat, order, false, false, st);
   std::vector<int32_t> ddiag(c->n, -1);
   for (int v = 0; v < c->n; ++v)
     for (int k = pat.row_ptr[v]; k < pat.row_ptr[v + 1]; ++k)
@@ -822,9 +944,155 @@ yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   return finish_dynamic(c);
 }
 
+// Leaves the context without contacts touching bodies.
+void clear_body_contacts(yasps_ctx* c) {
+  c->nbc = 0;
+  c->bgroups.clear();
+  c->pb = Part{};
+  c->plan_b = SpmvPart{};
+  c->hpat_b = PartPattern{};
+  c->nblk_b = c->ngrd_b = 0;
+  c->evaluated = false;
+  c->assembled = false;
+}
+
+// Host build of the body-contact part: row lists (a body's four rows once,
+// in vertex order), pattern and slot map over them (up to 8 rows, 36 pairs),
+// staging, diagonal positions, then its SpMV plan.
+yasps_status set_body_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
+  const int ns = C->n_contacts;
+  const int nv = c->nv, nfix = c->P.n_fixed, base = nv + nfix, nall = base + c->nbv;
+  std::vector<int32_t> ty(ns), idx((size_t)4 * ns), body(c->nbv);
+  if (ns) {
+    HIPCHK(c, hipMemcpy(ty.data(), C->type, (size_t)ns * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(idx.data(), C->idx, idx.size() * 4, hipMemcpyDeviceToHost));
+  }
+  if (c->nbv) HIPCHK(c, hipMemcpy(body.data(), c->P.body_of, body.size() * 4, hipMemcpyDeviceToHost));
+  static const int NV[4] = {4, 4, 3, 2};
+  std::vector<int32_t> rows((size_t)8 * ns, -1), vpos((size_t)4 * ns, -1);
+  std::vector<int> key(ns);
+  for (int s = 0; s < ns; ++s) {
+    const std::string at = "body contact " + std::to_string(s) + ": ";
+    if (ty[s] < 0 || ty[s] > 3) return fail(c, YASPS_E_ARG, at + "unknown type");
+    if (!valid_ids(idx.data(), ns, s, NV[ty[s]], nall))
+      return fail(c, YASPS_E_ARG, at + "vertex id out of range, repeated or misplaced");
+    int L = 0, K = 0;
+    for (int a = 0; a < NV[ty[s]]; ++a) {
+      const int v = idx[(size_t)a * ns + s];
+      if (v >= nv && v < base) continue;  // fixed
+      ++K;
+      int r0[4], nr = 1;
+      if (v < nv) {
+        r0[0] = v;
+      } else {
+        const int b = body[v - base];
+        nr = 4;
+        for (int j = 0; j < 4; ++j) r0[j] = nv + 4 * b + j;
+      }
+      int first = -1;
+      for (int j = 0; j < nr; ++j) {
+        int pos = -1;
+        for (int q = 0; q < L; ++q)
+          if (rows[(size_t)q * ns + s] == r0[j]) pos = q;
+        if (pos < 0) {
+          if (L == 8) return fail(c, YASPS_E_ARG, at + "more than 8 rows of degrees of freedom");
+          rows[(size_t)L * ns + s] = r0[j];
+          pos = L++;
+        }
+        if (j == 0) first = pos;
+      }
+      vpos[(size_t)a * ns + s] = first;
+    }
+    if (K == 0) return fail(c, YASPS_E_ARG, at + "no movable vertex");
+    key[s] = ty[s] * 8 + K;
+  }
+  PartPattern pat;
+  build_pattern(c->n, rows.data(), ns, false, pat, 8);
+  std::vector<int32_t> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+  std::vector<Group> groups;
+  for (int j = 0; j < ns;) {
+    int e = j;
+    while (e < ns && key[order[e]] == key[order[j]]) ++e;
+    groups.push_back(Group{key[order[j]] / 8, key[order[j]] % 8, j, e});
+    j = e;
+  }
+  Staging st;
+  build_staging(c->n, rows.data(), ns, pat, order, false, false, st, 8);
+  std::vector<int32_t> sidx((size_t)4 * ns), svpos((size_t)4 * ns), srows((size_t)8 * ns);
+  for (int j = 0; j < ns; ++j) {
+    for (int a = 0; a < 4; ++a) {
+      sidx[(size_t)a * ns + j] = idx[(size_t)a * ns + order[j]];
+      svpos[(size_t)a * ns + j] = vpos[(size_t)a * ns + order[j]];
+    }
+    for (int q = 0; q < 8; ++q) srows[(size_t)q * ns + j] = rows[(size_t)q * ns + order[j]];
+  }
+  std::vector<int32_t> bdiag(c->n, -1);
+  for (int v = 0; v < c->n; ++v)
+    for (int k = pat.row_ptr[v]; k < pat.row_ptr[v + 1]; ++k)
+      if (pat.col_idx[k] == v) bdiag[v] = k;
+  auto up = [c](int which, const std::vector<int32_t>& h) -> int32_t* {
+    int32_t* d = static_cast<int32_t*>(c->bc_buf[which].ensure(sizeof(int32_t) * std::max<size_t>(h.size(), 1)));
+    if (d && !h.empty() &&
+        hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return nullptr;
+    return d;
+  };
+  c->bc_idx = up(yasps_ctx::BC_IDX, sidx);
+  c->bc_vpos = up(yasps_ctx::BC_VPOS, svpos);
+  c->bc_rows = up(yasps_ctx::BC_ROWS, srows);
+  c->bc_spos = up(yasps_ctx::BC_SPOS, st.spos);
+  c->bc_gpos = up(yasps_ctx::BC_GPOS, st.gpos);
+  c->bc_cptr = up(yasps_ctx::BC_CPTR, st.cptr);
+  c->bc_gptr = up(yasps_ctx::BC_GPTR, st.gptr);
+  c->pb.rp = up(yasps_ctx::BC_RP, pat.row_ptr);
+  c->pb.ci = up(yasps_ctx::BC_COL, pat.col_idx);
+  c->bc_bdiag = up(yasps_ctx::BC_BDIAG, bdiag);
+  const bool mixed = c->prm.precision == YASPS_MIXED;
+  const size_t vsz = mixed ? sizeof(float) : sizeof(double);
+  void* stg = c->bc_buf[yasps_ctx::BC_STG].ensure(9 * vsz * (size_t)std::max(st.nblocks, 1));
+  void* vals = c->bc_buf[yasps_ctx::BC_VALS].ensure(9 * vsz * (size_t)std::max(pat.nnzb, 1));
+  c->gstg_b = static_cast<double*>(c->bc_buf[yasps_ctx::BC_GSTG].ensure(24 * (size_t)std::max(st.ngrads, 1)));
+  c->d_b = static_cast<double*>(c->bc_buf[yasps_ctx::BC_D].ensure(8 * (size_t)std::max(ns, 1)));
+  c->pos_blk = static_cast<double*>(c->bc_buf[yasps_ctx::BC_PBLK].ensure(8 * 90 * (size_t)std::max(ns, 1)));
+  c->pos_grd = static_cast<double*>(c->bc_buf[yasps_ctx::BC_PGRD].ensure(8 * 12 * (size_t)std::max(ns, 1)));
+  if (!c->bc_idx || !c->bc_vpos || !c->bc_rows || !c->bc_spos || !c->bc_gpos || !c->bc_cptr || !c->bc_gptr ||
+      !c->pb.rp || !c->pb.ci || !c->bc_bdiag || !stg || !vals || !c->gstg_b || !c->d_b || !c->pos_blk || !c->pos_grd)
+    return fail(c, YASPS_E_HIP, "upload of the body-contact index");
+  c->stg_b = mixed ? nullptr : static_cast<double*>(stg);
+  c->vals_b = mixed ? nullptr : static_cast<double*>(vals);
+  c->stg_b32 = mixed ? static_cast<float*>(stg) : nullptr;
+  c->vals_b32 = mixed ? static_cast<float*>(vals) : nullptr;
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the host arrays go out of scope
+  c->nbc = ns;
+  c->bgroups = std::move(groups);
+  c->pb.nnzb = pat.nnzb;
+  c->hpat_b = std::move(pat);
+  c->nblk_b = st.nblocks;
+  c->ngrd_b = st.ngrads;
+  yasps_status s = ensure_parts(c);
+  if (s) return s;
+  s = build_plan(c, 2, c->pb.rp, c->pb.ci, c->pb.nnzb, vals);
+  if (s) return s;
+  return ensure_pcg_work(c);
+}
+
 }  // namespace
 
 extern "C" {
+
+yasps_status yasps_set_body_contacts(yasps_ctx* c, const yasps_contacts* C) {
+  if (!c || !C) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (C->n_contacts < 0 || (C->n_contacts > 0 && (!C->type || !C->idx)))
+    return fail(c, YASPS_E_ARG, "bad contact arrays");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  clear_body_contacts(c);
+  const yasps_status s = set_body_contacts_host(c, C);
+  if (s) clear_body_contacts(c);  // a rejected or failed set leaves the context without body contacts
+  return s;
+}
 
 yasps_status yasps_set_contacts(yasps_ctx* c, const yasps_contacts* C) {
   if (!c || !C) return fail(c, YASPS_E_ARG, "NULL argument");
@@ -846,7 +1114,7 @@ namespace {
 yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info* info) {
   const bool exact = (flags & YASPS_EXACT) != 0;
   HIPCHK(c, hipMemsetAsync(c->flags, 0, 4, c->stream));
-  if (!c->prof.on && !c->groups.empty()) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  if (!c->prof.on && (!c->groups.empty() || c->nbc)) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
   c->prof.begin(YASPS_K_INERTIA);
   launch_inertia(inertia_args(c, x), c->stream);
   c->prof.end();
@@ -863,10 +1131,15 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
     }
     c->prof.end();
   }
+  if (c->nb) {
+    c->prof.begin(YASPS_K_SNH);
+    launch_body_eval(body_args(c, x), exact, c->stream);
+    c->prof.end();
+  }
   // the contact kernels write only the dynamic staging, their partials and
   // d: they run on the side stream beside the elastic kernels (in sequence
   // while the profiler times kernel classes on the context stream)
-  const bool fork = !c->prof.on && !c->groups.empty();
+  const bool fork = !c->prof.on && (!c->groups.empty() || c->nbc);
   hipStream_t cs = fork ? c->side : c->stream;
   if (fork) HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
   int off = 0;
@@ -875,6 +1148,13 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
     launch_contact_eval(g.type, g.nfree, contact_args(c, x, g, off), exact, cs);
     off += grid_of(g.end - g.begin, EVAL_BLOCK);
   }
+  // contacts touching bodies: position-space pass per group, then the map to the row lists
+  off = 0;
+  for (const Group& g : c->bgroups) {
+    launch_body_contact_eval(g.type, g.nfree, body_contact_args(c, x, g, off), exact, cs);
+    off += grid_of(g.end - g.begin, EVAL_BLOCK);
+  }
+  if (c->nbc) launch_body_contact_eval(0, -1, body_contact_args(c, x, Group{0, 0, 0, c->nbc}, 0), exact, cs);
   c->prof.end();
   if (fork) {
     HIPCHK(c, hipEventRecord(c->ev_join, c->side));
@@ -896,7 +1176,7 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
     info->e_elastic = h[1];
     info->e_contact = h[2];
     info->energy = h[0] + h[1] + h[2];
-    info->min_d = c->nc ? h[3] : INFINITY;
+    info->min_d = (c->nc || c->nbc) ? h[3] : INFINITY;
     info->n_active = (int32_t)h[4];
   }
   c->evaluated = true;
@@ -909,24 +1189,29 @@ yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   c->prof.begin(YASPS_K_ASSEMBLE);
   const bool mixed = c->prm.precision == YASPS_MIXED;
   const bool dyn = c->nc > 0;
+  const bool bod = c->nbc > 0;
   if (mixed) {
     launch_segsum_blocks_f32(c->ps.nnzb, c->nblk_s, c->cptr_s, c->stg_s32, c->vals_s32, c->stream);
     if (dyn) launch_segsum_blocks_f32(c->pd.nnzb, c->nblk_d, c->cptr_d, c->stg_d32, c->vals_d32, c->stream);
+    if (bod) launch_segsum_blocks_f32(c->pb.nnzb, c->nblk_b, c->bc_cptr, c->stg_b32, c->vals_b32, c->stream);
   } else {
     launch_segsum_blocks(c->ps.nnzb, c->nblk_s, c->cptr_s, c->stg_s, c->vals_s, c->stream);
     if (dyn) launch_segsum_blocks(c->pd.nnzb, c->nblk_d, c->cptr_d, c->stg_d, c->vals_d, c->stream);
+    if (bod) launch_segsum_blocks(c->pb.nnzb, c->nblk_b, c->bc_cptr, c->stg_b, c->vals_b, c->stream);
   }
-  launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0), c->gptr_s, c->gstg_s,
-                     dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream);
-  launch_add_mass_shift(c->n, c->ps.rp, c->P.mass, shift, c->vals_s, mixed ? c->vals_s32 : nullptr, c->stream);
+  launch_segsum_grad(c->n, (long long)c->ngrd_s + (dyn ? c->ngrd_d : 0) + (bod ? c->ngrd_b : 0), c->gptr_s,
+                     c->gstg_s, dyn ? c->gptr_d : nullptr, dyn ? c->gstg_d : nullptr, c->grad, c->stream,
+                     bod ? c->bc_gptr : nullptr, bod ? c->gstg_b : nullptr);
+  // the damping shift acts on the free vertices' rows (lumped masses)
+  launch_add_mass_shift(c->nv, c->ps.rp, c->P.mass, shift, c->vals_s, mixed ? c->vals_s32 : nullptr, c->stream);
   c->prof.end();
   c->prof.begin(YASPS_K_BLOCKINV);
   if (mixed)
     launch_block_inverse_f32(c->n, c->ps.rp, c->vals_s32, dyn ? c->ddiag : nullptr, dyn ? c->vals_d32 : nullptr,
-                             c->minv, c->flags, c->stream);
+                             c->minv, c->flags, c->stream, bod ? c->bc_bdiag : nullptr, bod ? c->vals_b32 : nullptr);
   else
     launch_block_inverse(c->n, c->ps.rp, c->vals_s, dyn ? c->ddiag : nullptr, dyn ? c->vals_d : nullptr, c->minv,
-                         c->flags, c->stream);
+                         c->flags, c->stream, bod ? c->bc_bdiag : nullptr, bod ? c->vals_b : nullptr);
   c->prof.end();
   HIPCHK(c, hipGetLastError());
   c->assembled = true;
@@ -947,10 +1232,17 @@ yasps_status trial_energy(yasps_ctx* c, const double* x0, const double* xt, doub
     launch_hinge_energy(hinge_args(c, xt, g, hoff), c->stream);
     hoff += grid_of(g.end - g.begin, EVAL_BLOCK);
   }
+  launch_body_energy(body_args(c, xt), c->stream);
   int off = 0;
   for (const Group& g : c->groups) {
     ContactArgs ca = contact_args(c, xt, g, off);
     launch_contact_energy(g.type, ca, x0, ca.nact_part, c->stream);  // nact slots reused as "infeasible" counts
+    off += grid_of(g.end - g.begin, EVAL_BLOCK);
+  }
+  off = 0;
+  for (const Group& g : c->bgroups) {
+    BodyContactArgs ba = body_contact_args(c, xt, g, off);
+    launch_body_contact_energy(g.type, ba, x0, ba.nact_part, c->stream);
     off += grid_of(g.end - g.begin, EVAL_BLOCK);
   }
   c->prof.end();
@@ -999,6 +1291,10 @@ yasps_status yasps_assemble_bsr(yasps_ctx* c, yasps_bsr_view* view) {
     view->values_are_f32 = mixed ? 1 : 0;
     view->grad = c->grad;
     view->block_inv = c->minv;
+    view->nnzb_body = c->nbc ? c->pb.nnzb : 0;
+    view->row_ptr_b = c->nbc ? c->pb.rp : nullptr;
+    view->col_idx_b = c->nbc ? c->pb.ci : nullptr;
+    view->values_b = c->nbc ? (mixed ? (const void*)c->vals_b32 : (const void*)c->vals_b) : nullptr;
   }
   return check_flags(c, f);
 }
@@ -1051,7 +1347,8 @@ yasps_status yasps_pcg_noalloc(yasps_ctx* c, const double* b, double* x, double 
                                yasps_pcg_info* info) {
   const yasps_status s = pcg_args(c, b, x, rtol, max_iter);
   if (s) return s;
-  const long long slots = (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0);
+  const long long slots =
+      (long long)c->plan_s.ntarget + (c->nc ? c->plan_d.ntarget : 0) + (c->nbc ? c->plan_b.ntarget : 0);
   const size_t need = pcg_workspace_bytes(c->n, slots);
   if (need > NOALLOC_SCRATCH_BYTES)
     return fail(c, YASPS_E_ARG, "yasps_pcg_noalloc: " + std::to_string(c->n) + " free vertices and " +
@@ -1118,7 +1415,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     return fail(c, YASPS_E_LINESEARCH, "the Newton direction is not a descent direction (g.p >= 0)");
   }
   double alpha = 1.0;
-  if (c->nc > 0 && pmax > 0.0) alpha = std::min(1.0, 0.4 * std::sqrt(ei.min_d) / pmax);
+  if ((c->nc > 0 || c->nbc > 0) && pmax > 0.0) alpha = std::min(1.0, 0.4 * std::sqrt(ei.min_d) / pmax);
   ni.alpha0 = alpha;
   bool accepted = false;
   double E1 = ei.energy;
@@ -1156,7 +1453,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
 }
 
 yasps_status yasps_get_pattern(yasps_ctx* c, int32_t part, int32_t* row_ptr, int32_t* col_idx, int32_t* slot) {
-  if (!c || (part != 0 && part != 1)) return fail(c, YASPS_E_ARG, "bad context or part");
+  if (!c || part < 0 || part > 2) return fail(c, YASPS_E_ARG, "bad context or part");
   if (part == 1 && !c->hpat_d_current) {  // device build: copy its pattern and slot map to the host once
     PartPattern& d = c->hpat_d;
     d.row_ptr.resize(c->n + 1);
@@ -1168,7 +1465,7 @@ yasps_status yasps_get_pattern(yasps_ctx* c, int32_t part, int32_t* row_ptr, int
     if (c->nc) HIPCHK(c, hipMemcpy(d.slot.data(), c->dslot, sizeof(int32_t) * 10 * (size_t)c->nc, hipMemcpyDeviceToHost));
     c->hpat_d_current = true;
   }
-  const PartPattern& h = part == 0 ? c->hpat_s : c->hpat_d;
+  const PartPattern& h = part == 0 ? c->hpat_s : (part == 1 ? c->hpat_d : c->hpat_b);
   const int n = c->n;
   if (row_ptr) {
     if (h.row_ptr.empty())
@@ -1213,16 +1510,18 @@ yasps_status yasps_lm_shift(yasps_ctx* c, double frac, double* out) {
   if (!(frac >= 0.0)) return fail(c, YASPS_E_ARG, "frac must be >= 0");
   if (!c->evaluated || !c->assembled) return fail(c, YASPS_E_ARG, "lm_shift called before assembly");
   HIPCHK(c, hipSetDevice(c->device));
-  const int n = c->n;
+  const int n = c->nv;  // the free vertices' rows (bodies have no lumped mass)
   if (n == 0) {
     *out = 0.0;
     return YASPS_OK;
   }
   const bool mixed = c->prm.precision == YASPS_MIXED;
-  const bool dyn = c->nc > 0;
+  const bool dyn = c->nc > 0, bod = c->nbc > 0;
   // ratios into x_trial, sorted into b_tmp (both (n, 3) work vectors of the context)
   launch_diag_ratio(n, c->ps.rp, mixed ? (const void*)c->vals_s32 : (const void*)c->vals_s, dyn ? c->ddiag : nullptr,
-                    dyn ? (mixed ? (const void*)c->vals_d32 : (const void*)c->vals_d) : nullptr, mixed, c->P.mass,
+                    dyn ? (mixed ? (const void*)c->vals_d32 : (const void*)c->vals_d) : nullptr,
+                    bod ? c->bc_bdiag : nullptr,
+                    bod ? (mixed ? (const void*)c->vals_b32 : (const void*)c->vals_b) : nullptr, mixed, c->P.mass,
                     c->x_trial, c->stream);
   HIPCHK(c, hipGetLastError());
   size_t bytes = 0;

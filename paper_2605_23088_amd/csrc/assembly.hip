@@ -84,12 +84,13 @@ YDEV void lane_sum(int j, int e, const T* __restrict__ stg, double acc[W]) {
 // segment: lane l sums contributions l, l + G, ... of its segment (W values
 // each, contiguous, so a group reads G consecutive contributions per step),
 // then the group combines its partial sums with a fixed butterfly and lane 0
-// writes the W results.  Two ranges (static and dynamic parts of the
-// gradient) may be chained per segment.
+// writes the W results.  Up to three ranges (static, dynamic and body-contact
+// parts of the gradient) may be chained per segment.
 template <class T, int W, int G>
 __global__ __launch_bounds__(RED_BLOCK) void segsum_kernel(int nseg, const int32_t* __restrict__ p1,
                                                            const T* __restrict__ s1, const int32_t* __restrict__ p2,
-                                                           const T* __restrict__ s2, T* __restrict__ out) {
+                                                           const T* __restrict__ s2, const int32_t* __restrict__ p3,
+                                                           const T* __restrict__ s3, T* __restrict__ out) {
   const int seg = (blockIdx.x * RED_BLOCK + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   double acc[W];
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(RED_BLOCK) void segsum_kernel(int nseg, const int32
   if (seg < nseg) {
     lane_sum<T, W, G>(p1[seg] + lane, p1[seg + 1], s1, acc);
     if (p2) lane_sum<T, W, G>(p2[seg] + lane, p2[seg + 1], s2, acc);
+    if (p3) lane_sum<T, W, G>(p3[seg] + lane, p3[seg + 1], s3, acc);
   }
 #pragma unroll
   for (int m = G / 2; m > 0; m >>= 1) {
@@ -120,16 +122,16 @@ int group_for(long long items, int nseg) {
 
 template <class T, int W>
 void launch_segsum(int nseg, const int32_t* p1, const T* s1, const int32_t* p2, const T* s2, T* out, int G,
-                   hipStream_t s) {
+                   hipStream_t s, const int32_t* p3 = nullptr, const T* s3 = nullptr) {
   if (nseg == 0) return;
   const size_t threads = (size_t)nseg * G;
-  const dim3 grid((unsigned)((threads + RED_BLOCK - 1) / RED_BLOCK));
+  const dim3 grid((unsigned)((threads + RED_BLOCK - 1) / RED_BLOCK)), b(RED_BLOCK);
   switch (G) {
-    case 4: hipLaunchKernelGGL((segsum_kernel<T, W, 4>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
-    case 8: hipLaunchKernelGGL((segsum_kernel<T, W, 8>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
-    case 16: hipLaunchKernelGGL((segsum_kernel<T, W, 16>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
-    case 32: hipLaunchKernelGGL((segsum_kernel<T, W, 32>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
-    default: hipLaunchKernelGGL((segsum_kernel<T, W, 64>), grid, dim3(RED_BLOCK), 0, s, nseg, p1, s1, p2, s2, out); break;
+    case 4: hipLaunchKernelGGL((segsum_kernel<T, W, 4>), grid, b, 0, s, nseg, p1, s1, p2, s2, p3, s3, out); break;
+    case 8: hipLaunchKernelGGL((segsum_kernel<T, W, 8>), grid, b, 0, s, nseg, p1, s1, p2, s2, p3, s3, out); break;
+    case 16: hipLaunchKernelGGL((segsum_kernel<T, W, 16>), grid, b, 0, s, nseg, p1, s1, p2, s2, p3, s3, out); break;
+    case 32: hipLaunchKernelGGL((segsum_kernel<T, W, 32>), grid, b, 0, s, nseg, p1, s1, p2, s2, p3, s3, out); break;
+    default: hipLaunchKernelGGL((segsum_kernel<T, W, 64>), grid, b, 0, s, nseg, p1, s1, p2, s2, p3, s3, out); break;
   }
 }
 
@@ -167,7 +169,8 @@ __global__ __launch_bounds__(RED_BLOCK) void block_inverse_kernel(int n, const i
                                                                   const T* __restrict__ vs,
                                                                   const int32_t* __restrict__ ddiag,
                                                                   const T* __restrict__ vd, double* __restrict__ inv,
-                                                                  uint32_t* flags) {
+                                                                  uint32_t* flags, const int32_t* __restrict__ bdiag,
+                                                                  const T* __restrict__ vb) {
   const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
   if (v >= n) return;
   double D[9];
@@ -179,6 +182,13 @@ __global__ __launch_bounds__(RED_BLOCK) void block_inverse_kernel(int n, const i
     if (dd >= 0) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) D[k] += double(vd[9 * (size_t)dd + k]);
+    }
+  }
+  if (bdiag) {
+    const int bd = bdiag[v];
+    if (bd >= 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) D[k] += double(vb[9 * (size_t)bd + k]);
     }
   }
   // adjugate / determinant; the block is symmetric, so compute the upper
@@ -284,8 +294,9 @@ void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cpt
 }
 
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
-                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s) {
-  launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s);
+                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s,
+                        const int32_t* gptr_b, const double* stg_b) {
+  launch_segsum<double, 3>(n, gptr_s, stg_s, gptr_d, stg_d, grad, group_for(ncontrib, n), s, gptr_b, stg_b);
 }
 
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
@@ -306,6 +317,8 @@ __global__ __launch_bounds__(RED_BLOCK) void diag_ratio_kernel(int n, const int3
                                                                const T* __restrict__ vs,
                                                                const int32_t* __restrict__ ddiag,
                                                                const T* __restrict__ vd,
+                                                               const int32_t* __restrict__ bdiag,
+                                                               const T* __restrict__ vb,
                                                                const double* __restrict__ mass,
                                                                double* __restrict__ ratio) {
   const int v = blockIdx.x * RED_BLOCK + threadIdx.x;
@@ -316,35 +329,43 @@ __global__ __launch_bounds__(RED_BLOCK) void diag_ratio_kernel(int n, const int3
     const T* e = vd + 9 * (size_t)ddiag[v];
     tr += double(e[0]) + double(e[4]) + double(e[8]);
   }
+  if (bdiag && bdiag[v] >= 0) {
+    const T* e = vb + 9 * (size_t)bdiag[v];
+    tr += double(e[0]) + double(e[4]) + double(e[8]);
+  }
   ratio[v] = fabs(tr) / (3.0 * mass[v]);
 }
 
 }  // namespace
 
 void launch_diag_ratio(int n, const int32_t* row_ptr_s, const void* vals_s, const int32_t* ddiag, const void* vals_d,
-                       bool f32, const double* mass, double* ratio, hipStream_t s) {
+                       const int32_t* bdiag, const void* vals_b, bool f32, const double* mass, double* ratio,
+                       hipStream_t s) {
   if (n == 0) return;
   const dim3 g((n + RED_BLOCK - 1) / RED_BLOCK), b(RED_BLOCK);
   if (f32)
     hipLaunchKernelGGL((diag_ratio_kernel<float>), g, b, 0, s, n, row_ptr_s, static_cast<const float*>(vals_s), ddiag,
-                       static_cast<const float*>(vals_d), mass, ratio);
+                       static_cast<const float*>(vals_d), bdiag, static_cast<const float*>(vals_b), mass, ratio);
   else
     hipLaunchKernelGGL((diag_ratio_kernel<double>), g, b, 0, s, n, row_ptr_s, static_cast<const double*>(vals_s),
-                       ddiag, static_cast<const double*>(vals_d), mass, ratio);
+                       ddiag, static_cast<const double*>(vals_d), bdiag, static_cast<const double*>(vals_b), mass,
+                       ratio);
 }
 
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s, const int32_t* ddiag,
-                          const double* vals_d, double* inv, uint32_t* flags, hipStream_t s) {
+                          const double* vals_d, double* inv, uint32_t* flags, hipStream_t s, const int32_t* bdiag,
+                          const double* vals_b) {
   if (n == 0) return;
   hipLaunchKernelGGL((block_inverse_kernel<double>), dim3((n + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s,
-                     n, row_ptr_s, vals_s, ddiag, vals_d, inv, flags);
+                     n, row_ptr_s, vals_s, ddiag, vals_d, inv, flags, bdiag, vals_b);
 }
 
 void launch_block_inverse_f32(int n, const int32_t* row_ptr_s, const float* vals_s, const int32_t* ddiag,
-                              const float* vals_d, double* inv, uint32_t* flags, hipStream_t s) {
+                              const float* vals_d, double* inv, uint32_t* flags, hipStream_t s,
+                              const int32_t* bdiag, const float* vals_b) {
   if (n == 0) return;
   hipLaunchKernelGGL((block_inverse_kernel<float>), dim3((n + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s,
-                     n, row_ptr_s, vals_s, ddiag, vals_d, inv, flags);
+                     n, row_ptr_s, vals_s, ddiag, vals_d, inv, flags, bdiag, vals_b);
 }
 
 void launch_finalize(int nseg, const int* off_host, const double* parts, const int* kind_host, double* out,

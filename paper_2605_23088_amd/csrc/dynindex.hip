@@ -287,30 +287,31 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   auto ialloc = [&](int which, long long m) {
     return static_cast<int32_t*>(alloc(which, sizeof(int32_t) * std::max<long long>(m, 1)));
   };
-  out.rp = ialloc(DI_RP, n + 1);
+  const int nr = std::max(in.nrows, n);  // row arrays span every row (the rows past n stay empty)
+  out.rp = ialloc(DI_RP, nr + 1);
   out.col = ialloc(DI_COL, nnzb);
   out.cptr = ialloc(DI_CPTR, nnzb + 1);
   out.slot = ialloc(DI_SLOT, 10ll * nc);
   out.spos = ialloc(DI_SPOS, 10ll * nc);
   out.gpos = ialloc(DI_GPOS, 4ll * nc);
-  out.gptr = ialloc(DI_GPTR, n + 1);
-  out.ddiag = ialloc(DI_DDIAG, n);
+  out.gptr = ialloc(DI_GPTR, nr + 1);
+  out.ddiag = ialloc(DI_DDIAG, nr);
   out.sidx = sidx;
   if (!out.rp || !out.col || !out.cptr || !out.slot || !out.spos || !out.gpos || !out.gptr || !out.ddiag) return -1;
-  int32_t* rowcnt = tmp.get<int32_t>(n);
+  int32_t* rowcnt = tmp.get<int32_t>(nr);
   DI_CHECK(tmp.err);
-  DI_CHECK(hipMemsetAsync(rowcnt, 0, sizeof(int32_t) * std::max(n, 1), s));
+  DI_CHECK(hipMemsetAsync(rowcnt, 0, sizeof(int32_t) * std::max(nr, 1), s));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.slot);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.spos);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(4ll * nc)), dim3(DI_BLOCK), 0, s, 4ll * nc, -1, out.gpos);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, (long long)n, -1, out.ddiag);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(nr)), dim3(DI_BLOCK), 0, s, (long long)nr, -1, out.ddiag);
   if (ne)
     hipLaunchKernelGGL(blocks_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, ne, nc, bkey_s, bval_s, blk, first,
                        order, out.spos, out.col, out.cptr, out.slot, rowcnt, out.ddiag, offdiag);
   DI_CHECK(hipMemcpyAsync(out.cptr + nnzb, &ne, sizeof(int), hipMemcpyHostToDevice, s));
-  DI_CHECK(prefix(tmp, rowcnt, out.rp, n, s));
+  DI_CHECK(prefix(tmp, rowcnt, out.rp, nr, s));
   if (ng) hipLaunchKernelGGL(grads_kernel, dim3(grid_of(ng)), dim3(DI_BLOCK), 0, s, ng, nc, gval_s, out.gpos);
-  hipLaunchKernelGGL(gptr_kernel, dim3(grid_of(n + 1)), dim3(DI_BLOCK), 0, s, n, ng, gkey_s, out.gptr);
+  hipLaunchKernelGGL(gptr_kernel, dim3(grid_of(nr + 1)), dim3(DI_BLOCK), 0, s, nr, ng, gkey_s, out.gptr);
 
   DI_CHECK(hipGetLastError());
   DI_CHECK(hipStreamSynchronize(s));  // the temporaries go out of scope

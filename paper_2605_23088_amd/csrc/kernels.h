@@ -101,6 +101,68 @@ struct InertiaArgs {
 void launch_inertia(const InertiaArgs& a, hipStream_t s);
 void launch_inertia_energy(const InertiaArgs& a, hipStream_t s);
 
+// Affine bodies: per body the inertia 1/2 (q - q~)^T (M4 (x) I3) (q - q~) (or,
+// static, the gravity potential) and the orthogonality energy
+// h^2 k 1/2 |A^T A - I|^2 over its four rows (a_1, a_2, a_3, t) at x rows
+// nv + 4 b ...: energies, 4 gradient rows and the 10 upper 3x3 blocks.
+struct BodyArgs {
+  int nv, nb;             // free vertices (the bodies' rows follow them), bodies
+  const double* x;        // (nv + 4 nb, 3)
+  const double* x_tilde;  // (nv + 4 nb, 3); unused when static
+  const double* M4;       // [nb][16]
+  const double* k;        // [nb]
+  double h2;
+  int is_static;
+  double g[3];
+  const int32_t* spos;    // [10][nb] staged block positions
+  const int32_t* gpos;    // [4][nb] staged gradient positions
+  double* blk;
+  float* blk32;
+  double* grd;
+  double* e_inertia;      // per workgroup
+  double* e_orth;         // per workgroup
+  uint32_t* flags;
+};
+void launch_body_eval(const BodyArgs& a, bool exact, hipStream_t s);
+void launch_body_energy(const BodyArgs& a, hipStream_t s);
+
+// Contact stencils touching affine bodies (the third part), stored grouped by
+// (type, number of movable vertices).  The position of a vertex comes from the
+// union of free (id < nv: x), fixed (id < nv + nfix: x_fixed) and body vertices
+// (k = id - nv - nfix: A r + t from the body's rows).  Pass 1 evaluates the
+// barrier over the movable positions (projected there) into position-space
+// scratch; pass 2 maps it to the stencil's row list (the chain rule through
+// the union) and stages the blocks and gradient rows.
+struct BodyContactArgs {
+  int nv, nfix;
+  const double* x;
+  const double* x_fixed;
+  const int32_t* body_of;    // [n_body_verts]
+  const double* body_rest;   // [n_body_verts][3]
+  int begin, end, ns;        // group range; all stencils (stride of the SoA arrays)
+  const int32_t* idx;        // [4][ns] vertex ids, storage order
+  const int32_t* vpos;       // [4][ns] list position of each vertex's first row, -1 none
+  const int32_t* rows;       // [8][ns] row lists, -1 padded
+  const int32_t* spos;       // [36][ns] staged block positions
+  const int32_t* gpos;       // [8][ns] staged gradient positions
+  double kappa, dhat;
+  int barrier;
+  double* pos_blk;           // [ns][10][9] movable-pair blocks (pair order over 4)
+  double* pos_grd;           // [ns][4][3]
+  double* blk;
+  float* blk32;
+  double* grd;
+  double* e_part;
+  double* d_out;
+  double* dmin_part;
+  double* nact_part;
+  uint32_t* flags;
+};
+void launch_body_contact_eval(int type, int nmov, const BodyContactArgs& a, bool exact, hipStream_t s);
+// Line-search trial at x (already x + alpha p); x0 = the step's start for the side test.
+void launch_body_contact_energy(int type, const BodyContactArgs& a, const double* x0, double* bad_part,
+                                hipStream_t s);
+
 // Contact stencils, processed in groups of equal (type, number of free vertices)
 // stored contiguously.
 struct ContactArgs {
@@ -132,7 +194,8 @@ void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, 
 // array equals the host builder's (pattern.cpp).  Input arrays are device
 // memory; the static share of the full rows is the static-only FullPattern.
 struct DynIndexIn {
-  int n, nall, nc;
+  int n, nall, nc;         // free vertices (ids below n have a row), all vertex ids, contacts
+  int nrows;               // rows of the matrix (>= n: affine-body rows follow the free vertices)
   const int32_t* type;     // [nc]
   const int32_t* idx;      // [4][nc], API order
   void* arena;             // device scratch for the temporaries (may be null)
@@ -167,20 +230,26 @@ void launch_segsum_blocks(int nslots, long long ncontrib, const int32_t* cptr, c
 void launch_segsum_blocks_f32(int nslots, long long ncontrib, const int32_t* cptr, const float* staged,
                               float* out, hipStream_t s);
 void launch_segsum_grad(int n, long long ncontrib, const int32_t* gptr_s, const double* stg_s,
-                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s);
+                        const int32_t* gptr_d, const double* stg_d, double* grad, hipStream_t s,
+                        const int32_t* gptr_b = nullptr, const double* stg_b = nullptr);
 // vals_s[row_ptr_s[v]] += shift m_v I (the diagonal block is first in its static row).
 void launch_add_mass_shift(int n, const int32_t* row_ptr_s, const double* mass, double shift, double* vals_s,
                            float* vals_s32, hipStream_t s);
-// ratio[v] = |tr(D_v)| / (3 m_v) for the assembled diagonal blocks D_v (static + dynamic).
+// ratio[v] = |tr(D_v)| / (3 m_v) for the assembled diagonal blocks D_v (static
+// + dynamic + body-contact parts) of the first n rows.
 void launch_diag_ratio(int n, const int32_t* row_ptr_s, const void* vals_s, const int32_t* ddiag, const void* vals_d,
-                       bool f32, const double* mass, double* ratio, hipStream_t s);
+                       const int32_t* bdiag, const void* vals_b, bool f32, const double* mass, double* ratio,
+                       hipStream_t s);
 // Block-Jacobi inverse of static + dynamic diagonal blocks.
+// (bdiag / vals_b: the body-contact part's diagonal blocks, or null.)
 void launch_block_inverse(int n, const int32_t* row_ptr_s, const double* vals_s,
                           const int32_t* ddiag, const double* vals_d, double* inv,
-                          uint32_t* flags, hipStream_t s);
+                          uint32_t* flags, hipStream_t s, const int32_t* bdiag = nullptr,
+                          const double* vals_b = nullptr);
 void launch_block_inverse_f32(int n, const int32_t* row_ptr_s, const float* vals_s,
                               const int32_t* ddiag, const float* vals_d, double* inv,
-                              uint32_t* flags, hipStream_t s);
+                              uint32_t* flags, hipStream_t s, const int32_t* bdiag = nullptr,
+                              const float* vals_b = nullptr);
 
 // Deterministic final sums of per-workgroup partials: out[k] = sum (or min) of
 // parts[off[k] .. off[k+1]).
@@ -221,9 +290,10 @@ enum { PL_RL, PL_M0, PL_TB, PL_META, PL_TEND, PL_WSLOT, PL_HPTR, PL_COUNT };
 int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, const void* vals, SpmvPart& out,
                     const std::function<void*(int, size_t)>& alloc, void* arena, size_t arena_bytes,
                     size_t* arena_needed, hipStream_t s);
+constexpr int PCG_PARTS = 3;  // static, dynamic (contacts), body contacts
 struct PcgMatrix {
   int n = 0;
-  SpmvPart part[2];          // static, dynamic (nblk = 0 without contacts)
+  SpmvPart part[PCG_PARTS];  // static, dynamic, body contacts (nblk = 0 when empty)
   const double* minv = nullptr;  // (n, 9) block-Jacobi inverse
   bool f32 = false;          // stored blocks in float32 (precision form)
 };

@@ -26,9 +26,10 @@ struct PartPattern {
   std::vector<int32_t> slot;      // [n_stencils][10], stencil-major (API order)
 };
 
-// Builds the pattern of one part from stencils given as [4][ns] vertex ids.
-// `diag` adds (v, v) for every free vertex.
-void build_pattern(int n_free, const int32_t* idx_soa, int ns, bool diag, PartPattern& out);
+// Builds the pattern of one part from stencils given as [width][ns] vertex (or
+// row) ids, ids >= n_free having no row; slot is [ns][width (width + 1) / 2].
+// `diag` adds (v, v) for every row.
+void build_pattern(int n_free, const int32_t* idx_soa, int ns, bool diag, PartPattern& out, int width = 4);
 
 // Staging layout: contributions of every slot are stored contiguously
 // (cptr[slot] .. cptr[slot + 1]) in the order: optional per-vertex leading
@@ -43,10 +44,12 @@ struct Staging {
 };
 
 // `order` lists the stencils in storage order (stencil ids into idx_soa);
-// slot must come from build_pattern over the same stencils (API order).
+// slot must come from build_pattern over the same stencils (API order).  The
+// leading entries are those of rows < nlead (-1: every row).
 void build_staging(int n_free, const int32_t* idx_soa, int ns, const PartPattern& pat,
-                   const std::vector<int32_t>& order, bool lead_block, bool lead_grad, Staging& out);
+                   const std::vector<int32_t>& order, bool lead_block, bool lead_grad, Staging& out,
+                   int width = 4, int nlead = -1);
 
-int used_vertices(const int32_t* idx_soa, int ns, int s);
+int used_vertices(const int32_t* idx_soa, int ns, int s, int width = 4);
 
 }  // namespace yasps

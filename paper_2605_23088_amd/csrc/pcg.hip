@@ -79,13 +79,13 @@ static_assert(MAX_WG_B % NXCD == 0 && MAX_WG_C % NXCD == 0, "partial-sum arrays 
 enum SpmvMode { SPMV_PCG = 0, SPMV_PLAIN = 1, SPMV_REPLACE = 2 };
 
 // Krylov vectors in VT (float64, or float32 in the precision form); the
-// solution x is always float64.  W0 / W1: the SpMV slots of the static and
-// dynamic parts (float64, 3 per slot).
+// solution x is always float64.  W[p]: the SpMV slots of part p (float64, 3
+// per slot).
 template <class VT>
 struct Vecs {
   VT *r, *u, *p, *s;
   double *part_b, *part_c;  // part_c holds 2 * MAX_WG_C partials
-  double *W0, *W1;
+  double* W[PCG_PARTS];     // SpMV slots of each part
 };
 
 // Adds the slots [e, f) of one part to w in slot order; four loads are issued
@@ -104,13 +104,24 @@ YDEV double add_slots(double w, const double* __restrict__ W, int e, int f, int 
   return w;
 }
 
-// w_v[c] = sum of the SpMV slots of vertex v, static part then dynamic, in slot order
-YDEV double w_sum(const PcgMatrix& A, const double* __restrict__ W0, const double* __restrict__ W1, int v, int c) {
-  const int32_t* h0 = A.part[0].hptr;
-  const int32_t* h1 = A.part[1].hptr;
-  const int e0 = h0 ? h0[v] : 0, f0 = h0 ? h0[v + 1] : 0;
-  const int e1 = h1 ? h1[v] : 0, f1 = h1 ? h1[v + 1] : 0;
-  return add_slots(add_slots(0.0, W0, e0, f0, c), W1, e1, f1, c);
+// w_v[c] = sum of the SpMV slots of row v, part by part, in slot order
+struct Slots {
+  double* W[PCG_PARTS];
+};
+YDEV double w_sum(const PcgMatrix& A, const Slots& S, int v, int c) {
+  double w = 0.0;
+#pragma unroll
+  for (int p = 0; p < PCG_PARTS; ++p)
+    if (const int32_t* h = A.part[p].hptr) w = add_slots(w, S.W[p], h[v], h[v + 1], c);
+  return w;
+}
+
+template <class VT>
+YHD Slots slots_of(const Vecs<VT>& V) {
+  Slots S;
+#pragma unroll
+  for (int p = 0; p < PCG_PARTS; ++p) S.W[p] = V.W[p];
+  return S;
 }
 
 // Chunked product W = slots of H u (see the file comment).  BT: stored block
@@ -123,8 +134,7 @@ YDEV double w_sum(const PcgMatrix& A, const double* __restrict__ W0, const doubl
 // summed after it), SPMV_PLAIN (product only), SPMV_REPLACE (product only,
 // skipped once the solver is done).
 template <class BT, class XT>
-__global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, const XT* __restrict__ u,
-                                                               double* __restrict__ W0, double* __restrict__ W1,
+__global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, const XT* __restrict__ u, Slots S,
                                                                double* __restrict__ part_b,
                                                                const double* __restrict__ part_c, PcgState* st,
                                                                int nb_c, int mode) {
@@ -141,14 +151,14 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
     gp[q] = in ? part_c[j] : 0.0;
     rp[q] = in ? part_c[nb_c + j] : 0.0;
   }
-  const int C0 = A.part[0].nchunk, C = C0 + A.part[1].nchunk;
+  const int C0 = A.part[0].nchunk, C1 = C0 + A.part[1].nchunk, C = C1 + A.part[2].nchunk;
   const int xcd = blockIdx.x % NXCD, per = gridDim.x / NXCD;
   const int cend = (int)((long long)C * (xcd + 1) / NXCD);
   double dlt = 0.0;
   for (int c = (int)((long long)C * xcd / NXCD) + (int)blockIdx.x / NXCD; c < cend; c += per) {
-    const bool dyn = c >= C0;
-    const SpmvPart& P = dyn ? A.part[1] : A.part[0];
-    const int cc = dyn ? c - C0 : c;
+    const int pi = c < C0 ? 0 : (c < C1 ? 1 : 2);
+    const SpmvPart& P = A.part[pi];
+    const int cc = c - (pi == 0 ? 0 : (pi == 1 ? C0 : C1));
     const int b0 = cc * P.chunk, b1 = min(b0 + P.chunk, P.nblk);
     const int m0 = P.m0[cc];
     const int32_t* __restrict__ rl = P.rl;  // null when every row holds blocks (row = compressed row)
@@ -185,7 +195,7 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
     }
     __syncthreads();
     const int t0 = P.tb[cc], nt = P.tb[cc + 1] - t0;
-    double* __restrict__ W = dyn ? W1 : W0;
+    double* __restrict__ W = S.W[pi];
     for (int q = threadIdx.x; q < nt; q += RED_BLOCK) {
       const int e1 = P.tend[t0 + q], e0 = q ? P.tend[t0 + q - 1] : 0;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
   for (int v = blockIdx.x * RED_BLOCK + threadIdx.x; v < A.n; v += gridDim.x * RED_BLOCK) {
     double r[3], u[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)v + c] - w_sum(A, V.W0, V.W1, v, c);
+    for (int c = 0; c < 3; ++c) r[c] = b[3 * (size_t)v + c] - w_sum(A, slots_of(V), v, c);
     precondition(A.minv, v, r, u);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -303,12 +313,11 @@ __global__ __launch_bounds__(RED_BLOCK) void pcg_replace_kernel(PcgMatrix A, con
 }
 
 // y = H x from the slots of a SPMV_PLAIN product
-__global__ __launch_bounds__(RED_BLOCK) void spmv_finish_kernel(PcgMatrix A, const double* __restrict__ W0,
-                                                                const double* __restrict__ W1, double* __restrict__ y) {
+__global__ __launch_bounds__(RED_BLOCK) void spmv_finish_kernel(PcgMatrix A, Slots S, double* __restrict__ y) {
   const long long i = (long long)blockIdx.x * RED_BLOCK + threadIdx.x;
   if (i >= 3ll * A.n) return;
   const int v = (int)(i / 3), c = (int)(i - 3ll * v);
-  y[i] = w_sum(A, W0, W1, v, c);
+  y[i] = w_sum(A, S, v, c);
 }
 
 // One pass of the update kernel: the values a thread reads, loaded before the
@@ -332,7 +341,7 @@ YDEV UpdLoads upd_load(const PcgMatrix& A, const double* x, const Vecs<VT>& V, i
     L.m0 = M[0];
     L.m1 = M[1];
     L.m2 = M[2];
-    L.w = double(VT(w_sum(A, V.W0, V.W1, v, c)));
+    L.w = double(VT(w_sum(A, slots_of(V), v, c)));
   }
   return L;
 }
@@ -423,12 +432,14 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
 
 int round_xcd(int g) { return (g + NXCD - 1) / NXCD * NXCD; }
 int grid_b(const PcgMatrix& A) {
-  return round_xcd(std::max(1, std::min(A.part[0].nchunk + A.part[1].nchunk, MAX_WG_B)));
+  return round_xcd(std::max(1, std::min(A.part[0].nchunk + A.part[1].nchunk + A.part[2].nchunk, MAX_WG_B)));
 }
 int grid_c(int n) { return round_xcd(std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C))); }
 // LDS of the chunk kernel: the larger chunk's products
 size_t spmv_lds_bytes(const PcgMatrix& A) {
-  return 3 * sizeof(double) * (size_t)std::max(1, std::max(A.part[0].max_entries, A.part[1].max_entries));
+  int m = 1;
+  for (const SpmvPart& P : A.part) m = std::max(m, P.max_entries);
+  return 3 * sizeof(double) * (size_t)m;
 }
 
 template <class VT>
@@ -439,9 +450,12 @@ void carve(void* work, const PcgMatrix& A, PcgState*& st, Vecs<VT>& V) {
   double* parts = reinterpret_cast<double*>(w + ((sizeof(PcgState) + 255) / 256) * 256);
   V.part_b = parts;
   V.part_c = parts + MAX_WG_B;
-  V.W0 = parts + MAX_WG_B + 2 * MAX_WG_C;
-  V.W1 = V.W0 + 3 * (size_t)A.part[0].ntarget;
-  VT* base = reinterpret_cast<VT*>(V.W1 + 3 * (size_t)A.part[1].ntarget);
+  double* q = parts + MAX_WG_B + 2 * MAX_WG_C;
+  for (int p = 0; p < PCG_PARTS; ++p) {
+    V.W[p] = q;
+    q += 3 * (size_t)A.part[p].ntarget;
+  }
+  VT* base = reinterpret_cast<VT*>(q);
   V.r = base;
   V.u = V.r + n3;
   V.p = V.u + n3;
@@ -460,11 +474,11 @@ void timed_launch(LaunchTimer* tm, int cls, KERNEL kernel, int grid, int block, 
 }
 
 // The chunked product.
-template <class BT, class XT>
-void launch_chunks(LaunchTimer* tm, const PcgMatrix& A, const XT* u, double* W0, double* W1, double* part_b,
+template <class BT, class XT, class VT>
+void launch_chunks(LaunchTimer* tm, const PcgMatrix& A, const XT* u, const Vecs<VT>& V, double* part_b,
                    const double* part_c, PcgState* st, int nb_c, int mode, hipStream_t s) {
-  timed_launch(tm, SPMV_CLASS, spmv_chunk_kernel<BT, XT>, grid_b(A), RED_BLOCK, spmv_lds_bytes(A), s, A, u, W0, W1,
-               part_b, part_c, st, nb_c, mode);
+  timed_launch(tm, SPMV_CLASS, spmv_chunk_kernel<BT, XT>, grid_b(A), RED_BLOCK, spmv_lds_bytes(A), s, A, u,
+               slots_of(V), part_b, part_c, st, nb_c, mode);
 }
 
 }  // namespace
@@ -513,12 +527,12 @@ void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hip
   Vecs<double> V;
   carve(work, A, st, V);
   if (A.f32)
-    launch_chunks<float, double>(tm, A, x, V.W0, V.W1, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
+    launch_chunks<float, double>(tm, A, x, V, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
   else
-    launch_chunks<double, double>(tm, A, x, V.W0, V.W1, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
+    launch_chunks<double, double>(tm, A, x, V, nullptr, nullptr, nullptr, 0, SPMV_PLAIN, s);
   const long long n3 = 3ll * A.n;
   timed_launch(tm, SPMV_CLASS, spmv_finish_kernel, (int)((n3 + RED_BLOCK - 1) / RED_BLOCK), RED_BLOCK, 0, s, A,
-               (const double*)V.W0, (const double*)V.W1, y);
+               slots_of(V), y);
 }
 
 namespace {
@@ -545,7 +559,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
     return 0;
   }
   auto replace = [&]() {  // r = b - H x in float64 (precision form)
-    launch_chunks<BT, double>(nullptr, A, x, V.W0, V.W1, nullptr, nullptr, st, 0, SPMV_REPLACE, s);
+    launch_chunks<BT, double>(nullptr, A, x, V, nullptr, nullptr, st, 0, SPMV_REPLACE, s);
     hipLaunchKernelGGL((pcg_replace_kernel<VT>), dim3(nb_c), dim3(RED_BLOCK), 0, s, A, b, V, st);
   };
   timed_launch(tm, UPDATE_CLASS, pcg_init_kernel<VT>, nb_c, RED_BLOCK, 0, s, A, b, x, V, st);
@@ -562,7 +576,7 @@ int pcg_run(const PcgMatrix& A, const double* b, double* x, double rtol, int max
   constexpr int MAX_RESTARTS = 32;
   for (;;) {
     for (int k = 0; k < batch; ++k) {
-      launch_chunks<BT, VT>(tm, A, V.u, V.W0, V.W1, V.part_b, V.part_c, st, nb_c, SPMV_PCG, s);
+      launch_chunks<BT, VT>(tm, A, V.u, V, V.part_b, V.part_c, st, nb_c, SPMV_PCG, s);
       timed_launch(tm, UPDATE_CLASS, pcg_update_kernel<VT>, nb_c, UPD_BLOCK, 0, s, A, x, V, st, nb_b);
       ++launched;
       if (MIXED && launched % REPLACE_EVERY == 0) replace();

@@ -28,7 +28,8 @@ INDEX_DEVICE, INDEX_HOST = 0, 1  # yasps_params.index_build
 
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
            "yasps_pcg_noalloc", "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
-           "yasps_profile_query", "yasps_spmv", "yasps_lm_shift", "yasps_destroy", "yasps_last_error"]
+           "yasps_profile_query", "yasps_spmv", "yasps_lm_shift", "yasps_set_body_contacts", "yasps_destroy",
+           "yasps_last_error"]
 K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH, K_CLOTH = range(9)
 KERNEL_CLASSES = ["inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "pcg_spmv", "pcg_update",
                   "linesearch", "cloth_eval"]
@@ -42,7 +43,9 @@ class Problem(C.Structure):
                 ("is_static", C.c_int32), ("n_tris", C.c_int32), ("tri_idx", C.c_void_p),
                 ("tri_dm_inv", C.c_void_p), ("tri_area", C.c_void_p), ("mu_c", C.c_double), ("lambda_c", C.c_double),
                 ("thickness", C.c_double), ("n_hinges", C.c_int32), ("hinge_idx", C.c_void_p),
-                ("hinge_rest", C.c_void_p)]
+                ("hinge_rest", C.c_void_p), ("n_bodies", C.c_int32), ("body_mass", C.c_void_p),
+                ("body_k", C.c_void_p), ("n_body_verts", C.c_int32), ("body_of", C.c_void_p),
+                ("body_rest", C.c_void_p)]
 
 
 class Contacts(C.Structure):
@@ -62,7 +65,9 @@ class BsrView(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("nnzb_static", C.c_int32), ("nnzb_dynamic", C.c_int32),
                 ("row_ptr_s", C.c_void_p), ("col_idx_s", C.c_void_p), ("values_s", C.c_void_p),
                 ("row_ptr_d", C.c_void_p), ("col_idx_d", C.c_void_p), ("values_d", C.c_void_p),
-                ("values_are_f32", C.c_int32), ("grad", C.c_void_p), ("block_inv", C.c_void_p)]
+                ("values_are_f32", C.c_int32), ("grad", C.c_void_p), ("block_inv", C.c_void_p),
+                ("nnzb_body", C.c_int32), ("row_ptr_b", C.c_void_p), ("col_idx_b", C.c_void_p),
+                ("values_b", C.c_void_p)]
 
 
 class PcgInfo(C.Structure):
@@ -95,6 +100,7 @@ def lib():
         P = C.c_void_p
         L.yasps_create.argtypes = [C.POINTER(P), P, C.POINTER(Problem), C.POINTER(Params)]
         L.yasps_set_contacts.argtypes = [P, C.POINTER(Contacts)]
+        L.yasps_set_body_contacts.argtypes = [P, C.POINTER(Contacts)]
         L.yasps_eval_stencils.argtypes = [P, P, C.c_int32, C.POINTER(EvalInfo)]
         L.yasps_assemble_bsr.argtypes = [P, C.POINTER(BsrView)]
         L.yasps_pcg.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(PcgInfo)]
@@ -138,7 +144,9 @@ def _ptr(t):
 class Yasps:
     """One context of the library bound to a synthetic problem dict (see
     :mod:`paper_2605_23088_amd.synth`).  Problem arrays are uploaded once and
-    kept alive here; positions are (n_free, 3) float64 CUDA tensors."""
+    kept alive here; positions are (n, 3) float64 CUDA tensors over the rows of
+    degrees of freedom: the free vertices, then a_1, a_2, a_3, t of each affine
+    body (n = n_free + 4 n_bodies)."""
 
     def __init__(self, prob, device="cuda", precision=FP64, proj=F_SPACE, barrier=SQLOG, contacts=True,
                  index_build=INDEX_DEVICE):
@@ -149,12 +157,17 @@ class Yasps:
         L = lib()
         d = self.dev
         f64 = dict(dtype=torch.float64, device=d)
-        self.n = int(prob["n_free"])
+        self.nv = int(prob["n_free"])
+        self.nb = int(prob.get("n_bodies", 0))
+        self.n = self.nv + 4 * self.nb
         nt = int(prob["tet_idx"].shape[0])
         self.nt = nt
         self._x_fixed = torch.as_tensor(np.asarray(prob["x_fixed"]).reshape(-1, 3), **f64).contiguous()
         self._mass = torch.as_tensor(prob["mass"], **f64).contiguous()
-        self._x_tilde = torch.as_tensor(prob["x_tilde"], **f64).contiguous()
+        xt = np.asarray(prob["x_tilde"], np.float64).reshape(-1, 3)
+        if self.nb:
+            xt = np.concatenate([xt, np.asarray(prob["body_qt"], np.float64).reshape(-1, 3)])
+        self._x_tilde = torch.as_tensor(xt, **f64).contiguous()
         self._tet = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["tet_idx"], np.int32).T),
                                     device=d).contiguous()
         self._dm = torch.as_tensor(np.ascontiguousarray(np.asarray(prob["dm_inv"]).reshape(nt, 9).T), **f64)
@@ -163,7 +176,7 @@ class Yasps:
         if "mu_t" in prob:
             self._ml = torch.as_tensor(np.stack([prob["mu_t"], prob["lam_t"]]), **f64).contiguous()
         P = Problem()
-        P.n_free = self.n
+        P.n_free = self.nv
         P.n_fixed = int(self._x_fixed.shape[0])
         P.x_fixed = _ptr(self._x_fixed)
         P.mass = _ptr(self._mass)
@@ -205,6 +218,19 @@ class Yasps:
             P.n_hinges = nh
             P.hinge_idx = _ptr(self._hin)
             P.hinge_rest = _ptr(self._hrest)
+        # affine bodies: M4 [nb][16], k_b [nb], body of each body vertex, rest positions [nbv][3]
+        self.nbc = 0
+        if self.nb:
+            self._bM4 = torch.as_tensor(np.asarray(prob["body_M4"], np.float64).reshape(self.nb, 16), **f64)
+            self._bk = torch.as_tensor(np.asarray(prob["body_k"], np.float64).reshape(self.nb), **f64)
+            self._bof = torch.as_tensor(np.asarray(prob["abd_body"], np.int32), **i32).contiguous()
+            self._brest = torch.as_tensor(np.asarray(prob["abd_rest"], np.float64).reshape(-1, 3), **f64)
+            P.n_bodies = self.nb
+            P.body_mass = _ptr(self._bM4)
+            P.body_k = _ptr(self._bk)
+            P.n_body_verts = int(self._bof.shape[0])
+            P.body_of = _ptr(self._bof)
+            P.body_rest = _ptr(self._brest.contiguous())
         self.params = Params(precision, proj, barrier, index_build)
         self.stream = torch.cuda.current_stream(d)
         ctx = C.c_void_p()
@@ -215,6 +241,8 @@ class Yasps:
         self.nc = 0
         if contacts and len(prob.get("ctype", [])):
             self.set_contacts(prob["ctype"], prob["cidx"])
+        if contacts and len(prob.get("bctype", [])):
+            self.set_body_contacts(prob["bctype"], prob["bcidx"])
 
     def _check(self, rc, allow=()):
         if rc != OK and rc not in allow:
@@ -253,6 +281,20 @@ class Yasps:
             raise
         self.nc = int(t.shape[0])
 
+    def set_body_contacts(self, ctype, cidx):
+        """Host arrays: types (n_s) and vertex ids (n_s, 4) of the stencils touching bodies."""
+        ctype = np.asarray(ctype, np.int32)
+        cidx = np.asarray(cidx, np.int32).reshape(-1, 4)
+        t = torch.as_tensor(ctype, device=self.dev).contiguous()
+        i = torch.as_tensor(np.ascontiguousarray(cidx.T), device=self.dev).contiguous()
+        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i))
+        try:
+            self._check(lib().yasps_set_body_contacts(self.ctx, C.byref(Cs)))
+        except YaspsError:
+            self.nbc = 0
+            raise
+        self.nbc = int(t.shape[0])
+
     def eval(self, x, exact=False, allow=()):
         info = EvalInfo()
         rc = self._check(lib().yasps_eval_stencils(self.ctx, _ptr(x), EXACT if exact else PROJECTED,
@@ -285,6 +327,10 @@ class Yasps:
             out["row_ptr_d"] = self._dev_copy(v.row_ptr_d, n + 1, torch.int32)
             out["col_idx_d"] = self._dev_copy(v.col_idx_d, v.nnzb_dynamic, torch.int32)
             out["values_d"] = self._dev_copy(v.values_d, 9 * v.nnzb_dynamic, vt).view(-1, 3, 3)
+        if v.nnzb_body:
+            out["row_ptr_b"] = self._dev_copy(v.row_ptr_b, n + 1, torch.int32)
+            out["col_idx_b"] = self._dev_copy(v.col_idx_b, v.nnzb_body, torch.int32)
+            out["values_b"] = self._dev_copy(v.values_b, 9 * v.nnzb_body, vt).view(-1, 3, 3)
         return out
 
     def _dev_copy(self, ptr, count, dtype):
@@ -319,12 +365,16 @@ class Yasps:
         return out
 
     def pattern(self, part):
+        """Part 0 static (tets, triangles, hinges, bodies), 1 contacts, 2 body
+        contacts: row_ptr, col_idx and the slot map (10 slots a stencil, 36 for
+        part 2)."""
         n = self.n
-        ns = self.nt + self.nf + self.nh if part == 0 else self.nc
+        ns = (self.nt + self.nf + self.nh + self.nb, self.nc, self.nbc)[part]
+        width = 36 if part == 2 else 10
         rp = np.zeros(n + 1, np.int32)
-        lib().yasps_get_pattern(self.ctx, part, rp.ctypes.data_as(C.c_void_p), None, None)
+        self._check(lib().yasps_get_pattern(self.ctx, part, rp.ctypes.data_as(C.c_void_p), None, None))
         ci = np.zeros(max(int(rp[-1]), 1), np.int32)
-        sl = np.zeros((max(ns, 1), 10), np.int32)
+        sl = np.zeros((max(ns, 1), width), np.int32)
         self._check(lib().yasps_get_pattern(self.ctx, part, rp.ctypes.data_as(C.c_void_p),
                                             ci.ctypes.data_as(C.c_void_p), sl.ctypes.data_as(C.c_void_p)))
         return rp, ci[:int(rp[-1])], sl[:ns]
