@@ -131,6 +131,68 @@ def measured_traffic(kernel, workload, precision):
     return rec["bytes_per_launch"] if rec.get("source_sha256") == sha else None
 
 
+# kernel class -> the device kernel's name in rocprofv3 output
+KERNEL_NAMES = {"pcg_spmv": "spmv_chunk_kernel", "pcg_update": "pcg_update_kernel"}
+
+
+def _pmc_rows(d):
+    """(kernel name, counter value) per dispatch from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def _pmc_sum_per_dispatch(d, prefix):
+    vals = [v for name, v in _pmc_rows(d) if prefix + "<" in name or name.endswith(prefix)]
+    if not vals:
+        raise ValueError(f"no dispatch of {prefix} in {d}")
+    # launches that exit at once after convergence carry almost no traffic
+    keep = [v for v in vals if v >= 0.1 * max(vals)]
+    return sum(keep) / len(keep), len(keep), len(vals)
+
+
+def traffic_record(spec, dirs, commands):
+    """Writes profiles/traffic_<kernel>_<workload>_<precision>.json from four
+    rocprofv3 --pmc runs: FETCH_SIZE and WRITE_SIZE of the workload, then of the
+    plain copy of --copy-calibration-mb (the factors that turn KiB into bytes)."""
+    import hashlib
+    kernel, workload, precision = spec.split(":")
+    prefix = KERNEL_NAMES[kernel]
+    fetch, nf, tf = _pmc_sum_per_dispatch(dirs[0], prefix)
+    write, nw, tw = _pmc_sum_per_dispatch(dirs[1], prefix)
+    cf = max(v for name, v in _pmc_rows(dirs[2]) if "copyBuffer" in name)
+    cw = max(v for name, v in _pmc_rows(dirs[3]) if "copyBuffer" in name)
+    cal_bytes = None
+    for c in commands:
+        if "--copy-calibration-mb" in c:
+            cal_bytes = int(c.split("--copy-calibration-mb")[1].split()[0]) << 20
+    ff, wf = cal_bytes / 1024.0 / cf, cal_bytes / 1024.0 / cw
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "paper_2605_23088_amd", "csrc", KERNEL_SOURCES[kernel]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"kernel": kernel, "workload": workload, "precision": precision, "device_kernel": prefix,
+           "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
+           "copy_calibration": {"bytes": cal_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff,
+                                "write_factor": wf},
+           "bytes_per_launch": 1024.0 * (ff * fetch + wf * write),
+           "launches_averaged": min(nf, nw), "launches_traced": max(tf, tw),
+           "note": "launches that exit at once after convergence (counters under 10 % of the largest) are excluded",
+           "commands": list(commands), "source_sha256": sha}
+    out = os.path.join(here, "profiles", f"traffic_{kernel}_{workload}_{precision}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"written": out, "bytes_per_launch": rec["bytes_per_launch"]}))
+
+
 def n_stencils(prob):
     return (prob["tet_idx"].shape[0] + prob["ctype"].shape[0] + len(prob.get("tri_idx", [])) +
             len(prob.get("hinge_idx", [])))
@@ -350,7 +412,14 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
+    ap.add_argument("--traffic-record", metavar="KERNEL:WORKLOAD:PRECISION",
+                    help="summarise four rocprofv3 --pmc runs (--pmc-dirs) into the profiles/ traffic record and "
+                         "exit (no GPU use)")
+    ap.add_argument("--pmc-dirs", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
+    ap.add_argument("--pmc-commands", nargs=4, help="the four rocprofv3 commands, recorded with the summary")
     args = ap.parse_args()
+    if args.traffic_record:
+        return traffic_record(args.traffic_record, args.pmc_dirs, args.pmc_commands)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is not sharded "
               "across GPUs)", file=sys.stderr)

@@ -146,6 +146,12 @@ typedef struct {
   int32_t n_contacts;
   const int32_t* type; /* [n_contacts] YASPS_PT / EE / PE / PP */
   const int32_t* idx;  /* [4][n_contacts] vertex ids in the order given for the type */
+  const double* ee_eps; /* [n_contacts] or NULL: edge-edge mollifier thresholds eps_x (IPC's
+                           1e-3 |a1 - a0|^2 |b1 - b0|^2 from rest edge lengths).  An EE stencil
+                           with eps_x > 0 and c = |(a1 - a0) x (b1 - b0)|^2 < eps_x has the
+                           barrier m(c) kappa b(d), m = (c / eps_x)(2 - c / eps_x) (near-parallel
+                           edges; m = 1 above eps_x).  Ignored for the other types; NULL or
+                           eps_x <= 0: no mollifier. */
 } yasps_contacts;
 
 typedef struct {

@@ -92,6 +92,8 @@ class AffineScene:
         self.classic = classic
         self.ctype = np.asarray(prob["bctype"], np.int64)
         self.cidx = np.asarray(prob["bcidx"], np.int64).reshape(-1, 4)
+        # edge-edge mollifier thresholds of these stencils, or none
+        self.ee_eps = np.asarray(prob["bee_eps"], np.float64) if prob.get("bee_eps") is not None else None
         self.rows, self.W = self.row_lists(self.cidx)
         # patterns: the body stencils (4 rows each, static) and the body contacts
         brows = self.n_free + 4 * np.arange(self.nb)[:, None] + np.arange(4)[None, :]
@@ -180,13 +182,24 @@ class AffineScene:
         row-list Hessian (ns, 24, 24) J^T Proj(H_p) J, and d."""
         xs, mov = self.positions(X)
         E, gp, Hp, d = local.contact_local(xs, torch.as_tensor(self.ctype), mov, float(self.p["kappa"]),
-                                           float(self.p["dhat"]), hess, self.classic)
+                                           float(self.p["dhat"]), hess, self.classic, self.ee_eps)
         # J: position (vertex a, axis i) -> row list (j, axis l): W[a, j] delta_il
         W = torch.as_tensor(self.W)
         J = torch.einsum("saj,il->saijl", W, torch.eye(3)).reshape(-1, 12, 3 * MAX_ROWS)
         g = (J.transpose(1, 2) @ gp.reshape(-1, 12, 1)).reshape(-1, MAX_ROWS, 3)
         H = J.transpose(1, 2) @ Hp @ J
         return E, g, local.sym(H), d
+
+    def mollifiers(self, X):
+        """m(c) of every body contact (1 except for mollified edge-edge stencils)."""
+        m = torch.ones(self.cidx.shape[0])
+        if self.ee_eps is None:
+            return m
+        xs, _ = self.positions(X)
+        sel = torch.nonzero(torch.as_tensor(self.ctype) == 1).flatten()
+        if sel.numel():
+            m[sel] = en.ee_mollifier(vmap(en.ee_cross_norm)(xs[sel]), torch.as_tensor(self.ee_eps)[sel])
+        return m
 
     def distances(self, X):
         xs, _ = self.positions(X)
@@ -332,6 +345,7 @@ class AffineOracle:
         bfun = en.barrier_ipc_classic if self.base.classic else en.barrier
         act = d < dhat
         Ec = torch.where(act, bfun(torch.where(act, d, torch.full_like(d, dhat)), dhat, kappa), torch.zeros_like(d))
+        Ec = Ec * self.scene.mollifiers(X)
         return self.base.energy(xf) + float(Ein.sum()) + float(Eor.sum()) + float(Ec.sum())
 
     def distances(self, X):

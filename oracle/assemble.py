@@ -36,6 +36,8 @@ class Oracle:
         self.tet_idx = np.asarray(prob["tet_idx"], np.int64)
         self.cidx = np.asarray(prob["cidx"], np.int64)
         self.ctype = np.asarray(prob["ctype"], np.int64)
+        # edge-edge mollifier thresholds (IPC's near-parallel treatment), or none
+        self.ee_eps = np.asarray(prob["ee_eps"], np.float64) if prob.get("ee_eps") is not None else None
         nf = len(prob.get("tri_idx", []))
         nh = len(prob.get("hinge_idx", []))
         self.tri_idx = np.full((nf, 4), -1, np.int64)
@@ -108,7 +110,19 @@ class Oracle:
         xc, free = local.gather_positions(local.T(x), self.x_fixed, self.cidx, self.n)
         return local.contact_local(xc, torch.as_tensor(self.ctype), free,
                                    float(self.p["kappa"]), float(self.p["dhat"]), hess,
-                                   self.classic)
+                                   self.classic, self.ee_eps)
+
+    def mollifiers(self, x):
+        """m(c) of every contact stencil (1 except for mollified edge-edge stencils)."""
+        m = torch.ones(len(self.ctype))
+        if self.ee_eps is None:
+            return m
+        xc, _ = local.gather_positions(local.T(np.asarray(x).reshape(self.n, 3)), self.x_fixed, self.cidx, self.n)
+        sel = torch.nonzero(torch.as_tensor(self.ctype) == 1).flatten()
+        if sel.numel():
+            c = torch.vmap(en.ee_cross_norm)(xc[sel])
+            m[sel] = en.ee_mollifier(c, torch.as_tensor(self.ee_eps)[sel])
+        return m
 
     # ------------------------------------------------------------ whole problem
     def eval(self, x, hess=PROJECTED):
@@ -189,7 +203,7 @@ class Oracle:
         bfun = en.barrier_ipc_classic if self.classic else en.barrier
         act = dt < dhat
         Ec = torch.where(act, bfun(torch.where(act, dt, torch.full_like(dt, dhat)), dhat, kappa),
-                         torch.zeros_like(dt))
+                         torch.zeros_like(dt)) * self.mollifiers(x)
         return dict(inertia=e_i, tets=Et, membranes=Ef, hinges=Eh, contacts=float(Ec.sum()),
                     contact_terms=Ec.numpy())
 

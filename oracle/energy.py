@@ -108,6 +108,23 @@ def dist_pp(x):
     return torch.dot(d, d)
 
 
+def ee_cross_norm(x):
+    """c = ||(a1 - a0) x (b1 - b0)||^2 of an edge-edge stencil x = [a0, a1, b0, b1]
+    (zero for parallel edges)."""
+    n = _cross(x[1] - x[0], x[3] - x[2])
+    return torch.dot(n, n)
+
+
+def ee_mollifier(c, eps):
+    """The edge-edge mollifier of Incremental Potential Contact (Li et al.
+    2020): m(c) = -c^2 / eps^2 + 2 c / eps for c < eps, else 1, with the
+    threshold eps = 1e-3 ||a1 - a0||^2 ||b1 - b0||^2 taken at rest.  eps <= 0
+    means no mollifier (m = 1)."""
+    on = (eps > 0) & (c < eps)
+    e = torch.where(eps > 0, eps, torch.ones_like(eps))
+    return torch.where(on, -(c * c) / (e * e) + 2.0 * c / e, torch.ones_like(c))
+
+
 DIST = (dist_pt, dist_ee, dist_pe, dist_pp)
 N_VERTS = (4, 4, 3, 2)
 

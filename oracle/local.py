@@ -141,14 +141,16 @@ def hinge_local(xh, theta_bar, stiffness, h, free, hess=PROJECTED):
     return E, g, sym(project_principal(H, m12))
 
 
-def contact_local(xc, ctype, free, kappa, dhat, hess=PROJECTED, classic=False):
+def contact_local(xc, ctype, free, kappa, dhat, hess=PROJECTED, classic=False, eps=None):
     """Barrier stencils.  xc (n, 4, 3) vertex rows (unused rows arbitrary finite),
     ctype (n,), free (n, 4) bool (False for fixed and unused vertices).
 
     Returns kappa b(d) (n,), its gradient (n, 4, 3) (fixed vertices zeroed), the
     free-DoF Hessian (n, 12, 12) projected on its free principal submatrix (the
     Hessian with fixed vertices held constant), and d (n,).  Stencils with
-    d >= dhat contribute exactly zero; d <= 0 raises ValueError."""
+    d >= dhat contribute exactly zero; d <= 0 raises ValueError.  eps (n,) or
+    None: edge-edge mollifier thresholds; an EE stencil's energy is then
+    m(c) kappa b(d) (``energy.ee_mollifier``)."""
     n = xc.shape[0]
     E = torch.zeros(n)
     g = torch.zeros(n, 4, 3)
@@ -165,14 +167,23 @@ def contact_local(xc, ctype, free, kappa, dhat, hess=PROJECTED, classic=False):
         if bool((dt <= 0).any()):
             raise ValueError("contact stencil with non-positive distance")
 
-        def f(xs, dist=dist):
-            return bfun(dist(xs), dhat, kappa)
-
         act = (dt < dhat).to(x.dtype)
         d[sel] = dt
-        E[sel] = vmap(f)(x) * act
-        g[sel] = vmap(grad(f))(x) * act.view(-1, 1, 1)
-        H[sel] = vmap(hessian(f))(x).reshape(-1, 12, 12) * act.view(-1, 1, 1)
+        if t == 1 and eps is not None:
+            def f(xs, e, dist=dist):
+                return en.ee_mollifier(en.ee_cross_norm(xs), e) * bfun(dist(xs), dhat, kappa)
+
+            es = torch.as_tensor(eps, dtype=x.dtype)[sel]
+            E[sel] = vmap(f)(x, es) * act
+            g[sel] = vmap(grad(f))(x, es) * act.view(-1, 1, 1)
+            H[sel] = vmap(hessian(f))(x, es).reshape(-1, 12, 12) * act.view(-1, 1, 1)
+        else:
+            def f(xs, dist=dist):
+                return bfun(dist(xs), dhat, kappa)
+
+            E[sel] = vmap(f)(x) * act
+            g[sel] = vmap(grad(f))(x) * act.view(-1, 1, 1)
+            H[sel] = vmap(hessian(f))(x).reshape(-1, 12, 12) * act.view(-1, 1, 1)
     g = g * free.unsqueeze(-1)
     m12 = _mask12(free)
     if hess == EXACT:

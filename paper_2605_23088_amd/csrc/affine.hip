@@ -220,7 +220,9 @@ __global__ __launch_bounds__(EVAL_BLOCK) void body_contact_kernel(BodyContactArg
 #pragma unroll
         for (int l = 0; l < 3; ++l) dst[3 * i + l] = B[i][l];
     };
-    const bool ok = contact_stencil<TYPE, K, EXACT>(xv, fl, a.kappa, a.dhat, a.barrier, e, d, side, gsink, bsink);
+    const double eps = (TYPE == 1 && a.eps) ? a.eps[s] : 0.0;
+    const bool ok =
+        contact_stencil<TYPE, K, EXACT>(xv, fl, a.kappa, a.dhat, a.barrier, e, d, side, gsink, bsink, eps);
     a.d_out[s] = d;
     dmin = d;
     if (!ok || !finite(d) || !finite(e)) atomicOr(a.flags, FLAG_NONFINITE);
@@ -343,7 +345,9 @@ __global__ __launch_bounds__(EVAL_BLOCK) void body_contact_energy_kernel(BodyCon
     if (bad == 0.0 && D.d < a.dhat) {
       double b0, b1, b2;
       barrier(D.d, a.dhat, a.barrier, b0, b1, b2);
-      e = a.kappa * b0;
+      double m = 1.0;
+      if constexpr (TYPE == 1) m = a.eps ? ee_mollifier(u, a.eps[s]) : 1.0;
+      e = m < 1.0 ? a.kappa * m * b0 : a.kappa * b0;
     }
   }
   const double es = block_sum<EVAL_BLOCK>(e, lds);

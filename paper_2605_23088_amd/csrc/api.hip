@@ -164,7 +164,7 @@ struct yasps_ctx {
 
   // contacts touching affine bodies (third part, built on the host)
   enum { BC_IDX, BC_VPOS, BC_ROWS, BC_SPOS, BC_GPOS, BC_CPTR, BC_GPTR, BC_RP, BC_COL, BC_BDIAG, BC_STG, BC_GSTG,
-         BC_VALS, BC_D, BC_PBLK, BC_PGRD, BC_COUNT };
+         BC_VALS, BC_D, BC_PBLK, BC_PGRD, BC_EPS, BC_COUNT };
   GrowBuf bc_buf[BC_COUNT];
   int nbc = 0, nblk_b = 0, ngrd_b = 0;
   std::vector<Group> bgroups;
@@ -175,6 +175,7 @@ struct yasps_ctx {
   double *stg_b = nullptr, *gstg_b = nullptr, *vals_b = nullptr, *d_b = nullptr, *pos_blk = nullptr,
          *pos_grd = nullptr;
   float *stg_b32 = nullptr, *vals_b32 = nullptr;
+  double* bc_eps = nullptr;  // edge-edge mollifier thresholds (storage order) or null
   SpmvPart plan_b;
   GrowBuf plan_b_buf[PL_COUNT];
 
@@ -189,6 +190,7 @@ struct yasps_ctx {
   int nblk_d = 0, ngrd_d = 0;
   double *stg_d = nullptr, *gstg_d = nullptr, *vals_d = nullptr, *d_c = nullptr;
   float *stg_d32 = nullptr, *vals_d32 = nullptr;
+  double* c_eps = nullptr;  // edge-edge mollifier thresholds (storage order) or null
 
   // shared
   double *grad = nullptr, *minv = nullptr, *parts = nullptr, *scal = nullptr;
@@ -305,6 +307,7 @@ void clear_contacts(yasps_ctx* c) {
   c->c_idx = c->spos_c = c->gpos_c = c->cptr_d = c->gptr_d = c->ddiag = nullptr;
   c->stg_d = c->gstg_d = c->vals_d = c->d_c = nullptr;
   c->stg_d32 = c->vals_d32 = nullptr;
+  c->c_eps = nullptr;
   c->nblk_d = c->ngrd_d = 0;
   c->evaluated = false;
   c->assembled = false;
@@ -447,6 +450,7 @@ ContactArgs contact_args(const yasps_ctx* c, const double* x, const Group& g, in
   a.idx = c->c_idx;
   a.spos = c->spos_c;
   a.gpos = c->gpos_c;
+  a.eps = c->c_eps;
   a.kappa = c->P.kappa;
   a.dhat = c->P.dhat;
   a.barrier = c->prm.barrier;
@@ -502,6 +506,7 @@ BodyContactArgs body_contact_args(const yasps_ctx* c, const double* x, const Gro
   a.rows = c->bc_rows;
   a.spos = c->bc_spos;
   a.gpos = c->bc_gpos;
+  a.eps = c->bc_eps;
   a.kappa = c->P.kappa;
   a.dhat = c->P.dhat;
   a.barrier = c->prm.barrier;
@@ -834,6 +839,7 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   in.nc = nc;
   in.type = C->type;
   in.idx = C->idx;
+  in.eps = C->ee_eps;
   in.arena = c->di_arena;
   in.arena_bytes = c->di_arena_bytes;
   GrowBuf* bufs = c->di_buf;
@@ -859,6 +865,7 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   c->nblk_d = o.nent;
   c->ngrd_d = o.ngrad;
   c->c_idx = o.sidx;
+  c->c_eps = o.seps;
   c->spos_c = o.spos;
   c->gpos_c = o.gpos;
   c->cptr_d = o.cptr;
@@ -911,6 +918,13 @@ yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   std::vector<int32_t> sidx((size_t)4 * nc);
   for (int j = 0; j < nc; ++j)
     for (int a = 0; a < 4; ++a) sidx[(size_t)a * nc + j] = idx[(size_t)a * nc + order[j]];
+  std::vector<double> eps, seps;
+  if (C->ee_eps) {
+    eps.resize(nc);
+    seps.resize(nc);
+    if (nc) HIPCHK(c, hipMemcpy(eps.data(), C->ee_eps, (size_t)nc * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < nc; ++j) seps[j] = eps[order[j]];
+  }
   Staging st;
   build_staging(c->n, ridx.data(), nc, pat, order, false, false, st);
   std::vector<int32_t> ddiag(c->n, -1);
@@ -933,7 +947,12 @@ yasps_status set_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   c->cptr_d = up(DI_CPTR, st.cptr);
   c->gptr_d = up(DI_GPTR, st.gptr);
   c->ddiag = up(DI_DDIAG, ddiag);
-  if (!c->pd.rp || !c->pd.ci || !c->c_idx || !c->spos_c || !c->gpos_c || !c->cptr_d || !c->gptr_d || !c->ddiag)
+  c->c_eps = C->ee_eps ? static_cast<double*>(c->di_buf[DI_EPS].ensure(sizeof(double) * std::max(nc, 1))) : nullptr;
+  if (c->c_eps && nc &&
+      hipMemcpyAsync(c->c_eps, seps.data(), (size_t)nc * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    c->c_eps = nullptr;
+  if (!c->pd.rp || !c->pd.ci || !c->c_idx || !c->spos_c || !c->gpos_c || !c->cptr_d || !c->gptr_d || !c->ddiag ||
+      (C->ee_eps && !c->c_eps))
     return fail(c, YASPS_E_HIP, "upload of the contact index");
   HIPCHK(c, hipStreamSynchronize(c->stream));  // the host arrays go out of scope
   c->nc = nc;
@@ -951,6 +970,7 @@ void clear_body_contacts(yasps_ctx* c) {
   c->pb = Part{};
   c->plan_b = SpmvPart{};
   c->hpat_b = PartPattern{};
+  c->bc_eps = nullptr;
   c->nblk_b = c->ngrd_b = 0;
   c->evaluated = false;
   c->assembled = false;
@@ -1021,6 +1041,13 @@ yasps_status set_body_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   Staging st;
   build_staging(c->n, rows.data(), ns, pat, order, false, false, st, 8);
   std::vector<int32_t> sidx((size_t)4 * ns), svpos((size_t)4 * ns), srows((size_t)8 * ns);
+  std::vector<double> eps, seps;
+  if (C->ee_eps) {
+    eps.resize(ns);
+    seps.resize(ns);
+    if (ns) HIPCHK(c, hipMemcpy(eps.data(), C->ee_eps, (size_t)ns * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < ns; ++j) seps[j] = eps[order[j]];
+  }
   for (int j = 0; j < ns; ++j) {
     for (int a = 0; a < 4; ++a) {
       sidx[(size_t)a * ns + j] = idx[(size_t)a * ns + order[j]];
@@ -1057,8 +1084,14 @@ yasps_status set_body_contacts_host(yasps_ctx* c, const yasps_contacts* C) {
   c->d_b = static_cast<double*>(c->bc_buf[yasps_ctx::BC_D].ensure(8 * (size_t)std::max(ns, 1)));
   c->pos_blk = static_cast<double*>(c->bc_buf[yasps_ctx::BC_PBLK].ensure(8 * 90 * (size_t)std::max(ns, 1)));
   c->pos_grd = static_cast<double*>(c->bc_buf[yasps_ctx::BC_PGRD].ensure(8 * 12 * (size_t)std::max(ns, 1)));
+  c->bc_eps = C->ee_eps ? static_cast<double*>(c->bc_buf[yasps_ctx::BC_EPS].ensure(8 * (size_t)std::max(ns, 1)))
+                        : nullptr;
+  if (c->bc_eps && ns &&
+      hipMemcpyAsync(c->bc_eps, seps.data(), (size_t)ns * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    c->bc_eps = nullptr;
   if (!c->bc_idx || !c->bc_vpos || !c->bc_rows || !c->bc_spos || !c->bc_gpos || !c->bc_cptr || !c->bc_gptr ||
-      !c->pb.rp || !c->pb.ci || !c->bc_bdiag || !stg || !vals || !c->gstg_b || !c->d_b || !c->pos_blk || !c->pos_grd)
+      !c->pb.rp || !c->pb.ci || !c->bc_bdiag || !stg || !vals || !c->gstg_b || !c->d_b || !c->pos_blk || !c->pos_grd ||
+      (C->ee_eps && !c->bc_eps))
     return fail(c, YASPS_E_HIP, "upload of the body-contact index");
   c->stg_b = mixed ? nullptr : static_cast<double*>(stg);
   c->vals_b = mixed ? nullptr : static_cast<double*>(vals);

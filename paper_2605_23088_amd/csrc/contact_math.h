@@ -555,16 +555,30 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
   }
 }
 
+// Edge-edge mollifier of near-parallel edges (IPC, Li et al. 2020): with
+// c = |e1 x e2|^2 and a threshold eps (eps_x = 1e-3 |e1_rest|^2 |e2_rest|^2),
+// m(c) = (c / eps)(2 - c / eps) below eps and 1 above; the barrier of the
+// stencil is m(c) b(d).  m is C^1 at eps (m' = 2 (1 - c / eps) / eps vanishes
+// there).  eps <= 0 means no mollifier.  u = (w, e1, e2) of an EE stencil.
+YHD double ee_mollifier(const double (&u)[3][3], double eps) {
+  if (!(eps > 0.0)) return 1.0;
+  double n[3];
+  cross(u[1], u[2], n);
+  const double r = dot(n, n) / eps;
+  return r < 1.0 ? r * (2.0 - r) : 1.0;
+}
+
 // Energy, free-vertex gradient rows and free-vertex upper Hessian blocks of one
 // contact stencil with K free vertices (sinks as in emit_reduced).  Returns
 // false when an input is not finite.  d receives the squared distance;
-// e = kappa b(d) (0 when d >= dhat or d <= 0).  PT_FIXED_POINT: a
+// e = kappa b(d) (0 when d >= dhat or d <= 0), times the mollifier m(c) for
+// an edge-edge stencil with eps > 0 (ee_mollifier).  PT_FIXED_POINT: a
 // point-triangle stencil whose point is fixed and whose triangle is free
 // (fl = 1, 2, 3), projected through project_pt_fixed_point.  Its frame is
 // degenerate only with the triangle, and then d is not finite either.
 template <int TYPE, int K, bool EXACT, bool PT_FIXED_POINT = false, class GS, class BS>
 YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
-                         double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink) {
+                         double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink, double eps = 0.0) {
   constexpr int NU = Topo<TYPE>::NU;
   double u[NU][3];
   const bool ok = diff_vars<TYPE>(xv, u);
@@ -578,12 +592,54 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
   const double kb1 = kappa * b1, kb2 = kappa * b2;
   // u-space barrier gradient and Hessian (zero when inactive)
   double gu[3 * NU];
+  bool mollified = false;
+  if constexpr (TYPE == 1) {
+    if (active && eps > 0.0) {
+      // m(c) b(d): gradient m b' grad d + b grad m, Hessian
+      // m (b'' grad d grad d^T + b' hess d) + b' (grad d grad m^T + grad m grad d^T) + b hess m,
+      // grad m = m' grad c, hess m = m'' grad c grad c^T + m' hess c (c = N of the distance)
+      const double *e1 = u[1], *e2 = u[2];
+      double n[3], e2n[3], ne1[3];
+      cross(e1, e2, n);
+      const double N = dot(n, n);
+      if (N < eps) {
+        mollified = true;
+        cross(e2, n, e2n);
+        cross(n, e1, ne1);
+        double dN[9];
 #pragma unroll
-  for (int r = 0; r < 3 * NU; ++r) gu[r] = kb1 * D.g[r];
+        for (int i = 0; i < 3; ++i) {
+          dN[i] = 0.0;
+          dN[3 + i] = 2.0 * e2n[i];
+          dN[6 + i] = 2.0 * ne1[i];
+        }
+        const double r = N / eps, m = r * (2.0 - r), m1 = 2.0 * (1.0 - r) / eps, m2 = -2.0 / (eps * eps);
+        e = kappa * m * b0;
+        const double km = kappa * m, kb0 = kappa * b0;
 #pragma unroll
-  for (int r = 0; r < 3 * NU; ++r)
+        for (int q = 0; q < 9; ++q) gu[q] = fma(km * b1, D.g[q], kb0 * m1 * dN[q]);
 #pragma unroll
-    for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
+        for (int q = 0; q < 9; ++q)
+#pragma unroll
+          for (int c = q; c < 9; ++c) {
+            const int B1 = q / 3, B2 = c / 3, i = q % 3, l = c % 3;
+            const double hN = (B1 == 0 || B2 == 0) ? 0.0 : crossnorm_hess(e1, e2, n, B1 - 1, B2 - 1, i, l);
+            const double hb = fma(kb2 * D.g[q], D.g[c], kb1 * D.H(q, c));
+            const double cross_t = kb1 * m1 * (D.g[q] * dN[c] + dN[q] * D.g[c]);
+            const double hm = kb0 * (m2 * dN[q] * dN[c] + m1 * hN);
+            D.H(q, c) = m * hb + cross_t + hm;
+          }
+      }
+    }
+  }
+  if (!mollified) {
+#pragma unroll
+    for (int r = 0; r < 3 * NU; ++r) gu[r] = kb1 * D.g[r];
+#pragma unroll
+    for (int r = 0; r < 3 * NU; ++r)
+#pragma unroll
+      for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
+  }
   if constexpr (PT_FIXED_POINT && !EXACT) {
     static_assert(TYPE == 0 && K == 3, "point-triangle stencils with the triangle free");
     // the triangle's frame: t1 along e1, n along e1 x e2, t2 = n x t1

@@ -88,10 +88,11 @@ __global__ __launch_bounds__(DI_BLOCK) void classify_kernel(int nc, int n, int n
 __global__ void entries_kernel(int nc, int n, const int32_t* __restrict__ idx, const int32_t* __restrict__ order,
                                uint64_t pad, int32_t* __restrict__ sidx, uint64_t* __restrict__ bkey,
                                int32_t* __restrict__ bval, uint32_t* __restrict__ gkey, int32_t* __restrict__ gval,
-                               int* counts) {
+                               int* counts, const double* __restrict__ eps, double* __restrict__ seps) {
   const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (j >= nc) return;
   const int s = order[j];
+  if (eps) seps[j] = eps[s];
   int v[4];
   int used = 0;
 #pragma unroll
@@ -260,11 +261,12 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   int32_t* gval = tmp.get<int32_t>(nge);
   int32_t* gval_s = tmp.get<int32_t>(nge);
   int32_t* sidx = static_cast<int32_t*>(alloc(DI_SIDX, sizeof(int32_t) * std::max<long long>(nge, 1)));
+  double* seps = in.eps ? static_cast<double*>(alloc(DI_EPS, sizeof(double) * std::max(nc, 1))) : nullptr;
   DI_CHECK(tmp.err);
-  if (!sidx) return -1;
+  if (!sidx || (in.eps && !seps)) return -1;
   if (nc) {
     hipLaunchKernelGGL(entries_kernel, dim3(grid_of(nc)), dim3(DI_BLOCK), 0, s, nc, n, in.idx, order, bpad, sidx,
-                       bkey, bval, gkey, gval, counts);
+                       bkey, bval, gkey, gval, counts, in.eps, seps);
     DI_CHECK(sort_pairs(tmp, bkey, bkey_s, bval, bval_s, nbe, 32 + nbits, s));
     DI_CHECK(sort_pairs(tmp, gkey, gkey_s, gval, gval_s, nge, nbits, s));
   }
@@ -297,6 +299,7 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   out.gptr = ialloc(DI_GPTR, nr + 1);
   out.ddiag = ialloc(DI_DDIAG, nr);
   out.sidx = sidx;
+  out.seps = seps;
   if (!out.rp || !out.col || !out.cptr || !out.slot || !out.spos || !out.gpos || !out.gptr || !out.ddiag) return -1;
   int32_t* rowcnt = tmp.get<int32_t>(nr);
   DI_CHECK(tmp.err);

@@ -145,6 +145,7 @@ struct BodyContactArgs {
   const int32_t* rows;       // [8][ns] row lists, -1 padded
   const int32_t* spos;       // [36][ns] staged block positions
   const int32_t* gpos;       // [8][ns] staged gradient positions
+  const double* eps;         // [ns] edge-edge mollifier thresholds in storage order, or null
   double kappa, dhat;
   int barrier;
   double* pos_blk;           // [ns][10][9] movable-pair blocks (pair order over 4)
@@ -174,6 +175,7 @@ struct ContactArgs {
   const int32_t* idx;    // [4][nc]
   const int32_t* spos;   // [10][nc] canonical local-pair order
   const int32_t* gpos;   // [4][nc]
+  const double* eps;     // [nc] edge-edge mollifier thresholds in storage order, or null (none)
   double kappa, dhat;
   int barrier;           // 0 squared-log, 1 classic
   double* blk;
@@ -198,6 +200,7 @@ struct DynIndexIn {
   int nrows;               // rows of the matrix (>= n: affine-body rows follow the free vertices)
   const int32_t* type;     // [nc]
   const int32_t* idx;      // [4][nc], API order
+  const double* eps;       // [nc] edge-edge mollifier thresholds, API order, or null
   void* arena;             // device scratch for the temporaries (may be null)
   size_t arena_bytes;
 };
@@ -213,8 +216,9 @@ struct DynIndexOut {
   // vertex [n]
   int32_t *sidx = nullptr, *rp = nullptr, *col = nullptr, *slot = nullptr, *spos = nullptr, *gpos = nullptr,
           *cptr = nullptr, *gptr = nullptr, *ddiag = nullptr;
+  double* seps = nullptr;  // [nc] mollifier thresholds in storage order (null without in.eps)
 };
-enum { DI_SIDX, DI_RP, DI_COL, DI_CPTR, DI_SLOT, DI_SPOS, DI_GPOS, DI_GPTR, DI_DDIAG, DI_COUNT };
+enum { DI_SIDX, DI_RP, DI_COL, DI_CPTR, DI_SLOT, DI_SPOS, DI_GPOS, DI_GPTR, DI_DDIAG, DI_EPS, DI_COUNT };
 // 0 built, 1 invalid contacts (err_* set), -1 HIP failure.  Synchronises s.
 int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::function<void*(int, size_t)>& alloc,
                         hipStream_t s);

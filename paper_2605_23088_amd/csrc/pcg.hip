@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 #include "blockreduce.h"
@@ -431,8 +432,17 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
 }
 
 int round_xcd(int g) { return (g + NXCD - 1) / NXCD * NXCD; }
+// SpMV workgroups at most (YASPS_SPMV_WG: a tuning override, NXCD .. MAX_WG_B)
+int wg_cap_b() {
+  static const int cap = [] {
+    const char* e = std::getenv("YASPS_SPMV_WG");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= NXCD && v <= MAX_WG_B) ? v / NXCD * NXCD : MAX_WG_B;
+  }();
+  return cap;
+}
 int grid_b(const PcgMatrix& A) {
-  return round_xcd(std::max(1, std::min(A.part[0].nchunk + A.part[1].nchunk + A.part[2].nchunk, MAX_WG_B)));
+  return round_xcd(std::max(1, std::min(A.part[0].nchunk + A.part[1].nchunk + A.part[2].nchunk, wg_cap_b())));
 }
 int grid_c(int n) { return round_xcd(std::max(1, std::min((n + UPD_VERTS - 1) / UPD_VERTS, MAX_WG_C))); }
 // LDS of the chunk kernel: the larger chunk's products

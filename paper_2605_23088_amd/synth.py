@@ -180,7 +180,7 @@ def _pack(n_free, x0, x_fixed, mass, x_tilde, tets, dm_inv, vol, ctype, cidx, **
 # Contacts against a fixed collider under the bottom face
 # --------------------------------------------------------------------------
 
-def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, tri_ok=None):
+def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, tri_ok=None, ee_angle=None):
     """PT and EE stencils between the bottom face (z = 0) of a grid block and a
     private fixed feature per stencil placed below it.
 
@@ -188,7 +188,10 @@ def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, t
         over the bottom triangles, is set) and a fixed point at
         centroid - sqrt(d) z, d ~ U(dlo, dhi) (d is a squared distance).
     EE: a uniformly chosen bottom edge and a fixed horizontal edge of length a,
-        perpendicular to it, through midpoint - sqrt(d) z.
+        perpendicular to it, through midpoint - sqrt(d) z; with ee_angle =
+        (lo, hi) the fixed edge instead makes an angle +-U(lo, hi) (radians)
+        with the bottom edge (near-parallel pairs for the edge-edge mollifier;
+        the lines still cross above each other's midpoints).
     Both are interior-type by construction.  Returns (ctype, cidx, x_fixed)."""
     tris = face_triangles(nx, ny, 0)
     edges = face_edges(nx, ny, 0)
@@ -214,6 +217,10 @@ def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, t
         dirn = p1 - p0
         perp = np.stack([-dirn[:, 1], dirn[:, 0], np.zeros(n_ee)], 1)
         perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+        if ee_angle is not None:
+            th = rng.uniform(ee_angle[0], ee_angle[1], size=n_ee) * rng.choice([-1.0, 1.0], size=n_ee)
+            u = dirn / np.linalg.norm(dirn, axis=1, keepdims=True)
+            perp = np.cos(th)[:, None] * u + np.sin(th)[:, None] * perp
         q0 = mid - 0.5 * a * perp
         q1 = mid + 0.5 * a * perp
         base = n_free + n_pt
@@ -228,13 +235,16 @@ def _collider_contacts(rng, X, nx, ny, n_pt, n_ee, n_free, dlo=1e-4, dhi=1e-3, t
 
 
 def block_problem(nx, ny, nz, a, n_pt, n_ee, seed, E=1e5, nu=0.4, rho=1000.0, h=1e-2,
-                  kappa=1e4, dhat=1e-3, random_F=True, name="block", dlo=1e-4, dhi=1e-3):
+                  kappa=1e4, dhat=1e-3, random_F=True, name="block", dlo=1e-4, dhi=1e-3, ee_angle=None):
     """A Kuhn block [0, nx a] x [0, ny a] x [0, nz a] at its exact grid positions,
     with seeded per-tet rest shapes (so x0 carries random deformation gradients
     with singular values in [0.7, 1.4]) and n_pt + n_ee contact stencils against
     a fixed collider under the bottom face, squared distances U(dlo, dhi) (a
     range reaching past dhat gives inactive stencils).  All block vertices are
-    free."""
+    free.  With ee_angle the collider edges are near-parallel to their bottom
+    edges (see _collider_contacts) and the problem carries `ee_eps`, IPC's
+    mollifier thresholds 1e-3 |e_a|^2 |e_b|^2 of every EE stencil from the
+    edge lengths at x0 (0 for the other stencils)."""
     r_pos, r_con, _, _ = _streams(seed)
     X = grid_vertices(nx, ny, nz, a)
     tets = kuhn_tets(nx, ny, nz)
@@ -245,12 +255,21 @@ def block_problem(nx, ny, nz, a, n_pt, n_ee, seed, E=1e5, nu=0.4, rho=1000.0, h=
         dm_inv, vol = np.linalg.inv(Ds), np.abs(np.linalg.det(Ds)) / 6.0
     n = X.shape[0]
     mass = _lumped_mass(n, tets, vol, rho)
-    ctype, cidx, x_fixed = _collider_contacts(r_con, X, nx, ny, n_pt, n_ee, n, dlo, dhi)
+    ctype, cidx, x_fixed = _collider_contacts(r_con, X, nx, ny, n_pt, n_ee, n, dlo, dhi, ee_angle=ee_angle)
     mu, lam = lame(E, nu)
     x_tilde = X + h * h * GRAVITY
-    return _pack(n, X, x_fixed, mass, x_tilde, tets, dm_inv, vol, ctype, cidx,
-                 mu=mu, lam=lam, h=h, kappa=kappa, dhat=dhat, rho=rho, name=name,
-                 grid=(nx, ny, nz), spacing=a)
+    p = _pack(n, X, x_fixed, mass, x_tilde, tets, dm_inv, vol, ctype, cidx,
+              mu=mu, lam=lam, h=h, kappa=kappa, dhat=dhat, rho=rho, name=name,
+              grid=(nx, ny, nz), spacing=a)
+    if ee_angle is not None:
+        xa = np.concatenate([X, x_fixed])
+        ee = ctype == EE
+        ea = xa[cidx[ee, 1]] - xa[cidx[ee, 0]]
+        eb = xa[cidx[ee, 3]] - xa[cidx[ee, 2]]
+        eps = np.zeros(len(ctype))
+        eps[ee] = 1e-3 * (ea * ea).sum(1) * (eb * eb).sum(1)
+        p["ee_eps"] = eps
+    return p
 
 
 # --------------------------------------------------------------------------
@@ -860,4 +879,8 @@ def affine_block(seed=41, nx=5, ny=4, nz=3, n_pt=120, n_ee=120, n_pp=40, n_pt1=6
              body_k=np.full(nb, k_orth), abd_body=body_of, abd_rest=rest,
              bctype=np.array(bct, np.int32), bcidx=bci,
              X0=np.concatenate([X, q0.reshape(-1, 3)]), name=f"affine{nx}x{ny}x{nz}")
+    if p.get("ee_eps") is not None:  # near-parallel collider edges (ee_angle): thresholds follow their stencils
+        eps = p["ee_eps"]
+        p["ee_eps"] = eps[keep]
+        p["bee_eps"] = np.concatenate([eps[to_body], np.zeros(len(bct) - len(to_body))])
     return p

@@ -49,7 +49,7 @@ class Problem(C.Structure):
 
 
 class Contacts(C.Structure):
-    _fields_ = [("n_contacts", C.c_int32), ("type", C.c_void_p), ("idx", C.c_void_p)]
+    _fields_ = [("n_contacts", C.c_int32), ("type", C.c_void_p), ("idx", C.c_void_p), ("ee_eps", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -240,9 +240,9 @@ class Yasps:
         self.ctx = ctx
         self.nc = 0
         if contacts and len(prob.get("ctype", [])):
-            self.set_contacts(prob["ctype"], prob["cidx"])
+            self.set_contacts(prob["ctype"], prob["cidx"], prob.get("ee_eps"))
         if contacts and len(prob.get("bctype", [])):
-            self.set_body_contacts(prob["bctype"], prob["bcidx"])
+            self.set_body_contacts(prob["bctype"], prob["bcidx"], prob.get("bee_eps"))
 
     def _check(self, rc, allow=()):
         if rc != OK and rc not in allow:
@@ -261,19 +261,25 @@ class Yasps:
             pass
 
     # ------------------------------------------------------------ calls
-    def set_contacts(self, ctype, cidx):
-        """Host arrays: types (n_c) and vertex ids (n_c, 4)."""
+    def set_contacts(self, ctype, cidx, ee_eps=None):
+        """Host arrays: types (n_c), vertex ids (n_c, 4) and optionally the
+        edge-edge mollifier thresholds (n_c)."""
         ctype = np.asarray(ctype, np.int32)
         cidx = np.asarray(cidx, np.int32).reshape(-1, 4)
         t = torch.as_tensor(ctype, device=self.dev).contiguous()
         i = torch.as_tensor(np.ascontiguousarray(cidx.T), device=self.dev).contiguous()
-        self.set_contacts_device(t, i)
+        e = None if ee_eps is None else torch.as_tensor(np.asarray(ee_eps, np.float64), device=self.dev)
+        self.set_contacts_device(t, i, e)
 
-    def set_contacts_device(self, t, i):
-        """Device int32 tensors in the library's layout: types [n_c], ids [4][n_c]."""
+    def set_contacts_device(self, t, i, eps=None):
+        """Device tensors in the library's layout: int32 types [n_c], int32 ids
+        [4][n_c], float64 mollifier thresholds [n_c] or None."""
         assert t.dtype == torch.int32 and i.dtype == torch.int32 and i.shape == (4, t.shape[0])
         t, i = t.contiguous(), i.contiguous()  # kept alive through the call
-        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i))
+        if eps is not None:
+            assert eps.dtype == torch.float64 and eps.shape == t.shape
+            eps = eps.contiguous()
+        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i), _ptr(eps))
         try:
             self._check(lib().yasps_set_contacts(self.ctx, C.byref(Cs)))
         except YaspsError:
@@ -281,13 +287,15 @@ class Yasps:
             raise
         self.nc = int(t.shape[0])
 
-    def set_body_contacts(self, ctype, cidx):
-        """Host arrays: types (n_s) and vertex ids (n_s, 4) of the stencils touching bodies."""
+    def set_body_contacts(self, ctype, cidx, ee_eps=None):
+        """Host arrays: types (n_s), vertex ids (n_s, 4) and optionally the
+        edge-edge mollifier thresholds (n_s) of the stencils touching bodies."""
         ctype = np.asarray(ctype, np.int32)
         cidx = np.asarray(cidx, np.int32).reshape(-1, 4)
         t = torch.as_tensor(ctype, device=self.dev).contiguous()
         i = torch.as_tensor(np.ascontiguousarray(cidx.T), device=self.dev).contiguous()
-        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i))
+        e = None if ee_eps is None else torch.as_tensor(np.asarray(ee_eps, np.float64), device=self.dev).contiguous()
+        Cs = Contacts(int(t.shape[0]), _ptr(t), _ptr(i), _ptr(e))
         try:
             self._check(lib().yasps_set_body_contacts(self.ctx, C.byref(Cs)))
         except YaspsError:

@@ -9,7 +9,7 @@ using namespace yasps::cmath;
 namespace {
 
 template <int T, int K, bool EX, bool PTFP = false>
-int run(const double* x12, const int* fl4, double kappa, double dhat, int classic, double* e, double* d,
+int run(const double* x12, const int* fl4, double kappa, double dhat, int classic, double eps, double* e, double* d,
         double* g12, double* H144) {
   double xv[4][3];
   int fl[4];
@@ -30,28 +30,28 @@ int run(const double* x12, const int* fl4, double kappa, double dhat, int classi
       }
   };
   double side;
-  return contact_stencil<T, K, EX, PTFP>(xv, fl, kappa, dhat, classic, *e, *d, side, gs, bs) ? 0 : 1;
+  return contact_stencil<T, K, EX, PTFP>(xv, fl, kappa, dhat, classic, *e, *d, side, gs, bs, eps) ? 0 : 1;
 }
 
 template <bool EX>
 int dispatch(int type, int nfree, const double* x12, const int* fl4, double kappa, double dhat, int classic,
-             double* e, double* d, double* g, double* H) {
+             double eps, double* e, double* d, double* g, double* H) {
   switch (type * 8 + nfree) {
-    case 0 * 8 + 1: return run<0, 1, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 0 * 8 + 2: return run<0, 2, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
+    case 0 * 8 + 1: return run<0, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 0 * 8 + 2: return run<0, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     case 0 * 8 + 3:  // the library runs a triangle-free stencil through its own kernel
-      if (fl4[0] == 1 && fl4[1] == 2 && fl4[2] == 3) return run<0, 3, EX, true>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-      return run<0, 3, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 0 * 8 + 4: return run<0, 4, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 1 * 8 + 1: return run<1, 1, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 1 * 8 + 2: return run<1, 2, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 1 * 8 + 3: return run<1, 3, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 1 * 8 + 4: return run<1, 4, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 2 * 8 + 1: return run<2, 1, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 2 * 8 + 2: return run<2, 2, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 2 * 8 + 3: return run<2, 3, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 3 * 8 + 1: return run<3, 1, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
-    case 3 * 8 + 2: return run<3, 2, EX>(x12, fl4, kappa, dhat, classic, e, d, g, H);
+      if (fl4[0] == 1 && fl4[1] == 2 && fl4[2] == 3) return run<0, 3, EX, true>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+      return run<0, 3, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 0 * 8 + 4: return run<0, 4, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 1 * 8 + 1: return run<1, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 1 * 8 + 2: return run<1, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 1 * 8 + 3: return run<1, 3, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 1 * 8 + 4: return run<1, 4, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 2 * 8 + 1: return run<2, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 2 * 8 + 2: return run<2, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 2 * 8 + 3: return run<2, 3, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 3 * 8 + 1: return run<3, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 3 * 8 + 2: return run<3, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     default: return 2;
   }
 }
@@ -59,7 +59,7 @@ int dispatch(int type, int nfree, const double* x12, const int* fl4, double kapp
 }  // namespace
 
 extern "C" int contact_host(int type, int nfree, int exact, const double* x12, const int* fl4, double kappa,
-                            double dhat, int classic, double* e, double* d, double* g12, double* H144) {
-  return exact ? dispatch<true>(type, nfree, x12, fl4, kappa, dhat, classic, e, d, g12, H144)
-               : dispatch<false>(type, nfree, x12, fl4, kappa, dhat, classic, e, d, g12, H144);
+                            double dhat, int classic, double eps, double* e, double* d, double* g12, double* H144) {
+  return exact ? dispatch<true>(type, nfree, x12, fl4, kappa, dhat, classic, eps, e, d, g12, H144)
+               : dispatch<false>(type, nfree, x12, fl4, kappa, dhat, classic, eps, e, d, g12, H144);
 }

@@ -21,7 +21,7 @@ NV = (4, 4, 3, 2)
 def harness():
     L = native_build.load("contact_host")
     L.contact_host.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
-                               C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                               C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.contact_host.restype = C.c_int
     return L
 
@@ -41,14 +41,14 @@ def stencils(t, n, seed):
     return x
 
 
-def run_host(L, t, K, exact, x, fl, classic=0):
+def run_host(L, t, K, exact, x, fl, classic=0, eps=0.0):
     e, d = C.c_double(), C.c_double()
     g = np.zeros(12)
     H = np.zeros(144)
     xs = np.ascontiguousarray(x, np.float64)
     f = np.ascontiguousarray(fl, np.int32)
-    rc = L.contact_host(t, K, int(exact), xs.ctypes.data, f.ctypes.data, KAPPA, DHAT, classic, C.byref(e), C.byref(d),
-                        g.ctypes.data, H.ctypes.data)
+    rc = L.contact_host(t, K, int(exact), xs.ctypes.data, f.ctypes.data, KAPPA, DHAT, classic, eps, C.byref(e),
+                        C.byref(d), g.ctypes.data, H.ctypes.data)
     assert rc == 0
     return e.value, d.value, g.reshape(4, 3), H.reshape(12, 12)
 
@@ -103,3 +103,41 @@ def test_contact_math_inactive_beyond_dhat(harness, t, classic):
                     d_o = float(en.DIST[t](torch.tensor(xv)))
                     assert d >= DHAT and abs(d - d_o) <= 1e-12 * d_o
                     assert e == 0.0 and not g.any() and not H.any(), (t, K, freeset, exact, d)
+
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("classic", [0, 1])
+def test_ee_mollifier_matches_oracle(harness, exact, classic):
+    """Near-parallel edge-edge stencils under the mollifier (eps_x above c for
+    most of them, below for some): every free set against the oracle's m(c) b(d)."""
+    n = 8
+    rng = np.random.default_rng(300 + classic)
+    la, lb = 0.05, 0.05
+    x = np.zeros((n, 4, 3))
+    th = rng.uniform(0.004, 0.05, size=n)
+    for s in range(n):
+        x[s, 0] = [-la / 2, 0.0, 0.0]
+        x[s, 1] = [la / 2, 0.0, 0.0]
+        u = np.array([np.cos(th[s]), np.sin(th[s]), 0.0])
+        c0 = np.array([0.0, 0.0, -0.02])
+        x[s, 2] = c0 - lb / 2 * u
+        x[s, 3] = c0 + lb / 2 * u
+    x += 1e-4 * rng.standard_normal(x.shape)
+    eps = np.full(n, 1e-3 * la ** 2 * lb ** 2)
+    c = np.array([float(en.ee_cross_norm(torch.tensor(x[s]))) for s in range(n)])
+    assert (c < eps).sum() >= 3 and (c >= eps).sum() >= 1
+    for K in range(1, 5):
+        for freeset in itertools.combinations(range(4), K):
+            fl = list(freeset) + [0] * (4 - K)
+            free = torch.zeros(n, 4, dtype=torch.bool)
+            free[:, list(freeset)] = True
+            Eo, go, Ho, do = local.contact_local(torch.tensor(x), torch.full((n,), 1), free, KAPPA, DHAT,
+                                                 local.EXACT if exact else local.PROJECTED,
+                                                 classic=bool(classic), eps=eps)
+            for s in range(n):
+                e, d, g, H = run_host(harness, 1, K, exact, x[s], fl, classic, eps[s])
+                sc = np.abs(Ho[s].numpy()).max() + 1e-300
+                assert abs(e - float(Eo[s])) <= 1e-10 * abs(float(Eo[s])) + 1e-300, (K, freeset, s)
+                assert np.abs(g - go[s].numpy()).max() <= 1e-10 * np.abs(go[s].numpy()).max()
+                err = np.abs(H - Ho[s].numpy()).max()
+                assert err <= 1e-10 * sc, (K, freeset, exact, s, err, sc)

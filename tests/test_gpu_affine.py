@@ -18,7 +18,7 @@ from paper_2605_23088_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
-CASES = ["affine", "affine_mid", "affine_classic"]
+CASES = ["affine", "affine_mid", "affine_classic", "affine_mollified"]
 _cache = {}
 
 
@@ -30,6 +30,8 @@ def case(name):
                                   n_ee2=150, n_fixed_pt=100)
     if name == "affine_classic":  # about a fifth of the stencils inactive
         return synth.affine_block(seed=44, dhi=1.25e-3)
+    if name == "affine_mollified":  # near-parallel free-body edge pairs under the EE mollifier
+        return synth.affine_block(seed=45, ee_angle=(0.005, 0.06))
     raise KeyError(name)
 
 

@@ -42,6 +42,8 @@ def case(name):
         return shaken(synth.c5_static(seed=13, nx=6, ny=5, nz=4, a=0.05, n_pt=200, kappa=1e4, pin="corners"), 0.05)
     if name == "xspace_block":
         return shaken(synth.small_block(seed=15, nx=5, ny=4, nz=3, n_pt=150, n_ee=150), 0.2)
+    if name == "mollified":  # near-parallel collider edges: about half the EE stencils mollified
+        return synth.small_block(seed=16, nx=5, ny=4, nz=3, n_pt=100, n_ee=200, ee_angle=(0.005, 0.06))
     raise KeyError(name)
 
 
@@ -58,7 +60,7 @@ def shaken(p, a, frac=0.2, seed=5):
     return q
 
 
-CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static"]
+CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static", "mollified"]
 _cache = {}
 
 
@@ -84,6 +86,27 @@ def test_xspace_cases_cover_both_reductions():
     of = oasm.Oracle(p)
     hx, hf = ox.eval(p["x0"])["H_t"], of.eval(p["x0"])["H_t"]
     assert np.abs(hx - hf).max() > 1e-6 * np.abs(hf).max()
+
+
+def test_mollified_case_has_both_kinds():
+    p = case("mollified")
+    m = oasm.Oracle(p).mollifiers(p["x0"]).numpy()
+    ee = p["ctype"] == 1
+    assert 0.3 <= float((m[ee] < 1.0).mean()) <= 0.7 and (m[~ee] == 1.0).all()
+
+
+def test_mollifier_host_index_build():
+    """The host index build carries the thresholds into storage order as the
+    device build does: identical evaluation and assembly, bit for bit."""
+    from paper_2605_23088_amd.yasps import INDEX_HOST, Yasps
+    p, o, g = setup("mollified")
+    gh = Yasps(p, index_build=INDEX_HOST)
+    ia, ib = g.eval(xdev(p)), gh.eval(xdev(p))
+    assert ia["energy"] == ib["energy"] and ia["e_contact"] == ib["e_contact"]
+    a, b = g.assemble(), gh.assemble()
+    for k in ("values_d", "grad"):
+        assert torch.equal(a[k], b[k]), k
+    gh.close()
 
 
 def test_classic_case_has_inactive_stencils():
