@@ -59,7 +59,7 @@ def algorithmic(prob, g, view, projected=True, mixed=False):
     n = g.n
     nt = g.nt
     ct = prob["ctype"]
-    nnzb = view.nnzb_static + view.nnzb_dynamic
+    nnzb = view.nnzb_static + view.nnzb_dynamic + view.nnzb_body
     ci = np.asarray(prob["cidx"])
     pt_fp = (ct == 0) & (ci[:, 0] >= n) & (ci[:, 1:] < n).all(axis=1) if len(ct) else np.zeros(0, bool)
     c_flops = (sum(CONTACT_FLOPS[int(t)] * int(((ct == t) & ~pt_fp).sum()) for t in range(4)) +
