@@ -342,6 +342,88 @@ yasps_status yasps_theta_adjoint(yasps_ctx* ctx, const double* x, const double* 
  * Errors: YASPS_E_ARG (before any assembly, frac < 0), YASPS_E_HIP. */
 yasps_status yasps_lm_shift(yasps_ctx* ctx, double frac, double* out);
 
+/* ---- Time stepping with contact (IPC's frame loop; the paper takes its
+ * collision detection and CCD from an external module, section "Limitations")
+ * ---- */
+
+/* Collision surface: the primitives whose pairs can touch.  Vertex ids as in
+ * yasps_contacts (free or fixed).  Device arrays, copied. */
+typedef struct {
+  int32_t n_points;
+  const int32_t* points;        /* [n_points] vertex ids */
+  int32_t n_edges;
+  const int32_t* edges;         /* [2][n_edges] */
+  int32_t n_tris;
+  const int32_t* tris;          /* [3][n_tris] */
+  const double* edge_rest_len2; /* [n_edges] squared rest lengths, or NULL: the edge-edge stencils found
+                                   get the mollifier threshold 1e-3 |a|^2 |b|^2 (none when NULL) */
+  double cell;                  /* cell size of the search grid (> 0; about the longest edge) */
+} yasps_surface;
+
+typedef struct {
+  double tol;           /* stop when max_v |p_v| / h < tol (m/s; the paper's examples use 1e-2) */
+  int32_t max_newton;   /* Newton iterations at most (default 50) */
+  double rtol;          /* PCG relative tolerance (default 1e-8) */
+  int32_t max_iter;     /* PCG iteration cap (default 20000) */
+  double armijo;        /* sufficient-decrease constant (default 1e-4) */
+  int32_t max_halvings; /* line-search halvings (default 40) */
+  double ccd_s;         /* additive CCD: stop once the distance falls below ccd_s times its start (0.1) */
+} yasps_frame_params;
+
+typedef struct {
+  int32_t newton_iters;   /* steps taken */
+  int32_t cg_iters;       /* PCG iterations of all solves */
+  int32_t ls_trials;      /* line-search energy evaluations */
+  int32_t n_contacts_max; /* most stencils found by one proximity search */
+  double e_begin, e_end;  /* incremental potential at the first and the last iterate */
+  double alpha_min;       /* smallest accepted step */
+  int32_t converged;      /* 1 if the stop rule was met */
+  float ms_detect, ms_newton, ms_ccd, ms_linesearch; /* device time per phase (HIP events) */
+} yasps_frame_info;
+
+/* Sets the collision surface (replaces the previous one).  Errors:
+ * YASPS_E_ARG (ids out of range, a degenerate edge or triangle, cell <= 0),
+ * YASPS_E_HIP. */
+yasps_status yasps_set_surface(yasps_ctx* ctx, const yasps_surface* S);
+
+/* Proximity search at positions x (n_rows, 3): every point-triangle and
+ * edge-edge pair of the surface (no shared vertex, at least one free vertex)
+ * whose squared distance is below dhat becomes one contact stencil, typed by
+ * where its closest points lie (point-triangle: face / edge / vertex -> PT /
+ * PE / PP; edge-edge: both interiors / one endpoint / two endpoints -> EE / PE
+ * / PP; Ericson, Real-Time Collision Detection, 5.1.5 and 5.1.9).  Pairs are
+ * not merged, so the barrier sum is IPC's sum over primitive pairs.  The
+ * stencils replace the contact set (as yasps_set_contacts with the device
+ * index build); order: point-triangle pairs by (point, triangle), then
+ * edge-edge pairs by (edge, edge).  *n_contacts (may be NULL) receives their
+ * number.  Errors: YASPS_E_ARG (no surface), YASPS_E_HIP. */
+yasps_status yasps_detect(yasps_ctx* ctx, const double* x, int32_t* n_contacts);
+
+/* Copies the stencils of the last yasps_detect to HOST arrays (any may be
+ * NULL): type [n], idx [4][n], ee_eps [n] (0 for non-EE stencils).
+ * Errors: YASPS_E_HIP. */
+yasps_status yasps_get_detected(yasps_ctx* ctx, int32_t* type, int32_t* idx, double* ee_eps);
+
+/* Largest conservative step along x + t p, t <= t_max: the minimum over the
+ * point-triangle and edge-edge pairs whose swept boxes (inflated by
+ * sqrt(dhat) / 2) overlap of additive CCD (Li, Kaufman, Jiang 2021), which
+ * stops a pair once its distance falls below s times its start value.
+ * x, p: (n_rows, 3) device arrays.  Errors: YASPS_E_ARG, YASPS_E_HIP. */
+yasps_status yasps_ccd(yasps_ctx* ctx, const double* x, const double* p, double t_max, double s, double* t_out);
+
+/* One implicit-Euler time step with contact (IPC): x_tilde = x + h v + h^2 g
+ * (the problem's h and gravity; the problem's x_tilde is not used), then
+ * Newton iterations, each: proximity search at x (yasps_detect), projected
+ * Newton direction p by PCG, stop when max_v |p_v| / h < tol, step bound by
+ * CCD, Armijo backtracking on E with the contacts found at each trial; at the
+ * end v = (x - x_start) / h.  x and v (n_rows, 3) device arrays, updated in
+ * place.  `prm` may be NULL for defaults.  Needs the dynamic form, a surface,
+ * and no affine bodies.  Errors: YASPS_E_ARG, YASPS_E_UNIMPL (bodies),
+ * YASPS_E_NOCONV (max_newton reached; x, v hold the last iterate),
+ * YASPS_E_LINESEARCH, YASPS_E_BREAKDOWN, YASPS_E_HIP. */
+yasps_status yasps_frame(yasps_ctx* ctx, double* x, double* v, const yasps_frame_params* prm,
+                         yasps_frame_info* info);
+
 /* Kernel classes timed by the opt-in profiler (yasps_profile_*). */
 #define YASPS_K_INERTIA 0       /* inertia / gravity term per vertex */
 #define YASPS_K_SNH 1           /* Neo-Hookean tet evaluation (energy, gradient, projected Hessian) */

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("YASPS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "elastic.hip", "contact.hip", "cloth.hip", "assembly.hip", "pcg.hip", "dynindex.hip",
-           "spmvplan.hip", "affine.hip", "pattern.cpp"]
+           "spmvplan.hip", "affine.hip", "collision.hip", "pattern.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

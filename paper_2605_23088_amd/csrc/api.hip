@@ -179,6 +179,14 @@ struct yasps_ctx {
   SpmvPart plan_b;
   GrowBuf plan_b_buf[PL_COUNT];
 
+  // collision surface of the time stepping (proximity search, CCD)
+  CdSurface surf{};
+  bool has_surface = false;
+  std::vector<void*> surf_allocs;
+  GrowBuf cd_buf[CD_COUNT];
+  CdOutput detected;             // the last proximity search's stencils (device, in cd_buf)
+  GrowBuf xt_frame, xs_frame;    // a frame's inertial target and start positions
+
   // a second stream for the contact kernels, which run beside the elastic ones
   // during an evaluation (fork / join through the two events)
   hipStream_t side = nullptr;
@@ -570,6 +578,9 @@ void yasps_destroy(yasps_ctx* ctx) {
   for (GrowBuf* set : {ctx->plan_s_buf, ctx->plan_d_buf, ctx->plan_b_buf})
     for (int k = 0; k < PL_COUNT; ++k) set[k].release();
   for (GrowBuf& b : ctx->di_buf) b.release();
+  for (GrowBuf& b : ctx->cd_buf) b.release();
+  free_list(ctx->surf_allocs);
+  for (GrowBuf* b : {&ctx->xt_frame, &ctx->xs_frame}) b->release();
   for (GrowBuf* b : {&ctx->stg_d_buf, &ctx->gstg_d_buf, &ctx->vals_d_buf, &ctx->d_c_buf, &ctx->pcg_work}) b->release();
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -1577,6 +1588,281 @@ yasps_status yasps_theta_adjoint(yasps_ctx* c, const double* x, const double* la
   launch_snh_theta_adjoint(snh_args(c, x), lambda, theta, grad_theta, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return YASPS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+CdAlloc cd_alloc(yasps_ctx* c) {
+  GrowBuf* bufs = c->cd_buf;
+  return [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
+}
+
+CdPositions cd_positions(const yasps_ctx* c, const double* x, const double* p = nullptr, double t = 0.0) {
+  CdPositions X{};
+  X.nv = c->nv;
+  X.x = x;
+  X.xf = c->P.x_fixed;
+  X.p = p;
+  X.t = t;
+  return X;
+}
+
+// Proximity search at x; the stencils found become the contact set.
+yasps_status detect(yasps_ctx* c, const double* x, int32_t* n_out) {
+  size_t need = 0;
+  const int r = cd_detect(c->surf, cd_positions(c, x), c->P.dhat, cd_alloc(c), c->di_arena, c->di_arena_bytes, &need,
+                          c->stream, c->detected);
+  grow_arena(c, need);
+  if (r != 0) {
+    c->detected = CdOutput{};
+    return r == -2 ? fail(c, YASPS_E_ARG, "proximity search: a box over too many grid cells (a non-finite "
+                                          "position, or the cell size far below the primitives)")
+                   : fail(c, YASPS_E_HIP, "proximity search");
+  }
+  yasps_contacts C{c->detected.n, c->detected.type, c->detected.idx, c->surf.len2 ? c->detected.eps : nullptr};
+  clear_contacts(c);
+  yasps_status s = set_contacts_device(c, &C);
+  if (s) {
+    clear_contacts(c);
+    return s;
+  }
+  if (n_out) *n_out = c->detected.n;
+  return YASPS_OK;
+}
+
+yasps_status ccd(yasps_ctx* c, const double* x, const double* p, double t_max, double s_ccd, double* t_out) {
+  size_t need = 0;
+  const int r = cd_ccd(c->surf, cd_positions(c, x, p, t_max), c->P.dhat, t_max, s_ccd, cd_alloc(c), c->di_arena,
+                       c->di_arena_bytes, &need, c->stream, t_out);
+  grow_arena(c, need);
+  if (r == -2) return fail(c, YASPS_E_ARG, "CCD: a swept box over too many grid cells (a non-finite position or "
+                                           "motion, or the cell size far below the motion)");
+  if (r != 0) return fail(c, YASPS_E_HIP, "continuous collision detection");
+  return YASPS_OK;
+}
+
+// E(x) with the contacts found at x: inertia + elastic terms, plus the
+// barrier energy of the proximity search at x.
+yasps_status frame_energy(yasps_ctx* c, const double* x, double* E) {
+  const PartsLayout L = parts_layout(c);
+  c->prof.begin(YASPS_K_LINESEARCH);
+  launch_inertia_energy(inertia_args(c, x), c->stream);
+  launch_snh_energy(snh_args(c, x), c->stream);
+  launch_membrane_energy(membrane_args(c, x), c->stream);
+  int hoff = 0;
+  for (const Group& g : c->hgroups) {
+    launch_hinge_energy(hinge_args(c, x, g, hoff), c->stream);
+    hoff += grid_of(g.end - g.begin, EVAL_BLOCK);
+  }
+  c->prof.end();
+  HIPCHK(c, hipGetLastError());
+  const int kinds[2] = {0, 0};
+  launch_finalize(2, L.off, c->parts, kinds, c->scal, c->stream);
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double ec = 0.0;
+  size_t need = 0;
+  const int r = cd_energy(c->surf, cd_positions(c, x), c->P.dhat, c->P.kappa, c->prm.barrier, cd_alloc(c), c->di_arena,
+                          c->di_arena_bytes, &need, c->stream, &ec);  // synchronises the stream
+  grow_arena(c, need);
+  if (r == -2) return fail(c, YASPS_E_ARG, "line search: a box over too many grid cells");
+  if (r != 0) return fail(c, YASPS_E_HIP, "contact energy of the proximity search");
+  c->prof.collect();
+  *E = c->host_scal[0] + c->host_scal[1] + ec;
+  return YASPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+yasps_status yasps_set_surface(yasps_ctx* c, const yasps_surface* S) {
+  if (!c || !S) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (S->n_points < 0 || S->n_edges < 0 || S->n_tris < 0 || (S->n_points && !S->points) ||
+      (S->n_edges && !S->edges) || (S->n_tris && !S->tris))
+    return fail(c, YASPS_E_ARG, "bad surface arrays");
+  if (!(S->cell > 0.0)) return fail(c, YASPS_E_ARG, "cell must be > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_surface = false;
+  free_list(c->surf_allocs);
+  const int nall = c->P.n_free + c->P.n_fixed;
+  std::vector<int32_t> pts(S->n_points), ed((size_t)2 * S->n_edges), tr((size_t)3 * S->n_tris);
+  if (S->n_points) HIPCHK(c, hipMemcpy(pts.data(), S->points, pts.size() * 4, hipMemcpyDeviceToHost));
+  if (S->n_edges) HIPCHK(c, hipMemcpy(ed.data(), S->edges, ed.size() * 4, hipMemcpyDeviceToHost));
+  if (S->n_tris) HIPCHK(c, hipMemcpy(tr.data(), S->tris, tr.size() * 4, hipMemcpyDeviceToHost));
+  auto bad = [nall](int v) { return v < 0 || v >= nall; };
+  for (int32_t v : pts)
+    if (bad(v)) return fail(c, YASPS_E_ARG, "surface point id out of range");
+  for (int j = 0; j < S->n_edges; ++j)
+    if (bad(ed[j]) || bad(ed[(size_t)S->n_edges + j]) || ed[j] == ed[(size_t)S->n_edges + j])
+      return fail(c, YASPS_E_ARG, "surface edge " + std::to_string(j) + ": bad vertex ids");
+  for (int j = 0; j < S->n_tris; ++j) {
+    const int a = tr[j], b = tr[(size_t)S->n_tris + j], d = tr[2 * (size_t)S->n_tris + j];
+    if (bad(a) || bad(b) || bad(d) || a == b || b == d || a == d)
+      return fail(c, YASPS_E_ARG, "surface triangle " + std::to_string(j) + ": bad vertex ids");
+  }
+  CdSurface& D = c->surf;
+  D = CdSurface{};
+  D.np = S->n_points;
+  D.ne = S->n_edges;
+  D.nt = S->n_tris;
+  D.cell = S->cell;
+  int32_t *dp = nullptr, *de = nullptr, *dt = nullptr;
+  HIPCHK(c, upload(c->surf_allocs, &dp, pts, c->stream));
+  HIPCHK(c, upload(c->surf_allocs, &de, ed, c->stream));
+  HIPCHK(c, upload(c->surf_allocs, &dt, tr, c->stream));
+  D.points = dp;
+  D.edges = de;
+  D.tris = dt;
+  if (S->edge_rest_len2) {
+    double* dl = nullptr;
+    HIPCHK(c, dalloc(c->surf_allocs, &dl, (size_t)std::max(S->n_edges, 1)));
+    if (S->n_edges)
+      HIPCHK(c, hipMemcpyAsync(dl, S->edge_rest_len2, (size_t)S->n_edges * 8, hipMemcpyDeviceToDevice, c->stream));
+    D.len2 = dl;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_surface = true;
+  return YASPS_OK;
+}
+
+yasps_status yasps_detect(yasps_ctx* c, const double* x, int32_t* n_contacts) {
+  if (!c || !x) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (!c->has_surface) return fail(c, YASPS_E_ARG, "no collision surface (yasps_set_surface)");
+  HIPCHK(c, hipSetDevice(c->device));
+  return detect(c, x, n_contacts);
+}
+
+yasps_status yasps_get_detected(yasps_ctx* c, int32_t* type, int32_t* idx, double* ee_eps) {
+  if (!c) return fail(c, YASPS_E_ARG, "NULL context");
+  HIPCHK(c, hipSetDevice(c->device));
+  const CdOutput& o = c->detected;
+  if (o.n == 0) return YASPS_OK;
+  if (type) HIPCHK(c, hipMemcpy(type, o.type, (size_t)o.n * 4, hipMemcpyDeviceToHost));
+  if (idx) HIPCHK(c, hipMemcpy(idx, o.idx, 4 * (size_t)o.n * 4, hipMemcpyDeviceToHost));
+  if (ee_eps) HIPCHK(c, hipMemcpy(ee_eps, o.eps, (size_t)o.n * 8, hipMemcpyDeviceToHost));
+  return YASPS_OK;
+}
+
+yasps_status yasps_ccd(yasps_ctx* c, const double* x, const double* p, double t_max, double s, double* t_out) {
+  if (!c || !x || !p || !t_out) return fail(c, YASPS_E_ARG, "NULL argument");
+  if (!c->has_surface) return fail(c, YASPS_E_ARG, "no collision surface (yasps_set_surface)");
+  if (!(t_max >= 0.0) || !(s > 0.0 && s < 1.0)) return fail(c, YASPS_E_ARG, "need t_max >= 0 and 0 < s < 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  return ccd(c, x, p, t_max, s, t_out);
+}
+
+yasps_status yasps_frame(yasps_ctx* c, double* x, double* v, const yasps_frame_params* prm, yasps_frame_info* info) {
+  if (!c || !x || !v) return fail(c, YASPS_E_ARG, "NULL argument");
+  yasps_frame_params fp{1e-2, 50, 1e-8, 20000, 1e-4, 40, 0.1};
+  if (prm) fp = *prm;
+  if (!(fp.tol > 0.0) || fp.max_newton < 1 || !(fp.ccd_s > 0.0 && fp.ccd_s < 1.0))
+    return fail(c, YASPS_E_ARG, "need tol > 0, max_newton >= 1, 0 < ccd_s < 1");
+  if (c->P.is_static) return fail(c, YASPS_E_ARG, "time stepping needs the dynamic form (is_static = 0)");
+  if (!c->has_surface) return fail(c, YASPS_E_ARG, "no collision surface (yasps_set_surface)");
+  if (c->nb) return fail(c, YASPS_E_UNIMPL, "time stepping with affine bodies is not supported");
+  HIPCHK(c, hipSetDevice(c->device));
+  const double h = c->P.h;
+  const size_t bytes = 3 * (size_t)c->nv * sizeof(double);
+  double* xt = static_cast<double*>(c->xt_frame.ensure(std::max<size_t>(bytes, 8)));
+  double* xs = static_cast<double*>(c->xs_frame.ensure(std::max<size_t>(bytes, 8)));
+  if (!xt || !xs) return fail(c, YASPS_E_HIP, "hipMalloc of the frame buffers");
+  launch_frame_tilde(c->nv, x, v, h, c->P.gravity, xt, c->stream);
+  HIPCHK(c, hipMemcpyAsync(xs, x, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipGetLastError());
+  // the frame's inertial target replaces the problem's for its duration
+  struct Restore {
+    yasps_ctx* c;
+    const double* keep;
+    ~Restore() { c->P.x_tilde = keep; }
+  } restore{c, c->P.x_tilde};
+  c->P.x_tilde = xt;
+  yasps_frame_info fi{};
+  fi.alpha_min = 1.0;
+  hipEvent_t* ev = c->ev;
+  float ms;
+  yasps_status s = YASPS_OK;
+  for (int it = 0; it < fp.max_newton; ++it) {
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    int32_t nc = 0;
+    s = detect(c, x, &nc);
+    if (s) return s;
+    fi.n_contacts_max = std::max(fi.n_contacts_max, nc);
+    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    yasps_eval_info ei{};
+    s = run_eval(c, x, YASPS_PROJECTED, &ei);
+    if (s) return s;
+    if (it == 0) fi.e_begin = ei.energy;
+    fi.e_end = ei.energy;
+    s = run_assemble(c);
+    if (s) return s;
+    launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);
+    double rel = 0.0;
+    int status = 0;
+    const int cg = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, fp.rtol, fp.max_iter, c->prm.precision == YASPS_MIXED,
+                             c->pcg_work.p, &rel, &status, c->stream, &c->prof, c->host_scal + 16, &c->pcg_hint);
+    c->prof.collect();
+    if (cg < 0) return fail(c, YASPS_E_HIP, "pcg launch failed");
+    if (status == YASPS_E_BREAKDOWN) return fail(c, YASPS_E_BREAKDOWN, "PCG breakdown: p^T H p <= 0");
+    fi.cg_iters += cg;
+    {
+      const int nb = grid_of(c->n, RED_BLOCK);
+      const int nd = std::min(nb, 1024);
+      launch_max_norm3(c->n, c->p_dir, c->parts, nb, c->stream);
+      launch_dot(3 * c->n, c->grad, c->p_dir, c->parts + nb, nd, c->stream);
+      int off[3] = {0, nb, nb + nd};
+      int kind[2] = {2, 0};
+      launch_finalize(2, off, c->parts, kind, c->scal, c->stream);
+      HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipEventRecord(ev[2], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double pmax = c->host_scal[0], gp = c->host_scal[1];
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    fi.ms_detect += ms;
+    (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
+    fi.ms_newton += ms;
+    if (pmax / h < fp.tol) {  // the paper's stop rule: largest displacement per time step
+      fi.converged = 1;
+      break;
+    }
+    if (!(gp < 0.0)) return fail(c, YASPS_E_LINESEARCH, "the Newton direction is not a descent direction");
+    ++fi.newton_iters;
+    double alpha = 1.0;
+    s = ccd(c, x, c->p_dir, 1.0, fp.ccd_s, &alpha);
+    if (s) return s;
+    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+    fi.ms_ccd += ms;
+    bool accepted = false;
+    for (int k = 0; k <= fp.max_halvings; ++k) {
+      launch_axpy_to(3 * c->n, x, alpha, c->p_dir, c->x_trial, c->stream);
+      double E = 0.0;
+      ++fi.ls_trials;
+      s = frame_energy(c, c->x_trial, &E);
+      if (s) return s;
+      if (E <= ei.energy + fp.armijo * alpha * gp) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) return fail(c, YASPS_E_LINESEARCH, "no admissible step after the maximum number of halvings");
+    fi.alpha_min = std::min(fi.alpha_min, alpha);
+    HIPCHK(c, hipMemcpyAsync(x, c->x_trial, 3 * (size_t)c->n * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[4]));
+    (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
+    fi.ms_linesearch += ms;
+  }
+  launch_frame_velocity(c->nv, x, xs, h, v, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) *info = fi;
+  if (!fi.converged) return fail(c, YASPS_E_NOCONV, "Newton reached max_newton before the stop rule");
   return YASPS_OK;
 }
 

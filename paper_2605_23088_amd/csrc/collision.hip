@@ -1,0 +1,838 @@
+// Proximity search, the contact energy of the pairs found, and continuous
+// collision detection, for time stepping with contact.
+//
+// The paper leaves collision detection and CCD to an external module
+// (section "Limitations"; its examples use GIPC's, timed as "CCD+CD+
+// LargestStep").  The definitions here are Incremental Potential Contact's:
+// every point-triangle and edge-edge pair of the collision surface (no shared
+// vertex, at least one free vertex) closer than sqrt(dhat) contributes one
+// barrier stencil, typed by where its closest points lie (point-triangle: face
+// / edge / vertex -> PT / PE / PP; edge-edge: interiors / one endpoint / two
+// endpoints -> EE / PE / PP), found with the textbook closest-feature
+// constructions (Ericson, Real-Time Collision Detection, sections 5.1.5 and
+// 5.1.9).  The step bound is additive CCD (Li, Kaufman, Jiang 2021,
+// "Codimensional Incremental Potential Contact").
+//
+// Broad phase: a uniform grid in hashed cell keys.  The primitives of one
+// side (triangles, or edges) are registered in every cell their box inflated
+// by R covers (keys radix-sorted); a query primitive visits the cells of its
+// own box and tests each registered primitive there.  A pair is a candidate
+// when the primitives' boxes, each inflated by r, overlap (the exact test);
+// R = 2r (1 + 1e-9) makes the grid a superset of that, and a pair is taken
+// only in the cell that holds the low corner of the two grid boxes'
+// intersection, so each pair is tested once.  Swept boxes (over x and
+// x + t p) serve the CCD.
+//
+// Floating point: this file is compiled without contraction into fused
+// multiply-adds (pragma below), so every quantity that decides a type, a
+// candidate or a CCD step is computed by the same operations, in the same
+// order, as the textbook definitions written out plainly; the results do
+// not depend on the launch shape.  Output order is fixed: point-triangle
+// pairs by (point, triangle), then edge-edge pairs by (edge, edge).
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "blockreduce.h"
+#include "contact_math.h"
+#include "devsort.h"
+#include "kernels.h"
+
+namespace yasps {
+
+namespace {
+
+using devsort::DI_BLOCK;
+constexpr int CD_BLOCK = 256;
+constexpr long long CELL_OFF = 1ll << 20;  // cell coordinates in [-2^20, 2^20)
+constexpr int ACCD_MAX_STEPS = 10000;
+constexpr long long MAX_BOX_CELLS = 1 << 16;  // a box over more cells (a non-finite position, or a cell size
+                                              // far below the motion) is an error, so every loop is bounded
+
+YHD void sub3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[0] - b[0];
+  c[1] = a[1] - b[1];
+  c[2] = a[2] - b[2];
+}
+YHD double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+YHD double dist2(const double a[3], const double b[3]) {
+  double d[3];
+  sub3(a, b, d);
+  return dot3(d, d);
+}
+YHD double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+// Closest feature of triangle (a, b, c) to p: kind 0 face, 1 edge (l0, l1),
+// 2 vertex (l0); squared distance.
+YHD double point_triangle(const double p[3], const double a[3], const double b[3], const double c[3], int& kind,
+                          int& l0, int& l1) {
+  double ab[3], ac[3], ap[3], bp[3], cp[3], q[3];
+  sub3(b, a, ab);
+  sub3(c, a, ac);
+  sub3(p, a, ap);
+  const double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+  l1 = -1;
+  if (d1 <= 0.0 && d2 <= 0.0) {
+    kind = 2;
+    l0 = 0;
+    return dist2(p, a);
+  }
+  sub3(p, b, bp);
+  const double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+  if (d3 >= 0.0 && d4 <= d3) {
+    kind = 2;
+    l0 = 1;
+    return dist2(p, b);
+  }
+  const double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+    const double v = d1 / (d1 - d3);
+    for (int k = 0; k < 3; ++k) q[k] = a[k] + v * ab[k];
+    kind = 1;
+    l0 = 0;
+    l1 = 1;
+    return dist2(p, q);
+  }
+  sub3(p, c, cp);
+  const double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+  if (d6 >= 0.0 && d5 <= d6) {
+    kind = 2;
+    l0 = 2;
+    return dist2(p, c);
+  }
+  const double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+    const double w = d2 / (d2 - d6);
+    for (int k = 0; k < 3; ++k) q[k] = a[k] + w * ac[k];
+    kind = 1;
+    l0 = 0;
+    l1 = 2;
+    return dist2(p, q);
+  }
+  const double va = d3 * d6 - d5 * d4;
+  if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+    const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    double bc[3];
+    sub3(c, b, bc);
+    for (int k = 0; k < 3; ++k) q[k] = b[k] + w * bc[k];
+    kind = 1;
+    l0 = 1;
+    l1 = 2;
+    return dist2(p, q);
+  }
+  const double den = 1.0 / (va + vb + vc);
+  const double v = vb * den, w = vc * den;
+  for (int k = 0; k < 3; ++k) q[k] = a[k] + ab[k] * v + ac[k] * w;
+  kind = 0;
+  l0 = 0;
+  return dist2(p, q);
+}
+
+// Closest points of segments p1q1, p2q2: parameters s, t in [0, 1]; squared distance.
+YHD double segment_segment(const double p1[3], const double q1[3], const double p2[3], const double q2[3],
+                           double& s, double& t) {
+  double d1[3], d2[3], r[3];
+  sub3(q1, p1, d1);
+  sub3(q2, p2, d2);
+  sub3(p1, p2, r);
+  const double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+  const double c = dot3(d1, r), b = dot3(d1, d2);
+  const double den = a * e - b * b;
+  s = den != 0.0 ? clamp01((b * f - c * e) / den) : 0.0;
+  t = (b * s + f) / e;
+  if (t < 0.0) {
+    t = 0.0;
+    s = clamp01(-c / a);
+  } else if (t > 1.0) {
+    t = 1.0;
+    s = clamp01((b - c) / a);
+  }
+  double c1[3], c2[3];
+  for (int k = 0; k < 3; ++k) {
+    c1[k] = p1[k] + d1[k] * s;
+    c2[k] = p2[k] + d2[k] * t;
+  }
+  return dist2(c1, c2);
+}
+
+YDEV void vpos(const CdPositions& X, int v, double q[3]) {
+  const double* s = v < X.nv ? X.x + 3 * (size_t)v : X.xf + 3 * (size_t)(v - X.nv);
+  q[0] = s[0];
+  q[1] = s[1];
+  q[2] = s[2];
+}
+YDEV void vmove(const CdPositions& X, int v, double d[3]) {  // the vertex's motion (0 for fixed)
+  if (X.p && v < X.nv) {
+    const double* s = X.p + 3 * (size_t)v;
+    d[0] = s[0];
+    d[1] = s[1];
+    d[2] = s[2];
+  } else {
+    d[0] = d[1] = d[2] = 0.0;
+  }
+}
+
+// Box of a primitive inflated by r (over x, and x + t p when X.p is set).
+template <int K>
+YDEV void pbox(const CdPositions& X, const int (&ids)[K], double r, double lo[3], double hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = __builtin_inf();
+    hi[k] = -__builtin_inf();
+  }
+  for (int a = 0; a < K; ++a) {
+    double q[3];
+    vpos(X, ids[a], q);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fmin(lo[k], q[k]);
+      hi[k] = fmax(hi[k], q[k]);
+    }
+    if (X.p) {
+      double d[3];
+      vmove(X, ids[a], d);
+      for (int k = 0; k < 3; ++k) {
+        const double e = q[k] + X.t * d[k];
+        lo[k] = fmin(lo[k], e);
+        hi[k] = fmax(hi[k], e);
+      }
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = lo[k] - r;
+    hi[k] = hi[k] + r;
+  }
+}
+
+YDEV long long cell_of(double v, double cell) {
+  double f = floor(v / cell);
+  if (!(f == f)) f = 0.0;  // NaN: any cell (the box is rejected by its cell count or its exact test)
+  const long long c = f < -(double)CELL_OFF ? -CELL_OFF : (f >= (double)(CELL_OFF - 1) ? CELL_OFF - 1 : (long long)f);
+  return c + CELL_OFF;
+}
+YDEV uint64_t cell_key(long long ix, long long iy, long long iz) {
+  return ((uint64_t)ix << 42) | ((uint64_t)iy << 21) | (uint64_t)iz;
+}
+
+template <int K>
+YDEV void load_ids(const int32_t* prims, int m, int j, int (&ids)[K]) {
+  for (int a = 0; a < K; ++a) ids[a] = prims[(size_t)a * m + j];
+}
+
+// Cells covered by a box; 0 (and the error flag) when more than MAX_BOX_CELLS.
+YDEV long long box_cells(const double lo[3], const double hi[3], double cell, int* err) {
+  long long c = 1;
+  for (int k = 0; k < 3; ++k) {
+    const long long w = cell_of(hi[k], cell) - cell_of(lo[k], cell) + 1;
+    if (w < 1 || w > MAX_BOX_CELLS) {
+      atomicOr(err, 1);
+      return 0;
+    }
+    c *= w;
+  }
+  if (c > MAX_BOX_CELLS) {
+    atomicOr(err, 1);
+    return 0;
+  }
+  return c;
+}
+
+template <int K>
+__global__ void reg_count_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell, int32_t* cnt,
+                                 int* err) {
+  const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (j >= m) return;
+  int ids[K];
+  load_ids<K>(prims, m, j, ids);
+  double lo[3], hi[3];
+  pbox<K>(X, ids, R, lo, hi);
+  cnt[j] = (int32_t)box_cells(lo, hi, cell, err);
+}
+
+template <int K>
+__global__ void reg_fill_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell,
+                                const int32_t* off, uint64_t* keys, int32_t* vals, int* err) {
+  const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (j >= m) return;
+  int ids[K];
+  load_ids<K>(prims, m, j, ids);
+  double lo[3], hi[3];
+  pbox<K>(X, ids, R, lo, hi);
+  if (box_cells(lo, hi, cell, err) == 0) return;  // counted as 0
+  long long l[3], h[3];
+  for (int k = 0; k < 3; ++k) {
+    l[k] = cell_of(lo[k], cell);
+    h[k] = cell_of(hi[k], cell);
+  }
+  int o = off[j];
+  for (long long z = l[2]; z <= h[2]; ++z)
+    for (long long y = l[1]; y <= h[1]; ++y)
+      for (long long x = l[0]; x <= h[0]; ++x) {
+        keys[o] = cell_key(x, y, z);
+        vals[o] = j;
+        ++o;
+      }
+}
+
+YDEV int lower_bound(const uint64_t* keys, int n, uint64_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Squared distance of a point-triangle (x4 = p, a, b, c) or edge-edge pair.
+template <bool EEP>
+YDEV double pair_d2(const double (&x4)[4][3]) {
+  if constexpr (EEP) {
+    double s, t;
+    return segment_segment(x4[0], x4[1], x4[2], x4[3], s, t);
+  } else {
+    int kind, l0, l1;
+    return point_triangle(x4[0], x4[1], x4[2], x4[3], kind, l0, l1);
+  }
+}
+
+// Additive CCD of one pair along x + t p, t <= t_c.
+template <bool EEP>
+YDEV double accd(const double (&x4in)[4][3], const double (&p4)[4][3], double s, double t_c) {
+  double pm[3], pr[4][3], nrm[4], x4[4][3];
+  for (int k = 0; k < 3; ++k) pm[k] = (((0.0 + p4[0][k]) + p4[1][k]) + p4[2][k] + p4[3][k]) / 4.0;
+  for (int a = 0; a < 4; ++a) {
+    sub3(p4[a], pm, pr[a]);
+    nrm[a] = sqrt(dot3(pr[a], pr[a]));
+    for (int k = 0; k < 3; ++k) x4[a][k] = x4in[a][k];
+  }
+  const double lp = EEP ? fmax(nrm[0], nrm[1]) + fmax(nrm[2], nrm[3]) : nrm[0] + fmax(fmax(nrm[1], nrm[2]), nrm[3]);
+  if (lp == 0.0) return t_c;
+  double d = sqrt(pair_d2<EEP>(x4));
+  if (d == 0.0) return 0.0;
+  const double g = s * d;
+  double t = 0.0, tl = (1.0 - s) * d / lp;
+  for (int it = 0; it < ACCD_MAX_STEPS; ++it) {
+    for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 3; ++k) x4[a][k] = x4[a][k] + tl * pr[a][k];
+    d = sqrt(pair_d2<EEP>(x4));
+    if (t > 0.0 && d < g) return t;
+    t = t + tl;
+    if (t > t_c) return t_c;
+    tl = 0.9 * d / lp;
+  }
+  return t;
+}
+
+// Type-fixed squared distance of a stencil (the closed forms of the stencil
+// kernels, written plainly) and its barrier energy.
+YDEV double stencil_energy(int type, const double (&x4)[4][3], double eps, double kappa, double dhat, int classic) {
+  double d, m = 1.0;
+  if (type == 0 || type == 1) {
+    double e1[3], e2[3], n[3], w[3];
+    if (type == 0) {
+      sub3(x4[2], x4[1], e1);
+      sub3(x4[3], x4[1], e2);
+      sub3(x4[0], x4[1], w);
+    } else {
+      sub3(x4[1], x4[0], e1);
+      sub3(x4[3], x4[2], e2);
+      sub3(x4[0], x4[2], w);
+    }
+    cmath::cross(e1, e2, n);
+    const double s = dot3(w, n), N = dot3(n, n);
+    d = s * s / N;
+    if (type == 1 && eps > 0.0) {
+      const double r = N / eps;
+      m = r < 1.0 ? r * (2.0 - r) : 1.0;
+    }
+  } else if (type == 2) {
+    double a[3], b[3], c[3], e[3];
+    sub3(x4[1], x4[0], a);
+    sub3(x4[2], x4[0], b);
+    cmath::cross(a, b, c);
+    sub3(x4[2], x4[1], e);
+    d = dot3(c, c) / dot3(e, e);
+  } else {
+    d = dist2(x4[0], x4[1]);
+  }
+  if (!(d > 0.0) || !(d < dhat)) return 0.0;
+  double b0, b1, b2;
+  cmath::barrier(d, dhat, classic, b0, b1, b2);
+  return m < 1.0 ? kappa * m * b0 : kappa * b0;
+}
+
+struct QueryArgs {
+  int ma;                // query primitives
+  const int32_t* pa;     // [KA][ma]
+  int mb;                // registered primitives
+  const int32_t* pb;     // [KB][mb]
+  bool ee;               // edge-edge: the same set on both sides, pairs i < j
+  CdPositions X;
+  double r, R, cell;
+  int nreg;
+  const uint64_t* keys;  // sorted cell keys of the registered primitives
+  const int32_t* vals;   // their primitive ids
+  const double* len2;    // squared rest lengths of the edges (EE mollifier) or null
+  double dhat, kappa;
+  int classic;
+  double s_ccd, t_max;
+  int32_t* cnt;          // count pass
+  const int32_t* off;    // fill pass: first output of each query primitive
+  int cap;               // stride of the output idx array
+  int32_t* otype;
+  int32_t* oidx;         // [4][cap]
+  double* oeps;
+  int32_t* oord;         // edge-edge outputs: partner edge (the sort key within a query)
+  double* part;          // per-workgroup energy sums / CCD minima
+  int* err;              // set when a box spans too many cells
+};
+
+enum { Q_COUNT, Q_FILL, Q_ENERGY, Q_CCD };
+
+// The stencil of a candidate pair at positions X (type < 0: none).
+template <bool EEP>
+YDEV int narrow(const QueryArgs& q, int i, int j, const int* ia, const int* ib, int (&ids)[4], double& eps) {
+  double P[4][3];
+  eps = 0.0;
+  ids[0] = ids[1] = ids[2] = ids[3] = -1;
+  if constexpr (!EEP) {
+    vpos(q.X, ia[0], P[0]);
+    for (int a = 0; a < 3; ++a) vpos(q.X, ib[a], P[1 + a]);
+    int kind, l0, l1;
+    const double d2 = point_triangle(P[0], P[1], P[2], P[3], kind, l0, l1);
+    if (!(d2 < q.dhat)) return -1;
+    ids[0] = ia[0];
+    if (kind == 0) {
+      ids[1] = ib[0];
+      ids[2] = ib[1];
+      ids[3] = ib[2];
+      return 0;
+    }
+    if (kind == 1) {
+      ids[1] = ib[l0];
+      ids[2] = ib[l1];
+      return 2;
+    }
+    ids[1] = ib[l0];
+    return 3;
+  } else {
+    for (int a = 0; a < 2; ++a) {
+      vpos(q.X, ia[a], P[a]);
+      vpos(q.X, ib[a], P[2 + a]);
+    }
+    double s, t;
+    const double d2 = segment_segment(P[0], P[1], P[2], P[3], s, t);
+    if (!(d2 < q.dhat)) return -1;
+    const int sa = s == 0.0 ? 0 : (s == 1.0 ? 1 : -1);
+    const int tb = t == 0.0 ? 0 : (t == 1.0 ? 1 : -1);
+    if (sa < 0 && tb < 0) {
+      ids[0] = ia[0];
+      ids[1] = ia[1];
+      ids[2] = ib[0];
+      ids[3] = ib[1];
+      if (q.len2) eps = 1e-3 * q.len2[i] * q.len2[j];
+      return 1;
+    }
+    if (sa >= 0 && tb < 0) {
+      ids[0] = ia[sa];
+      ids[1] = ib[0];
+      ids[2] = ib[1];
+      return 2;
+    }
+    if (sa < 0 && tb >= 0) {
+      ids[0] = ib[tb];
+      ids[1] = ia[0];
+      ids[2] = ia[1];
+      return 2;
+    }
+    ids[0] = ia[sa];
+    ids[1] = ib[tb];
+    return 3;
+  }
+}
+
+template <int KA, int KB, int MODE>
+__global__ __launch_bounds__(CD_BLOCK) void query_kernel(QueryArgs q) {
+  constexpr bool EEP = KA == 2;
+  __shared__ double lds[CD_BLOCK];
+  const int i = blockIdx.x * CD_BLOCK + threadIdx.x;
+  int count = 0;
+  double acc = 0.0, tmin = q.t_max;
+  if (i < q.ma) {
+    int ia[KA];
+    load_ids<KA>(q.pa, q.ma, i, ia);
+    double lo0[3], hi0[3], lor[3], hir[3];
+    pbox<KA>(q.X, ia, 0.0, lo0, hi0);
+    pbox<KA>(q.X, ia, q.r, lor, hir);
+    long long cl[3], ch[3];
+    for (int k = 0; k < 3; ++k) {
+      cl[k] = cell_of(lo0[k], q.cell);
+      ch[k] = cell_of(hi0[k], q.cell);
+    }
+    if (box_cells(lo0, hi0, q.cell, q.err) == 0) ch[0] = cl[0] - 1;  // no cell visited
+    const int base = MODE == Q_FILL ? q.off[i] : 0;
+    const int lim = MODE == Q_FILL ? q.off[i + 1] : 0;  // this query's output segment [base, lim)
+    bool free_a = false;
+    for (int a = 0; a < KA; ++a) free_a |= ia[a] < q.X.nv;
+    for (long long z = cl[2]; z <= ch[2]; ++z)
+      for (long long y = cl[1]; y <= ch[1]; ++y)
+        for (long long x = cl[0]; x <= ch[0]; ++x) {
+          const uint64_t key = cell_key(x, y, z);
+          for (int e = lower_bound(q.keys, q.nreg, key); e < q.nreg && q.keys[e] == key; ++e) {
+            const int j = q.vals[e];
+            if (q.ee && j <= i) continue;
+            int ib[KB];
+            load_ids<KB>(q.pb, q.mb, j, ib);
+            // the exact candidate test: boxes inflated by r overlap
+            double lob[3], hib[3];
+            pbox<KB>(q.X, ib, q.r, lob, hib);
+            bool ov = true;
+            for (int k = 0; k < 3; ++k) ov = ov && lor[k] <= hib[k] && lob[k] <= hir[k];
+            if (!ov) continue;
+            // taken only in the cell of the low corner of the grid boxes' intersection
+            double loR[3], hiR[3];
+            pbox<KB>(q.X, ib, q.R, loR, hiR);
+            if (cell_of(fmax(lo0[0], loR[0]), q.cell) != x || cell_of(fmax(lo0[1], loR[1]), q.cell) != y ||
+                cell_of(fmax(lo0[2], loR[2]), q.cell) != z)
+              continue;
+            bool shared = false, free_b = false;
+            for (int a = 0; a < KA; ++a)
+              for (int b = 0; b < KB; ++b) shared |= ia[a] == ib[b];
+            for (int b = 0; b < KB; ++b) free_b |= ib[b] < q.X.nv;
+            if (shared || !(free_a || free_b)) continue;
+            if constexpr (MODE == Q_CCD) {
+              double P4[4][3], D4[4][3];
+              int v4[4];
+              if constexpr (EEP) {
+                v4[0] = ia[0], v4[1] = ia[1], v4[2] = ib[0], v4[3] = ib[1];
+              } else {
+                v4[0] = ia[0], v4[1] = ib[0], v4[2] = ib[1], v4[3] = ib[2];
+              }
+              for (int a = 0; a < 4; ++a) {
+                vpos(q.X, v4[a], P4[a]);
+                vmove(q.X, v4[a], D4[a]);
+              }
+              tmin = fmin(tmin, accd<EEP>(P4, D4, q.s_ccd, tmin));
+            } else {
+              int ids[4];
+              double eps;
+              const int type = narrow<EEP>(q, i, j, ia, ib, ids, eps);
+              if (type < 0) continue;
+              if constexpr (MODE == Q_FILL) {
+                const int o = base + count;
+                if (o >= lim) continue;  // (the count pass took the same decisions: never)
+                q.otype[o] = type;
+                for (int a = 0; a < 4; ++a) q.oidx[(size_t)a * q.cap + o] = ids[a];
+                q.oeps[o] = eps;
+                if (EEP) q.oord[o] = j;
+              } else if constexpr (MODE == Q_ENERGY) {
+                double P4[4][3] = {};
+                for (int a = 0; a < 4; ++a)
+                  if (ids[a] >= 0) vpos(q.X, ids[a], P4[a]);
+                acc += stencil_energy(type, P4, eps, q.kappa, q.dhat, q.classic);
+              }
+              ++count;
+            }
+          }
+        }
+    if constexpr (MODE == Q_COUNT) q.cnt[i] = count;
+    if constexpr (MODE == Q_FILL && EEP) {
+      // this edge's outputs in partner order (insertion sort; few per edge)
+      const int end = base + count < lim ? base + count : lim;
+      for (int a = base + 1; a < end; ++a)
+        for (int b = a; b > base && q.oord[b - 1] > q.oord[b]; --b) {
+          const int t0 = q.otype[b], o0 = q.oord[b];
+          const double e0 = q.oeps[b];
+          q.otype[b] = q.otype[b - 1];
+          q.oord[b] = q.oord[b - 1];
+          q.oeps[b] = q.oeps[b - 1];
+          q.otype[b - 1] = t0;
+          q.oord[b - 1] = o0;
+          q.oeps[b - 1] = e0;
+          for (int k = 0; k < 4; ++k) {
+            int32_t* col = q.oidx + (size_t)k * q.cap;
+            const int v0 = col[b];
+            col[b] = col[b - 1];
+            col[b - 1] = v0;
+          }
+        }
+    }
+  }
+  if constexpr (MODE == Q_ENERGY) {
+    const double es = block_sum<CD_BLOCK>(acc, lds);
+    if (threadIdx.x == 0) q.part[blockIdx.x] = es;
+  }
+  if constexpr (MODE == Q_CCD) {
+    const double tm = block_min<CD_BLOCK>(tmin, lds);
+    if (threadIdx.x == 0) q.part[blockIdx.x] = tm;
+  }
+}
+
+// part[0] = sum (kind 0) or min (kind 1) of part[0 .. m)
+__global__ __launch_bounds__(CD_BLOCK) void fold_kernel(double* part, int m, int kind) {
+  __shared__ double lds[CD_BLOCK];
+  double v = kind ? __builtin_inf() : 0.0;
+  for (int k = threadIdx.x; k < m; k += CD_BLOCK) v = kind ? fmin(v, part[k]) : v + part[k];
+  const double r = kind ? block_min<CD_BLOCK>(v, lds) : block_sum<CD_BLOCK>(v, lds);
+  if (threadIdx.x == 0) part[0] = r;
+}
+
+// x_tilde = x + h v + h^2 g, and v = (x - x_start) / h, over the free rows
+__global__ void frame_tilde_kernel(int n3, const double* __restrict__ x, const double* __restrict__ v, double h,
+                                   double g0, double g1, double g2, double* __restrict__ xt) {
+  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (i >= n3) return;
+  const int c = i % 3;
+  const double g = c == 0 ? g0 : (c == 1 ? g1 : g2);
+  xt[i] = x[i] + h * v[i] + h * h * g;
+}
+__global__ void frame_velocity_kernel(int n3, const double* __restrict__ x, const double* __restrict__ xs, double h,
+                                      double* __restrict__ v) {
+  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (i >= n3) return;
+  v[i] = (x[i] - xs[i]) / h;
+}
+
+int grid_q(int m) { return (m + CD_BLOCK - 1) / CD_BLOCK; }
+
+#define CD_CHECK(call)                  \
+  do {                                  \
+    if ((call) != hipSuccess) return -1; \
+  } while (0)
+
+// Registration of one side (triangles: K = 3, edges: K = 2): sorted cell keys.
+struct Reg {
+  int n = 0;
+  uint64_t* keys = nullptr;
+  int32_t* vals = nullptr;
+};
+
+template <int K>
+int register_side(int m, const int32_t* prims, const CdPositions& X, double R, double cell, const CdAlloc& alloc,
+                  int which, devsort::Temp& tmp, hipStream_t s, int* err, Reg& out) {
+  out = Reg{};
+  if (m == 0) return 0;
+  int32_t* cnt = tmp.get<int32_t>(m);
+  int32_t* off = tmp.get<int32_t>(m + 1);
+  CD_CHECK(tmp.err);
+  hipLaunchKernelGGL(reg_count_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell,
+                     cnt, err);
+  CD_CHECK(devsort::prefix(tmp, cnt, off, m, s));
+  int h[2] = {0, 0};
+  CD_CHECK(hipMemcpyAsync(&h[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(&h[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipStreamSynchronize(s));
+  if (h[1]) return -2;
+  const int total = h[0];
+  if (total <= 0) return -2;
+  uint64_t* keys = tmp.get<uint64_t>(total);
+  int32_t* vals = tmp.get<int32_t>(total);
+  CD_CHECK(tmp.err);
+  uint64_t* ks = static_cast<uint64_t*>(alloc(which, sizeof(uint64_t) * (size_t)total));
+  int32_t* vs = static_cast<int32_t*>(alloc(which + 1, sizeof(int32_t) * (size_t)total));
+  if (!ks || !vs) return -1;
+  hipLaunchKernelGGL(reg_fill_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell, off,
+                     keys, vals, err);
+  CD_CHECK(devsort::sort_pairs(tmp, keys, ks, vals, vs, total, 63, s));
+  out.n = total;
+  out.keys = ks;
+  out.vals = vs;
+  return 0;
+}
+
+QueryArgs query_args(const CdSurface& S, const CdPositions& X, bool ee, const Reg& reg, double r, double dhat,
+                     int* err) {
+  QueryArgs q{};
+  q.err = err;
+  q.ee = ee;
+  q.ma = ee ? S.ne : S.np;
+  q.pa = ee ? S.edges : S.points;
+  q.mb = ee ? S.ne : S.nt;
+  q.pb = ee ? S.edges : S.tris;
+  q.X = X;
+  q.r = r;
+  q.R = 2.0 * r * (1.0 + 1e-9);
+  q.cell = S.cell;
+  q.nreg = reg.n;
+  q.keys = reg.keys;
+  q.vals = reg.vals;
+  q.len2 = S.len2;
+  q.dhat = dhat;
+  return q;
+}
+
+template <int MODE>
+void launch_query(const QueryArgs& q, hipStream_t s) {
+  if (q.ma == 0 || q.nreg == 0) return;
+  if (q.ee)
+    hipLaunchKernelGGL((query_kernel<2, 2, MODE>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+  else
+    hipLaunchKernelGGL((query_kernel<1, 3, MODE>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+}
+
+}  // namespace
+
+void launch_frame_tilde(int nv, const double* x, const double* v, double h, const double g[3], double* xt,
+                        hipStream_t s) {
+  if (nv == 0) return;
+  hipLaunchKernelGGL(frame_tilde_kernel, dim3(devsort::grid_of(3ll * nv)), dim3(DI_BLOCK), 0, s, 3 * nv, x, v, h,
+                     g[0], g[1], g[2], xt);
+}
+
+void launch_frame_velocity(int nv, const double* x, const double* xs, double h, double* v, hipStream_t s) {
+  if (nv == 0) return;
+  hipLaunchKernelGGL(frame_velocity_kernel, dim3(devsort::grid_of(3ll * nv)), dim3(DI_BLOCK), 0, s, 3 * nv, x, xs,
+                     h, v);
+}
+
+namespace {
+
+// Registrations of both sides and the two query argument sets; 0, -1 (HIP) or
+// -2 (a box over too many cells).
+int prepare(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc& alloc, devsort::Temp& tmp,
+            hipStream_t s, int*& err, QueryArgs& qp, QueryArgs& qe) {
+  const double r = 0.5 * std::sqrt(dhat), R = 2.0 * r * (1.0 + 1e-9);
+  err = tmp.get<int>(1);
+  CD_CHECK(tmp.err);
+  CD_CHECK(hipMemsetAsync(err, 0, sizeof(int), s));
+  Reg rt, re;
+  int e = register_side<3>(S.nt, S.tris, X, R, S.cell, alloc, CD_REG_T, tmp, s, err, rt);
+  if (e) return e;
+  e = register_side<2>(S.ne, S.edges, X, R, S.cell, alloc, CD_REG_E, tmp, s, err, re);
+  if (e) return e;
+  qp = query_args(S, X, false, rt, r, dhat, err);
+  qe = query_args(S, X, true, re, r, dhat, err);
+  return 0;
+}
+
+// After the queries: the error flag (the stream is synchronised by the caller first).
+int finish(int* err, hipStream_t s) {
+  int h = 0;
+  CD_CHECK(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipStreamSynchronize(s));
+  return h ? -2 : 0;
+}
+
+}  // namespace
+
+int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc& alloc, void* arena,
+              size_t arena_bytes, size_t* arena_needed, hipStream_t s, CdOutput& out) {
+  devsort::Temp tmp;
+  tmp.arena = static_cast<char*>(arena);
+  tmp.cap = arena_bytes;
+  out = CdOutput{};
+  int* err = nullptr;
+  QueryArgs qp{}, qe{};
+  int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
+  if (e) return e;
+  const int np = S.np, ne = S.ne;
+  int32_t* cnt = tmp.get<int32_t>((size_t)np + ne);
+  int32_t* off = tmp.get<int32_t>((size_t)np + ne + 1);
+  CD_CHECK(tmp.err);
+  CD_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ((size_t)np + ne), s));
+  qp.cnt = cnt;
+  qe.cnt = cnt + np;
+  launch_query<Q_COUNT>(qp, s);
+  launch_query<Q_COUNT>(qe, s);
+  CD_CHECK(devsort::prefix(tmp, cnt, off, (long long)np + ne, s));
+  int total = 0;
+  CD_CHECK(hipMemcpyAsync(&total, off + np + ne, sizeof(int), hipMemcpyDeviceToHost, s));
+  e = finish(err, s);
+  if (e) return e;
+  const int cap = std::max(total, 1);
+  out.type = static_cast<int32_t*>(alloc(CD_TYPE, sizeof(int32_t) * (size_t)cap));
+  out.idx = static_cast<int32_t*>(alloc(CD_IDX, 4 * sizeof(int32_t) * (size_t)cap));
+  out.eps = static_cast<double*>(alloc(CD_EPS, sizeof(double) * (size_t)cap));
+  int32_t* ord = static_cast<int32_t*>(alloc(CD_ORD, sizeof(int32_t) * (size_t)cap));
+  if (!out.type || !out.idx || !out.eps || !ord) return -1;
+  for (QueryArgs* q : {&qp, &qe}) {
+    q->off = q == &qp ? off : off + np;
+    q->cap = total;
+    q->otype = out.type;
+    q->oidx = out.idx;
+    q->oeps = out.eps;
+    q->oord = ord;
+  }
+  if (total) {
+    launch_query<Q_FILL>(qp, s);
+    launch_query<Q_FILL>(qe, s);
+  }
+  CD_CHECK(hipGetLastError());
+  e = finish(err, s);  // also keeps the temporaries alive until the queries are done
+  if (e) return e;
+  out.n = total;
+  *arena_needed = tmp.used;
+  return 0;
+}
+
+int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kappa, int classic, const CdAlloc& alloc,
+              void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* e_out) {
+  devsort::Temp tmp;
+  tmp.arena = static_cast<char*>(arena);
+  tmp.cap = arena_bytes;
+  int* err = nullptr;
+  QueryArgs qp{}, qe{};
+  int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
+  if (e) return e;
+  const int gp = (qp.ma && qp.nreg) ? grid_q(qp.ma) : 0, ge = (qe.ma && qe.nreg) ? grid_q(qe.ma) : 0;
+  double* part = tmp.get<double>((size_t)gp + ge + 1);
+  CD_CHECK(tmp.err);
+  for (QueryArgs* q : {&qp, &qe}) {
+    q->kappa = kappa;
+    q->classic = classic;
+  }
+  qp.part = part;
+  qe.part = part + gp;
+  launch_query<Q_ENERGY>(qp, s);
+  launch_query<Q_ENERGY>(qe, s);
+  double val = 0.0;
+  if (gp + ge) {
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(CD_BLOCK), 0, s, part, gp + ge, 0);
+    CD_CHECK(hipMemcpyAsync(&val, part, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  CD_CHECK(hipGetLastError());
+  e = finish(err, s);
+  if (e) return e;
+  *e_out = val;
+  *arena_needed = tmp.used;
+  return 0;
+}
+
+int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, double s_ccd, const CdAlloc& alloc,
+           void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* t_out) {
+  devsort::Temp tmp;
+  tmp.arena = static_cast<char*>(arena);
+  tmp.cap = arena_bytes;
+  int* err = nullptr;
+  QueryArgs qp{}, qe{};
+  int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
+  if (e) return e;
+  const int gp = (qp.ma && qp.nreg) ? grid_q(qp.ma) : 0, ge = (qe.ma && qe.nreg) ? grid_q(qe.ma) : 0;
+  double* part = tmp.get<double>((size_t)gp + ge + 1);
+  CD_CHECK(tmp.err);
+  for (QueryArgs* q : {&qp, &qe}) {
+    q->s_ccd = s_ccd;
+    q->t_max = t_max;
+  }
+  qp.part = part;
+  qe.part = part + gp;
+  launch_query<Q_CCD>(qp, s);
+  launch_query<Q_CCD>(qe, s);
+  double t = t_max;
+  if (gp + ge) {
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(CD_BLOCK), 0, s, part, gp + ge, 1);
+    CD_CHECK(hipMemcpyAsync(&t, part, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  CD_CHECK(hipGetLastError());
+  e = finish(err, s);
+  if (e) return e;
+  *t_out = std::fmin(t, t_max);
+  *arena_needed = tmp.used;
+  return 0;
+}
+
+}  // namespace yasps

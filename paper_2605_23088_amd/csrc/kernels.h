@@ -332,4 +332,48 @@ hipError_t noalloc_scratch(int device, void** ptr);
 // y = H x (both parts, symmetric upper storage) through the solver's SpMV kernel.
 void launch_spmv(const PcgMatrix& A, const double* x, double* y, void* work, hipStream_t s, LaunchTimer* tm);
 
+// Collision surface and positions of the proximity search / CCD (collision.hip).
+struct CdSurface {
+  int np, ne, nt;          // points, edges, triangles
+  const int32_t* points;   // [np] vertex ids
+  const int32_t* edges;    // [2][ne]
+  const int32_t* tris;     // [3][nt]
+  const double* len2;      // [ne] squared rest lengths (EE mollifier thresholds) or null
+  double cell;             // grid cell size
+};
+struct CdPositions {
+  int nv;                  // free vertices (ids below nv are rows of x)
+  const double* x;         // (nv, 3) free positions
+  const double* xf;        // fixed positions
+  const double* p;         // (nv, 3) motion of the free vertices (CCD: swept boxes over x + t p) or null
+  double t;
+};
+struct CdOutput {
+  int n = 0;               // stencils found
+  int32_t* type = nullptr; // [n]
+  int32_t* idx = nullptr;  // [4][n] (stride n)
+  double* eps = nullptr;   // [n] mollifier thresholds (0 for the non-EE stencils)
+};
+// Grow-only buffers of the collision module: sorted cell keys / ids of the
+// triangles and of the edges, and the detected stencils.
+enum { CD_REG_T, CD_REG_T_V, CD_REG_E, CD_REG_E_V, CD_TYPE, CD_IDX, CD_EPS, CD_ORD, CD_COUNT };
+using CdAlloc = std::function<void*(int, size_t)>;
+// Contact stencils at X (squared distance below dhat), in the fixed order
+// (point-triangle pairs by (point, triangle), then edge-edge pairs by (edge,
+// edge)).  0 ok, -1 HIP failure, -2 a primitive's box over too many grid cells
+// (a non-finite position or a cell size far below the motion).  Synchronises s.
+int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc& alloc, void* arena,
+              size_t arena_bytes, size_t* arena_needed, hipStream_t s, CdOutput& out);
+// Barrier energy of the stencils found at X (the same pairs as cd_detect).
+int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kappa, int classic, const CdAlloc& alloc,
+              void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* e_out);
+// Largest conservative step t <= t_max along X.x + t X.p (additive CCD over the
+// candidate pairs of the swept boxes).
+int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, double s_ccd, const CdAlloc& alloc,
+           void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* t_out);
+// Time stepping: x_tilde = x + h v + h^2 g and v = (x - x_start) / h over the free rows.
+void launch_frame_tilde(int nv, const double* x, const double* v, double h, const double g[3], double* xt,
+                        hipStream_t s);
+void launch_frame_velocity(int nv, const double* x, const double* xs, double h, double* v, hipStream_t s);
+
 }  // namespace yasps

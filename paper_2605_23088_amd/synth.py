@@ -884,3 +884,78 @@ def affine_block(seed=41, nx=5, ny=4, nz=3, n_pt=120, n_ee=120, n_pp=40, n_pt1=6
         p["ee_eps"] = eps[keep]
         p["bee_eps"] = np.concatenate([eps[to_body], np.zeros(len(bct) - len(to_body))])
     return p
+
+
+# --------------------------------------------------------------------------
+# Time stepping with contact: a block dropped onto a fixed ground
+# --------------------------------------------------------------------------
+
+def boundary_surface(tets):
+    """Boundary triangles of a tet mesh (faces of exactly one tet), their
+    edges and vertices."""
+    tets = np.asarray(tets, np.int64)
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 3, 2]], tets[:, [0, 1, 3]], tets[:, [0, 2, 1]]])
+    key = np.sort(faces, axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    tris = faces[cnt[inv.ravel()] == 1]
+    e = np.sort(np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]]), axis=1)
+    edges = np.unique(e, axis=0)
+    return tris, edges, np.unique(tris)
+
+
+def ground_grid(cells, size, angle, center, z=0.0):
+    """A flat square of cells x cells (each split along a diagonal), side
+    `size`, rotated by `angle` about the vertical through `center`: vertices,
+    triangles, edges (local ids)."""
+    t = np.linspace(-0.5 * size, 0.5 * size, cells + 1)
+    gx, gy = np.meshgrid(t, t, indexing="xy")
+    c, s_ = np.cos(angle), np.sin(angle)
+    V = np.stack([center[0] + c * gx.ravel() - s_ * gy.ravel(), center[1] + s_ * gx.ravel() + c * gy.ravel(),
+                  np.full(gx.size, z)], 1)
+    vid = lambda i, j: j * (cells + 1) + i
+    tris, edges = [], set()
+    for j in range(cells):
+        for i in range(cells):
+            a, b, cc, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris += [(a, b, cc), (a, cc, d)]
+            for u, w in ((a, b), (b, cc), (cc, a), (cc, d), (d, a)):
+                edges.add((min(u, w), max(u, w)))
+    return V, np.array(tris, np.int64), np.array(sorted(edges), np.int64)
+
+
+def drop_scene(seed=51, nx=3, ny=3, nz=2, a=0.1, gap=0.012, v0=-1.0, ground_cells=5, ground_size=0.6,
+               ground_angle=0.37, h=1e-2, E=1e5, nu=0.4, rho=1000.0, kappa=1e3, dhat=1e-4, jitter=1e-3):
+    """A free Kuhn block (rest shape = its initial shape) a gap above a fixed,
+    rotated ground grid, falling at v0 (m/s, vertical): the time-stepping
+    scene.  The block's vertices are jittered by N(0, jitter^2 a^2) (so no
+    edge pair is exactly parallel) before the rest shapes are taken.  The
+    collision surface: the block's boundary triangles, edges and vertices, and
+    the ground's (fixed ids n_free + k).  Keys: the problem (no contacts),
+    `v0` (n, 3), surface arrays `surf_points`, `surf_edges`, `surf_tris`,
+    `surf_len2` (squared rest edge lengths), `cell` (grid cell size)."""
+    rng = np.random.default_rng(seed)
+    X = grid_vertices(nx, ny, nz, a, origin=(0.0, 0.0, gap))
+    X = X + rng.normal(0.0, jitter * a, X.shape)
+    X[:, 2] = np.maximum(X[:, 2], gap * 0.5)
+    tets = kuhn_tets(nx, ny, nz)
+    Ds = _edge_matrix(X, tets)
+    dm_inv, vol = np.linalg.inv(Ds), np.abs(np.linalg.det(Ds)) / 6.0
+    n = X.shape[0]
+    mass = _lumped_mass(n, tets, vol, rho)
+    center = (0.5 * nx * a + 0.013, 0.5 * ny * a - 0.021)
+    G, gt, ge = ground_grid(ground_cells, ground_size, ground_angle, center)
+    mu, lam = lame(E, nu)
+    v = np.zeros((n, 3))
+    v[:, 2] = v0
+    x_tilde = X + h * v + h * h * GRAVITY
+    p = _pack(n, X, G, mass, x_tilde, tets, dm_inv, vol, np.zeros(0, np.int32), np.zeros((0, 4), np.int32),
+              mu=mu, lam=lam, h=h, kappa=kappa, dhat=dhat, rho=rho, name=f"drop{nx}x{ny}x{nz}", spacing=a)
+    bt, be, bp = boundary_surface(tets)
+    tris = np.concatenate([bt, gt + n])
+    edges = np.concatenate([be, ge + n])
+    points = np.concatenate([bp, np.arange(G.shape[0]) + n])
+    xa = np.concatenate([X, G])
+    len2 = ((xa[edges[:, 1]] - xa[edges[:, 0]]) ** 2).sum(1)
+    p.update(v0=v, surf_points=points.astype(np.int32), surf_edges=edges.astype(np.int32),
+             surf_tris=tris.astype(np.int32), surf_len2=len2, cell=max(a, ground_size / ground_cells) * 1.01)
+    return p

@@ -28,8 +28,8 @@ INDEX_DEVICE, INDEX_HOST = 0, 1  # yasps_params.index_build
 
 EXPORTS = ["yasps_create", "yasps_set_contacts", "yasps_eval_stencils", "yasps_assemble_bsr", "yasps_pcg",
            "yasps_pcg_noalloc", "yasps_newton_step", "yasps_get_pattern", "yasps_theta_adjoint", "yasps_profile_enable",
-           "yasps_profile_query", "yasps_spmv", "yasps_lm_shift", "yasps_set_body_contacts", "yasps_destroy",
-           "yasps_last_error"]
+           "yasps_profile_query", "yasps_spmv", "yasps_lm_shift", "yasps_set_body_contacts", "yasps_set_surface",
+           "yasps_detect", "yasps_get_detected", "yasps_ccd", "yasps_frame", "yasps_destroy", "yasps_last_error"]
 K_INERTIA, K_SNH, K_CONTACT, K_ASSEMBLE, K_BLOCKINV, K_SPMV, K_PCG_UPDATE, K_LINESEARCH, K_CLOTH = range(9)
 KERNEL_CLASSES = ["inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "pcg_spmv", "pcg_update",
                   "linesearch", "cloth_eval"]
@@ -68,6 +68,23 @@ class BsrView(C.Structure):
                 ("values_are_f32", C.c_int32), ("grad", C.c_void_p), ("block_inv", C.c_void_p),
                 ("nnzb_body", C.c_int32), ("row_ptr_b", C.c_void_p), ("col_idx_b", C.c_void_p),
                 ("values_b", C.c_void_p)]
+
+
+class Surface(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("points", C.c_void_p), ("n_edges", C.c_int32), ("edges", C.c_void_p),
+                ("n_tris", C.c_int32), ("tris", C.c_void_p), ("edge_rest_len2", C.c_void_p), ("cell", C.c_double)]
+
+
+class FrameParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_newton", C.c_int32), ("rtol", C.c_double), ("max_iter", C.c_int32),
+                ("armijo", C.c_double), ("max_halvings", C.c_int32), ("ccd_s", C.c_double)]
+
+
+class FrameInfo(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("cg_iters", C.c_int32), ("ls_trials", C.c_int32),
+                ("n_contacts_max", C.c_int32), ("e_begin", C.c_double), ("e_end", C.c_double),
+                ("alpha_min", C.c_double), ("converged", C.c_int32), ("ms_detect", C.c_float),
+                ("ms_newton", C.c_float), ("ms_ccd", C.c_float), ("ms_linesearch", C.c_float)]
 
 
 class PcgInfo(C.Structure):
@@ -112,6 +129,11 @@ def lib():
         L.yasps_profile_query.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.yasps_spmv.argtypes = [P, P, P]
         L.yasps_lm_shift.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
+        L.yasps_set_surface.argtypes = [P, C.POINTER(Surface)]
+        L.yasps_detect.argtypes = [P, P, C.POINTER(C.c_int32)]
+        L.yasps_get_detected.argtypes = [P, P, P, P]
+        L.yasps_ccd.argtypes = [P, P, P, C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.yasps_frame.argtypes = [P, P, P, C.POINTER(FrameParams), C.POINTER(FrameInfo)]
         L.yasps_destroy.argtypes = [P]
         L.yasps_destroy.restype = None
         L.yasps_last_error.argtypes = [P]
@@ -412,4 +434,50 @@ class Yasps:
     def theta_adjoint(self, x, lam, theta):
         out = torch.empty(self.nt, dtype=torch.float64, device=self.dev)
         self._check(lib().yasps_theta_adjoint(self.ctx, _ptr(x), _ptr(lam), _ptr(theta), _ptr(out)))
+        return out
+
+    # ------------------------------------------------------------ time stepping
+    def set_surface(self, points, edges, tris, edge_rest_len2=None, cell=None):
+        """Host arrays: point ids (m,), edges (k, 2), triangles (t, 3), squared
+        rest edge lengths (k,) or None, grid cell size (default: 1.01 x the
+        longest rest edge)."""
+        i32 = dict(dtype=torch.int32, device=self.dev)
+        pts = torch.as_tensor(np.asarray(points, np.int32), **i32).contiguous()
+        ed = torch.as_tensor(np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2).T), **i32).contiguous()
+        tr = torch.as_tensor(np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1, 3).T), **i32).contiguous()
+        l2 = None
+        if edge_rest_len2 is not None:
+            l2 = torch.as_tensor(np.asarray(edge_rest_len2, np.float64), dtype=torch.float64, device=self.dev)
+        if cell is None:
+            cell = 1.01 * float(np.sqrt(np.max(edge_rest_len2))) if edge_rest_len2 is not None else 1.0
+        S = Surface(int(pts.shape[0]), _ptr(pts), int(ed.shape[1]), _ptr(ed), int(tr.shape[1]), _ptr(tr), _ptr(l2),
+                    float(cell))
+        self._check(lib().yasps_set_surface(self.ctx, C.byref(S)))
+
+    def detect(self, x):
+        """Proximity search at x; the stencils become the contact set.  Returns
+        (ctype (m,), cidx (m, 4), ee_eps (m,)) as host arrays."""
+        n = C.c_int32()
+        self._check(lib().yasps_detect(self.ctx, _ptr(x), C.byref(n)))
+        m = n.value
+        self.nc = m
+        t = np.zeros(max(m, 1), np.int32)
+        i = np.zeros((4, max(m, 1)), np.int32)
+        e = np.zeros(max(m, 1), np.float64)
+        self._check(lib().yasps_get_detected(self.ctx, t.ctypes.data_as(C.c_void_p), i.ctypes.data_as(C.c_void_p),
+                                             e.ctypes.data_as(C.c_void_p)))
+        return t[:m], np.ascontiguousarray(i.reshape(4, -1)[:, :m].T) if m else np.zeros((0, 4), np.int32), e[:m]
+
+    def ccd(self, x, p, t_max=1.0, s=0.1):
+        out = C.c_double()
+        self._check(lib().yasps_ccd(self.ctx, _ptr(x), _ptr(p), t_max, s, C.byref(out)))
+        return out.value
+
+    def frame(self, x, v, tol=1e-2, max_newton=50, rtol=1e-8, max_iter=20000, armijo=1e-4, max_halvings=40,
+              ccd_s=0.1, allow=()):
+        prm = FrameParams(tol, max_newton, rtol, max_iter, armijo, max_halvings, ccd_s)
+        info = FrameInfo()
+        rc = self._check(lib().yasps_frame(self.ctx, _ptr(x), _ptr(v), C.byref(prm), C.byref(info)), allow)
+        out = {k: getattr(info, k) for k, _ in FrameInfo._fields_}
+        out["status"] = rc
         return out
