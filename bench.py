@@ -397,6 +397,96 @@ def bench_static(args):
     print(json.dumps(line), flush=True)
 
 
+def frames_cpu_baseline(runs=3):
+    """The oracle's time stepping on a small drop scene (3x3x2 cells), timed
+    per frame: the oracle as it stands (brute-force pair search in Python),
+    median over the first frames with contact."""
+    import numpy as np
+    from oracle import collision as ocol
+    from oracle import timestep as ots
+    from paper_2605_23088_amd import synth
+    p = synth.drop_scene()
+    S = ocol.Surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["n_free"], p["surf_len2"])
+    st = ots.Stepper(p, S)
+    x, v = p["x0"], p["v0"]
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        x, v, info = st.frame(x, v)
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    import torch
+    return {"value": 1.0 / med, "unit": "frames/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"the 3x3x2-cell drop scene ({len(p['tet_idx'])} tets): median of {runs} frames "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+
+
+def bench_frames(args):
+    """Time stepping with contact: a free Kuhn block (rest shape, falling at
+    1 m/s) landing on a fixed, rotated ground grid; every frame runs Newton
+    iterations with a proximity search per iterate and per line-search trial,
+    the CCD step bound, and the stop rule max|p|/h < 1e-2 m/s.  Timed: K
+    frames after W warm-up frames (the block is already in contact when the
+    timed frames start)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_23088_amd import synth
+    from paper_2605_23088_amd.yasps import Yasps
+
+    c = args.cells
+    nz = max(2, c // 2)
+    log(f"[bench] generating the drop scene {c}x{c}x{nz}")
+    a = 1.0 / c
+    p = synth.drop_scene(nx=c, ny=c, nz=nz, a=a, gap=0.2 * a, ground_cells=int(1.25 * c), ground_size=1.5,
+                         kappa=1e4, dhat=(0.4 * a) ** 2)
+    g = Yasps(p, contacts=False)
+    g.set_surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["surf_len2"], p["cell"])
+    x = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda").contiguous()
+    v = torch.as_tensor(p["v0"], dtype=torch.float64, device="cuda").contiguous()
+    for k in range(args.warmup):
+        info = g.frame(x, v)
+        log(f"[bench] warm-up frame {k}: {info['newton_iters']} Newton, {info['cg_iters']} PCG, "
+            f"{info['n_contacts_max']} contacts")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(g.frame(x, v))
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    log(f"[bench] {args.steps} frames: {ms:.2f} ms per frame")
+    mean = lambda k: float(np.mean([i[k] for i in infos]))
+    cpu = None if args.no_cpu_baseline else frames_cpu_baseline()
+    line = {
+        "metric": "time-stepping frames/s (IPC frame: proximity search + Newton + CCD line search)",
+        "value": 1e3 / ms,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{c}x{c}x{nz}-cell Kuhn block ({len(p['tet_idx'])} tets) dropped on a "
+                               f"{int(1.25 * c)}^2-cell rotated ground; h = {p['h']}, dhat = {p['dhat']:.3g}, "
+                               f"kappa = {p['kappa']:.3g}",
+                   "tets": len(p["tet_idx"]), "free_vertices": int(p["n_free"]),
+                   "surface_points": len(p["surf_points"]), "surface_edges": len(p["surf_edges"]),
+                   "surface_triangles": len(p["surf_tris"])},
+        "newton_iters_per_frame": mean("newton_iters"),
+        "pcg_iters_per_frame": mean("cg_iters"),
+        "ls_trials_per_frame": mean("ls_trials"),
+        "contacts_max": int(max(i["n_contacts_max"] for i in infos)),
+        "phases_ms_per_frame": {k: mean("ms_" + k) for k in ("detect", "newton", "ccd", "linesearch")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,7 +497,7 @@ def main():
     ap.add_argument("--no-index-timing", dest="index_timing", action="store_false",
                     help="skip timing the contact index rebuild (device and host builds)")
     ap.add_argument("--cells", type=int, default=40, help="block size of the block40 workload")
-    ap.add_argument("--workload", choices=["block40", "cloth", "block80", "static"], default="block40")
+    ap.add_argument("--workload", choices=["block40", "cloth", "block80", "static", "frames"], default="block40")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (the reference kernel that scales "
@@ -443,6 +533,8 @@ def main():
 
     if args.workload == "static":
         return bench_static(args)
+    if args.workload == "frames":
+        return bench_frames(args)
 
     log(f"[bench] generating workload {args.workload}")
     cpu_frac, cpu_solve = 0.25, True
