@@ -656,6 +656,21 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
 #pragma unroll
     for (int i = 0; i < 3; ++i) Fr[1][i] = t2[i];
     emit_reduced<Topo<TYPE>, K, EXACT, true>(gu, D.H, fl, grad_sink, block_sink, Fr);
+  } else if constexpr (TYPE == 3 && !EXACT) {
+    // point-point in closed form: with u = q - p and d = |u|^2 the u-space
+    // Hessian kappa (b'' grad d grad d^T + b' hess d) = 4 kappa b'' u u^T + 2 kappa b' I
+    // has the eigenvalue 4 kappa b'' d + 2 kappa b' along u and 2 kappa b' twice
+    // across it; clamping them projects it, and the x-space Hessian (u-space
+    // block times [[1, -1], [-1, 1]], or the block itself with one vertex
+    // free) is then already positive semi-definite
+    const double la = fma(4.0 * kb2, D.d, 2.0 * kb1), lp = 2.0 * kb1;
+    const double pa = la > 0.0 ? la : 0.0, pp = lp > 0.0 ? lp : 0.0;
+    const double c = D.d > 0.0 ? (pa - pp) / D.d : 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = r; q < 3; ++q) D.H(r, q) = (r == q ? pp : 0.0) + c * u[0][r] * u[0][q];
+    emit_reduced<Topo<TYPE>, K, true>(gu, D.H, fl, grad_sink, block_sink);
   } else {
     emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
   }

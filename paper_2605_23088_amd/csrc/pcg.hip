@@ -134,6 +134,64 @@ YHD Slots slots_of(const Vecs<VT>& V) {
 // the update kernel's gamma / |r|^2 partials, loaded before the product and
 // summed after it), SPMV_PLAIN (product only), SPMV_REPLACE (product only,
 // skipped once the solver is done).
+// One stored block of the chunked product: its target rows, entries, values
+// and the two gathered vector rows.
+template <class BT, class XT>
+struct BlockIn {
+  int j, r, ey, et;
+  BT B[9];
+  XT x[3], u[3];
+};
+
+template <class BT, class XT>
+YDEV BlockIn<BT, XT> block_load(const SpmvPart& P, const BT* __restrict__ vals, const XT* __restrict__ u,
+                                const int32_t* __restrict__ rl, int m0, int k) {
+  BlockIn<BT, XT> L;
+  const uint32_t meta = P.meta[k];
+  L.j = P.col[k];
+  const int m = m0 + (int)(meta & 1023u);
+  L.r = rl ? rl[m] : m;
+  L.ey = (int)((meta >> 10) & 2047u);
+  L.et = (int)(meta >> 21);
+  const BT* bp = vals + 9 * (size_t)k;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) L.B[q] = bp[q];
+  const XT* xj = u + 3 * (size_t)L.j;
+  const XT* xr = u + 3 * (size_t)L.r;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    L.x[q] = xj[q];
+    L.u[q] = xr[q];
+  }
+  return L;
+}
+
+// B x_j to the row's entry; off the diagonal B^T u_r to the column's entry;
+// the block's share of delta = u^T H u.
+template <class BT, class XT>
+YDEV void block_products(const BlockIn<BT, XT>& L, double* E, double& dlt) {
+  double B[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) B[q] = double(L.B[q]);
+  const double x0 = double(L.x[0]), x1 = double(L.x[1]), x2 = double(L.x[2]);
+  const double u0 = double(L.u[0]), u1 = double(L.u[1]), u2 = double(L.u[2]);
+  const double y0 = fma(B[0], x0, fma(B[1], x1, B[2] * x2));
+  const double y1 = fma(B[3], x0, fma(B[4], x1, B[5] * x2));
+  const double y2 = fma(B[6], x0, fma(B[7], x1, B[8] * x2));
+  E[3 * L.ey] = y0;
+  E[3 * L.ey + 1] = y1;
+  E[3 * L.ey + 2] = y2;
+  const double uy = fma(u0, y0, fma(u1, y1, u2 * y2));
+  if (L.j != L.r) {
+    E[3 * L.et] = fma(B[0], u0, fma(B[3], u1, B[6] * u2));
+    E[3 * L.et + 1] = fma(B[1], u0, fma(B[4], u1, B[7] * u2));
+    E[3 * L.et + 2] = fma(B[2], u0, fma(B[5], u1, B[8] * u2));
+    dlt = fma(2.0, uy, dlt);
+  } else {
+    dlt += uy;
+  }
+}
+
 template <class BT, class XT>
 __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, const XT* __restrict__ u, Slots S,
                                                                double* __restrict__ part_b,
@@ -164,35 +222,16 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
     const int m0 = P.m0[cc];
     const int32_t* __restrict__ rl = P.rl;  // null when every row holds blocks (row = compressed row)
     const BT* __restrict__ vals = static_cast<const BT*>(P.vals);
-    for (int k = b0 + (int)threadIdx.x; k < b1; k += RED_BLOCK) {
-      const uint32_t meta = P.meta[k];
-      const int j = P.col[k];
-      const int m = m0 + (int)(meta & 1023u);
-      const int r = rl ? rl[m] : m;
-      const int ey = (int)((meta >> 10) & 2047u), et = (int)(meta >> 21);
-      const BT* bp = vals + 9 * (size_t)k;
-      double B[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) B[q] = double(bp[q]);
-      const XT* xj = u + 3 * (size_t)j;
-      const XT* xr = u + 3 * (size_t)r;
-      const double x0 = double(xj[0]), x1 = double(xj[1]), x2 = double(xj[2]);
-      const double u0 = double(xr[0]), u1 = double(xr[1]), u2 = double(xr[2]);
-      const double y0 = fma(B[0], x0, fma(B[1], x1, B[2] * x2));
-      const double y1 = fma(B[3], x0, fma(B[4], x1, B[5] * x2));
-      const double y2 = fma(B[6], x0, fma(B[7], x1, B[8] * x2));
-      E[3 * ey] = y0;
-      E[3 * ey + 1] = y1;
-      E[3 * ey + 2] = y2;
-      const double uy = fma(u0, y0, fma(u1, y1, u2 * y2));
-      if (j != r) {
-        E[3 * et] = fma(B[0], u0, fma(B[3], u1, B[6] * u2));
-        E[3 * et + 1] = fma(B[1], u0, fma(B[4], u1, B[7] * u2));
-        E[3 * et + 2] = fma(B[2], u0, fma(B[5], u1, B[8] * u2));
-        dlt = fma(2.0, uy, dlt);
-      } else {
-        dlt += uy;
-      }
+    // two blocks per thread and trip, all loads of both issued before either
+    // product (a chunk of RED_BLOCK blocks or fewer takes one)
+    for (int k = b0 + (int)threadIdx.x; k < b1; k += 2 * RED_BLOCK) {
+      const int k2 = k + RED_BLOCK;
+      const bool two = b1 - b0 > RED_BLOCK && k2 < b1;
+      BlockIn<BT, XT> L0 = block_load<BT, XT>(P, vals, u, rl, m0, k);
+      BlockIn<BT, XT> L1;
+      if (two) L1 = block_load<BT, XT>(P, vals, u, rl, m0, k2);
+      block_products(L0, E, dlt);
+      if (two) block_products(L1, E, dlt);
     }
     __syncthreads();
     const int t0 = P.tb[cc], nt = P.tb[cc + 1] - t0;
