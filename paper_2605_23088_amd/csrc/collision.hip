@@ -15,20 +15,21 @@
 //
 // Broad phase: a uniform grid in hashed cell keys.  The primitives of one
 // side (triangles, or edges) are registered in every cell their box inflated
-// by R covers (keys radix-sorted); a query primitive visits the cells of its
-// own box and tests each registered primitive there.  A pair is a candidate
-// when the primitives' boxes, each inflated by r, overlap (the exact test);
-// R = 2r (1 + 1e-9) makes the grid a superset of that, and a pair is taken
-// only in the cell that holds the low corner of the two grid boxes'
-// intersection, so each pair is tested once.  Swept boxes (over x and
-// x + t p) serve the CCD.
+// by R covers (keys radix-sorted); every (query primitive, registered entry)
+// of the cells a query's own box covers is listed (count, scan, fill), and
+// one thread per listed pair runs the tests: a pair is a candidate when the
+// primitives' boxes, each inflated by r, overlap (the exact test); R = 2r (1 +
+// 1e-9) makes the grid a superset of that, and a pair is taken only in the
+// cell that holds the low corner of the two grid boxes' intersection, so each
+// pair is tested once.  Swept boxes (over x and x + t p) serve the CCD.
 //
 // Floating point: this file is compiled without contraction into fused
 // multiply-adds (pragma below), so every quantity that decides a type, a
 // candidate or a CCD step is computed by the same operations, in the same
 // order, as the textbook definitions written out plainly; the results do
 // not depend on the launch shape.  Output order is fixed: point-triangle
-// pairs by (point, triangle), then edge-edge pairs by (edge, edge).
+// pairs by (point, triangle) (the listing order), then edge-edge pairs by
+// (edge, edge) (a radix sort of the hits).
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -380,13 +381,20 @@ struct QueryArgs {
   double dhat, kappa;
   int classic;
   double s_ccd, t_max;
-  int32_t* cnt;          // count pass
-  const int32_t* off;    // fill pass: first output of each query primitive
+  // candidates: every (query, registered entry) of the cells a query's box covers
+  int32_t* ccnt;         // [ma] candidates per query
+  const int32_t* coff;   // [ma + 1] their offsets
+  int ncand;
+  int32_t* cq;           // [ncand] query of each candidate
+  int32_t* ce;           // [ncand] registered entry (index into keys / vals)
+  int32_t* hit;          // [ncand] 1 if the candidate gives a stencil (count pass)
+  const int32_t* hoff;   // [ncand + 1] output position of each hit (fill pass)
+  int out0;              // first output of this query set
   int cap;               // stride of the output idx array
   int32_t* otype;
   int32_t* oidx;         // [4][cap]
   double* oeps;
-  int32_t* oord;         // edge-edge outputs: partner edge (the sort key within a query)
+  uint64_t* okey;        // edge-edge outputs: (edge, partner) sort key
   double* part;          // per-workgroup energy sums / CCD minima
   int* err;              // set when a box spans too many cells
 };
@@ -455,112 +463,132 @@ YDEV int narrow(const QueryArgs& q, int i, int j, const int* ia, const int* ib, 
   }
 }
 
-template <int KA, int KB, int MODE>
-__global__ __launch_bounds__(CD_BLOCK) void query_kernel(QueryArgs q) {
-  constexpr bool EEP = KA == 2;
-  __shared__ double lds[CD_BLOCK];
+// The cell range of a query primitive's own box (none when it spans too many cells).
+template <int KA>
+YDEV bool query_cells(const QueryArgs& q, int i, int (&ia)[KA], double (&lo0)[3], long long (&cl)[3],
+                      long long (&ch)[3]) {
+  load_ids<KA>(q.pa, q.ma, i, ia);
+  double hi0[3];
+  pbox<KA>(q.X, ia, 0.0, lo0, hi0);
+  for (int k = 0; k < 3; ++k) {
+    cl[k] = cell_of(lo0[k], q.cell);
+    ch[k] = cell_of(hi0[k], q.cell);
+  }
+  return box_cells(lo0, hi0, q.cell, q.err) != 0;
+}
+
+// Pass 1 (WRITE = false): candidates per query, the registered entries of the
+// cells its box covers; pass 2 (WRITE = true): the (query, entry) list, query
+// by query, cells in (z, y, x) order, entries in key order.
+template <int KA, bool WRITE>
+__global__ __launch_bounds__(CD_BLOCK) void cand_kernel(QueryArgs q) {
   const int i = blockIdx.x * CD_BLOCK + threadIdx.x;
-  int count = 0;
-  double acc = 0.0, tmin = q.t_max;
-  if (i < q.ma) {
-    int ia[KA];
-    load_ids<KA>(q.pa, q.ma, i, ia);
-    double lo0[3], hi0[3], lor[3], hir[3];
-    pbox<KA>(q.X, ia, 0.0, lo0, hi0);
-    pbox<KA>(q.X, ia, q.r, lor, hir);
-    long long cl[3], ch[3];
-    for (int k = 0; k < 3; ++k) {
-      cl[k] = cell_of(lo0[k], q.cell);
-      ch[k] = cell_of(hi0[k], q.cell);
-    }
-    if (box_cells(lo0, hi0, q.cell, q.err) == 0) ch[0] = cl[0] - 1;  // no cell visited
-    const int base = MODE == Q_FILL ? q.off[i] : 0;
-    const int lim = MODE == Q_FILL ? q.off[i + 1] : 0;  // this query's output segment [base, lim)
-    bool free_a = false;
-    for (int a = 0; a < KA; ++a) free_a |= ia[a] < q.X.nv;
+  if (i >= q.ma) return;
+  int ia[KA];
+  double lo0[3];
+  long long cl[3], ch[3];
+  int c = 0;
+  if (query_cells<KA>(q, i, ia, lo0, cl, ch)) {
+    int o = WRITE ? q.coff[i] : 0;
     for (long long z = cl[2]; z <= ch[2]; ++z)
       for (long long y = cl[1]; y <= ch[1]; ++y)
         for (long long x = cl[0]; x <= ch[0]; ++x) {
           const uint64_t key = cell_key(x, y, z);
           for (int e = lower_bound(q.keys, q.nreg, key); e < q.nreg && q.keys[e] == key; ++e) {
-            const int j = q.vals[e];
-            if (q.ee && j <= i) continue;
-            int ib[KB];
-            load_ids<KB>(q.pb, q.mb, j, ib);
-            // the exact candidate test: boxes inflated by r overlap
-            double lob[3], hib[3];
-            pbox<KB>(q.X, ib, q.r, lob, hib);
-            bool ov = true;
-            for (int k = 0; k < 3; ++k) ov = ov && lor[k] <= hib[k] && lob[k] <= hir[k];
-            if (!ov) continue;
-            // taken only in the cell of the low corner of the grid boxes' intersection
-            double loR[3], hiR[3];
-            pbox<KB>(q.X, ib, q.R, loR, hiR);
-            if (cell_of(fmax(lo0[0], loR[0]), q.cell) != x || cell_of(fmax(lo0[1], loR[1]), q.cell) != y ||
-                cell_of(fmax(lo0[2], loR[2]), q.cell) != z)
-              continue;
-            bool shared = false, free_b = false;
-            for (int a = 0; a < KA; ++a)
-              for (int b = 0; b < KB; ++b) shared |= ia[a] == ib[b];
-            for (int b = 0; b < KB; ++b) free_b |= ib[b] < q.X.nv;
-            if (shared || !(free_a || free_b)) continue;
-            if constexpr (MODE == Q_CCD) {
-              double P4[4][3], D4[4][3];
-              int v4[4];
-              if constexpr (EEP) {
-                v4[0] = ia[0], v4[1] = ia[1], v4[2] = ib[0], v4[3] = ib[1];
-              } else {
-                v4[0] = ia[0], v4[1] = ib[0], v4[2] = ib[1], v4[3] = ib[2];
-              }
-              for (int a = 0; a < 4; ++a) {
-                vpos(q.X, v4[a], P4[a]);
-                vmove(q.X, v4[a], D4[a]);
-              }
-              tmin = fmin(tmin, accd<EEP>(P4, D4, q.s_ccd, tmin));
-            } else {
-              int ids[4];
-              double eps;
-              const int type = narrow<EEP>(q, i, j, ia, ib, ids, eps);
-              if (type < 0) continue;
-              if constexpr (MODE == Q_FILL) {
-                const int o = base + count;
-                if (o >= lim) continue;  // (the count pass took the same decisions: never)
-                q.otype[o] = type;
-                for (int a = 0; a < 4; ++a) q.oidx[(size_t)a * q.cap + o] = ids[a];
-                q.oeps[o] = eps;
-                if (EEP) q.oord[o] = j;
-              } else if constexpr (MODE == Q_ENERGY) {
-                double P4[4][3] = {};
-                for (int a = 0; a < 4; ++a)
-                  if (ids[a] >= 0) vpos(q.X, ids[a], P4[a]);
-                acc += stencil_energy(type, P4, eps, q.kappa, q.dhat, q.classic);
-              }
-              ++count;
+            if constexpr (WRITE) {
+              q.cq[o] = i;
+              q.ce[o] = e;
+              ++o;
             }
+            ++c;
           }
         }
-    if constexpr (MODE == Q_COUNT) q.cnt[i] = count;
-    if constexpr (MODE == Q_FILL && EEP) {
-      // this edge's outputs in partner order (insertion sort; few per edge)
-      const int end = base + count < lim ? base + count : lim;
-      for (int a = base + 1; a < end; ++a)
-        for (int b = a; b > base && q.oord[b - 1] > q.oord[b]; --b) {
-          const int t0 = q.otype[b], o0 = q.oord[b];
-          const double e0 = q.oeps[b];
-          q.otype[b] = q.otype[b - 1];
-          q.oord[b] = q.oord[b - 1];
-          q.oeps[b] = q.oeps[b - 1];
-          q.otype[b - 1] = t0;
-          q.oord[b - 1] = o0;
-          q.oeps[b - 1] = e0;
-          for (int k = 0; k < 4; ++k) {
-            int32_t* col = q.oidx + (size_t)k * q.cap;
-            const int v0 = col[b];
-            col[b] = col[b - 1];
-            col[b - 1] = v0;
-          }
-        }
+  }
+  if constexpr (!WRITE) q.ccnt[i] = c;
+}
+
+// One candidate per thread: the exact candidate test, the owner-cell test,
+// the shared-vertex and fixed-pair filters, then per MODE the narrow phase
+// (hit flag, stencil output, barrier energy) or additive CCD.
+template <int KA, int KB, int MODE>
+__global__ __launch_bounds__(CD_BLOCK) void pair_kernel(QueryArgs q) {
+  constexpr bool EEP = KA == 2;
+  __shared__ double lds[CD_BLOCK];
+  const int t = blockIdx.x * CD_BLOCK + threadIdx.x;
+  double acc = 0.0, tmin = q.t_max;
+  int hit = 0;
+  if (t < q.ncand) {
+    const int i = q.cq[t], e = q.ce[t];
+    const int j = q.vals[e];
+    const uint64_t key = q.keys[e];
+    const long long x = (long long)((key >> 42) & 0x1FFFFFull), y = (long long)((key >> 21) & 0x1FFFFFull),
+                    z = (long long)(key & 0x1FFFFFull);
+    bool take = !(q.ee && j <= i);
+    int ia[KA], ib[KB];
+    load_ids<KA>(q.pa, q.ma, i, ia);
+    load_ids<KB>(q.pb, q.mb, j, ib);
+    if (take) {
+      // the exact candidate test: boxes inflated by r overlap
+      double lor[3], hir[3], lob[3], hib[3];
+      pbox<KA>(q.X, ia, q.r, lor, hir);
+      pbox<KB>(q.X, ib, q.r, lob, hib);
+      for (int k = 0; k < 3; ++k) take = take && lor[k] <= hib[k] && lob[k] <= hir[k];
     }
+    if (take) {
+      // taken only in the cell of the low corner of the grid boxes' intersection
+      double lo0[3], hi0[3], loR[3], hiR[3];
+      pbox<KA>(q.X, ia, 0.0, lo0, hi0);
+      pbox<KB>(q.X, ib, q.R, loR, hiR);
+      take = cell_of(fmax(lo0[0], loR[0]), q.cell) == x && cell_of(fmax(lo0[1], loR[1]), q.cell) == y &&
+             cell_of(fmax(lo0[2], loR[2]), q.cell) == z;
+    }
+    if (take) {
+      bool shared = false, free_a = false, free_b = false;
+      for (int a = 0; a < KA; ++a) {
+        free_a |= ia[a] < q.X.nv;
+        for (int b = 0; b < KB; ++b) shared |= ia[a] == ib[b];
+      }
+      for (int b = 0; b < KB; ++b) free_b |= ib[b] < q.X.nv;
+      take = !shared && (free_a || free_b);
+    }
+    if (take) {
+      if constexpr (MODE == Q_CCD) {
+        double P4[4][3], D4[4][3];
+        int v4[4];
+        if constexpr (EEP) {
+          v4[0] = ia[0], v4[1] = ia[1], v4[2] = ib[0], v4[3] = ib[1];
+        } else {
+          v4[0] = ia[0], v4[1] = ib[0], v4[2] = ib[1], v4[3] = ib[2];
+        }
+        for (int a = 0; a < 4; ++a) {
+          vpos(q.X, v4[a], P4[a]);
+          vmove(q.X, v4[a], D4[a]);
+        }
+        tmin = accd<EEP>(P4, D4, q.s_ccd, q.t_max);
+      } else {
+        int ids[4];
+        double eps;
+        const int type = narrow<EEP>(q, i, j, ia, ib, ids, eps);
+        if (type >= 0) {
+          hit = 1;
+          if constexpr (MODE == Q_FILL) {
+            const int o = q.out0 + q.hoff[t];
+            q.otype[o] = type;
+            for (int a = 0; a < 4; ++a) q.oidx[(size_t)a * q.cap + o] = ids[a];
+            q.oeps[o] = eps;
+            if (EEP) q.okey[q.hoff[t]] = ((uint64_t)i << 32) | (uint64_t)j;
+          } else if constexpr (MODE == Q_ENERGY) {
+            double P4[4][3] = {};
+            for (int a = 0; a < 4; ++a)
+              if (ids[a] >= 0) vpos(q.X, ids[a], P4[a]);
+            acc = stencil_energy(type, P4, eps, q.kappa, q.dhat, q.classic);
+          }
+        }
+      }
+    }
+  }
+  if constexpr (MODE == Q_COUNT) {
+    if (t < q.ncand) q.hit[t] = hit;
   }
   if constexpr (MODE == Q_ENERGY) {
     const double es = block_sum<CD_BLOCK>(acc, lds);
@@ -570,6 +598,24 @@ __global__ __launch_bounds__(CD_BLOCK) void query_kernel(QueryArgs q) {
     const double tm = block_min<CD_BLOCK>(tmin, lds);
     if (threadIdx.x == 0) q.part[blockIdx.x] = tm;
   }
+}
+
+// The edge-edge outputs in (edge, partner) order: out[k] = in[perm[k]].
+__global__ void gather_kernel(int m, const int32_t* __restrict__ perm, const int32_t* __restrict__ ti,
+                              const int32_t* __restrict__ ii, int istride, const double* __restrict__ ei,
+                              int32_t* __restrict__ to, int32_t* __restrict__ io, int ostride,
+                              double* __restrict__ eo) {
+  const int k = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (k >= m) return;
+  const int s = perm[k];
+  to[k] = ti[s];
+  eo[k] = ei[s];
+  for (int a = 0; a < 4; ++a) io[(size_t)a * ostride + k] = ii[(size_t)a * istride + s];
+}
+
+__global__ void iota32_kernel(int m, int32_t* v) {
+  const int k = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (k < m) v[k] = k;
 }
 
 // part[0] = sum (kind 0) or min (kind 1) of part[0 .. m)
@@ -665,15 +711,6 @@ QueryArgs query_args(const CdSurface& S, const CdPositions& X, bool ee, const Re
   return q;
 }
 
-template <int MODE>
-void launch_query(const QueryArgs& q, hipStream_t s) {
-  if (q.ma == 0 || q.nreg == 0) return;
-  if (q.ee)
-    hipLaunchKernelGGL((query_kernel<2, 2, MODE>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
-  else
-    hipLaunchKernelGGL((query_kernel<1, 3, MODE>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
-}
-
 }  // namespace
 
 void launch_frame_tilde(int nv, const double* x, const double* v, double h, const double g[3], double* xt,
@@ -709,12 +746,84 @@ int prepare(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc
   return 0;
 }
 
-// After the queries: the error flag (the stream is synchronised by the caller first).
+// The error flag (synchronises the stream).
 int finish(int* err, hipStream_t s) {
   int h = 0;
   CD_CHECK(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipStreamSynchronize(s));
   return h ? -2 : 0;
+}
+
+// Candidate lists of both query sets (one count read-back for the two).
+int candidates(QueryArgs& qp, QueryArgs& qe, devsort::Temp& tmp, hipStream_t s, int* err) {
+  QueryArgs* qs[2] = {&qp, &qe};
+  int32_t* off[2] = {nullptr, nullptr};
+  for (int k = 0; k < 2; ++k) {
+    QueryArgs& q = *qs[k];
+    if (q.ma == 0 || q.nreg == 0) continue;
+    q.ccnt = tmp.get<int32_t>(q.ma);
+    off[k] = tmp.get<int32_t>((size_t)q.ma + 1);
+    CD_CHECK(tmp.err);
+    if (q.ee)
+      hipLaunchKernelGGL((cand_kernel<2, false>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+    else
+      hipLaunchKernelGGL((cand_kernel<1, false>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+    CD_CHECK(devsort::prefix(tmp, q.ccnt, off[k], q.ma, s));
+  }
+  int h[3] = {0, 0, 0};
+  for (int k = 0; k < 2; ++k)
+    if (off[k]) CD_CHECK(hipMemcpyAsync(&h[k], off[k] + qs[k]->ma, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(&h[2], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipStreamSynchronize(s));
+  if (h[2]) return -2;
+  for (int k = 0; k < 2; ++k) {
+    QueryArgs& q = *qs[k];
+    q.ncand = 0;
+    if (!off[k]) continue;
+    if (h[k] < 0) return -2;  // more candidates than an int counts
+    q.ncand = h[k];
+    q.coff = off[k];
+    q.cq = tmp.get<int32_t>(std::max(h[k], 1));
+    q.ce = tmp.get<int32_t>(std::max(h[k], 1));
+    CD_CHECK(tmp.err);
+    if (q.ee)
+      hipLaunchKernelGGL((cand_kernel<2, true>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+    else
+      hipLaunchKernelGGL((cand_kernel<1, true>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+  }
+  return 0;
+}
+
+template <int MODE>
+void launch_pairs(const QueryArgs& q, hipStream_t s) {
+  if (q.ncand == 0) return;
+  if (q.ee)
+    hipLaunchKernelGGL((pair_kernel<2, 2, MODE>), dim3(grid_q(q.ncand)), dim3(CD_BLOCK), 0, s, q);
+  else
+    hipLaunchKernelGGL((pair_kernel<1, 3, MODE>), dim3(grid_q(q.ncand)), dim3(CD_BLOCK), 0, s, q);
+}
+
+// Per-workgroup partials of both query sets folded into one value (kind 0 sum, 1 min).
+int fold_both(QueryArgs& qp, QueryArgs& qe, int mode, devsort::Temp& tmp, hipStream_t s, double init, double* out) {
+  const int gp = qp.ncand ? grid_q(qp.ncand) : 0, ge = qe.ncand ? grid_q(qe.ncand) : 0;
+  double* part = tmp.get<double>((size_t)gp + ge + 1);
+  CD_CHECK(tmp.err);
+  qp.part = part;
+  qe.part = part + gp;
+  if (mode == Q_ENERGY) {
+    launch_pairs<Q_ENERGY>(qp, s);
+    launch_pairs<Q_ENERGY>(qe, s);
+  } else {
+    launch_pairs<Q_CCD>(qp, s);
+    launch_pairs<Q_CCD>(qe, s);
+  }
+  *out = init;
+  if (gp + ge) {
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(CD_BLOCK), 0, s, part, gp + ge, mode == Q_CCD ? 1 : 0);
+    CD_CHECK(hipMemcpyAsync(out, part, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  CD_CHECK(hipGetLastError());
+  return 0;
 }
 
 }  // namespace
@@ -729,40 +838,66 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
   QueryArgs qp{}, qe{};
   int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
   if (e) return e;
-  const int np = S.np, ne = S.ne;
-  int32_t* cnt = tmp.get<int32_t>((size_t)np + ne);
-  int32_t* off = tmp.get<int32_t>((size_t)np + ne + 1);
-  CD_CHECK(tmp.err);
-  CD_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ((size_t)np + ne), s));
-  qp.cnt = cnt;
-  qe.cnt = cnt + np;
-  launch_query<Q_COUNT>(qp, s);
-  launch_query<Q_COUNT>(qe, s);
-  CD_CHECK(devsort::prefix(tmp, cnt, off, (long long)np + ne, s));
-  int total = 0;
-  CD_CHECK(hipMemcpyAsync(&total, off + np + ne, sizeof(int), hipMemcpyDeviceToHost, s));
+  e = candidates(qp, qe, tmp, s, err);
+  if (e) return e;
+  // hits per candidate, scanned into output positions
+  int32_t* hoff[2] = {nullptr, nullptr};
+  QueryArgs* qs[2] = {&qp, &qe};
+  for (int k = 0; k < 2; ++k) {
+    QueryArgs& q = *qs[k];
+    if (q.ncand == 0) continue;
+    q.hit = tmp.get<int32_t>(q.ncand);
+    hoff[k] = tmp.get<int32_t>((size_t)q.ncand + 1);
+    CD_CHECK(tmp.err);
+    launch_pairs<Q_COUNT>(q, s);
+    CD_CHECK(devsort::prefix(tmp, q.hit, hoff[k], q.ncand, s));
+  }
+  int m[2] = {0, 0};
+  for (int k = 0; k < 2; ++k)
+    if (hoff[k]) CD_CHECK(hipMemcpyAsync(&m[k], hoff[k] + qs[k]->ncand, sizeof(int), hipMemcpyDeviceToHost, s));
   e = finish(err, s);
   if (e) return e;
-  const int cap = std::max(total, 1);
+  const int total = m[0] + m[1], cap = std::max(total, 1);
   out.type = static_cast<int32_t*>(alloc(CD_TYPE, sizeof(int32_t) * (size_t)cap));
   out.idx = static_cast<int32_t*>(alloc(CD_IDX, 4 * sizeof(int32_t) * (size_t)cap));
   out.eps = static_cast<double*>(alloc(CD_EPS, sizeof(double) * (size_t)cap));
-  int32_t* ord = static_cast<int32_t*>(alloc(CD_ORD, sizeof(int32_t) * (size_t)cap));
-  if (!out.type || !out.idx || !out.eps || !ord) return -1;
-  for (QueryArgs* q : {&qp, &qe}) {
-    q->off = q == &qp ? off : off + np;
-    q->cap = total;
-    q->otype = out.type;
-    q->oidx = out.idx;
-    q->oeps = out.eps;
-    q->oord = ord;
+  if (!out.type || !out.idx || !out.eps) return -1;
+  // point-triangle outputs first (already in (point, triangle) order), then the
+  // edge-edge ones, written to a side buffer and put in (edge, partner) order
+  const int me = std::max(m[1], 1);
+  int32_t* te = tmp.get<int32_t>(me);
+  int32_t* ie = tmp.get<int32_t>(4 * (size_t)me);
+  double* ee = tmp.get<double>(me);
+  uint64_t* key = tmp.get<uint64_t>(me);
+  uint64_t* key_s = tmp.get<uint64_t>(me);
+  int32_t* perm = tmp.get<int32_t>(me);
+  int32_t* perm_s = tmp.get<int32_t>(me);
+  CD_CHECK(tmp.err);
+  if (m[0]) {
+    qp.hoff = hoff[0];
+    qp.out0 = 0;
+    qp.cap = total;
+    qp.otype = out.type;
+    qp.oidx = out.idx;
+    qp.oeps = out.eps;
+    launch_pairs<Q_FILL>(qp, s);
   }
-  if (total) {
-    launch_query<Q_FILL>(qp, s);
-    launch_query<Q_FILL>(qe, s);
+  if (m[1]) {
+    qe.hoff = hoff[1];
+    qe.out0 = 0;
+    qe.cap = m[1];
+    qe.otype = te;
+    qe.oidx = ie;
+    qe.oeps = ee;
+    qe.okey = key;
+    launch_pairs<Q_FILL>(qe, s);
+    hipLaunchKernelGGL(iota32_kernel, dim3(devsort::grid_of(m[1])), dim3(DI_BLOCK), 0, s, m[1], perm);
+    CD_CHECK(devsort::sort_pairs(tmp, key, key_s, perm, perm_s, m[1], 64, s));
+    hipLaunchKernelGGL(gather_kernel, dim3(devsort::grid_of(m[1])), dim3(DI_BLOCK), 0, s, m[1], perm_s, te, ie, m[1],
+                       ee, out.type + m[0], out.idx + m[0], total, out.eps + m[0]);
   }
   CD_CHECK(hipGetLastError());
-  e = finish(err, s);  // also keeps the temporaries alive until the queries are done
+  e = finish(err, s);  // also keeps the temporaries alive until the kernels are done
   if (e) return e;
   out.n = total;
   *arena_needed = tmp.used;
@@ -778,23 +913,15 @@ int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kapp
   QueryArgs qp{}, qe{};
   int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
   if (e) return e;
-  const int gp = (qp.ma && qp.nreg) ? grid_q(qp.ma) : 0, ge = (qe.ma && qe.nreg) ? grid_q(qe.ma) : 0;
-  double* part = tmp.get<double>((size_t)gp + ge + 1);
-  CD_CHECK(tmp.err);
+  e = candidates(qp, qe, tmp, s, err);
+  if (e) return e;
   for (QueryArgs* q : {&qp, &qe}) {
     q->kappa = kappa;
     q->classic = classic;
   }
-  qp.part = part;
-  qe.part = part + gp;
-  launch_query<Q_ENERGY>(qp, s);
-  launch_query<Q_ENERGY>(qe, s);
   double val = 0.0;
-  if (gp + ge) {
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(CD_BLOCK), 0, s, part, gp + ge, 0);
-    CD_CHECK(hipMemcpyAsync(&val, part, sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  CD_CHECK(hipGetLastError());
+  e = fold_both(qp, qe, Q_ENERGY, tmp, s, 0.0, &val);
+  if (e) return e;
   e = finish(err, s);
   if (e) return e;
   *e_out = val;
@@ -811,23 +938,15 @@ int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, 
   QueryArgs qp{}, qe{};
   int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
   if (e) return e;
-  const int gp = (qp.ma && qp.nreg) ? grid_q(qp.ma) : 0, ge = (qe.ma && qe.nreg) ? grid_q(qe.ma) : 0;
-  double* part = tmp.get<double>((size_t)gp + ge + 1);
-  CD_CHECK(tmp.err);
+  e = candidates(qp, qe, tmp, s, err);
+  if (e) return e;
   for (QueryArgs* q : {&qp, &qe}) {
     q->s_ccd = s_ccd;
     q->t_max = t_max;
   }
-  qp.part = part;
-  qe.part = part + gp;
-  launch_query<Q_CCD>(qp, s);
-  launch_query<Q_CCD>(qe, s);
   double t = t_max;
-  if (gp + ge) {
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(CD_BLOCK), 0, s, part, gp + ge, 1);
-    CD_CHECK(hipMemcpyAsync(&t, part, sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  CD_CHECK(hipGetLastError());
+  e = fold_both(qp, qe, Q_CCD, tmp, s, t_max, &t);
+  if (e) return e;
   e = finish(err, s);
   if (e) return e;
   *t_out = std::fmin(t, t_max);

@@ -356,7 +356,7 @@ struct CdOutput {
 };
 // Grow-only buffers of the collision module: sorted cell keys / ids of the
 // triangles and of the edges, and the detected stencils.
-enum { CD_REG_T, CD_REG_T_V, CD_REG_E, CD_REG_E_V, CD_TYPE, CD_IDX, CD_EPS, CD_ORD, CD_COUNT };
+enum { CD_REG_T, CD_REG_T_V, CD_REG_E, CD_REG_E_V, CD_TYPE, CD_IDX, CD_EPS, CD_COUNT };
 using CdAlloc = std::function<void*(int, size_t)>;
 // Contact stencils at X (squared distance below dhat), in the fixed order
 // (point-triangle pairs by (point, triangle), then edge-edge pairs by (edge,
