@@ -193,6 +193,51 @@ def traffic_record(spec, dirs, commands):
     print(json.dumps({"written": out, "bytes_per_launch": rec["bytes_per_launch"]}))
 
 
+VALU_F64 = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64")
+
+
+def valu_record(workload, pmc_dir, command):
+    """Writes profiles/valu_<workload>.json from one rocprofv3 --pmc run of the
+    four FP64 VALU instruction counters: per kernel, the FP64 operations per
+    dispatch, 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions (an
+    upper bound: inactive lanes count), and the kernel's registers, scratch
+    and LDS from the same records."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for fn in files:
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                short = name.replace("void ", "").replace("yasps::(anonymous namespace)::", "").replace("yasps::", "")
+                short = short[:short.index("(")] if "(" in short else short
+                k = per.setdefault(short, {"dispatches": set(), "counts": {c: 0.0 for c in VALU_F64},
+                                           "vgpr": int(r["VGPR_Count"]), "agpr": int(r["Accum_VGPR_Count"]),
+                                           "scratch_bytes": int(r["Scratch_Size"]),
+                                           "lds_bytes": int(r["LDS_Block_Size"]), "grid": int(r["Grid_Size"])})
+                k["dispatches"].add(r["Dispatch_Id"])
+                if r["Counter_Name"] in k["counts"]:
+                    k["counts"][r["Counter_Name"]] += float(r["Counter_Value"])
+    out = {}
+    for name, k in per.items():
+        nd = len(k["dispatches"])
+        c = {n: v / nd for n, v in k["counts"].items()}
+        flops = 64.0 * (c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"] +
+                        2.0 * c["SQ_INSTS_VALU_FMA_F64"])
+        if flops == 0.0:
+            continue
+        out[name] = {"dispatches": nd, "fp64_ops_per_dispatch": flops, "wave_instructions_per_dispatch": c,
+                     "vgpr": k["vgpr"], "agpr": k["agpr"], "scratch_bytes": k["scratch_bytes"],
+                     "lds_bytes": k["lds_bytes"], "grid": k["grid"]}
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"valu_{workload}.json")
+    with open(path, "w") as f:
+        json.dump({"workload": workload, "command": command, "kernels": out}, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"written": path, "kernels": len(out)}))
+
+
 def n_stencils(prob):
     return (prob["tet_idx"].shape[0] + prob["ctype"].shape[0] + len(prob.get("tri_idx", [])) +
             len(prob.get("hinge_idx", [])))
@@ -505,9 +550,16 @@ def main():
     ap.add_argument("--traffic-record", metavar="KERNEL:WORKLOAD:PRECISION",
                     help="summarise four rocprofv3 --pmc runs (--pmc-dirs) into the profiles/ traffic record and "
                          "exit (no GPU use)")
-    ap.add_argument("--pmc-dirs", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
-    ap.add_argument("--pmc-commands", nargs=4, help="the four rocprofv3 commands, recorded with the summary")
+    ap.add_argument("--pmc-dirs", nargs="+", metavar="DIR",
+                    help="counter directories: FETCH, WRITE, COPY_FETCH, COPY_WRITE (--traffic-record) or one "
+                         "(--valu-record)")
+    ap.add_argument("--pmc-commands", nargs="+", help="the rocprofv3 commands, recorded with the summary")
+    ap.add_argument("--valu-record", metavar="WORKLOAD",
+                    help="summarise one rocprofv3 --pmc run of the FP64 VALU counters (--pmc-dirs DIR, "
+                         "--pmc-commands CMD) into profiles/valu_<workload>.json and exit (no GPU use)")
     args = ap.parse_args()
+    if args.valu_record:
+        return valu_record(args.valu_record, args.pmc_dirs[0], args.pmc_commands[0])
     if args.traffic_record:
         return traffic_record(args.traffic_record, args.pmc_dirs, args.pmc_commands)
     if args.gpus != 1:
