@@ -387,15 +387,18 @@ typedef struct {
 yasps_status yasps_set_surface(yasps_ctx* ctx, const yasps_surface* S);
 
 /* Proximity search at positions x (n_rows, 3): every point-triangle and
- * edge-edge pair of the surface (no shared vertex, at least one free vertex)
- * whose squared distance is below dhat becomes one contact stencil, typed by
+ * edge-edge pair of the surface (no shared vertex, at least one free or
+ * affine-body vertex, not all its vertices on one body; a body vertex at
+ * r_1 a_1 + r_2 a_2 + r_3 a_3 + t) whose squared distance is below dhat
+ * becomes one contact stencil, typed by
  * where its closest points lie (point-triangle: face / edge / vertex -> PT /
  * PE / PP; edge-edge: both interiors / one endpoint / two endpoints -> EE / PE
  * / PP; Ericson, Real-Time Collision Detection, 5.1.5 and 5.1.9).  Pairs are
  * not merged, so the barrier sum is IPC's sum over primitive pairs.  The
  * stencils replace the contact set (as yasps_set_contacts with the device
- * index build); order: point-triangle pairs by (point, triangle), then
- * edge-edge pairs by (edge, edge).  *n_contacts (may be NULL) receives their
+ * index build; those that reach a body vertex replace the body contacts, as
+ * yasps_set_body_contacts); order: point-triangle pairs by (point,
+ * triangle), then edge-edge pairs by (edge, edge).  *n_contacts (may be NULL) receives their
  * number.  Errors: YASPS_E_ARG (no surface), YASPS_E_HIP. */
 yasps_status yasps_detect(yasps_ctx* ctx, const double* x, int32_t* n_contacts);
 
@@ -407,19 +410,23 @@ yasps_status yasps_get_detected(yasps_ctx* ctx, int32_t* type, int32_t* idx, dou
 /* Largest conservative step along x + t p, t <= t_max: the minimum over the
  * point-triangle and edge-edge pairs whose swept boxes (inflated by
  * sqrt(dhat) / 2) overlap of additive CCD (Li, Kaufman, Jiang 2021), which
- * stops a pair once its distance falls below s times its start value.
- * x, p: (n_rows, 3) device arrays.  Errors: YASPS_E_ARG, YASPS_E_HIP. */
+ * stops a pair once its distance falls below s times its start value.  A
+ * body vertex moves by the affine map of its body's row motion (linear, so
+ * its trajectory is a straight line).  x, p: (n_rows, 3) device arrays.
+ * Errors: YASPS_E_ARG, YASPS_E_HIP. */
 yasps_status yasps_ccd(yasps_ctx* ctx, const double* x, const double* p, double t_max, double s, double* t_out);
 
 /* One implicit-Euler time step with contact (IPC): x_tilde = x + h v + h^2 g
- * (the problem's h and gravity; the problem's x_tilde is not used), then
+ * (the problem's h and gravity, on the free rows and the bodies' t rows —
+ * M4^-1 of a body's gravity force moves t only; the problem's x_tilde is not
+ * used), then
  * Newton iterations, each: proximity search at x (yasps_detect), projected
  * Newton direction p by PCG, stop when max_v |p_v| / h < tol, step bound by
  * CCD, Armijo backtracking on E with the contacts found at each trial; at the
  * end v = (x - x_start) / h.  x and v (n_rows, 3) device arrays, updated in
- * place.  `prm` may be NULL for defaults.  Needs the dynamic form, a surface,
- * and no affine bodies.  Errors: YASPS_E_ARG, YASPS_E_UNIMPL (bodies),
- * YASPS_E_NOCONV (max_newton reached; x, v hold the last iterate),
+ * place.  `prm` may be NULL for defaults.  Needs the dynamic form and a
+ * surface.  Errors: YASPS_E_ARG, YASPS_E_NOCONV (max_newton reached; x, v
+ * hold the last iterate),
  * YASPS_E_LINESEARCH, YASPS_E_BREAKDOWN, YASPS_E_HIP. */
 yasps_status yasps_frame(yasps_ctx* ctx, double* x, double* v, const yasps_frame_params* prm,
                          yasps_frame_info* info);

@@ -165,24 +165,40 @@ def _overlap(lo_a, hi_a, lo_b, hi_b):
 
 class Surface:
     """Collision surface: point ids, edges (ne, 2), triangles (nt, 3) in the
-    vertex id space (free ids < n_free, fixed ids after), optional squared rest
-    edge lengths (the EE mollifier's thresholds 1e-3 |a|^2 |b|^2)."""
+    vertex id space (free ids < n_free, then n_fixed fixed ids, then affine-body
+    vertices with body_of[k]), optional squared rest edge lengths (the EE
+    mollifier's thresholds 1e-3 |a|^2 |b|^2).  A pair needs a movable vertex
+    (free or on a body) and is skipped when all its vertices lie on one body."""
 
-    def __init__(self, points, edges, tris, n_free, edge_rest_len2=None):
+    def __init__(self, points, edges, tris, n_free, edge_rest_len2=None, n_fixed=None, body_of=None):
         self.points = np.asarray(points, np.int64)
         self.edges = np.asarray(edges, np.int64).reshape(-1, 2)
         self.tris = np.asarray(tris, np.int64).reshape(-1, 3)
         self.n_free = int(n_free)
         self.len2 = None if edge_rest_len2 is None else np.asarray(edge_rest_len2, np.float64)
+        self.base = None if n_fixed is None else int(n_free) + int(n_fixed)
+        self.body_of = None if body_of is None else np.asarray(body_of, np.int64)
+
+    def _keep(self, ids):
+        """The pair of these vertex ids moves, and not as one body."""
+        ids = np.asarray(ids, np.int64)
+        if self.base is None:
+            return bool((ids < self.n_free).any())
+        mov = (ids < self.n_free) | (ids >= self.base)
+        if not mov.any():
+            return False
+        if (ids >= self.base).all():
+            b = self.body_of[ids - self.base]
+            if (b == b[0]).all():
+                return False
+        return True
 
     def _pt_candidates(self, lo_p, hi_p, lo_t, hi_t):
         m = _overlap(lo_p, hi_p, lo_t, hi_t)
         out = []
         for i, j in zip(*np.nonzero(m)):  # (point, triangle) in ascending order
             v, tri = int(self.points[i]), self.tris[j]
-            if v in tri:
-                continue
-            if v >= self.n_free and (tri >= self.n_free).all():
+            if v in tri or not self._keep([v, *tri]):
                 continue
             out.append((int(i), int(j)))
         return out
@@ -192,9 +208,7 @@ class Surface:
         out = []
         for i, j in zip(*np.nonzero(np.triu(m, 1))):
             ea, eb = self.edges[i], self.edges[j]
-            if ea[0] in eb or ea[1] in eb:
-                continue
-            if (ea >= self.n_free).all() and (eb >= self.n_free).all():
+            if ea[0] in eb or ea[1] in eb or not self._keep([*ea, *eb]):
                 continue
             out.append((int(i), int(j)))
         return out

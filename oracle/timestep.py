@@ -16,7 +16,13 @@ line-search trial (``collision.Surface.detect``) and the step bounded by CCD
             (E with the contacts at the trial positions); x += alpha p
     v = (x - x_start) / h
 
-Only free vertices move; fixed vertices keep their positions.
+Only free vertices and affine bodies move; fixed vertices keep their
+positions.  With affine bodies (``affine.AffineOracle``) x holds the rows of
+degrees of freedom (free vertices, then a_1, a_2, a_3, t per body); a body
+vertex sits at r_1 a_1 + r_2 a_2 + r_3 a_3 + t (summed left to right), its
+displacement under a row motion is the same map of the motion, gravity moves
+the t rows only (M4^-1 of a body's gravity force is e_4 (x) g), and the
+stencils that reach a body vertex form the body-contact part.
 """
 from __future__ import annotations
 
@@ -24,6 +30,7 @@ import math
 
 import numpy as np
 
+from . import affine as oaff
 from . import assemble as oasm
 from . import pcg as opcg
 
@@ -43,16 +50,47 @@ class Stepper:
         self.x_fixed = np.asarray(prob["x_fixed"], np.float64).reshape(-1, 3)
         self.dhat = float(prob["dhat"])
         self.g = np.asarray(gravity, np.float64)
+        self.nb = int(prob.get("n_bodies", 0))
+        self.rows = self.n + 4 * self.nb
+        if self.nb:
+            self.body_of = np.asarray(prob["abd_body"], np.int64)
+            self.rest = np.asarray(prob["abd_rest"], np.float64).reshape(-1, 3)
+
+    def _body_points(self, X):
+        """r_1 a_1 + r_2 a_2 + r_3 a_3 + t of every body vertex from rows X."""
+        q = X[self.n:].reshape(self.nb, 4, 3)[self.body_of]
+        r = self.rest
+        return r[:, 0:1] * q[:, 0] + r[:, 1:2] * q[:, 1] + r[:, 2:3] * q[:, 2] + q[:, 3]
 
     def xall(self, x):
-        return np.concatenate([np.asarray(x, np.float64).reshape(self.n, 3), self.x_fixed])
+        """Positions of every vertex id (free, fixed, body vertices)."""
+        X = np.asarray(x, np.float64).reshape(self.rows, 3)
+        parts = [X[:self.n], self.x_fixed]
+        if self.nb:
+            parts.append(self._body_points(X))
+        return np.concatenate(parts)
+
+    def pall(self, p):
+        """Displacements of every vertex id under the row motion p."""
+        P = np.asarray(p, np.float64).reshape(self.rows, 3)
+        parts = [P[:self.n], np.zeros_like(self.x_fixed)]
+        if self.nb:
+            parts.append(self._body_points(P))
+        return np.concatenate(parts)
 
     def oracle_at(self, x, x_tilde):
         """The oracle with the contacts found at positions x."""
         ct, ci, eps = self.surface.detect(self.xall(x), self.dhat)
         q = dict(self.p)
-        q.update(x_tilde=x_tilde, ctype=ct, cidx=ci, ee_eps=eps)
-        return oasm.Oracle(q, classic=self.classic), len(ct)
+        if not self.nb:
+            q.update(x_tilde=x_tilde, ctype=ct, cidx=ci, ee_eps=eps)
+            return oasm.Oracle(q, classic=self.classic), len(ct)
+        body = (ci >= self.n + self.x_fixed.shape[0]).any(axis=1)
+        e = eps if eps is not None else np.zeros(len(ct))
+        q.update(x_tilde=x_tilde[:self.n], body_qt=x_tilde[self.n:].reshape(self.nb, 4, 3),
+                 ctype=ct[~body], cidx=ci[~body], ee_eps=e[~body] if eps is not None else None,
+                 bctype=ct[body], bcidx=ci[body], bee_eps=e[body] if eps is not None else None)
+        return oaff.AffineOracle(q, classic=self.classic), len(ct)
 
     def energy(self, x, x_tilde):
         o, _ = self.oracle_at(x, x_tilde)
@@ -61,9 +99,12 @@ class Stepper:
     def frame(self, x, v, h=None, tol=1e-2, max_newton=50, rtol=1e-8, armijo=1e-4, max_halvings=40, s_ccd=0.1):
         """One time step from (x, v); returns (x1, v1, info)."""
         h = float(self.p["h"]) if h is None else h
-        x = np.asarray(x, np.float64).reshape(self.n, 3).copy()
-        v = np.asarray(v, np.float64).reshape(self.n, 3)
-        x_tilde = x + h * v + h * h * self.g[None, :]
+        x = np.asarray(x, np.float64).reshape(self.rows, 3).copy()
+        v = np.asarray(v, np.float64).reshape(self.rows, 3)
+        G = np.zeros((self.rows, 3))
+        G[:self.n] = self.g
+        G[self.n + 3::4] = self.g  # the bodies' t rows
+        x_tilde = x + h * v + h * h * G
         x_start = x.copy()
         info = dict(newton_iters=0, cg_iters=0, alphas=[], ccd=[], contacts=[], trials=[], energies=[])
         for _ in range(max_newton):
@@ -77,12 +118,11 @@ class Stepper:
             info["cg_iters"] += it
             info["contacts"].append(nc)
             info["energies"].append(ev["E"])
-            p = p.reshape(self.n, 3)
+            p = p.reshape(self.rows, 3)
             if np.sqrt((p * p).sum(axis=1)).max() / h < tol:
                 break
             info["newton_iters"] += 1
-            pall = np.concatenate([p, np.zeros_like(self.x_fixed)])
-            alpha = self.surface.ccd(self.xall(x), pall, 1.0, s_ccd, self.dhat)
+            alpha = self.surface.ccd(self.xall(x), self.pall(p), 1.0, s_ccd, self.dhat)
             info["ccd"].append(alpha)
             E0, gp = ev["E"], float(g @ p.ravel())
             for k in range(max_halvings + 1):

@@ -185,6 +185,7 @@ struct yasps_ctx {
   std::vector<void*> surf_allocs;
   GrowBuf cd_buf[CD_COUNT];
   CdOutput detected;             // the last proximity search's stencils (device, in cd_buf)
+  GrowBuf cd_split[6];           // with bodies: the stencils without / with body vertices (type, idx, eps)
   GrowBuf xt_frame, xs_frame;    // a frame's inertial target and start positions
 
   // a second stream for the contact kernels, which run beside the elastic ones
@@ -579,6 +580,7 @@ void yasps_destroy(yasps_ctx* ctx) {
     for (int k = 0; k < PL_COUNT; ++k) set[k].release();
   for (GrowBuf& b : ctx->di_buf) b.release();
   for (GrowBuf& b : ctx->cd_buf) b.release();
+  for (GrowBuf& b : ctx->cd_split) b.release();
   free_list(ctx->surf_allocs);
   for (GrowBuf* b : {&ctx->xt_frame, &ctx->xs_frame}) b->release();
   for (GrowBuf* b : {&ctx->stg_d_buf, &ctx->gstg_d_buf, &ctx->vals_d_buf, &ctx->d_c_buf, &ctx->pcg_work}) b->release();
@@ -1603,8 +1605,11 @@ CdAlloc cd_alloc(yasps_ctx* c) {
 CdPositions cd_positions(const yasps_ctx* c, const double* x, const double* p = nullptr, double t = 0.0) {
   CdPositions X{};
   X.nv = c->nv;
+  X.nfix = c->P.n_fixed;
   X.x = x;
   X.xf = c->P.x_fixed;
+  X.body_of = c->nbv ? c->P.body_of : nullptr;
+  X.body_rest = c->nbv ? c->P.body_rest : nullptr;
   X.p = p;
   X.t = t;
   return X;
@@ -1622,15 +1627,63 @@ yasps_status detect(yasps_ctx* c, const double* x, int32_t* n_out) {
                                           "position, or the cell size far below the primitives)")
                    : fail(c, YASPS_E_HIP, "proximity search");
   }
-  yasps_contacts C{c->detected.n, c->detected.type, c->detected.idx, c->surf.len2 ? c->detected.eps : nullptr};
+  if (n_out) *n_out = c->detected.n;
+  if (c->nb == 0) {
+    yasps_contacts C{c->detected.n, c->detected.type, c->detected.idx, c->surf.len2 ? c->detected.eps : nullptr};
+    clear_contacts(c);
+    yasps_status s = set_contacts_device(c, &C);
+    if (s) clear_contacts(c);
+    return s;
+  }
+  // with bodies: the stencils that reach a body vertex form the body-contact
+  // part (host build), the others the dynamic part; each keeps the search's order
+  const int n = c->detected.n, base = c->nv + c->P.n_fixed;
+  std::vector<int32_t> ty(n), idx((size_t)4 * n);
+  std::vector<double> eps(n);
+  if (n) {
+    HIPCHK(c, hipMemcpy(ty.data(), c->detected.type, (size_t)n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(idx.data(), c->detected.idx, idx.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(eps.data(), c->detected.eps, (size_t)n * 8, hipMemcpyDeviceToHost));
+  }
+  std::vector<int> sel[2];
+  for (int k = 0; k < n; ++k) {
+    bool body = false;
+    for (int a = 0; a < 4; ++a) body |= idx[(size_t)a * n + k] >= base;
+    sel[body ? 1 : 0].push_back(k);
+  }
+  yasps_contacts C[2];
+  for (int part = 0; part < 2; ++part) {
+    const int m = (int)sel[part].size();
+    std::vector<int32_t> t(m), i((size_t)4 * m);
+    std::vector<double> e(m);
+    for (int j = 0; j < m; ++j) {
+      const int k = sel[part][j];
+      t[j] = ty[k];
+      e[j] = eps[k];
+      for (int a = 0; a < 4; ++a) i[(size_t)a * m + j] = idx[(size_t)a * n + k];
+    }
+    GrowBuf* b = c->cd_split + 3 * part;
+    int32_t* dt = static_cast<int32_t*>(b[0].ensure(4 * (size_t)std::max(m, 1)));
+    int32_t* di = static_cast<int32_t*>(b[1].ensure(16 * (size_t)std::max(m, 1)));
+    double* de = static_cast<double*>(b[2].ensure(8 * (size_t)std::max(m, 1)));
+    if (!dt || !di || !de) return fail(c, YASPS_E_HIP, "hipMalloc of the split contact lists");
+    if (m) {
+      HIPCHK(c, hipMemcpy(dt, t.data(), (size_t)m * 4, hipMemcpyHostToDevice));
+      HIPCHK(c, hipMemcpy(di, i.data(), i.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(c, hipMemcpy(de, e.data(), (size_t)m * 8, hipMemcpyHostToDevice));
+    }
+    C[part] = yasps_contacts{m, dt, di, c->surf.len2 ? de : nullptr};
+  }
   clear_contacts(c);
-  yasps_status s = set_contacts_device(c, &C);
+  yasps_status s = set_contacts_device(c, &C[0]);
   if (s) {
     clear_contacts(c);
     return s;
   }
-  if (n_out) *n_out = c->detected.n;
-  return YASPS_OK;
+  clear_body_contacts(c);
+  s = set_body_contacts_host(c, &C[1]);
+  if (s) clear_body_contacts(c);
+  return s;
 }
 
 yasps_status ccd(yasps_ctx* c, const double* x, const double* p, double t_max, double s_ccd, double* t_out) {
@@ -1657,6 +1710,7 @@ yasps_status frame_energy(yasps_ctx* c, const double* x, double* E) {
     launch_hinge_energy(hinge_args(c, x, g, hoff), c->stream);
     hoff += grid_of(g.end - g.begin, EVAL_BLOCK);
   }
+  launch_body_energy(body_args(c, x), c->stream);  // the bodies' inertia and orthogonality partials
   c->prof.end();
   HIPCHK(c, hipGetLastError());
   const int kinds[2] = {0, 0};
@@ -1688,7 +1742,7 @@ yasps_status yasps_set_surface(yasps_ctx* c, const yasps_surface* S) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->has_surface = false;
   free_list(c->surf_allocs);
-  const int nall = c->P.n_free + c->P.n_fixed;
+  const int nall = c->P.n_free + c->P.n_fixed + c->nbv;
   std::vector<int32_t> pts(S->n_points), ed((size_t)2 * S->n_edges), tr((size_t)3 * S->n_tris);
   if (S->n_points) HIPCHK(c, hipMemcpy(pts.data(), S->points, pts.size() * 4, hipMemcpyDeviceToHost));
   if (S->n_edges) HIPCHK(c, hipMemcpy(ed.data(), S->edges, ed.size() * 4, hipMemcpyDeviceToHost));
@@ -1763,14 +1817,13 @@ yasps_status yasps_frame(yasps_ctx* c, double* x, double* v, const yasps_frame_p
     return fail(c, YASPS_E_ARG, "need tol > 0, max_newton >= 1, 0 < ccd_s < 1");
   if (c->P.is_static) return fail(c, YASPS_E_ARG, "time stepping needs the dynamic form (is_static = 0)");
   if (!c->has_surface) return fail(c, YASPS_E_ARG, "no collision surface (yasps_set_surface)");
-  if (c->nb) return fail(c, YASPS_E_UNIMPL, "time stepping with affine bodies is not supported");
   HIPCHK(c, hipSetDevice(c->device));
   const double h = c->P.h;
-  const size_t bytes = 3 * (size_t)c->nv * sizeof(double);
+  const size_t bytes = 3 * (size_t)c->n * sizeof(double);
   double* xt = static_cast<double*>(c->xt_frame.ensure(std::max<size_t>(bytes, 8)));
   double* xs = static_cast<double*>(c->xs_frame.ensure(std::max<size_t>(bytes, 8)));
   if (!xt || !xs) return fail(c, YASPS_E_HIP, "hipMalloc of the frame buffers");
-  launch_frame_tilde(c->nv, x, v, h, c->P.gravity, xt, c->stream);
+  launch_frame_tilde(c->nv, c->n, x, v, h, c->P.gravity, xt, c->stream);
   HIPCHK(c, hipMemcpyAsync(xs, x, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipGetLastError());
   // the frame's inertial target replaces the problem's for its duration
@@ -1858,7 +1911,7 @@ yasps_status yasps_frame(yasps_ctx* c, double* x, double* v, const yasps_frame_p
     (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
     fi.ms_linesearch += ms;
   }
-  launch_frame_velocity(c->nv, x, xs, h, v, c->stream);
+  launch_frame_velocity(c->n, x, xs, h, v, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (info) *info = fi;

@@ -5,7 +5,8 @@
 // (section "Limitations"; its examples use GIPC's, timed as "CCD+CD+
 // LargestStep").  The definitions here are Incremental Potential Contact's:
 // every point-triangle and edge-edge pair of the collision surface (no shared
-// vertex, at least one free vertex) closer than sqrt(dhat) contributes one
+// vertex, at least one free or affine-body vertex, not all of one body)
+// closer than sqrt(dhat) contributes one
 // barrier stencil, typed by where its closest points lie (point-triangle: face
 // / edge / vertex -> PT / PE / PP; edge-edge: interiors / one endpoint / two
 // endpoints -> EE / PE / PP), found with the textbook closest-feature
@@ -159,14 +160,31 @@ YHD double segment_segment(const double p1[3], const double q1[3], const double 
   return dist2(c1, c2);
 }
 
+// An affine body's vertex from its body's rows q = (a_1, a_2, a_3, t):
+// r_1 a_1 + r_2 a_2 + r_3 a_3 + t, summed left to right.
+YDEV void body_point(const CdPositions& X, int k, const double* rows, double q[3]) {
+  const double* r = X.body_rest + 3 * (size_t)k;
+  const double* a = rows + 3 * ((size_t)X.nv + 4 * (size_t)X.body_of[k]);
+  for (int i = 0; i < 3; ++i) q[i] = r[0] * a[i] + r[1] * a[3 + i] + r[2] * a[6 + i] + a[9 + i];
+}
 YDEV void vpos(const CdPositions& X, int v, double q[3]) {
+  if (v >= X.nv + X.nfix) {
+    body_point(X, v - X.nv - X.nfix, X.x, q);
+    return;
+  }
   const double* s = v < X.nv ? X.x + 3 * (size_t)v : X.xf + 3 * (size_t)(v - X.nv);
   q[0] = s[0];
   q[1] = s[1];
   q[2] = s[2];
 }
-YDEV void vmove(const CdPositions& X, int v, double d[3]) {  // the vertex's motion (0 for fixed)
-  if (X.p && v < X.nv) {
+YDEV bool movable(const CdPositions& X, int v) { return v < X.nv || v >= X.nv + X.nfix; }
+YDEV int body_id(const CdPositions& X, int v) { return v >= X.nv + X.nfix ? X.body_of[v - X.nv - X.nfix] : -1; }
+// The vertex's displacement under the row motion p (0 for fixed; for a body
+// vertex the same affine map of the body's row motion, which is linear).
+YDEV void vmove(const CdPositions& X, int v, double d[3]) {
+  if (X.p && v >= X.nv + X.nfix) {
+    body_point(X, v - X.nv - X.nfix, X.p, d);
+  } else if (X.p && v < X.nv) {
     const double* s = X.p + 3 * (size_t)v;
     d[0] = s[0];
     d[1] = s[1];
@@ -543,13 +561,20 @@ __global__ __launch_bounds__(CD_BLOCK) void pair_kernel(QueryArgs q) {
              cell_of(fmax(lo0[2], loR[2]), q.cell) == z;
     }
     if (take) {
-      bool shared = false, free_a = false, free_b = false;
+      // no shared vertex, something movable (free or body vertices), and not
+      // all the vertices of one affine body (its surface keeps its shape)
+      bool shared = false, mov = false, one_body = true;
+      const int b0 = body_id(q.X, ia[0]);
       for (int a = 0; a < KA; ++a) {
-        free_a |= ia[a] < q.X.nv;
+        mov |= movable(q.X, ia[a]);
+        one_body &= b0 >= 0 && body_id(q.X, ia[a]) == b0;
         for (int b = 0; b < KB; ++b) shared |= ia[a] == ib[b];
       }
-      for (int b = 0; b < KB; ++b) free_b |= ib[b] < q.X.nv;
-      take = !shared && (free_a || free_b);
+      for (int b = 0; b < KB; ++b) {
+        mov |= movable(q.X, ib[b]);
+        one_body &= b0 >= 0 && body_id(q.X, ib[b]) == b0;
+      }
+      take = !shared && mov && !one_body;
     }
     if (take) {
       if constexpr (MODE == Q_CCD) {
@@ -627,13 +652,16 @@ __global__ __launch_bounds__(CD_BLOCK) void fold_kernel(double* part, int m, int
   if (threadIdx.x == 0) part[0] = r;
 }
 
-// x_tilde = x + h v + h^2 g, and v = (x - x_start) / h, over the free rows
-__global__ void frame_tilde_kernel(int n3, const double* __restrict__ x, const double* __restrict__ v, double h,
-                                   double g0, double g1, double g2, double* __restrict__ xt) {
+// x_tilde = x + h v + h^2 g over the rows: the free rows and each body's t
+// row take gravity, the bodies' a rows none (the generalised gravity force of
+// a body is M4 e_4 (x) g, so M4^-1 of it moves t only); and v = (x - x_start) / h.
+__global__ void frame_tilde_kernel(int nv, int n3, const double* __restrict__ x, const double* __restrict__ v,
+                                   double h, double g0, double g1, double g2, double* __restrict__ xt) {
   const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i >= n3) return;
-  const int c = i % 3;
-  const double g = c == 0 ? g0 : (c == 1 ? g1 : g2);
+  const int row = i / 3, c = i % 3;
+  const bool grav = row < nv || (row - nv) % 4 == 3;
+  const double g = grav ? (c == 0 ? g0 : (c == 1 ? g1 : g2)) : 0.0;
   xt[i] = x[i] + h * v[i] + h * h * g;
 }
 __global__ void frame_velocity_kernel(int n3, const double* __restrict__ x, const double* __restrict__ xs, double h,
@@ -713,10 +741,10 @@ QueryArgs query_args(const CdSurface& S, const CdPositions& X, bool ee, const Re
 
 }  // namespace
 
-void launch_frame_tilde(int nv, const double* x, const double* v, double h, const double g[3], double* xt,
+void launch_frame_tilde(int nv, int n, const double* x, const double* v, double h, const double g[3], double* xt,
                         hipStream_t s) {
-  if (nv == 0) return;
-  hipLaunchKernelGGL(frame_tilde_kernel, dim3(devsort::grid_of(3ll * nv)), dim3(DI_BLOCK), 0, s, 3 * nv, x, v, h,
+  if (n == 0) return;
+  hipLaunchKernelGGL(frame_tilde_kernel, dim3(devsort::grid_of(3ll * n)), dim3(DI_BLOCK), 0, s, nv, 3 * n, x, v, h,
                      g[0], g[1], g[2], xt);
 }
 

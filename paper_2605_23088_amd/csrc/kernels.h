@@ -343,9 +343,12 @@ struct CdSurface {
 };
 struct CdPositions {
   int nv;                  // free vertices (ids below nv are rows of x)
-  const double* x;         // (nv, 3) free positions
+  int nfix;                // fixed vertices (ids nv .. nv + nfix); body vertices follow
+  const double* x;         // rows of degrees of freedom: free positions, then a_1, a_2, a_3, t per body
   const double* xf;        // fixed positions
-  const double* p;         // (nv, 3) motion of the free vertices (CCD: swept boxes over x + t p) or null
+  const int32_t* body_of;  // [body vertices] body of each, or null without bodies
+  const double* body_rest; // [body vertices][3] rest positions r (p = A r + t)
+  const double* p;         // motion of the rows (CCD: swept boxes over x + t p) or null
   double t;
 };
 struct CdOutput {
@@ -371,9 +374,10 @@ int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kapp
 // candidate pairs of the swept boxes).
 int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, double s_ccd, const CdAlloc& alloc,
            void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* t_out);
-// Time stepping: x_tilde = x + h v + h^2 g and v = (x - x_start) / h over the free rows.
-void launch_frame_tilde(int nv, const double* x, const double* v, double h, const double g[3], double* xt,
+// Time stepping: x_tilde = x + h v + h^2 g over the n rows (gravity on the free
+// rows and the bodies' t rows) and v = (x - x_start) / h.
+void launch_frame_tilde(int nv, int n, const double* x, const double* v, double h, const double g[3], double* xt,
                         hipStream_t s);
-void launch_frame_velocity(int nv, const double* x, const double* xs, double h, double* v, hipStream_t s);
+void launch_frame_velocity(int n, const double* x, const double* xs, double h, double* v, hipStream_t s);
 
 }  // namespace yasps

@@ -959,3 +959,56 @@ def drop_scene(seed=51, nx=3, ny=3, nz=2, a=0.1, gap=0.012, v0=-1.0, ground_cell
     p.update(v0=v, surf_points=points.astype(np.int32), surf_edges=edges.astype(np.int32),
              surf_tris=tris.astype(np.int32), surf_len2=len2, cell=max(a, ground_size / ground_cells) * 1.01)
     return p
+
+
+def drop_body_scene(seed=52, nx=3, ny=3, nz=2, a=0.1, bc=2, ab=0.1, gap=0.012, v0=-1.0, ground_cells=5,
+                    ground_size=0.6, ground_angle=0.37, h=1e-2, E=1e5, nu=0.4, rho=1000.0, kappa=1e3, dhat=1e-4,
+                    k_orth=1e5, jitter=1e-3):
+    """The drop scene with an affine cube stacked on the free block: the cube
+    (bc^3 cells of side ab, its boundary vertices as body vertices with rest
+    positions where they start, A = I, t = 0) a gap above the block's top, the
+    block a gap above the ground, both falling at v0.  Body mass rho (bc ab)^3
+    spread evenly over its vertices (M4 = sum m w w^T, w = (r, 1)),
+    orthogonality stiffness k_orth.  The collision surface adds the cube's
+    boundary triangles, edges and points (body vertex ids n_free + n_fixed + k).
+    Rows: X0 = [free x0; a_1, a_2, a_3, t], V0 likewise."""
+    p = drop_scene(seed=seed, nx=nx, ny=ny, nz=nz, a=a, gap=gap, v0=v0, ground_cells=ground_cells,
+                   ground_size=ground_size, ground_angle=ground_angle, h=h, E=E, nu=nu, rho=rho, kappa=kappa,
+                   dhat=dhat, jitter=jitter)
+    rng = np.random.default_rng(seed + 1)
+    n, nfix = p["n_free"], p["x_fixed"].shape[0]
+    top = p["x0"][:, 2].max()
+    # the cube, centred over the block, rotated a little about z (no parallel edges with the block)
+    C = grid_vertices(bc, bc, bc, ab)
+    C = C - C.mean(axis=0)
+    th = 0.21
+    R = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    C = C @ R.T + np.array([0.5 * nx * a, 0.5 * ny * a, top + gap + 0.5 * bc * ab])
+    C = C + rng.normal(0.0, jitter * ab, C.shape)
+    ctets = kuhn_tets(bc, bc, bc)
+    bt, be, bp = boundary_surface(ctets)
+    local = -np.ones(C.shape[0], np.int64)
+    local[bp] = np.arange(bp.size)
+    rest = C[bp]
+    nbv = rest.shape[0]
+    base = n + nfix
+    m = rho * (bc * ab) ** 3 / nbv
+    w = np.concatenate([rest, np.ones((nbv, 1))], 1)
+    M4 = (m * (w.T @ w))[None]
+    q0 = np.zeros((1, 4, 3))
+    q0[0, :3] = np.eye(3)
+    v_rows = np.zeros((1, 4, 3))
+    v_rows[0, 3, 2] = v0
+    tris = np.concatenate([p["surf_tris"], local[bt] + base])
+    edges = np.concatenate([p["surf_edges"], local[be] + base])
+    points = np.concatenate([p["surf_points"], np.arange(nbv) + base])
+    xa = np.concatenate([p["x0"], p["x_fixed"], rest])
+    len2 = ((xa[edges[:, 1]] - xa[edges[:, 0]]) ** 2).sum(1)
+    qt = q0.copy()
+    p.update(n_bodies=1, body_q0=q0, body_qt=qt, body_M4=M4, body_k=np.array([k_orth]),
+             abd_body=np.zeros(nbv, np.int64), abd_rest=rest, bctype=np.zeros(0, np.int32),
+             bcidx=np.zeros((0, 4), np.int32), X0=np.concatenate([p["x0"], q0.reshape(-1, 3)]),
+             V0=np.concatenate([p["v0"], v_rows.reshape(-1, 3)]), surf_points=points.astype(np.int32),
+             surf_edges=edges.astype(np.int32), surf_tris=tris.astype(np.int32), surf_len2=len2,
+             name=f"dropbody{nx}x{ny}x{nz}")
+    return p

@@ -111,3 +111,31 @@ def test_frame_errors():
     with pytest.raises(YaspsError) as e:
         g.set_surface(p["surf_points"], np.array([[0, 0]]), p["surf_tris"], None, 0.1)
     assert e.value.status == E_ARG
+
+
+def test_frames_with_an_affine_body_match_oracle():
+    """An affine cube dropped on the falling block: body vertices in the
+    proximity search and the CCD (their motion the affine map of the rows'),
+    body contacts in the third matrix part, gravity on the t rows."""
+    from paper_2605_23088_amd.yasps import Yasps
+    p = synth.drop_body_scene()
+    S = col.Surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["n_free"], p["surf_len2"],
+                    p["x_fixed"].shape[0], p["abd_body"])
+    st = ts.Stepper(p, S)
+    g = Yasps(p, contacts=False)
+    g.set_surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["surf_len2"], p["cell"])
+    xo, vo = p["X0"], p["V0"]
+    x, v = dev(p["X0"]), dev(p["V0"])
+    for f in range(3):
+        xo, vo, io = st.frame(xo, vo, rtol=1e-10)
+        info = g.frame(x, v, rtol=1e-10)
+        assert info["converged"] == 1
+        assert info["newton_iters"] == io["newton_iters"], (f, info, io["newton_iters"])
+        assert info["n_contacts_max"] == max(io["contacts"])
+        assert np.abs(x.cpu().numpy() - xo).max() <= 1e-9, f
+        assert np.abs(v.cpu().numpy() - vo).max() <= 1e-7, f
+    # the cube rests on the block: contacts between body and free vertices exist
+    xa = st.xall(x.cpu().numpy())
+    ct, ci, _ = S.detect(xa, p["dhat"])
+    base = p["n_free"] + p["x_fixed"].shape[0]
+    assert ((ci >= base).any(axis=1) & ((ci >= 0) & (ci < p["n_free"])).any(axis=1)).any()
