@@ -252,131 +252,218 @@ YHD bool diff_vars(const double (&xv)[4][3], double (&u)[Topo<TYPE>::NU][3]) {
   return ok;
 }
 
-// PSD projection of the 9 x 9 Hessian A of a point-triangle stencil whose
-// point is fixed (free vertices t0, t1, t2).  The plane distance does not
-// change when the triangle's vertices move inside their plane, so in the
-// orthonormal frame F = [t1 t2 n] of the plane (applied to every vertex) the
-// Hessian is M = [[0, B^T], [B, C]]: a zero 6 x 6 in-plane block, the 3 x 6
-// normal-by-in-plane block B and the 3 x 3 normal block C.  With the
-// Householder factorisation B^T = Q R (Q 6 x 3 orthonormal), M = W M6 W^T,
-// W = diag(Q, I3), M6 = [[0, R], [R^T, C]], and M annihilates the in-plane
-// directions orthogonal to Q; so Proj(M) = W Proj(M6) W^T, a 6 x 6 instead of
-// a 9 x 9 eigenproblem.  The computed in-plane block is zero up to rounding
-// and is dropped.  F's columns are (t1, t2, n) as rows of Fr.
-YHD void project_pt_fixed_point(Sym<9, double>& A, const double (&Fr)[3][3]) {
-  // frame coordinates: P'(Ia, Jb) = sum_ij Fr[a][i] A(3I+i, 3J+j) Fr[b][j]
-  double Bt[6][3];  // Bt[2I+a][J] = P'(I a, J n), a in {t1, t2}
-  double Cn[3][3];  // P'(I n, J n)
+// Rows (t/|t|, n/|n| x t/|t|, n/|n|) for t orthogonal to n; the identity
+// when either vanishes (the stencils below then have a distance that is zero
+// or not finite, hence a zero Hessian, which every frame projects to zero).
+YHD void orthonormal_frame(const double (&t)[3], const double (&n)[3], double (&Fr)[3][3]) {
+  const double lt = sqrt(dot(t, t)), ln = sqrt(dot(n, n));
+  const bool ok = lt > 0.0 && ln > 0.0 && finite(lt) && finite(ln);
+  const double it = ok ? 1.0 / lt : 0.0, in = ok ? 1.0 / ln : 0.0;
 #pragma unroll
-  for (int I = 0; I < 3; ++I)
+  for (int i = 0; i < 3; ++i) {
+    Fr[0][i] = ok ? t[i] * it : (i == 0 ? 1.0 : 0.0);
+    Fr[2][i] = ok ? n[i] * in : (i == 2 ? 1.0 : 0.0);
+  }
+  double c[3];
+  cross(Fr[2], Fr[0], c);
 #pragma unroll
-    for (int J = 0; J < 3; ++J) {
-      double T[3][3];  // Fr A_IJ
+  for (int i = 0; i < 3; ++i) Fr[1][i] = c[i];
+}
+
+// Closed-form PSD projection of a symmetric 2 x 2 matrix.  Its eigenvalues are
+// mid +- r (mid = (a + c)/2, r = sqrt(((a - c)/2)^2 + b^2)); with one of each
+// sign, A - l_- I is (l_+ - l_-) times the projector onto the positive
+// eigenvector, so Proj(A) = l_+ (A - l_- I) / (l_+ - l_-).
+YHD void psd_project2(Sym<2, double>& A) {
+  const double a = A(0, 0), b = A(0, 1), c = A(1, 1);
+  const double h = 0.5 * (a - c), mid = 0.5 * (a + c);
+  const double r = sqrt(fma(h, h, b * b));
+  const double lp = mid + r, lm = mid - r;
+  const bool keep = lm >= 0.0;  // both eigenvalues non-negative
+  const double f = lp > 0.0 ? lp / (r > 0.0 ? 2.0 * r : 1.0) : 0.0;
+  const double sc = keep ? 1.0 : f, sh = keep ? 0.0 : lm;
+  A(0, 0) = sc * (a - sh);
+  A(0, 1) = sc * b;
+  A(1, 1) = sc * (c - sh);
+}
+
+template <int N>
+YHD void psd_small(Sym<N, double>& A) {
+  if constexpr (N == 2)
+    psd_project2(A);
+  else
+    psd_project<N, double>(A);
+}
+
+// Frame coordinates of one vertex-slot block of a reduced Hessian A (3 m x 3 m,
+// blocks (I, J) of 3 x 3): P'(a, b) = sum_ij Fr[a][i] A(3I + i, 3J + j) Fr[b][j].
+template <int NN>
+YHD void block_to_frame(const Sym<NN, double>& A, int I, int J, const double (&Fr)[3][3], double (&P)[3][3]) {
+  double T[3][3];  // Fr A_IJ
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc = fma(Fr[a][i], A(3 * I + i, 3 * J + j), acc);
-          T[a][j] = acc;
-        }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc = fma(T[a][j], Fr[2][j], acc);
-        if (a < 2)
-          Bt[2 * I + a][J] = acc;
-        else
-          Cn[I][J] = acc;
-      }
+      for (int i = 0; i < 3; ++i) acc = fma(Fr[a][i], A(3 * I + i, 3 * J + j), acc);
+      T[a][j] = acc;
     }
-  // Householder QR of Bt (6 x 3): Bt = Q R
-  double V[3][6];  // reflector vectors (v_k has zeros above row k)
-  double R[3][3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc = fma(T[a][j], Fr[b][j], acc);
+      P[a][b] = acc;
+    }
+}
+
+// The inverse map: A_IJ = Fr^T P' Fr (the upper entries of a diagonal block).
+template <int NN>
+YHD void block_from_frame(Sym<NN, double>& A, int I, int J, const double (&Fr)[3][3], const double (&P)[3][3]) {
+  double T[3][3];  // P' Fr
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc = fma(P[a][b], Fr[b][j], acc);
+      T[a][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (I == J && j < i) continue;
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc = fma(Fr[a][i], T[a][j], acc);
+      A(3 * I + i, 3 * J + j) = acc;
+    }
+}
+
+// PSD projection of the reduced Hessian A of a point-triangle or edge-edge
+// barrier (m vertex slots: the free vertices, or the Helmert combinations of
+// all four).  Fr holds the orthonormal frame (t1, t2, n) of the stencil's plane
+// (the triangle's plane; the plane of both edge directions).  The squared
+// distance d = s^2/N does not change when the vertices move inside planes
+// parallel to it (the triangle stays in its plane and the point keeps its
+// height; each edge stays in its own parallel plane), so d is constant on that
+// 2m-dimensional affine subspace: its gradient and Hessian vanish there, and
+// so does the barrier Hessian kappa (b'' grad d grad d^T + b' hess d).  In
+// frame coordinates (two in-plane and one normal component per slot) the
+// Hessian is M = [[0, B^T], [B, C]] with the m x 2m normal-by-in-plane block B
+// and the m x m normal block C.  With the Householder factorisation
+// B^T = Q R (Q 2m x m orthonormal), M = W M' W^T, W = diag(Q, I_m),
+// M' = [[0, R], [R^T, C]], and M annihilates the in-plane directions
+// orthogonal to Q; so Proj(M) = W Proj(M') W^T, a 2m x 2m eigenproblem in
+// place of a 3m x 3m one (closed form for m = 1).  The computed in-plane block
+// is zero up to rounding and is dropped.
+template <int m>
+YHD void project_plane(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
+  double Bt[2 * m][m];  // Bt[2I + a][J] = P'(I a, J n), a in {t1, t2}
+  double Cn[m][m];      // P'(I n, J n)
+#pragma unroll
+  for (int I = 0; I < m; ++I)
+#pragma unroll
+    for (int J = I; J < m; ++J) {
+      double P[3][3];
+      block_to_frame<3 * m>(A, I, J, Fr, P);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        Bt[2 * I + a][J] = P[a][2];
+        if (J > I) Bt[2 * J + a][I] = P[2][a];
+      }
+      Cn[I][J] = P[2][2];
+      Cn[J][I] = P[2][2];
+    }
+  // Householder QR of Bt (2m x m): Bt = Q R
+  double V[m][2 * m];  // reflector vectors (v_k has zeros above row k)
+  double R[m][m];
+#pragma unroll
+  for (int k = 0; k < m; ++k) {
     double nrm2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) nrm2 = r >= k ? fma(Bt[r][k], Bt[r][k], nrm2) : nrm2;
+    for (int r = 0; r < 2 * m; ++r) nrm2 = r >= k ? fma(Bt[r][k], Bt[r][k], nrm2) : nrm2;
     const double nrm = sqrt(nrm2);
     const double alpha = Bt[k][k] >= 0.0 ? -nrm : nrm;  // v = x - alpha e_k, no cancellation
     double vn2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
+    for (int r = 0; r < 2 * m; ++r) {
       const double v = r < k ? 0.0 : (r == k ? Bt[k][k] - alpha : Bt[r][k]);
       V[k][r] = v;
       vn2 = fma(v, v, vn2);
     }
     const double inv = vn2 > 0.0 ? 2.0 / vn2 : 0.0;  // H_k = I - inv v v^T (identity when x = 0)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < m; ++c) {
       if (c < k) continue;
       double dotv = 0.0;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) dotv = fma(V[k][r], Bt[r][c], dotv);
+      for (int r = 0; r < 2 * m; ++r) dotv = fma(V[k][r], Bt[r][c], dotv);
       const double f = inv * dotv;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) Bt[r][c] = fma(-f, V[k][r], Bt[r][c]);
+      for (int r = 0; r < 2 * m; ++r) Bt[r][c] = fma(-f, V[k][r], Bt[r][c]);
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) R[k][c] = c < k ? 0.0 : Bt[k][c];
-    V[k][0] *= sqrt(inv);  // scale so that H_k = I - v v^T
+    for (int c = 0; c < m; ++c) R[k][c] = c < k ? 0.0 : Bt[k][c];
+    const double sq = sqrt(inv);  // scale so that H_k = I - v v^T
 #pragma unroll
-    for (int r = 1; r < 6; ++r) V[k][r] *= sqrt(inv);
+    for (int r = 0; r < 2 * m; ++r) V[k][r] *= sq;
   }
-  // Q = H_0 H_1 H_2 applied to the first three columns of I6
-  double Q[6][3];
+  // Q = H_0 ... H_{m-1} applied to the first m columns of I_2m
+  double Q[2 * m][m];
 #pragma unroll
-  for (int r = 0; r < 6; ++r)
+  for (int r = 0; r < 2 * m; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Q[r][c] = r == c ? 1.0 : 0.0;
+    for (int c = 0; c < m; ++c) Q[r][c] = r == c ? 1.0 : 0.0;
 #pragma unroll
-  for (int k = 2; k >= 0; --k)
+  for (int k = m - 1; k >= 0; --k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < m; ++c) {
       double dotv = 0.0;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) dotv = fma(V[k][r], Q[r][c], dotv);
+      for (int r = 0; r < 2 * m; ++r) dotv = fma(V[k][r], Q[r][c], dotv);
 #pragma unroll
-      for (int r = 0; r < 6; ++r) Q[r][c] = fma(-dotv, V[k][r], Q[r][c]);
+      for (int r = 0; r < 2 * m; ++r) Q[r][c] = fma(-dotv, V[k][r], Q[r][c]);
     }
   // the reduced matrix and its projection
-  Sym<6, double> M6;
+  Sym<2 * m, double> M;
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < m; ++i)
 #pragma unroll
-    for (int j = i; j < 3; ++j) M6(i, j) = 0.0;
+    for (int j = i; j < m; ++j) M(i, j) = 0.0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < m; ++i)
 #pragma unroll
-    for (int J = 0; J < 3; ++J) M6(i, 3 + J) = R[i][J];
+    for (int J = 0; J < m; ++J) M(i, m + J) = R[i][J];
 #pragma unroll
-  for (int I = 0; I < 3; ++I)
+  for (int I = 0; I < m; ++I)
 #pragma unroll
-    for (int J = I; J < 3; ++J) M6(3 + I, 3 + J) = 0.5 * (Cn[I][J] + Cn[J][I]);
-  psd_project<6, double>(M6);
+    for (int J = I; J < m; ++J) M(m + I, m + J) = Cn[I][J];
+  psd_small<2 * m>(M);
   // back to frame coordinates: P'_SS = Q P11 Q^T, P'_SN = Q P12, P'_NN = P22
-  double QP11[6][3], PSN[6][3];
+  double QP11[2 * m][m], PSN[2 * m][m];
 #pragma unroll
-  for (int r = 0; r < 6; ++r)
+  for (int r = 0; r < 2 * m; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < m; ++c) {
       double a1 = 0.0, a2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        a1 = fma(Q[r][k], M6(k, c), a1);
-        a2 = fma(Q[r][k], M6(k, 3 + c), a2);
+      for (int k = 0; k < m; ++k) {
+        a1 = fma(Q[r][k], M(k, c), a1);
+        a2 = fma(Q[r][k], M(k, m + c), a2);
       }
       QP11[r][c] = a1;
       PSN[r][c] = a2;
     }
-  // vertex blocks in frame coordinates, then back: A_IJ = Fr^T P'_IJ Fr
 #pragma unroll
-  for (int I = 0; I < 3; ++I)
+  for (int I = 0; I < m; ++I)
 #pragma unroll
-    for (int J = I; J < 3; ++J) {
+    for (int J = I; J < m; ++J) {
       double P[3][3];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -384,7 +471,7 @@ YHD void project_pt_fixed_point(Sym<9, double>& A, const double (&Fr)[3][3]) {
         for (int b = 0; b < 2; ++b) {
           double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) acc = fma(QP11[2 * I + a][k], Q[2 * J + b][k], acc);
+          for (int k = 0; k < m; ++k) acc = fma(QP11[2 * I + a][k], Q[2 * J + b][k], acc);
           P[a][b] = acc;
         }
 #pragma unroll
@@ -392,27 +479,56 @@ YHD void project_pt_fixed_point(Sym<9, double>& A, const double (&Fr)[3][3]) {
         P[a][2] = PSN[2 * I + a][J];
         P[2][a] = PSN[2 * J + a][I];
       }
-      P[2][2] = M6(3 + I, 3 + J);
-      double T[3][3];  // P Fr
+      P[2][2] = M(m + I, m + J);
+      block_from_frame<3 * m>(A, I, J, Fr, P);
+    }
+}
+
+// PSD projection of the reduced Hessian A of a point-edge barrier (m slots as
+// in project_plane).  Fr holds the orthonormal frame (e, nu, n): e along the
+// edge, n normal to the plane of the point and the edge, nu = n x e.  The
+// distance from the point to the edge's line does not change when any vertex
+// moves along e (the point slides parallel to the line, an edge vertex along
+// it), so the Hessian's (e, e) block vanishes; the reflection through the
+// stencil's plane maps the stencil onto itself, so the n components decouple
+// from the in-plane ones.  In frame coordinates the Hessian is therefore
+// diag(M, Nn) with M = [[0, B], [B^T, C]] over the (e, nu) components and Nn
+// over the n components: a 2m x 2m and an m x m eigenproblem in place of a
+// 3m x 3m one (both in closed form for m = 1, the second for m = 2).  The
+// computed (e, e) and cross blocks are zero up to rounding and are dropped.
+template <int m>
+YHD void project_line(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
+  Sym<2 * m, double> M;
+  Sym<m, double> Nn;
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+  for (int I = 0; I < m; ++I)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
+    for (int J = I; J < m; ++J) {
+      double P[3][3];
+      block_to_frame<3 * m>(A, I, J, Fr, P);
+      M(I, J) = 0.0;
+      M(I, m + J) = P[0][1];
+      if (J > I) M(J, m + I) = P[1][0];
+      M(m + I, m + J) = P[1][1];
+      Nn(I, J) = P[2][2];
+    }
+  psd_small<2 * m>(M);
+  if constexpr (m == 1)
+    Nn(0, 0) = fmax(Nn(0, 0), 0.0);
+  else
+    psd_small<m>(Nn);
 #pragma unroll
-          for (int b = 0; b < 3; ++b) acc = fma(P[a][b], Fr[b][j], acc);
-          T[a][j] = acc;
-        }
+  for (int I = 0; I < m; ++I)
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          if (I == J && j < i) continue;
-          double acc = 0.0;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) acc = fma(Fr[a][i], T[a][j], acc);
-          A(3 * I + i, 3 * J + j) = acc;
-        }
+    for (int J = I; J < m; ++J) {
+      double P[3][3];
+      P[0][0] = M(I, J);
+      P[0][1] = M(I, m + J);
+      P[1][0] = M(J, m + I);
+      P[1][1] = M(m + I, m + J);
+      P[0][2] = P[1][2] = P[2][0] = P[2][1] = 0.0;
+      P[2][2] = Nn(I, J);
+      block_from_frame<3 * m>(A, I, J, Fr, P);
     }
 }
 
@@ -425,12 +541,12 @@ YHD void project_pt_fixed_point(Sym<9, double>& A, const double (&Fr)[3][3]) {
 // Helmert basis when every vertex is free (exact reduction, the energy is
 // translation invariant), else on the free principal submatrix.
 //
-// PT_FIXED_POINT (point-triangle stencils whose free vertices are exactly the
-// triangle's): the projection takes the reduced path of
-// project_pt_fixed_point in the frame Fr (rows t1, t2, n of the triangle).
-template <class TOPO, int K, bool EXACT, bool PT_FIXED_POINT = false, class GS, class BS>
+// SPLIT selects the structured projection of that reduced matrix in the frame
+// *Fr: 1 = project_plane (point-triangle, edge-edge), 2 = project_line
+// (point-edge), 0 = a dense eigendecomposition.
+template <class TOPO, int K, bool EXACT, int SPLIT = 0, class GS, class BS>
 YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double>& Hu, const int (&fl)[4],
-                      GS&& grad_sink, BS&& block_sink, const double (*Fr)[3] = nullptr) {
+                      GS&& grad_sink, BS&& block_sink, const double (*Fr)[3][3] = nullptr) {
   constexpr int NV = TOPO::NV, NU = TOPO::NU;
   // coefficients M[U][fl[k]] selected at run time from the compile-time table
   double Mf[NU][K];
@@ -485,7 +601,12 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
               for (int W = 0; W < NU; ++W) acc = fma(R[U][I] * R[W][J], Hu(3 * U + i, 3 * W + l), acc);
             A(3 * I + i, 3 * J + l) = acc;
           }
-    psd_project<3 * NR, double>(A);
+    if constexpr (SPLIT == 1)
+      project_plane<NR>(A, *Fr);
+    else if constexpr (SPLIT == 2)
+      project_line<NR>(A, *Fr);
+    else
+      psd_project<3 * NR, double>(A);
 #pragma unroll
     for (int p = 0; p < NV; ++p)
 #pragma unroll
@@ -534,12 +655,12 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
             A(3 * I + i, 3 * J + l) = acc;
           }
     if constexpr (!EXACT) {
-      if constexpr (PT_FIXED_POINT) {
-        static_assert(K == 3 && NV == 4, "point-triangle stencils with the triangle free");
-        project_pt_fixed_point(A, *reinterpret_cast<const double(*)[3][3]>(Fr));
-      } else {
+      if constexpr (SPLIT == 1)
+        project_plane<K>(A, *Fr);
+      else if constexpr (SPLIT == 2)
+        project_line<K>(A, *Fr);
+      else
         psd_project<3 * K, double>(A);
-      }
     }
 #pragma unroll
     for (int I = 0; I < K; ++I)
@@ -572,11 +693,12 @@ YHD double ee_mollifier(const double (&u)[3][3], double eps) {
 // contact stencil with K free vertices (sinks as in emit_reduced).  Returns
 // false when an input is not finite.  d receives the squared distance;
 // e = kappa b(d) (0 when d >= dhat or d <= 0), times the mollifier m(c) for
-// an edge-edge stencil with eps > 0 (ee_mollifier).  PT_FIXED_POINT: a
-// point-triangle stencil whose point is fixed and whose triangle is free
-// (fl = 1, 2, 3), projected through project_pt_fixed_point.  Its frame is
-// degenerate only with the triangle, and then d is not finite either.
-template <int TYPE, int K, bool EXACT, bool PT_FIXED_POINT = false, class GS, class BS>
+// an edge-edge stencil with eps > 0 (ee_mollifier).  The projection is the
+// structured one of the stencil's type (project_plane, project_line, the
+// point-point closed form), except for a mollified edge-edge stencil: the
+// mollifier varies with the edges' in-plane directions, so that Hessian takes
+// the dense eigendecomposition.
+template <int TYPE, int K, bool EXACT, class GS, class BS>
 YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
                          double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink, double eps = 0.0) {
   constexpr int NU = Topo<TYPE>::NU;
@@ -640,22 +762,24 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
 #pragma unroll
       for (int c = r; c < 3 * NU; ++c) D.H(r, c) = fma(kb2 * D.g[r], D.g[c], kb1 * D.H(r, c));
   }
-  if constexpr (PT_FIXED_POINT && !EXACT) {
-    static_assert(TYPE == 0 && K == 3, "point-triangle stencils with the triangle free");
-    // the triangle's frame: t1 along e1, n along e1 x e2, t2 = n x t1
-    double n[3], t2[3];
-    cross(u[1], u[2], n);
-    const double l1 = sqrt(dot(u[1], u[1])), ln = sqrt(dot(n, n));
-    double Fr[3][3];
+  if constexpr ((TYPE == 0 || TYPE == 1 || TYPE == 2) && !EXACT) {
+    // point-triangle / edge-edge: t along e1, n along e1 x e2;
+    // point-edge (u = (a, b)): t along the edge b - a, n along a x b
+    double t[3], n[3], Fr[3][3];
+    if constexpr (TYPE == 2) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      Fr[0][i] = u[1][i] / l1;
-      Fr[2][i] = n[i] / ln;
+      for (int i = 0; i < 3; ++i) t[i] = u[1][i] - u[0][i];
+      cross(u[0], u[1], n);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) t[i] = u[1][i];
+      cross(u[1], u[2], n);
     }
-    cross(Fr[2], Fr[0], t2);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Fr[1][i] = t2[i];
-    emit_reduced<Topo<TYPE>, K, EXACT, true>(gu, D.H, fl, grad_sink, block_sink, Fr);
+    orthonormal_frame(t, n, Fr);
+    if (TYPE == 1 && mollified)
+      emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
+    else
+      emit_reduced<Topo<TYPE>, K, EXACT, TYPE == 2 ? 2 : 1>(gu, D.H, fl, grad_sink, block_sink, &Fr);
   } else if constexpr (TYPE == 3 && !EXACT) {
     // point-point in closed form: with u = q - p and d = |u|^2 the u-space
     // Hessian kappa (b'' grad d grad d^T + b' hess d) = 4 kappa b'' u u^T + 2 kappa b' I

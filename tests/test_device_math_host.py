@@ -141,3 +141,69 @@ def test_ee_mollifier_matches_oracle(harness, exact, classic):
                 assert np.abs(g - go[s].numpy()).max() <= 1e-10 * np.abs(go[s].numpy()).max()
                 err = np.abs(H - Ho[s].numpy()).max()
                 assert err <= 1e-10 * sc, (K, freeset, exact, s, err, sc)
+
+
+def random_rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    return q if np.linalg.det(q) > 0 else -q
+
+
+def oriented_stencils(t, n, seed):
+    """Stencils of type t in random orientations and shapes, all active
+    (0 < d < dhat): triangles, edges and points placed at a random distance
+    below sqrt(dhat) from the other primitive, then rotated and translated."""
+    rng = np.random.default_rng(seed)
+    h_max = np.sqrt(DHAT)
+    x = np.zeros((n, 4, 3))
+    for s in range(n):
+        h = rng.uniform(0.15, 0.95) * h_max
+        L = rng.uniform(0.02, 0.2)
+        if t == 0:  # triangle in z = 0, point above an arbitrary spot of its plane
+            tri = np.c_[L * rng.uniform(-1, 1, (3, 2)), np.zeros(3)]
+            p = np.r_[L * rng.uniform(-1.2, 1.2, 2), h * rng.choice([-1, 1])]
+            pts = np.vstack([p, tri])
+        elif t == 1:  # two edges in the planes z = 0 and z = h, at an angle
+            th = rng.uniform(0.2, np.pi - 0.2)
+            a0 = np.r_[L * rng.uniform(-1, 0), 0.0, 0.0]
+            a1 = np.r_[L * rng.uniform(0.2, 1), 0.0, 0.0]
+            u = np.array([np.cos(th), np.sin(th), 0.0])
+            c = np.r_[L * rng.uniform(-0.5, 0.5, 2), h]
+            b0 = c - L * rng.uniform(0.2, 1) * u
+            b1 = c + L * rng.uniform(0.2, 1) * u
+            pts = np.vstack([a0, a1, b0, b1])
+        else:  # edge along x, point at distance h from its line
+            e0 = np.r_[L * rng.uniform(-1, 0), 0.0, 0.0]
+            e1 = np.r_[L * rng.uniform(0.2, 1), 0.0, 0.0]
+            ph = rng.uniform(0, 2 * np.pi)
+            p = np.r_[L * rng.uniform(-1.5, 1.5), h * np.cos(ph), h * np.sin(ph)]
+            pts = np.vstack([p, e0, e1, np.zeros(3)])
+        R = random_rotation(rng)
+        off = rng.uniform(-1, 1, 3)
+        x[s, :NV[t]] = pts[:NV[t]] @ R.T + off
+    return x
+
+
+@pytest.mark.parametrize("t", [0, 1, 2])
+@pytest.mark.parametrize("classic", [0, 1])
+def test_structured_projection_random_orientations(harness, t, classic):
+    """The in-frame projections (plane split for point-triangle and edge-edge,
+    line split for point-edge, closed forms for the 2 x 2 pieces) against the
+    oracle's dense eigendecomposition of the free Hessian, on stencils in
+    random orientations, shapes and distances, for every free set."""
+    n = 24
+    x = oriented_stencils(t, n, 400 + 10 * t + classic)
+    for K in range(1, NV[t] + 1):
+        for freeset in itertools.combinations(range(NV[t]), K):
+            fl = list(freeset) + [0] * (4 - K)
+            free = torch.zeros(n, 4, dtype=torch.bool)
+            free[:, list(freeset)] = True
+            Eo, go, Ho, do = local.contact_local(torch.tensor(x), torch.full((n,), t), free, KAPPA, DHAT,
+                                                 local.PROJECTED, classic=bool(classic))
+            assert (do > 0).all() and (do < DHAT).all()
+            for s in range(n):
+                e, d, g, H = run_host(harness, t, K, False, x[s], fl, classic)
+                sc = np.abs(Ho[s].numpy()).max() + 1e-300
+                err = np.abs(H - Ho[s].numpy()).max()
+                assert err <= 1e-10 * sc, (t, K, freeset, s, err, sc)
+                assert np.linalg.eigvalsh(H).min() >= -1e-12 * sc
