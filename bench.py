@@ -38,8 +38,14 @@ FP64_VECTOR_TFLOPS = 78.6
 
 # Algorithmic work per unit:
 SNH_FLOPS_PER_TET = 4.0e3        # closed-form F-space eigensystem: 3x3 SVD, 9 rank-one modes, J_F map
-CONTACT_FLOPS = {0: 3.0e4, 1: 1.0e4, 2: 3.0e4, 3: 1.0e4}  # PT 9x9, EE 6x6 eigenproblems
-PT_FIXED_POINT_FLOPS = 1.25e4    # 6x6 eigenproblem + frame / QR transforms (point fixed, triangle free)
+# Contacts: distance, barrier and u-space Hessian plus the structured projection
+# of the free Hessian over m vertex slots (m = free vertices, or 3 / 2 / 1 for
+# all-free PT, EE / PE / PP): PT and EE in the stencil's plane frame (2m x 2m
+# eigenproblem: 6x6 Jacobi for m = 3, 4x4 for m = 2, closed form for m = 1), PE
+# in the edge frame (2m x 2m + m x m), PP in closed form; calibrated on the
+# measured FP64 VALU operations of the kernels
+CONTACT_FLOPS = {(0, 3): 1.6e4, (0, 2): 5.5e3, (0, 1): 2.5e3, (1, 3): 1.6e4, (1, 2): 5.5e3, (1, 1): 2.5e3,
+                 (2, 2): 5.0e3, (2, 1): 2.5e3, (3, 1): 1.0e3}
 MEMBRANE_FLOPS = 6.0e3           # 6x6 F-space Jacobi eigenproblem and the J_F map
 HINGE_FLOPS = 3.0e4              # 9x9 Helmert-reduced Jacobi eigenproblem
 
@@ -60,10 +66,14 @@ def algorithmic(prob, g, view, projected=True, mixed=False):
     nt = g.nt
     ct = prob["ctype"]
     nnzb = view.nnzb_static + view.nnzb_dynamic + view.nnzb_body
-    ci = np.asarray(prob["cidx"])
-    pt_fp = (ct == 0) & (ci[:, 0] >= n) & (ci[:, 1:] < n).all(axis=1) if len(ct) else np.zeros(0, bool)
-    c_flops = (sum(CONTACT_FLOPS[int(t)] * int(((ct == t) & ~pt_fp).sum()) for t in range(4)) +
-               PT_FIXED_POINT_FLOPS * int(pt_fp.sum()))
+    ci = np.asarray(prob["cidx"]).reshape(-1, 4)
+    c_flops = 0.0
+    if len(ct):
+        nv = np.array([4, 4, 3, 2])[np.asarray(ct)]
+        k = ((ci >= 0) & (ci < n)).sum(axis=1)
+        m = np.where(k == nv, nv - 1, k)
+        for (t, mm), f in CONTACT_FLOPS.items():
+            c_flops += f * int(((ct == t) & (m == mm)).sum())
     vb = 36.0 if mixed else 72.0   # bytes of one stored 3x3 block
     vv = 12.0 if mixed else 24.0   # bytes of one vertex of a Krylov vector
     cl_flops = MEMBRANE_FLOPS * len(prob.get("tri_idx", [])) + HINGE_FLOPS * len(prob.get("hinge_idx", []))

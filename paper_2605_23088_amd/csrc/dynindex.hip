@@ -7,9 +7,14 @@
 // set of upper block coordinates of every free pair of every stencil; the
 // stencils are stored grouped by (type, number of free vertices), stably; the
 // contributions of a block are staged contiguously in storage order of their
-// stencils and, within a stencil, in canonical pair order.  Sorting is done by
-// stable LSD radix sorts (rocPRIM), so every array equals the host builder's,
-// element for element.  The paper rebuilds only this part when the contacts
+// stencils and, within a stencil, in canonical pair order.  The storage order
+// comes from a stable counting sort by group key; the block entries (one per
+// free pair, written compacted) are ordered by a stable LSD radix sort
+// (rocPRIM) over only the key bits in use; the gradient entries are the
+// diagonal blocks' entries in that order.  Every array equals the host
+// builder's, element for element.  One host round trip
+// (the group counts, which size everything after them) precedes the final
+// synchronisation.  The paper rebuilds only this part when the contacts
 // change (section "Implementation", static / dynamic split).
 #include <hip/hip_runtime.h>
 
@@ -70,25 +75,61 @@ YDEV void classify_one(int s, int nc, int n, int nall, const int32_t* __restrict
 
 __global__ __launch_bounds__(DI_BLOCK) void classify_kernel(int nc, int n, int nall, const int32_t* __restrict__ type,
                                                             const int32_t* __restrict__ idx,
-                                                            uint32_t* __restrict__ gkey, int* err, int* gcount) {
-  // group counts: a workgroup histogram in LDS, one global add per nonzero bin
+                                                            uint32_t* __restrict__ gkey, int* err, int* gcount,
+                                                            int* __restrict__ blkhist) {
+  // group counts: a workgroup histogram in LDS, one global add per nonzero bin,
+  // and the workgroup's count of every key (key-major) for the stable scatter
   __shared__ int hist[32];
   if (threadIdx.x < 32) hist[threadIdx.x] = 0;
   __syncthreads();
   const int s = blockIdx.x * DI_BLOCK + threadIdx.x;
   classify_one(s, nc, n, nall, type, idx, gkey, err, hist);
   __syncthreads();
-  if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&gcount[threadIdx.x], hist[threadIdx.x]);
+  if (threadIdx.x < 32) {
+    blkhist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
+    if (hist[threadIdx.x]) atomicAdd(&gcount[threadIdx.x], hist[threadIdx.x]);
+  }
 }
 
-// Per stencil in storage order j (s = order[j]): its vertex ids in storage
-// order, one block entry per canonical pair q (key (r << 32) | c of a free pair,
-// else the pad key, which sorts last) and one gradient entry per used vertex
-// (its id if free, else the pad n).
-__global__ void entries_kernel(int nc, int n, const int32_t* __restrict__ idx, const int32_t* __restrict__ order,
-                               uint64_t pad, int32_t* __restrict__ sidx, uint64_t* __restrict__ bkey,
-                               int32_t* __restrict__ bval, uint32_t* __restrict__ gkey, int32_t* __restrict__ gval,
-                               int* counts, const double* __restrict__ eps, double* __restrict__ seps) {
+// Stable counting sort by group key (keys < 32): base = exclusive prefix of the
+// key-major workgroup counts; a stencil's rank among the equal keys of its
+// workgroup comes from wavefront ballots (lanes with the same key below it)
+// plus the counts of the same key in the workgroup's earlier wavefronts.
+__global__ __launch_bounds__(DI_BLOCK) void group_scatter_kernel(int nc, const uint32_t* __restrict__ gkey,
+                                                                 const int32_t* __restrict__ base,
+                                                                 int32_t* __restrict__ order) {
+  constexpr int NW = DI_BLOCK / 64;
+  __shared__ int cnt[NW][32];
+  for (int t = threadIdx.x; t < NW * 32; t += DI_BLOCK) cnt[t / 32][t % 32] = 0;
+  __syncthreads();
+  const int s = blockIdx.x * DI_BLOCK + threadIdx.x;
+  const bool in = s < nc;
+  const uint32_t k = in ? gkey[s] : 0u;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t same = __ballot(in);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const uint64_t ones = __ballot(in && ((k >> b) & 1u));
+    same &= ((k >> b) & 1u) ? ones : ~ones;
+  }
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int rank = __popcll(same & below);
+  if (in && rank == 0) cnt[w][k] = __popcll(same);
+  __syncthreads();
+  if (!in) return;
+  int off = base[(size_t)k * gridDim.x + blockIdx.x] + rank;
+  for (int q = 0; q < w; ++q) off += cnt[q][k];
+  order[off] = s;
+}
+
+// Per stencil in storage order j (s = order[j]): its vertex ids and mollifier
+// threshold in storage order, and -1 in the staging positions and slot-map
+// entries of its pairs and vertices that are not free (the free ones are
+// written by blocks_kernel).
+__global__ void stencil_kernel(int nc, int n, const int32_t* __restrict__ idx, const int32_t* __restrict__ order,
+                               int32_t* __restrict__ sidx, const double* __restrict__ eps,
+                               double* __restrict__ seps, int32_t* __restrict__ spos, int32_t* __restrict__ slot,
+                               int32_t* __restrict__ gpos) {
   const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (j >= nc) return;
   const int s = order[j];
@@ -101,56 +142,122 @@ __global__ void entries_kernel(int nc, int n, const int32_t* __restrict__ idx, c
     sidx[(size_t)a * nc + j] = v[a];
     used += v[a] >= 0 ? 1 : 0;
   }
-  int q = 0, nb = 0, ng = 0;
+  int q = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = a; b < 4; ++b) {
-      if (a < used && b < used) {
-        const bool fr = v[a] < n && v[b] < n;
-        const uint64_t r = (uint64_t)min(v[a], v[b]), c = (uint64_t)max(v[a], v[b]);
-        bkey[(size_t)j * 10 + q] = fr ? ((r << 32) | c) : pad;
-        nb += fr ? 1 : 0;
+      const bool pair = a < used && b < used;
+      const bool fr = pair && v[a] < n && v[b] < n;
+      if (pair) {
+        if (!fr) {
+          spos[(size_t)q * nc + j] = -1;
+          slot[(size_t)s * 10 + q] = -1;
+        }
         ++q;
       }
     }
-  for (; q < 10; ++q) bkey[(size_t)j * 10 + q] = pad;
-#pragma unroll
-  for (int k = 0; k < 10; ++k) bval[(size_t)j * 10 + k] = j * 10 + k;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const bool fr = v[a] >= 0 && v[a] < n;
-    gkey[(size_t)j * 4 + a] = fr ? (uint32_t)v[a] : (uint32_t)n;
-    gval[(size_t)j * 4 + a] = j * 4 + a;
-    ng += fr ? 1 : 0;
+  for (int r = q; r < 10; ++r) {
+    spos[(size_t)r * nc + j] = -1;
+    slot[(size_t)s * 10 + r] = -1;
   }
-  atomicAdd(&counts[0], nb);
-  atomicAdd(&counts[1], ng);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    if (!(v[a] >= 0 && v[a] < n)) gpos[(size_t)a * nc + j] = -1;
 }
 
-// first[i] = 1 where sorted block entry i opens a new block
-__global__ void first_kernel(int ne, const uint64_t* __restrict__ key, int32_t* __restrict__ first) {
+// The groups in storage order: first stencil, free vertices, vertices and
+// first block entry of each (every stencil of a group has the same number of
+// free vertices, hence nf (nf + 1) / 2 block entries).
+struct GroupTable {
+  int ng;
+  int begin[32], nf[32], nv[32];
+  int ebase[33];
+};
+
+YDEV int group_of(const GroupTable& T, long long e, const int* base) {
+  int g = 0;
+  for (int q = 1; q < T.ng; ++q) g = e >= base[q] ? q : g;
+  return g;
+}
+
+// One block entry per free pair (e < ne, in storage order of the stencils and
+// canonical pair order within one): key (r << bits) | c, value j * 10 + q
+// (q = the pair's index among the stencil's used pairs).
+__global__ void bentries_kernel(int ne, int nc, int n, int bits, GroupTable T, const int32_t* __restrict__ sidx,
+                                uint64_t* __restrict__ bkey, int32_t* __restrict__ bval) {
+  const int e = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (e >= ne) return;
+  const int g = group_of(T, e, T.ebase);
+  const int nf = T.nf[g], P = nf * (nf + 1) / 2;
+  const int local = e - T.ebase[g], jl = local / P, t = local - jl * P;
+  const int j = T.begin[g] + jl;
+  int v[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) v[a] = sidx[(size_t)a * nc + j];
+  int q = 0, f = 0, qs = 0, rs = 0, cs = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      const bool pair = v[a] >= 0 && v[b] >= 0;
+      const bool fr = pair && v[a] < n && v[b] < n;
+      if (fr && f == t) {
+        qs = q;
+        rs = min(v[a], v[b]);
+        cs = max(v[a], v[b]);
+      }
+      f += fr ? 1 : 0;
+      q += pair ? 1 : 0;
+    }
+  bkey[e] = ((uint64_t)rs << bits) | (uint64_t)cs;
+  bval[e] = j * 10 + qs;
+}
+
+// first[i] = 1 where sorted block entry i opens a new block; diag[i] = 1 on a
+// diagonal block's entries.  A stencil stages one diagonal entry per free
+// vertex, so the diagonal entries in sorted order are the gradient entries in
+// the gradient staging order (by vertex, then storage order of the stencils).
+__global__ void first_kernel(int ne, int bits, const uint64_t* __restrict__ key, int32_t* __restrict__ first,
+                             int32_t* __restrict__ diag) {
   const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i >= ne) return;
-  first[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+  const uint64_t k = key[i];
+  first[i] = (i == 0 || k != key[i - 1]) ? 1 : 0;
+  diag[i] = (k >> bits) == (k & ((1ull << bits) - 1)) ? 1 : 0;
 }
 
-// Block entries (sorted, i < ne; blk = inclusive count of block starts):
-// staged positions, block columns, contribution starts, slot map (API order),
-// per-row block counts, dynamic diagonal positions and the off-diagonal count.
-__global__ void blocks_kernel(int ne, int nc, const uint64_t* __restrict__ key, const int32_t* __restrict__ val,
-                              const int32_t* __restrict__ blk, const int32_t* __restrict__ first,
-                              const int32_t* __restrict__ order, int32_t* __restrict__ spos,
-                              int32_t* __restrict__ col, int32_t* __restrict__ cptr, int32_t* __restrict__ slot,
-                              int32_t* __restrict__ rowcnt, int32_t* __restrict__ ddiag, int* offdiag) {
+// Block entries (sorted, i < ne; blk = inclusive count of block starts, dpos =
+// exclusive count of diagonal entries): staged positions, block columns,
+// contribution starts, slot map (API order), per-row block counts, dynamic
+// diagonal positions, the off-diagonal count and the gradient staging
+// positions; the last thread closes cptr (cptr[nnzb] = ne).
+__global__ void blocks_kernel(int ne, int nc, int bits, GroupTable T, const uint64_t* __restrict__ key,
+                              const int32_t* __restrict__ val, const int32_t* __restrict__ blk,
+                              const int32_t* __restrict__ first, const int32_t* __restrict__ diag,
+                              const int32_t* __restrict__ dpos, const int32_t* __restrict__ order,
+                              int32_t* __restrict__ spos, int32_t* __restrict__ col, int32_t* __restrict__ cptr,
+                              int32_t* __restrict__ slot, int32_t* __restrict__ rowcnt, int32_t* __restrict__ ddiag,
+                              int32_t* __restrict__ gpos, int* offdiag) {
   const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i >= ne) return;
   const int jq = val[i], j = jq / 10, q = jq - 10 * (jq / 10);
   const int b = blk[i] - 1;
   spos[(size_t)q * nc + j] = i;
   slot[(size_t)order[j] * 10 + q] = b;
+  if (i == ne - 1) cptr[b + 1] = ne;
+  if (diag[i]) {
+    // q = the diagonal pair (a, a) among the stencil's nv used vertices:
+    // q = a nv - a (a - 1) / 2
+    const int nv = T.nv[group_of(T, j, T.begin)];
+    int a = 0;
+#pragma unroll
+    for (int t = 1; t < 4; ++t) a = q == t * nv - (t * (t - 1)) / 2 ? t : a;
+    gpos[(size_t)a * nc + j] = dpos[i];
+  }
   if (first[i]) {
-    const int r = (int)(key[i] >> 32), c = (int)(key[i] & 0xffffffffu);
+    const uint64_t k = key[i];
+    const int r = (int)(k >> bits), c = (int)(k & ((1ull << bits) - 1));
     col[b] = c;
     cptr[b] = i;
     atomicAdd(&rowcnt[r], 1);
@@ -161,38 +268,18 @@ __global__ void blocks_kernel(int ne, int nc, const uint64_t* __restrict__ key, 
   }
 }
 
-// Gradient entries (sorted by vertex, i < ng): staged positions, per-vertex counts.
-__global__ void grads_kernel(int ng, int nc, const int32_t* __restrict__ val, int32_t* __restrict__ gpos) {
-  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (i >= ng) return;
-  const int ja = val[i], j = ja / 4, a = ja - 4 * (ja / 4);
-  gpos[(size_t)a * nc + j] = i;
-}
-
-// gptr[v] = first sorted gradient entry of vertex v (v = 0 .. n; entries of
-// vertex v are [gptr[v], gptr[v + 1]))
-__global__ void gptr_kernel(int n, int ng, const uint32_t* __restrict__ key, int32_t* __restrict__ gptr) {
+// gradient entries of every row: the contributions of its dynamic diagonal block
+__global__ void gcount_kernel(int nr, const int32_t* __restrict__ ddiag, const int32_t* __restrict__ cptr,
+                              int32_t* __restrict__ gcnt) {
   const int v = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (v > n) return;
-  int lo = 0, hi = ng;
-  while (lo < hi) {
-    const int mid = (lo + hi) / 2;
-    if (key[mid] < (uint32_t)v)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  gptr[v] = lo;
+  if (v >= nr) return;
+  const int b = ddiag[v];
+  gcnt[v] = b >= 0 ? cptr[b + 1] - cptr[b] : 0;
 }
 
 __global__ void fill_i32_kernel(long long m, int32_t v, int32_t* __restrict__ p) {
   const long long i = (long long)blockIdx.x * DI_BLOCK + threadIdx.x;
   if (i < m) p[i] = v;
-}
-
-__global__ void iota_kernel(int m, int32_t* __restrict__ p) {
-  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (i < m) p[i] = i;
 }
 
 }  // namespace
@@ -215,28 +302,28 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
     DynIndexOut& o;
     ~Need() { o.arena_needed = t.used; }
   } need{tmp, out};
-  // small device scalars: err, counts[2] (block / gradient entries), offdiag, gcount[32]
+  // small device scalars: err, nnzb, offdiag, gcount[32]
   int* scal = tmp.get<int>(48);
   DI_CHECK(tmp.err);
   int* err = scal;
-  int* counts = scal + 1;
   int* offdiag = scal + 3;
   int* gcount = scal + 4;
   const int init[4] = {0x7fffffff, 0, 0, 0};
   DI_CHECK(hipMemsetAsync(scal, 0, 48 * sizeof(int), s));
   DI_CHECK(hipMemcpyAsync(scal, init, sizeof(init), hipMemcpyHostToDevice, s));
 
-  // 1. validation, group keys, storage order (stable by group key)
+  // 1. validation, group keys, storage order (a stable counting sort by group key)
+  const int nwg = grid_of(nc);
   uint32_t* gk = tmp.get<uint32_t>(nc);
-  uint32_t* gk_sorted = tmp.get<uint32_t>(nc);
-  int32_t* iota = tmp.get<int32_t>(nc);
+  int32_t* blkhist = tmp.get<int32_t>(32ll * nwg);
+  int32_t* blkbase = tmp.get<int32_t>(32ll * nwg + 1);
   int32_t* order = tmp.get<int32_t>(nc);
   DI_CHECK(tmp.err);
   if (nc) {
-    hipLaunchKernelGGL(classify_kernel, dim3(grid_of(nc)), dim3(DI_BLOCK), 0, s, nc, n, in.nall, in.type, in.idx,
-                       gk, err, gcount);
-    hipLaunchKernelGGL(iota_kernel, dim3(grid_of(nc)), dim3(DI_BLOCK), 0, s, nc, iota);
-    DI_CHECK(sort_pairs(tmp, gk, gk_sorted, iota, order, nc, 5, s));
+    hipLaunchKernelGGL(classify_kernel, dim3(nwg), dim3(DI_BLOCK), 0, s, nc, n, in.nall, in.type, in.idx, gk, err,
+                       gcount, blkhist);
+    DI_CHECK(prefix(tmp, blkhist, blkbase, 32ll * nwg, s));
+    hipLaunchKernelGGL(group_scatter_kernel, dim3(nwg), dim3(DI_BLOCK), 0, s, nc, gk, blkbase, order);
   }
   int head[36];
   DI_CHECK(hipMemcpyAsync(head, scal, sizeof(head), hipMemcpyDeviceToHost, s));
@@ -247,80 +334,91 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
     return 1;
   }
   std::copy(head + 4, head + 36, out.gcount);
-
-  // 2. block and gradient entries in storage order; stable sorts by block / vertex
-  const long long nbe = 10ll * nc, nge = 4ll * nc;
-  const int nbits = bits_for(n);
-  const uint64_t bpad = (uint64_t)n << 32;  // above every (r << 32) | c with r, c < n
-  uint64_t* bkey = tmp.get<uint64_t>(nbe);
-  uint64_t* bkey_s = tmp.get<uint64_t>(nbe);
-  int32_t* bval = tmp.get<int32_t>(nbe);
-  int32_t* bval_s = tmp.get<int32_t>(nbe);
-  uint32_t* gkey = tmp.get<uint32_t>(nge);
-  uint32_t* gkey_s = tmp.get<uint32_t>(nge);
-  int32_t* gval = tmp.get<int32_t>(nge);
-  int32_t* gval_s = tmp.get<int32_t>(nge);
-  int32_t* sidx = static_cast<int32_t*>(alloc(DI_SIDX, sizeof(int32_t) * std::max<long long>(nge, 1)));
-  double* seps = in.eps ? static_cast<double*>(alloc(DI_EPS, sizeof(double) * std::max(nc, 1))) : nullptr;
-  DI_CHECK(tmp.err);
-  if (!sidx || (in.eps && !seps)) return -1;
-  if (nc) {
-    hipLaunchKernelGGL(entries_kernel, dim3(grid_of(nc)), dim3(DI_BLOCK), 0, s, nc, n, in.idx, order, bpad, sidx,
-                       bkey, bval, gkey, gval, counts, in.eps, seps);
-    DI_CHECK(sort_pairs(tmp, bkey, bkey_s, bval, bval_s, nbe, 32 + nbits, s));
-    DI_CHECK(sort_pairs(tmp, gkey, gkey_s, gval, gval_s, nge, nbits, s));
+  GroupTable T{};
+  long long ne = 0, ng = 0;
+  for (int key = 0, j = 0; key < 32; ++key) {
+    const int cnt = out.gcount[key];
+    if (!cnt) continue;
+    const int nf = key % 8 == PT_TRIANGLE_FREE ? 3 : key % 8;
+    const int type = key / 8;
+    T.begin[T.ng] = j;
+    T.nf[T.ng] = nf;
+    T.nv[T.ng] = type == 3 ? 2 : (type == 2 ? 3 : 4);
+    T.ebase[T.ng] = (int)ne;
+    ++T.ng;
+    j += cnt;
+    ne += (long long)cnt * (nf * (nf + 1) / 2);
+    ng += (long long)cnt * nf;
   }
-  int cnt[2];
-  DI_CHECK(hipMemcpyAsync(cnt, counts, sizeof(cnt), hipMemcpyDeviceToHost, s));
-  DI_CHECK(hipStreamSynchronize(s));
-  const int ne = cnt[0], ng = cnt[1];
+  T.ebase[T.ng] = (int)ne;
 
-  // 3. blocks: starts, indices, pattern, slot map, staging
-  int32_t* first = tmp.get<int32_t>(ne);
-  int32_t* blk = tmp.get<int32_t>(ne);
-  DI_CHECK(tmp.err);
-  int nnzb = 0;
-  if (ne) {
-    hipLaunchKernelGGL(first_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, ne, bkey_s, first);
-    DI_CHECK(inclusive(tmp, first, blk, ne, s));
-    DI_CHECK(hipMemcpyAsync(&nnzb, blk + ne - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    DI_CHECK(hipStreamSynchronize(s));
-  }
+  // 2. the output arrays (slot-map and staging entries of pairs or vertices
+  //    that are not free are -1), storage-order stencils
   auto ialloc = [&](int which, long long m) {
     return static_cast<int32_t*>(alloc(which, sizeof(int32_t) * std::max<long long>(m, 1)));
   };
   const int nr = std::max(in.nrows, n);  // row arrays span every row (the rows past n stay empty)
+  out.sidx = ialloc(DI_SIDX, 4ll * nc);
+  out.seps = in.eps ? static_cast<double*>(alloc(DI_EPS, sizeof(double) * std::max(nc, 1))) : nullptr;
   out.rp = ialloc(DI_RP, nr + 1);
-  out.col = ialloc(DI_COL, nnzb);
-  out.cptr = ialloc(DI_CPTR, nnzb + 1);
+  out.col = ialloc(DI_COL, ne);           // nnzb <= ne
+  out.cptr = ialloc(DI_CPTR, ne + 1);
   out.slot = ialloc(DI_SLOT, 10ll * nc);
   out.spos = ialloc(DI_SPOS, 10ll * nc);
   out.gpos = ialloc(DI_GPOS, 4ll * nc);
   out.gptr = ialloc(DI_GPTR, nr + 1);
   out.ddiag = ialloc(DI_DDIAG, nr);
-  out.sidx = sidx;
-  out.seps = seps;
-  if (!out.rp || !out.col || !out.cptr || !out.slot || !out.spos || !out.gpos || !out.gptr || !out.ddiag) return -1;
-  int32_t* rowcnt = tmp.get<int32_t>(nr);
-  DI_CHECK(tmp.err);
-  DI_CHECK(hipMemsetAsync(rowcnt, 0, sizeof(int32_t) * std::max(nr, 1), s));
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.slot);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(10ll * nc)), dim3(DI_BLOCK), 0, s, 10ll * nc, -1, out.spos);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(4ll * nc)), dim3(DI_BLOCK), 0, s, 4ll * nc, -1, out.gpos);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(nr)), dim3(DI_BLOCK), 0, s, (long long)nr, -1, out.ddiag);
-  if (ne)
-    hipLaunchKernelGGL(blocks_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, ne, nc, bkey_s, bval_s, blk, first,
-                       order, out.spos, out.col, out.cptr, out.slot, rowcnt, out.ddiag, offdiag);
-  DI_CHECK(hipMemcpyAsync(out.cptr + nnzb, &ne, sizeof(int), hipMemcpyHostToDevice, s));
-  DI_CHECK(prefix(tmp, rowcnt, out.rp, nr, s));
-  if (ng) hipLaunchKernelGGL(grads_kernel, dim3(grid_of(ng)), dim3(DI_BLOCK), 0, s, ng, nc, gval_s, out.gpos);
-  hipLaunchKernelGGL(gptr_kernel, dim3(grid_of(nr + 1)), dim3(DI_BLOCK), 0, s, nr, ng, gkey_s, out.gptr);
+  if (!out.sidx || (in.eps && !out.seps) || !out.rp || !out.col || !out.cptr || !out.slot || !out.spos ||
+      !out.gpos || !out.gptr || !out.ddiag)
+    return -1;
+  if (nc)
+    hipLaunchKernelGGL(stencil_kernel, dim3(nwg), dim3(DI_BLOCK), 0, s, nc, n, in.idx, order, out.sidx, in.eps,
+                       out.seps, out.spos, out.slot, out.gpos);
 
+  // 3. block entries of the free pairs in storage order, stably sorted by
+  //    block (r, c); the gradient entries are the diagonal blocks' entries
+  const int nbits = bits_for(n);
+  uint64_t* bkey = tmp.get<uint64_t>(ne);
+  uint64_t* bkey_s = tmp.get<uint64_t>(ne);
+  int32_t* bval = tmp.get<int32_t>(ne);
+  int32_t* bval_s = tmp.get<int32_t>(ne);
+  int32_t* first = tmp.get<int32_t>(ne);
+  int32_t* blk = tmp.get<int32_t>(ne);
+  int32_t* diag = tmp.get<int32_t>(ne);
+  int32_t* dpos = tmp.get<int32_t>(ne + 1);
+  int32_t* rowcnt = tmp.get<int32_t>(nr);
+  int32_t* gcnt = tmp.get<int32_t>(nr);
+  DI_CHECK(tmp.err);
+  if (ne) {
+    hipLaunchKernelGGL(bentries_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, (int)ne, nc, n, nbits, T,
+                       out.sidx, bkey, bval);
+    DI_CHECK(sort_pairs(tmp, bkey, bkey_s, bval, bval_s, ne, 2 * nbits, s));
+  }
+
+  // 4. blocks: starts, indices, pattern, slot map, staging
+  DI_CHECK(hipMemsetAsync(rowcnt, 0, sizeof(int32_t) * std::max(nr, 1), s));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_of(nr)), dim3(DI_BLOCK), 0, s, (long long)nr, -1, out.ddiag);
+  if (ne) {
+    hipLaunchKernelGGL(first_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, (int)ne, nbits, bkey_s, first, diag);
+    DI_CHECK(inclusive(tmp, first, blk, ne, s));
+    DI_CHECK(prefix(tmp, diag, dpos, ne, s));
+    hipLaunchKernelGGL(blocks_kernel, dim3(grid_of(ne)), dim3(DI_BLOCK), 0, s, (int)ne, nc, nbits, T, bkey_s,
+                       bval_s, blk, first, diag, dpos, order, out.spos, out.col, out.cptr, out.slot, rowcnt,
+                       out.ddiag, out.gpos, offdiag);
+  } else {
+    DI_CHECK(hipMemsetAsync(out.cptr, 0, sizeof(int32_t), s));
+  }
+  DI_CHECK(prefix(tmp, rowcnt, out.rp, nr, s));
+  hipLaunchKernelGGL(gcount_kernel, dim3(grid_of(nr)), dim3(DI_BLOCK), 0, s, nr, out.ddiag, out.cptr, gcnt);
+  DI_CHECK(prefix(tmp, gcnt, out.gptr, nr, s));
+
+  int nnzb = 0;
+  if (ne) DI_CHECK(hipMemcpyAsync(&nnzb, blk + ne - 1, sizeof(int), hipMemcpyDeviceToHost, s));
   DI_CHECK(hipGetLastError());
-  DI_CHECK(hipStreamSynchronize(s));  // the temporaries go out of scope
+  DI_CHECK(hipStreamSynchronize(s));  // nnzb; the temporaries go out of scope
   out.nnzb = nnzb;
-  out.nent = ne;
-  out.ngrad = ng;
+  out.nent = (int)ne;
+  out.ngrad = (int)ng;
   return 0;
 }
 
