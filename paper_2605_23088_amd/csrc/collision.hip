@@ -14,11 +14,13 @@
 // 5.1.9).  The step bound is additive CCD (Li, Kaufman, Jiang 2021,
 // "Codimensional Incremental Potential Contact").
 //
-// Broad phase: a uniform grid in hashed cell keys.  The primitives of one
-// side (triangles, or edges) are registered in every cell their box inflated
-// by R covers (keys radix-sorted); every (query primitive, registered entry)
-// of the cells a query's own box covers is listed (count, scan, fill), and
-// one thread per listed pair runs the tests: a pair is a candidate when the
+// Broad phase: a uniform grid.  The primitives of one side (triangles, or
+// edges) are registered in every cell their box inflated by R covers, over
+// the box of cells the registered boxes span: counted per cell, scanned and
+// placed when that box holds at most 2^22 cells, else radix-sorted by cell
+// index; every (query primitive, registered entry) of the cells a query's
+// own box covers is listed (count, scan, fill), and one thread per listed
+// pair runs the tests: a pair is a candidate when the
 // primitives' boxes, each inflated by r, overlap (the exact test); R = 2r (1 +
 // 1e-9) makes the grid a superset of that, and a pair is taken only in the
 // cell that holds the low corner of the two grid boxes' intersection, so each
@@ -29,14 +31,16 @@
 // candidate or a CCD step is computed by the same operations, in the same
 // order, as the textbook definitions written out plainly; the results do
 // not depend on the launch shape.  Output order is fixed: point-triangle
-// pairs by (point, triangle) (the listing order), then edge-edge pairs by
-// (edge, edge) (a radix sort of the hits).
+// pairs by (point, triangle), then edge-edge pairs by (edge, edge): the
+// listing order, each query's candidates being sorted by primitive.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "blockreduce.h"
 #include "contact_math.h"
@@ -53,6 +57,7 @@ constexpr long long CELL_OFF = 1ll << 20;  // cell coordinates in [-2^20, 2^20)
 constexpr int ACCD_MAX_STEPS = 10000;
 constexpr long long MAX_BOX_CELLS = 1 << 16;  // a box over more cells (a non-finite position, or a cell size
                                               // far below the motion) is an error, so every loop is bounded
+constexpr long long DENSE_MAX_CELLS = 1 << 22;  // registrations over more grid cells sort their entries instead
 
 YHD void sub3(const double a[3], const double b[3], double c[3]) {
   c[0] = a[0] - b[0];
@@ -230,8 +235,28 @@ YDEV long long cell_of(double v, double cell) {
   const long long c = f < -(double)CELL_OFF ? -CELL_OFF : (f >= (double)(CELL_OFF - 1) ? CELL_OFF - 1 : (long long)f);
   return c + CELL_OFF;
 }
-YDEV uint64_t cell_key(long long ix, long long iy, long long iz) {
-  return ((uint64_t)ix << 42) | ((uint64_t)iy << 21) | (uint64_t)iz;
+// Grid cells of one registration: the box of cells the registered boxes
+// cover (lowest coordinate and span per axis), a cell's index within it
+// x-major.
+struct CellGrid {
+  int base[3];
+  long long span[3];
+};
+YDEV bool cell_in(const CellGrid& G, long long ix, long long iy, long long iz) {
+  const long long d[3] = {ix - G.base[0], iy - G.base[1], iz - G.base[2]};
+  bool in = true;
+  for (int k = 0; k < 3; ++k) in = in && d[k] >= 0 && d[k] < G.span[k];
+  return in;
+}
+YDEV uint64_t cell_index(const CellGrid& G, long long ix, long long iy, long long iz) {
+  return ((uint64_t)(ix - G.base[0]) * (uint64_t)G.span[1] + (uint64_t)(iy - G.base[1])) * (uint64_t)G.span[2] +
+         (uint64_t)(iz - G.base[2]);
+}
+YDEV void cell_coords(const CellGrid& G, uint64_t c, long long& ix, long long& iy, long long& iz) {
+  iz = (long long)(c % (uint64_t)G.span[2]) + G.base[2];
+  const uint64_t r = c / (uint64_t)G.span[2];
+  iy = (long long)(r % (uint64_t)G.span[1]) + G.base[1];
+  ix = (long long)(r / (uint64_t)G.span[1]) + G.base[0];
 }
 
 template <int K>
@@ -257,20 +282,41 @@ YDEV long long box_cells(const double lo[3], const double hi[3], double cell, in
   return c;
 }
 
+// Cells per registered box, and the range of cells they cover (range[0..2]
+// lowest, range[3..5] highest coordinate per axis), reduced over the
+// wavefront first (one atomic per wavefront and value).
 template <int K>
 __global__ void reg_count_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell, int32_t* cnt,
-                                 int* err) {
+                                 int* err, int* range) {
   const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (j >= m) return;
-  int ids[K];
-  load_ids<K>(prims, m, j, ids);
-  double lo[3], hi[3];
-  pbox<K>(X, ids, R, lo, hi);
-  cnt[j] = (int32_t)box_cells(lo, hi, cell, err);
+  int r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  if (j < m) {
+    int ids[K];
+    load_ids<K>(prims, m, j, ids);
+    double lo[3], hi[3];
+    pbox<K>(X, ids, R, lo, hi);
+    const long long c = box_cells(lo, hi, cell, err);
+    cnt[j] = (int32_t)c;
+    if (c)
+      for (int k = 0; k < 3; ++k) {
+        r[k] = (int)cell_of(lo[k], cell);
+        r[3 + k] = (int)cell_of(hi[k], cell);
+      }
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 3; ++k) {
+      r[k] = min(r[k], __shfl_xor(r[k], o));
+      r[3 + k] = max(r[3 + k], __shfl_xor(r[3 + k], o));
+    }
+  if ((threadIdx.x & 63) == 0 && r[0] != INT_MAX)
+    for (int k = 0; k < 3; ++k) {
+      atomicMin(&range[k], r[k]);
+      atomicMax(&range[3 + k], r[3 + k]);
+    }
 }
 
 template <int K>
-__global__ void reg_fill_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell,
+__global__ void reg_fill_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell, CellGrid G,
                                 const int32_t* off, uint64_t* keys, int32_t* vals, int* err) {
   const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
   if (j >= m) return;
@@ -288,10 +334,95 @@ __global__ void reg_fill_kernel(int m, const int32_t* prims, CdPositions X, doub
   for (long long z = l[2]; z <= h[2]; ++z)
     for (long long y = l[1]; y <= h[1]; ++y)
       for (long long x = l[0]; x <= h[0]; ++x) {
-        keys[o] = cell_key(x, y, z);
+        keys[o] = cell_index(G, x, y, z);
         vals[o] = j;
         ++o;
       }
+}
+
+// Dense registration (the grid's cells counted directly): pass 1 counts the
+// entries of every cell, pass 2 places them (in any order inside a cell;
+// cell_sort_kernel orders them).
+template <int K, bool PLACE>
+__global__ void reg_dense_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell, CellGrid G,
+                                 int32_t* count, int32_t* cursor, uint64_t* keys, int32_t* vals, int* err) {
+  const int j = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (j >= m) return;
+  int ids[K];
+  load_ids<K>(prims, m, j, ids);
+  double lo[3], hi[3];
+  pbox<K>(X, ids, R, lo, hi);
+  if (box_cells(lo, hi, cell, err) == 0) return;
+  long long l[3], h[3];
+  for (int k = 0; k < 3; ++k) {
+    l[k] = cell_of(lo[k], cell);
+    h[k] = cell_of(hi[k], cell);
+  }
+  for (long long z = l[2]; z <= h[2]; ++z)
+    for (long long y = l[1]; y <= h[1]; ++y)
+      for (long long x = l[0]; x <= h[0]; ++x) {
+        const uint64_t c = cell_index(G, x, y, z);
+        if constexpr (PLACE) {
+          const int o = atomicAdd(&cursor[c], 1);
+          keys[o] = c;
+          vals[o] = j;
+        } else {
+          atomicAdd(&count[c], 1);
+        }
+      }
+}
+
+// The edge-edge outputs in (edge, partner) order: out[k] = in[perm[k]].
+__global__ void gather_kernel(int m, const int32_t* __restrict__ perm, const int32_t* __restrict__ ti,
+                              const int32_t* __restrict__ ii, int istride, const double* __restrict__ ei,
+                              int32_t* __restrict__ to, int32_t* __restrict__ io, int ostride,
+                              double* __restrict__ eo) {
+  const int k = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (k >= m) return;
+  const int s = perm[k];
+  to[k] = ti[s];
+  eo[k] = ei[s];
+  for (int a = 0; a < 4; ++a) io[(size_t)a * ostride + k] = ii[(size_t)a * istride + s];
+}
+
+__global__ void iota32_kernel(int m, int32_t* v) {
+  const int i = blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (i < m) v[i] = i;
+}
+
+// The entries of every cell in primitive order.  A cell holds the few
+// primitives whose boxes reach it, each once: up to CELL_SORT_REGS of them are
+// loaded into registers and each is written at its rank (the count of smaller
+// ones; independent comparisons, no chain of dependent loads); a fuller cell
+// is insertion-sorted in place.
+constexpr int CELL_SORT_REGS = 64;
+__global__ void cell_sort_kernel(long long ncell, const int32_t* __restrict__ cstart, int32_t* __restrict__ vals) {
+  const long long c = (long long)blockIdx.x * DI_BLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  const int e0 = cstart[c], k = cstart[c + 1] - e0;
+  if (k <= 1) return;
+  if (k <= CELL_SORT_REGS) {
+    int v[CELL_SORT_REGS];
+#pragma unroll
+    for (int a = 0; a < CELL_SORT_REGS; ++a) v[a] = a < k ? vals[e0 + a] : INT_MAX;
+#pragma unroll
+    for (int a = 0; a < CELL_SORT_REGS; ++a) {
+      int r = 0;
+#pragma unroll
+      for (int b = 0; b < CELL_SORT_REGS; ++b) r += v[b] < v[a] ? 1 : 0;
+      if (a < k) vals[e0 + r] = v[a];
+    }
+    return;
+  }
+  for (int a = e0 + 1; a < e0 + k; ++a) {
+    const int v = vals[a];
+    int b = a - 1;
+    while (b >= e0 && vals[b] > v) {
+      vals[b + 1] = vals[b];
+      --b;
+    }
+    vals[b + 1] = v;
+  }
 }
 
 YDEV int lower_bound(const uint64_t* keys, int n, uint64_t key) {
@@ -393,8 +524,10 @@ struct QueryArgs {
   CdPositions X;
   double r, R, cell;
   int nreg;
-  const uint64_t* keys;  // sorted cell keys of the registered primitives
+  const uint64_t* keys;  // cell of every registered entry (entries grouped by cell, cells ascending)
   const int32_t* vals;   // their primitive ids
+  CellGrid grid;         // the registration's cells
+  const int32_t* cstart; // [cells + 1] first entry of every cell (dense registration), else null
   const double* len2;    // squared rest lengths of the edges (EE mollifier) or null
   double dhat, kappa;
   int classic;
@@ -408,11 +541,12 @@ struct QueryArgs {
   int32_t* hit;          // [ncand] 1 if the candidate gives a stencil (count pass)
   const int32_t* hoff;   // [ncand + 1] output position of each hit (fill pass)
   int out0;              // first output of this query set
+  uint64_t* okey;        // edge-edge outputs: (edge, partner) sort key, edge << kbits | partner
+  int kbits;             // bits of an edge index
   int cap;               // stride of the output idx array
   int32_t* otype;
   int32_t* oidx;         // [4][cap]
   double* oeps;
-  uint64_t* okey;        // edge-edge outputs: (edge, partner) sort key
   double* part;          // per-workgroup energy sums / CCD minima
   int* err;              // set when a box spans too many cells
 };
@@ -497,7 +631,7 @@ YDEV bool query_cells(const QueryArgs& q, int i, int (&ia)[KA], double (&lo0)[3]
 
 // Pass 1 (WRITE = false): candidates per query, the registered entries of the
 // cells its box covers; pass 2 (WRITE = true): the (query, entry) list, query
-// by query, cells in (z, y, x) order, entries in key order.
+// by query, cells in (z, y, x) order, entries in primitive order.
 template <int KA, bool WRITE>
 __global__ __launch_bounds__(CD_BLOCK) void cand_kernel(QueryArgs q) {
   const int i = blockIdx.x * CD_BLOCK + threadIdx.x;
@@ -511,8 +645,18 @@ __global__ __launch_bounds__(CD_BLOCK) void cand_kernel(QueryArgs q) {
     for (long long z = cl[2]; z <= ch[2]; ++z)
       for (long long y = cl[1]; y <= ch[1]; ++y)
         for (long long x = cl[0]; x <= ch[0]; ++x) {
-          const uint64_t key = cell_key(x, y, z);
-          for (int e = lower_bound(q.keys, q.nreg, key); e < q.nreg && q.keys[e] == key; ++e) {
+          if (!cell_in(q.grid, x, y, z)) continue;  // no registered entry there
+          const uint64_t key = cell_index(q.grid, x, y, z);
+          int e0, e1;
+          if (q.cstart) {
+            e0 = q.cstart[key];
+            e1 = q.cstart[key + 1];
+          } else {
+            e0 = lower_bound(q.keys, q.nreg, key);
+            e1 = e0;
+            while (e1 < q.nreg && q.keys[e1] == key) ++e1;
+          }
+          for (int e = e0; e < e1; ++e) {
             if constexpr (WRITE) {
               q.cq[o] = i;
               q.ce[o] = e;
@@ -538,9 +682,8 @@ __global__ __launch_bounds__(CD_BLOCK) void pair_kernel(QueryArgs q) {
   if (t < q.ncand) {
     const int i = q.cq[t], e = q.ce[t];
     const int j = q.vals[e];
-    const uint64_t key = q.keys[e];
-    const long long x = (long long)((key >> 42) & 0x1FFFFFull), y = (long long)((key >> 21) & 0x1FFFFFull),
-                    z = (long long)(key & 0x1FFFFFull);
+    long long x, y, z;
+    cell_coords(q.grid, q.keys[e], x, y, z);
     bool take = !(q.ee && j <= i);
     int ia[KA], ib[KB];
     load_ids<KA>(q.pa, q.ma, i, ia);
@@ -601,7 +744,7 @@ __global__ __launch_bounds__(CD_BLOCK) void pair_kernel(QueryArgs q) {
             q.otype[o] = type;
             for (int a = 0; a < 4; ++a) q.oidx[(size_t)a * q.cap + o] = ids[a];
             q.oeps[o] = eps;
-            if (EEP) q.okey[q.hoff[t]] = ((uint64_t)i << 32) | (uint64_t)j;
+            if (EEP) q.okey[q.hoff[t]] = ((uint64_t)i << q.kbits) | (uint64_t)j;
           } else if constexpr (MODE == Q_ENERGY) {
             double P4[4][3] = {};
             for (int a = 0; a < 4; ++a)
@@ -623,24 +766,6 @@ __global__ __launch_bounds__(CD_BLOCK) void pair_kernel(QueryArgs q) {
     const double tm = block_min<CD_BLOCK>(tmin, lds);
     if (threadIdx.x == 0) q.part[blockIdx.x] = tm;
   }
-}
-
-// The edge-edge outputs in (edge, partner) order: out[k] = in[perm[k]].
-__global__ void gather_kernel(int m, const int32_t* __restrict__ perm, const int32_t* __restrict__ ti,
-                              const int32_t* __restrict__ ii, int istride, const double* __restrict__ ei,
-                              int32_t* __restrict__ to, int32_t* __restrict__ io, int ostride,
-                              double* __restrict__ eo) {
-  const int k = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (k >= m) return;
-  const int s = perm[k];
-  to[k] = ti[s];
-  eo[k] = ei[s];
-  for (int a = 0; a < 4; ++a) io[(size_t)a * ostride + k] = ii[(size_t)a * istride + s];
-}
-
-__global__ void iota32_kernel(int m, int32_t* v) {
-  const int k = blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (k < m) v[k] = k;
 }
 
 // part[0] = sum (kind 0) or min (kind 1) of part[0 .. m)
@@ -683,6 +808,8 @@ struct Reg {
   int n = 0;
   uint64_t* keys = nullptr;
   int32_t* vals = nullptr;
+  CellGrid grid{};
+  int32_t* cstart = nullptr;
 };
 
 template <int K>
@@ -692,26 +819,60 @@ int register_side(int m, const int32_t* prims, const CdPositions& X, double R, d
   if (m == 0) return 0;
   int32_t* cnt = tmp.get<int32_t>(m);
   int32_t* off = tmp.get<int32_t>(m + 1);
+  int* range = tmp.get<int>(6);
   CD_CHECK(tmp.err);
+  const int range0[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  CD_CHECK(hipMemcpyAsync(range, range0, sizeof(range0), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(reg_count_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell,
-                     cnt, err);
+                     cnt, err, range);
   CD_CHECK(devsort::prefix(tmp, cnt, off, m, s));
-  int h[2] = {0, 0};
+  int h[2] = {0, 0}, rg[6] = {0, 0, 0, 0, 0, 0};
   CD_CHECK(hipMemcpyAsync(&h[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipMemcpyAsync(&h[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(rg, range, sizeof(rg), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipStreamSynchronize(s));
   if (h[1]) return -2;
   const int total = h[0];
   if (total <= 0) return -2;
-  uint64_t* keys = tmp.get<uint64_t>(total);
-  int32_t* vals = tmp.get<int32_t>(total);
-  CD_CHECK(tmp.err);
+  CellGrid G{};
+  double ncell = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    G.base[k] = rg[k];
+    G.span[k] = (long long)rg[3 + k] - rg[k] + 1;
+    ncell *= (double)G.span[k];
+  }
   uint64_t* ks = static_cast<uint64_t*>(alloc(which, sizeof(uint64_t) * (size_t)total));
   int32_t* vs = static_cast<int32_t*>(alloc(which + 1, sizeof(int32_t) * (size_t)total));
   if (!ks || !vs) return -1;
-  hipLaunchKernelGGL(reg_fill_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell, off,
-                     keys, vals, err);
-  CD_CHECK(devsort::sort_pairs(tmp, keys, ks, vals, vs, total, 63, s));
+  long long dense_max = DENSE_MAX_CELLS;
+  if (const char* ev = std::getenv("YASPS_GRID_DENSE_MAX")) dense_max = std::atoll(ev);  // test override
+  if (ncell <= (double)dense_max) {
+    // dense: count per cell, scan, place
+    const long long nc = (long long)ncell;
+    int32_t* count = tmp.get<int32_t>(nc);
+    int32_t* cursor = tmp.get<int32_t>(nc + 1);
+    CD_CHECK(tmp.err);
+    int32_t* cs = static_cast<int32_t*>(alloc(which + 2, sizeof(int32_t) * (size_t)(nc + 1)));
+    if (!cs) return -1;
+    CD_CHECK(hipMemsetAsync(count, 0, sizeof(int32_t) * (size_t)nc, s));
+    hipLaunchKernelGGL((reg_dense_kernel<K, false>), dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X,
+                       R, cell, G, count, nullptr, nullptr, nullptr, err);
+    CD_CHECK(devsort::prefix(tmp, count, cs, nc, s));
+    CD_CHECK(hipMemcpyAsync(cursor, cs, sizeof(int32_t) * (size_t)(nc + 1), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((reg_dense_kernel<K, true>), dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X,
+                       R, cell, G, nullptr, cursor, ks, vs, err);
+    hipLaunchKernelGGL(cell_sort_kernel, dim3(devsort::grid_of(nc)), dim3(DI_BLOCK), 0, s, nc, cs, vs);
+    out.cstart = cs;
+  } else {
+    // sparse: keys per (primitive, cell), stably sorted by cell
+    uint64_t* keys = tmp.get<uint64_t>(total);
+    int32_t* vals = tmp.get<int32_t>(total);
+    CD_CHECK(tmp.err);
+    hipLaunchKernelGGL(reg_fill_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell, G,
+                       off, keys, vals, err);
+    CD_CHECK(devsort::sort_pairs(tmp, keys, ks, vals, vs, total, devsort::bits_for((long long)(ncell - 1.0)), s));
+  }
+  out.grid = G;
   out.n = total;
   out.keys = ks;
   out.vals = vs;
@@ -734,6 +895,9 @@ QueryArgs query_args(const CdSurface& S, const CdPositions& X, bool ee, const Re
   q.nreg = reg.n;
   q.keys = reg.keys;
   q.vals = reg.vals;
+  q.grid = reg.grid;
+  q.cstart = reg.cstart;
+  q.kbits = devsort::bits_for(std::max(S.ne, 1));
   q.len2 = S.len2;
   q.dhat = dhat;
   return q;
@@ -890,7 +1054,8 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
   out.idx = static_cast<int32_t*>(alloc(CD_IDX, 4 * sizeof(int32_t) * (size_t)cap));
   out.eps = static_cast<double*>(alloc(CD_EPS, sizeof(double) * (size_t)cap));
   if (!out.type || !out.idx || !out.eps) return -1;
-  // point-triangle outputs first (already in (point, triangle) order), then the
+  // point-triangle outputs first (a point's box is one cell, whose entries are
+  // in triangle order: the listing is in (point, triangle) order), then the
   // edge-edge ones, written to a side buffer and put in (edge, partner) order
   const int me = std::max(m[1], 1);
   int32_t* te = tmp.get<int32_t>(me);
@@ -920,7 +1085,7 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
     qe.okey = key;
     launch_pairs<Q_FILL>(qe, s);
     hipLaunchKernelGGL(iota32_kernel, dim3(devsort::grid_of(m[1])), dim3(DI_BLOCK), 0, s, m[1], perm);
-    CD_CHECK(devsort::sort_pairs(tmp, key, key_s, perm, perm_s, m[1], 64, s));
+    CD_CHECK(devsort::sort_pairs(tmp, key, key_s, perm, perm_s, m[1], 2 * qe.kbits, s));
     hipLaunchKernelGGL(gather_kernel, dim3(devsort::grid_of(m[1])), dim3(DI_BLOCK), 0, s, m[1], perm_s, te, ie, m[1],
                        ee, out.type + m[0], out.idx + m[0], total, out.eps + m[0]);
   }

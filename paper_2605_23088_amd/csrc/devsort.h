@@ -49,15 +49,35 @@ struct Temp {
   }
 };
 
-template <class K, class V>
-hipError_t sort_pairs(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long long m, int end_bit, hipStream_t s) {
-  if (m == 0) return hipSuccess;
+// Stable radix sort of (key, value) pairs over key bits [0, end_bit).  rocPRIM
+// sorts up to 2^20 items by merging sorted blocks (about two launches per
+// doubling of the sorted run past 1024 items) unless told otherwise; its
+// one-sweep LSD sort takes about three launches per 8-bit digit.  The cheaper
+// of the two by that count is taken (one-sweep for keys of few bits).
+template <class Config, class K, class V>
+hipError_t sort_pairs_with(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long long m, int end_bit,
+                           hipStream_t s) {
   size_t bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
+  hipError_t e =
+      rocprim::radix_sort_pairs<Config>(nullptr, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
   if (e != hipSuccess) return e;
   void* store = tmp.get<char>(bytes);
   if (tmp.err != hipSuccess) return tmp.err;
-  return rocprim::radix_sort_pairs(store, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
+  return rocprim::radix_sort_pairs<Config>(store, bytes, ki, ko, vi, vo, (size_t)m, 0u, (unsigned)end_bit, s);
+}
+
+template <class K, class V>
+hipError_t sort_pairs(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long long m, int end_bit, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  int merges = 0;
+  for (long long run = 1024; run < m; run *= 2) ++merges;
+  const int digits = (end_bit + 7) / 8;
+  if (m <= (1ll << 20) && 3 * digits + 2 < 2 * merges + 1) {
+    using onesweep = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                rocprim::default_config, 0>;
+    return sort_pairs_with<onesweep>(tmp, ki, ko, vi, vo, m, end_bit, s);
+  }
+  return sort_pairs_with<rocprim::default_config>(tmp, ki, ko, vi, vo, m, end_bit, s);
 }
 
 // out[0] = 0, out[k + 1] = in[0] + ... + in[k]  (k < m)

@@ -358,9 +358,10 @@ struct CdOutput {
   int32_t* idx = nullptr;  // [4][n] (stride n)
   double* eps = nullptr;   // [n] mollifier thresholds (0 for the non-EE stencils)
 };
-// Grow-only buffers of the collision module: sorted cell keys / ids of the
-// triangles and of the edges, and the detected stencils.
-enum { CD_REG_T, CD_REG_T_V, CD_REG_E, CD_REG_E_V, CD_TYPE, CD_IDX, CD_EPS, CD_COUNT };
+// Grow-only buffers of the collision module: the registrations of the
+// triangles and of the edges (cell and primitive of every entry, first entry
+// of every cell), and the detected stencils.
+enum { CD_REG_T, CD_REG_T_V, CD_REG_T_C, CD_REG_E, CD_REG_E_V, CD_REG_E_C, CD_TYPE, CD_IDX, CD_EPS, CD_COUNT };
 using CdAlloc = std::function<void*(int, size_t)>;
 // Contact stencils at X (squared distance below dhat), in the fixed order
 // (point-triangle pairs by (point, triangle), then edge-edge pairs by (edge,

@@ -46,9 +46,9 @@ __global__ void plan_rows_kernel(int n, const int32_t* __restrict__ rp, int32_t*
 }
 
 // compressed rows, chunk heads, and the products to sort: block k's row
-// product at 2k (key (chunk of k, row)), its transposed product at 2k + 1
-// (key (chunk of k, column) off the diagonal, the pad on it)
-__global__ void plan_fill_kernel(int n, int ch, uint64_t pad, const int32_t* __restrict__ rp,
+// product at 2k (key chunk of k << rbits | row), its transposed product at
+// 2k + 1 (key chunk of k << rbits | column off the diagonal, the pad on it)
+__global__ void plan_fill_kernel(int n, int ch, int rbits, uint64_t pad, const int32_t* __restrict__ rp,
                                  const int32_t* __restrict__ col, const int32_t* __restrict__ mpos,
                                  int32_t* __restrict__ rl, int32_t* __restrict__ m0, uint64_t* __restrict__ key,
                                  int32_t* __restrict__ val) {
@@ -62,15 +62,15 @@ __global__ void plan_fill_kernel(int n, int ch, uint64_t pad, const int32_t* __r
   for (int k = a; k < b; ++k) {
     const uint64_t c = (uint64_t)(k / ch);
     const int j = col[k];
-    key[2 * (size_t)k] = (c << 32) | (uint64_t)r;
+    key[2 * (size_t)k] = (c << rbits) | (uint64_t)r;
     val[2 * (size_t)k] = 2 * k;
-    key[2 * (size_t)k + 1] = j != r ? ((c << 32) | (uint64_t)j) : pad;
+    key[2 * (size_t)k + 1] = j != r ? ((c << rbits) | (uint64_t)j) : pad;
     val[2 * (size_t)k + 1] = 2 * k + 1;
   }
 }
 
 // first sorted entry of every chunk; 1 where a new (chunk, target) starts
-__global__ void plan_starts_kernel(long long m, const uint64_t* __restrict__ key, uint64_t pad,
+__global__ void plan_starts_kernel(long long m, int rbits, const uint64_t* __restrict__ key, uint64_t pad,
                                    int32_t* __restrict__ cstart, int32_t* __restrict__ first) {
   const long long s = (long long)blockIdx.x * DI_BLOCK + threadIdx.x;
   if (s >= m) return;
@@ -78,12 +78,13 @@ __global__ void plan_starts_kernel(long long m, const uint64_t* __restrict__ key
   const bool real = k != pad;
   const bool head = real && (s == 0 || key[s - 1] != k);
   first[s] = head ? 1 : 0;
-  if (real && (s == 0 || (key[s - 1] >> 32) != (k >> 32))) cstart[(int)(k >> 32)] = (int)s;
+  if (real && (s == 0 || (key[s - 1] >> rbits) != (k >> rbits))) cstart[(int)(k >> rbits)] = (int)s;
 }
 
 // LDS entries of every product (into the packed block words), target ends,
 // chunk target starts, target rows
-__global__ void plan_place_kernel(long long m, const uint64_t* __restrict__ key, const int32_t* __restrict__ val,
+__global__ void plan_place_kernel(long long m, int rbits, const uint64_t* __restrict__ key,
+                                  const int32_t* __restrict__ val,
                                   uint64_t pad, const int32_t* __restrict__ cstart, const int32_t* __restrict__ tq,
                                   uint32_t* __restrict__ ypos, uint32_t* __restrict__ tpos,
                                   uint16_t* __restrict__ tend, int32_t* __restrict__ tb, int32_t* __restrict__ trow,
@@ -92,7 +93,7 @@ __global__ void plan_place_kernel(long long m, const uint64_t* __restrict__ key,
   if (s >= m) return;
   const uint64_t k = key[s];
   if (k == pad) return;
-  const int c = (int)(k >> 32);
+  const int c = (int)(k >> rbits);
   const int pos = (int)(s - cstart[c]);
   const int v = val[s];
   (v & 1 ? tpos : ypos)[v >> 1] = (uint32_t)pos;
@@ -101,7 +102,7 @@ __global__ void plan_place_kernel(long long m, const uint64_t* __restrict__ key,
     tend[t] = (uint16_t)(pos + 1);
     atomicMax(max_entries, pos + 1);
   }
-  if (s == 0 || key[s - 1] != k) trow[t] = (int)(k & 0xffffffffu);
+  if (s == 0 || key[s - 1] != k) trow[t] = (int)(k & ((1ull << rbits) - 1));
   if (s == cstart[c]) tb[c] = t;
 }
 
@@ -177,8 +178,9 @@ int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, cons
   const int ch = spmv_chunk_for(nblk);
   const int nchunk = (nblk + ch - 1) / ch;
   const long long m = 2ll * nblk;  // a row product and a transposed product (or the pad) per block
-  const uint64_t pad = (uint64_t)nchunk << 32;
-  const int kbits = 32 + bits_for(nchunk);
+  const int rbits = bits_for(n);
+  const uint64_t pad = (uint64_t)nchunk << rbits;
+  const int kbits = rbits + bits_for(nchunk);
   Temp tmp;
   tmp.arena = static_cast<char*>(arena);
   tmp.cap = arena_bytes;
@@ -213,11 +215,12 @@ int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, cons
 
   hipLaunchKernelGGL(plan_rows_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, rp, has);
   PL_CHECK(prefix(tmp, has, mpos, n, s));
-  hipLaunchKernelGGL(plan_fill_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, ch, pad, rp, col, mpos, rl, m0,
-                     key, val);
+  hipLaunchKernelGGL(plan_fill_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, ch, rbits, pad, rp, col, mpos, rl,
+                     m0, key, val);
   PL_CHECK(sort_pairs(tmp, key, key_s, val, val_s, m, kbits, s));
   PL_CHECK(hipMemsetAsync(scal, 0, 4 * sizeof(int), s));
-  hipLaunchKernelGGL(plan_starts_kernel, dim3(grid_of(m)), dim3(DI_BLOCK), 0, s, m, key_s, pad, cstart, first);
+  hipLaunchKernelGGL(plan_starts_kernel, dim3(grid_of(m)), dim3(DI_BLOCK), 0, s, m, rbits, key_s, pad, cstart,
+                     first);
   PL_CHECK(inclusive(tmp, first, tq, m, s));
   int head[2] = {0, 0};  // compressed rows, targets
   PL_CHECK(hipMemcpyAsync(&head[0], mpos + n, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -233,8 +236,8 @@ int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, cons
   int32_t* tid_s = tmp.get<int32_t>(nt);
   PL_CHECK(tmp.err);
   if (!tend || !wslot || !hptr) return -1;
-  hipLaunchKernelGGL(plan_place_kernel, dim3(grid_of(m)), dim3(DI_BLOCK), 0, s, m, key_s, val_s, pad, cstart, tq,
-                     ypos, tpos, tend, tb, trow, scal);
+  hipLaunchKernelGGL(plan_place_kernel, dim3(grid_of(m)), dim3(DI_BLOCK), 0, s, m, rbits, key_s, val_s, pad, cstart,
+                     tq, ypos, tpos, tend, tb, trow, scal);
   hipLaunchKernelGGL(plan_meta_kernel, dim3(grid_of(n)), dim3(DI_BLOCK), 0, s, n, ch, rp, col, mpos, m0, ypos, tpos,
                      meta);
   PL_CHECK(hipMemcpyAsync(tb + nchunk, &head[1], sizeof(int), hipMemcpyHostToDevice, s));

@@ -46,6 +46,33 @@ def test_detect_matches_oracle(gap):
     assert info["energy"] == pytest.approx(ev["E"], rel=1e-11)
 
 
+@pytest.mark.parametrize("dense_max", [None, "0"])
+@pytest.mark.parametrize("cell_scale", [1.0, 0.3])
+def test_detect_and_ccd_independent_of_the_grid(monkeypatch, dense_max, cell_scale):
+    """Counted (dense) and sorted registrations, coarse and fine cells (boxes
+    over many cells, so one pair is listed in several cells): the same
+    stencil list as the oracle, bit for bit and in its order, and the same
+    CCD bound."""
+    from paper_2605_23088_amd.yasps import Yasps
+    if dense_max is not None:
+        monkeypatch.setenv("YASPS_GRID_DENSE_MAX", dense_max)
+    p = synth.drop_scene(gap=0.004)
+    S = col.Surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["n_free"], p["surf_len2"])
+    g = Yasps(p, contacts=False)
+    g.set_surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["surf_len2"], cell_scale * p["cell"])
+    st = ts.Stepper(p, S)
+    ct_o, ci_o, eps_o = S.detect(st.xall(p["x0"]), p["dhat"])
+    ct, ci, eps = g.detect(dev(p["x0"]))
+    assert len(ct_o) > 20
+    assert np.array_equal(ct, ct_o) and np.array_equal(ci, ci_o) and np.array_equal(eps, eps_o)
+    rng = np.random.default_rng(7)
+    d = np.zeros((p["n_free"], 3))
+    d[:, 2] = -0.05
+    d += rng.normal(0.0, 0.01, d.shape)
+    t_o = S.ccd(st.xall(p["x0"]), np.concatenate([d, np.zeros_like(p["x_fixed"])]), 1.0, 0.1, p["dhat"])
+    assert g.ccd(dev(p["x0"]), dev(d), 1.0, 0.1) == t_o
+
+
 def test_detect_with_nothing_in_range():
     p, S, g = make(gap=0.5)
     ct, ci, eps = g.detect(dev(p["x0"]))
