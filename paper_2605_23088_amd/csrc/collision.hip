@@ -284,7 +284,7 @@ YDEV long long box_cells(const double lo[3], const double hi[3], double cell, in
 
 // Cells per registered box, and the range of cells they cover (range[0..2]
 // lowest, range[3..5] highest coordinate per axis), reduced over the
-// wavefront first (one atomic per wavefront and value).
+// workgroup first (one atomic per workgroup and value).
 template <int K>
 __global__ void reg_count_kernel(int m, const int32_t* prims, CdPositions X, double R, double cell, int32_t* cnt,
                                  int* err, int* range) {
@@ -308,11 +308,22 @@ __global__ void reg_count_kernel(int m, const int32_t* prims, CdPositions X, dou
       r[k] = min(r[k], __shfl_xor(r[k], o));
       r[3 + k] = max(r[3 + k], __shfl_xor(r[3 + k], o));
     }
-  if ((threadIdx.x & 63) == 0 && r[0] != INT_MAX)
-    for (int k = 0; k < 3; ++k) {
-      atomicMin(&range[k], r[k]);
-      atomicMax(&range[3 + k], r[3 + k]);
-    }
+  __shared__ int wr[DI_BLOCK / 64][6];
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; ++k) wr[threadIdx.x >> 6][k] = r[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < DI_BLOCK / 64; ++w)
+      for (int k = 0; k < 3; ++k) {
+        r[k] = min(r[k], wr[w][k]);
+        r[3 + k] = max(r[3 + k], wr[w][3 + k]);
+      }
+    if (r[0] != INT_MAX)
+      for (int k = 0; k < 3; ++k) {
+        atomicMin(&range[k], r[k]);
+        atomicMax(&range[3 + k], r[3 + k]);
+      }
+  }
 }
 
 template <int K>
