@@ -192,6 +192,7 @@ struct yasps_ctx {
   // during an evaluation (fork / join through the two events)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_eval = nullptr;  // after an evaluation's read-back copies (yasps_newton_step)
   Part pd;
   std::vector<Group> groups;
   int32_t *c_idx = nullptr, *spos_c = nullptr, *gpos_c = nullptr, *cptr_d = nullptr, *gptr_d = nullptr,
@@ -594,6 +595,7 @@ void yasps_destroy(yasps_ctx* ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_eval) (void)hipEventDestroy(ctx->ev_eval);
   delete ctx;
 }
 
@@ -644,7 +646,8 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
   // default priority, non-blocking: ordered against c->stream by events only
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_eval, hipEventDisableTiming) != hipSuccess)
     return bail(fail(c, YASPS_E_HIP, "stream / event creation"));
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "hipGetDevice failed"));
   {  // device address of the fixed workspace of yasps_pcg_noalloc (once per device; a
@@ -1157,7 +1160,12 @@ namespace {
 
 // Launches every evaluation kernel at x and the final reductions; fills host
 // scalars [E_inertia, E_elastic, E_contact, min_d, n_active] and flags.
-yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info* info) {
+yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info);
+
+// Launches the evaluation and the read-back of its sums and flags; unless
+// `defer`, waits for them and returns eval_collect's result, else returns once
+// launched (the caller calls eval_collect later).
+yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info* info, bool defer = false) {
   const bool exact = (flags & YASPS_EXACT) != 0;
   HIPCHK(c, hipMemsetAsync(c->flags, 0, 4, c->stream));
   if (!c->prof.on && (!c->groups.empty() || c->nbc)) HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
@@ -1212,7 +1220,15 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
   launch_finalize(5, L.off, c->parts, kinds, c->scal, c->stream);
   HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->host_scal + 8, c->flags, 4, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_eval, c->stream));
+  if (defer) return YASPS_OK;
+  return eval_collect(c, info);
+}
+
+// The evaluation's energies, minimum distance, active count and status once
+// its read-back (ev_eval) has completed.
+yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info) {
+  HIPCHK(c, hipEventSynchronize(c->ev_eval));
   c->prof.collect();
   uint32_t f;
   std::memcpy(&f, c->host_scal + 8, 4);
@@ -1264,8 +1280,8 @@ yasps_status run_assemble(yasps_ctx* c, double shift = 0.0) {
   return YASPS_OK;
 }
 
-// energy and feasibility at x_trial = x + alpha p; returns E and whether feasible
-yasps_status trial_energy(yasps_ctx* c, const double* x0, const double* xt, double* E, bool* feasible) {
+// energy terms and infeasible count at xt into scal[0..4] (launches only)
+yasps_status trial_energy_launch(yasps_ctx* c, const double* x0, const double* xt) {
   const PartsLayout L = parts_layout(c);
   c->prof.begin(YASPS_K_LINESEARCH);
   InertiaArgs ia = inertia_args(c, xt);
@@ -1295,6 +1311,13 @@ yasps_status trial_energy(yasps_ctx* c, const double* x0, const double* xt, doub
   HIPCHK(c, hipGetLastError());
   const int kinds[5] = {0, 0, 0, 1, 0};
   launch_finalize(5, L.off, c->parts, kinds, c->scal, c->stream);
+  return YASPS_OK;
+}
+
+// energy and feasibility at x_trial = x + alpha p; returns E and whether feasible
+yasps_status trial_energy(yasps_ctx* c, const double* x0, const double* xt, double* E, bool* feasible) {
+  const yasps_status s = trial_energy_launch(c, x0, xt);
+  if (s) return s;
   HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->prof.collect();
@@ -1418,13 +1441,16 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   yasps_newton_info ni{};
   HIPCHK(c, hipEventRecord(ev[0], c->stream));
   yasps_eval_info ei{};
-  yasps_status s = run_eval(c, x, p.hessian, &ei);
+  yasps_status s = run_eval(c, x, p.hessian, nullptr, true);
   if (s) return s;
   HIPCHK(c, hipEventRecord(ev[1], c->stream));
   s = run_assemble(c, p.shift);
   if (s) return s;
   HIPCHK(c, hipEventRecord(ev[2], c->stream));
   launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);
+  // the evaluation's sums and status (read back while the assembly runs)
+  s = eval_collect(c, &ei);
+  if (s) return s;
   double rel = 0.0;
   int status = 0;
   const int it = pcg_solve(pcg_matrix(c), c->b_tmp, c->p_dir, p.rtol, p.max_iter, c->prm.precision == YASPS_MIXED,
@@ -1437,7 +1463,10 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   ni.cg_rel_residual = rel;
   ni.cg_status = status;
   if (status == YASPS_E_BREAKDOWN) return fail(c, YASPS_E_BREAKDOWN, "PCG breakdown: p^T H p <= 0");
-  // max |p_v|, g . p and max |g_v| on the device
+  // max |p_v|, g . p and max |g_v| into scal[8..10], the step bound alpha_0
+  // into scal[11] and the first trial at x + alpha_0 p, all on the device
+  // before one read-back
+  const bool contacts = c->nc > 0 || c->nbc > 0;
   {
     const int nb = grid_of(c->n, RED_BLOCK);
     const int nd = std::min(nb, 1024);
@@ -1446,13 +1475,20 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     launch_max_norm3(c->n, c->grad, c->parts + nb + nd, nb, c->stream);
     int off[4] = {0, nb, nb + nd, 2 * nb + nd};
     int kind[3] = {2, 0, 2};
-    launch_finalize(3, off, c->parts, kind, c->scal, c->stream);
-    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    launch_finalize(3, off, c->parts, kind, c->scal + 8, c->stream);
+    // the evaluation's minimum distance is still in scal[3]
+    launch_step_bound(c->scal + 3, c->scal + 8, contacts ? 1 : 0, c->scal + 11, c->stream);
+    launch_axpy_to_dev(3 * c->n, x, c->scal + 11, c->p_dir, c->x_trial, c->stream);
   }
+  s = trial_energy_launch(c, x, c->x_trial);
+  if (s) return s;
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, 12 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  const double pmax = c->host_scal[0];
-  const double gp = c->host_scal[1];
-  ni.grad_max = c->host_scal[2];
+  c->prof.collect();
+  const double* h = c->host_scal;
+  const double pmax = h[8];
+  const double gp = h[9];
+  ni.grad_max = h[10];
   ni.grad_dot_p = gp;
   if (!(gp < 0.0) && pmax > 0.0) {
     // possible with the exact Hessian away from a minimum: not a descent direction
@@ -1460,13 +1496,22 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     if (info) *info = ni;
     return fail(c, YASPS_E_LINESEARCH, "the Newton direction is not a descent direction (g.p >= 0)");
   }
-  double alpha = 1.0;
-  if ((c->nc > 0 || c->nbc > 0) && pmax > 0.0) alpha = std::min(1.0, 0.4 * std::sqrt(ei.min_d) / pmax);
+  double alpha = h[11];
   ni.alpha0 = alpha;
   bool accepted = false;
   double E1 = ei.energy;
-  int trials = 0;
-  for (int k = 0; k <= p.max_halvings; ++k) {
+  int trials = 1;
+  {
+    const double E = h[0] + h[1] + h[2];
+    const bool feas = (h[4] == 0.0) && std::isfinite(E);
+    const bool tie = p.tie_rtol > 0.0 && std::fabs(E - ei.energy) <= p.tie_rtol * std::fabs(ei.energy);
+    if (feas && (E <= ei.energy + p.armijo * alpha * gp || tie)) {
+      accepted = true;
+      E1 = E;
+    }
+  }
+  for (int k = 1; k <= p.max_halvings && !accepted; ++k) {
+    alpha *= 0.5;
     launch_axpy_to(3 * c->n, x, alpha, c->p_dir, c->x_trial, c->stream);
     double E;
     bool feas;
@@ -1477,9 +1522,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
     if (feas && (E <= ei.energy + p.armijo * alpha * gp || tie)) {
       accepted = true;
       E1 = E;
-      break;
     }
-    alpha *= 0.5;
   }
   if (accepted) HIPCHK(c, hipMemcpyAsync(x, c->x_trial, 3 * (size_t)c->n * 8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipEventRecord(ev[4], c->stream));

@@ -248,6 +248,22 @@ __global__ __launch_bounds__(RED_BLOCK) void axpy_to_kernel(int n3, const double
   if (i < n3) y[i] = fma(a, p[i], x[i]);
 }
 
+__global__ __launch_bounds__(RED_BLOCK) void axpy_to_dev_kernel(int n3, const double* __restrict__ x,
+                                                                const double* __restrict__ a,
+                                                                const double* __restrict__ p,
+                                                                double* __restrict__ y) {
+  const int i = blockIdx.x * RED_BLOCK + threadIdx.x;
+  if (i < n3) y[i] = fma(*a, p[i], x[i]);
+}
+
+__global__ void step_bound_kernel(const double* __restrict__ min_d, const double* __restrict__ pmax, int contacts,
+                                  double* __restrict__ out) {
+  const double pm = *pmax;
+  double a = 1.0;
+  if (contacts && pm > 0.0) a = fmin(1.0, 0.4 * sqrt(*min_d) / pm);
+  *out = a;
+}
+
 __global__ __launch_bounds__(RED_BLOCK) void scale_kernel(int n3, const double* __restrict__ x, double a,
                                                           double* __restrict__ y) {
   const int i = blockIdx.x * RED_BLOCK + threadIdx.x;
@@ -381,6 +397,16 @@ void launch_axpy_to(int n3, const double* x, double alpha, const double* p, doub
   if (n3 == 0) return;
   hipLaunchKernelGGL(axpy_to_kernel, dim3((n3 + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s, n3, x,
                      alpha, p, y);
+}
+
+void launch_axpy_to_dev(int n3, const double* x, const double* alpha, const double* p, double* y, hipStream_t s) {
+  if (n3 == 0) return;
+  hipLaunchKernelGGL(axpy_to_dev_kernel, dim3((n3 + RED_BLOCK - 1) / RED_BLOCK), dim3(RED_BLOCK), 0, s, n3, x,
+                     alpha, p, y);
+}
+
+void launch_step_bound(const double* min_d, const double* pmax, int contacts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(step_bound_kernel, dim3(1), dim3(1), 0, s, min_d, pmax, contacts, out);
 }
 
 void launch_scale(int n3, const double* x, double a, double* y, hipStream_t s) {

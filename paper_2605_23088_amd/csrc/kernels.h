@@ -264,6 +264,11 @@ void launch_finalize(int nseg, const int* off_host, const double* parts, const i
 // Vector helpers.
 void launch_axpy_to(int n3, const double* x, double alpha, const double* p, double* y,
                     hipStream_t s);                            // y = x + alpha p
+// the same with alpha read from device memory
+void launch_axpy_to_dev(int n3, const double* x, const double* alpha, const double* p, double* y, hipStream_t s);
+// Newton step bound of the line search on the device: *out = min(1, 0.4 sqrt(min_d) / max_v |p_v|)
+// when there are contacts and p != 0, else 1 (min_d, max |p_v| read from device memory).
+void launch_step_bound(const double* min_d, const double* pmax, int contacts, double* out, hipStream_t s);
 void launch_scale(int n3, const double* x, double a, double* y, hipStream_t s);  // y = a x
 void launch_max_norm3(int n, const double* p, double* part, int nblk, hipStream_t s);
 // per-workgroup partial sums of a . b (grid-stride, fixed order)
