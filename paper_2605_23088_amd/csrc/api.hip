@@ -208,6 +208,7 @@ struct yasps_ctx {
   GrowBuf pcg_work;             // solver workspace (vectors, partials, SpMV slots)
   double *p_dir = nullptr, *x_trial = nullptr, *b_tmp = nullptr;
   double* host_scal = nullptr;  // pinned: [0, 16) scalars and flags, [16, 32) the PCG's polled state
+  int* pin = nullptr;            // pinned read-back scratch of the index, plan and collision builds (PIN_INTS)
   int pcg_hint = 0;             // iterations of the last PCG solve (sizes the next one's launch batches)
   int nparts_alloc = 0;
   bool evaluated = false;
@@ -284,7 +285,7 @@ yasps_status build_plan(yasps_ctx* c, int part, const int32_t* rp, const int32_t
   auto alloc = [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
   size_t need = 0;
   const int r = build_spmv_plan(c->n, rp, col, nblk, vals, out, alloc, c->di_arena, c->di_arena_bytes, &need,
-                                c->stream);
+                                c->pin, c->stream);
   grow_arena(c, need);
   if (r != 0) {
     out = SpmvPart{};
@@ -588,6 +589,7 @@ void yasps_destroy(yasps_ctx* ctx) {
   for (hipEvent_t e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   if (ctx->di_arena) (void)hipFree(ctx->di_arena);
   if (ctx->side) {
     (void)hipStreamSynchronize(ctx->side);
@@ -796,6 +798,8 @@ yasps_status yasps_create(yasps_ctx** out, void* hip_stream, const yasps_problem
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "hipEventCreate"));
   if (hipHostMalloc((void**)&c->host_scal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(c, YASPS_E_HIP, "hipHostMalloc"));
+  if (hipHostMalloc((void**)&c->pin, devsort::PIN_INTS * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(c, YASPS_E_HIP, "hipHostMalloc"));
   s = ensure_parts(c);
   if (s) return bail(s);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(c, YASPS_E_HIP, "stream sync"));
@@ -858,6 +862,7 @@ yasps_status set_contacts_device(yasps_ctx* c, const yasps_contacts* C) {
   in.eps = C->ee_eps;
   in.arena = c->di_arena;
   in.arena_bytes = c->di_arena_bytes;
+  in.pin = c->pin;
   GrowBuf* bufs = c->di_buf;
   auto alloc = [bufs](int which, size_t bytes) { return bufs[which].ensure(bytes); };
   DynIndexOut o;
@@ -1662,7 +1667,7 @@ CdPositions cd_positions(const yasps_ctx* c, const double* x, const double* p = 
 yasps_status detect(yasps_ctx* c, const double* x, int32_t* n_out) {
   size_t need = 0;
   const int r = cd_detect(c->surf, cd_positions(c, x), c->P.dhat, cd_alloc(c), c->di_arena, c->di_arena_bytes, &need,
-                          c->stream, c->detected);
+                          c->pin, c->stream, c->detected);
   grow_arena(c, need);
   if (r != 0) {
     c->detected = CdOutput{};
@@ -1732,7 +1737,7 @@ yasps_status detect(yasps_ctx* c, const double* x, int32_t* n_out) {
 yasps_status ccd(yasps_ctx* c, const double* x, const double* p, double t_max, double s_ccd, double* t_out) {
   size_t need = 0;
   const int r = cd_ccd(c->surf, cd_positions(c, x, p, t_max), c->P.dhat, t_max, s_ccd, cd_alloc(c), c->di_arena,
-                       c->di_arena_bytes, &need, c->stream, t_out);
+                       c->di_arena_bytes, &need, c->pin, c->stream, t_out);
   grow_arena(c, need);
   if (r == -2) return fail(c, YASPS_E_ARG, "CCD: a swept box over too many grid cells (a non-finite position or "
                                            "motion, or the cell size far below the motion)");
@@ -1762,7 +1767,7 @@ yasps_status frame_energy(yasps_ctx* c, const double* x, double* E) {
   double ec = 0.0;
   size_t need = 0;
   const int r = cd_energy(c->surf, cd_positions(c, x), c->P.dhat, c->P.kappa, c->prm.barrier, cd_alloc(c), c->di_arena,
-                          c->di_arena_bytes, &need, c->stream, &ec);  // synchronises the stream
+                          c->di_arena_bytes, &need, c->pin, c->stream, &ec);  // synchronises the stream
   grow_arena(c, need);
   if (r == -2) return fail(c, YASPS_E_ARG, "line search: a box over too many grid cells");
   if (r != 0) return fail(c, YASPS_E_HIP, "contact energy of the proximity search");
@@ -1931,6 +1936,8 @@ yasps_status yasps_frame(yasps_ctx* c, double* x, double* v, const yasps_frame_p
     s = ccd(c, x, c->p_dir, 1.0, fp.ccd_s, &alpha);
     if (s) return s;
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[3]));
+    ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
     fi.ms_ccd += ms;
     bool accepted = false;

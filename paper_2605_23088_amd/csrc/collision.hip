@@ -837,10 +837,11 @@ int register_side(int m, const int32_t* prims, const CdPositions& X, double R, d
   hipLaunchKernelGGL(reg_count_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell,
                      cnt, err, range);
   CD_CHECK(devsort::prefix(tmp, cnt, off, m, s));
-  int h[2] = {0, 0}, rg[6] = {0, 0, 0, 0, 0, 0};
+  int* h = tmp.pin;  // total, error flag, cell range
+  int* rg = tmp.pin + 2;
   CD_CHECK(hipMemcpyAsync(&h[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipMemcpyAsync(&h[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
-  CD_CHECK(hipMemcpyAsync(rg, range, sizeof(rg), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(rg, range, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipStreamSynchronize(s));
   if (h[1]) return -2;
   const int total = h[0];
@@ -949,12 +950,16 @@ int prepare(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc
   return 0;
 }
 
-// The error flag (synchronises the stream).
-int finish(int* err, hipStream_t s) {
-  int h = 0;
-  CD_CHECK(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+// Slots of the pinned read-back scratch: counts first, the error flag at
+// PIN_ERR, a folded double at PIN_VAL.
+constexpr int PIN_ERR = 15, PIN_VAL = 16;
+
+// The error flag (synchronises the stream; read-backs queued before it are
+// then complete too).
+int finish(devsort::Temp& tmp, int* err, hipStream_t s) {
+  CD_CHECK(hipMemcpyAsync(tmp.pin + PIN_ERR, err, sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipStreamSynchronize(s));
-  return h ? -2 : 0;
+  return tmp.pin[PIN_ERR] ? -2 : 0;
 }
 
 // Candidate lists of both query sets (one count read-back for the two).
@@ -973,9 +978,11 @@ int candidates(QueryArgs& qp, QueryArgs& qe, devsort::Temp& tmp, hipStream_t s, 
       hipLaunchKernelGGL((cand_kernel<1, false>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
     CD_CHECK(devsort::prefix(tmp, q.ccnt, off[k], q.ma, s));
   }
-  int h[3] = {0, 0, 0};
-  for (int k = 0; k < 2; ++k)
+  int* h = tmp.pin;
+  for (int k = 0; k < 2; ++k) {
+    h[k] = 0;
     if (off[k]) CD_CHECK(hipMemcpyAsync(&h[k], off[k] + qs[k]->ma, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   CD_CHECK(hipMemcpyAsync(&h[2], err, sizeof(int), hipMemcpyDeviceToHost, s));
   CD_CHECK(hipStreamSynchronize(s));
   if (h[2]) return -2;
@@ -1006,8 +1013,11 @@ void launch_pairs(const QueryArgs& q, hipStream_t s) {
     hipLaunchKernelGGL((pair_kernel<1, 3, MODE>), dim3(grid_q(q.ncand)), dim3(CD_BLOCK), 0, s, q);
 }
 
-// Per-workgroup partials of both query sets folded into one value (kind 0 sum, 1 min).
-int fold_both(QueryArgs& qp, QueryArgs& qe, int mode, devsort::Temp& tmp, hipStream_t s, double init, double* out) {
+// Per-workgroup partials of both query sets folded into one value (kind 0
+// sum, 1 min), read back into the pinned scratch at PIN_VAL (valid after
+// finish), which starts at init.
+int fold_both(QueryArgs& qp, QueryArgs& qe, int mode, devsort::Temp& tmp, hipStream_t s, double init) {
+  double* out = reinterpret_cast<double*>(tmp.pin + PIN_VAL);
   const int gp = qp.ncand ? grid_q(qp.ncand) : 0, ge = qe.ncand ? grid_q(qe.ncand) : 0;
   double* part = tmp.get<double>((size_t)gp + ge + 1);
   CD_CHECK(tmp.err);
@@ -1032,10 +1042,11 @@ int fold_both(QueryArgs& qp, QueryArgs& qe, int mode, devsort::Temp& tmp, hipStr
 }  // namespace
 
 int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc& alloc, void* arena,
-              size_t arena_bytes, size_t* arena_needed, hipStream_t s, CdOutput& out) {
+              size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, CdOutput& out) {
   devsort::Temp tmp;
   tmp.arena = static_cast<char*>(arena);
   tmp.cap = arena_bytes;
+  tmp.pin = pin;
   out = CdOutput{};
   int* err = nullptr;
   QueryArgs qp{}, qe{};
@@ -1055,10 +1066,12 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
     launch_pairs<Q_COUNT>(q, s);
     CD_CHECK(devsort::prefix(tmp, q.hit, hoff[k], q.ncand, s));
   }
-  int m[2] = {0, 0};
-  for (int k = 0; k < 2; ++k)
+  int* m = tmp.pin;
+  for (int k = 0; k < 2; ++k) {
+    m[k] = 0;
     if (hoff[k]) CD_CHECK(hipMemcpyAsync(&m[k], hoff[k] + qs[k]->ncand, sizeof(int), hipMemcpyDeviceToHost, s));
-  e = finish(err, s);
+  }
+  e = finish(tmp, err, s);
   if (e) return e;
   const int total = m[0] + m[1], cap = std::max(total, 1);
   out.type = static_cast<int32_t*>(alloc(CD_TYPE, sizeof(int32_t) * (size_t)cap));
@@ -1101,7 +1114,7 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
                        ee, out.type + m[0], out.idx + m[0], total, out.eps + m[0]);
   }
   CD_CHECK(hipGetLastError());
-  e = finish(err, s);  // also keeps the temporaries alive until the kernels are done
+  e = finish(tmp, err, s);  // also keeps the temporaries alive until the kernels are done
   if (e) return e;
   out.n = total;
   *arena_needed = tmp.used;
@@ -1109,10 +1122,11 @@ int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAll
 }
 
 int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kappa, int classic, const CdAlloc& alloc,
-              void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* e_out) {
+              void* arena, size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, double* e_out) {
   devsort::Temp tmp;
   tmp.arena = static_cast<char*>(arena);
   tmp.cap = arena_bytes;
+  tmp.pin = pin;
   int* err = nullptr;
   QueryArgs qp{}, qe{};
   int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
@@ -1123,21 +1137,21 @@ int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kapp
     q->kappa = kappa;
     q->classic = classic;
   }
-  double val = 0.0;
-  e = fold_both(qp, qe, Q_ENERGY, tmp, s, 0.0, &val);
+  e = fold_both(qp, qe, Q_ENERGY, tmp, s, 0.0);
   if (e) return e;
-  e = finish(err, s);
+  e = finish(tmp, err, s);
   if (e) return e;
-  *e_out = val;
+  *e_out = *reinterpret_cast<const double*>(tmp.pin + PIN_VAL);
   *arena_needed = tmp.used;
   return 0;
 }
 
 int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, double s_ccd, const CdAlloc& alloc,
-           void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* t_out) {
+           void* arena, size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, double* t_out) {
   devsort::Temp tmp;
   tmp.arena = static_cast<char*>(arena);
   tmp.cap = arena_bytes;
+  tmp.pin = pin;
   int* err = nullptr;
   QueryArgs qp{}, qe{};
   int e = prepare(S, X, dhat, alloc, tmp, s, err, qp, qe);
@@ -1148,12 +1162,11 @@ int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, 
     q->s_ccd = s_ccd;
     q->t_max = t_max;
   }
-  double t = t_max;
-  e = fold_both(qp, qe, Q_CCD, tmp, s, t_max, &t);
+  e = fold_both(qp, qe, Q_CCD, tmp, s, t_max);
   if (e) return e;
-  e = finish(err, s);
+  e = finish(tmp, err, s);
   if (e) return e;
-  *t_out = std::fmin(t, t_max);
+  *t_out = std::fmin(*reinterpret_cast<const double*>(tmp.pin + PIN_VAL), t_max);
   *arena_needed = tmp.used;
   return 0;
 }

@@ -14,6 +14,7 @@ namespace yasps {
 namespace devsort {
 
 constexpr int DI_BLOCK = 256;
+constexpr int PIN_INTS = 64;  // size of the pinned read-back scratch the builders are given
 
 inline int bits_for(long long v) {  // bits needed for values 0 .. v
   int b = 1;
@@ -29,6 +30,7 @@ inline int grid_of(long long m) { return (int)std::max<long long>(1, (m + DI_BLO
 struct Temp {
   char* arena = nullptr;
   size_t cap = 0, used = 0;
+  int* pin = nullptr;  // pinned host scratch (PIN_INTS ints) for the builds' read-backs
   std::vector<void*> ptrs;
   hipError_t err = hipSuccess;
   template <class T>

@@ -325,8 +325,8 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
     DI_CHECK(prefix(tmp, blkhist, blkbase, 32ll * nwg, s));
     hipLaunchKernelGGL(group_scatter_kernel, dim3(nwg), dim3(DI_BLOCK), 0, s, nc, gk, blkbase, order);
   }
-  int head[36];
-  DI_CHECK(hipMemcpyAsync(head, scal, sizeof(head), hipMemcpyDeviceToHost, s));
+  int* head = in.pin;  // err, -, -, offdiag, gcount[32]
+  DI_CHECK(hipMemcpyAsync(head, scal, 36 * sizeof(int), hipMemcpyDeviceToHost, s));
   DI_CHECK(hipStreamSynchronize(s));
   if (head[0] != 0x7fffffff) {
     out.err_stencil = head[0] >> 2;
@@ -412,11 +412,11 @@ int build_dynamic_index(const DynIndexIn& in, DynIndexOut& out, const std::funct
   hipLaunchKernelGGL(gcount_kernel, dim3(grid_of(nr)), dim3(DI_BLOCK), 0, s, nr, out.ddiag, out.cptr, gcnt);
   DI_CHECK(prefix(tmp, gcnt, out.gptr, nr, s));
 
-  int nnzb = 0;
-  if (ne) DI_CHECK(hipMemcpyAsync(&nnzb, blk + ne - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  in.pin[40] = 0;
+  if (ne) DI_CHECK(hipMemcpyAsync(in.pin + 40, blk + ne - 1, sizeof(int), hipMemcpyDeviceToHost, s));
   DI_CHECK(hipGetLastError());
   DI_CHECK(hipStreamSynchronize(s));  // nnzb; the temporaries go out of scope
-  out.nnzb = nnzb;
+  out.nnzb = in.pin[40];
   out.nent = (int)ne;
   out.ngrad = (int)ng;
   return 0;

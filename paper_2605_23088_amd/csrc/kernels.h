@@ -204,6 +204,7 @@ struct DynIndexIn {
   const double* eps;       // [nc] edge-edge mollifier thresholds, API order, or null
   void* arena;             // device scratch for the temporaries (may be null)
   size_t arena_bytes;
+  int* pin;                // pinned host scratch of PIN_INTS ints for the read-backs
 };
 struct DynIndexOut {
   int err_stencil = -1, err_reason = 0;  // first invalid stencil: 1 type, 2 vertex ids, 3 no free vertex
@@ -295,11 +296,12 @@ int spmv_chunk_for(long long nblk);
 enum { PL_RL, PL_M0, PL_TB, PL_META, PL_TEND, PL_WSLOT, PL_HPTR, PL_COUNT };
 // Builds one part's plan on the device from its row pointers [n + 1] and
 // columns [nblk] (device arrays).  Plan arrays come from alloc(PL_* id,
-// bytes); temporaries from the arena (or allocated and freed), *arena_needed =
+// bytes); temporaries from the arena (or allocated and freed), pin a pinned
+// host scratch of PIN_INTS ints for the read-backs, *arena_needed =
 // what they took.  0 built, -1 HIP failure.  Synchronises s.
 int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, const void* vals, SpmvPart& out,
                     const std::function<void*(int, size_t)>& alloc, void* arena, size_t arena_bytes,
-                    size_t* arena_needed, hipStream_t s);
+                    size_t* arena_needed, int* pin, hipStream_t s);
 constexpr int PCG_PARTS = 3;  // static, dynamic (contacts), body contacts
 struct PcgMatrix {
   int n = 0;
@@ -373,14 +375,14 @@ using CdAlloc = std::function<void*(int, size_t)>;
 // edge)).  0 ok, -1 HIP failure, -2 a primitive's box over too many grid cells
 // (a non-finite position or a cell size far below the motion).  Synchronises s.
 int cd_detect(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc& alloc, void* arena,
-              size_t arena_bytes, size_t* arena_needed, hipStream_t s, CdOutput& out);
+              size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, CdOutput& out);
 // Barrier energy of the stencils found at X (the same pairs as cd_detect).
 int cd_energy(const CdSurface& S, const CdPositions& X, double dhat, double kappa, int classic, const CdAlloc& alloc,
-              void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* e_out);
+              void* arena, size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, double* e_out);
 // Largest conservative step t <= t_max along X.x + t X.p (additive CCD over the
 // candidate pairs of the swept boxes).
 int cd_ccd(const CdSurface& S, const CdPositions& X, double dhat, double t_max, double s_ccd, const CdAlloc& alloc,
-           void* arena, size_t arena_bytes, size_t* arena_needed, hipStream_t s, double* t_out);
+           void* arena, size_t arena_bytes, size_t* arena_needed, int* pin, hipStream_t s, double* t_out);
 // Time stepping: x_tilde = x + h v + h^2 g over the n rows (gravity on the free
 // rows and the bodies' t rows) and v = (x - x_start) / h.
 void launch_frame_tilde(int nv, int n, const double* x, const double* v, double h, const double g[3], double* xt,

@@ -169,7 +169,7 @@ int spmv_chunk_for(long long nblk) {
 
 int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, const void* vals, SpmvPart& out,
                     const std::function<void*(int, size_t)>& alloc, void* arena, size_t arena_bytes,
-                    size_t* arena_needed, hipStream_t s) {
+                    size_t* arena_needed, int* pin, hipStream_t s) {
   out = SpmvPart{};
   out.vals = vals;
   out.col = col;
@@ -222,7 +222,7 @@ int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, cons
   hipLaunchKernelGGL(plan_starts_kernel, dim3(grid_of(m)), dim3(DI_BLOCK), 0, s, m, rbits, key_s, pad, cstart,
                      first);
   PL_CHECK(inclusive(tmp, first, tq, m, s));
-  int head[2] = {0, 0};  // compressed rows, targets
+  int* head = pin;  // compressed rows, targets
   PL_CHECK(hipMemcpyAsync(&head[0], mpos + n, sizeof(int), hipMemcpyDeviceToHost, s));
   PL_CHECK(hipMemcpyAsync(&head[1], tq + (m - 1), sizeof(int), hipMemcpyDeviceToHost, s));
   PL_CHECK(hipStreamSynchronize(s));
@@ -247,9 +247,9 @@ int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, int nblk, cons
   hipLaunchKernelGGL(plan_wslot_kernel, dim3(grid_of(nt)), dim3(DI_BLOCK), 0, s, nt, tid_s, wslot);
   hipLaunchKernelGGL(plan_hptr_kernel, dim3(grid_of((long long)n + 1)), dim3(DI_BLOCK), 0, s, n, nt, trow_s, hptr);
   PL_CHECK(hipGetLastError());
-  int max_entries = 0;
-  PL_CHECK(hipMemcpyAsync(&max_entries, scal, sizeof(int), hipMemcpyDeviceToHost, s));
-  PL_CHECK(hipStreamSynchronize(s));  // the temporaries and head[] go out of scope
+  PL_CHECK(hipMemcpyAsync(pin + 2, scal, sizeof(int), hipMemcpyDeviceToHost, s));
+  PL_CHECK(hipStreamSynchronize(s));  // the temporaries go out of scope
+  const int max_entries = pin[2];
   out.nblk = nblk;
   out.nrows = head[0];
   out.nchunk = nchunk;
