@@ -554,6 +554,8 @@ def main():
     ap.add_argument("--cells", type=int, default=40, help="block size of the block40 workload")
     ap.add_argument("--workload", choices=["block40", "cloth", "block80", "static", "frames"], default="block40")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--permute", action="store_true",
+                    help="relabel the free vertices by a seeded random permutation (block and cloth workloads)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -617,6 +619,9 @@ def main():
         prob = synth.block_problem(c, c, c, 1.0 / c, 200_000 * c ** 3 // 64000, 200_000 * c ** 3 // 64000,
                                    synth.SEEDS["C2"], name=f"C2-{c}")
         desc = f"{c}x{c}x{c}-cell Kuhn block"
+    if args.permute:  # seeded random relabelling of the free vertices (no favourable locality)
+        prob, _ = synth.permute_vertices(prob)
+        desc += " (free vertex ids randomly permuted)"
     nt, nc = prob["tet_idx"].shape[0], prob["ctype"].shape[0]
     nf, nh = len(prob.get("tri_idx", [])), len(prob.get("hinge_idx", []))
     log(f"[bench] {nt} tets, {nf} triangles, {nh} hinges, {prob['n_free']} free vertices, {nc} contacts; "
@@ -656,6 +661,8 @@ def main():
         cg_work = args.profiled_steps * float(np.mean([i["cg_iters"] for i in pinfos]))
         # counter records are per workload: the block workload at another size has none
         traffic_key = args.workload if args.workload != "block40" or args.cells == 40 else f"block{args.cells}cube"
+        if args.permute:
+            traffic_key += "_permuted"  # counters are taken per vertex order
         mixed = args.precision == "mixed"
         kernels, roofline = kernel_table(stats, algorithmic(prob, g, view, mixed=mixed), args.profiled_steps,
                                          cg_work, traffic_key, args.precision)

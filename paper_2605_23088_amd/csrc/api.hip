@@ -1165,7 +1165,7 @@ namespace {
 
 // Launches every evaluation kernel at x and the final reductions; fills host
 // scalars [E_inertia, E_elastic, E_contact, min_d, n_active] and flags.
-yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info);
+yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info, bool drained = true);
 
 // Launches the evaluation and the read-back of its sums and flags; unless
 // `defer`, waits for them and returns eval_collect's result, else returns once
@@ -1231,10 +1231,11 @@ yasps_status run_eval(yasps_ctx* c, const double* x, int flags, yasps_eval_info*
 }
 
 // The evaluation's energies, minimum distance, active count and status once
-// its read-back (ev_eval) has completed.
-yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info) {
+// its read-back (ev_eval) has completed.  `drained`: nothing was queued after
+// it, so the profiler's records are complete and can be collected.
+yasps_status eval_collect(yasps_ctx* c, yasps_eval_info* info, bool drained) {
   HIPCHK(c, hipEventSynchronize(c->ev_eval));
-  c->prof.collect();
+  if (drained) c->prof.collect();
   uint32_t f;
   std::memcpy(&f, c->host_scal + 8, 4);
   const double* h = c->host_scal;
@@ -1454,7 +1455,7 @@ yasps_status yasps_newton_step(yasps_ctx* c, double* x, const yasps_newton_param
   HIPCHK(c, hipEventRecord(ev[2], c->stream));
   launch_scale(3 * c->n, c->grad, -1.0, c->b_tmp, c->stream);
   // the evaluation's sums and status (read back while the assembly runs)
-  s = eval_collect(c, &ei);
+  s = eval_collect(c, &ei, false);
   if (s) return s;
   double rel = 0.0;
   int status = 0;

@@ -444,6 +444,35 @@ def c5_static(seed=SEEDS["C5"], nx=48, ny=48, nz=29, a=0.02, n_pt=300_000, nu=0.
                  x_tgt=x_tgt, name="C5", grid=(nx, ny, nz), spacing=a)
 
 
+VERTEX_INDEX_KEYS = ("tet_idx", "cidx", "tri_idx", "hinge_idx")
+VERTEX_ROW_KEYS = ("x0", "mass", "x_tilde", "v0", "x_tgt")
+
+
+def permute_vertices(prob, seed=12345):
+    """The same problem with its free vertices relabelled by a seeded random
+    permutation (new id perm[v] for old vertex v; fixed ids and -1 padding
+    unchanged), as the paper does to keep SpMV timings free of favourable
+    memory locality (section "SpMV" of the evaluation).  Returns (problem, perm)."""
+    n = int(prob["n_free"])
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int64)
+    q = dict(prob)
+    for key in VERTEX_ROW_KEYS:
+        if key in prob and prob[key] is not None:
+            a = np.asarray(prob[key])
+            if a.shape[0] == n:
+                b = np.empty_like(a)
+                b[perm] = a
+                q[key] = b
+    for key in VERTEX_INDEX_KEYS:
+        if key in prob and prob[key] is not None and len(prob[key]):
+            idx = np.asarray(prob[key])
+            free = (idx >= 0) & (idx < n)
+            out = idx.copy()
+            out[free] = perm[idx[free]]
+            q[key] = out.astype(idx.dtype)
+    return q, perm
+
+
 def small_block(seed=7, nx=5, ny=4, nz=3, n_pt=150, n_ee=150, **kw):
     """A few-hundred-tet version of the metric workload for fast parity runs."""
     return block_problem(nx, ny, nz, 1.0 / max(nx, ny, nz), n_pt, n_ee, seed,

@@ -44,6 +44,8 @@ def case(name):
         return shaken(synth.small_block(seed=15, nx=5, ny=4, nz=3, n_pt=150, n_ee=150), 0.2)
     if name == "mollified":  # near-parallel collider edges: about half the EE stencils mollified
         return synth.small_block(seed=16, nx=5, ny=4, nz=3, n_pt=100, n_ee=200, ee_angle=(0.005, 0.06))
+    if name == "permuted":  # free vertex ids randomly relabelled (the benchmark's --permute variant)
+        return synth.permute_vertices(synth.small_block(seed=17, nx=10, ny=9, nz=8, n_pt=600, n_ee=500))[0]
     raise KeyError(name)
 
 
@@ -60,7 +62,7 @@ def shaken(p, a, frac=0.2, seed=5):
     return q
 
 
-CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static", "mollified"]
+CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static", "mollified", "permuted"]
 _cache = {}
 
 
@@ -317,3 +319,19 @@ def test_empty_contacts_and_no_tets():
     x = xdev(p)
     ni = g.newton_step(x)
     assert ni["status"] == 0 and ni["alpha0"] == 1.0
+
+
+def test_profiler_sees_every_class_of_a_newton_step():
+    """The opt-in profiler times every kernel class a Newton step launches
+    (evaluation, assembly, block inverse, PCG, line search), each once per
+    step except the PCG's, with positive device time."""
+    p, o, g = setup("block")
+    g.profile(True)
+    x = xdev(p)
+    info = g.newton_step(x, rtol=1e-10)
+    st = g.profile_stats()
+    g.profile(False)
+    assert info["status"] == 0
+    for k in ("inertia", "snh_eval", "contact_eval", "assemble", "block_inverse", "linesearch"):
+        assert st[k]["launches"] >= 1 and st[k]["total_ms"] > 0.0, (k, st[k])
+    assert st["pcg_spmv"]["launches"] >= info["cg_iters"] and st["pcg_update"]["launches"] >= info["cg_iters"]
