@@ -823,26 +823,51 @@ struct Reg {
   int32_t* cstart = nullptr;
 };
 
+// Slots of the pinned read-back scratch: counts first, the error flag at
+// PIN_ERR, a folded double at PIN_VAL, the two registrations' counts and
+// ranges at PIN_REG_T and PIN_REG_E (8 each).
+constexpr int PIN_ERR = 15, PIN_VAL = 16, PIN_REG_T = 24, PIN_REG_E = 32;
+
+// Registration of one side in two phases, so that both sides share one host
+// round trip: count_side queues the per-box cell counts, their scan and the
+// cell range, read back into pin[0..7] (total, error flag, range); after the
+// synchronisation place_side builds the grid registration.
+struct RegCount {
+  int m = 0;
+  const int32_t* prims = nullptr;
+  int32_t* off = nullptr;
+  int* pin = nullptr;
+};
+
 template <int K>
-int register_side(int m, const int32_t* prims, const CdPositions& X, double R, double cell, const CdAlloc& alloc,
-                  int which, devsort::Temp& tmp, hipStream_t s, int* err, Reg& out) {
-  out = Reg{};
+int count_side(int m, const int32_t* prims, const CdPositions& X, double R, double cell, devsort::Temp& tmp,
+               hipStream_t s, int* err, int* pin, RegCount& rc) {
+  rc = RegCount{m, prims, nullptr, pin};
   if (m == 0) return 0;
   int32_t* cnt = tmp.get<int32_t>(m);
-  int32_t* off = tmp.get<int32_t>(m + 1);
+  rc.off = tmp.get<int32_t>(m + 1);
   int* range = tmp.get<int>(6);
   CD_CHECK(tmp.err);
-  const int range0[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
-  CD_CHECK(hipMemcpyAsync(range, range0, sizeof(range0), hipMemcpyHostToDevice, s));
+  CD_CHECK(hipMemsetD32Async(range, INT_MAX, 3, s));
+  CD_CHECK(hipMemsetD32Async(range + 3, INT_MIN, 3, s));
   hipLaunchKernelGGL(reg_count_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell,
                      cnt, err, range);
-  CD_CHECK(devsort::prefix(tmp, cnt, off, m, s));
-  int* h = tmp.pin;  // total, error flag, cell range
-  int* rg = tmp.pin + 2;
-  CD_CHECK(hipMemcpyAsync(&h[0], off + m, sizeof(int), hipMemcpyDeviceToHost, s));
-  CD_CHECK(hipMemcpyAsync(&h[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
-  CD_CHECK(hipMemcpyAsync(rg, range, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
-  CD_CHECK(hipStreamSynchronize(s));
+  CD_CHECK(devsort::prefix(tmp, cnt, rc.off, m, s));
+  CD_CHECK(hipMemcpyAsync(&pin[0], rc.off + m, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(&pin[1], err, sizeof(int), hipMemcpyDeviceToHost, s));
+  CD_CHECK(hipMemcpyAsync(&pin[2], range, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+  return 0;
+}
+
+template <int K>
+int place_side(const RegCount& rc, const CdPositions& X, double R, double cell, const CdAlloc& alloc, int which,
+               devsort::Temp& tmp, hipStream_t s, int* err, Reg& out) {
+  out = Reg{};
+  const int m = rc.m;
+  if (m == 0) return 0;
+  const int32_t* prims = rc.prims;
+  const int* h = rc.pin;  // total, error flag, cell range
+  const int* rg = rc.pin + 2;
   if (h[1]) return -2;
   const int total = h[0];
   if (total <= 0) return -2;
@@ -881,7 +906,7 @@ int register_side(int m, const int32_t* prims, const CdPositions& X, double R, d
     int32_t* vals = tmp.get<int32_t>(total);
     CD_CHECK(tmp.err);
     hipLaunchKernelGGL(reg_fill_kernel<K>, dim3(devsort::grid_of(m)), dim3(DI_BLOCK), 0, s, m, prims, X, R, cell, G,
-                       off, keys, vals, err);
+                       rc.off, keys, vals, err);
     CD_CHECK(devsort::sort_pairs(tmp, keys, ks, vals, vs, total, devsort::bits_for((long long)(ncell - 1.0)), s));
   }
   out.grid = G;
@@ -941,18 +966,20 @@ int prepare(const CdSurface& S, const CdPositions& X, double dhat, const CdAlloc
   CD_CHECK(tmp.err);
   CD_CHECK(hipMemsetAsync(err, 0, sizeof(int), s));
   Reg rt, re;
-  int e = register_side<3>(S.nt, S.tris, X, R, S.cell, alloc, CD_REG_T, tmp, s, err, rt);
+  RegCount ct, ce;
+  int e = count_side<3>(S.nt, S.tris, X, R, S.cell, tmp, s, err, tmp.pin + PIN_REG_T, ct);
   if (e) return e;
-  e = register_side<2>(S.ne, S.edges, X, R, S.cell, alloc, CD_REG_E, tmp, s, err, re);
+  e = count_side<2>(S.ne, S.edges, X, R, S.cell, tmp, s, err, tmp.pin + PIN_REG_E, ce);
+  if (e) return e;
+  CD_CHECK(hipStreamSynchronize(s));
+  e = place_side<3>(ct, X, R, S.cell, alloc, CD_REG_T, tmp, s, err, rt);
+  if (e) return e;
+  e = place_side<2>(ce, X, R, S.cell, alloc, CD_REG_E, tmp, s, err, re);
   if (e) return e;
   qp = query_args(S, X, false, rt, r, dhat, err);
   qe = query_args(S, X, true, re, r, dhat, err);
   return 0;
 }
-
-// Slots of the pinned read-back scratch: counts first, the error flag at
-// PIN_ERR, a folded double at PIN_VAL.
-constexpr int PIN_ERR = 15, PIN_VAL = 16;
 
 // The error flag (synchronises the stream; read-backs queued before it are
 // then complete too).
