@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import energy as en
 from paper_2605_23088_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -49,7 +50,36 @@ def compare(p, gd, gh, solve=True):
         same(xd.cpu().numpy(), xh.cpu().numpy())
 
 
+def mixed_random(seed=21, n=1500):
+    """Every type with every pattern of free and fixed vertices, interleaved in
+    random order (random distinct vertices of a small block and its collider;
+    the stencils need not be close, a distance beyond dhat is an exact zero)."""
+    p = synth.small_block(seed=seed, nx=5, ny=4, nz=3, n_pt=150, n_ee=150)
+    rng = np.random.default_rng(seed)
+    nf, nfix = p["n_free"], len(p["x_fixed"])
+    x = np.concatenate([p["x0"], p["x_fixed"]])
+    ct = rng.integers(0, 4, n).astype(np.int32)
+    ci = np.full((n, 4), -1, np.int32)
+    for s in range(n):
+        nv = (4, 4, 3, 2)[ct[s]]
+        while True:
+            kf = rng.integers(1, nv + 1)  # free vertices of this stencil
+            ids = np.concatenate([rng.choice(nf, kf, replace=False), nf + rng.choice(nfix, nv - kf, replace=False)])
+            rng.shuffle(ids)
+            xs = np.zeros((4, 3))
+            xs[:nv] = x[ids]
+            if ct[s] == 1:  # keep the two edges well away from parallel
+                a, b = xs[1] - xs[0], xs[3] - xs[2]
+                if np.linalg.norm(np.cross(a, b)) < 0.2 * np.linalg.norm(a) * np.linalg.norm(b):
+                    continue
+            if float(en.DIST[int(ct[s])](torch.as_tensor(xs))) > 1e-8:  # no stencil at zero distance
+                break
+        ci[s, :nv] = ids
+    return dict(p, ctype=ct, cidx=ci)
+
+
 CASES = {
+    "mixed_random": mixed_random,
     "two_cubes": lambda: synth.c1_two_cubes(),
     "block_10x9x8": lambda: synth.small_block(seed=11, nx=10, ny=9, nz=8, n_pt=700, n_ee=400),
     "cloth_small": lambda: synth.small_cloth(),

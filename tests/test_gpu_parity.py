@@ -44,9 +44,70 @@ def case(name):
         return shaken(synth.small_block(seed=15, nx=5, ny=4, nz=3, n_pt=150, n_ee=150), 0.2)
     if name == "mollified":  # near-parallel collider edges: about half the EE stencils mollified
         return synth.small_block(seed=16, nx=5, ny=4, nz=3, n_pt=100, n_ee=200, ee_angle=(0.005, 0.06))
+    if name == "all_kinds":
+        return all_kinds()
     if name == "permuted":  # free vertex ids randomly relabelled (the benchmark's --permute variant)
         return synth.permute_vertices(synth.small_block(seed=17, nx=10, ny=9, nz=8, n_pt=600, n_ee=500))[0]
     raise KeyError(name)
+
+
+def all_kinds(seed=18, per=6):
+    """A small block plus active contact stencils of every type and every
+    pattern of free and fixed vertices (each (type, free set) `per` times), on
+    private vertices in random orientations at distances below sqrt(dhat):
+    every contact kernel group and every projection path of the library."""
+    import itertools
+    p = synth.small_block(seed=seed, nx=3, ny=2, nz=2, n_pt=0, n_ee=0)
+    rng = np.random.default_rng(seed)
+    h_max = np.sqrt(p["dhat"])
+    xf, xfix, ct, ci = list(p["x0"]), list(p["x_fixed"]), [], []
+    n0 = p["n_free"]
+    stencils = []
+    for t, nv in ((0, 4), (1, 4), (2, 3), (3, 2)):
+        for k in range(1, nv + 1):
+            for fs in itertools.combinations(range(nv), k):
+                stencils += [(t, fs)] * per
+    rng.shuffle(stencils)
+    for s_, (t, fs) in enumerate(stencils):
+        hd = rng.uniform(0.3, 0.9) * h_max
+        L = rng.uniform(0.02, 0.1)
+        if t == 0:
+            pts = np.vstack([[L * rng.uniform(-0.3, 0.6), L * rng.uniform(-0.3, 0.6), hd],
+                             [0, 0, 0], [L, 0, 0], [0, L, 0]])
+        elif t == 1:
+            th = rng.uniform(0.4, np.pi - 0.4)
+            u = np.array([np.cos(th), np.sin(th), 0.0])
+            c = np.array([0.0, 0.0, hd])
+            pts = np.vstack([[-L, 0, 0], [L, 0, 0], c - L * u, c + L * u])
+        elif t == 2:
+            ph = rng.uniform(0, 2 * np.pi)
+            pts = np.vstack([[L * rng.uniform(-0.5, 0.5), hd * np.cos(ph), hd * np.sin(ph)], [-L, 0, 0], [L, 0, 0]])
+        else:
+            d = rng.normal(size=3)
+            pts = np.vstack([[0, 0, 0], hd * d / np.linalg.norm(d)])
+        q_, r_ = np.linalg.qr(rng.standard_normal((3, 3)))
+        pts = pts @ (q_ * np.sign(np.diag(r_))).T + np.array([10.0 + 0.5 * s_, 0.0, 0.0])
+        ids = [-1, -1, -1, -1]
+        for a in range(len(pts)):
+            if a in fs:
+                ids[a] = len(xf)
+                xf.append(pts[a])
+            else:
+                ids[a] = -2 - len(xfix)  # fixed: resolved below
+                xfix.append(pts[a])
+        ct.append(t)
+        ci.append(ids)
+    nfree = len(xf)
+    ci = np.array(ci, np.int32)
+    fixed = ci <= -2
+    ci[fixed] = nfree + (-2 - ci[fixed])
+    q = dict(p)
+    x0 = np.array(xf)
+    q.update(n_free=nfree, x0=x0, x_fixed=np.array(xfix).reshape(-1, 3), ctype=np.array(ct, np.int32), cidx=ci)
+    extra = nfree - n0
+    q["mass"] = np.concatenate([p["mass"], np.full(extra, 100.0)])  # inertia-dominated: a short solve
+    q["x_tilde"] = np.concatenate([p["x_tilde"], x0[n0:] + (np.asarray(p["x_tilde"])[0] - np.asarray(p["x0"])[0])])
+    return q
 
 
 def shaken(p, a, frac=0.2, seed=5):
@@ -62,7 +123,8 @@ def shaken(p, a, frac=0.2, seed=5):
     return q
 
 
-CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static", "mollified", "permuted"]
+CASES = ["C1", "block", "block_mid", "static", "classic", "xspace_block", "xspace_static", "mollified", "permuted",
+         "all_kinds"]
 _cache = {}
 
 
