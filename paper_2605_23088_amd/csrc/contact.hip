@@ -15,7 +15,7 @@ YDEV const double* vptr(const ContactArgs& a, int v) {
   return v < a.n_free ? a.x + 3 * (size_t)v : a.x_fixed + 3 * (size_t)(v - a.n_free);
 }
 
-template <int TYPE, int K, bool EXACT>
+template <int TYPE, int K, bool EXACT, bool TRI_FREE>
 __global__ __launch_bounds__(EVAL_BLOCK) void contact_kernel(ContactArgs a) {
   constexpr int NV = Topo<TYPE>::NV;
   __shared__ double lds[EVAL_BLOCK];
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(EVAL_BLOCK) void contact_kernel(ContactArgs a) {
       }
     };
     const double eps = (TYPE == 1 && a.eps) ? a.eps[s] : 0.0;
-    const bool ok = contact_stencil<TYPE, K, EXACT>(xv, fl, a.kappa, a.dhat, a.barrier, e, d, side, gsink, bsink, eps);
+    const bool ok = contact_stencil<TYPE, K, EXACT, TRI_FREE>(xv, fl, a.kappa, a.dhat, a.barrier, e, d, side, gsink, bsink, eps);
     a.d_out[s] = d;
     dmin = d;
     if (!ok || !finite(d) || !finite(e)) atomicOr(a.flags, FLAG_NONFINITE);
@@ -129,13 +129,13 @@ __global__ __launch_bounds__(EVAL_BLOCK) void contact_energy_kernel(ContactArgs 
   }
 }
 
-template <int TYPE, int K>
+template <int TYPE, int K, bool TRI_FREE = false>
 void launch_tk(const ContactArgs& a, bool exact, hipStream_t s) {
   const int grid = (a.end - a.begin + EVAL_BLOCK - 1) / EVAL_BLOCK;
   if (exact)
-    hipLaunchKernelGGL((contact_kernel<TYPE, K, true>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((contact_kernel<TYPE, K, true, TRI_FREE>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
   else
-    hipLaunchKernelGGL((contact_kernel<TYPE, K, false>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((contact_kernel<TYPE, K, false, TRI_FREE>), dim3(grid), dim3(EVAL_BLOCK), 0, s, a);
 }
 
 }  // namespace
@@ -147,7 +147,7 @@ void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, 
     case 0 * 8 + 2: launch_tk<0, 2>(a, exact, s); break;
     case 0 * 8 + 3: launch_tk<0, 3>(a, exact, s); break;
     case 0 * 8 + 4: launch_tk<0, 4>(a, exact, s); break;
-    case 0 * 8 + PT_TRIANGLE_FREE: launch_tk<0, 3>(a, exact, s); break;
+    case 0 * 8 + PT_TRIANGLE_FREE: launch_tk<0, 3, true>(a, exact, s); break;
     case 1 * 8 + 1: launch_tk<1, 1>(a, exact, s); break;
     case 1 * 8 + 2: launch_tk<1, 2>(a, exact, s); break;
     case 1 * 8 + 3: launch_tk<1, 3>(a, exact, s); break;

@@ -362,8 +362,17 @@ YHD void block_from_frame(Sym<NN, double>& A, int I, int J, const double (&Fr)[3
 // orthogonal to Q; so Proj(M) = W Proj(M') W^T, a 2m x 2m eigenproblem in
 // place of a 3m x 3m one (closed form for m = 1).  The computed in-plane block
 // is zero up to rounding and is dropped.
-template <int m>
+//
+// SHIFT_NULL (the three free slots are a triangle's vertices, the point
+// fixed): moving the whole triangle along its normal changes the distance but
+// not where the point's foot lies in it, so B annihilates the uniform normal
+// shift s = (1, 1, 1)/sqrt(3).  In the normal coordinates rotated to
+// (s, the two Helmert directions orthogonal to it) B's first column vanishes
+// and is dropped: Q is 2m x (m - 1) and M' is (2m - 1) x (2m - 1).
+template <int m, bool SHIFT_NULL = false>
 YHD void project_plane(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
+  constexpr int nW = SHIFT_NULL ? m - 1 : m;  // normal directions B reaches
+  constexpr int NM = nW + m;                  // size of the reduced problem
   double Bt[2 * m][m];  // Bt[2I + a][J] = P'(I a, J n), a in {t1, t2}
   double Cn[m][m];      // P'(I n, J n)
 #pragma unroll
@@ -380,85 +389,138 @@ YHD void project_plane(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
       Cn[I][J] = P[2][2];
       Cn[J][I] = P[2][2];
     }
-  // Householder QR of Bt (2m x m): Bt = Q R
-  double V[m][2 * m];  // reflector vectors (v_k has zeros above row k)
-  double R[m][m];
+  // normal coordinates: Wb[j][c] = component of slot j of direction c (the
+  // identity, or (s, Helmert directions))
+  double Wb[m][m];
 #pragma unroll
-  for (int k = 0; k < m; ++k) {
+  for (int j = 0; j < m; ++j)
+#pragma unroll
+    for (int c = 0; c < m; ++c)
+      Wb[j][c] = SHIFT_NULL ? (c == 0 ? 1.0 / sqrt(double(m)) : helmert(j, c - 1)) : (j == c ? 1.0 : 0.0);
+  double Bw[2 * m][nW];  // the columns of Bt Wb that B reaches
+#pragma unroll
+  for (int r = 0; r < 2 * m; ++r)
+#pragma unroll
+    for (int c = 0; c < nW; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < m; ++j) acc = fma(Bt[r][j], Wb[j][c + (m - nW)], acc);
+      Bw[r][c] = acc;
+    }
+  double Cw[m][m];  // Wb^T Cn Wb
+#pragma unroll
+  for (int c = 0; c < m; ++c)
+#pragma unroll
+    for (int d = 0; d < m; ++d) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < m; ++j)
+#pragma unroll
+        for (int l = 0; l < m; ++l) acc = fma(Wb[j][c] * Cn[j][l], Wb[l][d], acc);
+      Cw[c][d] = acc;
+    }
+  // Householder QR of Bw (2m x nW): Bw = Q R
+  double V[nW][2 * m];  // reflector vectors (v_k has zeros above row k)
+  double R[nW][nW];
+#pragma unroll
+  for (int k = 0; k < nW; ++k) {
     double nrm2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 2 * m; ++r) nrm2 = r >= k ? fma(Bt[r][k], Bt[r][k], nrm2) : nrm2;
+    for (int r = 0; r < 2 * m; ++r) nrm2 = r >= k ? fma(Bw[r][k], Bw[r][k], nrm2) : nrm2;
     const double nrm = sqrt(nrm2);
-    const double alpha = Bt[k][k] >= 0.0 ? -nrm : nrm;  // v = x - alpha e_k, no cancellation
+    const double alpha = Bw[k][k] >= 0.0 ? -nrm : nrm;  // v = x - alpha e_k, no cancellation
     double vn2 = 0.0;
 #pragma unroll
     for (int r = 0; r < 2 * m; ++r) {
-      const double v = r < k ? 0.0 : (r == k ? Bt[k][k] - alpha : Bt[r][k]);
+      const double v = r < k ? 0.0 : (r == k ? Bw[k][k] - alpha : Bw[r][k]);
       V[k][r] = v;
       vn2 = fma(v, v, vn2);
     }
     const double inv = vn2 > 0.0 ? 2.0 / vn2 : 0.0;  // H_k = I - inv v v^T (identity when x = 0)
 #pragma unroll
-    for (int c = 0; c < m; ++c) {
+    for (int c = 0; c < nW; ++c) {
       if (c < k) continue;
       double dotv = 0.0;
 #pragma unroll
-      for (int r = 0; r < 2 * m; ++r) dotv = fma(V[k][r], Bt[r][c], dotv);
+      for (int r = 0; r < 2 * m; ++r) dotv = fma(V[k][r], Bw[r][c], dotv);
       const double f = inv * dotv;
 #pragma unroll
-      for (int r = 0; r < 2 * m; ++r) Bt[r][c] = fma(-f, V[k][r], Bt[r][c]);
+      for (int r = 0; r < 2 * m; ++r) Bw[r][c] = fma(-f, V[k][r], Bw[r][c]);
     }
 #pragma unroll
-    for (int c = 0; c < m; ++c) R[k][c] = c < k ? 0.0 : Bt[k][c];
+    for (int c = 0; c < nW; ++c) R[k][c] = c < k ? 0.0 : Bw[k][c];
     const double sq = sqrt(inv);  // scale so that H_k = I - v v^T
 #pragma unroll
     for (int r = 0; r < 2 * m; ++r) V[k][r] *= sq;
   }
-  // Q = H_0 ... H_{m-1} applied to the first m columns of I_2m
-  double Q[2 * m][m];
+  // Q = H_0 ... H_{nW-1} applied to the first nW columns of I_2m
+  double Q[2 * m][nW];
 #pragma unroll
   for (int r = 0; r < 2 * m; ++r)
 #pragma unroll
-    for (int c = 0; c < m; ++c) Q[r][c] = r == c ? 1.0 : 0.0;
+    for (int c = 0; c < nW; ++c) Q[r][c] = r == c ? 1.0 : 0.0;
 #pragma unroll
-  for (int k = m - 1; k >= 0; --k)
+  for (int k = nW - 1; k >= 0; --k)
 #pragma unroll
-    for (int c = 0; c < m; ++c) {
+    for (int c = 0; c < nW; ++c) {
       double dotv = 0.0;
 #pragma unroll
       for (int r = 0; r < 2 * m; ++r) dotv = fma(V[k][r], Q[r][c], dotv);
 #pragma unroll
       for (int r = 0; r < 2 * m; ++r) Q[r][c] = fma(-dotv, V[k][r], Q[r][c]);
     }
-  // the reduced matrix and its projection
-  Sym<2 * m, double> M;
+  // the reduced matrix [[0, R~], [R~^T, Cw]] (R~ = R beside a zero column for s) and its projection
+  Sym<NM, double> M;
 #pragma unroll
-  for (int i = 0; i < m; ++i)
+  for (int i = 0; i < nW; ++i)
 #pragma unroll
-    for (int j = i; j < m; ++j) M(i, j) = 0.0;
+    for (int j = i; j < nW; ++j) M(i, j) = 0.0;
 #pragma unroll
-  for (int i = 0; i < m; ++i)
+  for (int i = 0; i < nW; ++i)
 #pragma unroll
-    for (int J = 0; J < m; ++J) M(i, m + J) = R[i][J];
+    for (int c = 0; c < m; ++c) M(i, nW + c) = c < m - nW ? 0.0 : R[i][c - (m - nW)];
+#pragma unroll
+  for (int c = 0; c < m; ++c)
+#pragma unroll
+    for (int d = c; d < m; ++d) M(nW + c, nW + d) = Cw[c][d];
+  psd_small<NM>(M);
+  // back to frame coordinates: P'_SS = Q P11 Q^T, P'_SN = Q P12 Wb^T, P'_NN = Wb P22 Wb^T
+  double QP11[2 * m][nW], PSN[2 * m][m], PNN[m][m];
+#pragma unroll
+  for (int r = 0; r < 2 * m; ++r) {
+#pragma unroll
+    for (int c = 0; c < nW; ++c) {
+      double a1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < nW; ++k) a1 = fma(Q[r][k], M(k, c), a1);
+      QP11[r][c] = a1;
+    }
+    double qp12[m];
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      double a2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < nW; ++k) a2 = fma(Q[r][k], M(k, nW + c), a2);
+      qp12[c] = a2;
+    }
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < m; ++c) acc = fma(qp12[c], Wb[j][c], acc);
+      PSN[r][j] = acc;
+    }
+  }
 #pragma unroll
   for (int I = 0; I < m; ++I)
 #pragma unroll
-    for (int J = I; J < m; ++J) M(m + I, m + J) = Cn[I][J];
-  psd_small<2 * m>(M);
-  // back to frame coordinates: P'_SS = Q P11 Q^T, P'_SN = Q P12, P'_NN = P22
-  double QP11[2 * m][m], PSN[2 * m][m];
+    for (int J = 0; J < m; ++J) {
+      double acc = 0.0;
 #pragma unroll
-  for (int r = 0; r < 2 * m; ++r)
+      for (int c = 0; c < m; ++c)
 #pragma unroll
-    for (int c = 0; c < m; ++c) {
-      double a1 = 0.0, a2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < m; ++k) {
-        a1 = fma(Q[r][k], M(k, c), a1);
-        a2 = fma(Q[r][k], M(k, m + c), a2);
-      }
-      QP11[r][c] = a1;
-      PSN[r][c] = a2;
+        for (int d = 0; d < m; ++d) acc = fma(Wb[I][c] * M(nW + c, nW + d), Wb[J][d], acc);
+      PNN[I][J] = acc;
     }
 #pragma unroll
   for (int I = 0; I < m; ++I)
@@ -471,7 +533,7 @@ YHD void project_plane(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
         for (int b = 0; b < 2; ++b) {
           double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < m; ++k) acc = fma(QP11[2 * I + a][k], Q[2 * J + b][k], acc);
+          for (int k = 0; k < nW; ++k) acc = fma(QP11[2 * I + a][k], Q[2 * J + b][k], acc);
           P[a][b] = acc;
         }
 #pragma unroll
@@ -479,7 +541,7 @@ YHD void project_plane(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
         P[a][2] = PSN[2 * I + a][J];
         P[2][a] = PSN[2 * J + a][I];
       }
-      P[2][2] = M(m + I, m + J);
+      P[2][2] = PNN[I][J];
       block_from_frame<3 * m>(A, I, J, Fr, P);
     }
 }
@@ -542,8 +604,9 @@ YHD void project_line(Sym<3 * m, double>& A, const double (&Fr)[3][3]) {
 // translation invariant), else on the free principal submatrix.
 //
 // SPLIT selects the structured projection of that reduced matrix in the frame
-// *Fr: 1 = project_plane (point-triangle, edge-edge), 2 = project_line
-// (point-edge), 0 = a dense eigendecomposition.
+// *Fr: 1 = project_plane (point-triangle, edge-edge), 3 = project_plane with
+// the triangle's uniform normal shift (free slots = the triangle's vertices),
+// 2 = project_line (point-edge), 0 = a dense eigendecomposition.
 template <class TOPO, int K, bool EXACT, int SPLIT = 0, class GS, class BS>
 YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double>& Hu, const int (&fl)[4],
                       GS&& grad_sink, BS&& block_sink, const double (*Fr)[3][3] = nullptr) {
@@ -657,6 +720,8 @@ YHD void emit_reduced(const double (&gu)[3 * TOPO::NU], Sym<3 * TOPO::NU, double
     if constexpr (!EXACT) {
       if constexpr (SPLIT == 1)
         project_plane<K>(A, *Fr);
+      else if constexpr (SPLIT == 3)
+        project_plane<K, true>(A, *Fr);
       else if constexpr (SPLIT == 2)
         project_line<K>(A, *Fr);
       else
@@ -697,8 +762,10 @@ YHD double ee_mollifier(const double (&u)[3][3], double eps) {
 // structured one of the stencil's type (project_plane, project_line, the
 // point-point closed form), except for a mollified edge-edge stencil: the
 // mollifier varies with the edges' in-plane directions, so that Hessian takes
-// the dense eigendecomposition.
-template <int TYPE, int K, bool EXACT, class GS, class BS>
+// the dense eigendecomposition.  TRI_FREE: a point-triangle stencil whose free
+// vertices are exactly the triangle's (fl = 1, 2, 3; the point fixed), which
+// takes project_plane's uniform-shift reduction.
+template <int TYPE, int K, bool EXACT, bool TRI_FREE = false, class GS, class BS>
 YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double kappa, double dhat, int classic,
                          double& e, double& d, double& side, GS&& grad_sink, BS&& block_sink, double eps = 0.0) {
   constexpr int NU = Topo<TYPE>::NU;
@@ -779,7 +846,8 @@ YHD bool contact_stencil(const double (&xv)[4][3], const int (&fl)[4], double ka
     if (TYPE == 1 && mollified)
       emit_reduced<Topo<TYPE>, K, EXACT>(gu, D.H, fl, grad_sink, block_sink);
     else
-      emit_reduced<Topo<TYPE>, K, EXACT, TYPE == 2 ? 2 : 1>(gu, D.H, fl, grad_sink, block_sink, &Fr);
+      emit_reduced<Topo<TYPE>, K, EXACT, TYPE == 2 ? 2 : (TRI_FREE && TYPE == 0 && K == 3 ? 3 : 1)>(
+          gu, D.H, fl, grad_sink, block_sink, &Fr);
   } else if constexpr (TYPE == 3 && !EXACT) {
     // point-point in closed form: with u = q - p and d = |u|^2 the u-space
     // Hessian kappa (b'' grad d grad d^T + b' hess d) = 4 kappa b'' u u^T + 2 kappa b' I

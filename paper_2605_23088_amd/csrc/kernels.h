@@ -189,8 +189,8 @@ struct ContactArgs {
 };
 // `nfree` is the number of free vertices of the group's stencils, or
 // PT_TRIANGLE_FREE for point-triangle stencils whose point is fixed and whose
-// three triangle vertices are free (a group of their own: one free-vertex
-// pattern, the same in every stencil of the group).
+// three triangle vertices are free (a group and kernel of their own: the
+// projection uses the triangle's uniform normal shift).
 constexpr int PT_TRIANGLE_FREE = 5;
 void launch_contact_eval(int type, int nfree, const ContactArgs& a, bool exact, hipStream_t s);
 // Device build of the dynamic part's index structures (dynindex.hip); every

@@ -8,7 +8,7 @@ using namespace yasps::cmath;
 
 namespace {
 
-template <int T, int K, bool EX>
+template <int T, int K, bool EX, bool TRI = false>
 int run(const double* x12, const int* fl4, double kappa, double dhat, int classic, double eps, double* e, double* d,
         double* g12, double* H144) {
   double xv[4][3];
@@ -30,7 +30,7 @@ int run(const double* x12, const int* fl4, double kappa, double dhat, int classi
       }
   };
   double side;
-  return contact_stencil<T, K, EX>(xv, fl, kappa, dhat, classic, *e, *d, side, gs, bs, eps) ? 0 : 1;
+  return contact_stencil<T, K, EX, TRI>(xv, fl, kappa, dhat, classic, *e, *d, side, gs, bs, eps) ? 0 : 1;
 }
 
 template <bool EX>
@@ -39,7 +39,9 @@ int dispatch(int type, int nfree, const double* x12, const int* fl4, double kapp
   switch (type * 8 + nfree) {
     case 0 * 8 + 1: return run<0, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     case 0 * 8 + 2: return run<0, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
-    case 0 * 8 + 3: return run<0, 3, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+    case 0 * 8 + 3:  // the library runs a triangle-free stencil through its own kernel
+      if (fl4[0] == 1 && fl4[1] == 2 && fl4[2] == 3) return run<0, 3, EX, true>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
+      return run<0, 3, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     case 0 * 8 + 4: return run<0, 4, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     case 1 * 8 + 1: return run<1, 1, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
     case 1 * 8 + 2: return run<1, 2, EX>(x12, fl4, kappa, dhat, classic, eps, e, d, g, H);
