@@ -82,7 +82,7 @@ typedef int32_t yasps_status;
 /* yasps_params.index_build: where yasps_set_contacts builds the dynamic part's
    pattern, slot map, staging layout and SpMV rows (identical results; the paper
    rebuilds only this part when the contacts change, section "Implementation") */
-#define YASPS_INDEX_DEVICE 0 /* on the GPU: stable radix sorts and scans */
+#define YASPS_INDEX_DEVICE 0 /* on the GPU: a stable counting sort, a stable radix sort and scans */
 #define YASPS_INDEX_HOST 1   /* on the host (reference) */
 
 typedef struct yasps_ctx yasps_ctx;
@@ -357,7 +357,10 @@ typedef struct {
   const int32_t* tris;          /* [3][n_tris] */
   const double* edge_rest_len2; /* [n_edges] squared rest lengths, or NULL: the edge-edge stencils found
                                    get the mollifier threshold 1e-3 |a|^2 |b|^2 (none when NULL) */
-  double cell;                  /* cell size of the search grid (> 0; about the longest edge) */
+  double cell;                  /* cell size of the search grid (> 0; about the longest edge).  A search
+                                   counts its entries per cell over the box of cells the primitives
+                                   span (up to 2^22 cells, else it sorts them by cell: slower); a
+                                   primitive whose box covers more than 2^16 cells is an error */
 } yasps_surface;
 
 typedef struct {
@@ -399,7 +402,9 @@ yasps_status yasps_set_surface(yasps_ctx* ctx, const yasps_surface* S);
  * index build; those that reach a body vertex replace the body contacts, as
  * yasps_set_body_contacts); order: point-triangle pairs by (point,
  * triangle), then edge-edge pairs by (edge, edge).  *n_contacts (may be NULL) receives their
- * number.  Errors: YASPS_E_ARG (no surface), YASPS_E_HIP. */
+ * number.  Errors: YASPS_E_ARG (no surface; a primitive's box over more than
+ * 2^16 grid cells: a non-finite position or a cell size far below the
+ * primitives), YASPS_E_HIP. */
 yasps_status yasps_detect(yasps_ctx* ctx, const double* x, int32_t* n_contacts);
 
 /* Copies the stencils of the last yasps_detect to HOST arrays (any may be
