@@ -199,7 +199,9 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
                                                                int nb_c, int mode) {
   extern __shared__ double E[];  // [entries][3] products of one chunk, grouped by target row
   __shared__ double lds[RED_BLOCK];
-  if (mode != SPMV_PLAIN && st->done) return;
+  // The solver's done flag is loaded with the first chunk's data and tested
+  // before the first barrier (a finished solve leaves before any store).
+  const int dn = mode != SPMV_PLAIN ? st->done : 0;
   const bool book = mode == SPMV_PCG && blockIdx.x == 0;  // uniform per workgroup
   constexpr int PC = (MAX_WG_C + RED_BLOCK - 1) / RED_BLOCK;
   double gp[PC], rp[PC];
@@ -222,6 +224,13 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
     const int m0 = P.m0[cc];
     const int32_t* __restrict__ rl = P.rl;  // null when every row holds blocks (row = compressed row)
     const BT* __restrict__ vals = static_cast<const BT*>(P.vals);
+    // the first target row of this thread: its entry range and slot are
+    // loaded with the blocks, ahead of the barrier
+    const int t0 = P.tb[cc], nt = P.tb[cc + 1] - t0;
+    const int q0 = threadIdx.x;
+    const int pe1 = q0 < nt ? P.tend[t0 + q0] : 0;
+    const int pe0 = q0 < nt && q0 ? P.tend[t0 + q0 - 1] : 0;
+    const int pws = q0 < nt ? P.wslot[t0 + q0] : 0;
     // two blocks per thread and trip, all loads of both issued before either
     // product (a chunk of RED_BLOCK blocks or fewer takes one)
     for (int k = b0 + (int)threadIdx.x; k < b1; k += 2 * RED_BLOCK) {
@@ -233,25 +242,27 @@ __global__ __launch_bounds__(RED_BLOCK) void spmv_chunk_kernel(PcgMatrix A, cons
       block_products(L0, E, dlt);
       if (two) block_products(L1, E, dlt);
     }
+    if (dn) return;  // uniform: every thread of the workgroup leaves here
     __syncthreads();
-    const int t0 = P.tb[cc], nt = P.tb[cc + 1] - t0;
     double* __restrict__ W = S.W[pi];
     for (int q = threadIdx.x; q < nt; q += RED_BLOCK) {
-      const int e1 = P.tend[t0 + q], e0 = q ? P.tend[t0 + q - 1] : 0;
+      const bool f = q == q0;
+      const int e1 = f ? pe1 : P.tend[t0 + q], e0 = f ? pe0 : (q ? P.tend[t0 + q - 1] : 0);
+      const int ws = f ? pws : P.wslot[t0 + q];
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int e = e0; e < e1; ++e) {
         s0 += E[3 * e];
         s1 += E[3 * e + 1];
         s2 += E[3 * e + 2];
       }
-      double* w = W + 3 * (size_t)P.wslot[t0 + q];
+      double* w = W + 3 * (size_t)ws;
       w[0] = s0;
       w[1] = s1;
       w[2] = s2;
     }
     __syncthreads();  // E is refilled by the next chunk
   }
-  if (mode != SPMV_PCG) return;
+  if (mode != SPMV_PCG || dn) return;
   const double ds = block_sum<RED_BLOCK>(dlt, lds);
   if (threadIdx.x == 0) part_b[blockIdx.x] = ds;
   if (!book) return;
@@ -396,7 +407,10 @@ YDEV UpdLoads upd_load(const PcgMatrix& A, const double* x, const Vecs<VT>& V, i
 template <class VT>
 __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, double* __restrict__ x, Vecs<VT> V,
                                                                PcgState* st, int nb_b) {
-  if (st->done) return;
+  // every scalar of the state in one batch of loads, tested after the first
+  // pass's vector loads are issued
+  const int dn = st->done, i = st->iter_b, ra = st->restart_at;
+  const double g0 = st->gamma[0], g1 = st->gamma[1], a0 = st->alpha[0], a1 = st->alpha[1];
   __shared__ double lds[UPD_BLOCK];
   __shared__ double rsh[UPD_BLOCK];
   const int t = threadIdx.x;
@@ -412,15 +426,15 @@ __global__ __launch_bounds__(UPD_BLOCK) void pcg_update_kernel(PcgMatrix A, doub
     bp[q] = j < nb_b ? V.part_b[j] : 0.0;
   }
   UpdLoads cur = upd_load(A, x, V, base, t, vl, c);
-  const int i = st->iter_b;
-  const double gamma = st->gamma[i & 1];
+  if (dn) return;
+  const double gamma = (i & 1) ? g1 : g0;
   double dacc = 0.0;  // the association of a strided per-thread sum
 #pragma unroll
   for (int q = 0; q < PB; ++q) dacc += bp[q];
   const double delta = block_sum<UPD_BLOCK>(dacc, lds);
-  const bool restart = i == st->restart_at;
-  const double beta = restart ? 0.0 : gamma / st->gamma[(i - 1) & 1];
-  const double pAp = restart ? delta : delta - beta * gamma / st->alpha[(i - 1) & 1];
+  const bool restart = i == ra;
+  const double beta = restart ? 0.0 : gamma / ((i & 1) ? g0 : g1);
+  const double pAp = restart ? delta : delta - beta * gamma / ((i & 1) ? a0 : a1);
   const bool first = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(pAp > 0.0)) {
     if (first) {
