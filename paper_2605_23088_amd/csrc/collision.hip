@@ -402,37 +402,64 @@ __global__ void iota32_kernel(int m, int32_t* v) {
 }
 
 // The entries of every cell in primitive order.  A cell holds the few
-// primitives whose boxes reach it, each once: up to CELL_SORT_REGS of them are
-// loaded into registers and each is written at its rank (the count of smaller
-// ones; independent comparisons, no chain of dependent loads); a fuller cell
-// is insertion-sorted in place.
-constexpr int CELL_SORT_REGS = 64;
-__global__ void cell_sort_kernel(long long ncell, const int32_t* __restrict__ cstart, int32_t* __restrict__ vals) {
+// primitives whose boxes reach it (each once; about 20 on the surfaces here).
+// A thread loads its cell's entries into registers (all loads issued at once,
+// empty slots padded with INT_MAX), sorts them with a bitonic network of N
+// inputs, N the wavefront's largest cell rounded up to 8, 16, 32 or 64 (one
+// network per wavefront, all compare-exchanges fixed at compile time), and
+// writes them back in order.  A cell of more than 64 entries is
+// insertion-sorted in place by its thread.
+static_assert(DI_BLOCK % 64 == 0, "cell_sort_kernel: whole wavefronts");
+template <int N>
+YDEV void network_sort(int32_t* __restrict__ p, int k) {
+  int v[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) v[a] = a < k ? p[a] : INT_MAX;
+#pragma unroll
+  for (int m = 2; m <= N; m <<= 1)
+#pragma unroll
+    for (int j = m >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int a = v[i], b = v[l];
+          const bool up = (i & m) == 0;
+          v[i] = up ? min(a, b) : max(a, b);
+          v[l] = up ? max(a, b) : min(a, b);
+        }
+      }
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+    if (a < k) p[a] = v[a];
+}
+__global__ __launch_bounds__(DI_BLOCK) void cell_sort_kernel(long long ncell, const int32_t* __restrict__ cstart, int32_t* __restrict__ vals) {
   const long long c = (long long)blockIdx.x * DI_BLOCK + threadIdx.x;
-  if (c >= ncell) return;
-  const int e0 = cstart[c], k = cstart[c + 1] - e0;
-  if (k <= 1) return;
-  if (k <= CELL_SORT_REGS) {
-    int v[CELL_SORT_REGS];
-#pragma unroll
-    for (int a = 0; a < CELL_SORT_REGS; ++a) v[a] = a < k ? vals[e0 + a] : INT_MAX;
-#pragma unroll
-    for (int a = 0; a < CELL_SORT_REGS; ++a) {
-      int r = 0;
-#pragma unroll
-      for (int b = 0; b < CELL_SORT_REGS; ++b) r += v[b] < v[a] ? 1 : 0;
-      if (a < k) vals[e0 + r] = v[a];
+  const bool in = c < ncell;
+  const int e0 = in ? cstart[c] : 0;
+  const int k = in ? cstart[c + 1] - e0 : 0;
+  int kmax = k;
+  for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+  if (kmax <= 1) return;  // uniform
+  int32_t* p = vals + e0;
+  if (kmax <= 8) {
+    network_sort<8>(p, k);
+  } else if (kmax <= 16) {
+    network_sort<16>(p, k);
+  } else if (kmax <= 32) {
+    network_sort<32>(p, k);
+  } else if (k <= 64) {
+    network_sort<64>(p, k);
+  } else {
+    for (int a = 1; a < k; ++a) {
+      const int v = p[a];
+      int b = a - 1;
+      while (b >= 0 && p[b] > v) {
+        p[b + 1] = p[b];
+        --b;
+      }
+      p[b + 1] = v;
     }
-    return;
-  }
-  for (int a = e0 + 1; a < e0 + k; ++a) {
-    const int v = vals[a];
-    int b = a - 1;
-    while (b >= e0 && vals[b] > v) {
-      vals[b + 1] = vals[b];
-      --b;
-    }
-    vals[b + 1] = v;
   }
 }
 

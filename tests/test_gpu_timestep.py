@@ -73,6 +73,26 @@ def test_detect_and_ccd_independent_of_the_grid(monkeypatch, dense_max, cell_sca
     assert g.ccd(dev(p["x0"]), dev(d), 1.0, 0.1) == t_o
 
 
+@pytest.mark.parametrize("scene,cell_scale", [("small", 3.0), ("mid", 5.0)])
+def test_detect_with_crowded_cells(scene, cell_scale):
+    """Cells far larger than the primitives: up to 172 edges in one cell of the
+    small scene and 546 in the mid one, so every way the search orders a
+    cell's entries runs (one wavefront rank sort for up to 64 entries, four
+    entries per lane up to 256, an in-place insertion sort beyond); the same
+    stencil list as the oracle, bit for bit and in its order."""
+    from paper_2605_23088_amd.yasps import Yasps
+    kw = dict(gap=0.004) if scene == "small" else dict(nx=6, ny=6, nz=3, a=0.05, gap=0.004, ground_cells=10)
+    p = synth.drop_scene(**kw)
+    S = col.Surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["n_free"], p["surf_len2"])
+    g = Yasps(p, contacts=False)
+    g.set_surface(p["surf_points"], p["surf_edges"], p["surf_tris"], p["surf_len2"], cell_scale * p["cell"])
+    st = ts.Stepper(p, S)
+    ct_o, ci_o, eps_o = S.detect(st.xall(p["x0"]), p["dhat"])
+    ct, ci, eps = g.detect(dev(p["x0"]))
+    assert len(ct_o) > 20
+    assert np.array_equal(ct, ct_o) and np.array_equal(ci, ci_o) and np.array_equal(eps, eps_o)
+
+
 def test_detect_with_nothing_in_range():
     p, S, g = make(gap=0.5)
     ct, ci, eps = g.detect(dev(p["x0"]))
