@@ -674,10 +674,16 @@ YDEV bool query_cells(const QueryArgs& q, int i, int (&ia)[KA], double (&lo0)[3]
 
 // Pass 1 (WRITE = false): candidates per query, the registered entries of the
 // cells its box covers; pass 2 (WRITE = true): the (query, entry) list, query
-// by query, cells in (z, y, x) order, entries in primitive order.
+// by query, cells in (z, y, x) order, entries in primitive order.  In pass 2 a
+// team of CAND_TEAM lanes takes one query: the lanes walk its cells together
+// and share out each cell's entries, every entry going to the same position
+// as in a walk by one thread.
+constexpr int CAND_TEAM = 8;
 template <int KA, bool WRITE>
 __global__ __launch_bounds__(CD_BLOCK) void cand_kernel(QueryArgs q) {
-  const int i = blockIdx.x * CD_BLOCK + threadIdx.x;
+  constexpr int T = WRITE ? CAND_TEAM : 1;
+  const long long g = (long long)blockIdx.x * CD_BLOCK + threadIdx.x;
+  const int i = (int)(g / T), t = (int)(g % T);
   if (i >= q.ma) return;
   int ia[KA];
   double lo0[3];
@@ -699,14 +705,14 @@ __global__ __launch_bounds__(CD_BLOCK) void cand_kernel(QueryArgs q) {
             e1 = e0;
             while (e1 < q.nreg && q.keys[e1] == key) ++e1;
           }
-          for (int e = e0; e < e1; ++e) {
-            if constexpr (WRITE) {
-              q.cq[o] = i;
-              q.ce[o] = e;
-              ++o;
+          if constexpr (WRITE) {
+            for (int e = e0 + t; e < e1; e += T) {
+              q.cq[o + (e - e0)] = i;
+              q.ce[o + (e - e0)] = e;
             }
-            ++c;
+            o += e1 - e0;
           }
+          c += e1 - e0;
         }
   }
   if constexpr (!WRITE) q.ccnt[i] = c;
@@ -839,7 +845,7 @@ __global__ void frame_velocity_kernel(int n3, const double* __restrict__ x, cons
   v[i] = (x[i] - xs[i]) / h;
 }
 
-int grid_q(int m) { return (m + CD_BLOCK - 1) / CD_BLOCK; }
+int grid_q(long long m) { return (int)((m + CD_BLOCK - 1) / CD_BLOCK); }
 
 #define CD_CHECK(call)                  \
   do {                                  \
@@ -1057,9 +1063,9 @@ int candidates(QueryArgs& qp, QueryArgs& qe, devsort::Temp& tmp, hipStream_t s, 
     q.ce = tmp.get<int32_t>(std::max(h[k], 1));
     CD_CHECK(tmp.err);
     if (q.ee)
-      hipLaunchKernelGGL((cand_kernel<2, true>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+      hipLaunchKernelGGL((cand_kernel<2, true>), dim3(grid_q((long long)CAND_TEAM * q.ma)), dim3(CD_BLOCK), 0, s, q);
     else
-      hipLaunchKernelGGL((cand_kernel<1, true>), dim3(grid_q(q.ma)), dim3(CD_BLOCK), 0, s, q);
+      hipLaunchKernelGGL((cand_kernel<1, true>), dim3(grid_q((long long)CAND_TEAM * q.ma)), dim3(CD_BLOCK), 0, s, q);
   }
   return 0;
 }
