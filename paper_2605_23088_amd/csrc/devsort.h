@@ -6,6 +6,8 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include <algorithm>
 #include <vector>
@@ -82,16 +84,25 @@ hipError_t sort_pairs(Temp& tmp, const K* ki, K* ko, const V* vi, V* vo, long lo
   return sort_pairs_with<rocprim::default_config>(tmp, ki, ko, vi, vo, m, end_bit, s);
 }
 
-// out[0] = 0, out[k + 1] = in[0] + ... + in[k]  (k < m)
+// in[k] for k < m, 0 at k = m: the input of an exclusive scan of m + 1 values
+struct PaddedInput {
+  const int32_t* in;
+  size_t m;
+  __host__ __device__ int32_t operator()(size_t k) const { return k < m ? in[k] : 0; }
+};
+
+// out[0] = 0, out[k + 1] = in[0] + ... + in[k]  (k < m): one exclusive scan
+// of m + 1 values (no separate launch for out[0])
 inline hipError_t prefix(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(out, 0, sizeof(int32_t), s);
-  if (e != hipSuccess || m == 0) return e;
+  const auto src =
+      rocprim::make_transform_iterator(rocprim::make_counting_iterator<size_t>(0), PaddedInput{in, (size_t)m});
   size_t bytes = 0;
-  e = rocprim::inclusive_scan(nullptr, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
+  hipError_t e = rocprim::exclusive_scan(nullptr, bytes, src, out, int32_t(0), (size_t)m + 1,
+                                         rocprim::plus<int32_t>(), s);
   if (e != hipSuccess) return e;
   void* store = tmp.get<char>(bytes);
   if (tmp.err != hipSuccess) return tmp.err;
-  return rocprim::inclusive_scan(store, bytes, in, out + 1, (size_t)m, rocprim::plus<int32_t>(), s);
+  return rocprim::exclusive_scan(store, bytes, src, out, int32_t(0), (size_t)m + 1, rocprim::plus<int32_t>(), s);
 }
 
 inline hipError_t inclusive(Temp& tmp, const int32_t* in, int32_t* out, long long m, hipStream_t s) {
